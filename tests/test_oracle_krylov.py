@@ -1,0 +1,87 @@
+"""Oracle Krylov solves and the Section 4 stopping rules."""
+import math
+
+import numpy as np
+import scipy.sparse as sp
+
+import workloads as W
+from oracle import krylov, smw, split as osplit
+
+
+def _small(seed=0, n=120):
+    return W.random_sparse(n, 0.04, seed, diag=3.0)
+
+
+def test_exact_preconditioner_one_iteration():
+    A = _small()
+    Minv = sp.csr_matrix(np.linalg.inv(A.toarray()))
+    b = A @ np.ones(A.shape[0])
+    x, it, st = krylov.bicgstab(A, Minv, b, 1e-10 * np.linalg.norm(b))
+    assert st == "converged" and it == 1
+    assert np.allclose(x, 1.0, atol=1e-10)
+    x, it, st = krylov.gmres(A, Minv, b, 1e-10 * np.linalg.norm(b))
+    assert st == "converged" and it == 1
+
+
+def test_unpreconditioned_gmres_exact_in_n_steps():
+    A = _small(1, n=40)
+    I = sp.identity(40, format="csr")
+    b = np.random.default_rng(1).standard_normal(40)
+    x, it, st = krylov.gmres(A, I, b, 1e-11 * np.linalg.norm(b), restart=40, maxit=40)
+    assert st == "converged" and it <= 40
+    assert np.allclose(x, np.linalg.solve(A.toarray(), b), atol=1e-9)
+
+
+def test_bicgstab_true_residual_and_dense_solution():
+    A = _small(2, n=200)
+    I = sp.identity(200, format="csr")
+    b = np.random.default_rng(2).standard_normal(200)
+    thr = 1e-9 * np.linalg.norm(b)
+    x, it, st = krylov.bicgstab(A, I, b, thr)
+    assert st == "converged"
+    assert np.linalg.norm(b - A @ x) < thr
+    xd = np.linalg.solve(A.toarray(), b)
+    kappa = np.linalg.cond(A.toarray())
+    assert np.linalg.norm(x - xd) <= kappa * 1e-9 * np.linalg.norm(xd)
+
+
+def test_zero_rhs_and_maxit():
+    A = _small(3)
+    I = sp.identity(A.shape[0], format="csr")
+    x, it, st = krylov.bicgstab(A, I, np.zeros(A.shape[0]), 1e-12)
+    assert st == "converged" and it == 0 and not x.any()
+    b = np.ones(A.shape[0])
+    x, it, st = krylov.bicgstab(A, I, b, 1e-300, maxit=3)
+    assert st == "maxit" and it == 3
+
+
+def test_stopping_rules_imply_target():
+    """Section 4 theorem: (stopb) and (stopU2) with the true c imply rr < eps."""
+    rng = np.random.default_rng(4)
+    w = W.make(1)
+    S = osplit.split(w.A)
+    A, At, b = w.A, S.At, w.b
+    U = S.U.toarray()
+    Atd = At.toarray()
+    y = np.linalg.solve(Atd, b)
+    Wx = np.linalg.solve(Atd, U)
+    eps = 1e-6
+    s = S.s
+    _, z, c = smw.recover(y, Wx, S.D)
+    thr = krylov.thresholds(np.linalg.norm(b), s, eps, c=c)
+    # perturb the exact solutions so that each residual sits just under its threshold
+    yh = y + np.linalg.solve(Atd, rng.standard_normal(b.size))
+    ry = b - At @ yh
+    yh = y + (yh - y) * (0.99 * thr[0] / np.linalg.norm(ry))
+    Wh = Wx.copy()
+    for j in range(s):
+        d = np.linalg.solve(Atd, rng.standard_normal(b.size))
+        rj = At @ d
+        Wh[:, j] = Wx[:, j] + d * (0.99 * thr[j + 1] / np.linalg.norm(rj))
+    assert np.linalg.norm(b - At @ yh) < thr[0]
+    xh, z2, c2 = smw.recover(yh, Wh, S.D)
+    # c of the perturbed solutions is close to the exact one; the bound uses c2
+    thr2 = krylov.thresholds(np.linalg.norm(b), s, eps, c=max(c, c2) * 1.0001)
+    assert all(np.linalg.norm(U[:, j] - At @ Wh[:, j]) < thr2[j + 1] * 1.0001 for j in range(s))
+    assert smw.relres(A, xh, b) < eps
+    assert math.isclose(thr[0], 0.5 * eps * np.linalg.norm(b))

@@ -1,0 +1,155 @@
+"""Plant plausible mistakes in copies of oracle functions; the pins must catch each one.
+
+Nothing here touches the GPU: every mistake is planted in the CPU oracle.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import workloads as W
+from oracle import lsq, pattern as opat, smw, spai, split as osplit
+from tests import pins
+from tests.test_oracle_split import _matrix_like, _table3
+
+
+def _tie_matrix():
+    n = 30
+    A = sp.lil_matrix((n, n))
+    for i in range(n):
+        A[i, i] = 4.0
+    for i in [8, 12] + list(range(20, 30)):
+        A[i, 10] = 1.0
+    return sp.csr_matrix(A)
+
+
+def _split_variant(mode):
+    def f(A, dense_factor=10.0, keep=None, rule="nearest"):
+        A = sp.csr_matrix(A)
+        n = A.shape[0]
+        if mode == "round_p":
+            p_override = int(round(A.nnz / n))
+        elif mode == "ge_threshold":
+            p_override = None
+        else:
+            p_override = None
+        S = osplit.split(A, dense_factor if mode != "ge_threshold" else dense_factor - 1e-9,
+                         keep=keep, rule=rule)
+        if p_override is not None:
+            S.p = p_override
+        if mode == "tie_larger":
+            # redo the selection with ties going to the larger row index
+            C = A.tocsc()
+            C.sort_indices()
+            kk = S.keep
+            At = A.toarray()
+            Ud = np.zeros((n, S.s))
+            for d, j in enumerate(S.D):
+                rows = [i for i in C.indices[C.indptr[j]:C.indptr[j + 1]] if i != j]
+                rows.sort(key=lambda i: (abs(i - j), -i))
+                for i in rows[kk - 1:]:
+                    Ud[i, d] = At[i, j]
+                    At[i, j] = 0.0
+            S.At = sp.csr_matrix(At)
+            S.U = sp.csc_matrix(Ud)
+        if mode == "keep_minus_one":
+            return osplit.split(A, dense_factor, keep=max(1, (keep or A.nnz // n) - 1), rule=rule)
+        return S
+    return f
+
+
+@pytest.mark.parametrize("mode", ["round_p", "ge_threshold"])
+def test_table3_catches(mode):
+    f = _split_variant(mode)
+    caught = False
+    for row in _table3():
+        A = _matrix_like(row)
+        S = f(A, keep=row["keep"])
+        if S.p != row["p"] or S.s != row["s"]:
+            caught = True
+            break
+    assert caught
+
+
+@pytest.mark.parametrize("mode", ["tie_larger", "keep_minus_one"])
+def test_split_bruteforce_catches(mode):
+    f = _split_variant(mode)
+    A = _tie_matrix()
+    with pytest.raises(AssertionError):
+        # the brute-force pin on the tie matrix (p = 1, so the threshold factor is 2)
+        pins.check_split_bruteforce(lambda M, keep=None: f(M, 2.0, keep=keep), A, keep=2,
+                                    dense_factor=2.0)
+
+
+def test_pattern_transposed_operand_caught():
+    At = W.random_sparse(50, 0.05, 0)
+
+    def wrong(C, k):
+        R = sp.csr_matrix(C)
+        out = set()
+        for j in R.indices[R.indptr[k]:R.indptr[k + 1]]:
+            out.update(R.indices[R.indptr[j]:R.indptr[j + 1]].tolist())
+        return np.array(sorted(out))
+    with pytest.raises(AssertionError):
+        pins.check_pattern_A2_bruteforce(wrong, At)
+
+
+def test_lsq_missing_rows_caught():
+    w = W.make(2, dims=(7, 7, 7), s=2, density=0.2)
+    S = osplit.split(w.A)
+    C = opat.as_csc(S.At)
+
+    def wrong(C, J, k):
+        I = opat.col_rows(C, k)          # rows of column k only, not of A~(:, J)
+        pos = {int(i): t for t, i in enumerate(I)}
+        Ah = np.zeros((len(I), len(J)))
+        for c, j in enumerate(J):
+            for i, v in zip(C.indices[C.indptr[j]:C.indptr[j + 1]], C.data[C.indptr[j]:C.indptr[j + 1]]):
+                if int(i) in pos:
+                    Ah[pos[int(i)], c] = v
+        e = (I == k).astype(float)
+        m = np.linalg.lstsq(Ah, e, rcond=None)[0]
+        return I, m, float(np.linalg.norm(Ah @ m - e))
+    k = 171
+    with pytest.raises(AssertionError):
+        pins.check_ls_optimality(wrong, S.At, opat.pattern_A2(C, k), k)
+
+
+def test_lsq_transposed_block_caught():
+    At = W.random_sparse(20, 0.15, 1, diag=2.0)
+
+    def wrong(C, J, k):
+        I, m, res = lsq.solve_column(sp.csc_matrix(sp.csr_matrix(C).T), J, k)
+        return I, m, res
+    with pytest.raises(AssertionError):
+        pins.check_full_pattern_inverse(wrong, At)
+
+
+def test_spai_gain_without_norm_caught():
+    w = W.make(3, n=300, s=2, density=0.2)
+    S = osplit.split(w.A)
+    C = opat.as_csc(S.At)
+    k = 5
+    J = opat.pattern_A(C, k)
+    I, m, res = lsq.solve_column(C, J, k)
+    r = lsq.dense_block(C, I, J) @ m - (I == k)
+
+    def wrong(C, R, cn2, J, I, r):
+        return spai.candidate_gains(C, R, np.ones_like(cn2), J, I, r)
+    with pytest.raises(AssertionError):
+        pins.check_spai_gains(wrong, S.At, J, I, r)
+
+
+@pytest.mark.parametrize("mistake", ["sign", "transposed_rows"])
+def test_smw_mistakes_caught(mistake):
+    w = W.make(1)
+    S = osplit.split(w.A)
+    U = S.U.toarray()
+
+    def wrong(y, Wm, D):
+        s = len(D)
+        K = np.eye(s) + (Wm[D, :] if mistake == "sign" else Wm[D, :].T)
+        z = np.linalg.solve(K, y[D])
+        x = y + Wm @ z if mistake == "sign" else y - Wm @ z
+        return x, z, float(np.linalg.norm(z))
+    with pytest.raises(AssertionError):
+        pins.check_smw_exact(wrong, w.A, S.At, U, S.D, w.b)
