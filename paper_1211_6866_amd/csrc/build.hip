@@ -1,0 +1,234 @@
+// Build of M: patterns, column least squares, dropping and assembly.
+//
+// After every m_k is computed on its pattern J_k, entries with |m_jk| <= tol_k
+// are dropped (Section 2.2, PSAI(tol), (tolk)): tol_k = tau (absolute) or
+// delta / (|J_k| * ||A~||_1); the entry of largest magnitude of each column is
+// always kept.  M is assembled in CSC (column k = m_k; this is the CSR of M^T
+// used by the adjoint) and transposed once to CSR for the forward products.
+#include "sai_internal.hpp"
+
+namespace sai {
+
+// defined in other translation units
+void build_patterns(const sai_split_s* sp, int kind, hipStream_t st, const Allocator& al,
+                    DBuf<int64_t>& jptr, DBuf<int32_t>& jidx, DBuf<int64_t>& iptr,
+                    DBuf<int32_t>& iidx, DBuf<int32_t>& cntJ, DBuf<int32_t>& cntI);
+template <class T>
+int solve_columns(const sai_split_s* sp, const int64_t* jptr, const int32_t* jidx,
+                  const int64_t* iptr, const int32_t* iidx, const int32_t* cntJ,
+                  const int32_t* cntI, int maxI, int maxJ, T* mout, double* res,
+                  int64_t* bucket_cols, const Allocator& al, hipStream_t st);
+template <class V>
+void csr_transpose(int32_t nrows, int32_t ncols, const int32_t* rp, const int32_t* ci, const V* v,
+                   int32_t* cp, int32_t* ri, V* cv, const Allocator& al, hipStream_t st);
+void spai_patterns(const sai_split_s* sp, const sai_build_opts& o, hipStream_t st,
+                   const Allocator& al, DBuf<int64_t>& jptr, DBuf<int32_t>& jidx,
+                   DBuf<int64_t>& iptr, DBuf<int32_t>& iidx, DBuf<int32_t>& cntJ,
+                   DBuf<int32_t>& cntI);
+
+namespace {
+
+constexpr int NT = 256;
+
+__global__ void k_stats(int32_t n, const int32_t* cntJ, const int32_t* cntI, const double* res,
+                        double delta, int* out /* maxI, maxJ, n_c */) {
+  const int64_t k = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (k >= n) return;
+  atomicMax(&out[0], cntI[k]);
+  atomicMax(&out[1], cntJ[k]);
+  if (res && res[k] > delta) atomicAdd(&out[2], 1);
+}
+
+__global__ void k_maxI(int32_t n, const int32_t* cntJ, const int32_t* cntI, int* out) {
+  const int64_t k = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (k >= n) return;
+  atomicMax(&out[0], cntI[k]);
+  atomicMax(&out[1], cntJ[k]);
+}
+
+// ||A~||_1 = max_j sum_i |a_ij|; stored as the bit pattern of a non-negative double,
+// whose integer order equals its numeric order, so atomicMax is exact.
+__global__ void k_norm1(int32_t n, const int32_t* cp, const double* cv, unsigned long long* out) {
+  const int64_t j = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (j >= n) return;
+  double s = 0.0;
+  for (int32_t e = cp[j]; e < cp[j + 1]; ++e) s += fabs(cv[e]);
+  atomicMax(out, (unsigned long long)__double_as_longlong(s));
+}
+
+template <class T>
+__global__ void k_drop_count(int32_t n, const int64_t* __restrict__ jptr, const T* __restrict__ m,
+                             int mode, double tau, double delta, double norm1,
+                             int32_t* __restrict__ cnt) {
+  const int64_t k = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (k >= n) return;
+  const int64_t a = jptr[k], b = jptr[k + 1];
+  const int nj = (int)(b - a);
+  double thr = -1.0;
+  if (mode == SAI_DROP_ABS) thr = tau;
+  else if (mode == SAI_DROP_TOLK) thr = delta / ((double)nj * norm1);
+  int64_t amax = a;
+  double vmax = -1.0;
+  for (int64_t e = a; e < b; ++e) {
+    const double v = fabs((double)m[e]);
+    if (v > vmax) { vmax = v; amax = e; }
+  }
+  int c = 0;
+  for (int64_t e = a; e < b; ++e)
+    if (fabs((double)m[e]) > thr || e == amax) ++c;
+  cnt[k] = c;
+}
+
+template <class T>
+__global__ void k_drop_scatter(int32_t n, const int64_t* __restrict__ jptr,
+                               const int32_t* __restrict__ jidx, const T* __restrict__ m, int mode,
+                               double tau, double delta, double norm1,
+                               const int32_t* __restrict__ colp, int32_t* __restrict__ rowi,
+                               T* __restrict__ cval) {
+  const int64_t k = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (k >= n) return;
+  const int64_t a = jptr[k], b = jptr[k + 1];
+  const int nj = (int)(b - a);
+  double thr = -1.0;
+  if (mode == SAI_DROP_ABS) thr = tau;
+  else if (mode == SAI_DROP_TOLK) thr = delta / ((double)nj * norm1);
+  int64_t amax = a;
+  double vmax = -1.0;
+  for (int64_t e = a; e < b; ++e) {
+    const double v = fabs((double)m[e]);
+    if (v > vmax) { vmax = v; amax = e; }
+  }
+  int32_t o = colp[k];
+  for (int64_t e = a; e < b; ++e) {
+    if (fabs((double)m[e]) > thr || e == amax) {
+      rowi[o] = jidx[e];
+      cval[o] = m[e];
+      ++o;
+    }
+  }
+}
+
+template <class T>
+void build_typed(const sai_split_s* sp, const sai_build_opts& o, hipStream_t st, sai_precond_s* pc,
+                 sai_build_stats* stats) {
+  const Allocator& al = pc->al;
+  const int32_t n = sp->n;
+  EventTimer t_all, t_pat, t_ls, t_asm;
+  t_all.start(st);
+  t_pat.start(st);
+  DBuf<int64_t> jptr, iptr;
+  DBuf<int32_t> jidx, iidx, cntJ, cntI;
+  if (o.pattern == SAI_PAT_SPAI)
+    spai_patterns(sp, o, st, al, jptr, jidx, iptr, iidx, cntJ, cntI);
+  else
+    build_patterns(sp, o.pattern, st, al, jptr, jidx, iptr, iidx, cntJ, cntI);
+  t_pat.stop(st);
+  int64_t tot[2];
+  HIPC(hipMemcpyAsync(&tot[0], jptr.p + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  HIPC(hipMemcpyAsync(&tot[1], iptr.p + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  DBuf<int> mx(&al, 4);
+  HIPC(hipMemsetAsync(mx.p, 0, 4 * sizeof(int), st));
+  hipLaunchKernelGGL(k_maxI, dim3(grid_for(n, NT)), dim3(NT), 0, st, n, cntJ.p, cntI.p, mx.p);
+  LAUNCH_CHECK();
+  int hmx[4];
+  HIPC(hipMemcpyAsync(hmx, mx.p, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPC(hipStreamSynchronize(st));
+  const int64_t nnz_full = tot[0];
+
+  t_ls.start(st);
+  DBuf<T> mfull(&al, (size_t)nnz_full + 1);
+  DBuf<double> res(&al, (size_t)n + 1);
+  int64_t bcols[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const int nsing = solve_columns<T>(sp, jptr.p, jidx.p, iptr.p, iidx.p, cntJ.p, cntI.p, hmx[0],
+                                     hmx[1], mfull.p, res.p, bcols, al, st);
+  t_ls.stop(st);
+  if (nsing > 0)
+    SAI_THROW(SAI_ESINGULAR, "%d column least-squares blocks are rank deficient", nsing);
+
+  t_asm.start(st);
+  double norm1 = 0.0;
+  if (o.drop == SAI_DROP_TOLK) {
+    DBuf<unsigned long long> nb(&al, 1);
+    HIPC(hipMemsetAsync(nb.p, 0, sizeof(unsigned long long), st));
+    hipLaunchKernelGGL(k_norm1, dim3(grid_for(n, NT)), dim3(NT), 0, st, n, sp->t_col_ptr.p,
+                       sp->t_cval.p, nb.p);
+    LAUNCH_CHECK();
+    unsigned long long bits = read_scalar(nb.p, st);
+    memcpy(&norm1, &bits, sizeof(double));
+  }
+  DBuf<int32_t> ccnt(&al, (size_t)n + 1);
+  hipLaunchKernelGGL((k_drop_count<T>), dim3(grid_for(n, NT)), dim3(NT), 0, st, n, jptr.p, mfull.p,
+                     o.drop, o.tau, o.delta, norm1, ccnt.p);
+  LAUNCH_CHECK();
+  pc->col_ptr.alloc(&al, (size_t)n + 1);
+  exclusive_scan_i32(ccnt.p, pc->col_ptr.p, n, al, st);
+  const int32_t nnz = read_scalar(pc->col_ptr.p + n, st);
+  pc->nnz = nnz;
+  pc->row_idx.alloc(&al, (size_t)nnz + 1);
+  pc->cval.alloc(&al, ((size_t)nnz + 1) * sizeof(T));
+  hipLaunchKernelGGL((k_drop_scatter<T>), dim3(grid_for(n, NT)), dim3(NT), 0, st, n, jptr.p, jidx.p,
+                     mfull.p, o.drop, o.tau, o.delta, norm1, pc->col_ptr.p, pc->row_idx.p,
+                     (T*)pc->cval.p);
+  LAUNCH_CHECK();
+  pc->row_ptr.alloc(&al, (size_t)n + 1);
+  pc->col_idx.alloc(&al, (size_t)nnz + 1);
+  pc->val.alloc(&al, ((size_t)nnz + 1) * sizeof(T));
+  csr_transpose<T>(n, n, pc->col_ptr.p, pc->row_idx.p, (const T*)pc->cval.p, pc->row_ptr.p,
+                   pc->col_idx.p, (T*)pc->val.p, al, st);
+  t_asm.stop(st);
+  t_all.stop(st);
+
+  if (stats) {
+    DBuf<int> so(&al, 4);
+    HIPC(hipMemsetAsync(so.p, 0, 4 * sizeof(int), st));
+    hipLaunchKernelGGL(k_stats, dim3(grid_for(n, NT)), dim3(NT), 0, st, n, cntJ.p, cntI.p, res.p,
+                       o.delta, so.p);
+    LAUNCH_CHECK();
+    int hs[4];
+    HIPC(hipMemcpyAsync(hs, so.p, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    stats->n = n;
+    stats->nnz_m = nnz;
+    stats->nnz_m_full = nnz_full;
+    stats->sum_i = tot[1];
+    stats->max_i = hs[0];
+    stats->max_j = hs[1];
+    stats->n_c = hs[2];
+    stats->spar = sp->nnz_t > 0 ? (double)nnz / (double)sp->nnz_t : 0.0;
+    for (int v = 0; v < 8; ++v) stats->bucket_cols[v] = bcols[v];
+    stats->t_pattern_ms = t_pat.ms();
+    stats->t_ls_ms = t_ls.ms();
+    stats->t_assemble_ms = t_asm.ms();
+    stats->t_total_ms = t_all.ms();
+  }
+  if (o.keep_lists) {
+    pc->j_ptr = std::move(jptr);
+    pc->j_idx = std::move(jidx);
+    pc->i_ptr = std::move(iptr);
+    pc->i_idx = std::move(iidx);
+    pc->res = std::move(res);
+    DBuf<char> mf(&al, ((size_t)nnz_full + 1) * sizeof(T));
+    HIPC(hipMemcpyAsync(mf.p, mfull.p, (size_t)nnz_full * sizeof(T), hipMemcpyDeviceToDevice, st));
+    pc->m_full = std::move(mf);
+  }
+  HIPC(hipStreamSynchronize(st));
+}
+
+}  // namespace
+
+void build_impl(const sai_split_s* sp, const sai_build_opts& o, hipStream_t st, sai_precond_s* pc,
+                sai_build_stats* stats) {
+  if (o.pattern < SAI_PAT_A || o.pattern > SAI_PAT_SPAI) SAI_THROW(SAI_EINVAL, "bad pattern");
+  if (o.drop < SAI_DROP_NONE || o.drop > SAI_DROP_TOLK) SAI_THROW(SAI_EINVAL, "bad drop mode");
+  if (o.precision != SAI_FP32 && o.precision != SAI_FP64) SAI_THROW(SAI_EINVAL, "bad precision");
+  pc->al = sp->al;
+  pc->al.stream = st;
+  pc->n = sp->n;
+  pc->precision = o.precision;
+  if (o.precision == SAI_FP32)
+    build_typed<float>(sp, o, st, pc, stats);
+  else
+    build_typed<double>(sp, o, st, pc, stats);
+}
+
+}  // namespace sai

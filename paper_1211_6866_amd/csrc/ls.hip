@@ -1,0 +1,526 @@
+// Column least-squares solves: m_k = argmin ||A~(I_k, J_k) m - e_k(I_k)||
+// (Section 2, (subprob) -> (lsprob)), by Householder QR and back-substitution.
+//
+// Register kernels (k_ls_qr): a group of G lanes (G = 16, 32 or 64) owns one
+// problem; lane l of the group holds rows l, l+G, ..., l+(R-1)G of the dense
+// block in registers, so the factorisation never touches memory.  Column
+// reductions are butterfly sums over the group: four DPP steps inside a row of
+// 16 lanes (quad_perm xor-1, quad_perm xor-2, row_half_mirror, row_mirror),
+// plus cross-row shuffles for G = 32/64.  Every lane of a group receives the
+// bit-identical sum.  The j (reflector) and c (column) loops are fully
+// unrolled so that all register indices are static; a wave-uniform guard
+// skips the steps past the widest problem of the wave.
+//
+// The block is gathered first, one problem at a time, through an LDS tile: the
+// entries of the columns A~(:, j), j in J_k, are scattered to the position of
+// their row in I_k (binary search in the sorted I_k).
+//
+// Large problems (k_ls_qr_big) use one 256-thread workgroup with the block in a
+// global workspace.
+#include "sai_internal.hpp"
+
+namespace sai {
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xF, 0xF, true);
+  int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Sum over the G consecutive lanes of a group; identical result in every lane.
+template <int G, class T>
+__device__ __forceinline__ T gsum(T v) {
+  static_assert(G == 16 || G == 32 || G == 64, "group size");
+  v += dpp_mov<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_mov<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_mov<0x141>(v);  // row_half_mirror
+  v += dpp_mov<0x140>(v);  // row_mirror
+  if constexpr (G >= 32) v += __shfl_xor(v, 16, 64);
+  if constexpr (G >= 64) v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
+__device__ __forceinline__ int wave_max_i(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__device__ __forceinline__ int lower_bound_lds(const int32_t* a, int n, int32_t x) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (a[mid] < x) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+template <class T, int G, int R, int JMAX>
+__global__ void __launch_bounds__(64) k_ls_qr(const int32_t* __restrict__ cols, int ncols,
+                                              const int64_t* __restrict__ jptr,
+                                              const int32_t* __restrict__ jidx,
+                                              const int64_t* __restrict__ iptr,
+                                              const int32_t* __restrict__ iidx,
+                                              const int32_t* __restrict__ cp,
+                                              const int32_t* __restrict__ ri,
+                                              const double* __restrict__ cv, T* __restrict__ mout,
+                                              double* __restrict__ res_out, int* __restrict__ nsing) {
+  constexpr int NP = 64 / G;
+  constexpr int ROWS = G * R;
+  constexpr int LDT = JMAX + 1;
+  constexpr int MS = (JMAX + G - 1) / G;
+  static_assert(JMAX <= ROWS, "row slots must cover the columns");
+  __shared__ T tile[ROWS * LDT];
+  __shared__ int32_t sI[ROWS];
+  __shared__ int32_t sStart[JMAX];
+  __shared__ int32_t sOff[JMAX + 1];
+
+  const int lane = threadIdx.x;
+  const int g = lane / G;
+  const int li = lane % G;
+
+  for (int64_t base = (int64_t)blockIdx.x * NP; base < ncols; base += (int64_t)gridDim.x * NP) {
+    const int64_t myidx = base + g;
+    const bool valid = myidx < ncols;
+    const int k = valid ? cols[myidx] : -1;
+    const int nJ = valid ? (int)(jptr[k + 1] - jptr[k]) : 0;
+    const int nI = valid ? (int)(iptr[k + 1] - iptr[k]) : 0;
+
+    T a[R][JMAX];
+    T b[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      b[r] = 0;
+#pragma unroll
+      for (int c = 0; c < JMAX; ++c) a[r][c] = 0;
+    }
+
+    // ---- gather, one problem of the wave at a time
+    for (int p = 0; p < NP; ++p) {
+      const int kp = __shfl(k, p * G, 64);
+      if (kp < 0) continue;
+      const int nJp = __shfl(nJ, p * G, 64);
+      const int nIp = __shfl(nI, p * G, 64);
+      const int64_t jo = jptr[kp], io = iptr[kp];
+      int cnt = 0;
+      if (lane < nJp) {
+        const int32_t j = jidx[jo + lane];
+        const int32_t s0 = cp[j];
+        cnt = cp[j + 1] - s0;
+        sStart[lane] = s0;
+      }
+      int incl = cnt;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        int v = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += v;
+      }
+      if (lane < nJp) sOff[lane] = incl - cnt;
+      const int total = __shfl(incl, 63, 64);
+      if (lane == 0) sOff[nJp] = total;
+      for (int t = lane; t < nIp; t += 64) sI[t] = iidx[io + t];
+      for (int t = lane; t < ROWS * LDT; t += 64) tile[t] = (T)0;
+      __syncthreads();
+      for (int f = lane; f < total; f += 64) {
+        int lo = 0, hi = nJp - 1;
+        while (lo < hi) {
+          int mid = (lo + hi + 1) >> 1;
+          if (sOff[mid] <= f) lo = mid; else hi = mid - 1;
+        }
+        const int32_t e = sStart[lo] + (f - sOff[lo]);
+        const int pos = lower_bound_lds(sI, nIp, ri[e]);
+        tile[pos * LDT + lo] = (T)cv[e];
+      }
+      __syncthreads();
+      if (g == p) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int rho = li + G * r;
+          if (rho < nIp) {
+#pragma unroll
+            for (int c = 0; c < JMAX; ++c) a[r][c] = tile[rho * LDT + c];
+            b[r] = (sI[rho] == kp) ? (T)1 : (T)0;
+          }
+        }
+      }
+      __syncthreads();
+    }
+
+    const int nJmax = wave_max_i(nJ);
+    bool sing = false;
+
+    // ---- Householder QR; Q^T is applied to the right-hand side as we go
+#pragma unroll
+    for (int j = 0; j < JMAX; ++j) {
+      if (j < nJmax) {
+        const bool act = j < nJ;
+        T tail = 0, ap = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int rho = li + G * r;
+          const T x = a[r][j];
+          if (rho > j) tail += x * x;
+          if (rho == j) ap = x;
+        }
+        tail = gsum<G>(tail);
+        const T alpha = gsum<G>(ap);
+        const T normx = sqrt(tail + alpha * alpha);
+        const T sgn = alpha >= (T)0 ? (T)1 : (T)-1;
+        const T vj = alpha + sgn * normx;
+        const T vtv = tail + vj * vj;
+        const bool ok = act && normx > (T)0;
+        if (act && !(normx > (T)0)) sing = true;
+        const T tau = ok ? (T)2 / vtv : (T)0;
+        T v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int rho = li + G * r;
+          v[r] = rho > j ? a[r][j] : (rho == j ? vj : (T)0);
+        }
+#pragma unroll
+        for (int c = j + 1; c < JMAX; ++c) {
+          if (c < nJmax) {
+            T d = 0;
+#pragma unroll
+            for (int r = 0; r < R; ++r) d += v[r] * a[r][c];
+            d = gsum<G>(d);
+            const T f = tau * d;
+#pragma unroll
+            for (int r = 0; r < R; ++r) a[r][c] -= f * v[r];
+          }
+        }
+        {
+          T d = 0;
+#pragma unroll
+          for (int r = 0; r < R; ++r) d += v[r] * b[r];
+          d = gsum<G>(d);
+          const T f = tau * d;
+#pragma unroll
+          for (int r = 0; r < R; ++r) b[r] -= f * v[r];
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int rho = li + G * r;
+          if (rho == j && act) a[r][j] = -sgn * normx;
+        }
+      }
+    }
+
+    // ---- back-substitution R m = (Q^T e)[0:nJ]
+    T macc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) macc[r] = 0;
+    T mown[MS];
+#pragma unroll
+    for (int q = 0; q < MS; ++q) mown[q] = 0;
+#pragma unroll
+    for (int c = JMAX - 1; c >= 0; --c) {
+      if (c < nJmax) {
+        const int rc = c / G;
+        T part = 0;
+        if (c < nJ && li == c % G && !sing) part = (b[rc] - macc[rc]) / a[rc][c];
+        const T mc = gsum<G>(part);
+        if (li == c % G) mown[c / G] = mc;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int rho = li + G * r;
+          if (rho < c) macc[r] += a[r][c] * mc;
+        }
+      }
+    }
+    T rs = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int rho = li + G * r;
+      if (rho >= nJ) rs += b[r] * b[r];
+    }
+    rs = gsum<G>(rs);
+    if (valid) {
+      const int64_t jo = jptr[k];
+#pragma unroll
+      for (int q = 0; q < MS; ++q) {
+        const int c = li + G * q;
+        if (c < nJ) mout[jo + c] = mown[q];
+      }
+      if (li == 0) {
+        res_out[k] = (double)sqrt(rs);
+        if (sing) atomicAdd(nsing, 1);
+      }
+    }
+  }
+}
+
+// ---- large problems: one workgroup, block in global memory ------------------
+
+constexpr int BIG_NT = 256;
+constexpr int BIG_MAXI = 4096;
+constexpr int BIG_MAXJ = 128;
+
+template <class T>
+__global__ void __launch_bounds__(BIG_NT) k_ls_qr_big(const int32_t* __restrict__ cols, int ncols,
+                                                      const int64_t* __restrict__ jptr,
+                                                      const int32_t* __restrict__ jidx,
+                                                      const int64_t* __restrict__ iptr,
+                                                      const int32_t* __restrict__ iidx,
+                                                      const int32_t* __restrict__ cp,
+                                                      const int32_t* __restrict__ ri,
+                                                      const double* __restrict__ cv,
+                                                      T* __restrict__ work, int64_t work_stride,
+                                                      T* __restrict__ mout, double* __restrict__ res_out,
+                                                      int* __restrict__ nsing) {
+  __shared__ int32_t sI[BIG_MAXI];
+  __shared__ int32_t sStart[BIG_MAXJ];
+  __shared__ int32_t sOff[BIG_MAXJ + 1];
+  __shared__ T sd[BIG_MAXJ + 1];
+  __shared__ T sm[BIG_MAXJ];
+  __shared__ T red[BIG_NT / 64];
+  const int tid = threadIdx.x, lane = tid % 64, w = tid / 64;
+  T* W = work + (int64_t)blockIdx.x * work_stride;
+  for (int64_t q = blockIdx.x; q < ncols; q += gridDim.x) {
+    const int k = cols[q];
+    const int64_t jo = jptr[k], io = iptr[k];
+    const int nJ = (int)(jptr[k + 1] - jo), nI = (int)(iptr[k + 1] - io);
+    T* bvec = W + (int64_t)nI * nJ;  // column nJ of the workspace = right-hand side
+    for (int t = tid; t < nI; t += BIG_NT) sI[t] = iidx[io + t];
+    if (tid == 0) {
+      int acc = 0;
+      for (int c = 0; c < nJ; ++c) {
+        const int32_t j = jidx[jo + c];
+        sStart[c] = cp[j];
+        sOff[c] = acc;
+        acc += cp[j + 1] - cp[j];
+      }
+      sOff[nJ] = acc;
+    }
+    for (int64_t t = tid; t < (int64_t)nI * (nJ + 1); t += BIG_NT) W[t] = (T)0;
+    __syncthreads();
+    const int total = sOff[nJ];
+    for (int f = tid; f < total; f += BIG_NT) {
+      int lo = 0, hi = nJ - 1;
+      while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (sOff[mid] <= f) lo = mid; else hi = mid - 1;
+      }
+      const int32_t e = sStart[lo] + (f - sOff[lo]);
+      const int pos = lower_bound_lds(sI, nI, ri[e]);
+      W[(int64_t)lo * nI + pos] = (T)cv[e];
+    }
+    for (int t = tid; t < nI; t += BIG_NT) bvec[t] = (sI[t] == k) ? (T)1 : (T)0;
+    __syncthreads();
+    bool sing = false;
+    for (int j = 0; j < nJ; ++j) {
+      T* colj = W + (int64_t)j * nI;
+      T tail = 0;
+      for (int t = j + 1 + tid; t < nI; t += BIG_NT) tail += colj[t] * colj[t];
+      tail = block_sum<BIG_NT>(tail, red);
+      const T alpha = j < nI ? colj[j] : (T)0;
+      const T normx = sqrt(tail + alpha * alpha);
+      const T sgn = alpha >= (T)0 ? (T)1 : (T)-1;
+      const T vj = alpha + sgn * normx;
+      const T vtv = tail + vj * vj;
+      const bool ok = normx > (T)0;
+      if (!ok) sing = true;
+      const T tau = ok ? (T)2 / vtv : (T)0;
+      __syncthreads();
+      if (tid == 0 && j < nI) colj[j] = vj;  // column j now holds v (rows >= j)
+      __syncthreads();
+      // dots with the remaining columns and the right-hand side (column nJ)
+      for (int c = j + 1 + w; c <= nJ; c += BIG_NT / 64) {
+        const T* colc = W + (int64_t)c * nI;
+        T d = 0;
+        for (int t = j + lane; t < nI; t += 64) d += colj[t] * colc[t];
+        d = wave_sum(d);
+        if (lane == 0) sd[c] = tau * d;
+      }
+      __syncthreads();
+      const int rows = nI - j;
+      const int ncol = nJ - j;  // columns j+1..nJ
+      for (int64_t t = tid; t < (int64_t)rows * ncol; t += BIG_NT) {
+        const int c = j + 1 + (int)(t / rows);
+        const int rr = j + (int)(t % rows);
+        W[(int64_t)c * nI + rr] -= sd[c] * colj[rr];
+      }
+      __syncthreads();
+      if (tid == 0 && j < nI) colj[j] = -sgn * normx;  // R_jj
+      __syncthreads();
+    }
+    // back-substitution (one wave)
+    if (w == 0) {
+      for (int c = nJ - 1; c >= 0; --c) {
+        T part = 0;
+        for (int q2 = c + 1 + lane; q2 < nJ; q2 += 64) part += W[(int64_t)q2 * nI + c] * sm[q2];
+        part = wave_sum(part);
+        if (lane == 0) sm[c] = sing ? (T)0 : (bvec[c] - part) / W[(int64_t)c * nI + c];
+        // sm is written and read by this wave only; LDS accesses of one wave are in order
+      }
+    }
+    __syncthreads();
+    T rs = 0;
+    for (int t = nJ + tid; t < nI; t += BIG_NT) rs += bvec[t] * bvec[t];
+    rs = block_sum<BIG_NT>(rs, red);
+    __syncthreads();
+    for (int c = tid; c < nJ; c += BIG_NT) mout[jo + c] = sm[c];
+    if (tid == 0) {
+      res_out[k] = (double)sqrt(rs);
+      if (sing) atomicAdd(nsing, 1);
+    }
+    __syncthreads();
+  }
+}
+
+// ---- bucketing and dispatch ---------------------------------------------------
+
+struct Variant {
+  int maxI, maxJ;
+};
+
+template <class T>
+struct VariantTable;
+
+// float: register variants, then the global-memory kernel
+template <>
+struct VariantTable<float> {
+  static constexpr int N = 7;
+  static constexpr Variant v[N] = {{16, 8}, {32, 16}, {64, 32}, {128, 32}, {256, 32}, {128, 64},
+                                   {BIG_MAXI, BIG_MAXJ}};
+};
+template <>
+struct VariantTable<double> {
+  static constexpr int N = 6;
+  static constexpr Variant v[N] = {{16, 8}, {32, 16}, {64, 32}, {128, 32}, {64, 64},
+                                   {BIG_MAXI, BIG_MAXJ}};
+};
+
+__global__ void k_bucket_assign(int32_t n, const int32_t* __restrict__ cntJ,
+                                const int32_t* __restrict__ cntI, int nv, const int* __restrict__ vmaxI,
+                                const int* __restrict__ vmaxJ, int32_t* __restrict__ bucket,
+                                int* __restrict__ bcount) {
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k >= n) return;
+  int b = -1;
+  for (int v = 0; v < nv; ++v)
+    if (cntI[k] <= vmaxI[v] && cntJ[k] <= vmaxJ[v]) { b = v; break; }
+  bucket[k] = b;
+  atomicAdd(&bcount[b < 0 ? nv : b], 1);
+}
+
+__global__ void k_bucket_scatter(int32_t n, const int32_t* __restrict__ bucket,
+                                 const int64_t* __restrict__ boff, int* __restrict__ bcur,
+                                 int32_t* __restrict__ lists) {
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k >= n) return;
+  const int b = bucket[k];
+  if (b < 0) return;
+  const int slot = atomicAdd(&bcur[b], 1);
+  lists[boff[b] + slot] = (int32_t)k;
+}
+
+template <class T, int G, int R, int JMAX>
+void launch_qr(const int32_t* list, int cnt, const int64_t* jptr, const int32_t* jidx,
+               const int64_t* iptr, const int32_t* iidx, const sai_split_s* sp, T* mout,
+               double* res, int* nsing, hipStream_t st) {
+  if (cnt <= 0) return;
+  constexpr int NP = 64 / G;
+  const unsigned grid = grid_for(cnt, NP, 1u << 20);
+  hipLaunchKernelGGL((k_ls_qr<T, G, R, JMAX>), dim3(grid), dim3(64), 0, st, list, cnt, jptr, jidx,
+                     iptr, iidx, sp->t_col_ptr.p, sp->t_row_idx.p, sp->t_cval.p, mout, res, nsing);
+  LAUNCH_CHECK();
+}
+
+template <class T>
+void dispatch_variant(int v, const int32_t* list, int cnt, const int64_t* jptr,
+                      const int32_t* jidx, const int64_t* iptr, const int32_t* iidx,
+                      const sai_split_s* sp, T* mout, double* res, int* nsing, int maxI, int maxJ,
+                      const Allocator& al, hipStream_t st) {
+  if (cnt <= 0) return;
+  constexpr bool F = sizeof(T) == 4;
+  if constexpr (F) {
+    switch (v) {
+      case 0: launch_qr<T, 16, 1, 8>(list, cnt, jptr, jidx, iptr, iidx, sp, mout, res, nsing, st); return;
+      case 1: launch_qr<T, 16, 2, 16>(list, cnt, jptr, jidx, iptr, iidx, sp, mout, res, nsing, st); return;
+      case 2: launch_qr<T, 16, 4, 32>(list, cnt, jptr, jidx, iptr, iidx, sp, mout, res, nsing, st); return;
+      case 3: launch_qr<T, 64, 2, 32>(list, cnt, jptr, jidx, iptr, iidx, sp, mout, res, nsing, st); return;
+      case 4: launch_qr<T, 64, 4, 32>(list, cnt, jptr, jidx, iptr, iidx, sp, mout, res, nsing, st); return;
+      case 5: launch_qr<T, 64, 2, 64>(list, cnt, jptr, jidx, iptr, iidx, sp, mout, res, nsing, st); return;
+      default: break;
+    }
+  } else {
+    switch (v) {
+      case 0: launch_qr<T, 16, 1, 8>(list, cnt, jptr, jidx, iptr, iidx, sp, mout, res, nsing, st); return;
+      case 1: launch_qr<T, 16, 2, 16>(list, cnt, jptr, jidx, iptr, iidx, sp, mout, res, nsing, st); return;
+      case 2: launch_qr<T, 32, 2, 32>(list, cnt, jptr, jidx, iptr, iidx, sp, mout, res, nsing, st); return;
+      case 3: launch_qr<T, 64, 2, 32>(list, cnt, jptr, jidx, iptr, iidx, sp, mout, res, nsing, st); return;
+      case 4: launch_qr<T, 64, 1, 64>(list, cnt, jptr, jidx, iptr, iidx, sp, mout, res, nsing, st); return;
+      default: break;
+    }
+  }
+  // global-memory kernel for everything larger
+  const unsigned grid = (unsigned)std::min(cnt, 1024);
+  const int64_t stride = (int64_t)maxI * (maxJ + 1);
+  DBuf<T> work(&al, (size_t)grid * stride);
+  hipLaunchKernelGGL((k_ls_qr_big<T>), dim3(grid), dim3(BIG_NT), 0, st, list, cnt, jptr, jidx, iptr,
+                     iidx, sp->t_col_ptr.p, sp->t_row_idx.p, sp->t_cval.p, work.p, stride, mout, res,
+                     nsing);
+  LAUNCH_CHECK();
+  HIPC(hipStreamSynchronize(st));
+}
+
+// Solve every column's LS problem; mout is indexed like jidx.  Returns the
+// number of columns whose block was rank deficient.  bucket_cols (host, 8) gets
+// the number of columns per kernel variant.
+template <class T>
+int solve_columns(const sai_split_s* sp, const int64_t* jptr, const int32_t* jidx,
+                  const int64_t* iptr, const int32_t* iidx, const int32_t* cntJ,
+                  const int32_t* cntI, int maxI, int maxJ, T* mout, double* res,
+                  int64_t* bucket_cols, const Allocator& al, hipStream_t st) {
+  using VT = VariantTable<T>;
+  const int32_t n = sp->n;
+  constexpr int NV = VT::N;
+  int hmaxI[NV], hmaxJ[NV];
+  for (int v = 0; v < NV; ++v) { hmaxI[v] = VT::v[v].maxI; hmaxJ[v] = VT::v[v].maxJ; }
+  DBuf<int> vmax(&al, 2 * NV), bcount(&al, NV + 1), bcur(&al, NV + 1), nsing(&al, 1);
+  DBuf<int32_t> bucket(&al, (size_t)n);
+  HIPC(hipMemcpyAsync(vmax.p, hmaxI, sizeof(int) * NV, hipMemcpyHostToDevice, st));
+  HIPC(hipMemcpyAsync(vmax.p + NV, hmaxJ, sizeof(int) * NV, hipMemcpyHostToDevice, st));
+  HIPC(hipMemsetAsync(bcount.p, 0, sizeof(int) * (NV + 1), st));
+  HIPC(hipMemsetAsync(bcur.p, 0, sizeof(int) * (NV + 1), st));
+  HIPC(hipMemsetAsync(nsing.p, 0, sizeof(int), st));
+  hipLaunchKernelGGL(k_bucket_assign, dim3(grid_for(n, 256)), dim3(256), 0, st, n, cntJ, cntI, NV,
+                     vmax.p, vmax.p + NV, bucket.p, bcount.p);
+  LAUNCH_CHECK();
+  int hc[NV + 1];
+  HIPC(hipMemcpyAsync(hc, bcount.p, sizeof(int) * (NV + 1), hipMemcpyDeviceToHost, st));
+  HIPC(hipStreamSynchronize(st));
+  if (hc[NV] > 0)
+    SAI_THROW(SAI_ETOOBIG, "%d columns exceed |I| <= %d or |J| <= %d", hc[NV], BIG_MAXI, BIG_MAXJ);
+  int64_t hoff[NV + 1];
+  hoff[0] = 0;
+  for (int v = 0; v < NV; ++v) hoff[v + 1] = hoff[v] + hc[v];
+  DBuf<int64_t> boff(&al, NV + 1);
+  DBuf<int32_t> lists(&al, (size_t)n + 1);
+  HIPC(hipMemcpyAsync(boff.p, hoff, sizeof(int64_t) * (NV + 1), hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_bucket_scatter, dim3(grid_for(n, 256)), dim3(256), 0, st, n, bucket.p, boff.p,
+                     bcur.p, lists.p);
+  LAUNCH_CHECK();
+  for (int v = 0; v < NV; ++v) {
+    if (bucket_cols && v < 8) bucket_cols[v] = hc[v];
+    dispatch_variant<T>(v, lists.p + hoff[v], hc[v], jptr, jidx, iptr, iidx, sp, mout, res, nsing.p,
+                        maxI, maxJ, al, st);
+  }
+  return read_scalar(nsing.p, st);
+}
+
+template int solve_columns<float>(const sai_split_s*, const int64_t*, const int32_t*, const int64_t*,
+                                  const int32_t*, const int32_t*, const int32_t*, int, int, float*,
+                                  double*, int64_t*, const Allocator&, hipStream_t);
+template int solve_columns<double>(const sai_split_s*, const int64_t*, const int32_t*, const int64_t*,
+                                   const int32_t*, const int32_t*, const int32_t*, int, int, double*,
+                                   double*, int64_t*, const Allocator&, hipStream_t);
+
+}  // namespace sai

@@ -1,0 +1,215 @@
+// Pattern builder: J_k (pattern of column k of M) and I_k (nonzero rows of
+// A~(:, J_k)) for every column, from the CSC of A~.
+//
+// J_k = P(A~(:,k)) or, for the static PSAI-style pattern, the structural
+// P(|A~|^2 e_k) = union of P(A~(:,j)) over j in P(A~(:,k)) (Section 2.2, the
+// l = 2 member of the BPSAI envelope P((I+|A|)^l)).  I_k = union of
+// P(A~(:,j)) over j in J_k (Section 2, definition of L_k before (lsprob)).
+//
+// One wavefront (a 64-thread workgroup) per column: the candidate indices of a
+// union are gathered into LDS, bitonic-sorted and de-duplicated with a ballot
+// prefix, so both lists come out sorted ascending.  A count pass sizes the
+// lists, a prefix sum places them, and a fill pass writes them.
+#include "sai_internal.hpp"
+
+namespace sai {
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (WAVE - 1); }
+
+// Gather the concatenation of P(A~(:, L[t])) for t < nL into cand[0..m); returns m
+// (or -1 if it would exceed cap).  L and the scratch arrays live in LDS.
+__device__ int gather_cols(const int32_t* __restrict__ cp, const int32_t* __restrict__ ri,
+                           const int32_t* L, int nL, int32_t* cand, int cap, int32_t* s_start,
+                           int32_t* s_off /* nL+1 */) {
+  const int l = lane_id();
+  // column starts and a running prefix of the counts
+  int base = 0;
+  for (int t0 = 0; t0 < nL; t0 += WAVE) {
+    const int t = t0 + l;
+    int c = 0;
+    if (t < nL) {
+      const int32_t j = L[t];
+      const int32_t a = cp[j];
+      c = cp[j + 1] - a;
+      s_start[t] = a;
+    }
+    // inclusive wave scan of c
+    int incl = c;
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+      int v = __shfl_up(incl, o, WAVE);
+      if (l >= o) incl += v;
+    }
+    if (t < nL) s_off[t] = base + incl - c;
+    base += __shfl(incl, WAVE - 1, WAVE);
+  }
+  if (l == 0) s_off[nL] = base;
+  __syncthreads();
+  if (base > cap) return -1;
+  for (int f = l; f < base; f += WAVE) {
+    // t = last index with s_off[t] <= f
+    int lo = 0, hi = nL - 1;
+    while (lo < hi) {
+      int mid = (lo + hi + 1) >> 1;
+      if (s_off[mid] <= f) lo = mid; else hi = mid - 1;
+    }
+    cand[f] = ri[s_start[lo] + (f - s_off[lo])];
+  }
+  __syncthreads();
+  return base;
+}
+
+// Sort cand[0..m) ascending in place (bitonic over the next power of two) and
+// remove duplicates; returns the number of unique values.
+__device__ int sort_unique(int32_t* cand, int m, int cap) {
+  const int l = lane_id();
+  int P = 1;
+  while (P < m) P <<= 1;
+  if (P > cap) P = cap;  // m <= cap and cap is a power of two
+  for (int i = m + l; i < P; i += WAVE) cand[i] = 0x7fffffff;
+  __syncthreads();
+  for (int k = 2; k <= P; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int t = l; t < (P >> 1); t += WAVE) {
+        const int i = 2 * j * (t / j) + (t % j);
+        const int q = i + j;
+        const int32_t a = cand[i], b = cand[q];
+        const bool up = (i & k) == 0;
+        if ((a > b) == up) { cand[i] = b; cand[q] = a; }
+      }
+      __syncthreads();
+    }
+  }
+  int out = 0;
+  for (int c0 = 0; c0 < m; c0 += WAVE) {
+    const int i = c0 + l;
+    int32_t v = 0;
+    bool keep = false;
+    if (i < m) {
+      v = cand[i];
+      keep = (i == 0) || (cand[i - 1] != v);
+    }
+    const unsigned long long bal = __ballot(keep);
+    const int before = __popcll(bal & ((1ull << l) - 1ull));
+    __syncthreads();
+    if (keep) cand[out + before] = v;
+    out += __popcll(bal);
+    __syncthreads();
+  }
+  return out;
+}
+
+template <int CAP>
+__global__ void __launch_bounds__(64) k_pattern(int32_t n, int kind, const int32_t* __restrict__ cp,
+                                                const int32_t* __restrict__ ri, int mode,
+                                                const int32_t* __restrict__ only /* flags or NULL */,
+                                                int want,
+                                                int32_t* __restrict__ cntJ, int32_t* __restrict__ cntI,
+                                                const int64_t* __restrict__ jptr,
+                                                int32_t* __restrict__ jout,
+                                                const int64_t* __restrict__ iptr,
+                                                int32_t* __restrict__ iout, int* __restrict__ nover) {
+  constexpr int CAPJ = 256;
+  __shared__ int32_t cand[CAP];
+  __shared__ int32_t sJ[CAPJ];
+  __shared__ int32_t s_start[CAPJ];
+  __shared__ int32_t s_off[CAPJ + 1];
+  const int l = lane_id();
+  for (int64_t k = blockIdx.x; k < n; k += gridDim.x) {
+    if (only && only[k] != want) continue;
+    int nJ;
+    // ---- J_k
+    const int32_t a0 = cp[k], c0 = cp[k + 1] - cp[k];
+    if (kind == SAI_PAT_A2) {
+      // L = P(A~(:,k)), kept in sJ temporarily
+      if (c0 > CAPJ) { if (l == 0 && mode == 0) { cntJ[k] = -1; atomicAdd(nover, 1); } continue; }
+      for (int t = l; t < c0; t += WAVE) sJ[t] = ri[a0 + t];
+      __syncthreads();
+      int m = gather_cols(cp, ri, sJ, c0, cand, CAP, s_start, s_off);
+      if (m < 0) { if (l == 0 && mode == 0) { cntJ[k] = -1; atomicAdd(nover, 1); } __syncthreads(); continue; }
+      nJ = sort_unique(cand, m, CAP);
+      if (nJ > CAPJ) { if (l == 0 && mode == 0) { cntJ[k] = -1; atomicAdd(nover, 1); } __syncthreads(); continue; }
+      for (int t = l; t < nJ; t += WAVE) sJ[t] = cand[t];
+      __syncthreads();
+    } else {
+      if (c0 > CAPJ) { if (l == 0 && mode == 0) { cntJ[k] = -1; atomicAdd(nover, 1); } continue; }
+      nJ = c0;
+      for (int t = l; t < nJ; t += WAVE) sJ[t] = ri[a0 + t];
+      __syncthreads();
+    }
+    // ---- I_k
+    int m = gather_cols(cp, ri, sJ, nJ, cand, CAP, s_start, s_off);
+    if (m < 0) { if (l == 0 && mode == 0) { cntJ[k] = -1; atomicAdd(nover, 1); } __syncthreads(); continue; }
+    const int nI = sort_unique(cand, m, CAP);
+    if (mode == 0) {
+      if (l == 0) { cntJ[k] = nJ; cntI[k] = nI; }
+    } else {
+      const int64_t jo = jptr[k], io = iptr[k];
+      for (int t = l; t < nJ; t += WAVE) jout[jo + t] = sJ[t];
+      for (int t = l; t < nI; t += WAVE) iout[io + t] = cand[t];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_flag_neg(int32_t n, const int32_t* cnt, int32_t* flag) {
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k < n) flag[k] = cnt[k] < 0 ? 1 : 0;
+}
+
+// Sizes, offsets and lists of J_k and I_k.  jptr/iptr get n+1 entries.
+void build_patterns(const sai_split_s* sp, int kind, hipStream_t st, const Allocator& al,
+                    DBuf<int64_t>& jptr, DBuf<int32_t>& jidx, DBuf<int64_t>& iptr,
+                    DBuf<int32_t>& iidx, DBuf<int32_t>& cntJ, DBuf<int32_t>& cntI) {
+  const int32_t n = sp->n;
+  cntJ.alloc(&al, (size_t)n + 1);
+  cntI.alloc(&al, (size_t)n + 1);
+  DBuf<int> nover(&al, 2);
+  HIPC(hipMemsetAsync(nover.p, 0, 2 * sizeof(int), st));
+  const unsigned grid = (unsigned)std::min<int64_t>(n, 1 << 20);
+  constexpr int CAP_S = 1024, CAP_L = 8192;
+  hipLaunchKernelGGL((k_pattern<CAP_S>), dim3(grid), dim3(64), 0, st, n, kind, sp->t_col_ptr.p,
+                     sp->t_row_idx.p, 0, (const int32_t*)nullptr, 0, cntJ.p, cntI.p,
+                     (const int64_t*)nullptr, (int32_t*)nullptr, (const int64_t*)nullptr,
+                     (int32_t*)nullptr, nover.p);
+  LAUNCH_CHECK();
+  const int over = read_scalar(nover.p, st);
+  DBuf<int32_t> flag;
+  if (over > 0) {
+    flag.alloc(&al, (size_t)n + 1);
+    hipLaunchKernelGGL(k_flag_neg, dim3(grid_for(n, 256)), dim3(256), 0, st, n, cntJ.p, flag.p);
+    LAUNCH_CHECK();
+    HIPC(hipMemsetAsync(nover.p, 0, 2 * sizeof(int), st));
+    hipLaunchKernelGGL((k_pattern<CAP_L>), dim3(grid), dim3(64), 0, st, n, kind, sp->t_col_ptr.p,
+                       sp->t_row_idx.p, 0, (const int32_t*)flag.p, 1, cntJ.p, cntI.p,
+                       (const int64_t*)nullptr, (int32_t*)nullptr, (const int64_t*)nullptr,
+                       (int32_t*)nullptr, nover.p);
+    LAUNCH_CHECK();
+    if (read_scalar(nover.p, st) > 0)
+      SAI_THROW(SAI_ETOOBIG, "a pattern union exceeds %d candidate indices", CAP_L);
+  }
+  jptr.alloc(&al, (size_t)n + 1);
+  iptr.alloc(&al, (size_t)n + 1);
+  exclusive_scan_i32_to_i64(cntJ.p, jptr.p, n, al, st);
+  exclusive_scan_i32_to_i64(cntI.p, iptr.p, n, al, st);
+  int64_t tot[2];
+  HIPC(hipMemcpyAsync(&tot[0], jptr.p + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  HIPC(hipMemcpyAsync(&tot[1], iptr.p + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  HIPC(hipStreamSynchronize(st));
+  jidx.alloc(&al, (size_t)tot[0] + 1);
+  iidx.alloc(&al, (size_t)tot[1] + 1);
+  hipLaunchKernelGGL((k_pattern<CAP_S>), dim3(grid), dim3(64), 0, st, n, kind, sp->t_col_ptr.p,
+                     sp->t_row_idx.p, 1, over > 0 ? (const int32_t*)flag.p : (const int32_t*)nullptr, 0,
+                     cntJ.p, cntI.p, (const int64_t*)jptr.p, jidx.p, (const int64_t*)iptr.p, iidx.p,
+                     nover.p);
+  LAUNCH_CHECK();
+  if (over > 0) {
+    // columns that overflowed the small kernel are re-filled by the large one
+    hipLaunchKernelGGL((k_pattern<CAP_L>), dim3(grid), dim3(64), 0, st, n, kind, sp->t_col_ptr.p,
+                       sp->t_row_idx.p, 1, (const int32_t*)flag.p, 1, cntJ.p, cntI.p,
+                       (const int64_t*)jptr.p, jidx.p, (const int64_t*)iptr.p, iidx.p, nover.p);
+    LAUNCH_CHECK();
+  }
+}
+
+}  // namespace sai

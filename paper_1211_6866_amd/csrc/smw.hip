@@ -1,0 +1,371 @@
+// SMW recovery, residual check, Procedure * end to end, and the adjoint.
+//
+// Recovery (Procedure * step 3, (update1); Section 4 (composi)): with
+// Y = [y_hat, W_hat] (n x (s+1), row-major) and V = (e_{j_1} .. e_{j_s}),
+//   K = I + W_hat(j_d, :),  z = K^{-1} y_hat(j_d),  x = y_hat - W_hat z,
+// K factored by LU with partial pivoting in float64; c = ||z||.
+// Residual (rrnorm): rr = ||b - A~ x - U x(j)|| / ||b||, A = A~ + U V^T.
+// Adjoint (Theorem 3.1 applied to A^T = A~^T + V U^T): A~^T [eta, Z] =
+// [g, V], K' = I + U^T Z, lambda = eta - Z K'^{-1} U^T eta; dL/db = lambda and
+// dL/dA_ij = -lambda_i x_j.
+#include "sai_internal.hpp"
+
+namespace sai {
+namespace {
+
+constexpr int NT = 256;
+constexpr int NBR = 1024;
+
+__global__ void k_smw_gather(int s, int kk, const int32_t* __restrict__ D, const double* __restrict__ Y,
+                             double* __restrict__ K, double* __restrict__ rhs) {
+  const int t = blockIdx.x * NT + threadIdx.x;
+  if (t >= s * s) return;
+  const int d = t / s, e = t % s;
+  K[t] = (d == e ? 1.0 : 0.0) + Y[(int64_t)D[d] * kk + 1 + e];
+  if (e == 0) rhs[d] = Y[(int64_t)D[d] * kk];
+}
+
+// x_i = Y[i,0] - sum_e Y[i, 1+e] z_e
+__global__ void k_smw_apply(int64_t n, int s, int kk, const double* __restrict__ Y,
+                            const double* __restrict__ z, double* __restrict__ x) {
+  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
+    double acc = Y[i * kk];
+    for (int e = 0; e < s; ++e) acc -= Y[i * kk + 1 + e] * z[e];
+    x[i] = acc;
+  }
+}
+
+// partial sums of ||b - A~ x - U x(j)||^2 and ||b||^2
+__global__ void __launch_bounds__(NT) k_residual(int64_t n, const int32_t* __restrict__ rp,
+                                                 const int32_t* __restrict__ ci,
+                                                 const double* __restrict__ v,
+                                                 const int32_t* __restrict__ urp,
+                                                 const int32_t* __restrict__ ucol,
+                                                 const double* __restrict__ uval,
+                                                 const int32_t* __restrict__ D,
+                                                 const double* __restrict__ b,
+                                                 const double* __restrict__ x, double* __restrict__ part) {
+  __shared__ double red[NT / WAVE];
+  double a1 = 0.0, a2 = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
+    double y = 0.0;
+    for (int32_t e = rp[i]; e < rp[i + 1]; ++e) y += v[e] * x[ci[e]];
+    for (int32_t e = urp[i]; e < urp[i + 1]; ++e) y += uval[e] * x[D[ucol[e]]];
+    const double r = b[i] - y;
+    a1 += r * r;
+    a2 += b[i] * b[i];
+  }
+  a1 = block_sum<NT>(a1, red);
+  a2 = block_sum<NT>(a2, red);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = a1;
+    part[NBR + blockIdx.x] = a2;
+  }
+}
+
+__global__ void __launch_bounds__(NT) k_residual_final(int nb, const double* part, double* out) {
+  __shared__ double red[NT / WAVE];
+  double a1 = 0.0, a2 = 0.0;
+  for (int i = threadIdx.x; i < nb; i += NT) {
+    a1 += part[i];
+    a2 += part[NBR + i];
+  }
+  a1 = block_sum<NT>(a1, red);
+  a2 = block_sum<NT>(a2, red);
+  if (threadIdx.x == 0) {
+    out[0] = a1;
+    out[1] = a2;
+  }
+}
+
+// R = [b | U] (row-major n x (s+1))
+__global__ void k_rhs_bu(int64_t n, int s, const double* __restrict__ b,
+                         const int32_t* __restrict__ urp, const int32_t* __restrict__ ucol,
+                         const double* __restrict__ uval, double* __restrict__ R) {
+  const int kk = s + 1;
+  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
+    R[i * kk] = b[i];
+    for (int d = 0; d < s; ++d) R[i * kk + 1 + d] = 0.0;
+    for (int32_t e = urp[i]; e < urp[i + 1]; ++e) R[i * kk + 1 + ucol[e]] = uval[e];
+  }
+}
+
+// R = [g | V] with V = (e_{j_1}..e_{j_s})
+__global__ void k_rhs_gv(int64_t n, int s, const double* __restrict__ g, double* __restrict__ R) {
+  const int kk = s + 1;
+  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
+    R[i * kk] = g[i];
+    for (int d = 0; d < s; ++d) R[i * kk + 1 + d] = 0.0;
+  }
+}
+__global__ void k_set_units(int s, const int32_t* D, double* R) {
+  const int d = blockIdx.x * NT + threadIdx.x;
+  if (d < s) R[(int64_t)D[d] * (s + 1) + 1 + d] = 1.0;
+}
+
+// correction solves: R = U - A~ W for the auxiliary columns (c-refinement)
+__global__ void k_aux_residual(int64_t n, int s, const int32_t* __restrict__ rp,
+                               const int32_t* __restrict__ ci, const double* __restrict__ v,
+                               const int32_t* __restrict__ urp, const int32_t* __restrict__ ucol,
+                               const double* __restrict__ uval, const double* __restrict__ Y,
+                               double* __restrict__ R) {
+  const int kk = s + 1;
+  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
+    for (int d = 0; d < s; ++d) {
+      double y = 0.0;
+      for (int32_t e = rp[i]; e < rp[i + 1]; ++e) y += v[e] * Y[(int64_t)ci[e] * kk + 1 + d];
+      R[i * s + d] = -y;
+    }
+    for (int32_t e = urp[i]; e < urp[i + 1]; ++e) R[i * s + ucol[e]] += uval[e];
+  }
+}
+__global__ void k_aux_add(int64_t n, int s, const double* __restrict__ dW, double* __restrict__ Y) {
+  const int kk = s + 1;
+  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT)
+    for (int d = 0; d < s; ++d) Y[i * kk + 1 + d] += dW[i * s + d];
+}
+
+// P = U^T Y (s x kk): block b accumulates the U entries of its row range in row
+// order; lane e owns column e.  Then the partials are summed over blocks in order.
+constexpr int UTY_ROWS = 4096;
+__global__ void __launch_bounds__(64) k_uty_partial(int64_t n, int s, int kk,
+                                                    const int32_t* __restrict__ urp,
+                                                    const int32_t* __restrict__ ucol,
+                                                    const double* __restrict__ uval,
+                                                    const double* __restrict__ Y,
+                                                    double* __restrict__ part) {
+  extern __shared__ double acc[];  // s * kk
+  const int e = threadIdx.x;
+  for (int t = e; t < s * kk; t += 64) acc[t] = 0.0;
+  __syncthreads();
+  const int64_t i0 = (int64_t)blockIdx.x * UTY_ROWS;
+  const int64_t i1 = std::min<int64_t>(n, i0 + UTY_ROWS);
+  for (int64_t i = i0; i < i1; ++i) {
+    for (int32_t q = urp[i]; q < urp[i + 1]; ++q) {
+      const int d = ucol[q];
+      const double u = uval[q];
+      for (int c = e; c < kk; c += 64) acc[d * kk + c] += u * Y[i * kk + c];
+    }
+  }
+  __syncthreads();
+  for (int t = e; t < s * kk; t += 64) part[(int64_t)blockIdx.x * s * kk + t] = acc[t];
+}
+__global__ void k_uty_final(int nb, int s, int kk, const double* __restrict__ part,
+                            double* __restrict__ P) {
+  const int t = blockIdx.x * NT + threadIdx.x;
+  if (t >= s * kk) return;
+  double a = 0.0;
+  for (int b = 0; b < nb; ++b) a += part[(int64_t)b * s * kk + t];
+  P[t] = a;
+}
+// K' = I + P[:, 1:], rhs = P[:, 0]
+__global__ void k_kprime(int s, int kk, const double* P, double* K, double* rhs) {
+  const int t = blockIdx.x * NT + threadIdx.x;
+  if (t >= s * s) return;
+  const int d = t / s, e = t % s;
+  K[t] = (d == e ? 1.0 : 0.0) + P[d * kk + 1 + e];
+  if (e == 0) rhs[d] = P[d * kk];
+}
+
+__global__ void k_grad_a(int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                         const double* __restrict__ lam, const double* __restrict__ x,
+                         double* __restrict__ ga) {
+  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
+    const double l = lam[i];
+    for (int32_t e = rp[i]; e < rp[i + 1]; ++e) ga[e] = -l * x[ci[e]];
+  }
+}
+
+unsigned rows_grid(int64_t n) { return grid_for(n, NT, 8192); }
+
+std::vector<double> thresholds(double bnorm, int s, double eps, double c) {
+  std::vector<double> t(s + 1);
+  t[0] = 0.5 * eps * bnorm;
+  for (int d = 1; d <= s; ++d) t[d] = eps * bnorm / (2.0 * std::sqrt((double)s) * c);
+  return t;
+}
+
+}  // namespace
+
+void smw_recover(const sai_split_s* sp, const double* Y, double* x, double* c_host, hipStream_t st) {
+  const Allocator al{sp->al.a, st};
+  const int s = sp->s, kk = s + 1;
+  const int64_t n = sp->n;
+  if (s == 0) {
+    hipLaunchKernelGGL(k_smw_apply, dim3(rows_grid(n)), dim3(NT), 0, st, n, 0, 1, Y,
+                       (const double*)nullptr, x);
+    LAUNCH_CHECK();
+    if (c_host) *c_host = 0.0;
+    HIPC(hipStreamSynchronize(st));
+    return;
+  }
+  DBuf<double> K(&al, (size_t)s * s), z(&al, (size_t)s);
+  hipLaunchKernelGGL(k_smw_gather, dim3(grid_for(s * s, NT)), dim3(NT), 0, st, s, kk,
+                     sp->dense_cols.p, Y, K.p, z.p);
+  LAUNCH_CHECK();
+  if (!dense_lu_solve(K.p, z.p, s, 1, al, st))
+    SAI_THROW(SAI_ESINGULAR, "I + V^T W is singular (zero pivot)");
+  hipLaunchKernelGGL(k_smw_apply, dim3(rows_grid(n)), dim3(NT), 0, st, n, s, kk, Y,
+                     (const double*)z.p, x);
+  LAUNCH_CHECK();
+  if (c_host) {
+    std::vector<double> hz(s);
+    HIPC(hipMemcpyAsync(hz.data(), z.p, sizeof(double) * s, hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    double a = 0.0;
+    for (double v : hz) a += v * v;
+    *c_host = std::sqrt(a);
+  }
+  HIPC(hipStreamSynchronize(st));
+}
+
+double residual_impl(const sai_split_s* sp, const double* b, const double* x, hipStream_t st) {
+  const Allocator al{sp->al.a, st};
+  const int64_t n = sp->n;
+  DBuf<double> part(&al, 2 * NBR + 2);
+  const unsigned nb = grid_for(n, NT, NBR);
+  hipLaunchKernelGGL(k_residual, dim3(nb), dim3(NT), 0, st, n, sp->t_row_ptr.p, sp->t_col_idx.p,
+                     sp->t_val.p, sp->u_row_ptr.p, sp->u_col.p, sp->u_val.p, sp->dense_cols.p, b, x,
+                     part.p);
+  LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_residual_final, dim3(1), dim3(NT), 0, st, (int)nb, part.p, part.p + 2 * NBR);
+  LAUNCH_CHECK();
+  double h[2];
+  HIPC(hipMemcpyAsync(h, part.p + 2 * NBR, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPC(hipStreamSynchronize(st));
+  return h[1] > 0.0 ? std::sqrt(h[0] / h[1]) : std::sqrt(h[0]);
+}
+
+void solve_impl(const sai_split_s* sp, const sai_precond_s* pc, const double* b, double* x,
+                const sai_solve_opts& o, hipStream_t st, sai_solve_stats* stats) {
+  const Allocator al{sp->al.a, st};
+  const int s = sp->s, kk = s + 1;
+  const int64_t n = sp->n;
+  if (kk > 64) SAI_THROW(SAI_ETOOBIG, "s + 1 = %d exceeds 64 right-hand sides", kk);
+  EventTimer t_solve, t_smw, t_chk;
+  DBuf<double> R(&al, (size_t)n * kk), Y(&al, (size_t)n * kk);
+  hipLaunchKernelGGL(k_rhs_bu, dim3(rows_grid(n)), dim3(NT), 0, st, n, s, b, sp->u_row_ptr.p,
+                     sp->u_col.p, sp->u_val.p, R.p);
+  LAUNCH_CHECK();
+  const double bnorm = dev_norm2(b, n, 1, al, st);
+  std::vector<double> thr = thresholds(bnorm, s, o.eps, 1.0);
+  std::vector<int32_t> its(kk, 0), sts(kk, 0);
+  t_solve.start(st);
+  int code = krylov_impl(sp, pc, 0, kk, R.p, Y.p, thr.data(), o, st, its.data(), sts.data());
+  t_solve.stop(st);
+  double c = 0.0;
+  t_smw.start(st);
+  smw_recover(sp, Y.p, x, &c, st);
+  t_smw.stop(st);
+  t_chk.start(st);
+  double rr = residual_impl(sp, b, x, st);
+  t_chk.stop(st);
+  float extra_ms = 0.0f;
+  if (o.c_mode == SAI_C_ONE_THEN_REFINE && rr >= o.eps && c > 1.0 && s > 0 && code == SAI_OK) {
+    // continue the auxiliary solves to the thresholds with the computed c
+    EventTimer t_ref;
+    t_ref.start(st);
+    std::vector<double> thr2 = thresholds(bnorm, s, o.eps, c);
+    DBuf<double> Raux(&al, (size_t)n * s), dW(&al, (size_t)n * s);
+    hipLaunchKernelGGL(k_aux_residual, dim3(rows_grid(n)), dim3(NT), 0, st, n, s, sp->t_row_ptr.p,
+                       sp->t_col_idx.p, sp->t_val.p, sp->u_row_ptr.p, sp->u_col.p, sp->u_val.p,
+                       Y.p, Raux.p);
+    LAUNCH_CHECK();
+    std::vector<int32_t> its2(s, 0), sts2(s, 0);
+    code = krylov_impl(sp, pc, 0, s, Raux.p, dW.p, thr2.data() + 1, o, st, its2.data(), sts2.data());
+    hipLaunchKernelGGL(k_aux_add, dim3(rows_grid(n)), dim3(NT), 0, st, n, s, dW.p, Y.p);
+    LAUNCH_CHECK();
+    for (int d = 0; d < s; ++d) its[d + 1] += its2[d];
+    smw_recover(sp, Y.p, x, &c, st);
+    rr = residual_impl(sp, b, x, st);
+    t_ref.stop(st);
+    extra_ms = t_ref.ms();
+  }
+  if (stats) {
+    stats->s = s;
+    stats->status = code;
+    int mx = 0;
+    for (int q = 0; q < kk; ++q) mx = std::max(mx, its[q]);
+    stats->iters_max = mx;
+    if (stats->iters)
+      for (int q = 0; q < kk; ++q) stats->iters[q] = its[q];
+    stats->rr = rr;
+    stats->a = rr / o.eps;
+    stats->c = c;
+    stats->t_solve_ms = t_solve.ms() + extra_ms;
+    stats->t_smw_ms = t_smw.ms();
+    stats->t_check_ms = t_chk.ms();
+  }
+  if (code != SAI_OK) throw Error{code, "Krylov solve did not converge on every column"};
+}
+
+void backward_impl(const sai_split_s* sp, const sai_precond_s* pc, const double* x, const double* gx,
+                   double* gb, double* ga, const sai_solve_opts& o, hipStream_t st,
+                   sai_solve_stats* stats) {
+  const Allocator al{sp->al.a, st};
+  const int s = sp->s, kk = s + 1;
+  const int64_t n = sp->n;
+  if (kk > 64) SAI_THROW(SAI_ETOOBIG, "s + 1 = %d exceeds 64 right-hand sides", kk);
+  EventTimer t_solve, t_smw;
+  DBuf<double> R(&al, (size_t)n * kk), Y(&al, (size_t)n * kk), lam(&al, (size_t)n);
+  hipLaunchKernelGGL(k_rhs_gv, dim3(rows_grid(n)), dim3(NT), 0, st, n, s, gx, R.p);
+  LAUNCH_CHECK();
+  if (s > 0) {
+    hipLaunchKernelGGL(k_set_units, dim3(grid_for(s, NT)), dim3(NT), 0, st, s, sp->dense_cols.p, R.p);
+    LAUNCH_CHECK();
+  }
+  const double gnorm = dev_norm2(gx, n, 1, al, st);
+  std::vector<double> thr = thresholds(gnorm, s, o.eps, 1.0);
+  std::vector<int32_t> its(kk, 0), sts(kk, 0);
+  t_solve.start(st);
+  const int code = krylov_impl(sp, pc, 1, kk, R.p, Y.p, thr.data(), o, st, its.data(), sts.data());
+  t_solve.stop(st);
+  t_smw.start(st);
+  if (s > 0) {
+    const int64_t nb = (n + UTY_ROWS - 1) / UTY_ROWS;
+    DBuf<double> part(&al, (size_t)nb * s * kk), P(&al, (size_t)s * kk), K(&al, (size_t)s * s),
+        w(&al, (size_t)s);
+    hipLaunchKernelGGL(k_uty_partial, dim3((unsigned)nb), dim3(64), sizeof(double) * s * kk, st, n, s,
+                       kk, sp->u_row_ptr.p, sp->u_col.p, sp->u_val.p, Y.p, part.p);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_uty_final, dim3(grid_for(s * kk, NT)), dim3(NT), 0, st, (int)nb, s, kk, part.p,
+                       P.p);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_kprime, dim3(grid_for(s * s, NT)), dim3(NT), 0, st, s, kk, P.p, K.p, w.p);
+    LAUNCH_CHECK();
+    if (!dense_lu_solve(K.p, w.p, s, 1, al, st))
+      SAI_THROW(SAI_ESINGULAR, "I + U^T Z is singular (zero pivot)");
+    hipLaunchKernelGGL(k_smw_apply, dim3(rows_grid(n)), dim3(NT), 0, st, n, s, kk, Y.p,
+                       (const double*)w.p, lam.p);
+  } else {
+    hipLaunchKernelGGL(k_smw_apply, dim3(rows_grid(n)), dim3(NT), 0, st, n, 0, 1, Y.p,
+                       (const double*)nullptr, lam.p);
+  }
+  LAUNCH_CHECK();
+  if (gb) HIPC(hipMemcpyAsync(gb, lam.p, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+  if (ga) {
+    hipLaunchKernelGGL(k_grad_a, dim3(rows_grid(n)), dim3(NT), 0, st, n, sp->a_row_ptr.p,
+                       sp->a_col_idx.p, (const double*)lam.p, x, ga);
+    LAUNCH_CHECK();
+  }
+  t_smw.stop(st);
+  HIPC(hipStreamSynchronize(st));
+  if (stats) {
+    stats->s = s;
+    stats->status = code;
+    int mx = 0;
+    for (int q = 0; q < kk; ++q) mx = std::max(mx, its[q]);
+    stats->iters_max = mx;
+    if (stats->iters)
+      for (int q = 0; q < kk; ++q) stats->iters[q] = its[q];
+    stats->rr = 0.0;
+    stats->a = 0.0;
+    stats->c = 0.0;
+    stats->t_solve_ms = t_solve.ms();
+    stats->t_smw_ms = t_smw.ms();
+    stats->t_check_ms = 0.0f;
+  }
+  if (code != SAI_OK) throw Error{code, "adjoint Krylov solve did not converge on every column"};
+}
+
+}  // namespace sai

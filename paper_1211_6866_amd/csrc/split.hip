@@ -1,0 +1,370 @@
+// Split A = A~ + U V^T on the device (Procedure * step 1; Section 3 (split);
+// Section 4, first and second issues).
+//
+// p = floor(nnz/n); irregular columns are those with more than factor*p
+// nonzeros; each keeps its diagonal plus keep-1 off-diagonal entries chosen by
+// the smallest key (|i-j|, i) ("nearest", the paper's choice) or (-|a_ij|, i)
+// ("largest"); the rest move to U.  Every step is integer/index work or a value
+// copy, so the result is exact.
+#include "sai_internal.hpp"
+
+namespace sai {
+namespace {
+
+constexpr int NT = 256;
+
+enum { ERR_PTR = 1, ERR_COL = 2, ERR_ORDER = 4, ERR_VAL = 8, ERR_ZERODIAG = 16 };
+
+__global__ void k_validate_count(int32_t n, int64_t nnz, const int32_t* __restrict__ row_ptr,
+                                 const int32_t* __restrict__ col, const double* __restrict__ val,
+                                 int32_t* __restrict__ colcnt, int* __restrict__ err) {
+  const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (i == 0 && (row_ptr[0] != 0 || (int64_t)row_ptr[n] != nnz)) atomicOr(err, ERR_PTR);
+  if (i >= n) return;
+  const int32_t a = row_ptr[i], b = row_ptr[i + 1];
+  if (b < a || a < 0 || (int64_t)b > nnz) { atomicOr(err, ERR_PTR); return; }
+  int32_t prev = -1;
+  int e_local = 0;
+  for (int32_t e = a; e < b; ++e) {
+    const int32_t j = col[e];
+    if (j < 0 || j >= n) { e_local |= ERR_COL; continue; }
+    if (j <= prev) e_local |= ERR_ORDER;
+    prev = j;
+    if (!isfinite(val[e])) e_local |= ERR_VAL;
+    atomicAdd(&colcnt[j], 1);
+  }
+  if (e_local) atomicOr(err, e_local);
+}
+
+__global__ void k_dense_flag(int32_t n, const int32_t* colcnt, double thr, int32_t* flag) {
+  const int64_t j = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (j < n) flag[j] = ((double)colcnt[j] > thr) ? 1 : 0;
+}
+
+__global__ void k_dense_compact(int32_t n, const int32_t* flag, const int32_t* pos,
+                                const int32_t* colcnt, int32_t* dense_cols, int32_t* dcount,
+                                int32_t* colmap) {
+  const int64_t j = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (j >= n) return;
+  if (flag[j]) {
+    const int32_t d = pos[j];
+    dense_cols[d] = (int32_t)j;
+    dcount[d] = colcnt[j];
+    colmap[j] = d;
+  } else {
+    colmap[j] = -1;
+  }
+}
+
+// Collect (row, CSR position) of every entry of every irregular column.
+__global__ void k_dense_gather(int32_t n, const int32_t* __restrict__ row_ptr,
+                               const int32_t* __restrict__ col, const int32_t* __restrict__ colmap,
+                               const int64_t* __restrict__ doff, int32_t* __restrict__ dcur,
+                               int32_t* __restrict__ lrow, int32_t* __restrict__ lpos) {
+  const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (i >= n) return;
+  for (int32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+    const int32_t d = colmap[col[e]];
+    if (d >= 0) {
+      const int32_t slot = atomicAdd(&dcur[d], 1);
+      lrow[doff[d] + slot] = (int32_t)i;
+      lpos[doff[d] + slot] = e;
+    }
+  }
+}
+
+struct Key {
+  double a;
+  int32_t i;
+};
+__device__ __forceinline__ bool key_less(const Key& x, const Key& y) {
+  return x.a < y.a || (x.a == y.a && x.i < y.i);
+}
+
+// One workgroup per irregular column: choose the keep-1 smallest keys among the
+// off-diagonal entries by keep-1 rounds of "smallest key above the previous
+// one"; mark the others as dropped.
+__global__ void __launch_bounds__(NT) k_dense_select(const int32_t* __restrict__ dense_cols,
+                                                     const int64_t* __restrict__ doff,
+                                                     const int32_t* __restrict__ dcount,
+                                                     const int32_t* __restrict__ lrow,
+                                                     const int32_t* __restrict__ lpos,
+                                                     const double* __restrict__ val, int keep,
+                                                     int rule, uint8_t* __restrict__ drop,
+                                                     int* __restrict__ err) {
+  __shared__ double sa[NT];
+  __shared__ int32_t si[NT];
+  __shared__ int has_diag;
+  const int d = blockIdx.x;
+  const int32_t j = dense_cols[d];
+  const int64_t off = doff[d];
+  const int32_t cnt = dcount[d];
+  if (threadIdx.x == 0) has_diag = 0;
+  __syncthreads();
+  for (int32_t t = threadIdx.x; t < cnt; t += NT)
+    if (lrow[off + t] == j) has_diag = 1;
+  __syncthreads();
+  if (!has_diag) {
+    if (threadIdx.x == 0) atomicOr(err, ERR_ZERODIAG);
+    return;
+  }
+  Key last{-INFINITY, -1};
+  bool have = false;  // at least one key selected
+  for (int r = 0; r < keep - 1; ++r) {
+    Key best{INFINITY, 0x7fffffff};
+    for (int32_t t = threadIdx.x; t < cnt; t += NT) {
+      const int32_t i = lrow[off + t];
+      if (i == j) continue;
+      Key k;
+      k.i = i;
+      k.a = (rule == SAI_KEEP_NEAREST) ? (double)(i > j ? i - j : j - i) : -fabs(val[lpos[off + t]]);
+      if (key_less(last, k) && key_less(k, best)) best = k;
+    }
+    sa[threadIdx.x] = best.a;
+    si[threadIdx.x] = best.i;
+    __syncthreads();
+    for (int o = NT / 2; o > 0; o >>= 1) {
+      if ((int)threadIdx.x < o) {
+        Key x{sa[threadIdx.x], si[threadIdx.x]}, y{sa[threadIdx.x + o], si[threadIdx.x + o]};
+        if (key_less(y, x)) { sa[threadIdx.x] = y.a; si[threadIdx.x] = y.i; }
+      }
+      __syncthreads();
+    }
+    Key b{sa[0], si[0]};
+    __syncthreads();
+    if (b.i == 0x7fffffff) break;  // fewer off-diagonals than keep-1
+    last = b;
+    have = true;
+  }
+  for (int32_t t = threadIdx.x; t < cnt; t += NT) {
+    const int32_t i = lrow[off + t];
+    if (i == j) continue;
+    bool kept = false;
+    if (have) {
+      Key k;
+      k.i = i;
+      k.a = (rule == SAI_KEEP_NEAREST) ? (double)(i > j ? i - j : j - i) : -fabs(val[lpos[off + t]]);
+      kept = !key_less(last, k);  // k <= last
+    }
+    if (!kept) drop[lpos[off + t]] = 1;
+  }
+}
+
+__global__ void k_row_counts(int32_t n, const int32_t* __restrict__ row_ptr,
+                             const uint8_t* __restrict__ drop, int32_t* __restrict__ tcnt,
+                             int32_t* __restrict__ ucnt) {
+  const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (i >= n) return;
+  int32_t t = 0, u = 0;
+  for (int32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+    if (drop[e]) ++u; else ++t;
+  }
+  tcnt[i] = t;
+  ucnt[i] = u;
+}
+
+__global__ void k_row_scatter(int32_t n, const int32_t* __restrict__ row_ptr,
+                              const int32_t* __restrict__ col, const double* __restrict__ val,
+                              const uint8_t* __restrict__ drop, const int32_t* __restrict__ colmap,
+                              const int32_t* __restrict__ t_row_ptr, int32_t* __restrict__ t_col,
+                              double* __restrict__ t_val, const int32_t* __restrict__ u_row_ptr,
+                              int32_t* __restrict__ u_col, double* __restrict__ u_val) {
+  const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (i >= n) return;
+  int32_t pt = t_row_ptr[i], pu = u_row_ptr[i];
+  for (int32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+    if (drop[e]) {
+      u_col[pu] = colmap[col[e]];
+      u_val[pu] = val[e];
+      ++pu;
+    } else {
+      t_col[pt] = col[e];
+      t_val[pt] = val[e];
+      ++pt;
+    }
+  }
+}
+
+}  // namespace
+
+// ---- CSR -> CSC transpose (shared with the build) ----------------------------
+
+__global__ void k_tr_count(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                           int32_t* __restrict__ cnt) {
+  const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (i >= n) return;
+  for (int32_t e = rp[i]; e < rp[i + 1]; ++e) atomicAdd(&cnt[ci[e]], 1);
+}
+
+template <class V>
+__global__ void k_tr_scatter(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                             const V* __restrict__ v, const int32_t* __restrict__ cp,
+                             int32_t* __restrict__ cur, int32_t* __restrict__ ri, V* __restrict__ cv) {
+  const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (i >= n) return;
+  for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+    const int32_t j = ci[e];
+    const int32_t slot = cp[j] + atomicAdd(&cur[j], 1);
+    ri[slot] = (int32_t)i;
+    cv[slot] = v[e];
+  }
+}
+
+// Sort each column segment by row (insertion sort; segments are short for the
+// regular sparse matrices this is used on).  Makes the transpose deterministic.
+template <class V>
+__global__ void k_tr_sort(int32_t m, const int32_t* __restrict__ cp, int32_t* __restrict__ ri,
+                          V* __restrict__ cv) {
+  const int64_t j = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (j >= m) return;
+  const int32_t a = cp[j], b = cp[j + 1];
+  for (int32_t x = a + 1; x < b; ++x) {
+    const int32_t r = ri[x];
+    const V w = cv[x];
+    int32_t y = x - 1;
+    while (y >= a && ri[y] > r) {
+      ri[y + 1] = ri[y];
+      cv[y + 1] = cv[y];
+      --y;
+    }
+    ri[y + 1] = r;
+    cv[y + 1] = w;
+  }
+}
+
+template <class V>
+void csr_transpose(int32_t nrows, int32_t ncols, const int32_t* rp, const int32_t* ci, const V* v,
+                   int32_t* cp, int32_t* ri, V* cv, const Allocator& al, hipStream_t st) {
+  DBuf<int32_t> cnt(&al, (size_t)ncols + 1);
+  HIPC(hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * ((size_t)ncols + 1), st));
+  hipLaunchKernelGGL(k_tr_count, dim3(grid_for(nrows, NT)), dim3(NT), 0, st, nrows, rp, ci, cnt.p);
+  LAUNCH_CHECK();
+  exclusive_scan_i32(cnt.p, cp, ncols, al, st);
+  HIPC(hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * ((size_t)ncols + 1), st));
+  hipLaunchKernelGGL((k_tr_scatter<V>), dim3(grid_for(nrows, NT)), dim3(NT), 0, st, nrows, rp, ci, v,
+                     cp, cnt.p, ri, cv);
+  LAUNCH_CHECK();
+  hipLaunchKernelGGL((k_tr_sort<V>), dim3(grid_for(ncols, NT)), dim3(NT), 0, st, ncols, cp, ri, cv);
+  LAUNCH_CHECK();
+}
+
+template void csr_transpose<double>(int32_t, int32_t, const int32_t*, const int32_t*, const double*,
+                                    int32_t*, int32_t*, double*, const Allocator&, hipStream_t);
+template void csr_transpose<float>(int32_t, int32_t, const int32_t*, const int32_t*, const float*,
+                                   int32_t*, int32_t*, float*, const Allocator&, hipStream_t);
+
+void split_impl(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                const double* val, const sai_split_opts& o, const Allocator& al_in, sai_split_s* h) {
+  // every buffer (temporary or owned by the handle) refers to the handle's allocator,
+  // which lives as long as the handle
+  h->al = al_in;
+  const Allocator& al = h->al;
+  hipStream_t st = al.stream;
+  if (n <= 0 || nnz < 0 || nnz >= (int64_t)INT32_MAX || !row_ptr || (nnz > 0 && (!col_idx || !val)))
+    SAI_THROW(SAI_EINVAL, "bad CSR arguments (n=%d nnz=%lld)", n, (long long)nnz);
+  if (!(o.dense_factor > 0.0)) SAI_THROW(SAI_EINVAL, "dense_factor must be > 0");
+  if (o.rule != SAI_KEEP_NEAREST && o.rule != SAI_KEEP_LARGEST) SAI_THROW(SAI_EINVAL, "bad rule");
+  h->n = n;
+  h->nnz_a = nnz;
+  const int32_t p = (int32_t)(nnz / n);
+  h->p = p;
+  const int32_t keep = o.keep > 0 ? o.keep : (p > 0 ? p : 1);
+  h->keep = keep;
+
+  DBuf<int32_t> colcnt(&al, (size_t)n + 1), flag(&al, (size_t)n + 1), pos(&al, (size_t)n + 1),
+      colmap(&al, (size_t)n);
+  DBuf<int> err(&al, 4);
+  HIPC(hipMemsetAsync(colcnt.p, 0, sizeof(int32_t) * ((size_t)n + 1), st));
+  HIPC(hipMemsetAsync(err.p, 0, sizeof(int) * 4, st));
+  hipLaunchKernelGGL(k_validate_count, dim3(grid_for(n, NT)), dim3(NT), 0, st, n, nnz, row_ptr,
+                     col_idx, val, colcnt.p, err.p);
+  LAUNCH_CHECK();
+  const double thr = o.dense_factor * (double)p;
+  hipLaunchKernelGGL(k_dense_flag, dim3(grid_for(n, NT)), dim3(NT), 0, st, n, colcnt.p, thr, flag.p);
+  LAUNCH_CHECK();
+  exclusive_scan_i32(flag.p, pos.p, n, al, st);
+  HostStage hs(64);
+  HIPC(hipMemcpyAsync(hs.as<int32_t>(), pos.p + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIPC(hipMemcpyAsync(hs.as<int32_t>() + 1, err.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPC(hipStreamSynchronize(st));
+  const int32_t s = hs.as<int32_t>()[0];
+  const int e0 = hs.as<int32_t>()[1];
+  if (e0) SAI_THROW(SAI_EINVAL, "malformed CSR input (flags 0x%x)", e0);
+  h->s = s;
+
+  h->dense_cols.alloc(&al, (size_t)s + 1);
+  DBuf<int32_t> dcount(&al, (size_t)s + 1);
+  hipLaunchKernelGGL(k_dense_compact, dim3(grid_for(n, NT)), dim3(NT), 0, st, n, flag.p, pos.p,
+                     colcnt.p, h->dense_cols.p, dcount.p, colmap.p);
+  LAUNCH_CHECK();
+
+  DBuf<uint8_t> drop(&al, (size_t)nnz + 1);
+  HIPC(hipMemsetAsync(drop.p, 0, (size_t)nnz + 1, st));
+  int64_t nnz_u = 0;
+  if (s > 0) {
+    std::vector<int32_t> hc(s);
+    HIPC(hipMemcpyAsync(hc.data(), dcount.p, sizeof(int32_t) * s, hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    std::vector<int64_t> hoff(s + 1, 0);
+    for (int d = 0; d < s; ++d) hoff[d + 1] = hoff[d] + hc[d];
+    DBuf<int64_t> doff(&al, (size_t)s + 1);
+    DBuf<int32_t> dcur(&al, (size_t)s + 1), lrow(&al, (size_t)hoff[s] + 1), lpos(&al, (size_t)hoff[s] + 1);
+    HIPC(hipMemcpyAsync(doff.p, hoff.data(), sizeof(int64_t) * (s + 1), hipMemcpyHostToDevice, st));
+    HIPC(hipMemsetAsync(dcur.p, 0, sizeof(int32_t) * (s + 1), st));
+    hipLaunchKernelGGL(k_dense_gather, dim3(grid_for(n, NT)), dim3(NT), 0, st, n, row_ptr, col_idx,
+                       colmap.p, doff.p, dcur.p, lrow.p, lpos.p);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_dense_select, dim3(s), dim3(NT), 0, st, h->dense_cols.p, doff.p, dcount.p,
+                       lrow.p, lpos.p, val, keep, o.rule, drop.p, err.p);
+    LAUNCH_CHECK();
+    const int e1 = read_scalar(err.p, st);
+    if (e1 & ERR_ZERODIAG) SAI_THROW(SAI_EZERODIAG, "an irregular column has no diagonal entry");
+    for (int d = 0; d < s; ++d) nnz_u += hc[d] - std::min<int64_t>(hc[d], keep);
+  }
+  const int64_t nnz_t = nnz - nnz_u;
+  h->nnz_t = nnz_t;
+  h->nnz_u = nnz_u;
+
+  DBuf<int32_t> tcnt(&al, (size_t)n + 1), ucnt(&al, (size_t)n + 1);
+  hipLaunchKernelGGL(k_row_counts, dim3(grid_for(n, NT)), dim3(NT), 0, st, n, row_ptr, drop.p,
+                     tcnt.p, ucnt.p);
+  LAUNCH_CHECK();
+  h->t_row_ptr.alloc(&al, (size_t)n + 1);
+  h->u_row_ptr.alloc(&al, (size_t)n + 1);
+  exclusive_scan_i32(tcnt.p, h->t_row_ptr.p, n, al, st);
+  exclusive_scan_i32(ucnt.p, h->u_row_ptr.p, n, al, st);
+  h->t_col_idx.alloc(&al, (size_t)nnz_t + 1);
+  h->t_val.alloc(&al, (size_t)nnz_t + 1);
+  h->u_col.alloc(&al, (size_t)nnz_u + 1);
+  h->u_val.alloc(&al, (size_t)nnz_u + 1);
+  hipLaunchKernelGGL(k_row_scatter, dim3(grid_for(n, NT)), dim3(NT), 0, st, n, row_ptr, col_idx, val,
+                     drop.p, colmap.p, h->t_row_ptr.p, h->t_col_idx.p, h->t_val.p, h->u_row_ptr.p,
+                     h->u_col.p, h->u_val.p);
+  LAUNCH_CHECK();
+  {
+    int32_t tot[2];
+    HIPC(hipMemcpyAsync(&tot[0], h->t_row_ptr.p + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPC(hipMemcpyAsync(&tot[1], h->u_row_ptr.p + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    if (tot[0] != nnz_t || tot[1] != nnz_u)
+      SAI_THROW(SAI_EHIP, "split count mismatch (%d/%lld, %d/%lld)", tot[0], (long long)nnz_t, tot[1],
+                (long long)nnz_u);
+  }
+  // CSC of A~
+  h->t_col_ptr.alloc(&al, (size_t)n + 1);
+  h->t_row_idx.alloc(&al, (size_t)nnz_t + 1);
+  h->t_cval.alloc(&al, (size_t)nnz_t + 1);
+  csr_transpose<double>(n, n, h->t_row_ptr.p, h->t_col_idx.p, h->t_val.p, h->t_col_ptr.p,
+                        h->t_row_idx.p, h->t_cval.p, al, st);
+  // structure of A (gradients are returned in A's CSR order)
+  h->a_row_ptr.alloc(&al, (size_t)n + 1);
+  h->a_col_idx.alloc(&al, (size_t)nnz + 1);
+  HIPC(hipMemcpyAsync(h->a_row_ptr.p, row_ptr, sizeof(int32_t) * ((size_t)n + 1),
+                      hipMemcpyDeviceToDevice, st));
+  if (nnz > 0)
+    HIPC(hipMemcpyAsync(h->a_col_idx.p, col_idx, sizeof(int32_t) * (size_t)nnz,
+                        hipMemcpyDeviceToDevice, st));
+  HIPC(hipStreamSynchronize(st));
+}
+
+}  // namespace sai

@@ -1,0 +1,274 @@
+"""GPU path vs the FP64 oracle, through the C ABI (Python binding = marshalling only).
+
+Bars: integer/index outputs bit-exact; M per column rel. 1e-12 (FP64 build) or
+1e-4 (FP32 build); x to the residual tolerance 1e-8 (rr recomputed on the host
+in FP64) and the forward error it implies; gradients rel. 1e-5 (normwise).
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import workloads as W
+from oracle import adjoint as oadj
+from oracle import drop as odrop
+from oracle import krylov as okry
+from oracle import lsq as olsq
+from oracle import pattern as opat
+from oracle import pipeline as opipe
+from oracle import smw as osmw
+from oracle import split as osplit
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1211_6866_amd as P  # noqa: E402
+
+CASES = {
+    "c1": (1, {}),
+    "c2_12": (2, dict(dims=(12, 12, 12), s=4, density=0.2)),
+    "c2_13x9x7": (2, dict(dims=(13, 9, 7), s=3, density=0.3)),
+    "c4_40": (4, dict(dims=(40, 37), s=3, density=0.15)),
+    "c3_3000": (3, dict(n=3000, s=4, density=0.05)),
+}
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _load(name):
+    idx, kw = CASES[name]
+    w = W.make(idx, **kw)
+    return w, P.csr_to_device(w.A)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_split_bit_exact(name):
+    w, (rp, ci, va) = _load(name)
+    S = osplit.split(w.A)
+    g = P.Split(rp, ci, va)
+    assert (g.s, g.p) == (S.s, S.p)
+    arr = g.arrays()
+    assert np.array_equal(_np(arr["dense_cols"]), S.D)
+    At = S.At
+    assert np.array_equal(_np(arr["t_row_ptr"]), At.indptr)
+    assert np.array_equal(_np(arr["t_col_idx"]), At.indices)
+    assert np.array_equal(_np(arr["t_val"]), At.data)           # copies: bit-exact
+    Ct = sp.csc_matrix(At)
+    Ct.sort_indices()
+    assert np.array_equal(_np(arr["t_col_ptr"]), Ct.indptr)
+    assert np.array_equal(_np(arr["t_row_idx"]), Ct.indices)
+    assert np.array_equal(_np(arr["t_cval"]), Ct.data)
+    Ur = sp.csr_matrix(S.U)
+    Ur.sort_indices()
+    assert np.array_equal(_np(arr["u_row_ptr"]), Ur.indptr)
+    assert np.array_equal(_np(arr["u_col"]), Ur.indices)
+    assert np.array_equal(_np(arr["u_val"]), Ur.data)
+
+
+def test_split_keep_and_largest_rule():
+    w, (rp, ci, va) = _load("c2_12")
+    for keep, rule, orule in [(1, P.KEEP_NEAREST, "nearest"), (4, P.KEEP_LARGEST, "largest")]:
+        S = osplit.split(w.A, keep=keep, rule=orule)
+        g = P.Split(rp, ci, va, keep=keep, rule=rule)
+        arr = g.arrays()
+        assert np.array_equal(_np(arr["t_col_idx"]), S.At.indices)
+        assert np.array_equal(_np(arr["t_val"]), S.At.data)
+
+
+@pytest.mark.parametrize("name,kind", [("c1", P.PAT_A), ("c1", P.PAT_A2), ("c2_12", P.PAT_A2),
+                                       ("c2_13x9x7", P.PAT_A2), ("c4_40", P.PAT_A2),
+                                       ("c3_3000", P.PAT_A)])
+@pytest.mark.parametrize("prec", [P.FP64, P.FP32])
+def test_patterns_and_columns(name, kind, prec):
+    w, (rp, ci, va) = _load(name)
+    S = osplit.split(w.A)
+    C = opat.as_csc(S.At)
+    g = P.Split(rp, ci, va)
+    pc = P.Precond(g, pattern=kind, drop=P.DROP_NONE, precision=prec, keep_lists=True)
+    arr = pc.arrays()
+    jp, ji, ip, ii = (_np(arr[k]) for k in ("j_ptr", "j_idx", "i_ptr", "i_idx"))
+    mf, res = _np(arr["m_full"]).astype(np.float64), _np(arr["res"])
+    n = w.A.shape[0]
+    f = opat.pattern_A if kind == P.PAT_A else opat.pattern_A2
+    tol = 1e-12 if prec == P.FP64 else 1e-4
+    worst = 0.0
+    for k in range(n):
+        J = f(C, k)
+        assert np.array_equal(ji[jp[k]:jp[k + 1]], J), k
+        I, m, r = olsq.solve_column(C, J, k)
+        assert np.array_equal(ii[ip[k]:ip[k + 1]], I), k
+        e = np.linalg.norm(mf[jp[k]:jp[k + 1]] - m) / np.linalg.norm(m)
+        worst = max(worst, e)
+        assert e <= tol, (k, e)
+        assert abs(res[k] - r) <= (1e-12 if prec == P.FP64 else 1e-5), (k, res[k], r)
+    print(f"worst column rel err {worst:.2e}")
+
+
+@pytest.mark.parametrize("drop,prec", [(P.DROP_ABS, P.FP64), (P.DROP_TOLK, P.FP64),
+                                       (P.DROP_ABS, P.FP32)])
+def test_drop_and_assembly(drop, prec):
+    w, (rp, ci, va) = _load("c2_12")
+    S = osplit.split(w.A)
+    n = w.A.shape[0]
+    g = P.Split(rp, ci, va)
+    pc = P.Precond(g, pattern=P.PAT_A2, drop=drop, tau=2e-3, delta=0.4, precision=prec,
+                   keep_lists=True)
+    arr = pc.arrays()
+    jp, ji = _np(arr["j_ptr"]), _np(arr["j_idx"])
+    Js = [ji[jp[k]:jp[k + 1]] for k in range(n)]
+    _, ms, _ = olsq.build_columns(S.At, Js)
+    mode = {P.DROP_ABS: "abs", P.DROP_TOLK: "tolk"}[drop]
+    Mo = odrop.assemble(n, Js, ms, mode, tau=2e-3, delta=0.4, At=S.At)
+    Mg = sp.csc_matrix((_np(arr["cval"]).astype(np.float64), _np(arr["row_idx"]),
+                        _np(arr["col_ptr"])), shape=(n, n))
+    if prec == P.FP64:
+        assert np.array_equal(Mg.indptr, Mo.indptr) and np.array_equal(Mg.indices, Mo.indices)
+        assert abs(Mg - Mo).max() <= 1e-12 * abs(Mo).max()
+    else:
+        # entries within FP32 rounding of the threshold may flip; count them
+        flips = abs((Mg != 0).astype(int) - (Mo != 0).astype(int)).sum()
+        assert flips <= max(2, int(1e-4 * Mo.nnz)), flips
+    # CSR is the transpose of the CSC, bit for bit
+    Mr = sp.csr_matrix((_np(arr["val"]).astype(np.float64), _np(arr["col_idx"]), _np(arr["row_ptr"])),
+                       shape=(n, n))
+    Mg.sort_indices()
+    assert (Mr != sp.csr_matrix(Mg)).nnz == 0
+
+
+@pytest.mark.parametrize("name,method", [("c1", P.GMRES), ("c1", P.BICGSTAB), ("c2_12", P.BICGSTAB),
+                                         ("c2_13x9x7", P.BICGSTAB), ("c4_40", P.BICGSTAB),
+                                         ("c3_3000", P.BICGSTAB)])
+def test_solve_end_to_end(name, method):
+    w, (rp, ci, va) = _load(name)
+    b = torch.from_numpy(w.b).cuda()
+    g = P.Split(rp, ci, va)
+    kind = P.PAT_A if name in ("c1", "c3_3000") else P.PAT_A2
+    drop = P.DROP_NONE if kind == P.PAT_A else P.DROP_ABS
+    pc = P.Precond(g, pattern=kind, drop=drop, tau=1e-3, precision=P.FP32)
+    x, st = P.solve(g, pc, b, method=method, restart=30, eps=1e-8)
+    xs = _np(x)
+    rr = np.linalg.norm(w.b - w.A @ xs) / np.linalg.norm(w.b)
+    assert rr < 1e-8 * 1.5, (rr, st)          # c = 1 may leave rr slightly above eps
+    assert abs(rr - st["rr"]) <= 1e-3 * rr + 1e-15
+    xd = sp.linalg.spsolve(sp.csc_matrix(w.A), w.b)
+    kest = 1e4
+    assert np.linalg.norm(xs - xd) <= 2 * kest * 1e-8 * np.linalg.norm(xd)
+    # the s+1 columns each met their own stopping rule (true residuals)
+    out = opipe.run(w.A, w.b, kind="A" if kind == P.PAT_A else "A2",
+                    drop="none" if drop == P.DROP_NONE else "abs",
+                    method="gmres" if method == P.GMRES else "bicgstab")
+    print(name, "gpu iters", st["iters"], "oracle iters", out["iters"], "rr", rr, out["rr"])
+
+
+def test_krylov_block_and_smw_vs_oracle():
+    w, (rp, ci, va) = _load("c2_12")
+    S = osplit.split(w.A)
+    g = P.Split(rp, ci, va)
+    pc = P.Precond(g, pattern=P.PAT_A2, drop=P.DROP_ABS, precision=P.FP64)
+    n, s = w.A.shape[0], S.s
+    R = np.zeros((n, s + 1))
+    R[:, 0] = w.b
+    R[:, 1:] = S.U.toarray()
+    thr = okry.thresholds(np.linalg.norm(w.b), s, 1e-10)
+    Rt = torch.from_numpy(R).cuda()
+    X, its, sts, code = P.krylov(g, pc, Rt, thr)
+    assert code == P.OK and all(v == 0 for v in sts)
+    Xh = _np(X)
+    for c in range(s + 1):
+        assert np.linalg.norm(R[:, c] - S.At @ Xh[:, c]) < thr[c]
+    # SMW recovery on the same Y, compared with the oracle's recovery
+    x, cval = P.smw(g, X)
+    xo, z, co = osmw.recover(Xh[:, 0], Xh[:, 1:], S.D)
+    assert np.linalg.norm(_np(x) - xo) <= 1e-12 * np.linalg.norm(xo)
+    assert abs(cval - co) <= 1e-12 * co
+    rr = P.residual(g, torch.from_numpy(w.b).cuda(), x)
+    assert abs(rr - osmw.relres(w.A, xo, w.b)) <= 1e-6 * rr + 1e-18
+    # transposed solve
+    Xt, its, sts, code = P.krylov(g, pc, Rt, thr, transpose=True)
+    Xth = _np(Xt)
+    AtT = sp.csr_matrix(S.At.T)
+    for c in range(s + 1):
+        assert np.linalg.norm(R[:, c] - AtT @ Xth[:, c]) < thr[c]
+
+
+@pytest.mark.parametrize("name", ["c1", "c2_12", "c4_40"])
+def test_adjoint_vs_oracle(name):
+    w, (rp, ci, va) = _load(name)
+    g = P.Split(rp, ci, va)
+    kind = P.PAT_A if name == "c1" else P.PAT_A2
+    pc = P.Precond(g, pattern=kind, drop=P.DROP_ABS if kind == P.PAT_A2 else P.DROP_NONE,
+                   precision=P.FP32)
+    b = torch.from_numpy(w.b).cuda()
+    x, _ = P.solve(g, pc, b, eps=1e-12)
+    xs = W.x_star(w.A.shape[0], w.seed)
+    gx = x - torch.from_numpy(xs).cuda()
+    gb, ga, st = P.backward(g, pc, x, gx, eps=1e-12)
+    Ad = w.A.toarray()
+    xd = np.linalg.solve(Ad, w.b)
+    lam = np.linalg.solve(Ad.T, xd - xs)
+    Gd = oadj.grad_A_values(w.A, lam, xd)
+    assert np.linalg.norm(_np(gb) - lam) <= 1e-5 * np.linalg.norm(lam)
+    assert np.linalg.norm(_np(ga) - Gd) <= 1e-5 * np.linalg.norm(Gd)
+
+
+def test_autograd_function():
+    w, (rp, ci, va) = _load("c2_12")
+    a = va.clone().requires_grad_(True)
+    b = torch.from_numpy(w.b).cuda().requires_grad_(True)
+    x = P.SAISolve.apply(a, b, rp, ci, dict(pattern=P.PAT_A2, drop=P.DROP_ABS, precision=P.FP32),
+                         dict(eps=1e-12))
+    xs = torch.from_numpy(W.x_star(w.A.shape[0], w.seed)).cuda()
+    loss = 0.5 * ((x - xs) ** 2).sum()
+    loss.backward()
+    Ad = w.A.toarray()
+    xd = np.linalg.solve(Ad, w.b)
+    lam = np.linalg.solve(Ad.T, xd - _np(xs))
+    assert np.linalg.norm(_np(b.grad) - lam) <= 1e-5 * np.linalg.norm(lam)
+    assert np.linalg.norm(_np(a.grad) - oadj.grad_A_values(w.A, lam, xd)) <= 1e-5 * np.linalg.norm(lam) * np.linalg.norm(xd)
+
+
+def test_error_paths():
+    # irregular column without a diagonal -> SAI_EZERODIAG
+    n = 30
+    A = sp.lil_matrix((n, n))
+    for i in range(n):
+        if i != 3:
+            A[i, i] = 2.0
+    for i in range(n):
+        if i != 3:
+            A[i, 3] = 0.5
+    A = sp.csr_matrix(A)
+    A.indptr = A.indptr.astype(np.int32)
+    A.indices = A.indices.astype(np.int32)
+    rp, ci, va = P.csr_to_device(A)
+    with pytest.raises(P.SaiError) as e:
+        P.Split(rp, ci, va)
+    assert e.value.code == P.EZERODIAG
+    # unsorted columns -> SAI_EINVAL
+    w, (rp, ci, va) = _load("c1")
+    ci2 = ci.clone()
+    ci2[[0, 1]] = ci2[[1, 0]]
+    with pytest.raises(P.SaiError) as e:
+        P.Split(rp, ci2, va)
+    assert e.value.code == P.EINVAL
+    # maxit = 1 -> SAI_ENOCONV with outputs written
+    g = P.Split(rp, ci, va)
+    pc = P.Precond(g, pattern=P.PAT_A, drop=P.DROP_NONE)
+    x, st = P.solve(g, pc, torch.from_numpy(w.b).cuda(), maxit=1, raise_on_error=False)
+    assert st["code"] == P.ENOCONV and np.isfinite(_np(x)).all()
+
+
+def test_repeat_runs_bit_identical():
+    w, (rp, ci, va) = _load("c2_12")
+    b = torch.from_numpy(w.b).cuda()
+    outs = []
+    for _ in range(2):
+        g = P.Split(rp, ci, va)
+        pc = P.Precond(g, pattern=P.PAT_A2, drop=P.DROP_ABS, precision=P.FP32)
+        x, _ = P.solve(g, pc, b)
+        outs.append(_np(x))
+    assert np.array_equal(outs[0], outs[1])

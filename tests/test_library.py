@@ -1,0 +1,35 @@
+"""The C-ABI library loads on the host and exports every function include/sai.h declares.
+
+No compute call is made (there may be no GPU here).
+"""
+import ctypes
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sai.h")
+LIB = os.path.join(ROOT, "paper_1211_6866_amd", "libsai.so")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = set(re.findall(r"\b(sai_[a-z0-9_]+)\s*\(", text))
+    return sorted(n for n in names if not n.endswith("_fn"))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ["sai_split", "sai_build", "sai_krylov", "sai_smw", "sai_solve", "sai_backward"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(LIB):
+        from paper_1211_6866_amd import build
+        build.build()
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+    lib.sai_strerror.restype = ctypes.c_char_p
+    assert lib.sai_strerror(0) == b"ok"
