@@ -255,6 +255,18 @@ int sai_backward(const sai_split_t* sp, const sai_precond_t* pc, const double* x
                  const double* grad_x, double* grad_b, double* grad_a_val,
                  const sai_solve_opts* opts, void* stream, sai_solve_stats* stats /* host */);
 
+/* -------------------------------------------------------------- profiling --
+ * While enabled, the library records a pair of HIP events on the launch stream
+ * around each of its kernel launches and accumulates, per kernel name, the
+ * number of launches and their total elapsed time.  sai_profile_enable(1)
+ * resets the totals; sai_profile_get resolves pending events (it waits for
+ * them) and returns entry i (0 <= i < sai_profile_count()).  Not thread-safe
+ * with respect to concurrent launches from several host threads. */
+int sai_profile_enable(int32_t on);
+int sai_profile_count(void);
+int sai_profile_get(int32_t i, char* name /* host, name_cap bytes */, int32_t name_cap,
+                    int64_t* launches /* host */, double* total_ms /* host */);
+
 /* ------------------------------------------------------------------ misc --*/
 const char* sai_strerror(int code);
 const char* sai_last_error(void);

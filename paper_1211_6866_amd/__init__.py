@@ -128,6 +128,9 @@ def lib():
     L.sai_strerror.argtypes = [C.c_int]
     L.sai_last_error.restype = C.c_char_p
     L.sai_memcpy_d2d.argtypes = [vp, vp, C.c_size_t, vp]
+    L.sai_profile_enable.argtypes = [i32]
+    L.sai_profile_count.argtypes = []
+    L.sai_profile_get.argtypes = [i32, C.c_char_p, i32, C.POINTER(i64), C.POINTER(C.c_double)]
 
     torch = _torch()
 
@@ -340,6 +343,26 @@ def backward(split: Split, pc: Precond, x, grad_x, want_b=True, want_a=True, rai
     if raise_on_error:
         _check(code, "sai_backward")
     return gb, ga, _stats_dict(st, iters)
+
+
+def profile_enable(on: bool = True):
+    """Start (and reset) or stop the library's per-kernel HIP-event timing."""
+    _check(lib().sai_profile_enable(int(bool(on))), "sai_profile_enable")
+
+
+def profile_read() -> dict:
+    """{kernel name: (launches, total ms)} accumulated since profile_enable(True)."""
+    L = lib()
+    out = {}
+    cnt = L.sai_profile_count()
+    if cnt < 0:
+        raise SaiError(EHIP, "sai_profile_count", "event query failed")
+    buf = C.create_string_buffer(128)
+    for i in range(cnt):
+        nl, ms = C.c_int64(), C.c_double()
+        _check(L.sai_profile_get(i, buf, 128, C.byref(nl), C.byref(ms)), "sai_profile_get")
+        out[buf.value.decode()] = (nl.value, ms.value)
+    return out
 
 
 def csr_to_device(A):

@@ -22,388 +22,10 @@
 // update at the end of each cycle, convergence on the true residual.
 #include "sai_internal.hpp"
 
+#include "bicgstab_kernels.hpp"
+
 namespace sai {
 namespace {
-
-constexpr int NT = 256;
-constexpr int NB = 1024;
-constexpr double TINY = 1e-300;
-
-enum { ST_ACTIVE = 0, ST_CONV = 1, ST_MAXIT = 2, ST_BREAK = 3 };
-
-template <class TV>
-struct Csr {
-  const int32_t* rp;
-  const int32_t* ci;
-  const TV* v;
-};
-
-struct State {
-  double *rho, *rho_old, *alpha, *omega, *beta, *thr;
-  int *status, *iters, *skip, *restarts, *half, *full, *rst, *halfconv, *wasact;
-  int* any;  // 0 half, 1 full, 2 restart, 3 active count, 4 half-converged
-  double* part;
-  unsigned* counter;
-};
-
-struct Vec {
-  const double* rhs;
-  double *x, *r, *rh, *p, *v, *s, *ph, *sh, *t;
-};
-
-__device__ __forceinline__ bool col_active(const State& S, int c) {
-  return S.status[c] == ST_ACTIVE && S.skip[c] == 0;
-}
-
-template <class TV>
-__device__ __forceinline__ double row_prod(const Csr<TV>& A, int64_t i, const double* X, int k,
-                                           int c) {
-  double acc = 0.0;
-  const int32_t e1 = A.rp[i + 1];
-  int32_t e = A.rp[i];
-  for (; e + 1 < e1; e += 2) {
-    const int32_t j0 = A.ci[e], j1 = A.ci[e + 1];
-    const double v0 = (double)A.v[e], v1 = (double)A.v[e + 1];
-    const double x0 = X[(int64_t)j0 * k + c], x1 = X[(int64_t)j1 * k + c];
-    acc += v0 * x0;
-    acc += v1 * x1;
-  }
-  if (e < e1) acc += (double)A.v[e] * X[(int64_t)A.ci[e] * k + c];
-  return acc;
-}
-
-// Block-reduce ND per-lane accumulators (per column), publish the block's
-// partials, and let the last block to finish form the totals in tot[d][c].
-// Returns true in the last block (all threads).
-template <int GK, int ND>
-__device__ bool reduce_dots(double (&acc)[ND], const State& S, double (*tot)[GK]) {
-  constexpr int RPB = NT / GK;
-  __shared__ double red[ND][NT];
-  __shared__ bool last;
-  const int t = threadIdx.x;
-#pragma unroll
-  for (int d = 0; d < ND; ++d) red[d][t] = acc[d];
-  __syncthreads();
-  if (t < GK) {
-#pragma unroll
-    for (int d = 0; d < ND; ++d) {
-      double s = 0.0;
-      for (int r = 0; r < RPB; ++r) s += red[d][r * GK + t];
-      S.part[((int64_t)d * NB + blockIdx.x) * GK + t] = s;
-    }
-  }
-  __threadfence();
-  __syncthreads();
-  if (t == 0) last = (atomicAdd(S.counter, 1u) == gridDim.x - 1);
-  __syncthreads();
-  if (!last) return false;
-  __threadfence();
-  const int c = t % GK, q = t / GK;
-#pragma unroll
-  for (int d = 0; d < ND; ++d) {
-    double s = 0.0;
-    for (int b = q; b < (int)gridDim.x; b += RPB)
-      s += __builtin_nontemporal_load(&S.part[((int64_t)d * NB + b) * GK + c]);
-    red[d][t] = s;
-  }
-  __syncthreads();
-  if (t < GK) {
-#pragma unroll
-    for (int d = 0; d < ND; ++d) {
-      double s = 0.0;
-      for (int r = 0; r < RPB; ++r) s += red[d][r * GK + t];
-      tot[d][t] = s;
-    }
-  }
-  if (t == 0) *S.counter = 0u;
-  __syncthreads();
-  return true;
-}
-
-#define ROW_LOOP                                                  \
-  constexpr int RPB = NT / GK;                                    \
-  const int c = threadIdx.x % GK;                                 \
-  const bool lane_ok = c < k;                                     \
-  for (int64_t i = (int64_t)blockIdx.x * RPB + threadIdx.x / GK; i < n; \
-       i += (int64_t)gridDim.x * RPB)
-
-// ---- initialisation: x = 0, r = r_hat = rhs, p = v = 0, rho = ||r||^2 ----------
-template <int GK>
-__global__ void __launch_bounds__(NT) k_init(int64_t n, int k, Vec V, State S) {
-  double acc[1] = {0.0};
-  ROW_LOOP {
-    if (!lane_ok) continue;
-    const int64_t q = i * k + c;
-    const double b = V.rhs[q];
-    V.x[q] = 0.0;
-    V.r[q] = b;
-    V.rh[q] = b;
-    V.p[q] = 0.0;
-    V.v[q] = 0.0;
-    acc[0] += b * b;
-  }
-  __shared__ double tot[1][GK];
-  if (!reduce_dots<GK, 1>(acc, S, tot)) return;
-  const int t = threadIdx.x;
-  if (t < k) {
-    const double rr = tot[0][t];
-    S.rho[t] = rr;
-    S.rho_old[t] = 1.0;
-    S.alpha[t] = 1.0;
-    S.omega[t] = 1.0;
-    S.beta[t] = rr;
-    S.skip[t] = 0;
-    S.restarts[t] = 0;
-    S.half[t] = S.full[t] = S.rst[t] = S.halfconv[t] = 0;
-    S.iters[t] = 0;
-    S.status[t] = (sqrt(rr) < S.thr[t]) ? ST_CONV : ST_ACTIVE;
-  }
-  if (t == 0) { S.any[0] = S.any[1] = S.any[2] = S.any[4] = 0; }
-}
-
-// ---- p = r + beta (p - omega v) -------------------------------------------------
-template <int GK>
-__global__ void __launch_bounds__(NT) k_pupdate(int64_t n, int k, Vec V, State S) {
-  ROW_LOOP {
-    if (!lane_ok || !col_active(S, c)) continue;
-    const int64_t q = i * k + c;
-    V.p[q] = V.r[q] + S.beta[c] * (V.p[q] - S.omega[c] * V.v[q]);
-  }
-}
-
-// ---- Y = Op X (plain product; columns not active are skipped) ---------------------
-template <int GK, class TV>
-__global__ void __launch_bounds__(NT) k_spmm(int64_t n, int k, Csr<TV> A, const double* X,
-                                             double* Y, State S) {
-  ROW_LOOP {
-    if (!lane_ok || !col_active(S, c)) continue;
-    Y[i * k + c] = row_prod(A, i, X, k, c);
-  }
-}
-
-// ---- v = A p_hat, sigma = r_hat^T v, alpha = rho / sigma --------------------------
-template <int GK>
-__global__ void __launch_bounds__(NT) k_av(int64_t n, int k, Csr<double> A, Vec V, State S) {
-  double acc[1] = {0.0};
-  ROW_LOOP {
-    if (!lane_ok || !col_active(S, c)) continue;
-    const double y = row_prod(A, i, V.ph, k, c);
-    V.v[i * k + c] = y;
-    acc[0] += V.rh[i * k + c] * y;
-  }
-  __shared__ double tot[1][GK];
-  if (!reduce_dots<GK, 1>(acc, S, tot)) return;
-  const int t = threadIdx.x;
-  if (t < k && col_active(S, t)) {
-    const double sig = tot[0][t];
-    if (fabs(sig) < TINY) {
-      S.skip[t] = 1;
-      S.rst[t] = 1;
-      S.any[2] = 1;
-    } else {
-      S.alpha[t] = S.rho[t] / sig;
-    }
-  }
-}
-
-// ---- s = r - alpha v, half-step flag when ||s|| < thr --------------------------
-template <int GK>
-__global__ void __launch_bounds__(NT) k_s(int64_t n, int k, Vec V, State S) {
-  double acc[1] = {0.0};
-  ROW_LOOP {
-    if (!lane_ok || !col_active(S, c)) continue;
-    const int64_t q = i * k + c;
-    const double sv = V.r[q] - S.alpha[c] * V.v[q];
-    V.s[q] = sv;
-    acc[0] += sv * sv;
-  }
-  __shared__ double tot[1][GK];
-  if (!reduce_dots<GK, 1>(acc, S, tot)) return;
-  const int t = threadIdx.x;
-  if (t < k && col_active(S, t)) {
-    if (sqrt(tot[0][t]) < S.thr[t]) {
-      S.half[t] = 1;
-      S.any[0] = 1;
-    }
-  }
-}
-
-// ---- half-step true residual: rhs - A (x + alpha p_hat) for flagged columns -------
-template <int GK>
-__global__ void __launch_bounds__(NT) k_halfcheck(int64_t n, int k, Csr<double> A, Vec V, State S) {
-  if (S.any[0] == 0) return;
-  double acc[1] = {0.0};
-  ROW_LOOP {
-    if (!lane_ok || !col_active(S, c) || !S.half[c]) continue;
-    const double al = S.alpha[c];
-    double y = 0.0;
-    for (int32_t e = A.rp[i]; e < A.rp[i + 1]; ++e) {
-      const int64_t q = (int64_t)A.ci[e] * k + c;
-      y += A.v[e] * (V.x[q] + al * V.ph[q]);
-    }
-    const double rt = V.rhs[i * k + c] - y;
-    acc[0] += rt * rt;
-  }
-  __shared__ double tot[1][GK];
-  if (!reduce_dots<GK, 1>(acc, S, tot)) return;
-  const int t = threadIdx.x;
-  if (t < k && col_active(S, t) && S.half[t]) {
-    if (sqrt(tot[0][t]) < S.thr[t]) {
-      S.halfconv[t] = 1;
-      S.any[4] = 1;
-    }
-  }
-}
-
-// ---- x += alpha p_hat for the columns that converged at the half step -------------
-template <int GK>
-__global__ void __launch_bounds__(NT) k_halfapply(int64_t n, int k, Vec V, State S, int it) {
-  if (S.any[4] == 0) return;
-  ROW_LOOP {
-    if (!lane_ok || !S.halfconv[c] || S.status[c] != ST_ACTIVE) continue;
-    const int64_t q = i * k + c;
-    V.x[q] += S.alpha[c] * V.ph[q];
-  }
-}
-
-// ---- t = A s_hat, omega = t^T s / t^T t -----------------------------------------
-template <int GK>
-__global__ void __launch_bounds__(NT) k_at(int64_t n, int k, Csr<double> A, Vec V, State S) {
-  double acc[2] = {0.0, 0.0};
-  ROW_LOOP {
-    if (!lane_ok || !col_active(S, c) || S.halfconv[c]) continue;
-    const double y = row_prod(A, i, V.sh, k, c);
-    V.t[i * k + c] = y;
-    acc[0] += y * V.s[i * k + c];
-    acc[1] += y * y;
-  }
-  __shared__ double tot[2][GK];
-  if (!reduce_dots<GK, 2>(acc, S, tot)) return;
-  const int t = threadIdx.x;
-  if (t < k && col_active(S, t) && !S.halfconv[t]) {
-    const double tt = tot[1][t];
-    if (tt < TINY) {
-      S.skip[t] = 1;
-      S.rst[t] = 1;
-      S.any[2] = 1;
-    } else {
-      S.omega[t] = tot[0][t] / tt;
-    }
-  }
-}
-
-// ---- x += alpha p_hat + omega s_hat, r = s - omega t, rho_new = r_hat^T r -----------
-template <int GK>
-__global__ void __launch_bounds__(NT) k_xr(int64_t n, int k, Vec V, State S) {
-  double acc[2] = {0.0, 0.0};
-  ROW_LOOP {
-    if (!lane_ok || !col_active(S, c) || S.halfconv[c]) continue;
-    const int64_t q = i * k + c;
-    V.x[q] += S.alpha[c] * V.ph[q] + S.omega[c] * V.sh[q];
-    const double rv = V.s[q] - S.omega[c] * V.t[q];
-    V.r[q] = rv;
-    acc[0] += V.rh[q] * rv;
-    acc[1] += rv * rv;
-  }
-  __shared__ double tot[2][GK];
-  if (!reduce_dots<GK, 2>(acc, S, tot)) return;
-  const int t = threadIdx.x;
-  if (t < k && col_active(S, t) && !S.halfconv[t]) {
-    const double rho_new = tot[0][t];
-    S.rho_old[t] = S.rho[t];
-    S.rho[t] = rho_new;
-    S.beta[t] = (rho_new / S.rho_old[t]) * (S.alpha[t] / S.omega[t]);
-    if (sqrt(tot[1][t]) < S.thr[t]) {
-      S.full[t] = 1;
-      S.any[1] = 1;  // breakdown checks follow the true-residual check
-    } else if (fabs(S.omega[t]) < TINY || fabs(rho_new) < TINY) {
-      S.rst[t] = 1;
-      S.any[2] = 1;
-    }
-  }
-}
-
-// ---- full-step true residual; replaces r when it does not pass --------------------
-template <int GK>
-__global__ void __launch_bounds__(NT) k_fullcheck(int64_t n, int k, Csr<double> A, Vec V, State S) {
-  if (S.any[1] == 0) return;
-  double acc[2] = {0.0, 0.0};
-  ROW_LOOP {
-    if (!lane_ok || !col_active(S, c) || !S.full[c]) continue;
-    const int64_t q = i * k + c;
-    const double rt = V.rhs[q] - row_prod(A, i, V.x, k, c);
-    V.r[q] = rt;
-    acc[0] += rt * rt;
-    acc[1] += V.rh[q] * rt;
-  }
-  __shared__ double tot[2][GK];
-  if (!reduce_dots<GK, 2>(acc, S, tot)) return;
-  const int t = threadIdx.x;
-  if (t < k && col_active(S, t) && S.full[t]) {
-    if (sqrt(tot[0][t]) < S.thr[t]) {
-      S.status[t] = ST_CONV;  // iteration count set at the end of the iteration
-    } else {
-      const double rho_new = tot[1][t];
-      S.rho[t] = rho_new;
-      S.beta[t] = (rho_new / S.rho_old[t]) * (S.alpha[t] / S.omega[t]);
-      if (fabs(S.omega[t]) < TINY || fabs(rho_new) < TINY) {
-        S.rst[t] = 1;
-        S.any[2] = 1;
-      }
-    }
-  }
-}
-
-// ---- restart: r_hat = r, p = v = 0, rho = r^T r ----------------------------------
-template <int GK>
-__global__ void __launch_bounds__(NT) k_restart(int64_t n, int k, Vec V, State S) {
-  if (S.any[2] == 0) return;
-  double acc[1] = {0.0};
-  ROW_LOOP {
-    if (!lane_ok || !S.rst[c] || S.status[c] != ST_ACTIVE) continue;
-    const int64_t q = i * k + c;
-    const double rv = V.r[q];
-    V.rh[q] = rv;
-    V.p[q] = 0.0;
-    V.v[q] = 0.0;
-    acc[0] += rv * rv;
-  }
-  __shared__ double tot[1][GK];
-  if (!reduce_dots<GK, 1>(acc, S, tot)) return;
-  const int t = threadIdx.x;
-  if (t < k && S.rst[t] && S.status[t] == ST_ACTIVE) {
-    const double rr = tot[0][t];
-    S.rho[t] = rr;
-    S.rho_old[t] = S.alpha[t] = S.omega[t] = 1.0;
-    S.beta[t] = rr;
-    S.restarts[t] += 1;
-    if (S.restarts[t] > 1) S.status[t] = ST_BREAK;
-  }
-}
-
-// ---- end of an iteration: record iterations, clear flags, count active columns ----
-__global__ void k_iter_end(int k, State S, int it, int maxit) {
-  __shared__ int cnt;
-  const int t = threadIdx.x;
-  if (t == 0) cnt = 0;
-  __syncthreads();
-  if (t < k) {
-    int st = S.status[t];
-    if (S.halfconv[t] && st == ST_ACTIVE) st = ST_CONV;
-    if (it > 0 && S.wasact[t]) S.iters[t] = it;
-    if (st == ST_ACTIVE && it >= maxit) st = ST_MAXIT;
-    S.status[t] = st;
-    S.wasact[t] = (st == ST_ACTIVE) ? 1 : 0;
-    S.skip[t] = 0;
-    S.half[t] = S.full[t] = S.rst[t] = S.halfconv[t] = 0;
-    if (st == ST_ACTIVE) atomicAdd(&cnt, 1);
-  }
-  __syncthreads();
-  if (t == 0) {
-    S.any[0] = S.any[1] = S.any[2] = S.any[4] = 0;
-    S.any[3] = cnt;
-  }
-}
 
 template <int GK, class TM>
 int bicgstab_gk(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, const double* R,
@@ -414,9 +36,7 @@ int bicgstab_gk(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, const 
       sh(&al, nk), t(&al, nk);
   DBuf<double> sc(&al, 6 * 64);
   DBuf<int> si(&al, 9 * 64 + 8);
-  DBuf<double> part(&al, (size_t)2 * NB * GK);
-  DBuf<unsigned> counter(&al, 1);
-  HIPC(hipMemsetAsync(counter.p, 0, sizeof(unsigned), st));
+  DBuf<double> part(&al, (size_t)2 * NBMAX * GK);
   HIPC(hipMemsetAsync(si.p, 0, sizeof(int) * (9 * 64 + 8), st));
   HIPC(hipMemcpyAsync(sc.p + 5 * 64, thr, sizeof(double) * k, hipMemcpyHostToDevice, st));
   State S;
@@ -437,12 +57,17 @@ int bicgstab_gk(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, const 
   S.wasact = si.p + 512;
   S.any = si.p + 576;
   S.part = part.p;
-  S.counter = counter.p;
   Vec V{R, X, r.p, rh.p, p.p, v.p, s.p, ph.p, sh.p, t.p};
   constexpr int RPB = NT / GK;
-  const unsigned grid = (unsigned)std::min<int64_t>(NB, (n + RPB - 1) / RPB);
+  // streaming kernels: one row per lane group; sparse products: tiles of SUB*RPB rows
+  const int grid = (int)std::min<int64_t>(NBMAX, (n + RPB - 1) / RPB);
+  const int tgrid = (int)std::min<int64_t>(NBMAX, (n + SUB * RPB - 1) / (SUB * RPB));
   HostStage hs(16);
-  hipLaunchKernelGGL((k_init<GK>), dim3(grid), dim3(NT), 0, st, n, k, V, S);
+  {
+    SAI_PROF("bicg_init", st);
+    hipLaunchKernelGGL((k_init<GK>), dim3(grid), dim3(NT), 0, st, n, k, V, S);
+    hipLaunchKernelGGL((k_fin<GK, 1, F_INIT>), dim3(1), dim3(NT), 0, st, k, S, grid);
+  }
   LAUNCH_CHECK();
   hipLaunchKernelGGL(k_iter_end, dim3(1), dim3(64), 0, st, k, S, 0, maxit);
   LAUNCH_CHECK();
@@ -450,18 +75,34 @@ int bicgstab_gk(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, const 
   HIPC(hipStreamSynchronize(st));
   int active = *hs.as<int>();
   for (int it = 1; it <= maxit && active > 0; ++it) {
-    hipLaunchKernelGGL((k_pupdate<GK>), dim3(grid), dim3(NT), 0, st, n, k, V, S);
-    hipLaunchKernelGGL((k_spmm<GK, TM>), dim3(grid), dim3(NT), 0, st, n, k, M, (const double*)V.p, V.ph, S);
-    hipLaunchKernelGGL((k_av<GK>), dim3(grid), dim3(NT), 0, st, n, k, A, V, S);
-    hipLaunchKernelGGL((k_s<GK>), dim3(grid), dim3(NT), 0, st, n, k, V, S);
-    hipLaunchKernelGGL((k_halfcheck<GK>), dim3(grid), dim3(NT), 0, st, n, k, A, V, S);
-    hipLaunchKernelGGL((k_halfapply<GK>), dim3(grid), dim3(NT), 0, st, n, k, V, S, it);
-    hipLaunchKernelGGL((k_spmm<GK, TM>), dim3(grid), dim3(NT), 0, st, n, k, M, (const double*)V.s, V.sh, S);
-    hipLaunchKernelGGL((k_at<GK>), dim3(grid), dim3(NT), 0, st, n, k, A, V, S);
-    hipLaunchKernelGGL((k_xr<GK>), dim3(grid), dim3(NT), 0, st, n, k, V, S);
-    hipLaunchKernelGGL((k_fullcheck<GK>), dim3(grid), dim3(NT), 0, st, n, k, A, V, S);
-    hipLaunchKernelGGL((k_restart<GK>), dim3(grid), dim3(NT), 0, st, n, k, V, S);
-    hipLaunchKernelGGL(k_iter_end, dim3(1), dim3(64), 0, st, k, S, it, maxit);
+#define LK(name, ...)              \
+  do {                             \
+    SAI_PROF(name, st);            \
+    hipLaunchKernelGGL(__VA_ARGS__); \
+  } while (0)
+    constexpr bool MF = sizeof(TM) == 4;
+    LK("bicg_p_update", (k_pupdate<GK>), dim3(grid), dim3(NT), 0, st, n, k, V, S);
+    LK(MF ? "bicg_spmm_M_f32" : "bicg_spmm_M_f64", (k_spmm<GK, TM>), dim3(tgrid), dim3(NT), 0, st, n,
+       k, M, (const double*)V.p, V.ph, S);
+    LK("bicg_spmm_A_dot1", (k_av<GK>), dim3(tgrid), dim3(NT), 0, st, n, k, A, V, S);
+    LK("bicg_finish", (k_fin<GK, 1, F_AV>), dim3(1), dim3(NT), 0, st, k, S, tgrid);
+    LK("bicg_s_update", (k_s<GK>), dim3(grid), dim3(NT), 0, st, n, k, V, S);
+    LK("bicg_finish", (k_fin<GK, 1, F_S>), dim3(1), dim3(NT), 0, st, k, S, grid);
+    LK("bicg_halfcheck", (k_halfcheck<GK>), dim3(grid), dim3(NT), 0, st, n, k, A, V, S);
+    LK("bicg_finish", (k_fin<GK, 1, F_HALF>), dim3(1), dim3(NT), 0, st, k, S, grid);
+    LK("bicg_halfapply", (k_halfapply<GK>), dim3(grid), dim3(NT), 0, st, n, k, V, S);
+    LK(MF ? "bicg_spmm_M_f32" : "bicg_spmm_M_f64", (k_spmm<GK, TM>), dim3(tgrid), dim3(NT), 0, st, n,
+       k, M, (const double*)V.s, V.sh, S);
+    LK("bicg_spmm_A_dot2", (k_at<GK>), dim3(tgrid), dim3(NT), 0, st, n, k, A, V, S);
+    LK("bicg_finish", (k_fin<GK, 2, F_AT>), dim3(1), dim3(NT), 0, st, k, S, tgrid);
+    LK("bicg_xr_update", (k_xr<GK>), dim3(grid), dim3(NT), 0, st, n, k, V, S);
+    LK("bicg_finish", (k_fin<GK, 2, F_XR>), dim3(1), dim3(NT), 0, st, k, S, grid);
+    LK("bicg_fullcheck", (k_fullcheck<GK>), dim3(grid), dim3(NT), 0, st, n, k, A, V, S);
+    LK("bicg_finish", (k_fin<GK, 2, F_FULL>), dim3(1), dim3(NT), 0, st, k, S, grid);
+    LK("bicg_restart", (k_restart<GK>), dim3(grid), dim3(NT), 0, st, n, k, V, S);
+    LK("bicg_finish", (k_fin<GK, 1, F_RESTART>), dim3(1), dim3(NT), 0, st, k, S, grid);
+    LK("bicg_iter_end", k_iter_end, dim3(1), dim3(64), 0, st, k, S, it, maxit);
+#undef LK
     LAUNCH_CHECK();
     HIPC(hipMemcpyAsync(hs.p, S.any + 3, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPC(hipStreamSynchronize(st));
@@ -636,6 +277,7 @@ int gmres_run(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, const do
   DBuf<double> dthr(&al, k);
   DBuf<int> dit(&al, k), dst(&al, k);
   HIPC(hipMemcpyAsync(dthr.p, thr, sizeof(double) * k, hipMemcpyHostToDevice, st));
+  SAI_PROF("gmres_fused", st);
   hipLaunchKernelGGL((k_gmres<TM>), dim3(k), dim3(GM_NT), 0, st, n, k, A, M, R, X, dthr.p, restart,
                      maxit, work.p, dit.p, dst.p);
   LAUNCH_CHECK();

@@ -402,23 +402,24 @@ __global__ void k_bucket_assign(int32_t n, const int32_t* __restrict__ cntJ,
                                 const int* __restrict__ vmaxJ, int32_t* __restrict__ bucket,
                                 int* __restrict__ bcount) {
   const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (k >= n) return;
-  int b = -1;
-  for (int v = 0; v < nv; ++v)
-    if (cntI[k] <= vmaxI[v] && cntJ[k] <= vmaxJ[v]) { b = v; break; }
-  bucket[k] = b;
-  atomicAdd(&bcount[b < 0 ? nv : b], 1);
+  int key = -1;
+  if (k < n) {
+    int b = -1;
+    for (int v = 0; v < nv; ++v)
+      if (cntI[k] <= vmaxI[v] && cntJ[k] <= vmaxJ[v]) { b = v; break; }
+    bucket[k] = b;
+    key = b < 0 ? nv : b;
+  }
+  (void)agg_slot(bcount, key);
 }
 
 __global__ void k_bucket_scatter(int32_t n, const int32_t* __restrict__ bucket,
                                  const int64_t* __restrict__ boff, int* __restrict__ bcur,
                                  int32_t* __restrict__ lists) {
   const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (k >= n) return;
-  const int b = bucket[k];
-  if (b < 0) return;
-  const int slot = atomicAdd(&bcur[b], 1);
-  lists[boff[b] + slot] = (int32_t)k;
+  const int b = k < n ? bucket[k] : -1;
+  const int slot = agg_slot(bcur, b);
+  if (b >= 0) lists[boff[b] + slot] = (int32_t)k;
 }
 
 template <class T, int G, int R, int JMAX>
@@ -428,6 +429,10 @@ void launch_qr(const int32_t* list, int cnt, const int64_t* jptr, const int32_t*
   if (cnt <= 0) return;
   constexpr int NP = 64 / G;
   const unsigned grid = grid_for(cnt, NP, 1u << 20);
+  static char name[64];
+  if (!name[0])
+    snprintf(name, sizeof(name), "ls_qr_%s_g%dr%dj%d", sizeof(T) == 4 ? "f32" : "f64", G, R, JMAX);
+  SAI_PROF(name, st);
   hipLaunchKernelGGL((k_ls_qr<T, G, R, JMAX>), dim3(grid), dim3(64), 0, st, list, cnt, jptr, jidx,
                      iptr, iidx, sp->t_col_ptr.p, sp->t_row_idx.p, sp->t_cval.p, mout, res, nsing);
   LAUNCH_CHECK();
@@ -464,6 +469,7 @@ void dispatch_variant(int v, const int32_t* list, int cnt, const int64_t* jptr,
   const unsigned grid = (unsigned)std::min(cnt, 1024);
   const int64_t stride = (int64_t)maxI * (maxJ + 1);
   DBuf<T> work(&al, (size_t)grid * stride);
+  SAI_PROF(sizeof(T) == 4 ? "ls_qr_f32_big" : "ls_qr_f64_big", st);
   hipLaunchKernelGGL((k_ls_qr_big<T>), dim3(grid), dim3(BIG_NT), 0, st, list, cnt, jptr, jidx, iptr,
                      iidx, sp->t_col_ptr.p, sp->t_row_idx.p, sp->t_cval.p, work.p, stride, mout, res,
                      nsing);

@@ -168,11 +168,14 @@ void build_patterns(const sai_split_s* sp, int kind, hipStream_t st, const Alloc
   HIPC(hipMemsetAsync(nover.p, 0, 2 * sizeof(int), st));
   const unsigned grid = (unsigned)std::min<int64_t>(n, 1 << 20);
   constexpr int CAP_S = 1024, CAP_L = 8192;
-  hipLaunchKernelGGL((k_pattern<CAP_S>), dim3(grid), dim3(64), 0, st, n, kind, sp->t_col_ptr.p,
-                     sp->t_row_idx.p, 0, (const int32_t*)nullptr, 0, cntJ.p, cntI.p,
-                     (const int64_t*)nullptr, (int32_t*)nullptr, (const int64_t*)nullptr,
-                     (int32_t*)nullptr, nover.p);
-  LAUNCH_CHECK();
+  {
+    SAI_PROF("pattern_count", st);
+    hipLaunchKernelGGL((k_pattern<CAP_S>), dim3(grid), dim3(64), 0, st, n, kind, sp->t_col_ptr.p,
+                       sp->t_row_idx.p, 0, (const int32_t*)nullptr, 0, cntJ.p, cntI.p,
+                       (const int64_t*)nullptr, (int32_t*)nullptr, (const int64_t*)nullptr,
+                       (int32_t*)nullptr, nover.p);
+    LAUNCH_CHECK();
+  }
   const int over = read_scalar(nover.p, st);
   DBuf<int32_t> flag;
   if (over > 0) {
@@ -198,6 +201,7 @@ void build_patterns(const sai_split_s* sp, int kind, hipStream_t st, const Alloc
   HIPC(hipStreamSynchronize(st));
   jidx.alloc(&al, (size_t)tot[0] + 1);
   iidx.alloc(&al, (size_t)tot[1] + 1);
+  SAI_PROF("pattern_fill", st);
   hipLaunchKernelGGL((k_pattern<CAP_S>), dim3(grid), dim3(64), 0, st, n, kind, sp->t_col_ptr.p,
                      sp->t_row_idx.p, 1, over > 0 ? (const int32_t*)flag.p : (const int32_t*)nullptr, 0,
                      cntJ.p, cntI.p, (const int64_t*)jptr.p, jidx.p, (const int64_t*)iptr.p, iidx.p,

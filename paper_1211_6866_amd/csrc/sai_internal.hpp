@@ -172,6 +172,27 @@ __device__ __forceinline__ T block_sum(T v, T* lds /* NT/64 */) {
   return t;
 }
 
+// Wave-aggregated counter increment: every lane with key >= 0 receives a slot
+// in counter[key] (one atomicAdd per distinct key per wave instead of one per
+// lane).  Must be called by all active lanes of the wave together.
+__device__ __forceinline__ int agg_slot(int* counter, int key) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  int slot = -1;
+  unsigned long long pending = __ballot(key >= 0);
+  while (pending) {
+    const int leader = __ffsll((long long)pending) - 1;
+    const int lk = __shfl(key, leader, WAVE);
+    const unsigned long long same = __ballot(key == lk);
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&counter[lk], __popcll(same));
+    base = __shfl(base, leader, WAVE);
+    if (key == lk) slot = base + __popcll(same & lt);
+    pending &= ~same;
+  }
+  return slot;
+}
+
 inline unsigned grid_for(int64_t work, int per_block, unsigned cap = 1u << 30) {
   int64_t g = (work + per_block - 1) / per_block;
   if (g < 1) g = 1;
@@ -212,6 +233,18 @@ struct EventTimer {
   void stop(hipStream_t st) { HIPC(hipEventRecord(b, st)); }
   float ms() { HIPC(hipEventSynchronize(b)); float t = 0; HIPC(hipEventElapsedTime(&t, a, b)); return t; }
 };
+
+// ---------------------------------------------------------------- profiling --
+
+// RAII scope: when profiling is enabled, records events around the launches
+// made while it is alive, on stream `st`, under `name`.
+struct ProfScope {
+  int slot = -1;
+  hipStream_t st = nullptr;
+  ProfScope(const char* name, hipStream_t s);
+  ~ProfScope();
+};
+#define SAI_PROF(name, st) ::sai::ProfScope _sai_prof_scope_##__LINE__((name), (st))
 
 // ------------------------------------------------------------ entry points --
 

@@ -191,6 +191,7 @@ void smw_recover(const sai_split_s* sp, const double* Y, double* x, double* c_ho
   const Allocator al{sp->al.a, st};
   const int s = sp->s, kk = s + 1;
   const int64_t n = sp->n;
+  SAI_PROF("smw_recover", st);
   if (s == 0) {
     hipLaunchKernelGGL(k_smw_apply, dim3(rows_grid(n)), dim3(NT), 0, st, n, 0, 1, Y,
                        (const double*)nullptr, x);
@@ -224,6 +225,7 @@ double residual_impl(const sai_split_s* sp, const double* b, const double* x, hi
   const int64_t n = sp->n;
   DBuf<double> part(&al, 2 * NBR + 2);
   const unsigned nb = grid_for(n, NT, NBR);
+  SAI_PROF("residual_check", st);
   hipLaunchKernelGGL(k_residual, dim3(nb), dim3(NT), 0, st, n, sp->t_row_ptr.p, sp->t_col_idx.p,
                      sp->t_val.p, sp->u_row_ptr.p, sp->u_col.p, sp->u_val.p, sp->dense_cols.p, b, x,
                      part.p);

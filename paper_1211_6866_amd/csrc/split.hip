@@ -62,11 +62,17 @@ __global__ void k_dense_gather(int32_t n, const int32_t* __restrict__ row_ptr,
                                const int64_t* __restrict__ doff, int32_t* __restrict__ dcur,
                                int32_t* __restrict__ lrow, int32_t* __restrict__ lpos) {
   const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
-  if (i >= n) return;
-  for (int32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
-    const int32_t d = colmap[col[e]];
+  const int32_t a = i < n ? row_ptr[i] : 0;
+  const int32_t len = i < n ? row_ptr[i + 1] - a : 0;
+  int mx = len;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o, WAVE));
+  // wave-uniform trip count so that the aggregated atomics see every lane
+  for (int32_t t = 0; t < mx; ++t) {
+    const int32_t e = a + t;
+    const int32_t d = t < len ? colmap[col[e]] : -1;
+    const int32_t slot = agg_slot(dcur, d);
     if (d >= 0) {
-      const int32_t slot = atomicAdd(&dcur[d], 1);
       lrow[doff[d] + slot] = (int32_t)i;
       lpos[doff[d] + slot] = e;
     }
@@ -218,6 +224,45 @@ __global__ void k_tr_sort(int32_t m, const int32_t* __restrict__ cp, int32_t* __
   const int64_t j = (int64_t)blockIdx.x * NT + threadIdx.x;
   if (j >= m) return;
   const int32_t a = cp[j], b = cp[j + 1];
+  if (b - a <= 32) {
+    // bitonic network in registers (all indices static)
+    const int len = b - a;
+    int32_t key[32];
+    V val[32];
+#pragma unroll
+    for (int t = 0; t < 32; ++t) {
+      key[t] = t < len ? ri[a + t] : 0x7fffffff;
+      val[t] = t < len ? cv[a + t] : V(0);
+    }
+#pragma unroll
+    for (int kk = 2; kk <= 32; kk <<= 1) {
+#pragma unroll
+      for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+#pragma unroll
+        for (int t = 0; t < 32; ++t) {
+          const int l = t ^ jj;
+          if (l > t) {
+            const bool up = (t & kk) == 0;
+            const bool sw = (key[t] > key[l]) == up;
+            const int32_t k0 = key[t], k1 = key[l];
+            const V v0 = val[t], v1 = val[l];
+            key[t] = sw ? k1 : k0;
+            key[l] = sw ? k0 : k1;
+            val[t] = sw ? v1 : v0;
+            val[l] = sw ? v0 : v1;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 32; ++t) {
+      if (t < len) {
+        ri[a + t] = key[t];
+        cv[a + t] = val[t];
+      }
+    }
+    return;
+  }
   for (int32_t x = a + 1; x < b; ++x) {
     const int32_t r = ri[x];
     const V w = cv[x];
@@ -260,6 +305,7 @@ void split_impl(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* c
   h->al = al_in;
   const Allocator& al = h->al;
   hipStream_t st = al.stream;
+  SAI_PROF("split", st);
   if (n <= 0 || nnz < 0 || nnz >= (int64_t)INT32_MAX || !row_ptr || (nnz > 0 && (!col_idx || !val)))
     SAI_THROW(SAI_EINVAL, "bad CSR arguments (n=%d nnz=%lld)", n, (long long)nnz);
   if (!(o.dense_factor > 0.0)) SAI_THROW(SAI_EINVAL, "dense_factor must be > 0");
