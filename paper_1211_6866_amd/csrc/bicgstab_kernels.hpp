@@ -17,7 +17,8 @@ namespace {
 constexpr int NT = 256;
 constexpr int NBMAX = 2048;
 constexpr int SUB = 4;
-constexpr int STAGE_CAP = 4096;
+constexpr int CAP_A = 1024;  // staged entries per tile: A~ (about 7 per row)
+constexpr int CAP_M = 3072;  // and M (about 25 per row)
 constexpr double TINY = 1e-300;
 
 enum { ST_ACTIVE = 0, ST_CONV = 1, ST_MAXIT = 2, ST_BREAK = 3 };
@@ -77,6 +78,36 @@ __device__ __forceinline__ double row_prod(const Csr<TV>& A, int64_t i, const do
   return row_prod_lds<TV>(A.ci, A.v, A.rp[i], A.rp[i + 1], X, k, c);
 }
 
+// SI rows at once, entries eb[q]..ee[q] in LDS: the gathers of the first CH
+// entries of every row are all issued before any is consumed (SI*CH loads in
+// flight per lane); entries past CH follow in a plain loop.
+template <class TV, int CH, int SI>
+__device__ __forceinline__ void rows_prod_batch(const int32_t* __restrict__ sci,
+                                                const TV* __restrict__ sv, const int (&eb)[SI],
+                                                const int (&ee)[SI], const double* __restrict__ X,
+                                                int k, int c, double (&out)[SI]) {
+  double xv[SI][CH];
+#pragma unroll
+  for (int q = 0; q < SI; ++q) {
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int e = eb[q] + u;
+      xv[q][u] = (e < ee[q]) ? X[(int64_t)sci[e] * k + c] : 0.0;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < SI; ++q) {
+    double a = 0.0;
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int e = eb[q] + u;
+      if (e < ee[q]) a += (double)sv[e] * xv[q][u];
+    }
+    if (ee[q] > eb[q] + CH) a += row_prod_lds<TV>(sci, sv, eb[q] + CH, ee[q], X, k, c);
+    out[q] = a;
+  }
+}
+
 // Block-reduce ND per-lane accumulators (per column) and publish the block's
 // partial sums for the finisher.
 template <int GK, int ND>
@@ -105,23 +136,35 @@ __device__ void block_partials(double (&acc)[ND], const State& S) {
   for (int64_t i = (int64_t)blockIdx.x * RPB + rib; i < n; i += (int64_t)gridDim.x * RPB)
 
 // Tile loop for sparse products: tiles of TR = SUB*RPB rows; every thread of the
-// block runs every iteration (the body synchronises).
+// block runs every iteration (the body synchronises).  Workgroups are dispatched
+// to the 8 XCDs round-robin (block b on XCD b % 8), and each XCD has its own L2;
+// so the tiles are split into 8 contiguous chunks, chunk x processed by the
+// blocks of XCD x.  The rows in flight on one XCD then form one window, and
+// the gathered rows of X (within the band of the matrix) stay in that XCD's L2.
 #define TILE_LOOP                                                                  \
   constexpr int RPB = NT / GK;                                                     \
   constexpr int TR = SUB * RPB;                                                    \
   const int c = threadIdx.x % GK;                                                  \
   const int rib = threadIdx.x / GK;                                                \
-  for (int64_t t0 = (int64_t)blockIdx.x * TR; t0 < n; t0 += (int64_t)gridDim.x * TR)
+  const int64_t ntile_ = (n + TR - 1) / TR;                                        \
+  const bool xcd_map_ = xmap && (gridDim.x % 8) == 0;                              \
+  const int64_t chunk_ = xcd_map_ ? (ntile_ + 7) / 8 : ntile_;                     \
+  const int64_t tfirst_ = xcd_map_ ? (int64_t)(blockIdx.x % 8) * chunk_ : 0;       \
+  const int64_t tstep_ = xcd_map_ ? gridDim.x / 8 : gridDim.x;                     \
+  const int64_t tlast_ = min<int64_t>(ntile_, tfirst_ + chunk_);                   \
+  for (int64_t tile_ = tfirst_ + (xcd_map_ ? blockIdx.x / 8 : blockIdx.x),         \
+               t0 = tile_ * TR;                                                    \
+       tile_ < tlast_; tile_ += tstep_, t0 = tile_ * TR)
 
 // Stage the entries of rows t0 .. t0+rows-1 in LDS; false when they do not fit.
-template <class TV>
+template <class TV, int CAP>
 __device__ __forceinline__ bool stage_tile(const Csr<TV>& A, int64_t t0, int rows, int32_t* s_rp,
                                            int32_t* s_ci, TV* s_v) {
   for (int q = threadIdx.x; q <= rows; q += NT) s_rp[q] = A.rp[t0 + q];
   __syncthreads();
   const int32_t e0 = s_rp[0];
   const int cnt = s_rp[rows] - e0;
-  const bool fit = cnt <= STAGE_CAP;
+  const bool fit = cnt <= CAP;
   if (fit) {
     for (int q = threadIdx.x; q < cnt; q += NT) {
       s_ci[q] = A.ci[e0 + q];
@@ -132,10 +175,10 @@ __device__ __forceinline__ bool stage_tile(const Csr<TV>& A, int64_t t0, int row
   return fit;
 }
 
-#define STAGE_DECL(TV)                        \
+#define STAGE_DECL(TV, CAP)                   \
   __shared__ int32_t s_rp[SUB * NT / GK + 1]; \
-  __shared__ int32_t s_ci[STAGE_CAP];         \
-  __shared__ TV s_v[STAGE_CAP];
+  __shared__ int32_t s_ci[CAP];               \
+  __shared__ TV s_v[CAP];
 
 // product of row r (tile-relative) with X; `fit` and `t0` from the tile loop
 #define STAGED_PROD(A, X, r)                                                                \
@@ -173,42 +216,64 @@ __global__ void __launch_bounds__(NT) k_pupdate(int64_t n, int k, Vec V, State S
 }
 
 // ---- Y = Op X (plain product for the active columns) -------------------------------
-template <int GK, class TV>
+// The lane's SUB rows of the tile are r = sb*RPB + rib; they are handled SI at a
+// time with rows_prod_batch (tile staged) or one by one from global memory.
+#define TILE_ROWS_PROD(TV, CH, SI, A, X, BODY)                                        \
+  if (fit) {                                                                          \
+    _Pragma("unroll") for (int b0 = 0; b0 < SUB; b0 += (SI)) {                        \
+      int eb[SI], ee[SI];                                                             \
+      double out[SI];                                                                 \
+      _Pragma("unroll") for (int q = 0; q < (SI); ++q) {                              \
+        const int r = (b0 + q) * RPB + rib;                                           \
+        eb[q] = r < rows ? s_rp[r] - s_rp[0] : 0;                                     \
+        ee[q] = r < rows ? s_rp[r + 1] - s_rp[0] : 0;                                 \
+      }                                                                               \
+      rows_prod_batch<TV, CH, SI>(s_ci, s_v, eb, ee, (X), k, c, out);                 \
+      _Pragma("unroll") for (int q = 0; q < (SI); ++q) {                              \
+        const int r = (b0 + q) * RPB + rib;                                           \
+        if (r < rows) {                                                               \
+          const double y = out[q];                                                    \
+          const int64_t qq = (t0 + r) * k + c;                                        \
+          BODY                                                                        \
+        }                                                                             \
+      }                                                                               \
+    }                                                                                 \
+  } else {                                                                            \
+    for (int sb = 0; sb < SUB; ++sb) {                                                \
+      const int r = sb * RPB + rib;                                                   \
+      if (r < rows) {                                                                 \
+        const double y = row_prod((A), t0 + r, (X), k, c);                            \
+        const int64_t qq = (t0 + r) * k + c;                                          \
+        BODY                                                                          \
+      }                                                                               \
+    }                                                                                 \
+  }
+
+template <int GK, class TV, int CH, int SI, int SUBT>
 __global__ void __launch_bounds__(NT) k_spmm(int64_t n, int k, Csr<TV> A, const double* __restrict__ X,
-                                             double* __restrict__ Y, State S) {
-  STAGE_DECL(TV)
+                                             double* __restrict__ Y, State S, int xmap) {
+  constexpr int SUB = SUBT;
+  STAGE_DECL(TV, CAP_M)
   const bool on = col_on(S, threadIdx.x % GK, k);
   TILE_LOOP {
     const int rows = (int)min<int64_t>(TR, n - t0);
-    const bool fit = stage_tile<TV>(A, t0, rows, s_rp, s_ci, s_v);
-#pragma unroll
-    for (int sb = 0; sb < SUB; ++sb) {
-      const int r = sb * RPB + rib;
-      if (on && r < rows) Y[(t0 + r) * k + c] = STAGED_PROD(A, X, r);
-    }
+    const bool fit = stage_tile<TV, CAP_M>(A, t0, rows, s_rp, s_ci, s_v);
+    if (on) { TILE_ROWS_PROD(TV, CH, SI, A, X, Y[qq] = y;) }
     __syncthreads();
   }
 }
 
 // ---- v = A p_hat; partial sigma = r_hat^T v --------------------------------------
-template <int GK>
-__global__ void __launch_bounds__(NT) k_av(int64_t n, int k, Csr<double> A, Vec V, State S) {
-  STAGE_DECL(double)
+template <int GK, int SUBT>
+__global__ void __launch_bounds__(NT) k_av(int64_t n, int k, Csr<double> A, Vec V, State S, int xmap) {
+  constexpr int SUB = SUBT;
+  STAGE_DECL(double, CAP_A)
   double acc[1] = {0.0};
   const bool on = col_on(S, threadIdx.x % GK, k);
   TILE_LOOP {
     const int rows = (int)min<int64_t>(TR, n - t0);
-    const bool fit = stage_tile<double>(A, t0, rows, s_rp, s_ci, s_v);
-#pragma unroll
-    for (int sb = 0; sb < SUB; ++sb) {
-      const int r = sb * RPB + rib;
-      if (on && r < rows) {
-        const int64_t q = (t0 + r) * k + c;
-        const double y = STAGED_PROD(A, V.ph, r);
-        V.v[q] = y;
-        acc[0] += V.rh[q] * y;
-      }
-    }
+    const bool fit = stage_tile<double, CAP_A>(A, t0, rows, s_rp, s_ci, s_v);
+    if (on) { TILE_ROWS_PROD(double, 8, SUB, A, V.ph, V.v[qq] = y; acc[0] += V.rh[qq] * y;) }
     __syncthreads();
   }
   block_partials<GK, 1>(acc, S);
@@ -266,25 +331,18 @@ __global__ void __launch_bounds__(NT) k_halfapply(int64_t n, int k, Vec V, State
 }
 
 // ---- t = A s_hat; partials t^T s, t^T t ------------------------------------------
-template <int GK>
-__global__ void __launch_bounds__(NT) k_at(int64_t n, int k, Csr<double> A, Vec V, State S) {
-  STAGE_DECL(double)
+template <int GK, int SUBT>
+__global__ void __launch_bounds__(NT) k_at(int64_t n, int k, Csr<double> A, Vec V, State S, int xmap) {
+  constexpr int SUB = SUBT;
+  STAGE_DECL(double, CAP_A)
   double acc[2] = {0.0, 0.0};
   const int cc = threadIdx.x % GK;
   const bool on = col_on(S, cc, k) && !S.halfconv[cc];
   TILE_LOOP {
     const int rows = (int)min<int64_t>(TR, n - t0);
-    const bool fit = stage_tile<double>(A, t0, rows, s_rp, s_ci, s_v);
-#pragma unroll
-    for (int sb = 0; sb < SUB; ++sb) {
-      const int r = sb * RPB + rib;
-      if (on && r < rows) {
-        const int64_t q = (t0 + r) * k + c;
-        const double y = STAGED_PROD(A, V.sh, r);
-        V.t[q] = y;
-        acc[0] += y * V.s[q];
-        acc[1] += y * y;
-      }
+    const bool fit = stage_tile<double, CAP_A>(A, t0, rows, s_rp, s_ci, s_v);
+    if (on) {
+      TILE_ROWS_PROD(double, 8, SUB, A, V.sh, V.t[qq] = y; acc[0] += y * V.s[qq]; acc[1] += y * y;)
     }
     __syncthreads();
   }
@@ -350,10 +408,12 @@ __global__ void __launch_bounds__(NT) k_restart(int64_t n, int k, Vec V, State S
 // ---- finishers: one block adds the partials and updates the column state -------
 enum { F_INIT, F_AV, F_S, F_HALF, F_AT, F_XR, F_FULL, F_RESTART };
 
+constexpr int FNT = 1024;  // finisher threads
+
 template <int GK, int ND, int OP>
-__global__ void __launch_bounds__(NT) k_fin(int k, State S, int nb) {
-  constexpr int RPB = NT / GK;
-  __shared__ double red[ND][NT];
+__global__ void __launch_bounds__(FNT) k_fin(int k, State S, int nb) {
+  constexpr int RPB = FNT / GK;
+  __shared__ double red[ND][FNT];
   __shared__ double tot[ND][GK];
   // a finisher whose main kernel returned early (flag not set) has nothing to do
   if (OP == F_HALF && S.any[0] == 0) return;

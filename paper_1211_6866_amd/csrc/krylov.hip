@@ -6,9 +6,9 @@
 // Blocks are n x k row-major (the k values of a row are contiguous).  A group
 // of GK lanes (GK = next power of two >= k) handles one row; lane c owns
 // column c.  Dot products are fused into the kernels that produce their
-// operands; the per-block partial sums are reduced by the last block to finish
-// (fixed order, so results are deterministic), which then updates the scalar
-// state of every column (alpha, omega, rho, beta, convergence flags).
+// operands; a one-block finisher adds the per-block partial sums in a fixed
+// order (so results are deterministic) and updates the scalar state of every
+// column (alpha, omega, rho, beta, convergence flags).
 //
 // BiCGStab follows van der Vorst's algorithm with r_hat = r_0.  Convergence
 // is declared on the true residual rhs - A~ x, computed whenever the recursive
@@ -61,12 +61,46 @@ int bicgstab_gk(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, const 
   constexpr int RPB = NT / GK;
   // streaming kernels: one row per lane group; sparse products: tiles of SUB*RPB rows
   const int grid = (int)std::min<int64_t>(NBMAX, (n + RPB - 1) / RPB);
-  const int tgrid = (int)std::min<int64_t>(NBMAX, (n + SUB * RPB - 1) / (SUB * RPB));
+  // Sparse products work on tiles of SUB*RPB rows; the grid is a multiple of the
+  // XCD count so that XCD-contiguous tile ranges can be used.
+  auto tiles_grid = [&](int sub) {
+    int g = (int)std::min<int64_t>(NBMAX, (n + sub * RPB - 1) / (sub * RPB));
+    return g >= 8 ? (g & ~7) : g;
+  };
+  const int xmap = tune_get("XMAP", 0);
+  // M product variant (rows per lane per tile, gathers batched per row, rows interleaved)
+  const int mvar = tune_get("SPMM_M", 3);
+  const int msub = (mvar == 1 || mvar == 2) ? 4 : (mvar == 3 ? 2 : 1);
+  const int mgrid = tiles_grid(msub);
+  auto spmm_m = [&](const double* X, double* Y) {
+    switch (mvar) {
+      case 1: hipLaunchKernelGGL((k_spmm<GK, TM, 8, 4, 4>), dim3(mgrid), dim3(NT), 0, st, n, k, M, X, Y, S, xmap); break;
+      case 2: hipLaunchKernelGGL((k_spmm<GK, TM, 32, 2, 4>), dim3(mgrid), dim3(NT), 0, st, n, k, M, X, Y, S, xmap); break;
+      case 3: hipLaunchKernelGGL((k_spmm<GK, TM, 16, 2, 2>), dim3(mgrid), dim3(NT), 0, st, n, k, M, X, Y, S, xmap); break;
+      case 4: hipLaunchKernelGGL((k_spmm<GK, TM, 16, 1, 1>), dim3(mgrid), dim3(NT), 0, st, n, k, M, X, Y, S, xmap); break;
+      case 5: hipLaunchKernelGGL((k_spmm<GK, TM, 32, 1, 1>), dim3(mgrid), dim3(NT), 0, st, n, k, M, X, Y, S, xmap); break;
+      default: hipLaunchKernelGGL((k_spmm<GK, TM, 8, 1, 1>), dim3(mgrid), dim3(NT), 0, st, n, k, M, X, Y, S, xmap); break;
+    }
+  };
+  // A~ product variant: rows per lane per tile (all interleaved, 8 gathers per row batched)
+  const int avar = tune_get("SPMM_A", 0);
+  const int asub = avar == 1 ? 1 : (avar == 2 ? 2 : 4);
+  const int tgrid = tiles_grid(asub);
+  auto spmm_av = [&]() {
+    if (asub == 1) hipLaunchKernelGGL((k_av<GK, 1>), dim3(tgrid), dim3(NT), 0, st, n, k, A, V, S, xmap);
+    else if (asub == 2) hipLaunchKernelGGL((k_av<GK, 2>), dim3(tgrid), dim3(NT), 0, st, n, k, A, V, S, xmap);
+    else hipLaunchKernelGGL((k_av<GK, 4>), dim3(tgrid), dim3(NT), 0, st, n, k, A, V, S, xmap);
+  };
+  auto spmm_at = [&]() {
+    if (asub == 1) hipLaunchKernelGGL((k_at<GK, 1>), dim3(tgrid), dim3(NT), 0, st, n, k, A, V, S, xmap);
+    else if (asub == 2) hipLaunchKernelGGL((k_at<GK, 2>), dim3(tgrid), dim3(NT), 0, st, n, k, A, V, S, xmap);
+    else hipLaunchKernelGGL((k_at<GK, 4>), dim3(tgrid), dim3(NT), 0, st, n, k, A, V, S, xmap);
+  };
   HostStage hs(16);
   {
     SAI_PROF("bicg_init", st);
     hipLaunchKernelGGL((k_init<GK>), dim3(grid), dim3(NT), 0, st, n, k, V, S);
-    hipLaunchKernelGGL((k_fin<GK, 1, F_INIT>), dim3(1), dim3(NT), 0, st, k, S, grid);
+    hipLaunchKernelGGL((k_fin<GK, 1, F_INIT>), dim3(1), dim3(FNT), 0, st, k, S, grid);
   }
   LAUNCH_CHECK();
   hipLaunchKernelGGL(k_iter_end, dim3(1), dim3(64), 0, st, k, S, 0, maxit);
@@ -82,25 +116,35 @@ int bicgstab_gk(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, const 
   } while (0)
     constexpr bool MF = sizeof(TM) == 4;
     LK("bicg_p_update", (k_pupdate<GK>), dim3(grid), dim3(NT), 0, st, n, k, V, S);
-    LK(MF ? "bicg_spmm_M_f32" : "bicg_spmm_M_f64", (k_spmm<GK, TM>), dim3(tgrid), dim3(NT), 0, st, n,
-       k, M, (const double*)V.p, V.ph, S);
-    LK("bicg_spmm_A_dot1", (k_av<GK>), dim3(tgrid), dim3(NT), 0, st, n, k, A, V, S);
-    LK("bicg_finish", (k_fin<GK, 1, F_AV>), dim3(1), dim3(NT), 0, st, k, S, tgrid);
+    {
+      SAI_PROF(MF ? "bicg_spmm_M_f32" : "bicg_spmm_M_f64", st);
+      spmm_m(V.p, V.ph);
+    }
+    {
+      SAI_PROF("bicg_spmm_A_dot1", st);
+      spmm_av();
+    }
+    LK("bicg_finish", (k_fin<GK, 1, F_AV>), dim3(1), dim3(FNT), 0, st, k, S, tgrid);
     LK("bicg_s_update", (k_s<GK>), dim3(grid), dim3(NT), 0, st, n, k, V, S);
-    LK("bicg_finish", (k_fin<GK, 1, F_S>), dim3(1), dim3(NT), 0, st, k, S, grid);
+    LK("bicg_finish", (k_fin<GK, 1, F_S>), dim3(1), dim3(FNT), 0, st, k, S, grid);
     LK("bicg_halfcheck", (k_halfcheck<GK>), dim3(grid), dim3(NT), 0, st, n, k, A, V, S);
-    LK("bicg_finish", (k_fin<GK, 1, F_HALF>), dim3(1), dim3(NT), 0, st, k, S, grid);
+    LK("bicg_finish", (k_fin<GK, 1, F_HALF>), dim3(1), dim3(FNT), 0, st, k, S, grid);
     LK("bicg_halfapply", (k_halfapply<GK>), dim3(grid), dim3(NT), 0, st, n, k, V, S);
-    LK(MF ? "bicg_spmm_M_f32" : "bicg_spmm_M_f64", (k_spmm<GK, TM>), dim3(tgrid), dim3(NT), 0, st, n,
-       k, M, (const double*)V.s, V.sh, S);
-    LK("bicg_spmm_A_dot2", (k_at<GK>), dim3(tgrid), dim3(NT), 0, st, n, k, A, V, S);
-    LK("bicg_finish", (k_fin<GK, 2, F_AT>), dim3(1), dim3(NT), 0, st, k, S, tgrid);
+    {
+      SAI_PROF(MF ? "bicg_spmm_M_f32" : "bicg_spmm_M_f64", st);
+      spmm_m(V.s, V.sh);
+    }
+    {
+      SAI_PROF("bicg_spmm_A_dot2", st);
+      spmm_at();
+    }
+    LK("bicg_finish", (k_fin<GK, 2, F_AT>), dim3(1), dim3(FNT), 0, st, k, S, tgrid);
     LK("bicg_xr_update", (k_xr<GK>), dim3(grid), dim3(NT), 0, st, n, k, V, S);
-    LK("bicg_finish", (k_fin<GK, 2, F_XR>), dim3(1), dim3(NT), 0, st, k, S, grid);
+    LK("bicg_finish", (k_fin<GK, 2, F_XR>), dim3(1), dim3(FNT), 0, st, k, S, grid);
     LK("bicg_fullcheck", (k_fullcheck<GK>), dim3(grid), dim3(NT), 0, st, n, k, A, V, S);
-    LK("bicg_finish", (k_fin<GK, 2, F_FULL>), dim3(1), dim3(NT), 0, st, k, S, grid);
+    LK("bicg_finish", (k_fin<GK, 2, F_FULL>), dim3(1), dim3(FNT), 0, st, k, S, grid);
     LK("bicg_restart", (k_restart<GK>), dim3(grid), dim3(NT), 0, st, n, k, V, S);
-    LK("bicg_finish", (k_fin<GK, 1, F_RESTART>), dim3(1), dim3(NT), 0, st, k, S, grid);
+    LK("bicg_finish", (k_fin<GK, 1, F_RESTART>), dim3(1), dim3(FNT), 0, st, k, S, grid);
     LK("bicg_iter_end", k_iter_end, dim3(1), dim3(64), 0, st, k, S, it, maxit);
 #undef LK
     LAUNCH_CHECK();

@@ -152,6 +152,65 @@ __global__ void __launch_bounds__(64) k_pattern(int32_t n, int kind, const int32
   }
 }
 
+// I_k = union of P(A~(:, j)) over the given J_k (count pass: mode 0, fill: mode 1).
+template <int CAP>
+__global__ void __launch_bounds__(64) k_rows_of(int32_t n, const int32_t* __restrict__ cp,
+                                                const int32_t* __restrict__ ri,
+                                                const int64_t* __restrict__ jptr,
+                                                const int32_t* __restrict__ jidx, int mode,
+                                                int32_t* __restrict__ cntI,
+                                                const int64_t* __restrict__ iptr,
+                                                int32_t* __restrict__ iout, int* __restrict__ nover) {
+  constexpr int CAPJ = 256;
+  __shared__ int32_t cand[CAP];
+  __shared__ int32_t sJ[CAPJ];
+  __shared__ int32_t s_start[CAPJ];
+  __shared__ int32_t s_off[CAPJ + 1];
+  const int l = lane_id();
+  for (int64_t k = blockIdx.x; k < n; k += gridDim.x) {
+    const int64_t j0 = jptr[k];
+    const int nJ = (int)(jptr[k + 1] - j0);
+    if (nJ > CAPJ) { if (l == 0) atomicAdd(nover, 1); continue; }
+    for (int t = l; t < nJ; t += WAVE) sJ[t] = jidx[j0 + t];
+    __syncthreads();
+    const int m = gather_cols(cp, ri, sJ, nJ, cand, CAP, s_start, s_off);
+    if (m < 0) { if (l == 0) atomicAdd(nover, 1); __syncthreads(); continue; }
+    const int nI = sort_unique(cand, m, CAP);
+    if (mode == 0) {
+      if (l == 0) cntI[k] = nI;
+    } else {
+      const int64_t io = iptr[k];
+      for (int t = l; t < nI; t += WAVE) iout[io + t] = cand[t];
+    }
+    __syncthreads();
+  }
+}
+
+void rows_of_patterns(const sai_split_s* sp, hipStream_t st, const Allocator& al,
+                      const DBuf<int64_t>& jptr, const DBuf<int32_t>& jidx, DBuf<int64_t>& iptr,
+                      DBuf<int32_t>& iidx, DBuf<int32_t>& cntI) {
+  const int32_t n = sp->n;
+  constexpr int CAP = 8192;
+  cntI.alloc(&al, (size_t)n + 1);
+  DBuf<int> nover(&al, 2);
+  HIPC(hipMemsetAsync(nover.p, 0, 2 * sizeof(int), st));
+  const unsigned grid = (unsigned)std::min<int64_t>(n, 1 << 20);
+  hipLaunchKernelGGL((k_rows_of<CAP>), dim3(grid), dim3(64), 0, st, n, sp->t_col_ptr.p,
+                     sp->t_row_idx.p, jptr.p, jidx.p, 0, cntI.p, (const int64_t*)nullptr,
+                     (int32_t*)nullptr, nover.p);
+  LAUNCH_CHECK();
+  if (read_scalar(nover.p, st) > 0)
+    SAI_THROW(SAI_ETOOBIG, "a row set I_k exceeds %d candidate indices", CAP);
+  iptr.alloc(&al, (size_t)n + 1);
+  exclusive_scan_i32_to_i64(cntI.p, iptr.p, n, al, st);
+  const int64_t tot = read_scalar(iptr.p + n, st);
+  iidx.alloc(&al, (size_t)tot + 1);
+  hipLaunchKernelGGL((k_rows_of<CAP>), dim3(grid), dim3(64), 0, st, n, sp->t_col_ptr.p,
+                     sp->t_row_idx.p, jptr.p, jidx.p, 1, cntI.p, (const int64_t*)iptr.p, iidx.p,
+                     nover.p);
+  LAUNCH_CHECK();
+}
+
 __global__ void k_flag_neg(int32_t n, const int32_t* cnt, int32_t* flag) {
   const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (k < n) flag[k] = cnt[k] < 0 ? 1 : 0;

@@ -220,6 +220,10 @@ T read_scalar(const T* dev, hipStream_t st) {
   return v;
 }
 
+// Tuning knob `name` (kernel variant or size choice): the value of the
+// environment variable SAI_TUNE_<name> if set, else `dflt`.
+int tune_get(const char* name, int dflt);
+
 void fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st);
 void fill_f64(double* p, double v, int64_t n, hipStream_t st);
 void zero_bytes(void* p, size_t bytes, hipStream_t st);

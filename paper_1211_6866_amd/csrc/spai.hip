@@ -1,12 +1,459 @@
-// SPAI adaptive pattern search (Section 2.1).  Placeholder until the kernel lands.
+// SPAI adaptive pattern search on A~ (Section 2.1), in float64.
+//
+// One workgroup per column k.  Starting from J = P(A~(:, k)) (or {k}), each
+// step:
+//   I   = nonzero rows of A~(:, J)                         (gather, sort, unique)
+//   m   = argmin ||A~(I, J) m - e_k(I)||                   (Householder QR)
+//   r   = A~(:, J) m - e_k on I;  stop if ||r|| <= delta
+//   N   = nonzero columns of A~(I, :);  J~ = N \ J         (candi)
+//   g_j = (r^T A~ e_j)^2 / ||A~ e_j||^2 for j in J~        (from (muj), (rhoj):
+//         rho_j^2 = ||r||^2 - g_j, so the largest g_j are the smallest rho_j)
+//   J  += the per_step candidates of largest g_j (ties: smaller j).
+// After at most `steps` augmentations the final J_k is written; the final
+// least-squares solve in the build precision happens in the common column
+// solver, as for the static patterns.  The candidate set is taken
+// structurally (all rows of I_k), and the augmented problem is solved again
+// from scratch (the paper updates the factors; the minimiser is the same).
 #include "sai_internal.hpp"
 
 namespace sai {
 
-void spai_patterns(const sai_split_s*, const sai_build_opts&, hipStream_t, const Allocator&,
-                   DBuf<int64_t>&, DBuf<int32_t>&, DBuf<int64_t>&, DBuf<int32_t>&, DBuf<int32_t>&,
-                   DBuf<int32_t>&) {
-  SAI_THROW(SAI_EINVAL, "the SPAI pattern is not available in this build");
+void rows_of_patterns(const sai_split_s* sp, hipStream_t st, const Allocator& al,
+                      const DBuf<int64_t>& jptr, const DBuf<int32_t>& jidx, DBuf<int64_t>& iptr,
+                      DBuf<int32_t>& iidx, DBuf<int32_t>& cntI);
+
+namespace {
+
+constexpr int SNT = 256;
+constexpr int SJMAX = 128;   // |J_k| limit during the search
+constexpr int SCAPI = 2048;  // |I_k| limit during the search
+constexpr int SCAPN = 8192;  // candidate entries before de-duplication
+constexpr int NSLOT = 512;   // columns searched concurrently (workspace slots)
+
+enum { E_TOOBIG = 1, E_SING = 2 };
+
+struct Ws {
+  int32_t* I;     // SCAPI
+  int32_t* cand;  // SCAPN
+  int32_t* off;   // SCAPI + 1
+  double* W;      // SCAPI * (SJMAX + 1), column-major block + right-hand side
+  double* r;      // SCAPI
+  double* g;      // SCAPN
+};
+
+__device__ __forceinline__ int bsearch_eq(const int32_t* a, int n, int32_t x) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (a[mid] < x) lo = mid + 1; else hi = mid;
+  }
+  return (lo < n && a[lo] == x) ? lo : -1;
+}
+
+__device__ double blk_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
+  __syncthreads();
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < SNT / WAVE; ++i) s += red[i];
+  __syncthreads();
+  return s;
+}
+
+// In-place exclusive prefix sum of a[0..m); returns the total.
+__device__ int blk_exscan(int32_t* a, int m, int* wsum /* SNT/WAVE + 1 */) {
+  const int tid = threadIdx.x, w = tid / WAVE, l = tid % WAVE;
+  int carry = 0;
+  for (int base = 0; base < m; base += SNT) {
+    const int i = base + tid;
+    const int v = i < m ? a[i] : 0;
+    int incl = v;
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+      const int t = __shfl_up(incl, o, WAVE);
+      if (l >= o) incl += t;
+    }
+    __syncthreads();
+    if (l == WAVE - 1) wsum[w] = incl;
+    __syncthreads();
+    int woff = 0, tot = 0;
+    for (int q = 0; q < SNT / WAVE; ++q) {
+      if (q < w) woff += wsum[q];
+      tot += wsum[q];
+    }
+    if (i < m) a[i] = carry + woff + incl - v;
+    carry += tot;
+    __syncthreads();
+  }
+  return carry;
+}
+
+// Keep a[i] where keep(i) holds, preserving order (in place); returns the count.
+template <class Pred>
+__device__ int blk_compact(int32_t* a, int m, Pred keep, int* wsum) {
+  const int tid = threadIdx.x, w = tid / WAVE, l = tid % WAVE;
+  int out = 0;
+  for (int base = 0; base < m; base += SNT) {
+    const int i = base + tid;
+    int32_t v = 0;
+    bool k = false;
+    if (i < m) {
+      v = a[i];
+      k = keep(i, v);
+    }
+    const unsigned long long bal = __ballot(k);
+    const int before = __popcll(bal & ((l == 0) ? 0ull : (~0ull >> (64 - l))));
+    __syncthreads();
+    if (l == 0) wsum[w] = __popcll(bal);
+    __syncthreads();
+    int woff = 0, tot = 0;
+    for (int q = 0; q < SNT / WAVE; ++q) {
+      if (q < w) woff += wsum[q];
+      tot += wsum[q];
+    }
+    if (k) a[out + woff + before] = v;
+    out += tot;
+    __syncthreads();
+  }
+  return out;
+}
+
+// Bitonic sort of a[0..m) (padded to a power of two <= cap) and de-duplication.
+__device__ int blk_sort_unique(int32_t* a, int m, int* wsum) {
+  const int tid = threadIdx.x;
+  int P = 1;
+  while (P < m) P <<= 1;
+  for (int i = m + tid; i < P; i += SNT) a[i] = 0x7fffffff;
+  __syncthreads();
+  for (int k = 2; k <= P; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int t = tid; t < (P >> 1); t += SNT) {
+        const int i = 2 * j * (t / j) + (t % j);
+        const int q = i + j;
+        const int32_t x = a[i], y = a[q];
+        if ((x > y) == ((i & k) == 0)) { a[i] = y; a[q] = x; }
+      }
+      __syncthreads();
+    }
+  }
+  // the predicate reads the sorted array before any write of this chunk
+  return blk_compact(a, m, [&](int i, int32_t v) { return i == 0 || a[i - 1] != v; }, wsum);
+}
+
+__global__ void __launch_bounds__(SNT) k_colnorm2(int32_t n, const int32_t* cp, const double* cv,
+                                                  double* out) {
+  const int64_t j = (int64_t)blockIdx.x * SNT + threadIdx.x;
+  if (j >= n) return;
+  double s = 0.0;
+  for (int32_t e = cp[j]; e < cp[j + 1]; ++e) s += cv[e] * cv[e];
+  out[j] = s;
+}
+
+__global__ void __launch_bounds__(SNT) k_spai(int32_t n, const int32_t* __restrict__ cp,
+                                              const int32_t* __restrict__ ri,
+                                              const double* __restrict__ cv,
+                                              const int32_t* __restrict__ rp,
+                                              const int32_t* __restrict__ ci,
+                                              const double* __restrict__ cn2, int steps, int per,
+                                              double delta, int init,
+                                              const int64_t* __restrict__ jpoff,
+                                              int32_t* __restrict__ jpad, int32_t* __restrict__ cntJ,
+                                              Ws ws0, int* __restrict__ err) {
+  __shared__ int32_t sJ[SJMAX + 8];
+  __shared__ double sm[SJMAX];
+  __shared__ double sd[SJMAX + 1];
+  __shared__ double red[SNT / WAVE];
+  __shared__ int wsum[SNT / WAVE + 1];
+  __shared__ int32_t chosen[16];
+  __shared__ int s_int[4];
+  const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
+  const int slot = blockIdx.x;
+  Ws ws;
+  ws.I = ws0.I + (int64_t)slot * SCAPI;
+  ws.cand = ws0.cand + (int64_t)slot * SCAPN;
+  ws.off = ws0.off + (int64_t)slot * (SCAPI + 1);
+  ws.W = ws0.W + (int64_t)slot * SCAPI * (SJMAX + 1);
+  ws.r = ws0.r + (int64_t)slot * SCAPI;
+  ws.g = ws0.g + (int64_t)slot * SCAPN;
+
+  for (int64_t k = blockIdx.x; k < n; k += gridDim.x) {
+    // ---- initial pattern
+    int nJ;
+    if (init == SAI_INIT_DIAG) {
+      if (tid == 0) sJ[0] = (int32_t)k;
+      nJ = 1;
+    } else {
+      nJ = cp[k + 1] - cp[k];
+      if (nJ > SJMAX) {
+        if (tid == 0) atomicOr(err, E_TOOBIG);
+        continue;
+      }
+      for (int t = tid; t < nJ; t += SNT) sJ[t] = ri[cp[k] + t];
+    }
+    __syncthreads();
+    bool fail = false;
+    for (int step = 0; step < steps; ++step) {
+      // ---- I = rows of A~(:, J)
+      int tot = 0;
+      if (tid == 0) {
+        int acc = 0;
+        for (int c = 0; c < nJ; ++c) {
+          ws.off[c] = acc;
+          acc += cp[sJ[c] + 1] - cp[sJ[c]];
+        }
+        ws.off[nJ] = acc;
+        s_int[0] = acc;
+      }
+      __syncthreads();
+      tot = s_int[0];
+      if (tot > SCAPN) { fail = true; break; }
+      for (int f = tid; f < tot; f += SNT) {
+        int lo = 0, hi = nJ - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (ws.off[mid] <= f) lo = mid; else hi = mid - 1;
+        }
+        ws.cand[f] = ri[cp[sJ[lo]] + (f - ws.off[lo])];
+      }
+      __syncthreads();
+      const int nI = blk_sort_unique(ws.cand, tot, wsum);
+      if (nI > SCAPI || nI < nJ) { fail = true; break; }
+      for (int t = tid; t < nI; t += SNT) ws.I[t] = ws.cand[t];
+      __syncthreads();
+      // ---- dense block A~(I, J) (column-major, ld nI) and e_k(I) in column nJ
+      double* W = ws.W;
+      double* bv = W + (int64_t)nI * nJ;
+      for (int64_t t = tid; t < (int64_t)nI * (nJ + 1); t += SNT) W[t] = 0.0;
+      __syncthreads();
+      for (int c = 0; c < nJ; ++c) {
+        const int32_t j = sJ[c];
+        for (int32_t e = cp[j] + tid; e < cp[j + 1]; e += SNT) {
+          const int pos = bsearch_eq(ws.I, nI, ri[e]);
+          W[(int64_t)c * nI + pos] = cv[e];
+        }
+      }
+      for (int t = tid; t < nI; t += SNT) bv[t] = (ws.I[t] == k) ? 1.0 : 0.0;
+      __syncthreads();
+      // ---- Householder QR, Q^T applied to the right-hand side
+      bool sing = false;
+      for (int j = 0; j < nJ; ++j) {
+        double* colj = W + (int64_t)j * nI;
+        double tail = 0.0;
+        for (int t = j + 1 + tid; t < nI; t += SNT) tail += colj[t] * colj[t];
+        tail = blk_sum(tail, red);
+        const double alpha = colj[j];
+        const double normx = sqrt(tail + alpha * alpha);
+        const double sgn = alpha >= 0.0 ? 1.0 : -1.0;
+        const double vj = alpha + sgn * normx;
+        const double vtv = tail + vj * vj;
+        if (!(normx > 0.0)) sing = true;
+        const double tau = normx > 0.0 ? 2.0 / vtv : 0.0;
+        __syncthreads();
+        if (tid == 0) colj[j] = vj;
+        __syncthreads();
+        for (int c = j + 1 + w; c <= nJ; c += SNT / WAVE) {
+          const double* colc = W + (int64_t)c * nI;
+          double d = 0.0;
+          for (int t = j + lane; t < nI; t += WAVE) d += colj[t] * colc[t];
+          d = wave_sum(d);
+          if (lane == 0) sd[c] = tau * d;
+        }
+        __syncthreads();
+        const int rows = nI - j, ncol = nJ - j;
+        for (int64_t t = tid; t < (int64_t)rows * ncol; t += SNT) {
+          const int c = j + 1 + (int)(t / rows);
+          const int rr = j + (int)(t % rows);
+          W[(int64_t)c * nI + rr] -= sd[c] * colj[rr];
+        }
+        __syncthreads();
+        if (tid == 0) colj[j] = -sgn * normx;
+        __syncthreads();
+      }
+      if (sing) { fail = true; break; }
+      if (w == 0) {
+        for (int c = nJ - 1; c >= 0; --c) {
+          double part = 0.0;
+          for (int q = c + 1 + lane; q < nJ; q += WAVE) part += W[(int64_t)q * nI + c] * sm[q];
+          part = wave_sum(part);
+          if (lane == 0) sm[c] = (bv[c] - part) / W[(int64_t)c * nI + c];
+        }
+      }
+      __syncthreads();
+      // ---- residual r = A~(:, J) m - e_k on I (columns added in order)
+      for (int t = tid; t < nI; t += SNT) ws.r[t] = (ws.I[t] == k) ? -1.0 : 0.0;
+      __syncthreads();
+      for (int c = 0; c < nJ; ++c) {
+        const int32_t j = sJ[c];
+        const double mc = sm[c];
+        for (int32_t e = cp[j] + tid; e < cp[j + 1]; e += SNT) {
+          const int pos = bsearch_eq(ws.I, nI, ri[e]);
+          ws.r[pos] += cv[e] * mc;
+        }
+        __syncthreads();
+      }
+      double rr = 0.0;
+      for (int t = tid; t < nI; t += SNT) rr += ws.r[t] * ws.r[t];
+      rr = blk_sum(rr, red);
+      if (sqrt(rr) <= delta) break;
+      // ---- candidates: nonzero columns of A~(I, :), minus J
+      for (int t = tid; t < nI; t += SNT) ws.off[t] = rp[ws.I[t] + 1] - rp[ws.I[t]];
+      __syncthreads();
+      const int ntot = blk_exscan(ws.off, nI, wsum);
+      if (tid == 0) ws.off[nI] = ntot;
+      __syncthreads();
+      if (ntot > SCAPN) { fail = true; break; }
+      for (int f = tid; f < ntot; f += SNT) {
+        int lo = 0, hi = nI - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (ws.off[mid] <= f) lo = mid; else hi = mid - 1;
+        }
+        ws.cand[f] = ci[rp[ws.I[lo]] + (f - ws.off[lo])];
+      }
+      __syncthreads();
+      int nN = blk_sort_unique(ws.cand, ntot, wsum);
+      nN = blk_compact(ws.cand, nN, [&](int, int32_t v) { return bsearch_eq(sJ, nJ, v) < 0; }, wsum);
+      if (nN == 0) break;
+      // ---- gains g_j = (r^T A~ e_j)^2 / ||A~ e_j||^2
+      for (int t = tid; t < nN; t += SNT) {
+        const int32_t j = ws.cand[t];
+        double tj = 0.0;
+        for (int32_t e = cp[j]; e < cp[j + 1]; ++e) {
+          const int pos = bsearch_eq(ws.I, nI, ri[e]);
+          if (pos >= 0) tj += ws.r[pos] * cv[e];
+        }
+        ws.g[t] = tj * tj / cn2[j];
+      }
+      __syncthreads();
+      // ---- the `add` largest gains, ties to the smaller column index
+      const int add = min(min(per, nN), SJMAX - nJ);
+      for (int q = 0; q < add; ++q) {
+        double bg = -1.0;
+        int bt = -1;
+        for (int t = tid; t < nN; t += SNT) {
+          const double gv = ws.g[t];
+          if (gv > bg || (gv == bg && bt >= 0 && ws.cand[t] < ws.cand[bt])) { bg = gv; bt = t; }
+        }
+        // wave argmax, then across waves
+        for (int o = WAVE / 2; o > 0; o >>= 1) {
+          const double og = __shfl_xor(bg, o, WAVE);
+          const int ot = __shfl_xor(bt, o, WAVE);
+          const bool better = ot >= 0 && (og > bg || (og == bg && (bt < 0 || ws.cand[ot] < ws.cand[bt])));
+          if (better) { bg = og; bt = ot; }
+        }
+        __syncthreads();
+        if (lane == 0) { red[w] = bg; wsum[w] = bt; }
+        __syncthreads();
+        if (tid == 0) {
+          double gbest = -1.0;
+          int tbest = -1;
+          for (int q2 = 0; q2 < SNT / WAVE; ++q2) {
+            const double og = red[q2];
+            const int ot = wsum[q2];
+            if (ot >= 0 && (og > gbest || (og == gbest && (tbest < 0 || ws.cand[ot] < ws.cand[tbest])))) {
+              gbest = og;
+              tbest = ot;
+            }
+          }
+          chosen[q] = ws.cand[tbest];
+          ws.g[tbest] = -2.0;  // taken
+        }
+        __syncthreads();
+      }
+      // ---- J = sorted(J + chosen)
+      if (tid == 0) {
+        for (int q = 0; q < add; ++q) {
+          const int32_t v = chosen[q];
+          int pos = nJ;
+          while (pos > 0 && sJ[pos - 1] > v) {
+            sJ[pos] = sJ[pos - 1];
+            --pos;
+          }
+          sJ[pos] = v;
+          ++nJ;
+        }
+        s_int[1] = nJ;
+      }
+      __syncthreads();
+      nJ = s_int[1];
+    }
+    if (fail) {
+      if (tid == 0) atomicOr(err, E_TOOBIG);
+      __syncthreads();
+      continue;
+    }
+    const int64_t o = jpoff[k];
+    for (int t = tid; t < nJ; t += SNT) jpad[o + t] = sJ[t];
+    if (tid == 0) cntJ[k] = nJ;
+    __syncthreads();
+  }
+}
+
+__global__ void k_spai_ub(int32_t n, const int32_t* cp, int init, int extra, int32_t* ub) {
+  const int64_t k = (int64_t)blockIdx.x * SNT + threadIdx.x;
+  if (k < n) ub[k] = (init == SAI_INIT_DIAG ? 1 : cp[k + 1] - cp[k]) + extra;
+}
+
+__global__ void k_compact_lists(int32_t n, const int64_t* __restrict__ poff,
+                                const int32_t* __restrict__ pad, const int64_t* __restrict__ off,
+                                int32_t* __restrict__ out) {
+  const int64_t k = (int64_t)blockIdx.x * SNT + threadIdx.x;
+  if (k >= n) return;
+  const int64_t a = off[k], b = off[k + 1], p = poff[k];
+  for (int64_t t = 0; t < b - a; ++t) out[a + t] = pad[p + t];
+}
+
+}  // namespace
+
+void spai_patterns(const sai_split_s* sp, const sai_build_opts& o, hipStream_t st,
+                   const Allocator& al, DBuf<int64_t>& jptr, DBuf<int32_t>& jidx,
+                   DBuf<int64_t>& iptr, DBuf<int32_t>& iidx, DBuf<int32_t>& cntJ,
+                   DBuf<int32_t>& cntI) {
+  const int32_t n = sp->n;
+  if (o.spai_steps < 0 || o.spai_per_step < 1 || o.spai_per_step > 16)
+    SAI_THROW(SAI_EINVAL, "spai_steps >= 0 and 1 <= spai_per_step <= 16 required");
+  if (o.spai_init != SAI_INIT_PATTERN_A && o.spai_init != SAI_INIT_DIAG)
+    SAI_THROW(SAI_EINVAL, "bad spai_init");
+  SAI_PROF("spai_search", st);
+  DBuf<double> cn2(&al, (size_t)n);
+  hipLaunchKernelGGL(k_colnorm2, dim3(grid_for(n, SNT)), dim3(SNT), 0, st, n, sp->t_col_ptr.p,
+                     sp->t_cval.p, cn2.p);
+  LAUNCH_CHECK();
+  DBuf<int32_t> ub(&al, (size_t)n + 1);
+  hipLaunchKernelGGL(k_spai_ub, dim3(grid_for(n, SNT)), dim3(SNT), 0, st, n, sp->t_col_ptr.p,
+                     o.spai_init, o.spai_steps * o.spai_per_step, ub.p);
+  LAUNCH_CHECK();
+  DBuf<int64_t> poff(&al, (size_t)n + 1);
+  exclusive_scan_i32_to_i64(ub.p, poff.p, n, al, st);
+  const int64_t ptot = read_scalar(poff.p + n, st);
+  DBuf<int32_t> pad(&al, (size_t)ptot + 1);
+  cntJ.alloc(&al, (size_t)n + 1);
+  const int nslot = (int)std::min<int64_t>(n, NSLOT);
+  DBuf<int32_t> wI(&al, (size_t)nslot * SCAPI), wc(&al, (size_t)nslot * SCAPN),
+      wo(&al, (size_t)nslot * (SCAPI + 1));
+  DBuf<double> wW(&al, (size_t)nslot * SCAPI * (SJMAX + 1)), wr(&al, (size_t)nslot * SCAPI),
+      wg(&al, (size_t)nslot * SCAPN);
+  DBuf<int> err(&al, 1);
+  HIPC(hipMemsetAsync(err.p, 0, sizeof(int), st));
+  Ws ws{wI.p, wc.p, wo.p, wW.p, wr.p, wg.p};
+  hipLaunchKernelGGL(k_spai, dim3(nslot), dim3(SNT), 0, st, n, sp->t_col_ptr.p, sp->t_row_idx.p,
+                     sp->t_cval.p, sp->t_row_ptr.p, sp->t_col_idx.p, cn2.p, o.spai_steps,
+                     o.spai_per_step, o.delta, o.spai_init, poff.p, pad.p, cntJ.p, ws, err.p);
+  LAUNCH_CHECK();
+  const int e = read_scalar(err.p, st);
+  if (e)
+    SAI_THROW(SAI_ETOOBIG, "SPAI search exceeded |J| <= %d, |I| <= %d or %d candidates (or a "
+              "rank-deficient block)", SJMAX, SCAPI, SCAPN);
+  jptr.alloc(&al, (size_t)n + 1);
+  exclusive_scan_i32_to_i64(cntJ.p, jptr.p, n, al, st);
+  const int64_t jtot = read_scalar(jptr.p + n, st);
+  jidx.alloc(&al, (size_t)jtot + 1);
+  hipLaunchKernelGGL(k_compact_lists, dim3(grid_for(n, SNT)), dim3(SNT), 0, st, n, poff.p, pad.p,
+                     jptr.p, jidx.p);
+  LAUNCH_CHECK();
+  rows_of_patterns(sp, st, al, jptr, jidx, iptr, iidx, cntI);
 }
 
 }  // namespace sai

@@ -213,6 +213,13 @@ void exclusive_scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, const
   scan_rec<int32_t, int64_t>(in, out, n, al, st);
 }
 
+int tune_get(const char* name, int dflt) {
+  char key[128];
+  snprintf(key, sizeof(key), "SAI_TUNE_%s", name);
+  const char* v = getenv(key);
+  return (v && *v) ? atoi(v) : dflt;
+}
+
 void fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st) {
   if (n <= 0) return;
   hipLaunchKernelGGL((k_fill<int32_t>), dim3(grid_for(n, 256, 65536)), dim3(256), 0, st, p, v, n);

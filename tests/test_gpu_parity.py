@@ -108,6 +108,36 @@ def test_patterns_and_columns(name, kind, prec):
     print(f"worst column rel err {worst:.2e}")
 
 
+@pytest.mark.parametrize("delta,init,prec", [(0.4, P.INIT_PATTERN_A, P.FP64),
+                                              (0.05, P.INIT_PATTERN_A, P.FP64),
+                                              (0.05, P.INIT_PATTERN_A, P.FP32),
+                                              (0.2, P.INIT_DIAG, P.FP64)])
+def test_spai_patterns_and_columns(delta, init, prec):
+    from oracle import spai as ospai
+    w, (rp, ci, va) = _load("c3_3000")
+    S = osplit.split(w.A)
+    n = w.A.shape[0]
+    g = P.Split(rp, ci, va)
+    pc = P.Precond(g, pattern=P.PAT_SPAI, drop=P.DROP_NONE, delta=delta, spai_steps=3,
+                   spai_per_step=5, spai_init=init, precision=prec, keep_lists=True)
+    arr = pc.arrays()
+    jp, ji, ip, ii = (_np(arr[k]) for k in ("j_ptr", "j_idx", "i_ptr", "i_idx"))
+    mf = _np(arr["m_full"]).astype(np.float64)
+    out = ospai.spai(S.At, steps=3, per_step=5, delta=delta,
+                     init="A" if init == P.INIT_PATTERN_A else "diag")
+    tol = 1e-12 if prec == P.FP64 else 1e-4
+    augmented = 0
+    for k in range(n):
+        J, I, m, res, taken = out[k]
+        augmented += taken > 0
+        assert np.array_equal(ji[jp[k]:jp[k + 1]], J), k     # adaptive pattern: bit-exact
+        assert np.array_equal(ii[ip[k]:ip[k + 1]], I), k
+        e = np.linalg.norm(mf[jp[k]:jp[k + 1]] - m) / np.linalg.norm(m)
+        assert e <= tol, (k, e)
+    assert augmented > 0
+    print(f"delta={delta}: {augmented} columns augmented")
+
+
 @pytest.mark.parametrize("drop,prec", [(P.DROP_ABS, P.FP64), (P.DROP_TOLK, P.FP64),
                                        (P.DROP_ABS, P.FP32)])
 def test_drop_and_assembly(drop, prec):
