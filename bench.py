@@ -1,24 +1,27 @@
 #!/usr/bin/env python3
 """Benchmark of the SMW-split SAI path on one MI355X.
 
-Workload (default): 3D 7-point convection-diffusion on a 100^3 grid
-(n = 1,000,000) with s = 10 seeded dense columns at 5% density; static
+Default workload (--workload 2): 3D 7-point convection-diffusion on a 100^3
+grid (n = 1,000,000) with s = 10 seeded dense columns at 5% density; static
 pattern P(|A~|^2) with absolute dropping 1e-3; M built in FP32 ("mixed"),
 Krylov/SMW/check in FP64; 11 right-hand sides in one batched BiCGStab,
-eps = 1e-8.
+eps = 1e-8.  Workloads 1, 3, 4 and 5 are the other four configurations
+(GMRES(30) on a 45x45 grid; SPAI on a random n = 200,000 matrix; the 500x500
+grid with the adjoint; the 160^3 grid with 51 right-hand sides and the
+adjoint).
 
 One step = the whole path on inputs already resident in HBM: split A into
 A~ + U V^T, build M (patterns, column QR, dropping, CSC/CSR assembly), solve
-the s+1 systems to the paper's stopping rules, SMW recovery, and the FP64
-residual check.  value = n / (time per step): SAI columns carried to a 1e-8
-solution per second; the same step with M in FP64 ("plain") is timed after
+the s+1 systems to the paper's stopping rules, SMW recovery and the FP64
+residual check (plus, for the workloads with a loss, the adjoint solve and
+the gradients).  value = n / (time per step): SAI columns carried to a 1e-8
+solution per second.  The same step with M in FP64 ("plain") is timed after
 it.  Prints one JSON line.
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -39,6 +42,25 @@ LS_VARIANTS = {
 }
 
 
+def workload_settings(P, idx):
+    base = dict(pattern=P.PAT_A2, drop=P.DROP_ABS, tau=1e-3)
+    solve = dict(method=P.BICGSTAB, eps=1e-8, maxit=500)
+    if idx == 1:
+        return ("2d5pt_45x45_s3_dense20pct_patternA_gmres30",
+                dict(pattern=P.PAT_A, drop=P.DROP_NONE), dict(solve, method=P.GMRES, restart=30), False)
+    if idx == 2:
+        return "3d7pt_100^3_s10_dense5pct_psai_A2_drop1e-3", base, solve, False
+    if idx == 3:
+        return ("random_n200000_s20_dense2pct_spai_3x5_delta0.4",
+                dict(pattern=P.PAT_SPAI, drop=P.DROP_NONE, delta=0.4, spai_steps=3, spai_per_step=5),
+                solve, False)
+    if idx == 4:
+        return "2d5pt_500x500_s8_dense3pct_psai_A2_drop1e-3_adjoint", base, solve, True
+    if idx == 5:
+        return "3d7pt_160^3_s50_dense1pct_psai_A2_drop1e-3_adjoint", base, solve, True
+    raise SystemExit(f"unknown workload {idx}")
+
+
 def ls_flops(nI, nJ):
     """Householder QR of |I| x |J|, Q^T e and back-substitution."""
     return 2.0 * nJ * nJ * (nI - nJ / 3.0) + 4.0 * nI * nJ - nJ * nJ
@@ -48,64 +70,66 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w, gpu_iters, gpu_nnz_m, seconds=20.0):
+def cpu_baseline(w, bkw, gpu_iters, gpu_nnz_m, seconds=20.0):
     """The FP64 oracle, as it stands, timed on a bounded sample of the same workload."""
     import numpy as np
     import scipy.sparse as sp
-    try:
-        from threadpoolctl import threadpool_limits
-        limiter = threadpool_limits(1)
-        limiter.__enter__()
-    except Exception:  # noqa: BLE001
-        limiter = None
+    from threadpoolctl import threadpool_limits
+
     from oracle import drop as odrop
     from oracle import krylov as okry
     from oracle import lsq as olsq
     from oracle import pattern as opat
+    from oracle import spai as ospai
     from oracle import split as osplit
 
-    n = w.A.shape[0]
-    t0 = time.perf_counter()
-    S = osplit.split(w.A)
-    t_split = time.perf_counter() - t0
-    C = opat.as_csc(S.At)
-    rng = np.random.default_rng(0)
-    cols = rng.choice(n, size=n, replace=False)
-    t0 = time.perf_counter()
-    done = 0
-    budget = 0.5 * seconds
-    while done < cols.size and time.perf_counter() - t0 < budget:
-        k = int(cols[done])
-        J = opat.pattern_A2(C, k)
-        I, m, r = olsq.solve_column(C, J, k)
-        odrop.drop_column(m, 1e-3)
-        done += 1
-    t_col = (time.perf_counter() - t0) / done
-    # Krylov: two oracle BiCGStab iterations per right-hand side on the full
-    # system, with an operator of M's size (the P(|A~|^2) pattern, values 1/nnz).
-    At = sp.csr_matrix(S.At)
-    B = (At != 0).astype(np.float64)
-    Mp = sp.coo_matrix(B @ B)
-    keep = rng.random(Mp.nnz) < min(1.0, gpu_nnz_m / max(Mp.nnz, 1))  # M's size after dropping
-    Mp = sp.csr_matrix((np.full(int(keep.sum()), 1.0 / n), (Mp.row[keep], Mp.col[keep])),
-                       shape=(n, n))
-    R = np.zeros((n, S.s + 1))
-    R[:, 0] = w.b
-    R[:, 1:] = S.U.toarray()
-    t0 = time.perf_counter()
-    for c in range(S.s + 1):
-        okry.bicgstab(At, Mp, R[:, c], 1e-300, maxit=2)
-    t_two = time.perf_counter() - t0
-    t_iter = t_two / 2.0
-    est = t_split + n * t_col + gpu_iters * t_iter
-    if limiter is not None:
-        limiter.__exit__(None, None, None)
+    with threadpool_limits(1):
+        n = w.A.shape[0]
+        t0 = time.perf_counter()
+        S = osplit.split(w.A)
+        t_split = time.perf_counter() - t0
+        C = opat.as_csc(S.At)
+        R = sp.csr_matrix(S.At)
+        R.sort_indices()
+        cn2 = ospai.column_norms2(C) if bkw.get("pattern") == 2 else None
+        rng = np.random.default_rng(0)
+        cols = rng.permutation(n)
+        t0 = time.perf_counter()
+        done = 0
+        while done < n and time.perf_counter() - t0 < 0.5 * seconds:
+            k = int(cols[done])
+            if bkw.get("pattern") == 2:
+                ospai.spai_column(C, R, cn2, k, bkw["spai_steps"], bkw["spai_per_step"], bkw["delta"])
+            else:
+                J = opat.pattern_A(C, k) if bkw.get("pattern") == 0 else opat.pattern_A2(C, k)
+                I, m, r = olsq.solve_column(C, J, k)
+                if bkw.get("drop") == 1:
+                    odrop.drop_column(m, bkw["tau"])
+            done += 1
+        t_col = (time.perf_counter() - t0) / done
+        # Krylov: two oracle BiCGStab iterations per right-hand side at full n, with an
+        # operator of M's size (P(A~) or P(|A~|^2) thinned to nnz(M), values 1/n).
+        At = sp.csr_matrix(S.At)
+        B = (At != 0).astype(np.float64)
+        Mp = sp.coo_matrix(B @ B if bkw.get("pattern") == 1 else B)
+        keep = rng.random(Mp.nnz) < min(1.0, gpu_nnz_m / max(Mp.nnz, 1))
+        Mp = sp.csr_matrix((np.full(int(keep.sum()), 1.0 / n), (Mp.row[keep], Mp.col[keep])),
+                           shape=(n, n))
+        Rb = np.zeros((n, S.s + 1))
+        Rb[:, 0] = w.b
+        Rb[:, 1:] = S.U.toarray()
+        t0 = time.perf_counter()
+        for c in range(S.s + 1):
+            okry.bicgstab(At, Mp, Rb[:, c], 1e-300, maxit=2)
+        t_two = time.perf_counter() - t0
+    est = t_split + n * t_col + gpu_iters * t_two / 2.0
     return dict(
-        value=n / est, unit="columns/s (whole path, estimated from the sample)", cores=1, kind="oracle",
-        sample=(f"oracle split of the full matrix ({t_split:.2f} s); pattern + column QR + drop on "
+        value=n / est, unit="columns/s (whole path, estimated from the sample)", cores=1,
+        kind="oracle",
+        sample=(f"oracle split of the full matrix ({t_split:.2f} s); column pattern + QR (+ drop) on "
                 f"{done} random columns ({t_col * 1e6:.0f} us/column, x n); 2 BiCGStab iterations on "
-                f"all {S.s + 1} right-hand sides at full n with an operator of M's pattern "
-                f"({t_two:.2f} s, scaled by M's nnz and x {gpu_iters} iterations)"),
+                f"all {S.s + 1} right-hand sides at full n with an operator of nnz(M) "
+                f"({t_two:.2f} s, x {gpu_iters} / 2)"),
         est_seconds=est)
 
 
@@ -114,6 +138,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", type=int, default=2)
     ap.add_argument("--plain-steps", type=int, default=None)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -129,19 +154,23 @@ def main():
     import paper_1211_6866_amd as P
     import workloads as W
 
-    log("bench: generating workload 3D 100^3, s=10")
-    w = W.make(2)
+    name, bkw, skw, adjoint = workload_settings(P, args.workload)
+    log(f"bench: generating workload {args.workload} ({name})")
+    w = W.make(args.workload)
     n = w.A.shape[0]
     rp, ci, va = P.csr_to_device(w.A)
     b = torch.from_numpy(w.b).cuda()
-    bkw = dict(pattern=P.PAT_A2, drop=P.DROP_ABS, tau=1e-3)
-    skw = dict(method=P.BICGSTAB, eps=1e-8, maxit=500)
+    xstar = torch.from_numpy(W.x_star(n, w.seed)).cuda() if adjoint else None
+    times = {}
 
     def step(prec):
         sp_ = P.Split(rp, ci, va)
         pc = P.Precond(sp_, precision=prec, **bkw)
         x, st = P.solve(sp_, pc, b, **skw)
-        return sp_, pc, x, st
+        bst = None
+        if adjoint:
+            gb, ga, bst = P.backward(sp_, pc, x, x - xstar, **skw)
+        return sp_, pc, x, st, bst
 
     for i in range(args.warmup):
         log(f"bench: warmup {i}")
@@ -152,26 +181,32 @@ def main():
         P.profile_enable(True)
         t0 = time.perf_counter()
         last = None
-        builds = []
+        builds, solves, backs = [], [], []
         for i in range(K):
             last = step(prec)
             builds.append(last[1].stats.t_total_ms)
+            solves.append(last[3]["t_solve_ms"])
+            if last[4] is not None:
+                backs.append(last[4]["t_solve_ms"] + last[4]["t_smw_ms"])
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         prof = P.profile_read()
         P.profile_enable(False)
-        return (t1 - t0) / K * 1e3, last, prof, builds
+        return (t1 - t0) / K * 1e3, last, prof, builds, solves, backs
 
     log(f"bench: timing {args.steps} mixed steps")
-    ms_mixed, (sp_m, pc_m, x_m, st_m), prof, builds_m = timed(P.FP32, args.steps)
+    ms_mixed, (sp_m, pc_m, x_m, st_m, bst_m), prof, builds_m, solves_m, backs_m = timed(P.FP32, args.steps)
     kplain = args.plain_steps if args.plain_steps is not None else max(1, args.steps // 2)
-    log(f"bench: timing {kplain} plain FP64 steps")
-    ms_plain, (sp_p, pc_p, x_p, st_p), _, builds_p = timed(P.FP64, kplain)
+    plain = None
+    if kplain > 0:
+        log(f"bench: timing {kplain} plain FP64 steps")
+        ms_plain, (sp_p, pc_p, x_p, st_p, bst_p), _, builds_p, solves_p, _ = timed(P.FP64, kplain)
+        xhp = x_p.cpu().numpy()
+        plain = dict(ms=ms_plain, build=float(np.mean(builds_p)), st=st_p,
+                     rr_host=float(np.linalg.norm(w.b - w.A @ xhp) / np.linalg.norm(w.b)))
 
     xh = x_m.cpu().numpy()
     rr_host = float(np.linalg.norm(w.b - w.A @ xh) / np.linalg.norm(w.b))
-    xhp = x_p.cpu().numpy()
-    rr_host_p = float(np.linalg.norm(w.b - w.A @ xhp) / np.linalg.norm(w.b))
 
     # algorithmic work per kernel, for the roofline of the dominant one
     s = sp_m.s
@@ -190,7 +225,6 @@ def main():
         sel = (~assigned) & (nI <= maxI) & (nJ <= maxJ)
         assigned |= sel
         ls_work["ls_qr_f32_" + tag] = float(flops[sel].sum())
-    per_iter = int(st_m["iters_max"])
     bytes_kn = 8.0 * k * n
     hbm_bytes = {
         "bicg_spmm_M_f32": 8.0 * nnz_m + 4.0 * (n + 1) + 2 * bytes_kn,
@@ -200,15 +234,14 @@ def main():
         "bicg_s_update": 3 * bytes_kn,
         "bicg_xr_update": 8 * bytes_kn,
     }
-    kernels = []
-    for name, (launches, tot) in prof.items():
-        kernels.append((tot, name, launches))
-    kernels.sort(reverse=True)
-    dom_ms, dom, dom_launches = kernels[0]
+    kernels = sorted(((tot, nm, l) for nm, (l, tot) in prof.items()), reverse=True)
+    # the dominant kernel: the largest total among single kernels (scopes that cover
+    # several launches, like "split" or "spai_search", are listed but not chosen)
+    scopes = {"split", "smw_recover", "spai_search", "gmres_fused"}
+    dom_ms, dom, dom_launches = next(x for x in kernels if x[1] not in scopes)
     avg_ms = dom_ms / dom_launches
     if dom.startswith("ls_qr_f32"):
-        work = ls_work.get(dom, 0.0)
-        ach = work / (avg_ms * 1e-3) / 1e12
+        ach = ls_work.get(dom, 0.0) / (avg_ms * 1e-3) / 1e12
         roof = dict(bound="alu", achieved=round(ach, 3), peak=FP32_VEC_TFLOPS, unit="TFLOP/s",
                     frac=round(ach / FP32_VEC_TFLOPS, 4), traffic=None)
     elif dom in hbm_bytes:
@@ -221,19 +254,19 @@ def main():
     roof["avg_launch_ms"] = round(avg_ms, 4)
     roof["launches_per_step"] = dom_launches / args.steps
 
-    kern_table = {name: dict(launches=l, total_ms=round(t, 3), avg_ms=round(t / l, 4))
-                  for t, name, l in kernels}
-    for name, wb in hbm_bytes.items():
-        if name in kern_table:
-            kern_table[name]["GB/s"] = round(wb / (kern_table[name]["avg_ms"] * 1e-3) / 1e9, 1)
-    for name, wf in ls_work.items():
-        if name in kern_table and wf > 0:
-            kern_table[name]["TFLOP/s"] = round(wf / (kern_table[name]["avg_ms"] * 1e-3) / 1e12, 2)
+    kern_table = {nm: dict(launches=l, total_ms=round(t, 3), avg_ms=round(t / l, 4))
+                  for t, nm, l in kernels}
+    for nm, wb in hbm_bytes.items():
+        if nm in kern_table:
+            kern_table[nm]["GB/s"] = round(wb / (kern_table[nm]["avg_ms"] * 1e-3) / 1e9, 1)
+    for nm, wf in ls_work.items():
+        if nm in kern_table and wf > 0:
+            kern_table[nm]["TFLOP/s"] = round(wf / (kern_table[nm]["avg_ms"] * 1e-3) / 1e12, 2)
 
     cpu = None
     if not args.no_cpu:
         log("bench: CPU oracle baseline (bounded sample)")
-        cpu = cpu_baseline(w, per_iter, nnz_m, args.cpu_seconds)
+        cpu = cpu_baseline(w, bkw, int(st_m["iters_max"]), nnz_m, args.cpu_seconds)
 
     value = n / (ms_mixed * 1e-3)
     out = {
@@ -249,18 +282,21 @@ def main():
         "vs_baseline": None,
         "dtype": "f32 M build + f64 Krylov/SMW/check",
         "data": "synthetic",
-        "config": {"workload": "3d7pt_100^3_s10_dense5pct_psai_A2_drop1e-3", "n": n, "s": s,
-                   "nnz_A": int(w.A.nnz), "rhs": k, "solver": "bicgstab", "eps": 1e-8,
-                   "parallelism": "single GPU"},
-        "time_to_1e-8_ms": {"mixed": round(ms_mixed, 3), "plain_fp64": round(ms_plain, 3)},
+        "config": {"workload": name, "n": n, "s": s, "nnz_A": int(w.A.nnz), "rhs": k,
+                   "solver": "gmres30" if skw["method"] == P.GMRES else "bicgstab", "eps": skw["eps"],
+                   "adjoint_in_step": adjoint, "parallelism": "single GPU"},
+        "time_to_1e-8_ms": {"mixed": round(ms_mixed, 3),
+                            "plain_fp64": round(plain["ms"], 3) if plain else None},
         "build_ms": {"mixed": round(float(np.mean(builds_m)), 3),
-                     "plain_fp64": round(float(np.mean(builds_p)), 3)},
+                     "plain_fp64": round(plain["build"], 3) if plain else None},
         "build_columns_per_s": {"mixed": round(n / (np.mean(builds_m) * 1e-3), 1),
-                                "plain_fp64": round(n / (np.mean(builds_p) * 1e-3), 1)},
+                                "plain_fp64": round(n / (plain["build"] * 1e-3), 1) if plain else None},
+        "solve_ms": round(float(np.mean(solves_m)), 3),
+        "adjoint_ms": round(float(np.mean(backs_m)), 3) if backs_m else None,
         "solve": {"mixed": {"iters": st_m["iters"], "rr": st_m["rr"], "rr_host": rr_host,
-                            "t_solve_ms": round(st_m["t_solve_ms"], 3)},
-                  "plain_fp64": {"iters": st_p["iters"], "rr": st_p["rr"], "rr_host": rr_host_p,
-                                 "t_solve_ms": round(st_p["t_solve_ms"], 3)}},
+                            "c": st_m["c"]},
+                  "plain_fp64": ({"iters": plain["st"]["iters"], "rr": plain["st"]["rr"],
+                                  "rr_host": plain["rr_host"]} if plain else None)},
         "M": {"nnz": int(nnz_m), "spar": round(pc_m.stats.spar, 4), "max_I": pc_m.stats.max_i,
               "max_J": pc_m.stats.max_j, "n_c": pc_m.stats.n_c},
         "roofline": roof,
