@@ -248,6 +248,10 @@ int sai_solve(const sai_split_t* sp, const sai_precond_t* pc, const double* b, d
  * A~^T [eta, Z] = [grad_x, V] with M^T as right preconditioner under the
  * same stopping rules (column 0: (eps/2)||grad_x||; columns e_{j_d}:
  * eps ||grad_x|| / (2 sqrt(s))), then lambda = eta - Z (I + U^T Z)^{-1} U^T eta.
+ * With SAI_C_ONE_THEN_REFINE, if c' = ||(I + U^T Z)^{-1} U^T eta|| > 1 the s
+ * auxiliary solves are continued to eps ||grad_x|| / (2 sqrt(s) c') (the unit
+ * right-hand sides e_{j_d} are not scaled like grad_x, so c = 1 can leave the
+ * adjoint residual well above eps) and lambda is formed again; stats->c = c'.
  * Writes grad_b = lambda (device, n) and grad_a_val[e] = -lambda_i x_j for the
  * e-th stored entry (i, j) of the A given to sai_split (device, nnz(A), A's
  * CSR order).  Either output may be NULL. */

@@ -328,8 +328,13 @@ def solve(split: Split, pc: Precond, b, raise_on_error=True, **kw):
 
 def backward(split: Split, pc: Precond, x, grad_x, want_b=True, want_a=True, raise_on_error=True,
              **kw):
-    """Gradients (dL/db, dL/dA values in A's CSR order) for dL/dx = grad_x."""
+    """Gradients (dL/db, dL/dA values in A's CSR order) for dL/dx = grad_x.
+
+    The adjoint's auxiliary solves are refined to the theorem's threshold with the
+    computed c' unless c_mode is given (see sai_backward in include/sai.h).
+    """
     torch = _torch()
+    kw.setdefault("c_mode", C_ONE_THEN_REFINE)
     gb = torch.empty(split.n, dtype=torch.float64, device="cuda") if want_b else None
     ga = torch.empty(split.nnz, dtype=torch.float64, device="cuda") if want_a else None
     iters = (C.c_int32 * (split.s + 1))()

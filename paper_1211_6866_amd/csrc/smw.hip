@@ -119,6 +119,25 @@ __global__ void k_aux_residual(int64_t n, int s, const int32_t* __restrict__ rp,
     for (int32_t e = urp[i]; e < urp[i + 1]; ++e) R[i * s + ucol[e]] += uval[e];
   }
 }
+// adjoint correction solves: R = V - A~^T Z for the auxiliary columns, with A~^T
+// given as the CSC of A~ and V = (e_{j_1} .. e_{j_s})
+__global__ void k_aux_residual_t(int64_t n, int s, const int32_t* __restrict__ cp,
+                                 const int32_t* __restrict__ ri, const double* __restrict__ cv,
+                                 const double* __restrict__ Y, double* __restrict__ R) {
+  const int kk = s + 1;
+  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
+    for (int d = 0; d < s; ++d) {
+      double y = 0.0;
+      for (int32_t e = cp[i]; e < cp[i + 1]; ++e) y += cv[e] * Y[(int64_t)ri[e] * kk + 1 + d];
+      R[i * s + d] = -y;
+    }
+  }
+}
+__global__ void k_add_units(int s, const int32_t* D, double* R) {
+  const int d = blockIdx.x * NT + threadIdx.x;
+  if (d < s) R[(int64_t)D[d] * s + d] += 1.0;
+}
+
 __global__ void k_aux_add(int64_t n, int s, const double* __restrict__ dW, double* __restrict__ Y) {
   const int kk = s + 1;
   for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT)
@@ -320,10 +339,17 @@ void backward_impl(const sai_split_s* sp, const sai_precond_s* pc, const double*
   std::vector<double> thr = thresholds(gnorm, s, o.eps, 1.0);
   std::vector<int32_t> its(kk, 0), sts(kk, 0);
   t_solve.start(st);
-  const int code = krylov_impl(sp, pc, 1, kk, R.p, Y.p, thr.data(), o, st, its.data(), sts.data());
+  int code = krylov_impl(sp, pc, 1, kk, R.p, Y.p, thr.data(), o, st, its.data(), sts.data());
   t_solve.stop(st);
   t_smw.start(st);
-  if (s > 0) {
+  // lambda = eta - Z (I + U^T Z)^{-1} U^T eta; returns c' = ||(I + U^T Z)^{-1} U^T eta||
+  auto recover = [&]() -> double {
+    if (s == 0) {
+      hipLaunchKernelGGL(k_smw_apply, dim3(rows_grid(n)), dim3(NT), 0, st, n, 0, 1, Y.p,
+                         (const double*)nullptr, lam.p);
+      LAUNCH_CHECK();
+      return 0.0;
+    }
     const int64_t nb = (n + UTY_ROWS - 1) / UTY_ROWS;
     DBuf<double> part(&al, (size_t)nb * s * kk), P(&al, (size_t)s * kk), K(&al, (size_t)s * s),
         w(&al, (size_t)s);
@@ -339,11 +365,33 @@ void backward_impl(const sai_split_s* sp, const sai_precond_s* pc, const double*
       SAI_THROW(SAI_ESINGULAR, "I + U^T Z is singular (zero pivot)");
     hipLaunchKernelGGL(k_smw_apply, dim3(rows_grid(n)), dim3(NT), 0, st, n, s, kk, Y.p,
                        (const double*)w.p, lam.p);
-  } else {
-    hipLaunchKernelGGL(k_smw_apply, dim3(rows_grid(n)), dim3(NT), 0, st, n, 0, 1, Y.p,
-                       (const double*)nullptr, lam.p);
+    LAUNCH_CHECK();
+    std::vector<double> hw(s);
+    HIPC(hipMemcpyAsync(hw.data(), w.p, sizeof(double) * s, hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    double a = 0.0;
+    for (double v : hw) a += v * v;
+    return std::sqrt(a);
+  };
+  double cprime = recover();
+  if (o.c_mode == SAI_C_ONE_THEN_REFINE && cprime > 1.0 && s > 0 && code == SAI_OK) {
+    // the theorem's condition with the computed c': continue the s auxiliary
+    // solves (correction solves on V - A~^T Z) to eps ||g|| / (2 sqrt(s) c')
+    std::vector<double> thr2 = thresholds(gnorm, s, o.eps, cprime);
+    DBuf<double> Raux(&al, (size_t)n * s), dZ(&al, (size_t)n * s);
+    hipLaunchKernelGGL(k_aux_residual_t, dim3(rows_grid(n)), dim3(NT), 0, st, n, s, sp->t_col_ptr.p,
+                       sp->t_row_idx.p, sp->t_cval.p, Y.p, Raux.p);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_add_units, dim3(grid_for(s, NT)), dim3(NT), 0, st, s, sp->dense_cols.p,
+                       Raux.p);
+    LAUNCH_CHECK();
+    std::vector<int32_t> its2(s, 0), sts2(s, 0);
+    code = krylov_impl(sp, pc, 1, s, Raux.p, dZ.p, thr2.data() + 1, o, st, its2.data(), sts2.data());
+    hipLaunchKernelGGL(k_aux_add, dim3(rows_grid(n)), dim3(NT), 0, st, n, s, dZ.p, Y.p);
+    LAUNCH_CHECK();
+    for (int d = 0; d < s; ++d) its[d + 1] += its2[d];
+    cprime = recover();
   }
-  LAUNCH_CHECK();
   if (gb) HIPC(hipMemcpyAsync(gb, lam.p, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
   if (ga) {
     hipLaunchKernelGGL(k_grad_a, dim3(rows_grid(n)), dim3(NT), 0, st, n, sp->a_row_ptr.p,
@@ -362,7 +410,7 @@ void backward_impl(const sai_split_s* sp, const sai_precond_s* pc, const double*
       for (int q = 0; q < kk; ++q) stats->iters[q] = its[q];
     stats->rr = 0.0;
     stats->a = 0.0;
-    stats->c = 0.0;
+    stats->c = cprime;
     stats->t_solve_ms = t_solve.ms();
     stats->t_smw_ms = t_smw.ms();
     stats->t_check_ms = 0.0f;
