@@ -263,6 +263,8 @@ int sai_backward(const sai_split_t* sp, const sai_precond_t* pc, const double* x
  * While enabled, the library records a pair of HIP events on the launch stream
  * around each of its kernel launches and accumulates, per kernel name, the
  * number of launches and their total elapsed time.  sai_profile_enable(1)
+ * records every kernel, sai_profile_enable(2) only the sparse products, column
+ * solvers, SPAI search and GMRES (less event overhead), 0 stops; enabling
  * resets the totals; sai_profile_get resolves pending events (it waits for
  * them) and returns entry i (0 <= i < sai_profile_count()).  Not thread-safe
  * with respect to concurrent launches from several host threads. */

@@ -350,9 +350,10 @@ def backward(split: Split, pc: Precond, x, grad_x, want_b=True, want_a=True, rai
     return gb, ga, _stats_dict(st, iters)
 
 
-def profile_enable(on: bool = True):
-    """Start (and reset) or stop the library's per-kernel HIP-event timing."""
-    _check(lib().sai_profile_enable(int(bool(on))), "sai_profile_enable")
+def profile_enable(mode=1):
+    """Start (and reset) the library's per-kernel HIP-event timing: 1 = every kernel,
+    2 = only the kernels that can dominate (products, column solvers), 0/False = stop."""
+    _check(lib().sai_profile_enable(int(mode)), "sai_profile_enable")
 
 
 def profile_read() -> dict:

@@ -15,6 +15,7 @@ struct Pending {
 struct Registry {
   std::mutex mu;
   bool on = false;
+  int mode = 0;
   std::vector<Pending> pending;
   std::vector<hipEvent_t> pool;
   std::map<std::string, std::pair<int64_t, double>> totals;
@@ -51,10 +52,20 @@ Registry& reg() {
 
 }  // namespace
 
+// Mode 2 records only the kernels that can dominate a step (the sparse products,
+// the column solvers, the SPAI search and GMRES), to keep the event overhead low.
+static bool hot_name(const char* n) {
+  static const char* pre[] = {"bicg_spmm", "ls_qr", "spai", "gmres"};
+  for (const char* p : pre)
+    if (strncmp(n, p, strlen(p)) == 0) return true;
+  return false;
+}
+
 ProfScope::ProfScope(const char* name, hipStream_t s) : st(s) {
   Registry& r = reg();
   std::lock_guard<std::mutex> g(r.mu);
   if (!r.on) return;
+  if (r.mode == 2 && !hot_name(name)) return;
   Pending p{name, r.get_event(), r.get_event()};
   HIPC(hipEventRecord(p.a, s));
   r.pending.push_back(p);
@@ -82,6 +93,7 @@ int sai_profile_enable(int32_t on) {
   }
   r.totals.clear();
   r.on = on != 0;
+  r.mode = on;
   return SAI_OK;
 }
 
