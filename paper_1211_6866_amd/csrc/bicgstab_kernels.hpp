@@ -166,9 +166,11 @@ __device__ __forceinline__ bool stage_tile(const Csr<TV>& A, int64_t t0, int row
   const int cnt = s_rp[rows] - e0;
   const bool fit = cnt <= CAP;
   if (fit) {
+    // the matrix is streamed once per product: non-temporal loads keep it from
+    // displacing the gathered rows of X in L2
     for (int q = threadIdx.x; q < cnt; q += NT) {
-      s_ci[q] = A.ci[e0 + q];
-      s_v[q] = A.v[e0 + q];
+      s_ci[q] = __builtin_nontemporal_load(&A.ci[e0 + q]);
+      s_v[q] = __builtin_nontemporal_load(&A.v[e0 + q]);
     }
   }
   __syncthreads();
@@ -258,7 +260,7 @@ __global__ void __launch_bounds__(NT) k_spmm(int64_t n, int k, Csr<TV> A, const 
   TILE_LOOP {
     const int rows = (int)min<int64_t>(TR, n - t0);
     const bool fit = stage_tile<TV, CAP_M>(A, t0, rows, s_rp, s_ci, s_v);
-    if (on) { TILE_ROWS_PROD(TV, CH, SI, A, X, Y[qq] = y;) }
+    if (on) { TILE_ROWS_PROD(TV, CH, SI, A, X, __builtin_nontemporal_store(y, &Y[qq]);) }
     __syncthreads();
   }
 }
@@ -273,7 +275,10 @@ __global__ void __launch_bounds__(NT) k_av(int64_t n, int k, Csr<double> A, Vec 
   TILE_LOOP {
     const int rows = (int)min<int64_t>(TR, n - t0);
     const bool fit = stage_tile<double, CAP_A>(A, t0, rows, s_rp, s_ci, s_v);
-    if (on) { TILE_ROWS_PROD(double, 8, SUB, A, V.ph, V.v[qq] = y; acc[0] += V.rh[qq] * y;) }
+    if (on) {
+      TILE_ROWS_PROD(double, 8, SUB, A, V.ph, __builtin_nontemporal_store(y, &V.v[qq]);
+                     acc[0] += __builtin_nontemporal_load(&V.rh[qq]) * y;)
+    }
     __syncthreads();
   }
   block_partials<GK, 1>(acc, S);
@@ -342,7 +347,8 @@ __global__ void __launch_bounds__(NT) k_at(int64_t n, int k, Csr<double> A, Vec 
     const int rows = (int)min<int64_t>(TR, n - t0);
     const bool fit = stage_tile<double, CAP_A>(A, t0, rows, s_rp, s_ci, s_v);
     if (on) {
-      TILE_ROWS_PROD(double, 8, SUB, A, V.sh, V.t[qq] = y; acc[0] += y * V.s[qq]; acc[1] += y * y;)
+      TILE_ROWS_PROD(double, 8, SUB, A, V.sh, __builtin_nontemporal_store(y, &V.t[qq]);
+                     acc[0] += y * __builtin_nontemporal_load(&V.s[qq]); acc[1] += y * y;)
     }
     __syncthreads();
   }

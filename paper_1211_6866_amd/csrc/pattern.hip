@@ -99,6 +99,60 @@ __device__ int sort_unique(int32_t* cand, int m, int cap) {
   return out;
 }
 
+// Fast path of sort_unique for small unions (the common case for regular sparse
+// A~): de-duplicate through an LDS hash table (linear probing, atomicCAS), then
+// sort the <= 64 distinct values by rank (one value per lane, ranks from a
+// 64-step broadcast loop) and write them in order.  Falls back to the bitonic
+// sort when there are more than 64 distinct values or more than 512 candidates.
+constexpr int HT = 256;
+constexpr int32_t HT_EMPTY = 0x7fffffff;
+
+__device__ int sort_unique_fast(int32_t* cand, int m, int cap, int32_t* ht) {
+  const int l = lane_id();
+  if (m == 0) return 0;
+  if (m > 512) return sort_unique(cand, m, cap);
+  for (int i = l; i < HT; i += WAVE) ht[i] = HT_EMPTY;
+  __syncthreads();
+  int fresh = 0;
+  for (int i = l; i < m; i += WAVE) {
+    const int32_t v = cand[i];
+    unsigned h = ((unsigned)v * 2654435761u) >> 24;
+    bool placed = false;
+    for (int probe = 0; probe < HT; ++probe) {  // a full table ends the probing
+      const int32_t old = atomicCAS(&ht[h], HT_EMPTY, v);
+      if (old == HT_EMPTY) { ++fresh; placed = true; break; }
+      if (old == v) { placed = true; break; }
+      h = (h + 1) & (HT - 1);
+    }
+    if (!placed) fresh += HT;  // forces the fallback below
+  }
+  const int nu = wave_sum(fresh);
+  __syncthreads();
+  if (nu > WAVE) return sort_unique(cand, m, cap);
+  // compact the occupied slots into cand[0..nu) (the candidates are no longer
+  // needed), one value per lane
+  int base = 0;
+  for (int s0 = 0; s0 < HT; s0 += WAVE) {
+    const int32_t hv = ht[s0 + l];
+    const bool occ = hv != HT_EMPTY;
+    const unsigned long long bal = __ballot(occ);
+    if (occ) cand[base + __popcll(bal & ((l == 0) ? 0ull : (~0ull >> (64 - l))))] = hv;
+    base += __popcll(bal);
+  }
+  __syncthreads();
+  const int32_t u = l < nu ? cand[l] : HT_EMPTY;
+  // rank of u among the nu values (distinct), then ordered write
+  int rank = 0;
+  for (int t = 0; t < nu; ++t) {
+    const int32_t o = __shfl(u, t, WAVE);
+    rank += (o < u) ? 1 : 0;
+  }
+  __syncthreads();
+  if (l < nu) cand[rank] = u;
+  __syncthreads();
+  return nu;
+}
+
 template <int CAP>
 __global__ void __launch_bounds__(64) k_pattern(int32_t n, int kind, const int32_t* __restrict__ cp,
                                                 const int32_t* __restrict__ ri, int mode,
@@ -111,6 +165,7 @@ __global__ void __launch_bounds__(64) k_pattern(int32_t n, int kind, const int32
                                                 int32_t* __restrict__ iout, int* __restrict__ nover) {
   constexpr int CAPJ = 256;
   __shared__ int32_t cand[CAP];
+  __shared__ int32_t ht[HT];
   __shared__ int32_t sJ[CAPJ];
   __shared__ int32_t s_start[CAPJ];
   __shared__ int32_t s_off[CAPJ + 1];
@@ -127,7 +182,7 @@ __global__ void __launch_bounds__(64) k_pattern(int32_t n, int kind, const int32
       __syncthreads();
       int m = gather_cols(cp, ri, sJ, c0, cand, CAP, s_start, s_off);
       if (m < 0) { if (l == 0 && mode == 0) { cntJ[k] = -1; atomicAdd(nover, 1); } __syncthreads(); continue; }
-      nJ = sort_unique(cand, m, CAP);
+      nJ = sort_unique_fast(cand, m, CAP, ht);
       if (nJ > CAPJ) { if (l == 0 && mode == 0) { cntJ[k] = -1; atomicAdd(nover, 1); } __syncthreads(); continue; }
       for (int t = l; t < nJ; t += WAVE) sJ[t] = cand[t];
       __syncthreads();
@@ -140,7 +195,7 @@ __global__ void __launch_bounds__(64) k_pattern(int32_t n, int kind, const int32
     // ---- I_k
     int m = gather_cols(cp, ri, sJ, nJ, cand, CAP, s_start, s_off);
     if (m < 0) { if (l == 0 && mode == 0) { cntJ[k] = -1; atomicAdd(nover, 1); } __syncthreads(); continue; }
-    const int nI = sort_unique(cand, m, CAP);
+    const int nI = sort_unique_fast(cand, m, CAP, ht);
     if (mode == 0) {
       if (l == 0) { cntJ[k] = nJ; cntI[k] = nI; }
     } else {
@@ -163,6 +218,7 @@ __global__ void __launch_bounds__(64) k_rows_of(int32_t n, const int32_t* __rest
                                                 int32_t* __restrict__ iout, int* __restrict__ nover) {
   constexpr int CAPJ = 256;
   __shared__ int32_t cand[CAP];
+  __shared__ int32_t ht[HT];
   __shared__ int32_t sJ[CAPJ];
   __shared__ int32_t s_start[CAPJ];
   __shared__ int32_t s_off[CAPJ + 1];
@@ -175,7 +231,7 @@ __global__ void __launch_bounds__(64) k_rows_of(int32_t n, const int32_t* __rest
     __syncthreads();
     const int m = gather_cols(cp, ri, sJ, nJ, cand, CAP, s_start, s_off);
     if (m < 0) { if (l == 0) atomicAdd(nover, 1); __syncthreads(); continue; }
-    const int nI = sort_unique(cand, m, CAP);
+    const int nI = sort_unique_fast(cand, m, CAP, ht);
     if (mode == 0) {
       if (l == 0) cntI[k] = nI;
     } else {

@@ -79,6 +79,43 @@ __global__ void k_dense_gather(int32_t n, const int32_t* __restrict__ row_ptr,
   }
 }
 
+// Contention-free variant of the gather for s <= GATHER_SMAX: each block counts
+// the irregular-column entries of its rows in LDS (pass 0), a prefix sum over the
+// (column, block) counts in column-major order gives every block its slice of
+// every column's list, and pass 1 scatters into those slices.
+constexpr int GATHER_ROWS = 4096;
+constexpr int GATHER_SMAX = 1024;
+
+__global__ void __launch_bounds__(NT) k_dense_gather_blk(int32_t n, int s, const int32_t* __restrict__ row_ptr,
+                                                         const int32_t* __restrict__ col,
+                                                         const int32_t* __restrict__ colmap, int pass,
+                                                         int32_t* __restrict__ bcnt,
+                                                         const int64_t* __restrict__ boff,
+                                                         int32_t* __restrict__ lrow,
+                                                         int32_t* __restrict__ lpos) {
+  __shared__ int32_t cnt[GATHER_SMAX];
+  const int nb = gridDim.x;
+  for (int d = threadIdx.x; d < s; d += NT) cnt[d] = 0;
+  __syncthreads();
+  const int64_t r0 = (int64_t)blockIdx.x * GATHER_ROWS;
+  const int64_t r1 = min<int64_t>(n, r0 + GATHER_ROWS);
+  for (int64_t i = r0 + threadIdx.x; i < r1; i += NT) {
+    for (int32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+      const int32_t d = colmap[col[e]];
+      if (d < 0) continue;
+      const int32_t slot = atomicAdd(&cnt[d], 1);
+      if (pass == 1) {
+        const int64_t o = boff[(int64_t)d * nb + blockIdx.x] + slot;
+        lrow[o] = (int32_t)i;
+        lpos[o] = e;
+      }
+    }
+  }
+  __syncthreads();
+  if (pass == 0)
+    for (int d = threadIdx.x; d < s; d += NT) bcnt[(int64_t)d * nb + blockIdx.x] = cnt[d];
+}
+
 struct Key {
   double a;
   int32_t i;
@@ -356,10 +393,23 @@ void split_impl(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* c
     DBuf<int64_t> doff(&al, (size_t)s + 1);
     DBuf<int32_t> dcur(&al, (size_t)s + 1), lrow(&al, (size_t)hoff[s] + 1), lpos(&al, (size_t)hoff[s] + 1);
     HIPC(hipMemcpyAsync(doff.p, hoff.data(), sizeof(int64_t) * (s + 1), hipMemcpyHostToDevice, st));
-    HIPC(hipMemsetAsync(dcur.p, 0, sizeof(int32_t) * (s + 1), st));
-    hipLaunchKernelGGL(k_dense_gather, dim3(grid_for(n, NT)), dim3(NT), 0, st, n, row_ptr, col_idx,
-                       colmap.p, doff.p, dcur.p, lrow.p, lpos.p);
-    LAUNCH_CHECK();
+    if (s <= GATHER_SMAX) {
+      const int nbk = (int)((n + GATHER_ROWS - 1) / GATHER_ROWS);
+      DBuf<int32_t> bcnt(&al, (size_t)s * nbk + 1);
+      DBuf<int64_t> boff(&al, (size_t)s * nbk + 1);
+      hipLaunchKernelGGL(k_dense_gather_blk, dim3(nbk), dim3(NT), 0, st, n, s, row_ptr, col_idx,
+                         colmap.p, 0, bcnt.p, (const int64_t*)nullptr, lrow.p, lpos.p);
+      LAUNCH_CHECK();
+      exclusive_scan_i32_to_i64(bcnt.p, boff.p, (int64_t)s * nbk, al, st);
+      hipLaunchKernelGGL(k_dense_gather_blk, dim3(nbk), dim3(NT), 0, st, n, s, row_ptr, col_idx,
+                         colmap.p, 1, bcnt.p, (const int64_t*)boff.p, lrow.p, lpos.p);
+      LAUNCH_CHECK();
+    } else {
+      HIPC(hipMemsetAsync(dcur.p, 0, sizeof(int32_t) * (s + 1), st));
+      hipLaunchKernelGGL(k_dense_gather, dim3(grid_for(n, NT)), dim3(NT), 0, st, n, row_ptr, col_idx,
+                         colmap.p, doff.p, dcur.p, lrow.p, lpos.p);
+      LAUNCH_CHECK();
+    }
     hipLaunchKernelGGL(k_dense_select, dim3(s), dim3(NT), 0, st, h->dense_cols.p, doff.p, dcount.p,
                        lrow.p, lpos.p, val, keep, o.rule, drop.p, err.p);
     LAUNCH_CHECK();
