@@ -40,59 +40,72 @@ struct State {
 struct Vec {
   const double* rhs;
   double *x, *r, *rh, *p, *v, *s, *ph, *sh, *t;
+  // FP32 copies of p and s written beside them (null: not kept); the FP32
+  // preconditioner is applied to these copies
+  float *pf, *sf;
 };
 
 __device__ __forceinline__ bool col_on(const State& S, int c, int k) {
   return c < k && S.status[c] == ST_ACTIVE && S.skip[c] == 0;
 }
 
-// sum_e A_ie X[j_e, c] over entries eb..ee of (sci, sv)
-template <class TV>
+// sum_e A_ie X[j_e, c] over entries eb..ee of (sci, sv), accumulated in FP64
+// (a product of two FP32 numbers is exact in FP64)
+template <class TV, class XT>
 __device__ __forceinline__ double row_prod_lds(const int32_t* __restrict__ sci,
                                                const TV* __restrict__ sv, int eb, int ee,
-                                               const double* __restrict__ X, int k, int c) {
+                                               const XT* __restrict__ X, int k, int c) {
   double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   int e = eb;
   for (; e + 7 < ee; e += 8) {
-    double x[8];
+    XT x[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) x[u] = X[(int64_t)sci[e + u] * k + c];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) a[u] += (double)sv[e + u] * x[u];
+    for (int u = 0; u < 8; ++u) a[u] += (double)sv[e + u] * (double)x[u];
   }
   if (e + 3 < ee) {
-    double x[4];
+    XT x[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) x[u] = X[(int64_t)sci[e + u] * k + c];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) a[u] += (double)sv[e + u] * x[u];
+    for (int u = 0; u < 4; ++u) a[u] += (double)sv[e + u] * (double)x[u];
     e += 4;
   }
-  for (; e < ee; ++e) a[4] += (double)sv[e] * X[(int64_t)sci[e] * k + c];
+  for (; e < ee; ++e) a[4] += (double)sv[e] * (double)X[(int64_t)sci[e] * k + c];
   return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
 }
 
-template <class TV>
-__device__ __forceinline__ double row_prod(const Csr<TV>& A, int64_t i, const double* __restrict__ X,
+template <class TV, class XT>
+__device__ __forceinline__ double row_prod(const Csr<TV>& A, int64_t i, const XT* __restrict__ X,
                                            int k, int c) {
-  return row_prod_lds<TV>(A.ci, A.v, A.rp[i], A.rp[i + 1], X, k, c);
+  return row_prod_lds<TV, XT>(A.ci, A.v, A.rp[i], A.rp[i + 1], X, k, c);
 }
 
 // SI rows at once, entries eb[q]..ee[q] in LDS: the gathers of the first CH
 // entries of every row are all issued before any is consumed (SI*CH loads in
-// flight per lane); entries past CH follow in a plain loop.
-template <class TV, int CH, int SI>
+// flight per lane); entries past CH follow in a plain loop.  BF (branch-free):
+// a slot past the row's end loads row 0 of X (a valid address) and is
+// multiplied by zero, so that the compiler issues every load before the first
+// wait; otherwise each slot is guarded, which suits short rows (A~).
+template <class TV, int CH, int SI, bool BF, class XT>
 __device__ __forceinline__ void rows_prod_batch(const int32_t* __restrict__ sci,
                                                 const TV* __restrict__ sv, const int (&eb)[SI],
-                                                const int (&ee)[SI], const double* __restrict__ X,
+                                                const int (&ee)[SI], const XT* __restrict__ X,
                                                 int k, int c, double (&out)[SI]) {
-  double xv[SI][CH];
+  XT xv[SI][CH];
 #pragma unroll
   for (int q = 0; q < SI; ++q) {
 #pragma unroll
     for (int u = 0; u < CH; ++u) {
       const int e = eb[q] + u;
-      xv[q][u] = (e < ee[q]) ? X[(int64_t)sci[e] * k + c] : 0.0;
+      const bool ok = e < ee[q];
+      if constexpr (BF) {
+        const int j = sci[ok ? e : 0];
+        xv[q][u] = X[(int64_t)(ok ? j : 0) * k + c];
+      } else {
+        xv[q][u] = ok ? X[(int64_t)sci[e] * k + c] : XT(0);
+      }
     }
   }
 #pragma unroll
@@ -101,9 +114,15 @@ __device__ __forceinline__ void rows_prod_batch(const int32_t* __restrict__ sci,
 #pragma unroll
     for (int u = 0; u < CH; ++u) {
       const int e = eb[q] + u;
-      if (e < ee[q]) a += (double)sv[e] * xv[q][u];
+      const bool ok = e < ee[q];
+      if constexpr (BF) {
+        const TV w = sv[ok ? e : 0];
+        a += (double)(ok ? w : TV(0)) * (double)xv[q][u];
+      } else {
+        if (ok) a += (double)sv[e] * (double)xv[q][u];
+      }
     }
-    if (ee[q] > eb[q] + CH) a += row_prod_lds<TV>(sci, sv, eb[q] + CH, ee[q], X, k, c);
+    if (ee[q] > eb[q] + CH) a += row_prod_lds<TV, XT>(sci, sv, eb[q] + CH, ee[q], X, k, c);
     out[q] = a;
   }
 }
@@ -205,22 +224,24 @@ __global__ void __launch_bounds__(NT) k_init(int64_t n, int k, Vec V, State S) {
   block_partials<GK, 1>(acc, S);
 }
 
-// ---- p = r + beta (p - omega v) -------------------------------------------------
-template <int GK>
+// ---- p = r + beta (p - omega v) (and its FP32 copy) ------------------------------
+template <int GK, bool F32>
 __global__ void __launch_bounds__(NT) k_pupdate(int64_t n, int k, Vec V, State S) {
   const int cc = threadIdx.x % GK;
   if (!col_on(S, cc, k)) return;
   const double beta = S.beta[cc], omega = S.omega[cc];
   ROW_LOOP {
     const int64_t q = i * k + c;
-    V.p[q] = V.r[q] + beta * (V.p[q] - omega * V.v[q]);
+    const double pv = V.r[q] + beta * (V.p[q] - omega * V.v[q]);
+    V.p[q] = pv;
+    if constexpr (F32) V.pf[q] = (float)pv;
   }
 }
 
 // ---- Y = Op X (plain product for the active columns) -------------------------------
 // The lane's SUB rows of the tile are r = sb*RPB + rib; they are handled SI at a
 // time with rows_prod_batch (tile staged) or one by one from global memory.
-#define TILE_ROWS_PROD(TV, CH, SI, A, X, BODY)                                        \
+#define TILE_ROWS_PROD(TV, CH, SI, BF, A, X, BODY)                                      \
   if (fit) {                                                                          \
     _Pragma("unroll") for (int b0 = 0; b0 < SUB; b0 += (SI)) {                        \
       int eb[SI], ee[SI];                                                             \
@@ -230,7 +251,7 @@ __global__ void __launch_bounds__(NT) k_pupdate(int64_t n, int k, Vec V, State S
         eb[q] = r < rows ? s_rp[r] - s_rp[0] : 0;                                     \
         ee[q] = r < rows ? s_rp[r + 1] - s_rp[0] : 0;                                 \
       }                                                                               \
-      rows_prod_batch<TV, CH, SI>(s_ci, s_v, eb, ee, (X), k, c, out);                 \
+      rows_prod_batch<TV, CH, SI, BF>(s_ci, s_v, eb, ee, (X), k, c, out);              \
       _Pragma("unroll") for (int q = 0; q < (SI); ++q) {                              \
         const int r = (b0 + q) * RPB + rib;                                           \
         if (r < rows) {                                                               \
@@ -251,8 +272,8 @@ __global__ void __launch_bounds__(NT) k_pupdate(int64_t n, int k, Vec V, State S
     }                                                                                 \
   }
 
-template <int GK, class TV, int CH, int SI, int SUBT>
-__global__ void __launch_bounds__(NT) k_spmm(int64_t n, int k, Csr<TV> A, const double* __restrict__ X,
+template <int GK, class TV, int CH, int SI, int SUBT, class XT>
+__global__ void __launch_bounds__(NT) k_spmm(int64_t n, int k, Csr<TV> A, const XT* __restrict__ X,
                                              double* __restrict__ Y, State S, int xmap) {
   constexpr int SUB = SUBT;
   STAGE_DECL(TV, CAP_M)
@@ -260,7 +281,7 @@ __global__ void __launch_bounds__(NT) k_spmm(int64_t n, int k, Csr<TV> A, const 
   TILE_LOOP {
     const int rows = (int)min<int64_t>(TR, n - t0);
     const bool fit = stage_tile<TV, CAP_M>(A, t0, rows, s_rp, s_ci, s_v);
-    if (on) { TILE_ROWS_PROD(TV, CH, SI, A, X, __builtin_nontemporal_store(y, &Y[qq]);) }
+    if (on) { TILE_ROWS_PROD(TV, CH, SI, true, A, X, __builtin_nontemporal_store(y, &Y[qq]);) }
     __syncthreads();
   }
 }
@@ -276,7 +297,7 @@ __global__ void __launch_bounds__(NT) k_av(int64_t n, int k, Csr<double> A, Vec 
     const int rows = (int)min<int64_t>(TR, n - t0);
     const bool fit = stage_tile<double, CAP_A>(A, t0, rows, s_rp, s_ci, s_v);
     if (on) {
-      TILE_ROWS_PROD(double, 8, SUB, A, V.ph, __builtin_nontemporal_store(y, &V.v[qq]);
+      TILE_ROWS_PROD(double, 8, SUB, false, A, V.ph, __builtin_nontemporal_store(y, &V.v[qq]);
                      acc[0] += __builtin_nontemporal_load(&V.rh[qq]) * y;)
     }
     __syncthreads();
@@ -284,8 +305,8 @@ __global__ void __launch_bounds__(NT) k_av(int64_t n, int k, Csr<double> A, Vec 
   block_partials<GK, 1>(acc, S);
 }
 
-// ---- s = r - alpha v; partial ||s||^2 -----------------------------------------
-template <int GK>
+// ---- s = r - alpha v (and its FP32 copy); partial ||s||^2 -------------------------
+template <int GK, bool F32>
 __global__ void __launch_bounds__(NT) k_s(int64_t n, int k, Vec V, State S) {
   double acc[1] = {0.0};
   const int cc = threadIdx.x % GK;
@@ -296,6 +317,7 @@ __global__ void __launch_bounds__(NT) k_s(int64_t n, int k, Vec V, State S) {
     const int64_t q = i * k + c;
     const double sv = V.r[q] - alpha * V.v[q];
     V.s[q] = sv;
+    if constexpr (F32) V.sf[q] = (float)sv;
     acc[0] += sv * sv;
   }
   block_partials<GK, 1>(acc, S);
@@ -347,7 +369,7 @@ __global__ void __launch_bounds__(NT) k_at(int64_t n, int k, Csr<double> A, Vec 
     const int rows = (int)min<int64_t>(TR, n - t0);
     const bool fit = stage_tile<double, CAP_A>(A, t0, rows, s_rp, s_ci, s_v);
     if (on) {
-      TILE_ROWS_PROD(double, 8, SUB, A, V.sh, __builtin_nontemporal_store(y, &V.t[qq]);
+      TILE_ROWS_PROD(double, 8, SUB, false, A, V.sh, __builtin_nontemporal_store(y, &V.t[qq]);
                      acc[0] += y * __builtin_nontemporal_load(&V.s[qq]); acc[1] += y * y;)
     }
     __syncthreads();

@@ -20,6 +20,8 @@
 // GMRES(m) (used for the smallest workload) runs one workgroup per column for
 // the whole solve: modified Gram-Schmidt Arnoldi, Givens rotations, solution
 // update at the end of each cycle, convergence on the true residual.
+#include <type_traits>
+
 #include "sai_internal.hpp"
 
 #include "bicgstab_kernels.hpp"
@@ -29,11 +31,16 @@ namespace {
 
 template <int GK, class TM>
 int bicgstab_gk(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, const double* R,
-                double* X, const double* thr, int maxit, const Allocator& al, hipStream_t st,
+                double* X, const double* thr, int maxit, int pin, const Allocator& al, hipStream_t st,
                 int* iters, int* status) {
   const size_t nk = (size_t)n * k;
   DBuf<double> r(&al, nk), rh(&al, nk), p(&al, nk), v(&al, nk), s(&al, nk), ph(&al, nk),
       sh(&al, nk), t(&al, nk);
+  // The FP32 preconditioner is applied to FP32 copies of p and s (products
+  // accumulate in FP64): halves the gathered bytes of its sparse product.
+  constexpr bool MF = sizeof(TM) == 4;
+  const bool f32in = MF && pin == SAI_PIN_MATCH;
+  DBuf<float> pf(&al, f32in ? nk : 0), sf(&al, f32in ? nk : 0);
   DBuf<double> sc(&al, 6 * 64);
   DBuf<int> si(&al, 9 * 64 + 8);
   DBuf<double> part(&al, (size_t)2 * NBMAX * GK);
@@ -57,7 +64,7 @@ int bicgstab_gk(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, const 
   S.wasact = si.p + 512;
   S.any = si.p + 576;
   S.part = part.p;
-  Vec V{R, X, r.p, rh.p, p.p, v.p, s.p, ph.p, sh.p, t.p};
+  Vec V{R, X, r.p, rh.p, p.p, v.p, s.p, ph.p, sh.p, t.p, pf.p, sf.p};
   constexpr int RPB = NT / GK;
   // streaming kernels: one row per lane group; sparse products: tiles of SUB*RPB rows
   const int grid = (int)std::min<int64_t>(NBMAX, (n + RPB - 1) / RPB);
@@ -72,15 +79,20 @@ int bicgstab_gk(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, const 
   const int mvar = tune_get("SPMM_M", 3);
   const int msub = (mvar == 1 || mvar == 2) ? 4 : (mvar == 3 ? 2 : 1);
   const int mgrid = tiles_grid(msub);
-  auto spmm_m = [&](const double* X, double* Y) {
+  auto spmm_m_t = [&](auto X, double* Y) {
+    using XT = std::remove_const_t<std::remove_pointer_t<decltype(X)>>;
     switch (mvar) {
-      case 1: hipLaunchKernelGGL((k_spmm<GK, TM, 8, 4, 4>), dim3(mgrid), dim3(NT), 0, st, n, k, M, X, Y, S, xmap); break;
-      case 2: hipLaunchKernelGGL((k_spmm<GK, TM, 32, 2, 4>), dim3(mgrid), dim3(NT), 0, st, n, k, M, X, Y, S, xmap); break;
-      case 3: hipLaunchKernelGGL((k_spmm<GK, TM, 16, 2, 2>), dim3(mgrid), dim3(NT), 0, st, n, k, M, X, Y, S, xmap); break;
-      case 4: hipLaunchKernelGGL((k_spmm<GK, TM, 16, 1, 1>), dim3(mgrid), dim3(NT), 0, st, n, k, M, X, Y, S, xmap); break;
-      case 5: hipLaunchKernelGGL((k_spmm<GK, TM, 32, 1, 1>), dim3(mgrid), dim3(NT), 0, st, n, k, M, X, Y, S, xmap); break;
-      default: hipLaunchKernelGGL((k_spmm<GK, TM, 8, 1, 1>), dim3(mgrid), dim3(NT), 0, st, n, k, M, X, Y, S, xmap); break;
+      case 1: hipLaunchKernelGGL((k_spmm<GK, TM, 8, 4, 4, XT>), dim3(mgrid), dim3(NT), 0, st, n, k, M, X, Y, S, xmap); break;
+      case 2: hipLaunchKernelGGL((k_spmm<GK, TM, 32, 2, 4, XT>), dim3(mgrid), dim3(NT), 0, st, n, k, M, X, Y, S, xmap); break;
+      case 3: hipLaunchKernelGGL((k_spmm<GK, TM, 16, 2, 2, XT>), dim3(mgrid), dim3(NT), 0, st, n, k, M, X, Y, S, xmap); break;
+      case 4: hipLaunchKernelGGL((k_spmm<GK, TM, 16, 1, 1, XT>), dim3(mgrid), dim3(NT), 0, st, n, k, M, X, Y, S, xmap); break;
+      case 5: hipLaunchKernelGGL((k_spmm<GK, TM, 32, 1, 1, XT>), dim3(mgrid), dim3(NT), 0, st, n, k, M, X, Y, S, xmap); break;
+      default: hipLaunchKernelGGL((k_spmm<GK, TM, 8, 1, 1, XT>), dim3(mgrid), dim3(NT), 0, st, n, k, M, X, Y, S, xmap); break;
     }
+  };
+  auto spmm_m = [&](const double* X, const float* Xf, double* Y) {
+    if (f32in) spmm_m_t(Xf, Y);
+    else spmm_m_t(X, Y);
   };
   // A~ product variant: rows per lane per tile (all interleaved, 8 gathers per row batched)
   const int avar = tune_get("SPMM_A", 0);
@@ -114,25 +126,26 @@ int bicgstab_gk(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, const 
     SAI_PROF(name, st);            \
     hipLaunchKernelGGL(__VA_ARGS__); \
   } while (0)
-    constexpr bool MF = sizeof(TM) == 4;
-    LK("bicg_p_update", (k_pupdate<GK>), dim3(grid), dim3(NT), 0, st, n, k, V, S);
+    if (f32in) LK("bicg_p_update", (k_pupdate<GK, true>), dim3(grid), dim3(NT), 0, st, n, k, V, S);
+    else LK("bicg_p_update", (k_pupdate<GK, false>), dim3(grid), dim3(NT), 0, st, n, k, V, S);
     {
       SAI_PROF(MF ? "bicg_spmm_M_f32" : "bicg_spmm_M_f64", st);
-      spmm_m(V.p, V.ph);
+      spmm_m(V.p, V.pf, V.ph);
     }
     {
       SAI_PROF("bicg_spmm_A_dot1", st);
       spmm_av();
     }
     LK("bicg_finish", (k_fin<GK, 1, F_AV>), dim3(1), dim3(FNT), 0, st, k, S, tgrid);
-    LK("bicg_s_update", (k_s<GK>), dim3(grid), dim3(NT), 0, st, n, k, V, S);
+    if (f32in) LK("bicg_s_update", (k_s<GK, true>), dim3(grid), dim3(NT), 0, st, n, k, V, S);
+    else LK("bicg_s_update", (k_s<GK, false>), dim3(grid), dim3(NT), 0, st, n, k, V, S);
     LK("bicg_finish", (k_fin<GK, 1, F_S>), dim3(1), dim3(FNT), 0, st, k, S, grid);
     LK("bicg_halfcheck", (k_halfcheck<GK>), dim3(grid), dim3(NT), 0, st, n, k, A, V, S);
     LK("bicg_finish", (k_fin<GK, 1, F_HALF>), dim3(1), dim3(FNT), 0, st, k, S, grid);
     LK("bicg_halfapply", (k_halfapply<GK>), dim3(grid), dim3(NT), 0, st, n, k, V, S);
     {
       SAI_PROF(MF ? "bicg_spmm_M_f32" : "bicg_spmm_M_f64", st);
-      spmm_m(V.s, V.sh);
+      spmm_m(V.s, V.sf, V.sh);
     }
     {
       SAI_PROF("bicg_spmm_A_dot2", st);
@@ -356,11 +369,11 @@ int krylov_typed(const sai_split_s* sp, const sai_precond_s* pc, int transpose, 
   const int64_t n = sp->n;
   if (o.method == SAI_GMRES)
     return gmres_run<TM>(A, M, n, k, R, X, thr, o.restart, o.maxit, al, st, iters, status);
-  if (k <= 4) return bicgstab_gk<4, TM>(A, M, n, k, R, X, thr, o.maxit, al, st, iters, status);
-  if (k <= 8) return bicgstab_gk<8, TM>(A, M, n, k, R, X, thr, o.maxit, al, st, iters, status);
-  if (k <= 16) return bicgstab_gk<16, TM>(A, M, n, k, R, X, thr, o.maxit, al, st, iters, status);
-  if (k <= 32) return bicgstab_gk<32, TM>(A, M, n, k, R, X, thr, o.maxit, al, st, iters, status);
-  return bicgstab_gk<64, TM>(A, M, n, k, R, X, thr, o.maxit, al, st, iters, status);
+  if (k <= 4) return bicgstab_gk<4, TM>(A, M, n, k, R, X, thr, o.maxit, o.precond_input, al, st, iters, status);
+  if (k <= 8) return bicgstab_gk<8, TM>(A, M, n, k, R, X, thr, o.maxit, o.precond_input, al, st, iters, status);
+  if (k <= 16) return bicgstab_gk<16, TM>(A, M, n, k, R, X, thr, o.maxit, o.precond_input, al, st, iters, status);
+  if (k <= 32) return bicgstab_gk<32, TM>(A, M, n, k, R, X, thr, o.maxit, o.precond_input, al, st, iters, status);
+  return bicgstab_gk<64, TM>(A, M, n, k, R, X, thr, o.maxit, o.precond_input, al, st, iters, status);
 }
 
 }  // namespace
@@ -371,6 +384,8 @@ int krylov_impl(const sai_split_s* sp, const sai_precond_s* pc, int transpose, i
   if (k < 1 || k > 64) SAI_THROW(SAI_EINVAL, "k must be in [1, 64] (got %d)", k);
   if (o.method != SAI_BICGSTAB && o.method != SAI_GMRES) SAI_THROW(SAI_EINVAL, "bad method");
   if (o.maxit < 0) SAI_THROW(SAI_EINVAL, "maxit < 0");
+  if (o.precond_input != SAI_PIN_MATCH && o.precond_input != SAI_PIN_FP64)
+    SAI_THROW(SAI_EINVAL, "bad precond_input");
   if (pc->n != sp->n) SAI_THROW(SAI_EINVAL, "preconditioner and split sizes differ");
   if (pc->precision == SAI_FP32)
     return krylov_typed<float>(sp, pc, transpose, k, R, X, thr, o, st, iters, status);
