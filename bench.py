@@ -232,13 +232,12 @@ def main():
         assigned |= sel
         ls_work["ls_qr_f32_" + tag] = float(flops[sel].sum())
     bytes_kn = 8.0 * k * n
-    # the FP32 M reads FP32 copies of p and s (written by the p and s updates)
     hbm_bytes = {
-        "bicg_spmm_M_f32": 8.0 * nnz_m + 4.0 * (n + 1) + 1.5 * bytes_kn,
+        "bicg_spmm_M_f32": 8.0 * nnz_m + 4.0 * (n + 1) + 2 * bytes_kn,
         "bicg_spmm_A_dot1": 12.0 * nnz_t + 4.0 * (n + 1) + 3 * bytes_kn,
         "bicg_spmm_A_dot2": 12.0 * nnz_t + 4.0 * (n + 1) + 3 * bytes_kn,
-        "bicg_p_update": 4.5 * bytes_kn,
-        "bicg_s_update": 3.5 * bytes_kn,
+        "bicg_p_update": 4 * bytes_kn,
+        "bicg_s_update": 3 * bytes_kn,
         "bicg_xr_update": 8 * bytes_kn,
     }
     kernels = sorted(((tot, nm, l) for nm, (l, tot) in prof.items()), reverse=True)
@@ -288,7 +287,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 M (built and applied in f32, f64 accumulation) + f64 Krylov/SMW/check",
+        "dtype": "f32 M build + f64 Krylov/SMW/check",
         "data": "synthetic",
         "config": {"workload": name, "n": n, "s": s, "nnz_A": int(w.A.nnz), "rhs": k,
                    "solver": "gmres30" if skw["method"] == P.GMRES else "bicgstab", "eps": skw["eps"],

@@ -197,19 +197,12 @@ void sai_precond_destroy(sai_precond_t* h);
  * any column ended that way (X is written in every case).  k <= 64. */
 enum { SAI_BICGSTAB = 0, SAI_GMRES = 1 };
 enum { SAI_C_ONE = 0, SAI_C_ONE_THEN_REFINE = 1 };
-/* Precision of the vector that the preconditioner is applied to (BiCGStab):
- * SAI_PIN_MATCH rounds it to M's storage precision (an FP32 M is applied to an
- * FP32 copy of p and s, written by the kernels that form them; the products
- * still accumulate in float64 and every residual, inner product and update
- * stays float64); SAI_PIN_FP64 always applies M to the float64 vector. */
-enum { SAI_PIN_MATCH = 0, SAI_PIN_FP64 = 1 };
 typedef struct {
   int32_t method;   /* SAI_BICGSTAB | SAI_GMRES */
   int32_t restart;  /* GMRES(m): 30 */
   double eps;       /* 1e-8 */
   int32_t maxit;    /* 500 */
   int32_t c_mode;   /* SAI_C_ONE (paper) | SAI_C_ONE_THEN_REFINE */
-  int32_t precond_input; /* SAI_PIN_MATCH (default) | SAI_PIN_FP64 */
 } sai_solve_opts;
 
 int sai_krylov(const sai_split_t* sp, const sai_precond_t* pc, int32_t transpose, int32_t k,

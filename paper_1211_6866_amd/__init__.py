@@ -27,7 +27,6 @@ INIT_PATTERN_A, INIT_DIAG = 0, 1
 FP32, FP64 = 0, 1
 BICGSTAB, GMRES = 0, 1
 C_ONE, C_ONE_THEN_REFINE = 0, 1
-PIN_MATCH, PIN_FP64 = 0, 1
 
 
 class SaiError(RuntimeError):
@@ -81,7 +80,7 @@ class PrecondInfo(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("method", C.c_int32), ("restart", C.c_int32), ("eps", C.c_double),
-                ("maxit", C.c_int32), ("c_mode", C.c_int32), ("precond_input", C.c_int32)]
+                ("maxit", C.c_int32), ("c_mode", C.c_int32)]
 
 
 class SolveStats(C.Structure):
@@ -271,10 +270,8 @@ class Precond:
                     t_assemble_ms=s.t_assemble_ms, t_total_ms=s.t_total_ms)
 
 
-def _sopts(method=BICGSTAB, restart=30, eps=1e-8, maxit=500, c_mode=C_ONE,
-           precond_input=PIN_MATCH):
-    return SolveOpts(int(method), int(restart), float(eps), int(maxit), int(c_mode),
-                     int(precond_input))
+def _sopts(method=BICGSTAB, restart=30, eps=1e-8, maxit=500, c_mode=C_ONE):
+    return SolveOpts(int(method), int(restart), float(eps), int(maxit), int(c_mode))
 
 
 def krylov(split: Split, pc: Precond, R, thr, transpose=False, raise_on_error=True, **kw):

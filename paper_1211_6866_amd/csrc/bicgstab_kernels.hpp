@@ -1,13 +1,20 @@
 // Kernels of the batched right-preconditioned BiCGStab (included by krylov.hip).
 //
-// Blocks are n x k row-major.  A group of GK lanes (GK = next power of two >= k)
-// handles one row, lane c owning column c; a 256-thread block covers RPB =
-// 256/GK rows at a time.  Sparse products stage the column indices and values
-// of a tile of SUB*RPB consecutive rows in LDS with one coalesced copy, then
-// every lane gathers X[j, c] for up to eight entries at a time, so that eight
-// independent loads are in flight.  Per-column state (status, scalars) is read
-// once per kernel.  Dot products are reduced per block into partials; a
-// one-block finisher kernel adds the partials in a fixed order
+// The vectors of the k systems form n x kp row-major blocks, kp = k rounded up
+// to even (the pad column is never active).  A lane owns a pair of columns
+// (2l, 2l+1) of one row and moves them with one 16-byte access; LP lanes serve
+// a row (LP >= kp/2, from a fixed set so that 64/LP rows fill a wavefront
+// well), so a wavefront instruction covers RPW = 64/LP rows.  Compared with
+// one lane per column this cuts the number of gather instructions of the
+// sparse products, which are bound by the address/data path of the vector
+// memory unit rather than by HBM, by about 2.5x for k = 11.
+//
+// Sparse products stage the column indices and values of a tile of rows (one
+// row per lane) in LDS with one coalesced copy, then every lane gathers the
+// pairs X[j, 2l..2l+1] of its row in batches whose loads are all issued before
+// the first is consumed, sized so that no slot is padded.  Per-column state
+// (status, scalars) is read once per kernel.  Dot products are reduced per
+// block into partials; a one-block finisher adds the partials in a fixed order
 // (deterministic) and updates the per-column scalars and flags.
 #pragma once
 
@@ -16,9 +23,9 @@ namespace {
 
 constexpr int NT = 256;
 constexpr int NBMAX = 2048;
-constexpr int SUB = 4;
-constexpr int CAP_A = 1024;  // staged entries per tile: A~ (about 7 per row)
-constexpr int CAP_M = 3072;  // and M (about 25 per row)
+constexpr int PSTRIDE = 64;  // partial sums: [ND][NBMAX][PSTRIDE] doubles
+constexpr int CAP_A = 2048;  // staged entries per tile of A~
+constexpr int CAP_M = 2048;  // and of M
 constexpr double TINY = 1e-300;
 
 enum { ST_ACTIVE = 0, ST_CONV = 1, ST_MAXIT = 2, ST_BREAK = 3 };
@@ -37,134 +44,119 @@ struct State {
   double* part;
 };
 
+// n x kp blocks (b: the right-hand sides, copied in with the pad column zeroed)
 struct Vec {
-  const double* rhs;
-  double *x, *r, *rh, *p, *v, *s, *ph, *sh, *t;
-  // FP32 copies of p and s written beside them (null: not kept); the FP32
-  // preconditioner is applied to these copies
-  float *pf, *sf;
+  double *b, *x, *r, *rh, *p, *v, *s, *ph, *sh, *t;
 };
 
 __device__ __forceinline__ bool col_on(const State& S, int c, int k) {
   return c < k && S.status[c] == ST_ACTIVE && S.skip[c] == 0;
 }
 
-// sum_e A_ie X[j_e, c] over entries eb..ee of (sci, sv), accumulated in FP64
-// (a product of two FP32 numbers is exact in FP64)
-template <class TV, class XT>
-__device__ __forceinline__ double row_prod_lds(const int32_t* __restrict__ sci,
-                                               const TV* __restrict__ sv, int eb, int ee,
-                                               const XT* __restrict__ X, int k, int c) {
-  double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  int e = eb;
-  for (; e + 7 < ee; e += 8) {
-    XT x[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) x[u] = X[(int64_t)sci[e + u] * k + c];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) a[u] += (double)sv[e + u] * (double)x[u];
-  }
-  if (e + 3 < ee) {
-    XT x[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) x[u] = X[(int64_t)sci[e + u] * k + c];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) a[u] += (double)sv[e + u] * (double)x[u];
-    e += 4;
-  }
-  for (; e < ee; ++e) a[4] += (double)sv[e] * (double)X[(int64_t)sci[e] * k + c];
-  return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+__device__ __forceinline__ double2 ld2(const double* __restrict__ p, int64_t q) {
+  return *reinterpret_cast<const double2*>(p + q);
 }
 
-template <class TV, class XT>
-__device__ __forceinline__ double row_prod(const Csr<TV>& A, int64_t i, const XT* __restrict__ X,
-                                           int k, int c) {
-  return row_prod_lds<TV, XT>(A.ci, A.v, A.rp[i], A.rp[i + 1], X, k, c);
+// store the pair (a, b) at q, q+1, each half only where its column is on
+__device__ __forceinline__ void st2(double* __restrict__ p, int64_t q, double a, double b, bool o0,
+                                    bool o1) {
+  if (o0 && o1) {
+    *reinterpret_cast<double2*>(p + q) = make_double2(a, b);
+  } else {
+    if (o0) p[q] = a;
+    if (o1) p[q + 1] = b;
+  }
 }
 
-// SI rows at once, entries eb[q]..ee[q] in LDS: the gathers of the first CH
-// entries of every row are all issued before any is consumed (SI*CH loads in
-// flight per lane); entries past CH follow in a plain loop.  BF (branch-free):
-// a slot past the row's end loads row 0 of X (a valid address) and is
-// multiplied by zero, so that the compiler issues every load before the first
-// wait; otherwise each slot is guarded, which suits short rows (A~).
-template <class TV, int CH, int SI, bool BF, class XT>
-__device__ __forceinline__ void rows_prod_batch(const int32_t* __restrict__ sci,
-                                                const TV* __restrict__ sv, const int (&eb)[SI],
-                                                const int (&ee)[SI], const XT* __restrict__ X,
-                                                int k, int c, double (&out)[SI]) {
-  XT xv[SI][CH];
+// Lane geometry: LP lanes per row, RPW rows per wavefront, RPB rows per block.
+#define LANES(LP)                                                              \
+  constexpr int RPW = 64 / (LP);                                               \
+  constexpr int RPB = RPW * (NT / 64);                                         \
+  const int l_ = (int)(threadIdx.x & 63) % (LP);                               \
+  const bool lok_ = ((int)(threadIdx.x & 63) / (LP)) < RPW;                    \
+  const int rib = (int)(threadIdx.x >> 6) * RPW + (int)(threadIdx.x & 63) / (LP); \
+  const int c0 = 2 * l_;                                                       \
+  const bool live = lok_ && c0 < k;                                            \
+  (void)RPB;                                                                   \
+  (void)live;
+
+// rows i handled by this lane in a grid-stride loop (streaming kernels)
+#define ROW_LOOP for (int64_t i = (int64_t)blockIdx.x * RPB + rib; i < n; i += (int64_t)gridDim.x * RPB)
+
+// Product of one row (entries e..ee of (ci, v)) with the column pair c0, c0+1
+// of X (row stride kp): batches of CH entries while at least CH remain (all
+// loads of a batch issued before the first is consumed), then one batch of CH2,
+// then single entries, so that no load slot is wasted on a padded entry (the
+// gathers are bound by the vector memory unit's instruction throughput).
+template <class TV, int CH, int CH2>
+__device__ __forceinline__ void row_prod(const int32_t* __restrict__ ci, const TV* __restrict__ v, int e,
+                                         int ee, const double* __restrict__ X, int kp, int c0, double& a0,
+                                         double& a1) {
+  a0 = a1 = 0.0;
+  for (; e + CH <= ee; e += CH) {
+    double2 xv[CH];
 #pragma unroll
-  for (int q = 0; q < SI; ++q) {
+    for (int u = 0; u < CH; ++u) xv[u] = ld2(X, (int64_t)ci[e + u] * kp + c0);
 #pragma unroll
     for (int u = 0; u < CH; ++u) {
-      const int e = eb[q] + u;
-      const bool ok = e < ee[q];
-      if constexpr (BF) {
-        const int j = sci[ok ? e : 0];
-        xv[q][u] = X[(int64_t)(ok ? j : 0) * k + c];
-      } else {
-        xv[q][u] = ok ? X[(int64_t)sci[e] * k + c] : XT(0);
-      }
+      const double w = (double)v[e + u];
+      a0 += w * xv[u].x;
+      a1 += w * xv[u].y;
     }
   }
+  if (CH2 > 0 && e + CH2 <= ee) {
+    double2 xv[CH2 > 0 ? CH2 : 1];
 #pragma unroll
-  for (int q = 0; q < SI; ++q) {
-    double a = 0.0;
+    for (int u = 0; u < CH2; ++u) xv[u] = ld2(X, (int64_t)ci[e + u] * kp + c0);
 #pragma unroll
-    for (int u = 0; u < CH; ++u) {
-      const int e = eb[q] + u;
-      const bool ok = e < ee[q];
-      if constexpr (BF) {
-        const TV w = sv[ok ? e : 0];
-        a += (double)(ok ? w : TV(0)) * (double)xv[q][u];
-      } else {
-        if (ok) a += (double)sv[e] * (double)xv[q][u];
-      }
+    for (int u = 0; u < CH2; ++u) {
+      const double w = (double)v[e + u];
+      a0 += w * xv[u].x;
+      a1 += w * xv[u].y;
     }
-    if (ee[q] > eb[q] + CH) a += row_prod_lds<TV, XT>(sci, sv, eb[q] + CH, ee[q], X, k, c);
-    out[q] = a;
+    e += CH2;
+  }
+  for (; e < ee; ++e) {
+    const double2 x = ld2(X, (int64_t)ci[e] * kp + c0);
+    const double w = (double)v[e];
+    a0 += w * x.x;
+    a1 += w * x.y;
   }
 }
 
-// Block-reduce ND per-lane accumulators (per column) and publish the block's
-// partial sums for the finisher.
-template <int GK, int ND>
-__device__ void block_partials(double (&acc)[ND], const State& S) {
-  constexpr int RPB = NT / GK;
-  __shared__ double red[ND][NT];
+// Block-reduce ND per-lane accumulator pairs (per column) in a fixed order and
+// publish the block's partial sums for the finisher.
+template <int LP, int ND>
+__device__ void block_partials(double (&acc)[ND][2], const State& S) {
+  constexpr int RPW = 64 / LP;
+  __shared__ double red[ND][2 * NT];
   const int t = threadIdx.x;
 #pragma unroll
-  for (int d = 0; d < ND; ++d) red[d][t] = acc[d];
+  for (int d = 0; d < ND; ++d) {
+    red[d][2 * t] = acc[d][0];
+    red[d][2 * t + 1] = acc[d][1];
+  }
   __syncthreads();
-  if (t < GK) {
+  if (t < 2 * LP) {
+    const int l = t >> 1, j = t & 1;
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
       double s = 0.0;
-      for (int r = 0; r < RPB; ++r) s += red[d][r * GK + t];
-      S.part[((int64_t)d * NBMAX + blockIdx.x) * GK + t] = s;
+      for (int w = 0; w < NT / 64; ++w)
+        for (int rw = 0; rw < RPW; ++rw) s += red[d][2 * (w * 64 + rw * LP + l) + j];
+      S.part[((int64_t)d * NBMAX + blockIdx.x) * PSTRIDE + t] = s;
     }
   }
 }
 
-// Grid-stride loop over single rows (streaming kernels).
-#define ROW_LOOP                                                                   \
-  constexpr int RPB = NT / GK;                                                     \
-  const int c = threadIdx.x % GK;                                                  \
-  const int rib = threadIdx.x / GK;                                                \
-  for (int64_t i = (int64_t)blockIdx.x * RPB + rib; i < n; i += (int64_t)gridDim.x * RPB)
-
-// Tile loop for sparse products: tiles of TR = SUB*RPB rows; every thread of the
-// block runs every iteration (the body synchronises).  Workgroups are dispatched
-// to the 8 XCDs round-robin (block b on XCD b % 8), and each XCD has its own L2;
-// so the tiles are split into 8 contiguous chunks, chunk x processed by the
-// blocks of XCD x.  The rows in flight on one XCD then form one window, and
-// the gathered rows of X (within the band of the matrix) stay in that XCD's L2.
+// Tile loop for sparse products: tiles of TR = RPB rows (one per lane); every thread of
+// the block runs every iteration (the body synchronises).  Workgroups are
+// dispatched to the 8 XCDs round-robin (block b on XCD b % 8), and each XCD
+// has its own L2; with xmap the tiles are split into 8 contiguous chunks,
+// chunk x processed by the blocks of XCD x, so that the band of gathered rows
+// of X stays in that XCD's L2.
 #define TILE_LOOP                                                                  \
-  constexpr int RPB = NT / GK;                                                     \
-  constexpr int TR = SUB * RPB;                                                    \
-  const int c = threadIdx.x % GK;                                                  \
-  const int rib = threadIdx.x / GK;                                                \
+  constexpr int TR = RPB;                                                          \
   const int64_t ntile_ = (n + TR - 1) / TR;                                        \
   const bool xcd_map_ = xmap && (gridDim.x % 8) == 0;                              \
   const int64_t chunk_ = xcd_map_ ? (ntile_ + 7) / 8 : ntile_;                     \
@@ -196,241 +188,285 @@ __device__ __forceinline__ bool stage_tile(const Csr<TV>& A, int64_t t0, int row
   return fit;
 }
 
-#define STAGE_DECL(TV, CAP)                   \
-  __shared__ int32_t s_rp[SUB * NT / GK + 1]; \
-  __shared__ int32_t s_ci[CAP];               \
+#define STAGE_DECL(TV, CAP, TRW)       \
+  __shared__ int32_t s_rp[(TRW) + 1]; \
+  __shared__ int32_t s_ci[CAP];       \
   __shared__ TV s_v[CAP];
 
-// product of row r (tile-relative) with X; `fit` and `t0` from the tile loop
-#define STAGED_PROD(A, X, r)                                                                \
-  (fit ? row_prod_lds(s_ci, s_v, s_rp[r] - s_rp[0], s_rp[(r) + 1] - s_rp[0], (X), k, c)    \
-       : row_prod((A), t0 + (r), (X), k, c))
-
-// ---- initialisation: x = 0, r = r_hat = rhs, p = v = 0; partial ||r||^2 ----------
-template <int GK>
-__global__ void __launch_bounds__(NT) k_init(int64_t n, int k, Vec V, State S) {
-  double acc[1] = {0.0};
-  ROW_LOOP {
-    if (c >= k) continue;
-    const int64_t q = i * k + c;
-    const double b = V.rhs[q];
-    V.x[q] = 0.0;
-    V.r[q] = b;
-    V.rh[q] = b;
-    V.p[q] = 0.0;
-    V.v[q] = 0.0;
-    acc[0] += b * b;
+// The lane's row of the tile is r = rib (from LDS when the tile was staged,
+// else from the matrix in global memory).  If r < rows: PRE (loads issued
+// before the gathers), then BODY with y0, y1 (the pair's products) and qq (the
+// index of the pair's first element).
+#define TILE_ROW_PROD(TV, CH, CH2, A, X, PRE, BODY)                                     \
+  if (rib < rows) {                                                                     \
+    const int64_t qq = (t0 + rib) * kp + c0;                                            \
+    PRE                                                                                 \
+    double y0, y1;                                                                      \
+    if (fit)                                                                            \
+      row_prod<TV, CH, CH2>(s_ci, s_v, s_rp[rib] - s_rp[0], s_rp[rib + 1] - s_rp[0], (X), \
+                            kp, c0, y0, y1);                                            \
+    else                                                                                \
+      row_prod<TV, CH, CH2>((A).ci, (A).v, s_rp[rib], s_rp[rib + 1], (X), kp, c0, y0, y1); \
+    BODY                                                                                \
   }
-  block_partials<GK, 1>(acc, S);
+
+// ---- initialisation: b = R (pad column 0), x = 0, r = r_hat = b, p = v = 0 -------
+template <int LP>
+__global__ void __launch_bounds__(NT) k_init(int64_t n, int k, int kp, const double* __restrict__ R,
+                                             Vec V, State S) {
+  LANES(LP)
+  double acc[1][2] = {{0.0, 0.0}};
+  if (lok_ && c0 < kp) {
+    ROW_LOOP {
+      const int64_t q = i * kp + c0;
+      const double b0 = R[i * k + c0];
+      const double b1 = c0 + 1 < k ? R[i * k + c0 + 1] : 0.0;
+      const double2 bb = make_double2(b0, b1), zz = make_double2(0.0, 0.0);
+      *reinterpret_cast<double2*>(V.b + q) = bb;
+      *reinterpret_cast<double2*>(V.x + q) = zz;
+      *reinterpret_cast<double2*>(V.r + q) = bb;
+      *reinterpret_cast<double2*>(V.rh + q) = bb;
+      *reinterpret_cast<double2*>(V.p + q) = zz;
+      *reinterpret_cast<double2*>(V.v + q) = zz;
+      if (c0 + 1 == k) {  // zero the pad column of the other blocks
+        V.s[q + 1] = V.ph[q + 1] = V.sh[q + 1] = V.t[q + 1] = 0.0;
+      }
+      acc[0][0] += b0 * b0;
+      acc[0][1] += b1 * b1;
+    }
+  }
+  block_partials<LP, 1>(acc, S);
 }
 
-// ---- p = r + beta (p - omega v) (and its FP32 copy) ------------------------------
-template <int GK, bool F32>
-__global__ void __launch_bounds__(NT) k_pupdate(int64_t n, int k, Vec V, State S) {
-  const int cc = threadIdx.x % GK;
-  if (!col_on(S, cc, k)) return;
-  const double beta = S.beta[cc], omega = S.omega[cc];
+// ---- p = r + beta (p - omega v) -------------------------------------------------
+template <int LP>
+__global__ void __launch_bounds__(NT) k_pupdate(int64_t n, int k, int kp, Vec V, State S) {
+  LANES(LP)
+  const bool o0 = lok_ && col_on(S, c0, k), o1 = lok_ && col_on(S, c0 + 1, k);
+  if (!o0 && !o1) return;
+  const double be0 = o0 ? S.beta[c0] : 0.0, om0 = o0 ? S.omega[c0] : 0.0;
+  const double be1 = o1 ? S.beta[c0 + 1] : 0.0, om1 = o1 ? S.omega[c0 + 1] : 0.0;
   ROW_LOOP {
-    const int64_t q = i * k + c;
-    const double pv = V.r[q] + beta * (V.p[q] - omega * V.v[q]);
-    V.p[q] = pv;
-    if constexpr (F32) V.pf[q] = (float)pv;
+    const int64_t q = i * kp + c0;
+    const double2 r = ld2(V.r, q), p = ld2(V.p, q), v = ld2(V.v, q);
+    st2(V.p, q, r.x + be0 * (p.x - om0 * v.x), r.y + be1 * (p.y - om1 * v.y), o0, o1);
   }
 }
 
 // ---- Y = Op X (plain product for the active columns) -------------------------------
-// The lane's SUB rows of the tile are r = sb*RPB + rib; they are handled SI at a
-// time with rows_prod_batch (tile staged) or one by one from global memory.
-#define TILE_ROWS_PROD(TV, CH, SI, BF, A, X, BODY)                                      \
-  if (fit) {                                                                          \
-    _Pragma("unroll") for (int b0 = 0; b0 < SUB; b0 += (SI)) {                        \
-      int eb[SI], ee[SI];                                                             \
-      double out[SI];                                                                 \
-      _Pragma("unroll") for (int q = 0; q < (SI); ++q) {                              \
-        const int r = (b0 + q) * RPB + rib;                                           \
-        eb[q] = r < rows ? s_rp[r] - s_rp[0] : 0;                                     \
-        ee[q] = r < rows ? s_rp[r + 1] - s_rp[0] : 0;                                 \
-      }                                                                               \
-      rows_prod_batch<TV, CH, SI, BF>(s_ci, s_v, eb, ee, (X), k, c, out);              \
-      _Pragma("unroll") for (int q = 0; q < (SI); ++q) {                              \
-        const int r = (b0 + q) * RPB + rib;                                           \
-        if (r < rows) {                                                               \
-          const double y = out[q];                                                    \
-          const int64_t qq = (t0 + r) * k + c;                                        \
-          BODY                                                                        \
-        }                                                                             \
-      }                                                                               \
-    }                                                                                 \
-  } else {                                                                            \
-    for (int sb = 0; sb < SUB; ++sb) {                                                \
-      const int r = sb * RPB + rib;                                                   \
-      if (r < rows) {                                                                 \
-        const double y = row_prod((A), t0 + r, (X), k, c);                            \
-        const int64_t qq = (t0 + r) * k + c;                                          \
-        BODY                                                                          \
-      }                                                                               \
-    }                                                                                 \
-  }
-
-template <int GK, class TV, int CH, int SI, int SUBT, class XT>
-__global__ void __launch_bounds__(NT) k_spmm(int64_t n, int k, Csr<TV> A, const XT* __restrict__ X,
-                                             double* __restrict__ Y, State S, int xmap) {
-  constexpr int SUB = SUBT;
-  STAGE_DECL(TV, CAP_M)
-  const bool on = col_on(S, threadIdx.x % GK, k);
+template <int LP, class TV, int CH, int CH2>
+__global__ void __launch_bounds__(NT) k_spmm(int64_t n, int k, int kp, Csr<TV> A,
+                                             const double* __restrict__ X, double* __restrict__ Y,
+                                             State S, int xmap) {
+  LANES(LP)
+  STAGE_DECL(TV, CAP_M, RPB)
+  if (S.any[3] == 0) return;
+  const bool o0 = lok_ && col_on(S, c0, k), o1 = lok_ && col_on(S, c0 + 1, k);
   TILE_LOOP {
     const int rows = (int)min<int64_t>(TR, n - t0);
     const bool fit = stage_tile<TV, CAP_M>(A, t0, rows, s_rp, s_ci, s_v);
-    if (on) { TILE_ROWS_PROD(TV, CH, SI, true, A, X, __builtin_nontemporal_store(y, &Y[qq]);) }
+    if (o0 || o1) { TILE_ROW_PROD(TV, CH, CH2, A, X, , st2(Y, qq, y0, y1, o0, o1);) }
     __syncthreads();
   }
 }
 
 // ---- v = A p_hat; partial sigma = r_hat^T v --------------------------------------
-template <int GK, int SUBT>
-__global__ void __launch_bounds__(NT) k_av(int64_t n, int k, Csr<double> A, Vec V, State S, int xmap) {
-  constexpr int SUB = SUBT;
-  STAGE_DECL(double, CAP_A)
-  double acc[1] = {0.0};
-  const bool on = col_on(S, threadIdx.x % GK, k);
-  TILE_LOOP {
-    const int rows = (int)min<int64_t>(TR, n - t0);
-    const bool fit = stage_tile<double, CAP_A>(A, t0, rows, s_rp, s_ci, s_v);
-    if (on) {
-      TILE_ROWS_PROD(double, 8, SUB, false, A, V.ph, __builtin_nontemporal_store(y, &V.v[qq]);
-                     acc[0] += __builtin_nontemporal_load(&V.rh[qq]) * y;)
+template <int LP, int CH, int CH2>
+__global__ void __launch_bounds__(NT) k_av(int64_t n, int k, int kp, Csr<double> A, Vec V, State S,
+                                           int xmap) {
+  LANES(LP)
+  STAGE_DECL(double, CAP_A, RPB)
+  double acc[1][2] = {{0.0, 0.0}};
+  const bool o0 = lok_ && col_on(S, c0, k), o1 = lok_ && col_on(S, c0 + 1, k);
+  if (S.any[3] != 0) {
+    TILE_LOOP {
+      const int rows = (int)min<int64_t>(TR, n - t0);
+      const bool fit = stage_tile<double, CAP_A>(A, t0, rows, s_rp, s_ci, s_v);
+      if (o0 || o1) {
+        TILE_ROW_PROD(double, CH, CH2, A, V.ph, const double2 rh = ld2(V.rh, qq);,
+                      st2(V.v, qq, y0, y1, o0, o1);
+                      if (o0) acc[0][0] += rh.x * y0; if (o1) acc[0][1] += rh.y * y1;)
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
-  block_partials<GK, 1>(acc, S);
+  block_partials<LP, 1>(acc, S);
 }
 
-// ---- s = r - alpha v (and its FP32 copy); partial ||s||^2 -------------------------
-template <int GK, bool F32>
-__global__ void __launch_bounds__(NT) k_s(int64_t n, int k, Vec V, State S) {
-  double acc[1] = {0.0};
-  const int cc = threadIdx.x % GK;
-  const bool on = col_on(S, cc, k);
-  const double alpha = on ? S.alpha[cc] : 0.0;
-  ROW_LOOP {
-    if (!on) break;
-    const int64_t q = i * k + c;
-    const double sv = V.r[q] - alpha * V.v[q];
-    V.s[q] = sv;
-    if constexpr (F32) V.sf[q] = (float)sv;
-    acc[0] += sv * sv;
+// ---- s = r - alpha v; partial ||s||^2 -----------------------------------------
+template <int LP>
+__global__ void __launch_bounds__(NT) k_s(int64_t n, int k, int kp, Vec V, State S) {
+  LANES(LP)
+  double acc[1][2] = {{0.0, 0.0}};
+  const bool o0 = lok_ && col_on(S, c0, k), o1 = lok_ && col_on(S, c0 + 1, k);
+  const double al0 = o0 ? S.alpha[c0] : 0.0, al1 = o1 ? S.alpha[c0 + 1] : 0.0;
+  if (o0 || o1) {
+    ROW_LOOP {
+      const int64_t q = i * kp + c0;
+      const double2 r = ld2(V.r, q), v = ld2(V.v, q);
+      const double s0 = r.x - al0 * v.x, s1 = r.y - al1 * v.y;
+      st2(V.s, q, s0, s1, o0, o1);
+      if (o0) acc[0][0] += s0 * s0;
+      if (o1) acc[0][1] += s1 * s1;
+    }
   }
-  block_partials<GK, 1>(acc, S);
+  block_partials<LP, 1>(acc, S);
 }
 
-// ---- half-step true residual rhs - A (x + alpha p_hat), flagged columns only -------
-template <int GK>
-__global__ void __launch_bounds__(NT) k_halfcheck(int64_t n, int k, Csr<double> A, Vec V, State S) {
+// ---- half-step true residual b - A (x + alpha p_hat), flagged columns only -------
+template <int LP>
+__global__ void __launch_bounds__(NT) k_halfcheck(int64_t n, int k, int kp, Csr<double> A, Vec V,
+                                                  State S) {
   if (S.any[0] == 0) return;
-  double acc[1] = {0.0};
-  const int cc = threadIdx.x % GK;
-  const bool on = col_on(S, cc, k) && S.half[cc];
-  const double al = on ? S.alpha[cc] : 0.0;
-  ROW_LOOP {
-    if (!on) break;
-    double y = 0.0;
-    for (int32_t e = A.rp[i]; e < A.rp[i + 1]; ++e) {
-      const int64_t q = (int64_t)A.ci[e] * k + c;
-      y += A.v[e] * (V.x[q] + al * V.ph[q]);
+  LANES(LP)
+  double acc[1][2] = {{0.0, 0.0}};
+  const bool o0 = lok_ && col_on(S, c0, k) && S.half[c0];
+  const bool o1 = lok_ && col_on(S, c0 + 1, k) && S.half[c0 + 1];
+  const double al0 = o0 ? S.alpha[c0] : 0.0, al1 = o1 ? S.alpha[c0 + 1] : 0.0;
+  if (o0 || o1) {
+    ROW_LOOP {
+      double y0 = 0.0, y1 = 0.0;
+      for (int32_t e = A.rp[i]; e < A.rp[i + 1]; ++e) {
+        const int64_t q = (int64_t)A.ci[e] * kp + c0;
+        const double2 x = ld2(V.x, q), ph = ld2(V.ph, q);
+        y0 += A.v[e] * (x.x + al0 * ph.x);
+        y1 += A.v[e] * (x.y + al1 * ph.y);
+      }
+      const double2 b = ld2(V.b, i * kp + c0);
+      const double r0 = b.x - y0, r1 = b.y - y1;
+      if (o0) acc[0][0] += r0 * r0;
+      if (o1) acc[0][1] += r1 * r1;
     }
-    const double rt = V.rhs[i * k + c] - y;
-    acc[0] += rt * rt;
   }
-  block_partials<GK, 1>(acc, S);
+  block_partials<LP, 1>(acc, S);
 }
 
 // ---- x += alpha p_hat for the columns that converged at the half step -------------
-template <int GK>
-__global__ void __launch_bounds__(NT) k_halfapply(int64_t n, int k, Vec V, State S) {
+template <int LP>
+__global__ void __launch_bounds__(NT) k_halfapply(int64_t n, int k, int kp, Vec V, State S) {
   if (S.any[4] == 0) return;
-  const int cc = threadIdx.x % GK;
-  if (cc >= k || !S.halfconv[cc] || S.status[cc] != ST_ACTIVE) return;
-  const double al = S.alpha[cc];
+  LANES(LP)
+  const bool o0 = lok_ && c0 < k && S.halfconv[c0] && S.status[c0] == ST_ACTIVE;
+  const bool o1 = lok_ && c0 + 1 < k && S.halfconv[c0 + 1] && S.status[c0 + 1] == ST_ACTIVE;
+  if (!o0 && !o1) return;
+  const double al0 = o0 ? S.alpha[c0] : 0.0, al1 = o1 ? S.alpha[c0 + 1] : 0.0;
   ROW_LOOP {
-    const int64_t q = i * k + c;
-    V.x[q] += al * V.ph[q];
+    const int64_t q = i * kp + c0;
+    const double2 x = ld2(V.x, q), ph = ld2(V.ph, q);
+    st2(V.x, q, x.x + al0 * ph.x, x.y + al1 * ph.y, o0, o1);
   }
 }
 
 // ---- t = A s_hat; partials t^T s, t^T t ------------------------------------------
-template <int GK, int SUBT>
-__global__ void __launch_bounds__(NT) k_at(int64_t n, int k, Csr<double> A, Vec V, State S, int xmap) {
-  constexpr int SUB = SUBT;
-  STAGE_DECL(double, CAP_A)
-  double acc[2] = {0.0, 0.0};
-  const int cc = threadIdx.x % GK;
-  const bool on = col_on(S, cc, k) && !S.halfconv[cc];
-  TILE_LOOP {
-    const int rows = (int)min<int64_t>(TR, n - t0);
-    const bool fit = stage_tile<double, CAP_A>(A, t0, rows, s_rp, s_ci, s_v);
-    if (on) {
-      TILE_ROWS_PROD(double, 8, SUB, false, A, V.sh, __builtin_nontemporal_store(y, &V.t[qq]);
-                     acc[0] += y * __builtin_nontemporal_load(&V.s[qq]); acc[1] += y * y;)
+template <int LP, int CH, int CH2>
+__global__ void __launch_bounds__(NT) k_at(int64_t n, int k, int kp, Csr<double> A, Vec V, State S,
+                                           int xmap) {
+  LANES(LP)
+  STAGE_DECL(double, CAP_A, RPB)
+  double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+  const bool o0 = lok_ && col_on(S, c0, k) && !S.halfconv[c0];
+  const bool o1 = lok_ && col_on(S, c0 + 1, k) && !S.halfconv[c0 + 1];
+  if (S.any[3] != 0) {
+    TILE_LOOP {
+      const int rows = (int)min<int64_t>(TR, n - t0);
+      const bool fit = stage_tile<double, CAP_A>(A, t0, rows, s_rp, s_ci, s_v);
+      if (o0 || o1) {
+        TILE_ROW_PROD(double, CH, CH2, A, V.sh, const double2 sv = ld2(V.s, qq);,
+                      st2(V.t, qq, y0, y1, o0, o1);
+                      if (o0) { acc[0][0] += y0 * sv.x; acc[1][0] += y0 * y0; }
+                      if (o1) { acc[0][1] += y1 * sv.y; acc[1][1] += y1 * y1; })
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
-  block_partials<GK, 2>(acc, S);
+  block_partials<LP, 2>(acc, S);
 }
 
 // ---- x += alpha p_hat + omega s_hat, r = s - omega t; partials r_hat^T r, r^T r -----
-template <int GK>
-__global__ void __launch_bounds__(NT) k_xr(int64_t n, int k, Vec V, State S) {
-  double acc[2] = {0.0, 0.0};
-  const int cc = threadIdx.x % GK;
-  const bool on = col_on(S, cc, k) && !S.halfconv[cc];
-  const double alpha = on ? S.alpha[cc] : 0.0, omega = on ? S.omega[cc] : 0.0;
-  ROW_LOOP {
-    if (!on) break;
-    const int64_t q = i * k + c;
-    V.x[q] += alpha * V.ph[q] + omega * V.sh[q];
-    const double rv = V.s[q] - omega * V.t[q];
-    V.r[q] = rv;
-    acc[0] += V.rh[q] * rv;
-    acc[1] += rv * rv;
+template <int LP>
+__global__ void __launch_bounds__(NT) k_xr(int64_t n, int k, int kp, Vec V, State S) {
+  LANES(LP)
+  double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+  const bool o0 = lok_ && col_on(S, c0, k) && !S.halfconv[c0];
+  const bool o1 = lok_ && col_on(S, c0 + 1, k) && !S.halfconv[c0 + 1];
+  const double al0 = o0 ? S.alpha[c0] : 0.0, om0 = o0 ? S.omega[c0] : 0.0;
+  const double al1 = o1 ? S.alpha[c0 + 1] : 0.0, om1 = o1 ? S.omega[c0 + 1] : 0.0;
+  if (o0 || o1) {
+    ROW_LOOP {
+      const int64_t q = i * kp + c0;
+      const double2 x = ld2(V.x, q), ph = ld2(V.ph, q), sh = ld2(V.sh, q);
+      const double2 s = ld2(V.s, q), t = ld2(V.t, q), rh = ld2(V.rh, q);
+      st2(V.x, q, x.x + al0 * ph.x + om0 * sh.x, x.y + al1 * ph.y + om1 * sh.y, o0, o1);
+      const double r0 = s.x - om0 * t.x, r1 = s.y - om1 * t.y;
+      st2(V.r, q, r0, r1, o0, o1);
+      if (o0) { acc[0][0] += rh.x * r0; acc[1][0] += r0 * r0; }
+      if (o1) { acc[0][1] += rh.y * r1; acc[1][1] += r1 * r1; }
+    }
   }
-  block_partials<GK, 2>(acc, S);
+  block_partials<LP, 2>(acc, S);
 }
 
 // ---- full-step true residual; partials ||rt||^2, r_hat^T rt; r = rt -----------------
-template <int GK>
-__global__ void __launch_bounds__(NT) k_fullcheck(int64_t n, int k, Csr<double> A, Vec V, State S) {
+template <int LP>
+__global__ void __launch_bounds__(NT) k_fullcheck(int64_t n, int k, int kp, Csr<double> A, Vec V,
+                                                  State S) {
   if (S.any[1] == 0) return;
-  double acc[2] = {0.0, 0.0};
-  const int cc = threadIdx.x % GK;
-  const bool on = col_on(S, cc, k) && S.full[cc];
-  ROW_LOOP {
-    if (!on) break;
-    const int64_t q = i * k + c;
-    const double rt = V.rhs[q] - row_prod(A, i, V.x, k, c);
-    V.r[q] = rt;
-    acc[0] += rt * rt;
-    acc[1] += V.rh[q] * rt;
+  LANES(LP)
+  double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+  const bool o0 = lok_ && col_on(S, c0, k) && S.full[c0];
+  const bool o1 = lok_ && col_on(S, c0 + 1, k) && S.full[c0 + 1];
+  if (o0 || o1) {
+    ROW_LOOP {
+      double y0 = 0.0, y1 = 0.0;
+      for (int32_t e = A.rp[i]; e < A.rp[i + 1]; ++e) {
+        const double2 x = ld2(V.x, (int64_t)A.ci[e] * kp + c0);
+        y0 += A.v[e] * x.x;
+        y1 += A.v[e] * x.y;
+      }
+      const int64_t q = i * kp + c0;
+      const double2 b = ld2(V.b, q), rh = ld2(V.rh, q);
+      const double r0 = b.x - y0, r1 = b.y - y1;
+      st2(V.r, q, r0, r1, o0, o1);
+      if (o0) { acc[0][0] += r0 * r0; acc[1][0] += rh.x * r0; }
+      if (o1) { acc[0][1] += r1 * r1; acc[1][1] += rh.y * r1; }
+    }
   }
-  block_partials<GK, 2>(acc, S);
+  block_partials<LP, 2>(acc, S);
 }
 
 // ---- restart: r_hat = r, p = v = 0; partial r^T r ---------------------------------
-template <int GK>
-__global__ void __launch_bounds__(NT) k_restart(int64_t n, int k, Vec V, State S) {
+template <int LP>
+__global__ void __launch_bounds__(NT) k_restart(int64_t n, int k, int kp, Vec V, State S) {
   if (S.any[2] == 0) return;
-  double acc[1] = {0.0};
-  const int cc = threadIdx.x % GK;
-  const bool on = cc < k && S.rst[cc] && S.status[cc] == ST_ACTIVE;
-  ROW_LOOP {
-    if (!on) break;
-    const int64_t q = i * k + c;
-    const double rv = V.r[q];
-    V.rh[q] = rv;
-    V.p[q] = 0.0;
-    V.v[q] = 0.0;
-    acc[0] += rv * rv;
+  LANES(LP)
+  double acc[1][2] = {{0.0, 0.0}};
+  const bool o0 = lok_ && c0 < k && S.rst[c0] && S.status[c0] == ST_ACTIVE;
+  const bool o1 = lok_ && c0 + 1 < k && S.rst[c0 + 1] && S.status[c0 + 1] == ST_ACTIVE;
+  if (o0 || o1) {
+    ROW_LOOP {
+      const int64_t q = i * kp + c0;
+      const double2 r = ld2(V.r, q);
+      st2(V.rh, q, r.x, r.y, o0, o1);
+      st2(V.p, q, 0.0, 0.0, o0, o1);
+      st2(V.v, q, 0.0, 0.0, o0, o1);
+      if (o0) acc[0][0] += r.x * r.x;
+      if (o1) acc[0][1] += r.y * r.y;
+    }
   }
-  block_partials<GK, 1>(acc, S);
+  block_partials<LP, 1>(acc, S);
+}
+
+// ---- the solution block X (n x k, the caller's) from x (n x kp) -------------------
+template <int LP>
+__global__ void __launch_bounds__(NT) k_copy_out(int64_t n, int k, int kp, const double* __restrict__ x,
+                                                 double* __restrict__ X) {
+  LANES(LP)
+  if (!live) return;
+  ROW_LOOP {
+    const double2 v = ld2(x, i * kp + c0);
+    X[i * k + c0] = v.x;
+    if (c0 + 1 < k) X[i * k + c0 + 1] = v.y;
+  }
 }
 
 // ---- finishers: one block adds the partials and updates the column state -------
@@ -438,34 +474,40 @@ enum { F_INIT, F_AV, F_S, F_HALF, F_AT, F_XR, F_FULL, F_RESTART };
 
 constexpr int FNT = 1024;  // finisher threads
 
-template <int GK, int ND, int OP>
+template <int ND, int OP>
 __global__ void __launch_bounds__(FNT) k_fin(int k, State S, int nb) {
-  constexpr int RPB = FNT / GK;
   __shared__ double red[ND][FNT];
-  __shared__ double tot[ND][GK];
+  __shared__ double tot[ND][PSTRIDE];
   // a finisher whose main kernel returned early (flag not set) has nothing to do
   if (OP == F_HALF && S.any[0] == 0) return;
   if (OP == F_FULL && S.any[1] == 0) return;
   if (OP == F_RESTART && S.any[2] == 0) return;
+  // thread t sums the partials b = q, q + fq, ... of column c = t % k (fq
+  // threads per column, eight independent sums each); then the fq sums of a
+  // column are added in order of q
   const int t = threadIdx.x;
-  const int c = t % GK, q = t / GK;
+  const int fq = FNT / k;
+  const int c = t % k, q = t / k;
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
-    double s0 = 0.0, s1 = 0.0;
-    int b = q;
-    for (; b + RPB < nb; b += 2 * RPB) {
-      s0 += S.part[((int64_t)d * NBMAX + b) * GK + c];
-      s1 += S.part[((int64_t)d * NBMAX + b + RPB) * GK + c];
+    double s8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (q < fq) {
+      const double* P = S.part + (int64_t)d * NBMAX * PSTRIDE + c;
+      int b = q;
+      for (; b + 7 * fq < nb; b += 8 * fq) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s8[u] += P[(int64_t)(b + u * fq) * PSTRIDE];
+      }
+      for (; b < nb; b += fq) s8[0] += P[(int64_t)b * PSTRIDE];
     }
-    if (b < nb) s0 += S.part[((int64_t)d * NBMAX + b) * GK + c];
-    red[d][t] = s0 + s1;
+    red[d][t] = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
   }
   __syncthreads();
-  if (t < GK) {
+  if (t < k) {
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
       double s = 0.0;
-      for (int r = 0; r < RPB; ++r) s += red[d][r * GK + t];
+      for (int r = 0; r < fq; ++r) s += red[d][r * k + t];
       tot[d][t] = s;
     }
   }

@@ -3,12 +3,13 @@
 // an independent system; all k advance in lockstep so that every sparse
 // product streams the matrix once for all columns.
 //
-// Blocks are n x k row-major (the k values of a row are contiguous).  A group
-// of GK lanes (GK = next power of two >= k) handles one row; lane c owns
-// column c.  Dot products are fused into the kernels that produce their
-// operands; a one-block finisher adds the per-block partial sums in a fixed
-// order (so results are deterministic) and updates the scalar state of every
-// column (alpha, omega, rho, beta, convergence flags).
+// The caller's blocks are n x k row-major (the k values of a row are
+// contiguous); BiCGStab works on n x kp copies (kp = k rounded up to even) in
+// which a lane owns a pair of columns of one row.  Dot products are fused into
+// the kernels that produce their operands; a one-block finisher adds the
+// per-block partial sums in a fixed order (so results are deterministic) and
+// updates the scalar state of every column (alpha, omega, rho, beta,
+// convergence flags).
 //
 // BiCGStab follows van der Vorst's algorithm with r_hat = r_0.  Convergence
 // is declared on the true residual rhs - A~ x, computed whenever the recursive
@@ -20,8 +21,6 @@
 // GMRES(m) (used for the smallest workload) runs one workgroup per column for
 // the whole solve: modified Gram-Schmidt Arnoldi, Givens rotations, solution
 // update at the end of each cycle, convergence on the true residual.
-#include <type_traits>
-
 #include "sai_internal.hpp"
 
 #include "bicgstab_kernels.hpp"
@@ -29,21 +28,17 @@
 namespace sai {
 namespace {
 
-template <int GK, class TM>
-int bicgstab_gk(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, const double* R,
-                double* X, const double* thr, int maxit, int pin, const Allocator& al, hipStream_t st,
+template <int LP, class TM>
+int bicgstab_lp(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, const double* R,
+                double* X, const double* thr, int maxit, const Allocator& al, hipStream_t st,
                 int* iters, int* status) {
-  const size_t nk = (size_t)n * k;
-  DBuf<double> r(&al, nk), rh(&al, nk), p(&al, nk), v(&al, nk), s(&al, nk), ph(&al, nk),
-      sh(&al, nk), t(&al, nk);
-  // The FP32 preconditioner is applied to FP32 copies of p and s (products
-  // accumulate in FP64): halves the gathered bytes of its sparse product.
-  constexpr bool MF = sizeof(TM) == 4;
-  const bool f32in = MF && pin == SAI_PIN_MATCH;
-  DBuf<float> pf(&al, f32in ? nk : 0), sf(&al, f32in ? nk : 0);
+  const int kp = k + (k & 1);
+  const size_t nk = (size_t)n * kp;
+  DBuf<double> b(&al, nk), x(&al, nk), r(&al, nk), rh(&al, nk), p(&al, nk), v(&al, nk), s(&al, nk),
+      ph(&al, nk), sh(&al, nk), t(&al, nk);
   DBuf<double> sc(&al, 6 * 64);
   DBuf<int> si(&al, 9 * 64 + 8);
-  DBuf<double> part(&al, (size_t)2 * NBMAX * GK);
+  DBuf<double> part(&al, (size_t)2 * NBMAX * PSTRIDE);
   HIPC(hipMemsetAsync(si.p, 0, sizeof(int) * (9 * 64 + 8), st));
   HIPC(hipMemcpyAsync(sc.p + 5 * 64, thr, sizeof(double) * k, hipMemcpyHostToDevice, st));
   State S;
@@ -64,107 +59,130 @@ int bicgstab_gk(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, const 
   S.wasact = si.p + 512;
   S.any = si.p + 576;
   S.part = part.p;
-  Vec V{R, X, r.p, rh.p, p.p, v.p, s.p, ph.p, sh.p, t.p, pf.p, sf.p};
-  constexpr int RPB = NT / GK;
-  // streaming kernels: one row per lane group; sparse products: tiles of SUB*RPB rows
-  const int grid = (int)std::min<int64_t>(NBMAX, (n + RPB - 1) / RPB);
-  // Sparse products work on tiles of SUB*RPB rows; the grid is a multiple of the
-  // XCD count so that XCD-contiguous tile ranges can be used.
-  auto tiles_grid = [&](int sub) {
-    int g = (int)std::min<int64_t>(NBMAX, (n + sub * RPB - 1) / (sub * RPB));
-    return g >= 8 ? (g & ~7) : g;
+  Vec V{b.p, x.p, r.p, rh.p, p.p, v.p, s.p, ph.p, sh.p, t.p};
+  constexpr int RPB = (64 / LP) * (NT / 64);
+  // streaming kernels: a grid-stride loop over rows (fewer blocks also means
+  // fewer partial sums for the finishers to add)
+  const int grid = (int)std::min<int64_t>(tune_get("SGRID", 1024), (n + RPB - 1) / RPB);
+  // Sparse products work on tiles of RPB rows (one per lane).  Their grid is
+  // persistent: no more workgroups than fit on the device at once, so that the
+  // grid sweeps the rows in one pass; it is a multiple of the XCD count, and
+  // with XCD-contiguous tile ranges each XCD sweeps one contiguous eighth of
+  // the rows, keeping the band of gathered rows in its own L2.
+  const bool persist = tune_get("PERSIST", 1) != 0;
+  const int xmap = tune_get("XMAP", 1);
+  auto sp_grid = [&](const void* kern) {
+    const int64_t ntiles = (n + RPB - 1) / RPB;
+    int64_t g = std::min<int64_t>(NBMAX, ntiles);
+    if (persist) g = std::min<int64_t>(g, resident_blocks(kern, NT));
+    return (int)(g >= 8 ? (g & ~int64_t(7)) : g);
   };
-  const int xmap = tune_get("XMAP", 0);
-  // M product variant (rows per lane per tile, gathers batched per row, rows interleaved)
-  const int mvar = tune_get("SPMM_M", 3);
-  const int msub = (mvar == 1 || mvar == 2) ? 4 : (mvar == 3 ? 2 : 1);
-  const int mgrid = tiles_grid(msub);
-  auto spmm_m_t = [&](auto X, double* Y) {
-    using XT = std::remove_const_t<std::remove_pointer_t<decltype(X)>>;
+  // M product: gather batch sizes (CH while >= CH entries remain, then CH2)
+  const int mvar = tune_get("SPMM_M", 1);
+  auto spmm_m = [&](const double* Xin, double* Y) {
+    auto go = [&](auto kern) {
+      hipLaunchKernelGGL(kern, dim3(sp_grid((const void*)kern)), dim3(NT), 0, st, n, k, kp, M, Xin, Y,
+                         S, xmap);
+    };
     switch (mvar) {
-      case 1: hipLaunchKernelGGL((k_spmm<GK, TM, 8, 4, 4, XT>), dim3(mgrid), dim3(NT), 0, st, n, k, M, X, Y, S, xmap); break;
-      case 2: hipLaunchKernelGGL((k_spmm<GK, TM, 32, 2, 4, XT>), dim3(mgrid), dim3(NT), 0, st, n, k, M, X, Y, S, xmap); break;
-      case 3: hipLaunchKernelGGL((k_spmm<GK, TM, 16, 2, 2, XT>), dim3(mgrid), dim3(NT), 0, st, n, k, M, X, Y, S, xmap); break;
-      case 4: hipLaunchKernelGGL((k_spmm<GK, TM, 16, 1, 1, XT>), dim3(mgrid), dim3(NT), 0, st, n, k, M, X, Y, S, xmap); break;
-      case 5: hipLaunchKernelGGL((k_spmm<GK, TM, 32, 1, 1, XT>), dim3(mgrid), dim3(NT), 0, st, n, k, M, X, Y, S, xmap); break;
-      default: hipLaunchKernelGGL((k_spmm<GK, TM, 8, 1, 1, XT>), dim3(mgrid), dim3(NT), 0, st, n, k, M, X, Y, S, xmap); break;
+      case 0: go(k_spmm<LP, TM, 8, 4>); break;
+      case 2: go(k_spmm<LP, TM, 5, 0>); break;
+      case 3: go(k_spmm<LP, TM, 16, 8>); break;
+      default: go(k_spmm<LP, TM, 6, 3>); break;
     }
   };
-  auto spmm_m = [&](const double* X, const float* Xf, double* Y) {
-    if (f32in) spmm_m_t(Xf, Y);
-    else spmm_m_t(X, Y);
-  };
-  // A~ product variant: rows per lane per tile (all interleaved, 8 gathers per row batched)
+  // A~ products (with their dot products): gather batch sizes
   const int avar = tune_get("SPMM_A", 0);
-  const int asub = avar == 1 ? 1 : (avar == 2 ? 2 : 4);
-  const int tgrid = tiles_grid(asub);
+  const void* kav = avar == 1 ? (const void*)k_av<LP, 8, 4>
+                    : avar == 2 ? (const void*)k_av<LP, 7, 0> : (const void*)k_av<LP, 4, 2>;
+  const void* kat = avar == 1 ? (const void*)k_at<LP, 8, 4>
+                    : avar == 2 ? (const void*)k_at<LP, 7, 0> : (const void*)k_at<LP, 4, 2>;
+  const int tgrid = std::min(sp_grid(kav), sp_grid(kat));
   auto spmm_av = [&]() {
-    if (asub == 1) hipLaunchKernelGGL((k_av<GK, 1>), dim3(tgrid), dim3(NT), 0, st, n, k, A, V, S, xmap);
-    else if (asub == 2) hipLaunchKernelGGL((k_av<GK, 2>), dim3(tgrid), dim3(NT), 0, st, n, k, A, V, S, xmap);
-    else hipLaunchKernelGGL((k_av<GK, 4>), dim3(tgrid), dim3(NT), 0, st, n, k, A, V, S, xmap);
+    if (avar == 1) hipLaunchKernelGGL((k_av<LP, 8, 4>), dim3(tgrid), dim3(NT), 0, st, n, k, kp, A, V, S, xmap);
+    else if (avar == 2) hipLaunchKernelGGL((k_av<LP, 7, 0>), dim3(tgrid), dim3(NT), 0, st, n, k, kp, A, V, S, xmap);
+    else hipLaunchKernelGGL((k_av<LP, 4, 2>), dim3(tgrid), dim3(NT), 0, st, n, k, kp, A, V, S, xmap);
   };
   auto spmm_at = [&]() {
-    if (asub == 1) hipLaunchKernelGGL((k_at<GK, 1>), dim3(tgrid), dim3(NT), 0, st, n, k, A, V, S, xmap);
-    else if (asub == 2) hipLaunchKernelGGL((k_at<GK, 2>), dim3(tgrid), dim3(NT), 0, st, n, k, A, V, S, xmap);
-    else hipLaunchKernelGGL((k_at<GK, 4>), dim3(tgrid), dim3(NT), 0, st, n, k, A, V, S, xmap);
+    if (avar == 1) hipLaunchKernelGGL((k_at<LP, 8, 4>), dim3(tgrid), dim3(NT), 0, st, n, k, kp, A, V, S, xmap);
+    else if (avar == 2) hipLaunchKernelGGL((k_at<LP, 7, 0>), dim3(tgrid), dim3(NT), 0, st, n, k, kp, A, V, S, xmap);
+    else hipLaunchKernelGGL((k_at<LP, 4, 2>), dim3(tgrid), dim3(NT), 0, st, n, k, kp, A, V, S, xmap);
   };
-  HostStage hs(16);
   {
     SAI_PROF("bicg_init", st);
-    hipLaunchKernelGGL((k_init<GK>), dim3(grid), dim3(NT), 0, st, n, k, V, S);
-    hipLaunchKernelGGL((k_fin<GK, 1, F_INIT>), dim3(1), dim3(FNT), 0, st, k, S, grid);
+    hipLaunchKernelGGL((k_init<LP>), dim3(grid), dim3(NT), 0, st, n, k, kp, R, V, S);
+    hipLaunchKernelGGL((k_fin<1, F_INIT>), dim3(1), dim3(FNT), 0, st, k, S, grid);
   }
   LAUNCH_CHECK();
   hipLaunchKernelGGL(k_iter_end, dim3(1), dim3(64), 0, st, k, S, 0, maxit);
   LAUNCH_CHECK();
-  HIPC(hipMemcpyAsync(hs.p, S.any + 3, sizeof(int), hipMemcpyDeviceToHost, st));
-  HIPC(hipStreamSynchronize(st));
-  int active = *hs.as<int>();
-  for (int it = 1; it <= maxit && active > 0; ++it) {
+  // The active-column count of iteration it is read back while iteration it+1
+  // runs (two pinned slots, one event each), so the device never waits for the
+  // host.  An iteration queued after the last column stopped finds no active
+  // column and does no work.
+  HostStage hs(16);
+  int* slot = hs.as<int>();
+  hipEvent_t ev[2];
+  HIPC(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+  HIPC(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+  struct EvGuard {
+    hipEvent_t* e;
+    ~EvGuard() { (void)hipEventDestroy(e[0]); (void)hipEventDestroy(e[1]); }
+  } evg{ev};
+  HIPC(hipMemcpyAsync(slot, S.any + 3, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPC(hipEventRecord(ev[0], st));
+  HIPC(hipEventSynchronize(ev[0]));
+  bool go_on = slot[0] > 0;
+  for (int it = 1; it <= maxit && go_on; ++it) {
 #define LK(name, ...)              \
   do {                             \
     SAI_PROF(name, st);            \
     hipLaunchKernelGGL(__VA_ARGS__); \
   } while (0)
-    if (f32in) LK("bicg_p_update", (k_pupdate<GK, true>), dim3(grid), dim3(NT), 0, st, n, k, V, S);
-    else LK("bicg_p_update", (k_pupdate<GK, false>), dim3(grid), dim3(NT), 0, st, n, k, V, S);
+    constexpr bool MF = sizeof(TM) == 4;
+    LK("bicg_p_update", (k_pupdate<LP>), dim3(grid), dim3(NT), 0, st, n, k, kp, V, S);
     {
       SAI_PROF(MF ? "bicg_spmm_M_f32" : "bicg_spmm_M_f64", st);
-      spmm_m(V.p, V.pf, V.ph);
+      spmm_m(V.p, V.ph);
     }
     {
       SAI_PROF("bicg_spmm_A_dot1", st);
       spmm_av();
     }
-    LK("bicg_finish", (k_fin<GK, 1, F_AV>), dim3(1), dim3(FNT), 0, st, k, S, tgrid);
-    if (f32in) LK("bicg_s_update", (k_s<GK, true>), dim3(grid), dim3(NT), 0, st, n, k, V, S);
-    else LK("bicg_s_update", (k_s<GK, false>), dim3(grid), dim3(NT), 0, st, n, k, V, S);
-    LK("bicg_finish", (k_fin<GK, 1, F_S>), dim3(1), dim3(FNT), 0, st, k, S, grid);
-    LK("bicg_halfcheck", (k_halfcheck<GK>), dim3(grid), dim3(NT), 0, st, n, k, A, V, S);
-    LK("bicg_finish", (k_fin<GK, 1, F_HALF>), dim3(1), dim3(FNT), 0, st, k, S, grid);
-    LK("bicg_halfapply", (k_halfapply<GK>), dim3(grid), dim3(NT), 0, st, n, k, V, S);
+    LK("bicg_finish", (k_fin<1, F_AV>), dim3(1), dim3(FNT), 0, st, k, S, tgrid);
+    LK("bicg_s_update", (k_s<LP>), dim3(grid), dim3(NT), 0, st, n, k, kp, V, S);
+    LK("bicg_finish", (k_fin<1, F_S>), dim3(1), dim3(FNT), 0, st, k, S, grid);
+    LK("bicg_halfcheck", (k_halfcheck<LP>), dim3(grid), dim3(NT), 0, st, n, k, kp, A, V, S);
+    LK("bicg_finish", (k_fin<1, F_HALF>), dim3(1), dim3(FNT), 0, st, k, S, grid);
+    LK("bicg_halfapply", (k_halfapply<LP>), dim3(grid), dim3(NT), 0, st, n, k, kp, V, S);
     {
       SAI_PROF(MF ? "bicg_spmm_M_f32" : "bicg_spmm_M_f64", st);
-      spmm_m(V.s, V.sf, V.sh);
+      spmm_m(V.s, V.sh);
     }
     {
       SAI_PROF("bicg_spmm_A_dot2", st);
       spmm_at();
     }
-    LK("bicg_finish", (k_fin<GK, 2, F_AT>), dim3(1), dim3(FNT), 0, st, k, S, tgrid);
-    LK("bicg_xr_update", (k_xr<GK>), dim3(grid), dim3(NT), 0, st, n, k, V, S);
-    LK("bicg_finish", (k_fin<GK, 2, F_XR>), dim3(1), dim3(FNT), 0, st, k, S, grid);
-    LK("bicg_fullcheck", (k_fullcheck<GK>), dim3(grid), dim3(NT), 0, st, n, k, A, V, S);
-    LK("bicg_finish", (k_fin<GK, 2, F_FULL>), dim3(1), dim3(FNT), 0, st, k, S, grid);
-    LK("bicg_restart", (k_restart<GK>), dim3(grid), dim3(NT), 0, st, n, k, V, S);
-    LK("bicg_finish", (k_fin<GK, 1, F_RESTART>), dim3(1), dim3(FNT), 0, st, k, S, grid);
+    LK("bicg_finish", (k_fin<2, F_AT>), dim3(1), dim3(FNT), 0, st, k, S, tgrid);
+    LK("bicg_xr_update", (k_xr<LP>), dim3(grid), dim3(NT), 0, st, n, k, kp, V, S);
+    LK("bicg_finish", (k_fin<2, F_XR>), dim3(1), dim3(FNT), 0, st, k, S, grid);
+    LK("bicg_fullcheck", (k_fullcheck<LP>), dim3(grid), dim3(NT), 0, st, n, k, kp, A, V, S);
+    LK("bicg_finish", (k_fin<2, F_FULL>), dim3(1), dim3(FNT), 0, st, k, S, grid);
+    LK("bicg_restart", (k_restart<LP>), dim3(grid), dim3(NT), 0, st, n, k, kp, V, S);
+    LK("bicg_finish", (k_fin<1, F_RESTART>), dim3(1), dim3(FNT), 0, st, k, S, grid);
     LK("bicg_iter_end", k_iter_end, dim3(1), dim3(64), 0, st, k, S, it, maxit);
 #undef LK
     LAUNCH_CHECK();
-    HIPC(hipMemcpyAsync(hs.p, S.any + 3, sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPC(hipStreamSynchronize(st));
-    active = *hs.as<int>();
+    HIPC(hipMemcpyAsync(slot + (it & 1), S.any + 3, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPC(hipEventRecord(ev[it & 1], st));
+    if (it > 1) {
+      // count after iteration it-1 (iteration it is already queued behind it)
+      HIPC(hipEventSynchronize(ev[(it - 1) & 1]));
+      go_on = slot[(it - 1) & 1] > 0;
+    }
   }
+  hipLaunchKernelGGL((k_copy_out<LP>), dim3(grid), dim3(NT), 0, st, n, k, kp, V.x, X);
+  LAUNCH_CHECK();
   std::vector<int> hst(k), hit(k);
   HIPC(hipMemcpyAsync(hst.data(), S.status, sizeof(int) * k, hipMemcpyDeviceToHost, st));
   HIPC(hipMemcpyAsync(hit.data(), S.iters, sizeof(int) * k, hipMemcpyDeviceToHost, st));
@@ -369,11 +387,16 @@ int krylov_typed(const sai_split_s* sp, const sai_precond_s* pc, int transpose, 
   const int64_t n = sp->n;
   if (o.method == SAI_GMRES)
     return gmres_run<TM>(A, M, n, k, R, X, thr, o.restart, o.maxit, al, st, iters, status);
-  if (k <= 4) return bicgstab_gk<4, TM>(A, M, n, k, R, X, thr, o.maxit, o.precond_input, al, st, iters, status);
-  if (k <= 8) return bicgstab_gk<8, TM>(A, M, n, k, R, X, thr, o.maxit, o.precond_input, al, st, iters, status);
-  if (k <= 16) return bicgstab_gk<16, TM>(A, M, n, k, R, X, thr, o.maxit, o.precond_input, al, st, iters, status);
-  if (k <= 32) return bicgstab_gk<32, TM>(A, M, n, k, R, X, thr, o.maxit, o.precond_input, al, st, iters, status);
-  return bicgstab_gk<64, TM>(A, M, n, k, R, X, thr, o.maxit, o.precond_input, al, st, iters, status);
+  // lanes per row: the smallest of 1, 2, 4, 6, 8, 12, 16, 32 covering the pairs
+  const int pairs = (k + 1) / 2;
+  if (pairs <= 1) return bicgstab_lp<1, TM>(A, M, n, k, R, X, thr, o.maxit, al, st, iters, status);
+  if (pairs <= 2) return bicgstab_lp<2, TM>(A, M, n, k, R, X, thr, o.maxit, al, st, iters, status);
+  if (pairs <= 4) return bicgstab_lp<4, TM>(A, M, n, k, R, X, thr, o.maxit, al, st, iters, status);
+  if (pairs <= 6) return bicgstab_lp<6, TM>(A, M, n, k, R, X, thr, o.maxit, al, st, iters, status);
+  if (pairs <= 8) return bicgstab_lp<8, TM>(A, M, n, k, R, X, thr, o.maxit, al, st, iters, status);
+  if (pairs <= 12) return bicgstab_lp<12, TM>(A, M, n, k, R, X, thr, o.maxit, al, st, iters, status);
+  if (pairs <= 16) return bicgstab_lp<16, TM>(A, M, n, k, R, X, thr, o.maxit, al, st, iters, status);
+  return bicgstab_lp<32, TM>(A, M, n, k, R, X, thr, o.maxit, al, st, iters, status);
 }
 
 }  // namespace
@@ -384,8 +407,6 @@ int krylov_impl(const sai_split_s* sp, const sai_precond_s* pc, int transpose, i
   if (k < 1 || k > 64) SAI_THROW(SAI_EINVAL, "k must be in [1, 64] (got %d)", k);
   if (o.method != SAI_BICGSTAB && o.method != SAI_GMRES) SAI_THROW(SAI_EINVAL, "bad method");
   if (o.maxit < 0) SAI_THROW(SAI_EINVAL, "maxit < 0");
-  if (o.precond_input != SAI_PIN_MATCH && o.precond_input != SAI_PIN_FP64)
-    SAI_THROW(SAI_EINVAL, "bad precond_input");
   if (pc->n != sp->n) SAI_THROW(SAI_EINVAL, "preconditioner and split sizes differ");
   if (pc->precision == SAI_FP32)
     return krylov_typed<float>(sp, pc, transpose, k, R, X, thr, o, st, iters, status);

@@ -224,6 +224,10 @@ T read_scalar(const T* dev, hipStream_t st) {
 // environment variable SAI_TUNE_<name> if set, else `dflt`.
 int tune_get(const char* name, int dflt);
 
+// Workgroups of `kernel` (nt threads, no dynamic LDS) resident on the current
+// device at once (occupancy per CU times the CU count); cached per device.
+int resident_blocks(const void* kernel, int nt);
+
 void fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st);
 void fill_f64(double* p, double v, int64_t n, hipStream_t st);
 void zero_bytes(void* p, size_t bytes, hipStream_t st);

@@ -1,4 +1,8 @@
 // Device-wide scans, fills, deterministic norms and a small dense LU solver.
+#include <algorithm>
+#include <map>
+#include <mutex>
+
 #include "sai_internal.hpp"
 
 namespace sai {
@@ -218,6 +222,22 @@ int tune_get(const char* name, int dflt) {
   snprintf(key, sizeof(key), "SAI_TUNE_%s", name);
   const char* v = getenv(key);
   return (v && *v) ? atoi(v) : dflt;
+}
+
+int resident_blocks(const void* kernel, int nt) {
+  static std::mutex mu;
+  static std::map<std::pair<int, const void*>, int> cache;
+  int dev = 0;
+  HIPC(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find({dev, kernel});
+  if (it != cache.end()) return it->second;
+  int cus = 0, per_cu = 0;
+  HIPC(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  HIPC(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, nt, 0));
+  const int r = std::max(1, cus * per_cu);
+  cache[{dev, kernel}] = r;
+  return r;
 }
 
 void fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st) {
