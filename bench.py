@@ -27,6 +27,35 @@ import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
+
+# sources of the Krylov kernels: a stored counter measurement is used only while
+# they hash to what was measured
+KRYLOV_SOURCES = ("paper_1211_6866_amd/csrc/bicgstab_kernels.hpp", "paper_1211_6866_amd/csrc/krylov.hip")
+
+
+def counted_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from a committed rocprofv3
+    counter summary (profiles/counters_*.md, its json block), or None when there is
+    none or the kernel sources changed since it was taken."""
+    import glob
+    import hashlib
+    import re
+    h = hashlib.sha256()
+    for rel in KRYLOV_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    digest = h.hexdigest()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "counters_*.md"))):
+        with open(path) as f:
+            m = re.search(r"```json\n(.*?)\n```", f.read(), re.S)
+        if not m:
+            continue
+        info = json.loads(m.group(1))
+        if (info.get("kernel") == kernel and info.get("workload") == workload
+                and info.get("source_sha256") == digest):
+            info["file"] = os.path.relpath(path, ROOT)
+            return info
+    return None
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
@@ -259,6 +288,11 @@ def main():
     roof["kernel"] = dom
     roof["avg_launch_ms"] = round(avg_ms, 4)
     roof["launches_per_step"] = dom_launches / args.steps
+    counted = counted_traffic(dom, name)
+    if counted is not None:
+        roof["traffic"] = counted["traffic_bytes_per_launch"]
+        roof["traffic_unit"] = "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
+        roof["traffic_source"] = counted["file"]
 
     kern_table = {nm: dict(launches=l, total_ms=round(t, 3), avg_ms=round(t / l, 4))
                   for t, nm, l in sorted(((tot, nm, l) for nm, (l, tot) in prof_all.items()),

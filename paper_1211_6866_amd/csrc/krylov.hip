@@ -66,11 +66,14 @@ int bicgstab_lp(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, const 
   const int grid = (int)std::min<int64_t>(tune_get("SGRID", 1024), (n + RPB - 1) / RPB);
   // Sparse products work on tiles of RPB rows (one per lane).  Their grid is
   // persistent: no more workgroups than fit on the device at once, so that the
-  // grid sweeps the rows in one pass; it is a multiple of the XCD count, and
-  // with XCD-contiguous tile ranges each XCD sweeps one contiguous eighth of
-  // the rows, keeping the band of gathered rows in its own L2.
+  // grid sweeps the rows in one pass; it is a multiple of the XCD count.  When
+  // an n x kp block fits in the 256 MB last-level (MALL) cache, XCD-contiguous
+  // tile ranges let each XCD sweep one contiguous eighth of the rows and keep
+  // its band of gathered rows in its own L2; larger blocks are swept by all
+  // XCDs together (interleaved tiles), so that one band, not eight, must stay
+  // resident in the MALL.
   const bool persist = tune_get("PERSIST", 1) != 0;
-  const int xmap = tune_get("XMAP", 1);
+  const int xmap = tune_get("XMAP", nk * sizeof(double) <= (size_t(256) << 20) ? 1 : 0);
   auto sp_grid = [&](const void* kern) {
     const int64_t ntiles = (n + RPB - 1) / RPB;
     int64_t g = std::min<int64_t>(NBMAX, ntiles);
