@@ -30,20 +30,49 @@ namespace {
 
 constexpr int NT = 256;
 
-__global__ void k_stats(int32_t n, const int32_t* cntJ, const int32_t* cntI, const double* res,
-                        double delta, int* out /* maxI, maxJ, n_c */) {
-  const int64_t k = (int64_t)blockIdx.x * NT + threadIdx.x;
-  if (k >= n) return;
-  atomicMax(&out[0], cntI[k]);
-  atomicMax(&out[1], cntJ[k]);
-  if (res && res[k] > delta) atomicAdd(&out[2], 1);
+// max |I_k|, max |J_k| and (stats) the number of columns with residual > delta;
+// reduced per wavefront first, then one atomic per wavefront
+__device__ __forceinline__ int wmax_i(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ int wsum_i(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
 }
 
-__global__ void k_maxI(int32_t n, const int32_t* cntJ, const int32_t* cntI, int* out) {
-  const int64_t k = (int64_t)blockIdx.x * NT + threadIdx.x;
-  if (k >= n) return;
-  atomicMax(&out[0], cntI[k]);
-  atomicMax(&out[1], cntJ[k]);
+__global__ void __launch_bounds__(NT) k_stats(int32_t n, const int32_t* cntJ, const int32_t* cntI,
+                                              const double* res, double delta,
+                                              int* out /* maxI, maxJ, n_c */) {
+  int mi = 0, mj = 0, nc = 0;
+  for (int64_t k = (int64_t)blockIdx.x * NT + threadIdx.x; k < n; k += (int64_t)gridDim.x * NT) {
+    mi = max(mi, cntI[k]);
+    mj = max(mj, cntJ[k]);
+    if (res && res[k] > delta) ++nc;
+  }
+  __shared__ int red[3][NT / 64];
+  mi = wmax_i(mi);
+  mj = wmax_i(mj);
+  nc = wsum_i(nc);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[0][w] = mi;
+    red[1][w] = mj;
+    red[2][w] = nc;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < NT / 64; ++q) {
+      mi = max(mi, red[0][q]);
+      mj = max(mj, red[1][q]);
+      nc += red[2][q];
+    }
+    atomicMax(&out[0], mi);
+    atomicMax(&out[1], mj);
+    if (nc) atomicAdd(&out[2], nc);
+  }
 }
 
 // ||A~||_1 = max_j sum_i |a_ij|; stored as the bit pattern of a non-negative double,
@@ -56,56 +85,53 @@ __global__ void k_norm1(int32_t n, const int32_t* cp, const double* cv, unsigned
   atomicMax(out, (unsigned long long)__double_as_longlong(s));
 }
 
-template <class T>
-__global__ void k_drop_count(int32_t n, const int64_t* __restrict__ jptr, const T* __restrict__ m,
-                             int mode, double tau, double delta, double norm1,
-                             int32_t* __restrict__ cnt) {
-  const int64_t k = (int64_t)blockIdx.x * NT + threadIdx.x;
-  if (k >= n) return;
-  const int64_t a = jptr[k], b = jptr[k + 1];
+// Dropping (Section 2.2): entries of the computed column m_k with |m_jk| <= thr
+// are removed (thr = tau, or (tolk) delta / (|J_k| ||A~||_1)); the entry of
+// largest magnitude (the first of equals) is always kept.  32 lanes per column
+// (two columns per wavefront) read the column coalesced; the kept entries keep
+// their order (ballot prefix counts).  COUNT: number kept per column; else the
+// kept (row, value) pairs are written from colp[k] on.
+template <class T, bool COUNT>
+__global__ void __launch_bounds__(NT) k_drop(int32_t n, const int64_t* __restrict__ jptr,
+                                             const int32_t* __restrict__ jidx, const T* __restrict__ m,
+                                             int mode, double tau, double delta, double norm1,
+                                             int32_t* __restrict__ cnt, const int32_t* __restrict__ colp,
+                                             int32_t* __restrict__ rowi, T* __restrict__ cval) {
+  constexpr int G = 32;
+  const int lane = threadIdx.x & 63, gi = lane & (G - 1), half = lane & G;
+  const int64_t k = ((int64_t)blockIdx.x * NT + threadIdx.x) / G;
+  const bool valid = k < n;
+  const int64_t a = valid ? jptr[k] : 0, b = valid ? jptr[k + 1] : 0;
   const int nj = (int)(b - a);
   double thr = -1.0;
   if (mode == SAI_DROP_ABS) thr = tau;
   else if (mode == SAI_DROP_TOLK) thr = delta / ((double)nj * norm1);
-  int64_t amax = a;
+  // largest magnitude, first index among equals
   double vmax = -1.0;
-  for (int64_t e = a; e < b; ++e) {
+  int64_t amax = INT64_MAX;
+  for (int64_t e = a + gi; e < b; e += G) {
     const double v = fabs((double)m[e]);
     if (v > vmax) { vmax = v; amax = e; }
   }
-  int c = 0;
-  for (int64_t e = a; e < b; ++e)
-    if (fabs((double)m[e]) > thr || e == amax) ++c;
-  cnt[k] = c;
-}
-
-template <class T>
-__global__ void k_drop_scatter(int32_t n, const int64_t* __restrict__ jptr,
-                               const int32_t* __restrict__ jidx, const T* __restrict__ m, int mode,
-                               double tau, double delta, double norm1,
-                               const int32_t* __restrict__ colp, int32_t* __restrict__ rowi,
-                               T* __restrict__ cval) {
-  const int64_t k = (int64_t)blockIdx.x * NT + threadIdx.x;
-  if (k >= n) return;
-  const int64_t a = jptr[k], b = jptr[k + 1];
-  const int nj = (int)(b - a);
-  double thr = -1.0;
-  if (mode == SAI_DROP_ABS) thr = tau;
-  else if (mode == SAI_DROP_TOLK) thr = delta / ((double)nj * norm1);
-  int64_t amax = a;
-  double vmax = -1.0;
-  for (int64_t e = a; e < b; ++e) {
-    const double v = fabs((double)m[e]);
-    if (v > vmax) { vmax = v; amax = e; }
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) {
+    const double ov = __shfl_xor(vmax, o, 64);
+    const int64_t oa = __shfl_xor(amax, o, 64);
+    if (ov > vmax || (ov == vmax && oa < amax)) { vmax = ov; amax = oa; }
   }
-  int32_t o = colp[k];
-  for (int64_t e = a; e < b; ++e) {
-    if (fabs((double)m[e]) > thr || e == amax) {
-      rowi[o] = jidx[e];
-      cval[o] = m[e];
-      ++o;
+  int32_t o = COUNT ? 0 : (valid ? colp[k] : 0);
+  for (int64_t off = 0; __any(off < nj); off += G) {
+    const int64_t e = a + off + gi;
+    const bool kf = e < b && (fabs((double)m[e]) > thr || e == amax);
+    const uint32_t gm = (uint32_t)(__ballot(kf) >> half);
+    if (!COUNT && kf) {
+      const int32_t q = o + __popc(gm & ((1u << gi) - 1u));
+      rowi[q] = jidx[e];
+      cval[q] = m[e];
     }
+    o += __popc(gm);
   }
+  if (COUNT && valid && gi == 0) cnt[k] = o;
 }
 
 template <class T>
@@ -128,7 +154,8 @@ void build_typed(const sai_split_s* sp, const sai_build_opts& o, hipStream_t st,
   HIPC(hipMemcpyAsync(&tot[1], iptr.p + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   DBuf<int> mx(&al, 4);
   HIPC(hipMemsetAsync(mx.p, 0, 4 * sizeof(int), st));
-  hipLaunchKernelGGL(k_maxI, dim3(grid_for(n, NT)), dim3(NT), 0, st, n, cntJ.p, cntI.p, mx.p);
+  hipLaunchKernelGGL(k_stats, dim3(grid_for(n, NT, 256)), dim3(NT), 0, st, n, cntJ.p, cntI.p, nullptr, 0.0,
+                     mx.p);
   LAUNCH_CHECK();
   int hmx[4];
   HIPC(hipMemcpyAsync(hmx, mx.p, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -157,8 +184,9 @@ void build_typed(const sai_split_s* sp, const sai_build_opts& o, hipStream_t st,
     memcpy(&norm1, &bits, sizeof(double));
   }
   DBuf<int32_t> ccnt(&al, (size_t)n + 1);
-  hipLaunchKernelGGL((k_drop_count<T>), dim3(grid_for(n, NT)), dim3(NT), 0, st, n, jptr.p, mfull.p,
-                     o.drop, o.tau, o.delta, norm1, ccnt.p);
+  const unsigned dgrid = grid_for((int64_t)n * 32, NT);
+  hipLaunchKernelGGL((k_drop<T, true>), dim3(dgrid), dim3(NT), 0, st, n, jptr.p, jidx.p, mfull.p, o.drop,
+                     o.tau, o.delta, norm1, ccnt.p, nullptr, nullptr, nullptr);
   LAUNCH_CHECK();
   pc->col_ptr.alloc(&al, (size_t)n + 1);
   exclusive_scan_i32(ccnt.p, pc->col_ptr.p, n, al, st);
@@ -166,9 +194,8 @@ void build_typed(const sai_split_s* sp, const sai_build_opts& o, hipStream_t st,
   pc->nnz = nnz;
   pc->row_idx.alloc(&al, (size_t)nnz + 1);
   pc->cval.alloc(&al, ((size_t)nnz + 1) * sizeof(T));
-  hipLaunchKernelGGL((k_drop_scatter<T>), dim3(grid_for(n, NT)), dim3(NT), 0, st, n, jptr.p, jidx.p,
-                     mfull.p, o.drop, o.tau, o.delta, norm1, pc->col_ptr.p, pc->row_idx.p,
-                     (T*)pc->cval.p);
+  hipLaunchKernelGGL((k_drop<T, false>), dim3(dgrid), dim3(NT), 0, st, n, jptr.p, jidx.p, mfull.p, o.drop,
+                     o.tau, o.delta, norm1, nullptr, pc->col_ptr.p, pc->row_idx.p, (T*)pc->cval.p);
   LAUNCH_CHECK();
   pc->row_ptr.alloc(&al, (size_t)n + 1);
   pc->col_idx.alloc(&al, (size_t)nnz + 1);
@@ -181,7 +208,7 @@ void build_typed(const sai_split_s* sp, const sai_build_opts& o, hipStream_t st,
   if (stats) {
     DBuf<int> so(&al, 4);
     HIPC(hipMemsetAsync(so.p, 0, 4 * sizeof(int), st));
-    hipLaunchKernelGGL(k_stats, dim3(grid_for(n, NT)), dim3(NT), 0, st, n, cntJ.p, cntI.p, res.p,
+    hipLaunchKernelGGL(k_stats, dim3(grid_for(n, NT, 256)), dim3(NT), 0, st, n, cntJ.p, cntI.p, res.p,
                        o.delta, so.p);
     LAUNCH_CHECK();
     int hs[4];

@@ -397,29 +397,40 @@ struct VariantTable<double> {
                                    {BIG_MAXI, BIG_MAXJ}};
 };
 
-__global__ void k_bucket_assign(int32_t n, const int32_t* __restrict__ cntJ,
-                                const int32_t* __restrict__ cntI, int nv, const int* __restrict__ vmaxI,
-                                const int* __restrict__ vmaxJ, int32_t* __restrict__ bucket,
-                                int* __restrict__ bcount) {
-  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  int key = -1;
-  if (k < n) {
+constexpr int BK_NT = 1024;
+constexpr int BK_MAXV = 16;  // variants + 1 (the "too big" key)
+
+__global__ void __launch_bounds__(BK_NT) k_bucket_assign(int32_t n, const int32_t* __restrict__ cntJ,
+                                                         const int32_t* __restrict__ cntI, int nv,
+                                                         const int* __restrict__ vmaxI,
+                                                         const int* __restrict__ vmaxJ,
+                                                         int32_t* __restrict__ bucket,
+                                                         int* __restrict__ bcount) {
+  __shared__ int lcnt[BK_MAXV];
+  if (threadIdx.x < BK_MAXV) lcnt[threadIdx.x] = 0;
+  __syncthreads();
+  for (int64_t k = (int64_t)blockIdx.x * BK_NT + threadIdx.x; k < n; k += (int64_t)gridDim.x * BK_NT) {
     int b = -1;
     for (int v = 0; v < nv; ++v)
       if (cntI[k] <= vmaxI[v] && cntJ[k] <= vmaxJ[v]) { b = v; break; }
     bucket[k] = b;
-    key = b < 0 ? nv : b;
+    atomicAdd(&lcnt[b < 0 ? nv : b], 1);
   }
-  (void)agg_slot(bcount, key);
+  __syncthreads();
+  if (threadIdx.x <= nv && lcnt[threadIdx.x] > 0) atomicAdd(&bcount[threadIdx.x], lcnt[threadIdx.x]);
 }
 
-__global__ void k_bucket_scatter(int32_t n, const int32_t* __restrict__ bucket,
-                                 const int64_t* __restrict__ boff, int* __restrict__ bcur,
-                                 int32_t* __restrict__ lists) {
-  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int b = k < n ? bucket[k] : -1;
-  const int slot = agg_slot(bcur, b);
-  if (b >= 0) lists[boff[b] + slot] = (int32_t)k;
+__global__ void __launch_bounds__(BK_NT) k_bucket_scatter(int32_t n, const int32_t* __restrict__ bucket,
+                                                          const int64_t* __restrict__ boff,
+                                                          int* __restrict__ bcur,
+                                                          int32_t* __restrict__ lists) {
+  // every thread of the block runs the same number of iterations (block_slot syncs)
+  for (int64_t k0 = (int64_t)blockIdx.x * BK_NT; k0 < n; k0 += (int64_t)gridDim.x * BK_NT) {
+    const int64_t k = k0 + threadIdx.x;
+    const int b = k < n ? bucket[k] : -1;
+    const int slot = block_slot<BK_MAXV>(bcur, b);
+    if (b >= 0) lists[boff[b] + slot] = (int32_t)k;
+  }
 }
 
 template <class T, int G, int R, int JMAX>
@@ -497,7 +508,8 @@ int solve_columns(const sai_split_s* sp, const int64_t* jptr, const int32_t* jid
   HIPC(hipMemsetAsync(bcount.p, 0, sizeof(int) * (NV + 1), st));
   HIPC(hipMemsetAsync(bcur.p, 0, sizeof(int) * (NV + 1), st));
   HIPC(hipMemsetAsync(nsing.p, 0, sizeof(int), st));
-  hipLaunchKernelGGL(k_bucket_assign, dim3(grid_for(n, 256)), dim3(256), 0, st, n, cntJ, cntI, NV,
+  static_assert(NV + 1 <= BK_MAXV, "bucket keys");
+  hipLaunchKernelGGL(k_bucket_assign, dim3(grid_for(n, BK_NT, 512)), dim3(BK_NT), 0, st, n, cntJ, cntI, NV,
                      vmax.p, vmax.p + NV, bucket.p, bcount.p);
   LAUNCH_CHECK();
   int hc[NV + 1];
@@ -511,8 +523,8 @@ int solve_columns(const sai_split_s* sp, const int64_t* jptr, const int32_t* jid
   DBuf<int64_t> boff(&al, NV + 1);
   DBuf<int32_t> lists(&al, (size_t)n + 1);
   HIPC(hipMemcpyAsync(boff.p, hoff, sizeof(int64_t) * (NV + 1), hipMemcpyHostToDevice, st));
-  hipLaunchKernelGGL(k_bucket_scatter, dim3(grid_for(n, 256)), dim3(256), 0, st, n, bucket.p, boff.p,
-                     bcur.p, lists.p);
+  hipLaunchKernelGGL(k_bucket_scatter, dim3(grid_for(n, BK_NT, 512)), dim3(BK_NT), 0, st, n, bucket.p,
+                     boff.p, bcur.p, lists.p);
   LAUNCH_CHECK();
   for (int v = 0; v < NV; ++v) {
     if (bucket_cols && v < 8) bucket_cols[v] = hc[v];

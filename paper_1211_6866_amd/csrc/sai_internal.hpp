@@ -193,6 +193,24 @@ __device__ __forceinline__ int agg_slot(int* counter, int key) {
   return slot;
 }
 
+// Block-aggregated slot allocation: every thread of the block calls it with a
+// key in [0, NK) or -1; returns a distinct slot per key (global counter
+// gcounter[key] advanced once per key per block; LDS atomics inside the
+// block).  Order of the slots within a key is unspecified.
+template <int NK>
+__device__ __forceinline__ int block_slot(int* gcounter, int key) {
+  __shared__ int lcnt[NK], lbase[NK];
+  if (threadIdx.x < NK) lcnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int local = key >= 0 ? atomicAdd(&lcnt[key], 1) : -1;
+  __syncthreads();
+  if (threadIdx.x < NK && lcnt[threadIdx.x] > 0) lbase[threadIdx.x] = atomicAdd(&gcounter[threadIdx.x], lcnt[threadIdx.x]);
+  __syncthreads();
+  const int slot = key >= 0 ? lbase[key] + local : -1;
+  __syncthreads();
+  return slot;
+}
+
 inline unsigned grid_for(int64_t work, int per_block, unsigned cap = 1u << 30) {
   int64_t g = (work + per_block - 1) / per_block;
   if (g < 1) g = 1;

@@ -15,25 +15,83 @@ constexpr int NT = 256;
 
 enum { ERR_PTR = 1, ERR_COL = 2, ERR_ORDER = 4, ERR_VAL = 8, ERR_ZERODIAG = 16 };
 
-__global__ void k_validate_count(int32_t n, int64_t nnz, const int32_t* __restrict__ row_ptr,
-                                 const int32_t* __restrict__ col, const double* __restrict__ val,
-                                 int32_t* __restrict__ colcnt, int* __restrict__ err) {
-  const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
-  if (i == 0 && (row_ptr[0] != 0 || (int64_t)row_ptr[n] != nnz)) atomicOr(err, ERR_PTR);
-  if (i >= n) return;
-  const int32_t a = row_ptr[i], b = row_ptr[i + 1];
-  if (b < a || a < 0 || (int64_t)b > nnz) { atomicOr(err, ERR_PTR); return; }
-  int32_t prev = -1;
-  int e_local = 0;
-  for (int32_t e = a; e < b; ++e) {
-    const int32_t j = col[e];
-    if (j < 0 || j >= n) { e_local |= ERR_COL; continue; }
-    if (j <= prev) e_local |= ERR_ORDER;
-    prev = j;
-    if (!isfinite(val[e])) e_local |= ERR_VAL;
-    atomicAdd(&colcnt[j], 1);
+// Wave-cooperative traversal of a CSR block: the wavefront owns rows r0 ..
+// r0+63 and walks their entries (contiguous in memory) 64 at a time, so that
+// the reads of the entries are coalesced; the row of entry e is found by a
+// binary search over the 64 row starts held one per lane.
+struct WaveRows {
+  int64_t r0;
+  int32_t myrp;  // start of row r0 + lane (the end of the block for lanes past n)
+  int32_t e0, e1;
+  __device__ WaveRows(int32_t n, const int32_t* __restrict__ rp, int64_t r0_) : r0(r0_) {
+    const int lane = threadIdx.x & 63;
+    const int64_t r = r0 + lane;
+    const int64_t rend = min<int64_t>(r0 + 64, n);
+    myrp = rp[min<int64_t>(r, rend)];
+    e0 = __shfl(myrp, 0, 64);
+    e1 = rp[rend];
   }
-  if (e_local) atomicOr(err, e_local);
+  // tile-relative row (0..63) of entry e, e0 <= e < e1; every lane must call it
+  __device__ int row_of(int32_t e) const {
+    int lo = 0;
+#pragma unroll
+    for (int step = 32; step >= 1; step >>= 1) {
+      const int cand = lo + step;
+      const int32_t v = __shfl(myrp, cand & 63, 64);
+      if (cand < 64 && v <= e) lo = cand;
+    }
+    return lo;
+  }
+};
+
+// wavefronts of a 256-thread block, one 64-row block of rows each (grid-stride)
+#define WAVE_ROW_BLOCKS(n)                                                                   \
+  for (int64_t r0_ = ((int64_t)blockIdx.x * (NT / 64) + (threadIdx.x >> 6)) * 64; r0_ < (n); \
+       r0_ += (int64_t)gridDim.x * NT)
+
+
+// Checks the CSR input (row pointers monotone within [0, nnz], column indices
+// in range and strictly increasing within a row, finite values) and counts
+// the entries of every column.  A block of 64 rows whose row pointers are bad
+// is flagged and not read further.
+__global__ void __launch_bounds__(NT) k_validate_count(int32_t n, int64_t nnz,
+                                                       const int32_t* __restrict__ row_ptr,
+                                                       const int32_t* __restrict__ col,
+                                                       const double* __restrict__ val,
+                                                       int32_t* __restrict__ colcnt, int* __restrict__ err) {
+  const int lane = threadIdx.x & 63;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && (row_ptr[0] != 0 || (int64_t)row_ptr[n] != nnz))
+    atomicOr(err, ERR_PTR);
+  WAVE_ROW_BLOCKS(n) {
+    const int64_t r = r0_ + lane;
+    bool bad = false;
+    if (r < n) {
+      const int32_t a = row_ptr[r], b = row_ptr[r + 1];
+      bad = b < a || a < 0 || (int64_t)b > nnz;
+    }
+    if (__any(bad)) {
+      if (lane == 0) atomicOr(err, ERR_PTR);
+      continue;
+    }
+    const WaveRows w(n, row_ptr, r0_);
+    int e_local = 0;
+    for (int32_t base = w.e0; base < w.e1; base += 64) {
+      const int32_t e = base + lane;
+      const int t = w.row_of(min(e, w.e1 - 1));
+      const int32_t rs = __shfl(w.myrp, t, 64);
+      if (e < w.e1) {
+        const int32_t j = col[e];
+        if (j < 0 || j >= n) {
+          e_local |= ERR_COL;
+        } else {
+          if (e > rs && col[e - 1] >= j) e_local |= ERR_ORDER;
+          if (!isfinite(val[e])) e_local |= ERR_VAL;
+          atomicAdd(&colcnt[j], 1);
+        }
+      }
+    }
+    if (__any(e_local != 0) && e_local) atomicOr(err, e_local);
+  }
 }
 
 __global__ void k_dense_flag(int32_t n, const int32_t* colcnt, double thr, int32_t* flag) {
@@ -232,24 +290,40 @@ __global__ void k_row_scatter(int32_t n, const int32_t* __restrict__ row_ptr,
 
 // ---- CSR -> CSC transpose (shared with the build) ----------------------------
 
-__global__ void k_tr_count(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                           int32_t* __restrict__ cnt) {
+// One thread per row: the entries u of consecutive rows fall in different
+// columns, so the atomics of a wavefront instruction rarely collide.
+__global__ void __launch_bounds__(NT) k_tr_count(int32_t n, const int32_t* __restrict__ rp,
+                                                 const int32_t* __restrict__ ci, int32_t* __restrict__ cnt) {
   const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
   if (i >= n) return;
   for (int32_t e = rp[i]; e < rp[i + 1]; ++e) atomicAdd(&cnt[ci[e]], 1);
 }
 
+// One thread per row, its entries TB at a time: the TB slot reservations
+// (atomics that return a value) are all in flight before the first is used.
 template <class V>
-__global__ void k_tr_scatter(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                             const V* __restrict__ v, const int32_t* __restrict__ cp,
-                             int32_t* __restrict__ cur, int32_t* __restrict__ ri, V* __restrict__ cv) {
+__global__ void __launch_bounds__(NT) k_tr_scatter(int32_t n, const int32_t* __restrict__ rp,
+                                                   const int32_t* __restrict__ ci, const V* __restrict__ v,
+                                                   const int32_t* __restrict__ cp, int32_t* __restrict__ cur,
+                                                   int32_t* __restrict__ ri, V* __restrict__ cv) {
+  constexpr int TB = 8;
   const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
   if (i >= n) return;
-  for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
-    const int32_t j = ci[e];
-    const int32_t slot = cp[j] + atomicAdd(&cur[j], 1);
-    ri[slot] = (int32_t)i;
-    cv[slot] = v[e];
+  const int32_t a = rp[i], b = rp[i + 1];
+  for (int32_t e = a; e < b; e += TB) {
+    int32_t j[TB], slot[TB];
+#pragma unroll
+    for (int u = 0; u < TB; ++u) j[u] = e + u < b ? ci[e + u] : -1;
+#pragma unroll
+    for (int u = 0; u < TB; ++u) slot[u] = j[u] >= 0 ? atomicAdd(&cur[j[u]], 1) : 0;
+#pragma unroll
+    for (int u = 0; u < TB; ++u) {
+      if (j[u] >= 0) {
+        const int32_t q = cp[j[u]] + slot[u];
+        ri[q] = (int32_t)i;
+        cv[q] = v[e + u];
+      }
+    }
   }
 }
 
@@ -323,8 +397,8 @@ void csr_transpose(int32_t nrows, int32_t ncols, const int32_t* rp, const int32_
   LAUNCH_CHECK();
   exclusive_scan_i32(cnt.p, cp, ncols, al, st);
   HIPC(hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * ((size_t)ncols + 1), st));
-  hipLaunchKernelGGL((k_tr_scatter<V>), dim3(grid_for(nrows, NT)), dim3(NT), 0, st, nrows, rp, ci, v,
-                     cp, cnt.p, ri, cv);
+  hipLaunchKernelGGL((k_tr_scatter<V>), dim3(grid_for(nrows, NT)), dim3(NT), 0, st, nrows, rp, ci, v, cp,
+                     cnt.p, ri, cv);
   LAUNCH_CHECK();
   hipLaunchKernelGGL((k_tr_sort<V>), dim3(grid_for(ncols, NT)), dim3(NT), 0, st, ncols, cp, ri, cv);
   LAUNCH_CHECK();
@@ -359,7 +433,7 @@ void split_impl(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* c
   DBuf<int> err(&al, 4);
   HIPC(hipMemsetAsync(colcnt.p, 0, sizeof(int32_t) * ((size_t)n + 1), st));
   HIPC(hipMemsetAsync(err.p, 0, sizeof(int) * 4, st));
-  hipLaunchKernelGGL(k_validate_count, dim3(grid_for(n, NT)), dim3(NT), 0, st, n, nnz, row_ptr,
+  hipLaunchKernelGGL(k_validate_count, dim3(grid_for(((int64_t)n + 63) / 64 * 64, NT, 4096)), dim3(NT), 0, st, n, nnz, row_ptr,
                      col_idx, val, colcnt.p, err.p);
   LAUNCH_CHECK();
   const double thr = o.dense_factor * (double)p;
