@@ -8,8 +8,9 @@
 //
 // One wavefront (a 64-thread workgroup) per column: the candidate indices of a
 // union are gathered into LDS, bitonic-sorted and de-duplicated with a ballot
-// prefix, so both lists come out sorted ascending.  A count pass sizes the
-// lists, a prefix sum places them, and a fill pass writes them.
+// prefix (or, for small unions, an LDS hash table and a rank sort), so both
+// lists come out sorted ascending.  The lists are written at offsets from cheap
+// upper bounds of their lengths and then packed.
 #include "sai_internal.hpp"
 
 namespace sai {
@@ -153,6 +154,8 @@ __device__ int sort_unique_fast(int32_t* cand, int m, int cap, int32_t* ht) {
   return nu;
 }
 
+// mode 0: counts only; 1: lists at jptr/iptr; 2: lists at jptr/iptr and counts.
+// A column whose unions overflow the capacities gets cntJ = -1 (modes 0, 2).
 template <int CAP>
 __global__ void __launch_bounds__(64) k_pattern(int32_t n, int kind, const int32_t* __restrict__ cp,
                                                 const int32_t* __restrict__ ri, int mode,
@@ -177,33 +180,85 @@ __global__ void __launch_bounds__(64) k_pattern(int32_t n, int kind, const int32
     const int32_t a0 = cp[k], c0 = cp[k + 1] - cp[k];
     if (kind == SAI_PAT_A2) {
       // L = P(A~(:,k)), kept in sJ temporarily
-      if (c0 > CAPJ) { if (l == 0 && mode == 0) { cntJ[k] = -1; atomicAdd(nover, 1); } continue; }
+      if (c0 > CAPJ) { if (l == 0 && mode != 1) { cntJ[k] = -1; atomicAdd(nover, 1); } continue; }
       for (int t = l; t < c0; t += WAVE) sJ[t] = ri[a0 + t];
       __syncthreads();
       int m = gather_cols(cp, ri, sJ, c0, cand, CAP, s_start, s_off);
-      if (m < 0) { if (l == 0 && mode == 0) { cntJ[k] = -1; atomicAdd(nover, 1); } __syncthreads(); continue; }
+      if (m < 0) { if (l == 0 && mode != 1) { cntJ[k] = -1; atomicAdd(nover, 1); } __syncthreads(); continue; }
       nJ = sort_unique_fast(cand, m, CAP, ht);
-      if (nJ > CAPJ) { if (l == 0 && mode == 0) { cntJ[k] = -1; atomicAdd(nover, 1); } __syncthreads(); continue; }
+      if (nJ > CAPJ) { if (l == 0 && mode != 1) { cntJ[k] = -1; atomicAdd(nover, 1); } __syncthreads(); continue; }
       for (int t = l; t < nJ; t += WAVE) sJ[t] = cand[t];
       __syncthreads();
     } else {
-      if (c0 > CAPJ) { if (l == 0 && mode == 0) { cntJ[k] = -1; atomicAdd(nover, 1); } continue; }
+      if (c0 > CAPJ) { if (l == 0 && mode != 1) { cntJ[k] = -1; atomicAdd(nover, 1); } continue; }
       nJ = c0;
       for (int t = l; t < nJ; t += WAVE) sJ[t] = ri[a0 + t];
       __syncthreads();
     }
     // ---- I_k
     int m = gather_cols(cp, ri, sJ, nJ, cand, CAP, s_start, s_off);
-    if (m < 0) { if (l == 0 && mode == 0) { cntJ[k] = -1; atomicAdd(nover, 1); } __syncthreads(); continue; }
+    if (m < 0) { if (l == 0 && mode != 1) { cntJ[k] = -1; atomicAdd(nover, 1); } __syncthreads(); continue; }
     const int nI = sort_unique_fast(cand, m, CAP, ht);
-    if (mode == 0) {
+    if (mode != 1) {
       if (l == 0) { cntJ[k] = nJ; cntI[k] = nI; }
-    } else {
+    }
+    if (mode != 0) {
       const int64_t jo = jptr[k], io = iptr[k];
       for (int t = l; t < nJ; t += WAVE) jout[jo + t] = sJ[t];
       for (int t = l; t < nI; t += WAVE) iout[io + t] = cand[t];
     }
     __syncthreads();
+  }
+}
+
+// Upper bounds of |J_k| and |I_k| from column lengths only (no de-duplication):
+// w[j] = sum of |P(A~(:,i))| over i in P(A~(:,j)); for the static pattern
+// P(|A~|^2 e_k), |J_k| <= sum_{j in P(A~(:,k))} |P(A~(:,j))| and
+// |I_k| <= sum_{j in P(A~(:,k))} w[j]; for J_k = P(A~(:,k)), |I_k| <= w[k].
+__global__ void k_pat_w(int32_t n, const int32_t* __restrict__ cp, const int32_t* __restrict__ ri,
+                        int64_t* __restrict__ w) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= n) return;
+  int64_t s = 0;
+  for (int32_t e = cp[j]; e < cp[j + 1]; ++e) {
+    const int32_t i = ri[e];
+    s += cp[i + 1] - cp[i];
+  }
+  w[j] = s;
+}
+
+__global__ void k_pat_ub(int32_t n, int kind, const int32_t* __restrict__ cp,
+                         const int32_t* __restrict__ ri, const int64_t* __restrict__ w,
+                         int64_t* __restrict__ ubJ, int64_t* __restrict__ ubI) {
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k >= n) return;
+  if (kind == SAI_PAT_A2) {
+    int64_t sj = 0, si = 0;
+    for (int32_t e = cp[k]; e < cp[k + 1]; ++e) {
+      const int32_t j = ri[e];
+      sj += cp[j + 1] - cp[j];
+      si += w[j];
+    }
+    ubJ[k] = sj;
+    ubI[k] = si;
+  } else {
+    ubJ[k] = cp[k + 1] - cp[k];
+    ubI[k] = w[k];
+  }
+}
+
+// Copy the lists written at upper-bound offsets (src_ptr[k], length cnt[k]) to
+// their packed places dst_ptr[k]; one wavefront per column, coalesced.
+__global__ void __launch_bounds__(256) k_pack_lists(int32_t n, const int64_t* __restrict__ src_ptr,
+                                                    const int32_t* __restrict__ src,
+                                                    const int64_t* __restrict__ dst_ptr,
+                                                    int32_t* __restrict__ dst) {
+  const int l = lane_id();
+  for (int64_t k = ((int64_t)blockIdx.x * 256 + threadIdx.x) / WAVE; k < n;
+       k += (int64_t)gridDim.x * (256 / WAVE)) {
+    const int64_t a = src_ptr[k], b = dst_ptr[k];
+    const int c = (int)(dst_ptr[k + 1] - b);
+    for (int t = l; t < c; t += WAVE) dst[b + t] = src[a + t];
   }
 }
 
@@ -273,39 +328,60 @@ __global__ void k_flag_neg(int32_t n, const int32_t* cnt, int32_t* flag) {
 }
 
 // Sizes, offsets and lists of J_k and I_k.  jptr/iptr get n+1 entries.
+// One union pass: the lists are written at offsets from upper bounds of their
+// lengths (no de-duplication needed for the bounds), with their exact lengths,
+// then packed to the offsets of the exact lengths.
 void build_patterns(const sai_split_s* sp, int kind, hipStream_t st, const Allocator& al,
                     DBuf<int64_t>& jptr, DBuf<int32_t>& jidx, DBuf<int64_t>& iptr,
                     DBuf<int32_t>& iidx, DBuf<int32_t>& cntJ, DBuf<int32_t>& cntI) {
   const int32_t n = sp->n;
+  const int32_t* cp = sp->t_col_ptr.p;
+  const int32_t* ri = sp->t_row_idx.p;
   cntJ.alloc(&al, (size_t)n + 1);
   cntI.alloc(&al, (size_t)n + 1);
   DBuf<int> nover(&al, 2);
   HIPC(hipMemsetAsync(nover.p, 0, 2 * sizeof(int), st));
   const unsigned grid = (unsigned)std::min<int64_t>(n, 1 << 20);
   constexpr int CAP_S = 1024, CAP_L = 8192;
+  DBuf<int64_t> ujo(&al, (size_t)n + 1), uio(&al, (size_t)n + 1);
+  DBuf<int32_t> tJ, tI;
   {
-    SAI_PROF("pattern_count", st);
-    hipLaunchKernelGGL((k_pattern<CAP_S>), dim3(grid), dim3(64), 0, st, n, kind, sp->t_col_ptr.p,
-                       sp->t_row_idx.p, 0, (const int32_t*)nullptr, 0, cntJ.p, cntI.p,
-                       (const int64_t*)nullptr, (int32_t*)nullptr, (const int64_t*)nullptr,
-                       (int32_t*)nullptr, nover.p);
+    SAI_PROF("pattern_bounds", st);
+    DBuf<int64_t> w(&al, (size_t)n + 1), ubJ(&al, (size_t)n + 1), ubI(&al, (size_t)n + 1);
+    hipLaunchKernelGGL(k_pat_w, dim3(grid_for(n, 256)), dim3(256), 0, st, n, cp, ri, w.p);
+    hipLaunchKernelGGL(k_pat_ub, dim3(grid_for(n, 256)), dim3(256), 0, st, n, kind, cp, ri, w.p, ubJ.p,
+                       ubI.p);
     LAUNCH_CHECK();
+    exclusive_scan_i64(ubJ.p, ujo.p, n, al, st);
+    exclusive_scan_i64(ubI.p, uio.p, n, al, st);
+    int64_t ub[2];
+    HIPC(hipMemcpyAsync(&ub[0], ujo.p + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIPC(hipMemcpyAsync(&ub[1], uio.p + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    tJ.alloc(&al, (size_t)ub[0] + 1);
+    tI.alloc(&al, (size_t)ub[1] + 1);
   }
-  const int over = read_scalar(nover.p, st);
-  DBuf<int32_t> flag;
-  if (over > 0) {
-    flag.alloc(&al, (size_t)n + 1);
-    hipLaunchKernelGGL(k_flag_neg, dim3(grid_for(n, 256)), dim3(256), 0, st, n, cntJ.p, flag.p);
+  {
+    SAI_PROF("pattern_fill", st);
+    hipLaunchKernelGGL((k_pattern<CAP_S>), dim3(grid), dim3(64), 0, st, n, kind, cp, ri, 2,
+                       (const int32_t*)nullptr, 0, cntJ.p, cntI.p, (const int64_t*)ujo.p, tJ.p,
+                       (const int64_t*)uio.p, tI.p, nover.p);
     LAUNCH_CHECK();
-    HIPC(hipMemsetAsync(nover.p, 0, 2 * sizeof(int), st));
-    hipLaunchKernelGGL((k_pattern<CAP_L>), dim3(grid), dim3(64), 0, st, n, kind, sp->t_col_ptr.p,
-                       sp->t_row_idx.p, 0, (const int32_t*)flag.p, 1, cntJ.p, cntI.p,
-                       (const int64_t*)nullptr, (int32_t*)nullptr, (const int64_t*)nullptr,
-                       (int32_t*)nullptr, nover.p);
-    LAUNCH_CHECK();
-    if (read_scalar(nover.p, st) > 0)
-      SAI_THROW(SAI_ETOOBIG, "a pattern union exceeds %d candidate indices", CAP_L);
+    if (read_scalar(nover.p, st) > 0) {
+      // columns whose unions overflow the small kernel are redone by the large one
+      DBuf<int32_t> flag(&al, (size_t)n + 1);
+      hipLaunchKernelGGL(k_flag_neg, dim3(grid_for(n, 256)), dim3(256), 0, st, n, cntJ.p, flag.p);
+      LAUNCH_CHECK();
+      HIPC(hipMemsetAsync(nover.p, 0, 2 * sizeof(int), st));
+      hipLaunchKernelGGL((k_pattern<CAP_L>), dim3(grid), dim3(64), 0, st, n, kind, cp, ri, 2,
+                         (const int32_t*)flag.p, 1, cntJ.p, cntI.p, (const int64_t*)ujo.p, tJ.p,
+                         (const int64_t*)uio.p, tI.p, nover.p);
+      LAUNCH_CHECK();
+      if (read_scalar(nover.p, st) > 0)
+        SAI_THROW(SAI_ETOOBIG, "a pattern union exceeds %d candidate indices", CAP_L);
+    }
   }
+  SAI_PROF("pattern_pack", st);
   jptr.alloc(&al, (size_t)n + 1);
   iptr.alloc(&al, (size_t)n + 1);
   exclusive_scan_i32_to_i64(cntJ.p, jptr.p, n, al, st);
@@ -316,19 +392,10 @@ void build_patterns(const sai_split_s* sp, int kind, hipStream_t st, const Alloc
   HIPC(hipStreamSynchronize(st));
   jidx.alloc(&al, (size_t)tot[0] + 1);
   iidx.alloc(&al, (size_t)tot[1] + 1);
-  SAI_PROF("pattern_fill", st);
-  hipLaunchKernelGGL((k_pattern<CAP_S>), dim3(grid), dim3(64), 0, st, n, kind, sp->t_col_ptr.p,
-                     sp->t_row_idx.p, 1, over > 0 ? (const int32_t*)flag.p : (const int32_t*)nullptr, 0,
-                     cntJ.p, cntI.p, (const int64_t*)jptr.p, jidx.p, (const int64_t*)iptr.p, iidx.p,
-                     nover.p);
+  const unsigned pgrid = grid_for((int64_t)n * WAVE, 256, 8192);
+  hipLaunchKernelGGL(k_pack_lists, dim3(pgrid), dim3(256), 0, st, n, ujo.p, tJ.p, jptr.p, jidx.p);
+  hipLaunchKernelGGL(k_pack_lists, dim3(pgrid), dim3(256), 0, st, n, uio.p, tI.p, iptr.p, iidx.p);
   LAUNCH_CHECK();
-  if (over > 0) {
-    // columns that overflowed the small kernel are re-filled by the large one
-    hipLaunchKernelGGL((k_pattern<CAP_L>), dim3(grid), dim3(64), 0, st, n, kind, sp->t_col_ptr.p,
-                       sp->t_row_idx.p, 1, (const int32_t*)flag.p, 1, cntJ.p, cntI.p,
-                       (const int64_t*)jptr.p, jidx.p, (const int64_t*)iptr.p, iidx.p, nover.p);
-    LAUNCH_CHECK();
-  }
 }
 
 }  // namespace sai
