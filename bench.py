@@ -205,9 +205,21 @@ def main():
         log(f"bench: warmup {i}")
         step(P.FP32)
 
-    def timed(prec, K):
+    # one untimed mixed step with events around every kernel: the full table, and
+    # the dominant kernel (the largest total among single kernels; scopes that cover
+    # several launches, like "split" or "spai_search", are listed but not chosen)
+    P.profile_enable(1)
+    step(P.FP32)
+    prof_all = P.profile_read()
+    P.profile_enable(0)
+    scopes = {"split", "smw_recover", "spai_search", "gmres_fused", "pattern_bounds", "pattern_fill",
+              "pattern_pack", "bicg_init"}
+    dom = max((tot, nm) for nm, (l, tot) in prof_all.items() if nm not in scopes)[1]
+
+    def timed(prec, K, only=None):
         torch.cuda.synchronize()
-        P.profile_enable(2)  # events only around the kernels that can dominate
+        if only:
+            P.profile_enable(only=only)  # events only around the dominant kernel
         t0 = time.perf_counter()
         last = None
         builds, solves, backs = [], [], []
@@ -219,26 +231,24 @@ def main():
                 backs.append(last[4]["t_solve_ms"] + last[4]["t_smw_ms"])
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        prof = P.profile_read()
+        prof = P.profile_read() if only else {}
         P.profile_enable(False)
         return (t1 - t0) / K * 1e3, last, prof, builds, solves, backs
 
-    log(f"bench: timing {args.steps} mixed steps")
-    ms_mixed, (sp_m, pc_m, x_m, st_m, bst_m), prof, builds_m, solves_m, backs_m = timed(P.FP32, args.steps)
+    log(f"bench: timing {args.steps} mixed steps (events around {dom})")
+    ms_mixed, (sp_m, pc_m, x_m, st_m, bst_m), prof, builds_m, solves_m, backs_m = timed(P.FP32, args.steps,
+                                                                                      only=dom)
     kplain = args.plain_steps if args.plain_steps is not None else max(1, args.steps // 2)
     plain = None
     if kplain > 0:
         log(f"bench: timing {kplain} plain FP64 steps")
-        ms_plain, (sp_p, pc_p, x_p, st_p, bst_p), _, builds_p, solves_p, _ = timed(P.FP64, kplain)
+        # the same event overhead as the mixed steps: around the plain form of that kernel
+        dom_p = dom.replace("_f32", "_f64")
+        ms_plain, (sp_p, pc_p, x_p, st_p, bst_p), _, builds_p, solves_p, _ = timed(P.FP64, kplain,
+                                                                                 only=dom_p)
         xhp = x_p.cpu().numpy()
         plain = dict(ms=ms_plain, build=float(np.mean(builds_p)), st=st_p,
                      rr_host=float(np.linalg.norm(w.b - w.A @ xhp) / np.linalg.norm(w.b)))
-
-    # one more (untimed) mixed step with events around every kernel, for the full table
-    P.profile_enable(1)
-    step(P.FP32)
-    prof_all = P.profile_read()
-    P.profile_enable(0)
 
     xh = x_m.cpu().numpy()
     rr_host = float(np.linalg.norm(w.b - w.A @ xh) / np.linalg.norm(w.b))
@@ -269,11 +279,7 @@ def main():
         "bicg_s_update": 3 * bytes_kn,
         "bicg_xr_update": 8 * bytes_kn,
     }
-    kernels = sorted(((tot, nm, l) for nm, (l, tot) in prof.items()), reverse=True)
-    # the dominant kernel: the largest total among single kernels (scopes that cover
-    # several launches, like "split" or "spai_search", are listed but not chosen)
-    scopes = {"split", "smw_recover", "spai_search", "gmres_fused"}
-    dom_ms, dom, dom_launches = next(x for x in kernels if x[1] not in scopes)
+    dom_launches, dom_ms = prof[dom]
     avg_ms = dom_ms / dom_launches
     if dom.startswith("ls_qr_f32"):
         ach = ls_work.get(dom, 0.0) / (avg_ms * 1e-3) / 1e12

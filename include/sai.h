@@ -264,11 +264,14 @@ int sai_backward(const sai_split_t* sp, const sai_precond_t* pc, const double* x
  * around each of its kernel launches and accumulates, per kernel name, the
  * number of launches and their total elapsed time.  sai_profile_enable(1)
  * records every kernel, sai_profile_enable(2) only the sparse products, column
- * solvers, SPAI search and GMRES (less event overhead), 0 stops; enabling
- * resets the totals; sai_profile_get resolves pending events (it waits for
- * them) and returns entry i (0 <= i < sai_profile_count()).  Not thread-safe
- * with respect to concurrent launches from several host threads. */
+ * solvers, SPAI search and GMRES (less event overhead), sai_profile_enable(3)
+ * only the kernels whose name starts with the prefix given to
+ * sai_profile_only (host string, copied; "" matches every name), 0 stops;
+ * enabling resets the totals; sai_profile_get resolves pending events (it
+ * waits for them) and returns entry i (0 <= i < sai_profile_count()).  Not
+ * thread-safe with respect to concurrent launches from several host threads. */
 int sai_profile_enable(int32_t on);
+int sai_profile_only(const char* prefix /* host */);
 int sai_profile_count(void);
 int sai_profile_get(int32_t i, char* name /* host, name_cap bytes */, int32_t name_cap,
                     int64_t* launches /* host */, double* total_ms /* host */);

@@ -129,6 +129,7 @@ def lib():
     L.sai_last_error.restype = C.c_char_p
     L.sai_memcpy_d2d.argtypes = [vp, vp, C.c_size_t, vp]
     L.sai_profile_enable.argtypes = [i32]
+    L.sai_profile_only.argtypes = [C.c_char_p]
     L.sai_profile_count.argtypes = []
     L.sai_profile_get.argtypes = [i32, C.c_char_p, i32, C.POINTER(i64), C.POINTER(C.c_double)]
 
@@ -350,10 +351,15 @@ def backward(split: Split, pc: Precond, x, grad_x, want_b=True, want_a=True, rai
     return gb, ga, _stats_dict(st, iters)
 
 
-def profile_enable(mode=1):
+def profile_enable(mode=1, only=None):
     """Start (and reset) the library's per-kernel HIP-event timing: 1 = every kernel,
-    2 = only the kernels that can dominate (products, column solvers), 0/False = stop."""
-    _check(lib().sai_profile_enable(int(mode)), "sai_profile_enable")
+    2 = only the kernels that can dominate (products, column solvers), 0/False = stop;
+    with `only` (a name prefix) just the kernels whose name starts with it."""
+    L = lib()
+    if only is not None:
+        _check(L.sai_profile_only(str(only).encode()), "sai_profile_only")
+        mode = 3
+    _check(L.sai_profile_enable(int(mode)), "sai_profile_enable")
 
 
 def profile_read() -> dict:

@@ -16,6 +16,7 @@ struct Registry {
   std::mutex mu;
   bool on = false;
   int mode = 0;
+  std::string only;  // mode 3: record only the names that start with this
   std::vector<Pending> pending;
   std::vector<hipEvent_t> pool;
   std::map<std::string, std::pair<int64_t, double>> totals;
@@ -66,6 +67,7 @@ ProfScope::ProfScope(const char* name, hipStream_t s) : st(s) {
   std::lock_guard<std::mutex> g(r.mu);
   if (!r.on) return;
   if (r.mode == 2 && !hot_name(name)) return;
+  if (r.mode == 3 && strncmp(name, r.only.c_str(), r.only.size()) != 0) return;
   Pending p{name, r.get_event(), r.get_event()};
   HIPC(hipEventRecord(p.a, s));
   r.pending.push_back(p);
@@ -94,6 +96,13 @@ int sai_profile_enable(int32_t on) {
   r.totals.clear();
   r.on = on != 0;
   r.mode = on;
+  return SAI_OK;
+}
+
+int sai_profile_only(const char* prefix) {
+  auto& r = sai::reg();
+  std::lock_guard<std::mutex> g(r.mu);
+  r.only = prefix ? prefix : "";
   return SAI_OK;
 }
 
