@@ -64,8 +64,8 @@ FP64_VEC_TFLOPS = 78.6
 
 # register LS kernel variants in the order the library assigns columns to them
 LS_VARIANTS = {
-    "f32": [(16, 8, "g16r1j8"), (32, 16, "g16r2j16"), (64, 32, "g16r4j32"), (128, 32, "g64r2j32"),
-            (256, 32, "g64r4j32"), (128, 64, "g64r2j64"), (4096, 128, "big")],
+    "f32": [(16, 8, "g16r1j8"), (32, 16, "g16r2j16"), (64, 25, "g16r4j25"), (64, 32, "g16r4j32"),
+            (128, 32, "g64r2j32"), (256, 32, "g64r4j32"), (128, 64, "g64r2j64"), (4096, 128, "big")],
     "f64": [(16, 8, "g16r1j8"), (32, 16, "g16r2j16"), (64, 32, "g32r2j32"), (128, 32, "g64r2j32"),
             (64, 64, "g64r1j64"), (4096, 128, "big")],
 }

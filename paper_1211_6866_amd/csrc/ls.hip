@@ -61,8 +61,8 @@ __device__ __forceinline__ int lower_bound_lds(const int32_t* a, int n, int32_t 
   return lo;
 }
 
-template <class T, int G, int R, int JMAX>
-__global__ void __launch_bounds__(64) k_ls_qr(const int32_t* __restrict__ cols, int ncols,
+template <class T, int G, int R, int JMAX, int MINW = 1>
+__global__ void __launch_bounds__(64, MINW) k_ls_qr(const int32_t* __restrict__ cols, int ncols,
                                               const int64_t* __restrict__ jptr,
                                               const int32_t* __restrict__ jidx,
                                               const int64_t* __restrict__ iptr,
@@ -386,9 +386,9 @@ struct VariantTable;
 // float: register variants, then the global-memory kernel
 template <>
 struct VariantTable<float> {
-  static constexpr int N = 7;
-  static constexpr Variant v[N] = {{16, 8}, {32, 16}, {64, 32}, {128, 32}, {256, 32}, {128, 64},
-                                   {BIG_MAXI, BIG_MAXJ}};
+  static constexpr int N = 8;
+  static constexpr Variant v[N] = {{16, 8}, {32, 16}, {64, 25}, {64, 32}, {128, 32}, {256, 32},
+                                   {128, 64}, {BIG_MAXI, BIG_MAXJ}};
 };
 template <>
 struct VariantTable<double> {
@@ -433,7 +433,7 @@ __global__ void __launch_bounds__(BK_NT) k_bucket_scatter(int32_t n, const int32
   }
 }
 
-template <class T, int G, int R, int JMAX>
+template <class T, int G, int R, int JMAX, int MINW = 1>
 void launch_qr(const int32_t* list, int cnt, const int64_t* jptr, const int32_t* jidx,
                const int64_t* iptr, const int32_t* iidx, const sai_split_s* sp, T* mout,
                double* res, int* nsing, hipStream_t st) {
@@ -444,7 +444,7 @@ void launch_qr(const int32_t* list, int cnt, const int64_t* jptr, const int32_t*
   if (!name[0])
     snprintf(name, sizeof(name), "ls_qr_%s_g%dr%dj%d", sizeof(T) == 4 ? "f32" : "f64", G, R, JMAX);
   SAI_PROF(name, st);
-  hipLaunchKernelGGL((k_ls_qr<T, G, R, JMAX>), dim3(grid), dim3(64), 0, st, list, cnt, jptr, jidx,
+  hipLaunchKernelGGL((k_ls_qr<T, G, R, JMAX, MINW>), dim3(grid), dim3(64), 0, st, list, cnt, jptr, jidx,
                      iptr, iidx, sp->t_col_ptr.p, sp->t_row_idx.p, sp->t_cval.p, mout, res, nsing);
   LAUNCH_CHECK();
 }
@@ -460,10 +460,14 @@ void dispatch_variant(int v, const int32_t* list, int cnt, const int64_t* jptr,
     switch (v) {
       case 0: launch_qr<T, 16, 1, 8>(list, cnt, jptr, jidx, iptr, iidx, sp, mout, res, nsing, st); return;
       case 1: launch_qr<T, 16, 2, 16>(list, cnt, jptr, jidx, iptr, iidx, sp, mout, res, nsing, st); return;
-      case 2: launch_qr<T, 16, 4, 32>(list, cnt, jptr, jidx, iptr, iidx, sp, mout, res, nsing, st); return;
-      case 3: launch_qr<T, 64, 2, 32>(list, cnt, jptr, jidx, iptr, iidx, sp, mout, res, nsing, st); return;
-      case 4: launch_qr<T, 64, 4, 32>(list, cnt, jptr, jidx, iptr, iidx, sp, mout, res, nsing, st); return;
-      case 5: launch_qr<T, 64, 2, 64>(list, cnt, jptr, jidx, iptr, iidx, sp, mout, res, nsing, st); return;
+      case 2:  // 25-column problems (interior columns of P(|A~|^2) on 3D 7-point grids),
+               // held to 168 registers so that three wavefronts share a SIMD
+        launch_qr<T, 16, 4, 25, 3>(list, cnt, jptr, jidx, iptr, iidx, sp, mout, res, nsing, st);
+        return;
+      case 3: launch_qr<T, 16, 4, 32>(list, cnt, jptr, jidx, iptr, iidx, sp, mout, res, nsing, st); return;
+      case 4: launch_qr<T, 64, 2, 32>(list, cnt, jptr, jidx, iptr, iidx, sp, mout, res, nsing, st); return;
+      case 5: launch_qr<T, 64, 4, 32>(list, cnt, jptr, jidx, iptr, iidx, sp, mout, res, nsing, st); return;
+      case 6: launch_qr<T, 64, 2, 64>(list, cnt, jptr, jidx, iptr, iidx, sp, mout, res, nsing, st); return;
       default: break;
     }
   } else {
