@@ -24,8 +24,11 @@ namespace {
 constexpr int NT = 256;
 constexpr int NBMAX = 2048;
 constexpr int PSTRIDE = 64;  // partial sums: [ND][NBMAX][PSTRIDE] doubles
-constexpr int CAP_A = 2048;  // staged entries per tile of A~
-constexpr int CAP_M = 2048;  // and of M
+// staged entries per tile (RPB rows): A~ (regular part, about 2p entries per
+// row) gets 12 per row, at least 512, at most 2048; M gets 2048.  A smaller
+// staging area lets more workgroups share a CU.
+constexpr int cap_a(int rpb) { return rpb * 12 < 512 ? 512 : (rpb * 12 > 2048 ? 2048 : rpb * 12); }
+constexpr int CAP_M = 2048;
 constexpr double TINY = 1e-300;
 
 enum { ST_ACTIVE = 0, ST_CONV = 1, ST_MAXIT = 2, ST_BREAK = 3 };
@@ -139,10 +142,14 @@ __device__ void block_partials(double (&acc)[ND][2], const State& S) {
   __syncthreads();
   if (t < 2 * LP) {
     const int l = t >> 1, j = t & 1;
-#pragma unroll
+    // a short loop (not unrolled: only 2 LP threads run it, and unrolled it
+    // would hold every LDS value in registers across the whole kernel)
+#pragma unroll 1
     for (int d = 0; d < ND; ++d) {
       double s = 0.0;
+#pragma unroll 1
       for (int w = 0; w < NT / 64; ++w)
+#pragma unroll 2
         for (int rw = 0; rw < RPW; ++rw) s += red[d][2 * (w * 64 + rw * LP + l) + j];
       S.part[((int64_t)d * NBMAX + blockIdx.x) * PSTRIDE + t] = s;
     }
@@ -275,6 +282,7 @@ template <int LP, int CH, int CH2>
 __global__ void __launch_bounds__(NT) k_av(int64_t n, int k, int kp, Csr<double> A, Vec V, State S,
                                            int xmap) {
   LANES(LP)
+  constexpr int CAP_A = cap_a(RPB);
   STAGE_DECL(double, CAP_A, RPB)
   double acc[1][2] = {{0.0, 0.0}};
   const bool o0 = lok_ && col_on(S, c0, k), o1 = lok_ && col_on(S, c0 + 1, k);
@@ -362,6 +370,7 @@ template <int LP, int CH, int CH2>
 __global__ void __launch_bounds__(NT) k_at(int64_t n, int k, int kp, Csr<double> A, Vec V, State S,
                                            int xmap) {
   LANES(LP)
+  constexpr int CAP_A = cap_a(RPB);
   STAGE_DECL(double, CAP_A, RPB)
   double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
   const bool o0 = lok_ && col_on(S, c0, k) && !S.halfconv[c0];
