@@ -304,7 +304,51 @@ def test_krylov_block_widths(name):
     pc = P.Precond(g, pattern=kind, drop=P.DROP_ABS, tau=1e-3, precision=P.FP32)
     n = w.A.shape[0]
     rng = np.random.default_rng(5)
-    for k in (1, 2, 3, 5, 8, 11, 13, 23):
+    ks = (1, 2, 3, 5, 8, 11, 13, 23, 29, 40) if name == "c2_12" else (1, 11, 23)
+    for k in ks:
+        R = rng.standard_normal((n, k))
+        thr = [1e-10 * np.linalg.norm(R[:, c]) for c in range(k)]
+        Rt = torch.from_numpy(R).cuda()
+        for transpose in (False, True):
+            Aop = S.At if not transpose else sp.csr_matrix(S.At.T)
+            X, its, sts, code = P.krylov(g, pc, Rt, thr, transpose=transpose)
+            assert code == P.OK and all(v == 0 for v in sts), (k, transpose, its, sts)
+            Xh = _np(X)
+            for c in range(k):
+                assert np.linalg.norm(R[:, c] - Aop @ Xh[:, c]) < thr[c], (k, transpose, c)
+
+
+def test_krylov_long_rows():
+    # Rows far longer than a tile's LDS staging area (A~ and, with J_k = P(A~(:,k)),
+    # M get rows of 2500 entries): the products fall back to reading those tiles from
+    # global memory; every column still meets its true-residual threshold.
+    n = 3000
+    rng = np.random.default_rng(11)
+    rows, cols = [], []
+    for i in range(n):
+        c = rng.choice(n, size=5, replace=False)
+        rows += [i] * len(c)
+        cols += c.tolist()
+    for i in (100, 1700, 2900):
+        c = rng.choice(n, size=2500, replace=False)
+        rows += [i] * len(c)
+        cols += c.tolist()
+    vals = 0.05 * rng.standard_normal(len(rows))
+    A = sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
+    A.setdiag(0.0)
+    A.eliminate_zeros()
+    A = A + sp.diags(1.5 * np.asarray(abs(A).sum(axis=1)).ravel() + 1.0)
+    A = sp.csr_matrix(A)
+    A.sort_indices()
+    A.indptr = A.indptr.astype(np.int32)
+    A.indices = A.indices.astype(np.int32)
+    S = osplit.split(A)
+    rp, ci, va = P.csr_to_device(A)
+    g = P.Split(rp, ci, va)
+    assert g.s == S.s
+    pc = P.Precond(g, pattern=P.PAT_A, drop=P.DROP_NONE, precision=P.FP32)
+    assert int(np.diff(_np(pc.arrays()["row_ptr"])).max()) >= 2500
+    for k in (3, 11):
         R = rng.standard_normal((n, k))
         thr = [1e-10 * np.linalg.norm(R[:, c]) for c in range(k)]
         Rt = torch.from_numpy(R).cuda()
