@@ -43,7 +43,8 @@ struct Csr {
 struct State {
   double *rho, *rho_old, *alpha, *omega, *beta, *thr;
   int *status, *iters, *skip, *restarts, *half, *full, *rst, *halfconv, *wasact;
-  int* any;  // 0 half, 1 full, 2 restart, 3 active count, 4 half-converged
+  int* pend;  // t^T t below TINY at a column that awaits its half-step check
+  int* any;   // 0 half, 1 full, 2 restart, 3 active count, 4 half-converged
   double* part;
 };
 
@@ -301,24 +302,18 @@ __global__ void __launch_bounds__(NT) k_av(int64_t n, int k, int kp, Csr<double>
   block_partials<LP, 1>(acc, S);
 }
 
-// ---- s = r - alpha v; partial ||s||^2 -----------------------------------------
+// ---- s = r - alpha v (its norm is summed by k_at) --------------------------------
 template <int LP>
 __global__ void __launch_bounds__(NT) k_s(int64_t n, int k, int kp, Vec V, State S) {
   LANES(LP)
-  double acc[1][2] = {{0.0, 0.0}};
   const bool o0 = lok_ && col_on(S, c0, k), o1 = lok_ && col_on(S, c0 + 1, k);
+  if (!o0 && !o1) return;
   const double al0 = o0 ? S.alpha[c0] : 0.0, al1 = o1 ? S.alpha[c0 + 1] : 0.0;
-  if (o0 || o1) {
-    ROW_LOOP {
-      const int64_t q = i * kp + c0;
-      const double2 r = ld2(V.r, q), v = ld2(V.v, q);
-      const double s0 = r.x - al0 * v.x, s1 = r.y - al1 * v.y;
-      st2(V.s, q, s0, s1, o0, o1);
-      if (o0) acc[0][0] += s0 * s0;
-      if (o1) acc[0][1] += s1 * s1;
-    }
+  ROW_LOOP {
+    const int64_t q = i * kp + c0;
+    const double2 r = ld2(V.r, q), v = ld2(V.v, q);
+    st2(V.s, q, r.x - al0 * v.x, r.y - al1 * v.y, o0, o1);
   }
-  block_partials<LP, 1>(acc, S);
 }
 
 // ---- half-step true residual b - A (x + alpha p_hat), flagged columns only -------
@@ -349,32 +344,15 @@ __global__ void __launch_bounds__(NT) k_halfcheck(int64_t n, int k, int kp, Csr<
   block_partials<LP, 1>(acc, S);
 }
 
-// ---- x += alpha p_hat for the columns that converged at the half step -------------
-template <int LP>
-__global__ void __launch_bounds__(NT) k_halfapply(int64_t n, int k, int kp, Vec V, State S) {
-  if (S.any[4] == 0) return;
-  LANES(LP)
-  const bool o0 = lok_ && c0 < k && S.halfconv[c0] && S.status[c0] == ST_ACTIVE;
-  const bool o1 = lok_ && c0 + 1 < k && S.halfconv[c0 + 1] && S.status[c0 + 1] == ST_ACTIVE;
-  if (!o0 && !o1) return;
-  const double al0 = o0 ? S.alpha[c0] : 0.0, al1 = o1 ? S.alpha[c0 + 1] : 0.0;
-  ROW_LOOP {
-    const int64_t q = i * kp + c0;
-    const double2 x = ld2(V.x, q), ph = ld2(V.ph, q);
-    st2(V.x, q, x.x + al0 * ph.x, x.y + al1 * ph.y, o0, o1);
-  }
-}
-
-// ---- t = A s_hat; partials t^T s, t^T t ------------------------------------------
+// ---- t = A s_hat; partials t^T s, t^T t, s^T s ------------------------------------
 template <int LP, int CH, int CH2>
 __global__ void __launch_bounds__(NT) k_at(int64_t n, int k, int kp, Csr<double> A, Vec V, State S,
                                            int xmap) {
   LANES(LP)
   constexpr int CAP_A = cap_a(RPB);
   STAGE_DECL(double, CAP_A, RPB)
-  double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
-  const bool o0 = lok_ && col_on(S, c0, k) && !S.halfconv[c0];
-  const bool o1 = lok_ && col_on(S, c0 + 1, k) && !S.halfconv[c0 + 1];
+  double acc[3][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+  const bool o0 = lok_ && col_on(S, c0, k), o1 = lok_ && col_on(S, c0 + 1, k);
   if (S.any[3] != 0) {
     TILE_LOOP {
       const int rows = (int)min<int64_t>(TR, n - t0);
@@ -382,34 +360,38 @@ __global__ void __launch_bounds__(NT) k_at(int64_t n, int k, int kp, Csr<double>
       if (o0 || o1) {
         TILE_ROW_PROD(double, CH, CH2, A, V.sh, const double2 sv = ld2(V.s, qq);,
                       st2(V.t, qq, y0, y1, o0, o1);
-                      if (o0) { acc[0][0] += y0 * sv.x; acc[1][0] += y0 * y0; }
-                      if (o1) { acc[0][1] += y1 * sv.y; acc[1][1] += y1 * y1; })
+                      if (o0) { acc[0][0] += y0 * sv.x; acc[1][0] += y0 * y0; acc[2][0] += sv.x * sv.x; }
+                      if (o1) { acc[0][1] += y1 * sv.y; acc[1][1] += y1 * y1; acc[2][1] += sv.y * sv.y; })
       }
       __syncthreads();
     }
   }
-  block_partials<LP, 2>(acc, S);
+  block_partials<LP, 3>(acc, S);
 }
 
 // ---- x += alpha p_hat + omega s_hat, r = s - omega t; partials r_hat^T r, r^T r -----
+// Columns that converged at the half step only take x += alpha p_hat.
 template <int LP>
 __global__ void __launch_bounds__(NT) k_xr(int64_t n, int k, int kp, Vec V, State S) {
   LANES(LP)
   double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
-  const bool o0 = lok_ && col_on(S, c0, k) && !S.halfconv[c0];
-  const bool o1 = lok_ && col_on(S, c0 + 1, k) && !S.halfconv[c0 + 1];
-  const double al0 = o0 ? S.alpha[c0] : 0.0, om0 = o0 ? S.omega[c0] : 0.0;
-  const double al1 = o1 ? S.alpha[c0 + 1] : 0.0, om1 = o1 ? S.omega[c0 + 1] : 0.0;
-  if (o0 || o1) {
+  const bool a0 = lok_ && col_on(S, c0, k), a1 = lok_ && col_on(S, c0 + 1, k);
+  const bool h0 = a0 && S.halfconv[c0], h1 = a1 && S.halfconv[c0 + 1];
+  const bool o0 = a0 && !h0, o1 = a1 && !h1;  // full updates
+  const double al0 = a0 ? S.alpha[c0] : 0.0, om0 = o0 ? S.omega[c0] : 0.0;
+  const double al1 = a1 ? S.alpha[c0 + 1] : 0.0, om1 = o1 ? S.omega[c0 + 1] : 0.0;
+  if (a0 || a1) {
     ROW_LOOP {
       const int64_t q = i * kp + c0;
       const double2 x = ld2(V.x, q), ph = ld2(V.ph, q), sh = ld2(V.sh, q);
-      const double2 s = ld2(V.s, q), t = ld2(V.t, q), rh = ld2(V.rh, q);
-      st2(V.x, q, x.x + al0 * ph.x + om0 * sh.x, x.y + al1 * ph.y + om1 * sh.y, o0, o1);
-      const double r0 = s.x - om0 * t.x, r1 = s.y - om1 * t.y;
-      st2(V.r, q, r0, r1, o0, o1);
-      if (o0) { acc[0][0] += rh.x * r0; acc[1][0] += r0 * r0; }
-      if (o1) { acc[0][1] += rh.y * r1; acc[1][1] += r1 * r1; }
+      st2(V.x, q, x.x + al0 * ph.x + om0 * sh.x, x.y + al1 * ph.y + om1 * sh.y, a0, a1);
+      if (o0 || o1) {
+        const double2 s = ld2(V.s, q), t = ld2(V.t, q), rh = ld2(V.rh, q);
+        const double r0 = s.x - om0 * t.x, r1 = s.y - om1 * t.y;
+        st2(V.r, q, r0, r1, o0, o1);
+        if (o0) { acc[0][0] += rh.x * r0; acc[1][0] += r0 * r0; }
+        if (o1) { acc[0][1] += rh.y * r1; acc[1][1] += r1 * r1; }
+      }
     }
   }
   block_partials<LP, 2>(acc, S);
@@ -478,29 +460,55 @@ __global__ void __launch_bounds__(NT) k_copy_out(int64_t n, int k, int kp, const
   }
 }
 
+// ---- end of an iteration: record iterations, clear flags, count active columns ----
+// (all threads of the block call it; it synchronises)
+__device__ void iter_end_body(int k, const State& S, int it, int maxit) {
+  __shared__ int cnt;
+  const int t = threadIdx.x;
+  if (t == 0) cnt = 0;
+  __syncthreads();
+  if (t < k) {
+    int st = S.status[t];
+    if (S.halfconv[t] && st == ST_ACTIVE) st = ST_CONV;
+    if (it > 0 && S.wasact[t]) S.iters[t] = it;
+    if (st == ST_ACTIVE && it >= maxit) st = ST_MAXIT;
+    S.status[t] = st;
+    S.wasact[t] = (st == ST_ACTIVE) ? 1 : 0;
+    S.skip[t] = 0;
+    S.half[t] = S.full[t] = S.rst[t] = S.halfconv[t] = S.pend[t] = 0;
+    if (st == ST_ACTIVE) atomicAdd(&cnt, 1);
+  }
+  __syncthreads();
+  if (t == 0) {
+    S.any[0] = S.any[1] = S.any[2] = S.any[4] = 0;
+    S.any[3] = cnt;
+  }
+}
+
 // ---- finishers: one block adds the partials and updates the column state -------
-enum { F_INIT, F_AV, F_S, F_HALF, F_AT, F_XR, F_FULL, F_RESTART };
+enum { F_INIT, F_AV, F_AT, F_HALF, F_XR, F_FULL, F_RESTART_END };
 
 constexpr int FNT = 1024;  // finisher threads
 
 template <int ND, int OP>
-__global__ void __launch_bounds__(FNT) k_fin(int k, State S, int nb) {
+__global__ void __launch_bounds__(FNT) k_fin(int k, State S, int nb, int it = 0, int maxit = 0) {
   __shared__ double red[ND][FNT];
   __shared__ double tot[ND][PSTRIDE];
   // a finisher whose main kernel returned early (flag not set) has nothing to do
   if (OP == F_HALF && S.any[0] == 0) return;
   if (OP == F_FULL && S.any[1] == 0) return;
-  if (OP == F_RESTART && S.any[2] == 0) return;
+  // (F_RESTART_END always runs: it also closes the iteration)
   // thread t sums the partials b = q, q + fq, ... of column c = t % k (fq
   // threads per column, eight independent sums each); then the fq sums of a
   // column are added in order of q
   const int t = threadIdx.x;
   const int fq = FNT / k;
   const int c = t % k, q = t / k;
+  const bool sum = OP != F_RESTART_END || S.any[2] != 0;
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
     double s8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (q < fq) {
+    if (sum && q < fq) {
       const double* P = S.part + (int64_t)d * NBMAX * PSTRIDE + c;
       int b = q;
       for (; b + 7 * fq < nb; b += 8 * fq) {
@@ -521,7 +529,10 @@ __global__ void __launch_bounds__(FNT) k_fin(int k, State S, int nb) {
     }
   }
   __syncthreads();
-  if (t >= k) return;
+  if (t >= k) {
+    if constexpr (OP == F_RESTART_END) iter_end_body(k, S, it, maxit);
+    return;
+  }
   if constexpr (OP == F_INIT) {
     const double rr = tot[0][t];
     S.rho[t] = rr;
@@ -529,7 +540,7 @@ __global__ void __launch_bounds__(FNT) k_fin(int k, State S, int nb) {
     S.beta[t] = rr;
     S.skip[t] = 0;
     S.restarts[t] = 0;
-    S.half[t] = S.full[t] = S.rst[t] = S.halfconv[t] = 0;
+    S.half[t] = S.full[t] = S.rst[t] = S.halfconv[t] = S.pend[t] = 0;
     S.iters[t] = 0;
     S.status[t] = (sqrt(rr) < S.thr[t]) ? ST_CONV : ST_ACTIVE;
     if (t == 0) S.any[0] = S.any[1] = S.any[2] = S.any[4] = 0;
@@ -544,25 +555,38 @@ __global__ void __launch_bounds__(FNT) k_fin(int k, State S, int nb) {
         S.alpha[t] = S.rho[t] / sig;
       }
     }
-  } else if constexpr (OP == F_S) {
-    if (col_on(S, t, k) && sqrt(tot[0][t]) < S.thr[t]) {
-      S.half[t] = 1;
-      S.any[0] = 1;
+  } else if constexpr (OP == F_AT) {
+    // partials: t^T s, t^T t, s^T s.  The half-step check (||s|| < thr) is flagged
+    // here; a column waiting for it keeps a tiny t^T t as pending (a breakdown only
+    // if the check fails: s ~ 0 makes t ~ 0)
+    if (col_on(S, t, k)) {
+      const double tt = tot[1][t];
+      const bool half = sqrt(tot[2][t]) < S.thr[t];
+      if (half) {
+        S.half[t] = 1;
+        S.any[0] = 1;
+      }
+      if (tt < TINY) {
+        if (half) {
+          S.pend[t] = 1;
+        } else {
+          S.skip[t] = 1;
+          S.rst[t] = 1;
+          S.any[2] = 1;
+        }
+      } else {
+        S.omega[t] = tot[0][t] / tt;
+      }
     }
   } else if constexpr (OP == F_HALF) {
-    if (col_on(S, t, k) && S.half[t] && sqrt(tot[0][t]) < S.thr[t]) {
-      S.halfconv[t] = 1;
-      S.any[4] = 1;
-    }
-  } else if constexpr (OP == F_AT) {
-    if (col_on(S, t, k) && !S.halfconv[t]) {
-      const double tt = tot[1][t];
-      if (tt < TINY) {
+    if (col_on(S, t, k) && S.half[t]) {
+      if (sqrt(tot[0][t]) < S.thr[t]) {
+        S.halfconv[t] = 1;
+        S.any[4] = 1;
+      } else if (S.pend[t]) {
         S.skip[t] = 1;
         S.rst[t] = 1;
         S.any[2] = 1;
-      } else {
-        S.omega[t] = tot[0][t] / tt;
       }
     }
   } else if constexpr (OP == F_XR) {
@@ -593,8 +617,8 @@ __global__ void __launch_bounds__(FNT) k_fin(int k, State S, int nb) {
         }
       }
     }
-  } else if constexpr (OP == F_RESTART) {
-    if (S.rst[t] && S.status[t] == ST_ACTIVE) {
+  } else if constexpr (OP == F_RESTART_END) {
+    if (S.any[2] != 0 && S.rst[t] && S.status[t] == ST_ACTIVE) {
       const double rr = tot[0][t];
       S.rho[t] = rr;
       S.rho_old[t] = S.alpha[t] = S.omega[t] = 1.0;
@@ -603,31 +627,10 @@ __global__ void __launch_bounds__(FNT) k_fin(int k, State S, int nb) {
       if (S.restarts[t] > 1) S.status[t] = ST_BREAK;
     }
   }
+  if constexpr (OP == F_RESTART_END) iter_end_body(k, S, it, maxit);
 }
 
-// ---- end of an iteration: record iterations, clear flags, count active columns ----
-__global__ void k_iter_end(int k, State S, int it, int maxit) {
-  __shared__ int cnt;
-  const int t = threadIdx.x;
-  if (t == 0) cnt = 0;
-  __syncthreads();
-  if (t < k) {
-    int st = S.status[t];
-    if (S.halfconv[t] && st == ST_ACTIVE) st = ST_CONV;
-    if (it > 0 && S.wasact[t]) S.iters[t] = it;
-    if (st == ST_ACTIVE && it >= maxit) st = ST_MAXIT;
-    S.status[t] = st;
-    S.wasact[t] = (st == ST_ACTIVE) ? 1 : 0;
-    S.skip[t] = 0;
-    S.half[t] = S.full[t] = S.rst[t] = S.halfconv[t] = 0;
-    if (st == ST_ACTIVE) atomicAdd(&cnt, 1);
-  }
-  __syncthreads();
-  if (t == 0) {
-    S.any[0] = S.any[1] = S.any[2] = S.any[4] = 0;
-    S.any[3] = cnt;
-  }
-}
+__global__ void k_iter_end(int k, State S, int it, int maxit) { iter_end_body(k, S, it, maxit); }
 
 }  // namespace
 }  // namespace sai

@@ -16,7 +16,12 @@
 // residual (s at the half step, r at the full step) falls below the column's
 // threshold; a failed full-step check replaces r by the true residual.  A
 // breakdown (|rho|, |r_hat^T v|, |omega| or t^T t below 1e-300) restarts the
-// column once with r_hat = r; a second one stops it.
+// column once with r_hat = r; a second one stops it.  ||s|| is summed with t^T s
+// and t^T t (one reduction instead of two), so the half-step check runs after
+// t = A M s is formed; a column that converges there takes x += alpha p_hat
+// and its t is unused.  One iteration is 16 launches: 5 streaming kernels, 4
+// sparse products, 2 true-residual checks that return at once unless a column
+// is flagged, and 5 one-block finishers.
 //
 // GMRES(m) (used for the smallest workload) runs one workgroup per column for
 // the whole solve: modified Gram-Schmidt Arnoldi, Givens rotations, solution
@@ -37,9 +42,9 @@ int bicgstab_lp(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, const 
   DBuf<double> b(&al, nk), x(&al, nk), r(&al, nk), rh(&al, nk), p(&al, nk), v(&al, nk), s(&al, nk),
       ph(&al, nk), sh(&al, nk), t(&al, nk);
   DBuf<double> sc(&al, 6 * 64);
-  DBuf<int> si(&al, 9 * 64 + 8);
-  DBuf<double> part(&al, (size_t)2 * NBMAX * PSTRIDE);
-  HIPC(hipMemsetAsync(si.p, 0, sizeof(int) * (9 * 64 + 8), st));
+  DBuf<int> si(&al, 10 * 64 + 8);
+  DBuf<double> part(&al, (size_t)3 * NBMAX * PSTRIDE);
+  HIPC(hipMemsetAsync(si.p, 0, sizeof(int) * (10 * 64 + 8), st));
   HIPC(hipMemcpyAsync(sc.p + 5 * 64, thr, sizeof(double) * k, hipMemcpyHostToDevice, st));
   State S;
   S.rho = sc.p;
@@ -57,7 +62,8 @@ int bicgstab_lp(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, const 
   S.rst = si.p + 384;
   S.halfconv = si.p + 448;
   S.wasact = si.p + 512;
-  S.any = si.p + 576;
+  S.pend = si.p + 576;
+  S.any = si.p + 640;
   S.part = part.p;
   Vec V{b.p, x.p, r.p, rh.p, p.p, v.p, s.p, ph.p, sh.p, t.p};
   constexpr int RPB = (64 / LP) * (NT / 64);
@@ -114,7 +120,7 @@ int bicgstab_lp(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, const 
   {
     SAI_PROF("bicg_init", st);
     hipLaunchKernelGGL((k_init<LP>), dim3(grid), dim3(NT), 0, st, n, k, kp, R, V, S);
-    hipLaunchKernelGGL((k_fin<1, F_INIT>), dim3(1), dim3(FNT), 0, st, k, S, grid);
+    hipLaunchKernelGGL((k_fin<1, F_INIT>), dim3(1), dim3(FNT), 0, st, k, S, grid, 0, 0);
   }
   LAUNCH_CHECK();
   hipLaunchKernelGGL(k_iter_end, dim3(1), dim3(64), 0, st, k, S, 0, maxit);
@@ -152,12 +158,8 @@ int bicgstab_lp(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, const 
       SAI_PROF("bicg_spmm_A_dot1", st);
       spmm_av();
     }
-    LK("bicg_finish", (k_fin<1, F_AV>), dim3(1), dim3(FNT), 0, st, k, S, tgrid);
+    LK("bicg_finish", (k_fin<1, F_AV>), dim3(1), dim3(FNT), 0, st, k, S, tgrid, 0, 0);
     LK("bicg_s_update", (k_s<LP>), dim3(grid), dim3(NT), 0, st, n, k, kp, V, S);
-    LK("bicg_finish", (k_fin<1, F_S>), dim3(1), dim3(FNT), 0, st, k, S, grid);
-    LK("bicg_halfcheck", (k_halfcheck<LP>), dim3(grid), dim3(NT), 0, st, n, k, kp, A, V, S);
-    LK("bicg_finish", (k_fin<1, F_HALF>), dim3(1), dim3(FNT), 0, st, k, S, grid);
-    LK("bicg_halfapply", (k_halfapply<LP>), dim3(grid), dim3(NT), 0, st, n, k, kp, V, S);
     {
       SAI_PROF(MF ? "bicg_spmm_M_f32" : "bicg_spmm_M_f64", st);
       spmm_m(V.s, V.sh);
@@ -166,14 +168,15 @@ int bicgstab_lp(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, const 
       SAI_PROF("bicg_spmm_A_dot2", st);
       spmm_at();
     }
-    LK("bicg_finish", (k_fin<2, F_AT>), dim3(1), dim3(FNT), 0, st, k, S, tgrid);
+    LK("bicg_finish", (k_fin<3, F_AT>), dim3(1), dim3(FNT), 0, st, k, S, tgrid, 0, 0);
+    LK("bicg_halfcheck", (k_halfcheck<LP>), dim3(grid), dim3(NT), 0, st, n, k, kp, A, V, S);
+    LK("bicg_finish", (k_fin<1, F_HALF>), dim3(1), dim3(FNT), 0, st, k, S, grid, 0, 0);
     LK("bicg_xr_update", (k_xr<LP>), dim3(grid), dim3(NT), 0, st, n, k, kp, V, S);
-    LK("bicg_finish", (k_fin<2, F_XR>), dim3(1), dim3(FNT), 0, st, k, S, grid);
+    LK("bicg_finish", (k_fin<2, F_XR>), dim3(1), dim3(FNT), 0, st, k, S, grid, 0, 0);
     LK("bicg_fullcheck", (k_fullcheck<LP>), dim3(grid), dim3(NT), 0, st, n, k, kp, A, V, S);
-    LK("bicg_finish", (k_fin<2, F_FULL>), dim3(1), dim3(FNT), 0, st, k, S, grid);
+    LK("bicg_finish", (k_fin<2, F_FULL>), dim3(1), dim3(FNT), 0, st, k, S, grid, 0, 0);
     LK("bicg_restart", (k_restart<LP>), dim3(grid), dim3(NT), 0, st, n, k, kp, V, S);
-    LK("bicg_finish", (k_fin<1, F_RESTART>), dim3(1), dim3(FNT), 0, st, k, S, grid);
-    LK("bicg_iter_end", k_iter_end, dim3(1), dim3(64), 0, st, k, S, it, maxit);
+    LK("bicg_finish_end", (k_fin<1, F_RESTART_END>), dim3(1), dim3(FNT), 0, st, k, S, grid, it, maxit);
 #undef LK
     LAUNCH_CHECK();
     HIPC(hipMemcpyAsync(slot + (it & 1), S.any + 3, sizeof(int), hipMemcpyDeviceToHost, st));
