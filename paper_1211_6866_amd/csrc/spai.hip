@@ -28,7 +28,7 @@ constexpr int SNT = 256;
 constexpr int SJMAX = 128;   // |J_k| limit during the search
 constexpr int SCAPI = 2048;  // |I_k| limit during the search
 constexpr int SCAPN = 8192;  // candidate entries before de-duplication
-constexpr int NSLOT = 512;   // columns searched concurrently (workspace slots)
+constexpr int NSLOT_MAX = 4096;  // columns searched concurrently (workspace slots), at most
 
 enum { E_TOOBIG = 1, E_SING = 2 };
 
@@ -430,7 +430,11 @@ void spai_patterns(const sai_split_s* sp, const sai_build_opts& o, hipStream_t s
   const int64_t ptot = read_scalar(poff.p + n, st);
   DBuf<int32_t> pad(&al, (size_t)ptot + 1);
   cntJ.alloc(&al, (size_t)n + 1);
-  const int nslot = (int)std::min<int64_t>(n, NSLOT);
+  // one workspace slot per resident workgroup (the search is latency-bound:
+  // every workgroup the device can hold at once gets a column)
+  const int nslot = (int)std::min<int64_t>(
+      {(int64_t)n, (int64_t)NSLOT_MAX,
+       (int64_t)tune_get("SPAI_SLOTS", resident_blocks((const void*)k_spai, SNT))});
   DBuf<int32_t> wI(&al, (size_t)nslot * SCAPI), wc(&al, (size_t)nslot * SCAPN),
       wo(&al, (size_t)nslot * (SCAPI + 1));
   DBuf<double> wW(&al, (size_t)nslot * SCAPI * (SJMAX + 1)), wr(&al, (size_t)nslot * SCAPI),
