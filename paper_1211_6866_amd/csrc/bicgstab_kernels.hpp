@@ -25,10 +25,17 @@ constexpr int NT = 256;
 constexpr int NBMAX = 2048;
 constexpr int PSTRIDE = 64;  // partial sums: [ND][NBMAX][PSTRIDE] doubles
 // staged entries per tile (RPB rows): A~ (regular part, about 2p entries per
-// row) gets 12 per row, at least 512, at most 2048; M gets 2048.  A smaller
-// staging area lets more workgroups share a CU.
+// row) gets 12 per row, at least 512, at most 2048 (a smaller staging area lets
+// more workgroups share a CU); M gets 32 per row, at least 2048, within 40 KB of
+// LDS (index and value per entry).  Tiles that do not fit are read from global
+// memory.
 constexpr int cap_a(int rpb) { return rpb * 12 < 512 ? 512 : (rpb * 12 > 2048 ? 2048 : rpb * 12); }
-constexpr int CAP_M = 2048;
+template <class TV>
+constexpr int cap_m(int rpb) {
+  const int lim = (40 * 1024) / (int)(4 + sizeof(TV));
+  const int want = rpb * 32 < 2048 ? 2048 : rpb * 32;
+  return want < lim ? want : lim;
+}
 constexpr double TINY = 1e-300;
 
 enum { ST_ACTIVE = 0, ST_CONV = 1, ST_MAXIT = 2, ST_BREAK = 3 };
@@ -129,10 +136,16 @@ __device__ __forceinline__ void row_prod(const int32_t* __restrict__ ci, const T
 }
 
 // Block-reduce ND per-lane accumulator pairs (per column) in a fixed order and
-// publish the block's partial sums for the finisher.
+// publish the block's partial sums for the finisher.  Slot 2t+j (of 2 NT) holds
+// thread t's value for column 2((t & 63) % LP) + j, so slot s belongs to wave
+// s / 128 and wave row (s % 128) / (2 LP).  A tree first adds the wavefronts
+// (strides 256, 128), then, while LP is a power of two, the rows of a wavefront
+// (strides 64 ... 2 LP); for LP = 6 and 12 a short serial sum over the 64 / LP
+// rows finishes.
 template <int LP, int ND>
 __device__ void block_partials(double (&acc)[ND][2], const State& S) {
   constexpr int RPW = 64 / LP;
+  constexpr bool POW2 = (LP & (LP - 1)) == 0;
   __shared__ double red[ND][2 * NT];
   const int t = threadIdx.x;
 #pragma unroll
@@ -141,17 +154,24 @@ __device__ void block_partials(double (&acc)[ND][2], const State& S) {
     red[d][2 * t + 1] = acc[d][1];
   }
   __syncthreads();
+  // across wavefronts, then (power-of-two LP) across the rows of a wavefront
+  constexpr int LAST = POW2 ? 2 * LP : 128;
+#pragma unroll 1
+  for (int stride = NT; stride >= LAST; stride >>= 1) {
+    if (t < stride) {
+#pragma unroll
+      for (int d = 0; d < ND; ++d) red[d][t] += red[d][t + stride];
+    }
+    __syncthreads();
+  }
   if (t < 2 * LP) {
-    const int l = t >> 1, j = t & 1;
-    // a short loop (not unrolled: only 2 LP threads run it, and unrolled it
-    // would hold every LDS value in registers across the whole kernel)
 #pragma unroll 1
     for (int d = 0; d < ND; ++d) {
-      double s = 0.0;
+      double s = red[d][t];
+      if constexpr (!POW2) {
 #pragma unroll 1
-      for (int w = 0; w < NT / 64; ++w)
-#pragma unroll 2
-        for (int rw = 0; rw < RPW; ++rw) s += red[d][2 * (w * 64 + rw * LP + l) + j];
+        for (int rw = 1; rw < RPW; ++rw) s += red[d][t + 2 * LP * rw];
+      }
       S.part[((int64_t)d * NBMAX + blockIdx.x) * PSTRIDE + t] = s;
     }
   }
@@ -267,6 +287,7 @@ __global__ void __launch_bounds__(NT) k_spmm(int64_t n, int k, int kp, Csr<TV> A
                                              const double* __restrict__ X, double* __restrict__ Y,
                                              State S, int xmap) {
   LANES(LP)
+  constexpr int CAP_M = cap_m<TV>(RPB);
   STAGE_DECL(TV, CAP_M, RPB)
   if (S.any[3] == 0) return;
   const bool o0 = lok_ && col_on(S, c0, k), o1 = lok_ && col_on(S, c0 + 1, k);
@@ -499,8 +520,7 @@ __global__ void __launch_bounds__(FNT) k_fin(int k, State S, int nb, int it = 0,
   if (OP == F_FULL && S.any[1] == 0) return;
   // (F_RESTART_END always runs: it also closes the iteration)
   // thread t sums the partials b = q, q + fq, ... of column c = t % k (fq
-  // threads per column, eight independent sums each); then the fq sums of a
-  // column are added in order of q
+  // threads per column, eight independent sums each)
   const int t = threadIdx.x;
   const int fq = FNT / k;
   const int c = t % k, q = t / k;
@@ -520,13 +540,21 @@ __global__ void __launch_bounds__(FNT) k_fin(int k, State S, int nb, int it = 0,
     red[d][t] = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
   }
   __syncthreads();
+  // the fq sums of a column meet in a tree: at each level the upper half of
+  // the remaining sums (q >= h) is added onto the lower half (q - h)
+#pragma unroll 1
+  for (int cur = fq; cur > 1;) {
+    const int h = (cur + 1) >> 1;
+    if (q + h < cur) {
+#pragma unroll
+      for (int d = 0; d < ND; ++d) red[d][t] += red[d][t + h * k];
+    }
+    __syncthreads();
+    cur = h;
+  }
   if (t < k) {
 #pragma unroll
-    for (int d = 0; d < ND; ++d) {
-      double s = 0.0;
-      for (int r = 0; r < fq; ++r) s += red[d][r * k + t];
-      tot[d][t] = s;
-    }
+    for (int d = 0; d < ND; ++d) tot[d][t] = red[d][t];
   }
   __syncthreads();
   if (t >= k) {

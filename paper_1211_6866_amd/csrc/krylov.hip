@@ -33,39 +33,108 @@
 namespace sai {
 namespace {
 
+// ---- batched BiCGStab driver ---------------------------------------------------------
+//
+// The k systems start in one n x kp block.  When enough columns have stopped that
+// the remaining ones fit a narrower lane class, the block is narrowed: the stopped
+// columns' x (and status, iteration count) are handed out, the active columns'
+// vectors and scalars are gathered into a new block, and the iteration continues
+// there with fewer lanes per row.  Each column's arithmetic is unchanged (its
+// products, updates and stopping tests do not depend on the other columns; only
+// the order of the partial sums of its dot products follows the grid).
+
+// lanes per row for k columns: the smallest of 1, 2, 4, 6, 8, 12, 16, 32 covering
+// the column pairs
+int lp_class(int k) {
+  const int pairs = (k + 1) / 2;
+  const int cls[] = {1, 2, 4, 6, 8, 12, 16, 32};
+  for (int c : cls)
+    if (pairs <= c) return c;
+  return 32;
+}
+
+// For each of nv vector pairs: dst[i, to[q]] = src[i, from[q]] for q < np (and
+// dst[i, zero_col] = 0 when zero_col >= 0); one thread per (row, column)
+struct ColCopy {
+  const double* src[10];
+  double* dst[10];
+};
+__global__ void __launch_bounds__(NT) k_cols_copy(int64_t n, ColCopy cc, int nv, int lds, int ldd,
+                                                  const int* __restrict__ from, const int* __restrict__ to,
+                                                  int np, int zero_col) {
+  const int w = np + (zero_col >= 0 ? 1 : 0);
+  for (int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x; t < n * w; t += (int64_t)gridDim.x * NT) {
+    const int64_t i = t / w;
+    const int q = (int)(t % w);
+    for (int v = 0; v < nv; ++v) {
+      if (q < np) cc.dst[v][i * ldd + to[q]] = cc.src[v][i * lds + from[q]];
+      else cc.dst[v][i * ldd + zero_col] = 0.0;
+    }
+  }
+}
+
+// One block of systems: n x kp vectors (b, x, r, r_hat, p, v, s, p_hat, s_hat, t),
+// per-column scalars and flags, and the caller's column of each block column.
+struct Block {
+  int k = 0, kp = 0;
+  std::vector<int> cols;
+  DBuf<double> vec[10];
+  DBuf<double> sc;  // rho, rho_old, alpha, omega, beta, thr (64 each)
+  DBuf<int> si;     // status, iters, skip, restarts, half, full, rst, halfconv, wasact, pend (64 each), any
+  State S{};
+  Vec V{};
+};
+constexpr int SC_N = 6 * 64, SI_N = 10 * 64 + 8;
+
+// Set B up for k columns; the vector buffers are (re)allocated only when their
+// capacity (cap columns) is smaller than needed.
+void block_alloc(Block& B, int k, int64_t n, const Allocator& al, double* part, hipStream_t st,
+                 int& cap) {
+  B.k = k;
+  B.kp = k + (k & 1);
+  if (cap < B.kp) {
+    const size_t nk = (size_t)n * B.kp;
+    for (auto& v : B.vec) v.alloc(&al, nk);
+    cap = B.kp;
+  }
+  if (!B.sc.p) B.sc.alloc(&al, SC_N);
+  if (!B.si.p) B.si.alloc(&al, SI_N);
+  HIPC(hipMemsetAsync(B.sc.p, 0, sizeof(double) * SC_N, st));
+  HIPC(hipMemsetAsync(B.si.p, 0, sizeof(int) * SI_N, st));
+  State& S = B.S;
+  S.rho = B.sc.p;
+  S.rho_old = B.sc.p + 64;
+  S.alpha = B.sc.p + 128;
+  S.omega = B.sc.p + 192;
+  S.beta = B.sc.p + 256;
+  S.thr = B.sc.p + 320;
+  S.status = B.si.p;
+  S.iters = B.si.p + 64;
+  S.skip = B.si.p + 128;
+  S.restarts = B.si.p + 192;
+  S.half = B.si.p + 256;
+  S.full = B.si.p + 320;
+  S.rst = B.si.p + 384;
+  S.halfconv = B.si.p + 448;
+  S.wasact = B.si.p + 512;
+  S.pend = B.si.p + 576;
+  S.any = B.si.p + 640;
+  S.part = part;
+  B.V = Vec{B.vec[0].p, B.vec[1].p, B.vec[2].p, B.vec[3].p, B.vec[4].p,
+            B.vec[5].p, B.vec[6].p, B.vec[7].p, B.vec[8].p, B.vec[9].p};
+}
+
+enum { IT_DONE = 0, IT_NARROW = 1 };
+
+// Iterations it, it+1, ... on block B with LP lanes per row, until every column
+// has stopped or maxit is reached (IT_DONE), or the active columns would fit a
+// narrower lane class (IT_NARROW).  The first phase also initialises from R.
 template <int LP, class TM>
-int bicgstab_lp(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, const double* R,
-                double* X, const double* thr, int maxit, const Allocator& al, hipStream_t st,
-                int* iters, int* status) {
-  const int kp = k + (k & 1);
-  const size_t nk = (size_t)n * kp;
-  DBuf<double> b(&al, nk), x(&al, nk), r(&al, nk), rh(&al, nk), p(&al, nk), v(&al, nk), s(&al, nk),
-      ph(&al, nk), sh(&al, nk), t(&al, nk);
-  DBuf<double> sc(&al, 6 * 64);
-  DBuf<int> si(&al, 10 * 64 + 8);
-  DBuf<double> part(&al, (size_t)3 * NBMAX * PSTRIDE);
-  HIPC(hipMemsetAsync(si.p, 0, sizeof(int) * (10 * 64 + 8), st));
-  HIPC(hipMemcpyAsync(sc.p + 5 * 64, thr, sizeof(double) * k, hipMemcpyHostToDevice, st));
-  State S;
-  S.rho = sc.p;
-  S.rho_old = sc.p + 64;
-  S.alpha = sc.p + 128;
-  S.omega = sc.p + 192;
-  S.beta = sc.p + 256;
-  S.thr = sc.p + 320;
-  S.status = si.p;
-  S.iters = si.p + 64;
-  S.skip = si.p + 128;
-  S.restarts = si.p + 192;
-  S.half = si.p + 256;
-  S.full = si.p + 320;
-  S.rst = si.p + 384;
-  S.halfconv = si.p + 448;
-  S.wasact = si.p + 512;
-  S.pend = si.p + 576;
-  S.any = si.p + 640;
-  S.part = part.p;
-  Vec V{b.p, x.p, r.p, rh.p, p.p, v.p, s.p, ph.p, sh.p, t.p};
+int iterate(Block& B, const Csr<double>& A, const Csr<TM>& M, int64_t n, int& it, int maxit, bool first,
+            bool narrow_ok, const double* R, hipStream_t st, int* slot, hipEvent_t* ev) {
+  const int k = B.k, kp = B.kp;
+  const State S = B.S;
+  const Vec V = B.V;
   constexpr int RPB = (64 / LP) * (NT / 64);
   // streaming kernels: a grid-stride loop over rows (fewer blocks also means
   // fewer partial sums for the finishers to add)
@@ -79,6 +148,7 @@ int bicgstab_lp(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, const 
   // XCDs together (interleaved tiles), so that one band, not eight, must stay
   // resident in the MALL.
   const bool persist = tune_get("PERSIST", 1) != 0;
+  const size_t nk = (size_t)n * kp;
   const int xmap = tune_get("XMAP", nk * sizeof(double) <= (size_t(256) << 20) ? 1 : 0);
   auto sp_grid = [&](const void* kern) {
     const int64_t ntiles = (n + RPB - 1) / RPB;
@@ -117,32 +187,25 @@ int bicgstab_lp(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, const 
     else if (avar == 2) hipLaunchKernelGGL((k_at<LP, 7, 0>), dim3(tgrid), dim3(NT), 0, st, n, k, kp, A, V, S, xmap);
     else hipLaunchKernelGGL((k_at<LP, 4, 2>), dim3(tgrid), dim3(NT), 0, st, n, k, kp, A, V, S, xmap);
   };
-  {
-    SAI_PROF("bicg_init", st);
-    hipLaunchKernelGGL((k_init<LP>), dim3(grid), dim3(NT), 0, st, n, k, kp, R, V, S);
-    hipLaunchKernelGGL((k_fin<1, F_INIT>), dim3(1), dim3(FNT), 0, st, k, S, grid, 0, 0);
+  if (first) {
+    {
+      SAI_PROF("bicg_init", st);
+      hipLaunchKernelGGL((k_init<LP>), dim3(grid), dim3(NT), 0, st, n, k, kp, R, V, S);
+      hipLaunchKernelGGL((k_fin<1, F_INIT>), dim3(1), dim3(FNT), 0, st, k, S, grid, 0, 0);
+    }
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_iter_end, dim3(1), dim3(64), 0, st, k, S, 0, maxit);
+    LAUNCH_CHECK();
+    HIPC(hipMemcpyAsync(slot, S.any + 3, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    if (slot[0] == 0) return IT_DONE;
   }
-  LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_iter_end, dim3(1), dim3(64), 0, st, k, S, 0, maxit);
-  LAUNCH_CHECK();
   // The active-column count of iteration it is read back while iteration it+1
   // runs (two pinned slots, one event each), so the device never waits for the
   // host.  An iteration queued after the last column stopped finds no active
   // column and does no work.
-  HostStage hs(16);
-  int* slot = hs.as<int>();
-  hipEvent_t ev[2];
-  HIPC(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
-  HIPC(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
-  struct EvGuard {
-    hipEvent_t* e;
-    ~EvGuard() { (void)hipEventDestroy(e[0]); (void)hipEventDestroy(e[1]); }
-  } evg{ev};
-  HIPC(hipMemcpyAsync(slot, S.any + 3, sizeof(int), hipMemcpyDeviceToHost, st));
-  HIPC(hipEventRecord(ev[0], st));
-  HIPC(hipEventSynchronize(ev[0]));
-  bool go_on = slot[0] > 0;
-  for (int it = 1; it <= maxit && go_on; ++it) {
+  const int it0 = it;
+  for (; it <= maxit; ++it) {
 #define LK(name, ...)              \
   do {                             \
     SAI_PROF(name, st);            \
@@ -181,23 +244,154 @@ int bicgstab_lp(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, const 
     LAUNCH_CHECK();
     HIPC(hipMemcpyAsync(slot + (it & 1), S.any + 3, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPC(hipEventRecord(ev[it & 1], st));
-    if (it > 1) {
+    if (it > it0) {
       // count after iteration it-1 (iteration it is already queued behind it)
       HIPC(hipEventSynchronize(ev[(it - 1) & 1]));
-      go_on = slot[(it - 1) & 1] > 0;
+      const int act = slot[(it - 1) & 1];
+      if (act == 0) {
+        ++it;
+        return IT_DONE;
+      }
+      // narrow when the active columns fit a smaller lane class and the rows x
+      // columns dropped from every later iteration repay the cost of moving the
+      // block (about one iteration of idle device plus a copy)
+      const int64_t drop = n * (int64_t)(kp - (act + (act & 1)));
+      if (narrow_ok && LP > 1 && lp_class(act) < LP && 2 * act <= k &&
+          drop >= (int64_t)tune_get("NARROW_MIN", 2000000)) {
+        ++it;
+        return IT_NARROW;
+      }
     }
   }
-  hipLaunchKernelGGL((k_copy_out<LP>), dim3(grid), dim3(NT), 0, st, n, k, kp, V.x, X);
+  return IT_DONE;
+}
+
+template <class TM>
+int iterate_lp(int lp, Block& B, const Csr<double>& A, const Csr<TM>& M, int64_t n, int& it, int maxit,
+               bool first, bool narrow_ok, const double* R, hipStream_t st, int* slot, hipEvent_t* ev) {
+  switch (lp) {
+    case 1: return iterate<1, TM>(B, A, M, n, it, maxit, first, narrow_ok, R, st, slot, ev);
+    case 2: return iterate<2, TM>(B, A, M, n, it, maxit, first, narrow_ok, R, st, slot, ev);
+    case 4: return iterate<4, TM>(B, A, M, n, it, maxit, first, narrow_ok, R, st, slot, ev);
+    case 6: return iterate<6, TM>(B, A, M, n, it, maxit, first, narrow_ok, R, st, slot, ev);
+    case 8: return iterate<8, TM>(B, A, M, n, it, maxit, first, narrow_ok, R, st, slot, ev);
+    case 12: return iterate<12, TM>(B, A, M, n, it, maxit, first, narrow_ok, R, st, slot, ev);
+    case 16: return iterate<16, TM>(B, A, M, n, it, maxit, first, narrow_ok, R, st, slot, ev);
+    default: return iterate<32, TM>(B, A, M, n, it, maxit, first, narrow_ok, R, st, slot, ev);
+  }
+}
+
+// copy columns from[q] of each source (row stride lds) to columns to[q] of the
+// matching destination (row stride ldd); idx: a device array of 128 ints, hidx
+// a pinned host array of 128 ints that must stay unchanged until the copy ran
+void cols_copy(int64_t n, const ColCopy& cc, int nv, int lds, int ldd, const std::vector<int>& from,
+               const std::vector<int>& to, int zero_col, int* idx, int* hidx, hipStream_t st) {
+  const int np = (int)from.size();
+  if (np == 0 && zero_col < 0) return;
+  for (int q = 0; q < np; ++q) {
+    hidx[q] = from[q];
+    hidx[64 + q] = to[q];
+  }
+  HIPC(hipMemcpyAsync(idx, hidx, sizeof(int) * 2 * 64, hipMemcpyHostToDevice, st));
+  const int64_t work = n * (np + (zero_col >= 0 ? 1 : 0));
+  hipLaunchKernelGGL(k_cols_copy, dim3(grid_for(work, NT, 8192)), dim3(NT), 0, st, n, cc, nv, lds, ldd,
+                     idx, idx + 64, np, zero_col);
   LAUNCH_CHECK();
-  std::vector<int> hst(k), hit(k);
-  HIPC(hipMemcpyAsync(hst.data(), S.status, sizeof(int) * k, hipMemcpyDeviceToHost, st));
-  HIPC(hipMemcpyAsync(hit.data(), S.iters, sizeof(int) * k, hipMemcpyDeviceToHost, st));
+}
+
+template <class TM>
+int bicgstab(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, const double* R, double* X,
+             const double* thr, int maxit, const Allocator& al, hipStream_t st, int* iters, int* status) {
+  DBuf<double> part(&al, (size_t)3 * NBMAX * PSTRIDE);
+  // two sets of block buffers, used alternately when the block narrows
+  Block blk[2];
+  int cap[2] = {0, 0};
+  int cur = 0;
+  block_alloc(blk[0], k, n, al, part.p, st, cap[0]);
+  blk[0].cols.resize(k);
+  for (int c = 0; c < k; ++c) blk[0].cols[c] = c;
+  HIPC(hipMemcpyAsync(blk[0].S.thr, thr, sizeof(double) * k, hipMemcpyHostToDevice, st));
+  DBuf<int> idx(&al, 2 * 2 * 64);
+  HostStage hs(16 + 2 * 2 * 64 * sizeof(int) + sizeof(double) * SC_N + sizeof(int) * SI_N);
+  int* slot = hs.as<int>();
+  int* hidx = slot + 4;                                   // 2 x 128 ints
+  double* hsc = reinterpret_cast<double*>(hidx + 256);    // SC_N
+  int* hsi = reinterpret_cast<int*>(hsc + SC_N);           // SI_N
+  hipEvent_t ev[2];
+  HIPC(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+  HIPC(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+  struct EvGuard {
+    hipEvent_t* e;
+    ~EvGuard() { (void)hipEventDestroy(e[0]); (void)hipEventDestroy(e[1]); }
+  } evg{ev};
+  const bool narrow_ok = tune_get("NARROW", 1) != 0;
+  std::vector<int> rstat(k, ST_MAXIT), riter(k, 0);
+  int it = 1;
+  bool first = true;
+  for (;;) {
+    Block& B = blk[cur];
+    const int r = iterate_lp<TM>(lp_class(B.k), B, A, M, n, it, maxit, first, narrow_ok, R, st, slot, ev);
+    first = false;
+    HIPC(hipMemcpyAsync(hsc, B.sc.p, sizeof(double) * SC_N, hipMemcpyDeviceToHost, st));
+    HIPC(hipMemcpyAsync(hsi, B.si.p, sizeof(int) * SI_N, hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    // hand out the stopped columns (all of them at the end)
+    std::vector<int> keep, from, to;
+    for (int c = 0; c < B.k; ++c) {
+      if (r == IT_NARROW && hsi[c] == ST_ACTIVE) {
+        keep.push_back(c);
+      } else {
+        rstat[B.cols[c]] = hsi[c];
+        riter[B.cols[c]] = hsi[64 + c];
+        from.push_back(c);
+        to.push_back(B.cols[c]);
+      }
+    }
+    {
+      ColCopy cc{};
+      cc.src[0] = B.V.x;
+      cc.dst[0] = X;
+      cols_copy(n, cc, 1, B.kp, k, from, to, -1, idx.p, hidx, st);
+    }
+    if (keep.empty()) break;
+    // narrow: gather the active columns' vectors and scalars into the other set
+    Block& NB = blk[1 - cur];
+    block_alloc(NB, (int)keep.size(), n, al, part.p, st, cap[1 - cur]);
+    NB.cols.resize(keep.size());
+    std::vector<int> to2(keep.size());
+    for (size_t q = 0; q < keep.size(); ++q) {
+      NB.cols[q] = B.cols[keep[q]];
+      to2[q] = (int)q;
+    }
+    const int zc = (NB.k & 1) ? NB.k : -1;  // the pad column of the new block
+    {
+      ColCopy cc{};
+      for (int v = 0; v < 10; ++v) {
+        cc.src[v] = B.vec[v].p;
+        cc.dst[v] = NB.vec[v].p;
+      }
+      cols_copy(n, cc, 10, B.kp, NB.kp, keep, to2, zc, idx.p + 128, hidx + 128, st);
+    }
+    // scalars of the kept columns, in the pinned stage (read back above)
+    std::vector<double> nsc(SC_N, 0.0);
+    std::vector<int> nsi(SI_N, 0);
+    for (size_t q = 0; q < keep.size(); ++q) {
+      for (int a = 0; a < 6; ++a) nsc[a * 64 + q] = hsc[a * 64 + keep[q]];
+      for (int a = 0; a < 10; ++a) nsi[a * 64 + q] = hsi[a * 64 + keep[q]];
+    }
+    nsi[640 + 3] = (int)keep.size();  // active count; the flags are clear between iterations
+    std::memcpy(hsc, nsc.data(), sizeof(double) * SC_N);
+    std::memcpy(hsi, nsi.data(), sizeof(int) * SI_N);
+    HIPC(hipMemcpyAsync(NB.sc.p, hsc, sizeof(double) * SC_N, hipMemcpyHostToDevice, st));
+    HIPC(hipMemcpyAsync(NB.si.p, hsi, sizeof(int) * SI_N, hipMemcpyHostToDevice, st));
+    cur = 1 - cur;
+  }
   HIPC(hipStreamSynchronize(st));
   int worst = SAI_OK;
   for (int c = 0; c < k; ++c) {
-    int code = hst[c] == ST_CONV ? 0 : (hst[c] == ST_BREAK ? 2 : 1);
+    const int code = rstat[c] == ST_CONV ? 0 : (rstat[c] == ST_BREAK ? 2 : 1);
     if (status) status[c] = code;
-    if (iters) iters[c] = hit[c];
+    if (iters) iters[c] = riter[c];
     if (code == 2) worst = SAI_EBREAKDOWN;
     else if (code == 1 && worst == SAI_OK) worst = SAI_ENOCONV;
   }
@@ -393,16 +587,7 @@ int krylov_typed(const sai_split_s* sp, const sai_precond_s* pc, int transpose, 
   const int64_t n = sp->n;
   if (o.method == SAI_GMRES)
     return gmres_run<TM>(A, M, n, k, R, X, thr, o.restart, o.maxit, al, st, iters, status);
-  // lanes per row: the smallest of 1, 2, 4, 6, 8, 12, 16, 32 covering the pairs
-  const int pairs = (k + 1) / 2;
-  if (pairs <= 1) return bicgstab_lp<1, TM>(A, M, n, k, R, X, thr, o.maxit, al, st, iters, status);
-  if (pairs <= 2) return bicgstab_lp<2, TM>(A, M, n, k, R, X, thr, o.maxit, al, st, iters, status);
-  if (pairs <= 4) return bicgstab_lp<4, TM>(A, M, n, k, R, X, thr, o.maxit, al, st, iters, status);
-  if (pairs <= 6) return bicgstab_lp<6, TM>(A, M, n, k, R, X, thr, o.maxit, al, st, iters, status);
-  if (pairs <= 8) return bicgstab_lp<8, TM>(A, M, n, k, R, X, thr, o.maxit, al, st, iters, status);
-  if (pairs <= 12) return bicgstab_lp<12, TM>(A, M, n, k, R, X, thr, o.maxit, al, st, iters, status);
-  if (pairs <= 16) return bicgstab_lp<16, TM>(A, M, n, k, R, X, thr, o.maxit, al, st, iters, status);
-  return bicgstab_lp<32, TM>(A, M, n, k, R, X, thr, o.maxit, al, st, iters, status);
+  return bicgstab<TM>(A, M, n, k, R, X, thr, o.maxit, al, st, iters, status);
 }
 
 }  // namespace
