@@ -21,7 +21,7 @@ __device__ __forceinline__ int lane_id() { return threadIdx.x & (WAVE - 1); }
 // (or -1 if it would exceed cap).  L and the scratch arrays live in LDS.
 __device__ int gather_cols(const int32_t* __restrict__ cp, const int32_t* __restrict__ ri,
                            const int32_t* L, int nL, int32_t* cand, int cap, int32_t* s_start,
-                           int32_t* s_off /* nL+1 */) {
+                           int32_t* s_off /* nL */) {
   const int l = lane_id();
   // column starts and a running prefix of the counts
   int base = 0;
@@ -44,7 +44,6 @@ __device__ int gather_cols(const int32_t* __restrict__ cp, const int32_t* __rest
     if (t < nL) s_off[t] = base + incl - c;
     base += __shfl(incl, WAVE - 1, WAVE);
   }
-  if (l == 0) s_off[nL] = base;
   __syncthreads();
   if (base > cap) return -1;
   for (int f = l; f < base; f += WAVE) {
@@ -156,25 +155,28 @@ __device__ int sort_unique_fast(int32_t* cand, int m, int cap, int32_t* ht) {
 
 // mode 0: counts only; 1: lists at jptr/iptr; 2: lists at jptr/iptr and counts.
 // A column whose unions overflow the capacities gets cntJ = -1 (modes 0, 2).
+// Work item b < nwork is column list[b] (or column b when list is NULL).
 template <int CAP>
-__global__ void __launch_bounds__(64) k_pattern(int32_t n, int kind, const int32_t* __restrict__ cp,
+__global__ void __launch_bounds__(64) k_pattern(int32_t nwork, int kind, const int32_t* __restrict__ cp,
                                                 const int32_t* __restrict__ ri, int mode,
-                                                const int32_t* __restrict__ only /* flags or NULL */,
-                                                int want,
+                                                const int32_t* __restrict__ list,
                                                 int32_t* __restrict__ cntJ, int32_t* __restrict__ cntI,
                                                 const int64_t* __restrict__ jptr,
                                                 int32_t* __restrict__ jout,
                                                 const int64_t* __restrict__ iptr,
                                                 int32_t* __restrict__ iout, int* __restrict__ nover) {
   constexpr int CAPJ = 256;
+  static_assert(HT == CAPJ, "the hash table reuses the gather scratch");
   __shared__ int32_t cand[CAP];
-  __shared__ int32_t ht[HT];
   __shared__ int32_t sJ[CAPJ];
+  // gather scratch; the hash table of a union reuses s_start once the
+  // candidates are gathered
   __shared__ int32_t s_start[CAPJ];
-  __shared__ int32_t s_off[CAPJ + 1];
+  __shared__ int32_t s_off[CAPJ];
+  int32_t* const ht = s_start;
   const int l = lane_id();
-  for (int64_t k = blockIdx.x; k < n; k += gridDim.x) {
-    if (only && only[k] != want) continue;
+  for (int64_t b = blockIdx.x; b < nwork; b += gridDim.x) {
+    const int64_t k = list ? (int64_t)list[b] : b;
     int nJ;
     // ---- J_k
     const int32_t a0 = cp[k], c0 = cp[k + 1] - cp[k];
@@ -272,11 +274,14 @@ __global__ void __launch_bounds__(64) k_rows_of(int32_t n, const int32_t* __rest
                                                 const int64_t* __restrict__ iptr,
                                                 int32_t* __restrict__ iout, int* __restrict__ nover) {
   constexpr int CAPJ = 256;
+  static_assert(HT == CAPJ, "the hash table reuses the gather scratch");
   __shared__ int32_t cand[CAP];
-  __shared__ int32_t ht[HT];
   __shared__ int32_t sJ[CAPJ];
+  // gather scratch; the hash table of a union reuses s_start once the
+  // candidates are gathered
   __shared__ int32_t s_start[CAPJ];
-  __shared__ int32_t s_off[CAPJ + 1];
+  __shared__ int32_t s_off[CAPJ];
+  int32_t* const ht = s_start;
   const int l = lane_id();
   for (int64_t k = blockIdx.x; k < n; k += gridDim.x) {
     const int64_t j0 = jptr[k];
@@ -322,9 +327,15 @@ void rows_of_patterns(const sai_split_s* sp, hipStream_t st, const Allocator& al
   LAUNCH_CHECK();
 }
 
-__global__ void k_flag_neg(int32_t n, const int32_t* cnt, int32_t* flag) {
+// The columns with cnt < 0, in unspecified order (at most cap of them kept),
+// and their number.
+__global__ void __launch_bounds__(256) k_list_neg(int32_t n, const int32_t* __restrict__ cnt,
+                                                  int32_t* __restrict__ list, int cap,
+                                                  int* __restrict__ count) {
   const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (k < n) flag[k] = cnt[k] < 0 ? 1 : 0;
+  const bool neg = k < n && cnt[k] < 0;
+  const int slot = block_slot<1>(count, neg ? 0 : -1);
+  if (neg && slot < cap) list[slot] = (int32_t)k;
 }
 
 // Sizes, offsets and lists of J_k and I_k.  jptr/iptr get n+1 entries.
@@ -342,7 +353,8 @@ void build_patterns(const sai_split_s* sp, int kind, hipStream_t st, const Alloc
   DBuf<int> nover(&al, 2);
   HIPC(hipMemsetAsync(nover.p, 0, 2 * sizeof(int), st));
   const unsigned grid = (unsigned)std::min<int64_t>(n, 1 << 20);
-  constexpr int CAP_S = 1024, CAP_L = 8192;
+  // CAP_S = 512 keeps the small kernel within 5 KB of LDS (32 workgroups per CU)
+  constexpr int CAP_S = 512, CAP_L = 8192;
   DBuf<int64_t> ujo(&al, (size_t)n + 1), uio(&al, (size_t)n + 1);
   DBuf<int32_t> tJ, tI;
   {
@@ -364,17 +376,24 @@ void build_patterns(const sai_split_s* sp, int kind, hipStream_t st, const Alloc
   {
     SAI_PROF("pattern_fill", st);
     hipLaunchKernelGGL((k_pattern<CAP_S>), dim3(grid), dim3(64), 0, st, n, kind, cp, ri, 2,
-                       (const int32_t*)nullptr, 0, cntJ.p, cntI.p, (const int64_t*)ujo.p, tJ.p,
+                       (const int32_t*)nullptr, cntJ.p, cntI.p, (const int64_t*)ujo.p, tJ.p,
                        (const int64_t*)uio.p, tI.p, nover.p);
     LAUNCH_CHECK();
-    if (read_scalar(nover.p, st) > 0) {
-      // columns whose unions overflow the small kernel are redone by the large one
-      DBuf<int32_t> flag(&al, (size_t)n + 1);
-      hipLaunchKernelGGL(k_flag_neg, dim3(grid_for(n, 256)), dim3(256), 0, st, n, cntJ.p, flag.p);
-      LAUNCH_CHECK();
+    const int nbig = read_scalar(nover.p, st);
+    if (nbig > 0) {
+      // columns whose unions overflow the small kernel are redone by the large
+      // one, over a list of just those columns
+      DBuf<int32_t> list(&al, (size_t)nbig);
       HIPC(hipMemsetAsync(nover.p, 0, 2 * sizeof(int), st));
-      hipLaunchKernelGGL((k_pattern<CAP_L>), dim3(grid), dim3(64), 0, st, n, kind, cp, ri, 2,
-                         (const int32_t*)flag.p, 1, cntJ.p, cntI.p, (const int64_t*)ujo.p, tJ.p,
+      hipLaunchKernelGGL(k_list_neg, dim3(grid_for(n, 256)), dim3(256), 0, st, n, cntJ.p, list.p, nbig,
+                         nover.p + 1);
+      LAUNCH_CHECK();
+      // every column of the first pass got its count or -1, one -1 per overflow
+      if (read_scalar(nover.p + 1, st) != nbig)
+        SAI_THROW(SAI_EHIP, "pattern overflow list: %d columns listed, %d counted",
+                  read_scalar(nover.p + 1, st), nbig);
+      hipLaunchKernelGGL((k_pattern<CAP_L>), dim3(std::min(nbig, 1 << 20)), dim3(64), 0, st, nbig, kind,
+                         cp, ri, 2, (const int32_t*)list.p, cntJ.p, cntI.p, (const int64_t*)ujo.p, tJ.p,
                          (const int64_t*)uio.p, tI.p, nover.p);
       LAUNCH_CHECK();
       if (read_scalar(nover.p, st) > 0)

@@ -84,15 +84,29 @@ def test_split_keep_and_largest_rule():
                                        ("c3_3000", P.PAT_A)])
 @pytest.mark.parametrize("prec", [P.FP64, P.FP32])
 def test_patterns_and_columns(name, kind, prec):
-    w, (rp, ci, va) = _load(name)
-    S = osplit.split(w.A)
+    w, dev = _load(name)
+    _check_patterns(w.A, dev, kind, prec)
+
+
+@pytest.mark.parametrize("prec", [P.FP64, P.FP32])
+def test_patterns_long_candidate_lists(prec):
+    """Band of half-width 8: P(|A~|^2 e_k) has 33 entries and 33 * 17 = 561
+    candidates for I_k at interior columns, more than the small pattern kernel
+    holds, so those columns go through the large kernel's redo list."""
+    A = W.banded(600, 8, 2, 0.5, 7)
+    _check_patterns(A, P.csr_to_device(A), P.PAT_A2, prec)
+
+
+def _check_patterns(A, dev, kind, prec):
+    rp, ci, va = dev
+    S = osplit.split(A)
     C = opat.as_csc(S.At)
     g = P.Split(rp, ci, va)
     pc = P.Precond(g, pattern=kind, drop=P.DROP_NONE, precision=prec, keep_lists=True)
     arr = pc.arrays()
     jp, ji, ip, ii = (_np(arr[k]) for k in ("j_ptr", "j_idx", "i_ptr", "i_idx"))
     mf, res = _np(arr["m_full"]).astype(np.float64), _np(arr["res"])
-    n = w.A.shape[0]
+    n = A.shape[0]
     f = opat.pattern_A if kind == P.PAT_A else opat.pattern_A2
     tol = 1e-12 if prec == P.FP64 else 1e-4
     worst = 0.0

@@ -23,3 +23,18 @@ def test_workload_deterministic():
     a = W.make(1)
     b = W.make(1)
     assert (a.A != b.A).nnz == 0 and np.array_equal(a.b, b.b)
+
+
+def test_banded_generator():
+    A = W.banded(600, 8, 2, 0.5, 7)
+    assert A.shape == (600, 600) and A.indptr.dtype == np.int32
+    B = W.banded(600, 8, 2, 0.5, 7)
+    assert (A != B).nnz == 0
+    r, c = A.nonzero()
+    counts = np.bincount(c, minlength=600)
+    dense = np.flatnonzero(counts > 10 * (A.nnz // 600))
+    assert dense.size == 2
+    band = ~np.isin(c, dense)
+    assert np.all(np.abs(r[band] - c[band]) <= 8)
+    # interior columns hold the full band
+    assert np.all(counts[np.setdiff1d(np.arange(8, 592), dense)] == 17)

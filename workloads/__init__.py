@@ -234,3 +234,21 @@ def random_sparse(n: int, density: float, seed: int, diag: float = 0.0) -> sp.cs
     A.indptr = A.indptr.astype(np.int32)
     A.indices = A.indices.astype(np.int32)
     return A
+
+
+def banded(n: int, half_bw: int, s: int, density: float, seed: int) -> sp.csr_matrix:
+    """Seeded banded matrix (|i - j| <= half_bw, diagonally dominant) plus ``s`` dense
+    columns: wide enough bands make the candidate lists of the static pattern
+    P(|A~|^2 e_k) long (about (4 hb + 1)(2 hb + 1) entries), for tests."""
+    rg = np.random.default_rng(seed)
+    i = np.arange(n, dtype=np.int64)
+    rows, cols, vals = [], [], []
+    for d in range(-half_bw, half_bw + 1):
+        ok = (i + d >= 0) & (i + d < n)
+        rows.append(i[ok])
+        cols.append(i[ok] + d)
+        vals.append(np.full(ok.sum(), 2.0 * half_bw + 1.0 + rg.random()) if d == 0
+                    else rg.uniform(-1.0, 1.0, ok.sum()))
+    r, c, v = np.concatenate(rows), np.concatenate(cols), np.concatenate(vals)
+    r, c, v, _ = add_dense_columns(r, c, v, n, s, density, seed)
+    return _csr(r, c, v, n)
