@@ -23,7 +23,7 @@ namespace {
 
 constexpr int NT = 256;
 constexpr int NBMAX = 2048;
-constexpr int PSTRIDE = 64;  // partial sums: [ND][NBMAX][PSTRIDE] doubles
+constexpr int PSTRIDE = 64;  // most columns per block; partial sums: [ND][NBMAX][kp] doubles
 // staged entries per tile (RPB rows): A~ (regular part, about 2p entries per
 // row) gets 12 per row, at least 512, at most 2048 (a smaller staging area lets
 // more workgroups share a CU); M gets 32 per row, at least 2048, within 40 KB of
@@ -143,7 +143,7 @@ __device__ __forceinline__ void row_prod(const int32_t* __restrict__ ci, const T
 // (strides 64 ... 2 LP); for LP = 6 and 12 a short serial sum over the 64 / LP
 // rows finishes.
 template <int LP, int ND>
-__device__ void block_partials(double (&acc)[ND][2], const State& S) {
+__device__ void block_partials(double (&acc)[ND][2], const State& S, int kp) {
   constexpr int RPW = 64 / LP;
   constexpr bool POW2 = (LP & (LP - 1)) == 0;
   __shared__ double red[ND][2 * NT];
@@ -164,7 +164,7 @@ __device__ void block_partials(double (&acc)[ND][2], const State& S) {
     }
     __syncthreads();
   }
-  if (t < 2 * LP) {
+  if (t < kp) {
 #pragma unroll 1
     for (int d = 0; d < ND; ++d) {
       double s = red[d][t];
@@ -172,7 +172,7 @@ __device__ void block_partials(double (&acc)[ND][2], const State& S) {
 #pragma unroll 1
         for (int rw = 1; rw < RPW; ++rw) s += red[d][t + 2 * LP * rw];
       }
-      S.part[((int64_t)d * NBMAX + blockIdx.x) * PSTRIDE + t] = s;
+      S.part[((int64_t)d * NBMAX + blockIdx.x) * kp + t] = s;
     }
   }
 }
@@ -263,7 +263,7 @@ __global__ void __launch_bounds__(NT) k_init(int64_t n, int k, int kp, const dou
       acc[0][1] += b1 * b1;
     }
   }
-  block_partials<LP, 1>(acc, S);
+  block_partials<LP, 1>(acc, S, kp);
 }
 
 // ---- p = r + beta (p - omega v) -------------------------------------------------
@@ -320,7 +320,7 @@ __global__ void __launch_bounds__(NT) k_av(int64_t n, int k, int kp, Csr<double>
       __syncthreads();
     }
   }
-  block_partials<LP, 1>(acc, S);
+  block_partials<LP, 1>(acc, S, kp);
 }
 
 // ---- s = r - alpha v (its norm is summed by k_at) --------------------------------
@@ -362,7 +362,7 @@ __global__ void __launch_bounds__(NT) k_halfcheck(int64_t n, int k, int kp, Csr<
       if (o1) acc[0][1] += r1 * r1;
     }
   }
-  block_partials<LP, 1>(acc, S);
+  block_partials<LP, 1>(acc, S, kp);
 }
 
 // ---- t = A s_hat; partials t^T s, t^T t, s^T s ------------------------------------
@@ -387,7 +387,7 @@ __global__ void __launch_bounds__(NT) k_at(int64_t n, int k, int kp, Csr<double>
       __syncthreads();
     }
   }
-  block_partials<LP, 3>(acc, S);
+  block_partials<LP, 3>(acc, S, kp);
 }
 
 // ---- x += alpha p_hat + omega s_hat, r = s - omega t; partials r_hat^T r, r^T r -----
@@ -415,7 +415,7 @@ __global__ void __launch_bounds__(NT) k_xr(int64_t n, int k, int kp, Vec V, Stat
       }
     }
   }
-  block_partials<LP, 2>(acc, S);
+  block_partials<LP, 2>(acc, S, kp);
 }
 
 // ---- full-step true residual; partials ||rt||^2, r_hat^T rt; r = rt -----------------
@@ -443,7 +443,7 @@ __global__ void __launch_bounds__(NT) k_fullcheck(int64_t n, int k, int kp, Csr<
       if (o1) { acc[0][1] += r1 * r1; acc[1][1] += rh.y * r1; }
     }
   }
-  block_partials<LP, 2>(acc, S);
+  block_partials<LP, 2>(acc, S, kp);
 }
 
 // ---- restart: r_hat = r, p = v = 0; partial r^T r ---------------------------------
@@ -465,7 +465,7 @@ __global__ void __launch_bounds__(NT) k_restart(int64_t n, int k, int kp, Vec V,
       if (o1) acc[0][1] += r.y * r.y;
     }
   }
-  block_partials<LP, 1>(acc, S);
+  block_partials<LP, 1>(acc, S, kp);
 }
 
 // ---- the solution block X (n x k, the caller's) from x (n x kp) -------------------
@@ -513,48 +513,77 @@ constexpr int FNT = 1024;  // finisher threads
 
 template <int ND, int OP>
 __global__ void __launch_bounds__(FNT) k_fin(int k, State S, int nb, int it = 0, int maxit = 0) {
-  __shared__ double red[ND][FNT];
+  // partial sums are read as column pairs; U independent sums per pair and d
+  // keep U loads of every d in flight (the partials come from every XCD, so
+  // each round of loads is a trip past the L2)
+  constexpr int U = ND == 1 ? 16 : 8;
+  __shared__ double2 red[ND][FNT];
   __shared__ double tot[ND][PSTRIDE];
   // a finisher whose main kernel returned early (flag not set) has nothing to do
   if (OP == F_HALF && S.any[0] == 0) return;
   if (OP == F_FULL && S.any[1] == 0) return;
   // (F_RESTART_END always runs: it also closes the iteration)
-  // thread t sums the partials b = q, q + fq, ... of column c = t % k (fq
-  // threads per column, eight independent sums each)
+  // thread t sums the partials b = q, q + fq, ... of the column pair c2 = t % kh
+  // (columns 2 c2, 2 c2 + 1; fq threads per pair)
   const int t = threadIdx.x;
-  const int fq = FNT / k;
-  const int c = t % k, q = t / k;
+  const int kh = (k + 1) >> 1;
+  const int fq = FNT / kh;
+  const int c2 = t % kh, q = t / kh;
   const bool sum = OP != F_RESTART_END || S.any[2] != 0;
+  double2 acc[ND][U];
+#pragma unroll
+  for (int d = 0; d < ND; ++d)
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc[d][u] = make_double2(0.0, 0.0);
+  if (sum && q < fq) {
+    const double* P = S.part + 2 * c2;
+#pragma unroll 1
+    for (int b = q; b < nb; b += U * fq) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int bb = b + u * fq;
+        if (bb < nb) {
+#pragma unroll
+          for (int d = 0; d < ND; ++d) {
+            const double2 v = *(const double2*)(P + ((int64_t)d * NBMAX + bb) * (2 * kh));
+            acc[d][u].x += v.x;
+            acc[d][u].y += v.y;
+          }
+        }
+      }
+    }
+  }
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
-    double s8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (sum && q < fq) {
-      const double* P = S.part + (int64_t)d * NBMAX * PSTRIDE + c;
-      int b = q;
-      for (; b + 7 * fq < nb; b += 8 * fq) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u) s8[u] += P[(int64_t)(b + u * fq) * PSTRIDE];
+    for (int w = U / 2; w >= 1; w >>= 1)
+#pragma unroll
+      for (int u = 0; u < w; ++u) {
+        acc[d][u].x += acc[d][u + w].x;
+        acc[d][u].y += acc[d][u + w].y;
       }
-      for (; b < nb; b += fq) s8[0] += P[(int64_t)b * PSTRIDE];
-    }
-    red[d][t] = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
+    red[d][t] = acc[d][0];
   }
   __syncthreads();
-  // the fq sums of a column meet in a tree: at each level the upper half of
-  // the remaining sums (q >= h) is added onto the lower half (q - h)
+  // the fq sums of a pair meet in a tree: at each level the upper half of the
+  // remaining sums (q >= h) is added onto the lower half (q - h)
 #pragma unroll 1
   for (int cur = fq; cur > 1;) {
     const int h = (cur + 1) >> 1;
     if (q + h < cur) {
 #pragma unroll
-      for (int d = 0; d < ND; ++d) red[d][t] += red[d][t + h * k];
+      for (int d = 0; d < ND; ++d) {
+        const double2 o = red[d][t + h * kh];
+        red[d][t].x += o.x;
+        red[d][t].y += o.y;
+      }
     }
     __syncthreads();
     cur = h;
   }
   if (t < k) {
 #pragma unroll
-    for (int d = 0; d < ND; ++d) tot[d][t] = red[d][t];
+    for (int d = 0; d < ND; ++d) tot[d][t] = (t & 1) ? red[d][t >> 1].y : red[d][t >> 1].x;
   }
   __syncthreads();
   if (t >= k) {

@@ -50,6 +50,11 @@ struct WaveRows {
        r0_ += (int64_t)gridDim.x * NT)
 
 
+// Column counts are kept in CSTRIPE stripes (stripe = row mod CSTRIPE, layout
+// [stripe][n]), so that the many entries of an irregular column do not all
+// queue on one counter; k_dense_flag adds the stripes.
+constexpr int CSTRIPE = 8;
+
 // Checks the CSR input (row pointers monotone within [0, nnz], column indices
 // in range and strictly increasing within a row, finite values) and counts
 // the entries of every column.  A block of 64 rows whose row pointers are bad
@@ -58,7 +63,7 @@ __global__ void __launch_bounds__(NT) k_validate_count(int32_t n, int64_t nnz,
                                                        const int32_t* __restrict__ row_ptr,
                                                        const int32_t* __restrict__ col,
                                                        const double* __restrict__ val,
-                                                       int32_t* __restrict__ colcnt, int* __restrict__ err) {
+                                                       int32_t* __restrict__ colcnt8, int* __restrict__ err) {
   const int lane = threadIdx.x & 63;
   if (blockIdx.x == 0 && threadIdx.x == 0 && (row_ptr[0] != 0 || (int64_t)row_ptr[n] != nnz))
     atomicOr(err, ERR_PTR);
@@ -86,7 +91,7 @@ __global__ void __launch_bounds__(NT) k_validate_count(int32_t n, int64_t nnz,
         } else {
           if (e > rs && col[e - 1] >= j) e_local |= ERR_ORDER;
           if (!isfinite(val[e])) e_local |= ERR_VAL;
-          atomicAdd(&colcnt[j], 1);
+          atomicAdd(&colcnt8[(int64_t)(t % CSTRIPE) * n + j], 1);
         }
       }
     }
@@ -94,9 +99,15 @@ __global__ void __launch_bounds__(NT) k_validate_count(int32_t n, int64_t nnz,
   }
 }
 
-__global__ void k_dense_flag(int32_t n, const int32_t* colcnt, double thr, int32_t* flag) {
+__global__ void k_dense_flag(int32_t n, const int32_t* __restrict__ colcnt8, double thr,
+                             int32_t* __restrict__ colcnt, int32_t* __restrict__ flag) {
   const int64_t j = (int64_t)blockIdx.x * NT + threadIdx.x;
-  if (j < n) flag[j] = ((double)colcnt[j] > thr) ? 1 : 0;
+  if (j >= n) return;
+  int32_t c = 0;
+#pragma unroll
+  for (int q = 0; q < CSTRIPE; ++q) c += colcnt8[(int64_t)q * n + j];
+  colcnt[j] = c;
+  flag[j] = ((double)c > thr) ? 1 : 0;
 }
 
 __global__ void k_dense_compact(int32_t n, const int32_t* flag, const int32_t* pos,
@@ -431,13 +442,17 @@ void split_impl(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* c
   DBuf<int32_t> colcnt(&al, (size_t)n + 1), flag(&al, (size_t)n + 1), pos(&al, (size_t)n + 1),
       colmap(&al, (size_t)n);
   DBuf<int> err(&al, 4);
-  HIPC(hipMemsetAsync(colcnt.p, 0, sizeof(int32_t) * ((size_t)n + 1), st));
-  HIPC(hipMemsetAsync(err.p, 0, sizeof(int) * 4, st));
-  hipLaunchKernelGGL(k_validate_count, dim3(grid_for(((int64_t)n + 63) / 64 * 64, NT, 4096)), dim3(NT), 0, st, n, nnz, row_ptr,
-                     col_idx, val, colcnt.p, err.p);
-  LAUNCH_CHECK();
-  const double thr = o.dense_factor * (double)p;
-  hipLaunchKernelGGL(k_dense_flag, dim3(grid_for(n, NT)), dim3(NT), 0, st, n, colcnt.p, thr, flag.p);
+  {
+    DBuf<int32_t> colcnt8(&al, (size_t)CSTRIPE * n);
+    HIPC(hipMemsetAsync(colcnt8.p, 0, sizeof(int32_t) * (size_t)CSTRIPE * n, st));
+    HIPC(hipMemsetAsync(err.p, 0, sizeof(int) * 4, st));
+    hipLaunchKernelGGL(k_validate_count, dim3(grid_for(((int64_t)n + 63) / 64 * 64, NT, 4096)), dim3(NT), 0, st, n,
+                       nnz, row_ptr, col_idx, val, colcnt8.p, err.p);
+    LAUNCH_CHECK();
+    const double thr = o.dense_factor * (double)p;
+    hipLaunchKernelGGL(k_dense_flag, dim3(grid_for(n, NT)), dim3(NT), 0, st, n, colcnt8.p, thr, colcnt.p,
+                       flag.p);
+  }
   LAUNCH_CHECK();
   exclusive_scan_i32(flag.p, pos.p, n, al, st);
   HostStage hs(64);
