@@ -530,6 +530,32 @@ __global__ void __launch_bounds__(FNT) k_fin(int k, State S, int nb, int it = 0,
   const int fq = FNT / kh;
   const int c2 = t % kh, q = t / kh;
   const bool sum = OP != F_RESTART_END || S.any[2] != 0;
+  // the column state each update reads, loaded now so that these loads overlap
+  // the partial sums' (nothing below writes a field before reading it)
+  int st_status = 0, st_skip = 0, st_flag = 0, st_pend = 0, st_restarts = 0;
+  double st_rho = 0.0, st_rho_old = 0.0, st_alpha = 0.0, st_omega = 0.0, st_thr = 0.0;
+  if (t < k) {
+    st_status = S.status[t];
+    st_skip = S.skip[t];
+    if constexpr (OP == F_INIT || OP == F_AT || OP == F_HALF || OP == F_XR || OP == F_FULL) st_thr = S.thr[t];
+    if constexpr (OP == F_AV || OP == F_XR) st_rho = S.rho[t];
+    if constexpr (OP == F_XR || OP == F_FULL) {
+      st_alpha = S.alpha[t];
+      st_omega = S.omega[t];
+    }
+    if constexpr (OP == F_FULL) st_rho_old = S.rho_old[t];
+    if constexpr (OP == F_HALF) {
+      st_flag = S.half[t];
+      st_pend = S.pend[t];
+    }
+    if constexpr (OP == F_XR) st_flag = S.halfconv[t];
+    if constexpr (OP == F_FULL) st_flag = S.full[t];
+    if constexpr (OP == F_RESTART_END) {
+      st_flag = S.rst[t];
+      st_restarts = S.restarts[t];
+    }
+  }
+  const bool on = t < k && st_status == ST_ACTIVE && st_skip == 0;  // col_on(S, t, k)
   double2 acc[ND][U];
 #pragma unroll
   for (int d = 0; d < ND; ++d)
@@ -599,26 +625,26 @@ __global__ void __launch_bounds__(FNT) k_fin(int k, State S, int nb, int it = 0,
     S.restarts[t] = 0;
     S.half[t] = S.full[t] = S.rst[t] = S.halfconv[t] = S.pend[t] = 0;
     S.iters[t] = 0;
-    S.status[t] = (sqrt(rr) < S.thr[t]) ? ST_CONV : ST_ACTIVE;
+    S.status[t] = (sqrt(rr) < st_thr) ? ST_CONV : ST_ACTIVE;
     if (t == 0) S.any[0] = S.any[1] = S.any[2] = S.any[4] = 0;
   } else if constexpr (OP == F_AV) {
-    if (col_on(S, t, k)) {
+    if (on) {
       const double sig = tot[0][t];
       if (fabs(sig) < TINY) {
         S.skip[t] = 1;
         S.rst[t] = 1;
         S.any[2] = 1;
       } else {
-        S.alpha[t] = S.rho[t] / sig;
+        S.alpha[t] = st_rho / sig;
       }
     }
   } else if constexpr (OP == F_AT) {
     // partials: t^T s, t^T t, s^T s.  The half-step check (||s|| < thr) is flagged
     // here; a column waiting for it keeps a tiny t^T t as pending (a breakdown only
     // if the check fails: s ~ 0 makes t ~ 0)
-    if (col_on(S, t, k)) {
+    if (on) {
       const double tt = tot[1][t];
-      const bool half = sqrt(tot[2][t]) < S.thr[t];
+      const bool half = sqrt(tot[2][t]) < st_thr;
       if (half) {
         S.half[t] = 1;
         S.any[0] = 1;
@@ -636,52 +662,52 @@ __global__ void __launch_bounds__(FNT) k_fin(int k, State S, int nb, int it = 0,
       }
     }
   } else if constexpr (OP == F_HALF) {
-    if (col_on(S, t, k) && S.half[t]) {
-      if (sqrt(tot[0][t]) < S.thr[t]) {
+    if (on && st_flag) {
+      if (sqrt(tot[0][t]) < st_thr) {
         S.halfconv[t] = 1;
         S.any[4] = 1;
-      } else if (S.pend[t]) {
+      } else if (st_pend) {
         S.skip[t] = 1;
         S.rst[t] = 1;
         S.any[2] = 1;
       }
     }
   } else if constexpr (OP == F_XR) {
-    if (col_on(S, t, k) && !S.halfconv[t]) {
+    if (on && !st_flag) {
       const double rho_new = tot[0][t];
-      S.rho_old[t] = S.rho[t];
+      S.rho_old[t] = st_rho;
       S.rho[t] = rho_new;
-      S.beta[t] = (rho_new / S.rho_old[t]) * (S.alpha[t] / S.omega[t]);
-      if (sqrt(tot[1][t]) < S.thr[t]) {
+      S.beta[t] = (rho_new / st_rho) * (st_alpha / st_omega);
+      if (sqrt(tot[1][t]) < st_thr) {
         S.full[t] = 1;
         S.any[1] = 1;  // breakdown checks follow the true-residual check
-      } else if (fabs(S.omega[t]) < TINY || fabs(rho_new) < TINY) {
+      } else if (fabs(st_omega) < TINY || fabs(rho_new) < TINY) {
         S.rst[t] = 1;
         S.any[2] = 1;
       }
     }
   } else if constexpr (OP == F_FULL) {
-    if (col_on(S, t, k) && S.full[t]) {
-      if (sqrt(tot[0][t]) < S.thr[t]) {
+    if (on && st_flag) {
+      if (sqrt(tot[0][t]) < st_thr) {
         S.status[t] = ST_CONV;  // iteration count set at the end of the iteration
       } else {
         const double rho_new = tot[1][t];
         S.rho[t] = rho_new;
-        S.beta[t] = (rho_new / S.rho_old[t]) * (S.alpha[t] / S.omega[t]);
-        if (fabs(S.omega[t]) < TINY || fabs(rho_new) < TINY) {
+        S.beta[t] = (rho_new / st_rho_old) * (st_alpha / st_omega);
+        if (fabs(st_omega) < TINY || fabs(rho_new) < TINY) {
           S.rst[t] = 1;
           S.any[2] = 1;
         }
       }
     }
   } else if constexpr (OP == F_RESTART_END) {
-    if (S.any[2] != 0 && S.rst[t] && S.status[t] == ST_ACTIVE) {
+    if (S.any[2] != 0 && st_flag && st_status == ST_ACTIVE) {
       const double rr = tot[0][t];
       S.rho[t] = rr;
       S.rho_old[t] = S.alpha[t] = S.omega[t] = 1.0;
       S.beta[t] = rr;
-      S.restarts[t] += 1;
-      if (S.restarts[t] > 1) S.status[t] = ST_BREAK;
+      S.restarts[t] = st_restarts + 1;
+      if (st_restarts + 1 > 1) S.status[t] = ST_BREAK;
     }
   }
   if constexpr (OP == F_RESTART_END) iter_end_body(k, S, it, maxit);

@@ -46,6 +46,60 @@ __device__ __forceinline__ T gsum(T v) {
   return v;
 }
 
+// gsum over N independent values at once: the DPP steps of the N sums are
+// interleaved, so no step waits on the one just before it (each value gets the
+// same sequence of additions as gsum).  Only the first cnt values are summed
+// (cnt is a constant once the caller's loops are unrolled).
+template <int G, int N, class T>
+__device__ __forceinline__ void gsum_n(T (&v)[N], int cnt) {
+  static_assert(G == 16 || G == 32 || G == 64, "group size");
+#pragma unroll
+  for (int u = 0; u < N; ++u) if (u < cnt) v[u] += dpp_mov<0xB1>(v[u]);
+#pragma unroll
+  for (int u = 0; u < N; ++u) if (u < cnt) v[u] += dpp_mov<0x4E>(v[u]);
+#pragma unroll
+  for (int u = 0; u < N; ++u) if (u < cnt) v[u] += dpp_mov<0x141>(v[u]);
+#pragma unroll
+  for (int u = 0; u < N; ++u) if (u < cnt) v[u] += dpp_mov<0x140>(v[u]);
+  if constexpr (G >= 32) {
+#pragma unroll
+    for (int u = 0; u < N; ++u) if (u < cnt) v[u] += __shfl_xor(v[u], 16, 64);
+  }
+  if constexpr (G >= 64) {
+#pragma unroll
+    for (int u = 0; u < N; ++u) if (u < cnt) v[u] += __shfl_xor(v[u], 32, 64);
+  }
+}
+
+// Value of lane src (0 <= src < G) of the caller's group, in every lane of the
+// group.  G = 16: one DPP row broadcast (row_newbcast); src must be a constant
+// once the caller's loops are unrolled.
+template <int G, class T>
+__device__ __forceinline__ T gbcast(T v, int src) {
+  if constexpr (G == 16) {
+    switch (src) {
+      case 0: return dpp_mov<0x150>(v);
+      case 1: return dpp_mov<0x151>(v);
+      case 2: return dpp_mov<0x152>(v);
+      case 3: return dpp_mov<0x153>(v);
+      case 4: return dpp_mov<0x154>(v);
+      case 5: return dpp_mov<0x155>(v);
+      case 6: return dpp_mov<0x156>(v);
+      case 7: return dpp_mov<0x157>(v);
+      case 8: return dpp_mov<0x158>(v);
+      case 9: return dpp_mov<0x159>(v);
+      case 10: return dpp_mov<0x15A>(v);
+      case 11: return dpp_mov<0x15B>(v);
+      case 12: return dpp_mov<0x15C>(v);
+      case 13: return dpp_mov<0x15D>(v);
+      case 14: return dpp_mov<0x15E>(v);
+      default: return dpp_mov<0x15F>(v);
+    }
+  } else {
+    return __shfl(v, (int)(threadIdx.x & (64 - G)) + src, 64);
+  }
+}
+
 __device__ __forceinline__ int wave_max_i(int v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
@@ -75,6 +129,9 @@ __global__ void __launch_bounds__(64, MINW) k_ls_qr(const int32_t* __restrict__ 
   constexpr int ROWS = G * R;
   constexpr int LDT = JMAX + 1;
   constexpr int MS = (JMAX + G - 1) / G;
+  // columns reflected together (interleaved group sums); wider groups keep the
+  // larger variants from being fully unrolled, which would put a[][] in scratch
+  constexpr int GW = (G == 16 && sizeof(T) == 4) ? 4 : 1;
   static_assert(JMAX <= ROWS, "row slots must cover the columns");
   __shared__ T tile[ROWS * LDT];
   __shared__ int32_t sI[ROWS];
@@ -152,7 +209,8 @@ __global__ void __launch_bounds__(64, MINW) k_ls_qr(const int32_t* __restrict__ 
       __syncthreads();
     }
 
-    const int nJmax = wave_max_i(nJ);
+    // wave-uniform (a scalar), so that the guards below are scalar branches
+    const int nJmax = __builtin_amdgcn_readfirstlane(wave_max_i(nJ));
     bool sing = false;
 
     // ---- Householder QR; Q^T is applied to the right-hand side as we go
@@ -168,8 +226,10 @@ __global__ void __launch_bounds__(64, MINW) k_ls_qr(const int32_t* __restrict__ 
           if (rho > j) tail += x * x;
           if (rho == j) ap = x;
         }
-        tail = gsum<G>(tail);
-        const T alpha = gsum<G>(ap);
+        T ta[2] = {tail, ap};
+        gsum_n<G>(ta, 2);
+        tail = ta[0];
+        const T alpha = ta[1];
         const T normx = sqrt(tail + alpha * alpha);
         const T sgn = alpha >= (T)0 ? (T)1 : (T)-1;
         const T vj = alpha + sgn * normx;
@@ -183,26 +243,58 @@ __global__ void __launch_bounds__(64, MINW) k_ls_qr(const int32_t* __restrict__ 
           const int rho = li + G * r;
           v[r] = rho > j ? a[r][j] : (rho == j ? vj : (T)0);
         }
+        // reflect the right-hand side and columns j+1 .. JMAX-1, GW at a time
+        // (first group: b and columns j+1 .. j+GW-1), their group sums
+        // interleaved
+        {
+          T d[GW];
+          d[0] = 0;
 #pragma unroll
-        for (int c = j + 1; c < JMAX; ++c) {
-          if (c < nJmax) {
-            T d = 0;
+          for (int r = 0; r < R; ++r) d[0] += v[r] * b[r];
 #pragma unroll
-            for (int r = 0; r < R; ++r) d += v[r] * a[r][c];
-            d = gsum<G>(d);
-            const T f = tau * d;
+          for (int u = 1; u < GW; ++u) {
+            d[u] = 0;
+            if (j + u < JMAX) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) a[r][c] -= f * v[r];
+              for (int r = 0; r < R; ++r) d[u] += v[r] * a[r][j + u];
+            }
+          }
+          const int cnt = JMAX - j < GW ? JMAX - j : GW;
+          gsum_n<G>(d, cnt);
+#pragma unroll
+          for (int r = 0; r < R; ++r) b[r] -= (tau * d[0]) * v[r];
+#pragma unroll
+          for (int u = 1; u < GW; ++u) {
+            if (j + u < JMAX) {
+              const T f = tau * d[u];
+#pragma unroll
+              for (int r = 0; r < R; ++r) a[r][j + u] -= f * v[r];
+            }
           }
         }
-        {
-          T d = 0;
 #pragma unroll
-          for (int r = 0; r < R; ++r) d += v[r] * b[r];
-          d = gsum<G>(d);
-          const T f = tau * d;
+        for (int c0 = j + GW; c0 < JMAX; c0 += GW) {
+          if (c0 < nJmax) {
+            T d[GW];
 #pragma unroll
-          for (int r = 0; r < R; ++r) b[r] -= f * v[r];
+            for (int u = 0; u < GW; ++u) {
+              d[u] = 0;
+              if (c0 + u < JMAX) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) d[u] += v[r] * a[r][c0 + u];
+              }
+            }
+            const int cnt = JMAX - c0 < GW ? JMAX - c0 : GW;
+            gsum_n<G>(d, cnt);
+#pragma unroll
+            for (int u = 0; u < GW; ++u) {
+              if (c0 + u < JMAX) {
+                const T f = tau * d[u];
+#pragma unroll
+                for (int r = 0; r < R; ++r) a[r][c0 + u] -= f * v[r];
+              }
+            }
+          }
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -225,7 +317,7 @@ __global__ void __launch_bounds__(64, MINW) k_ls_qr(const int32_t* __restrict__ 
         const int rc = c / G;
         T part = 0;
         if (c < nJ && li == c % G && !sing) part = (b[rc] - macc[rc]) / a[rc][c];
-        const T mc = gsum<G>(part);
+        const T mc = gbcast<G>(part, c % G);
         if (li == c % G) mown[c / G] = mc;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
