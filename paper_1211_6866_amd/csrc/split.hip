@@ -262,6 +262,122 @@ __global__ void __launch_bounds__(NT) k_dense_select(const int32_t* __restrict__
   }
 }
 
+// Same selection in one pass over the column for keep - 1 <= SEL_K: every
+// thread keeps the keep - 1 smallest keys of its entries, sorted, in registers;
+// then keep - 1 rounds of a block minimum over the threads' current heads (the
+// thread whose head is taken moves to its next key) yield the keep - 1
+// smallest keys of the column (keys are distinct: one per row).
+constexpr int SEL_K = 16;
+
+__device__ __forceinline__ Key block_min_key(Key k, double* sa, int32_t* si) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    Key y{__shfl_xor(k.a, o, 64), __shfl_xor(k.i, o, 64)};
+    if (key_less(y, k)) k = y;
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sa[w] = k.a;
+    si[w] = k.i;
+  }
+  __syncthreads();
+  Key b{sa[0], si[0]};
+#pragma unroll
+  for (int q = 1; q < NT / 64; ++q) {
+    Key y{sa[q], si[q]};
+    if (key_less(y, b)) b = y;
+  }
+  __syncthreads();
+  return b;
+}
+
+__global__ void __launch_bounds__(NT) k_dense_select_k(const int32_t* __restrict__ dense_cols,
+                                                       const int64_t* __restrict__ doff,
+                                                       const int32_t* __restrict__ dcount,
+                                                       const int32_t* __restrict__ lrow,
+                                                       const int32_t* __restrict__ lpos,
+                                                       const double* __restrict__ val, int keep,
+                                                       int rule, uint8_t* __restrict__ drop,
+                                                       int* __restrict__ err) {
+  __shared__ double sa[NT / 64];
+  __shared__ int32_t si[NT / 64];
+  __shared__ int has_diag;
+  const int d = blockIdx.x;
+  const int32_t j = dense_cols[d];
+  const int64_t off = doff[d];
+  const int32_t cnt = dcount[d];
+  const int K = keep - 1;  // <= SEL_K (checked by the caller)
+  if (threadIdx.x == 0) has_diag = 0;
+  __syncthreads();
+  double ka[SEL_K];
+  int32_t ki[SEL_K];
+#pragma unroll
+  for (int u = 0; u < SEL_K; ++u) {
+    ka[u] = INFINITY;
+    ki[u] = 0x7fffffff;
+  }
+  bool diag = false;
+  for (int32_t t = threadIdx.x; t < cnt; t += NT) {
+    const int32_t i = lrow[off + t];
+    if (i == j) {
+      diag = true;
+      continue;
+    }
+    Key k;
+    k.i = i;
+    k.a = (rule == SAI_KEEP_NEAREST) ? (double)(i > j ? i - j : j - i) : -fabs(val[lpos[off + t]]);
+    // insert into the sorted list of the K smallest (slots >= K stay empty)
+#pragma unroll
+    for (int u = SEL_K - 1; u >= 0; --u) {
+      if (u < K) {
+        const Key cur{ka[u], ki[u]};
+        const Key prev = u > 0 ? Key{ka[u - 1], ki[u - 1]} : Key{-INFINITY, -1};
+        if (key_less(k, cur)) {
+          if (key_less(k, prev)) {
+            ka[u] = prev.a;  // shift up
+            ki[u] = prev.i;
+          } else {
+            ka[u] = k.a;  // k goes here
+            ki[u] = k.i;
+          }
+        }
+      }
+    }
+  }
+  if (diag) has_diag = 1;
+  __syncthreads();
+  if (!has_diag) {
+    if (threadIdx.x == 0) atomicOr(err, ERR_ZERODIAG);
+    return;
+  }
+  Key last{-INFINITY, -1};
+  bool have = false;
+  int head = 0;
+  for (int r = 0; r < K; ++r) {
+    Key mine{INFINITY, 0x7fffffff};
+#pragma unroll
+    for (int u = 0; u < SEL_K; ++u)
+      if (u == head) mine = Key{ka[u], ki[u]};
+    const Key b = block_min_key(mine, sa, si);
+    if (b.i == 0x7fffffff) break;  // fewer off-diagonals than keep-1
+    if (b.i == mine.i && head < SEL_K) ++head;
+    last = b;
+    have = true;
+  }
+  for (int32_t t = threadIdx.x; t < cnt; t += NT) {
+    const int32_t i = lrow[off + t];
+    if (i == j) continue;
+    bool kept = false;
+    if (have) {
+      Key k;
+      k.i = i;
+      k.a = (rule == SAI_KEEP_NEAREST) ? (double)(i > j ? i - j : j - i) : -fabs(val[lpos[off + t]]);
+      kept = !key_less(last, k);  // k <= last
+    }
+    if (!kept) drop[lpos[off + t]] = 1;
+  }
+}
+
 __global__ void k_row_counts(int32_t n, const int32_t* __restrict__ row_ptr,
                              const uint8_t* __restrict__ drop, int32_t* __restrict__ tcnt,
                              int32_t* __restrict__ ucnt) {
@@ -499,8 +615,12 @@ void split_impl(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* c
                          colmap.p, doff.p, dcur.p, lrow.p, lpos.p);
       LAUNCH_CHECK();
     }
-    hipLaunchKernelGGL(k_dense_select, dim3(s), dim3(NT), 0, st, h->dense_cols.p, doff.p, dcount.p,
-                       lrow.p, lpos.p, val, keep, o.rule, drop.p, err.p);
+    if (keep - 1 <= SEL_K)
+      hipLaunchKernelGGL(k_dense_select_k, dim3(s), dim3(NT), 0, st, h->dense_cols.p, doff.p, dcount.p,
+                         lrow.p, lpos.p, val, keep, o.rule, drop.p, err.p);
+    else
+      hipLaunchKernelGGL(k_dense_select, dim3(s), dim3(NT), 0, st, h->dense_cols.p, doff.p, dcount.p,
+                         lrow.p, lpos.p, val, keep, o.rule, drop.p, err.p);
     LAUNCH_CHECK();
     const int e1 = read_scalar(err.p, st);
     if (e1 & ERR_ZERODIAG) SAI_THROW(SAI_EZERODIAG, "an irregular column has no diagonal entry");

@@ -71,7 +71,11 @@ def test_split_bit_exact(name):
 
 def test_split_keep_and_largest_rule():
     w, (rp, ci, va) = _load("c2_12")
-    for keep, rule, orule in [(1, P.KEEP_NEAREST, "nearest"), (4, P.KEEP_LARGEST, "largest")]:
+    # keep - 1 <= 16 candidates per thread in registers; 18 and 30 take the
+    # multi-pass selection
+    for keep, rule, orule in [(1, P.KEEP_NEAREST, "nearest"), (4, P.KEEP_LARGEST, "largest"),
+                              (17, P.KEEP_LARGEST, "largest"), (17, P.KEEP_NEAREST, "nearest"),
+                              (18, P.KEEP_NEAREST, "nearest"), (30, P.KEEP_LARGEST, "largest")]:
         S = osplit.split(w.A, keep=keep, rule=orule)
         g = P.Split(rp, ci, va, keep=keep, rule=rule)
         arr = g.arrays()
