@@ -135,6 +135,54 @@ __device__ __forceinline__ void row_prod(const int32_t* __restrict__ ci, const T
   }
 }
 
+// Product of one row with X + al P (column pair c0, c0+1; al per column), each
+// entry added as v (x + al p) in order, the loads batched as in row_prod.
+template <class TV, int CH, int CH2>
+__device__ __forceinline__ void row_prod_xp(const int32_t* __restrict__ ci, const TV* __restrict__ v, int e,
+                                            int ee, const double* __restrict__ X,
+                                            const double* __restrict__ P, double al0, double al1, int kp,
+                                            int c0, double& a0, double& a1) {
+  a0 = a1 = 0.0;
+  for (; e + CH <= ee; e += CH) {
+    double2 xv[CH], pv[CH];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int64_t q = (int64_t)ci[e + u] * kp + c0;
+      xv[u] = ld2(X, q);
+      pv[u] = ld2(P, q);
+    }
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const double w = (double)v[e + u];
+      a0 += w * (xv[u].x + al0 * pv[u].x);
+      a1 += w * (xv[u].y + al1 * pv[u].y);
+    }
+  }
+  if (CH2 > 0 && e + CH2 <= ee) {
+    double2 xv[CH2 > 0 ? CH2 : 1], pv[CH2 > 0 ? CH2 : 1];
+#pragma unroll
+    for (int u = 0; u < CH2; ++u) {
+      const int64_t q = (int64_t)ci[e + u] * kp + c0;
+      xv[u] = ld2(X, q);
+      pv[u] = ld2(P, q);
+    }
+#pragma unroll
+    for (int u = 0; u < CH2; ++u) {
+      const double w = (double)v[e + u];
+      a0 += w * (xv[u].x + al0 * pv[u].x);
+      a1 += w * (xv[u].y + al1 * pv[u].y);
+    }
+    e += CH2;
+  }
+  for (; e < ee; ++e) {
+    const int64_t q = (int64_t)ci[e] * kp + c0;
+    const double2 x = ld2(X, q), p = ld2(P, q);
+    const double w = (double)v[e];
+    a0 += w * (x.x + al0 * p.x);
+    a1 += w * (x.y + al1 * p.y);
+  }
+}
+
 // Block-reduce ND per-lane accumulator pairs (per column) in a fixed order and
 // publish the block's partial sums for the finisher.  Slot 2t+j (of 2 NT) holds
 // thread t's value for column 2((t & 63) % LP) + j, so slot s belongs to wave
@@ -338,29 +386,35 @@ __global__ void __launch_bounds__(NT) k_s(int64_t n, int k, int kp, Vec V, State
 }
 
 // ---- half-step true residual b - A (x + alpha p_hat), flagged columns only -------
+// (persistent grid over tiles, A~ staged in LDS; called with the A~ products' grid)
 template <int LP>
 __global__ void __launch_bounds__(NT) k_halfcheck(int64_t n, int k, int kp, Csr<double> A, Vec V,
-                                                  State S) {
+                                                  State S, int xmap) {
   if (S.any[0] == 0) return;
   LANES(LP)
+  constexpr int CAP_A = cap_a(RPB);
+  STAGE_DECL(double, CAP_A, RPB)
   double acc[1][2] = {{0.0, 0.0}};
   const bool o0 = lok_ && col_on(S, c0, k) && S.half[c0];
   const bool o1 = lok_ && col_on(S, c0 + 1, k) && S.half[c0 + 1];
   const double al0 = o0 ? S.alpha[c0] : 0.0, al1 = o1 ? S.alpha[c0 + 1] : 0.0;
-  if (o0 || o1) {
-    ROW_LOOP {
-      double y0 = 0.0, y1 = 0.0;
-      for (int32_t e = A.rp[i]; e < A.rp[i + 1]; ++e) {
-        const int64_t q = (int64_t)A.ci[e] * kp + c0;
-        const double2 x = ld2(V.x, q), ph = ld2(V.ph, q);
-        y0 += A.v[e] * (x.x + al0 * ph.x);
-        y1 += A.v[e] * (x.y + al1 * ph.y);
-      }
-      const double2 b = ld2(V.b, i * kp + c0);
+  TILE_LOOP {
+    const int rows = (int)min<int64_t>(TR, n - t0);
+    const bool fit = stage_tile<double, CAP_A>(A, t0, rows, s_rp, s_ci, s_v);
+    if ((o0 || o1) && rib < rows) {
+      const int64_t qq = (t0 + rib) * kp + c0;
+      double y0, y1;
+      if (fit)
+        row_prod_xp<double, 4, 2>(s_ci, s_v, s_rp[rib] - s_rp[0], s_rp[rib + 1] - s_rp[0], V.x, V.ph, al0,
+                                  al1, kp, c0, y0, y1);
+      else
+        row_prod_xp<double, 4, 2>(A.ci, A.v, s_rp[rib], s_rp[rib + 1], V.x, V.ph, al0, al1, kp, c0, y0, y1);
+      const double2 b = ld2(V.b, qq);
       const double r0 = b.x - y0, r1 = b.y - y1;
       if (o0) acc[0][0] += r0 * r0;
       if (o1) acc[0][1] += r1 * r1;
     }
+    __syncthreads();
   }
   block_partials<LP, 1>(acc, S, kp);
 }
@@ -419,29 +473,28 @@ __global__ void __launch_bounds__(NT) k_xr(int64_t n, int k, int kp, Vec V, Stat
 }
 
 // ---- full-step true residual; partials ||rt||^2, r_hat^T rt; r = rt -----------------
+// (persistent grid over tiles, A~ staged in LDS; called with the A~ products' grid)
 template <int LP>
 __global__ void __launch_bounds__(NT) k_fullcheck(int64_t n, int k, int kp, Csr<double> A, Vec V,
-                                                  State S) {
+                                                  State S, int xmap) {
   if (S.any[1] == 0) return;
   LANES(LP)
+  constexpr int CAP_A = cap_a(RPB);
+  STAGE_DECL(double, CAP_A, RPB)
   double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
   const bool o0 = lok_ && col_on(S, c0, k) && S.full[c0];
   const bool o1 = lok_ && col_on(S, c0 + 1, k) && S.full[c0 + 1];
-  if (o0 || o1) {
-    ROW_LOOP {
-      double y0 = 0.0, y1 = 0.0;
-      for (int32_t e = A.rp[i]; e < A.rp[i + 1]; ++e) {
-        const double2 x = ld2(V.x, (int64_t)A.ci[e] * kp + c0);
-        y0 += A.v[e] * x.x;
-        y1 += A.v[e] * x.y;
-      }
-      const int64_t q = i * kp + c0;
-      const double2 b = ld2(V.b, q), rh = ld2(V.rh, q);
-      const double r0 = b.x - y0, r1 = b.y - y1;
-      st2(V.r, q, r0, r1, o0, o1);
-      if (o0) { acc[0][0] += r0 * r0; acc[1][0] += rh.x * r0; }
-      if (o1) { acc[0][1] += r1 * r1; acc[1][1] += rh.y * r1; }
+  TILE_LOOP {
+    const int rows = (int)min<int64_t>(TR, n - t0);
+    const bool fit = stage_tile<double, CAP_A>(A, t0, rows, s_rp, s_ci, s_v);
+    if (o0 || o1) {
+      TILE_ROW_PROD(double, 4, 2, A, V.x, const double2 b = ld2(V.b, qq); const double2 rh = ld2(V.rh, qq);,
+                    const double r0 = b.x - y0; const double r1 = b.y - y1;
+                    st2(V.r, qq, r0, r1, o0, o1);
+                    if (o0) { acc[0][0] += r0 * r0; acc[1][0] += rh.x * r0; }
+                    if (o1) { acc[0][1] += r1 * r1; acc[1][1] += rh.y * r1; })
     }
+    __syncthreads();
   }
   block_partials<LP, 2>(acc, S, kp);
 }

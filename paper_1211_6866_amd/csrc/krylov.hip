@@ -232,12 +232,12 @@ int iterate(Block& B, const Csr<double>& A, const Csr<TM>& M, int64_t n, int& it
       spmm_at();
     }
     LK("bicg_finish", (k_fin<3, F_AT>), dim3(1), dim3(FNT), 0, st, k, S, tgrid, 0, 0);
-    LK("bicg_halfcheck", (k_halfcheck<LP>), dim3(grid), dim3(NT), 0, st, n, k, kp, A, V, S);
-    LK("bicg_finish", (k_fin<1, F_HALF>), dim3(1), dim3(FNT), 0, st, k, S, grid, 0, 0);
+    LK("bicg_halfcheck", (k_halfcheck<LP>), dim3(tgrid), dim3(NT), 0, st, n, k, kp, A, V, S, xmap);
+    LK("bicg_finish", (k_fin<1, F_HALF>), dim3(1), dim3(FNT), 0, st, k, S, tgrid, 0, 0);
     LK("bicg_xr_update", (k_xr<LP>), dim3(grid), dim3(NT), 0, st, n, k, kp, V, S);
     LK("bicg_finish", (k_fin<2, F_XR>), dim3(1), dim3(FNT), 0, st, k, S, grid, 0, 0);
-    LK("bicg_fullcheck", (k_fullcheck<LP>), dim3(grid), dim3(NT), 0, st, n, k, kp, A, V, S);
-    LK("bicg_finish", (k_fin<2, F_FULL>), dim3(1), dim3(FNT), 0, st, k, S, grid, 0, 0);
+    LK("bicg_fullcheck", (k_fullcheck<LP>), dim3(tgrid), dim3(NT), 0, st, n, k, kp, A, V, S, xmap);
+    LK("bicg_finish", (k_fin<2, F_FULL>), dim3(1), dim3(FNT), 0, st, k, S, tgrid, 0, 0);
     LK("bicg_restart", (k_restart<LP>), dim3(grid), dim3(NT), 0, st, n, k, kp, V, S);
     LK("bicg_finish_end", (k_fin<1, F_RESTART_END>), dim3(1), dim3(FNT), 0, st, k, S, grid, it, maxit);
 #undef LK
