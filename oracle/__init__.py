@@ -12,6 +12,7 @@ one column or one right-hand side at a time, in float64:
 * ``pattern``    - static patterns P(A~) and P(|A~|^2) (Section 2.2, BPSAI envelope)
 * ``lsq``        - the column least-squares problems (Section 2, (subprob), (lsprob))
 * ``spai``       - SPAI augmentation (Section 2.1, (candi), (ls1d), (muj), (rhoj))
+* ``psai``       - PSAI(tol): power patterns P(|A~|^l e_k) with the (tolk) drop (Section 2.2)
 * ``drop``       - dropping of small entries of m_k (Section 2.2, (tolk)) and assembly of M
 * ``krylov``     - right-preconditioned BiCGStab and GMRES(m) with the stopping
                    rules of the Section 4 theorem ((stopb), (stopU2), c = 1)
@@ -25,4 +26,4 @@ Parity status: every function above is pinned by ``tests/test_oracle_*.py``
 against closed forms, library routines, invariants, brute force or values the
 paper prints; none is "parity unpinned".
 """
-from . import split, pattern, lsq, spai, drop, krylov, smw, adjoint, pipeline  # noqa: F401
+from . import split, pattern, lsq, spai, psai, drop, krylov, smw, adjoint, pipeline  # noqa: F401
