@@ -121,13 +121,20 @@ void sai_split_destroy(sai_split_t* h);
  *                P(A~(:,k)) (or {k}), spai_steps steps of spai_per_step indices,
  *                stopping when ||A~ m_k - e_k|| <= delta.  The pattern search
  *                always runs in float64; the final solve in `precision`.
+ *   SAI_PAT_PSAI_TOL  PSAI(tol) (Section 2.2): from S = {k}, loops l = 0 ..
+ *                psai_lmax add the structural power pattern P(|A~|^(l+1) e_k) to
+ *                S, solve on S, drop |m_jk| <= delta / (|S| ||A~||_1) (tolk,
+ *                the largest entry kept), and stop once ||A~ m_k - e_k|| <= delta
+ *                (the residual before that drop).  Runs in float64; the kept
+ *                values are stored in `precision` without a re-solve; `drop`
+ *                and `tau` are not used.
  * Dropping after the solve (Section 2.2, (tolk)): SAI_DROP_ABS drops
  * |m_jk| <= tau, SAI_DROP_TOLK drops |m_jk| <= delta/(|J_k| ||A~||_1); the
  * largest entry of each column is always kept; no re-solve.
  * precision: SAI_FP32 builds M in float32 ("mixed"), SAI_FP64 in float64.
  * Errors: SAI_EINVAL, SAI_ESINGULAR (a column block without full column rank),
  * SAI_ETOOBIG (|J_k| > 128 or |I_k| > 4096), SAI_ENOMEM, SAI_EHIP. */
-enum { SAI_PAT_A = 0, SAI_PAT_A2 = 1, SAI_PAT_SPAI = 2 };
+enum { SAI_PAT_A = 0, SAI_PAT_A2 = 1, SAI_PAT_SPAI = 2, SAI_PAT_PSAI_TOL = 3 };
 enum { SAI_DROP_NONE = 0, SAI_DROP_ABS = 1, SAI_DROP_TOLK = 2 };
 enum { SAI_INIT_PATTERN_A = 0, SAI_INIT_DIAG = 1 };
 enum { SAI_FP32 = 0, SAI_FP64 = 1 };
@@ -141,6 +148,7 @@ typedef struct {
   int32_t spai_init;    /* SAI_INIT_PATTERN_A | SAI_INIT_DIAG */
   int32_t precision;    /* SAI_FP32 | SAI_FP64 */
   int32_t keep_lists;   /* nonzero: keep J_k, I_k, pre-drop m_k and res_k for inspection */
+  int32_t psai_lmax;    /* SAI_PAT_PSAI_TOL: last loop index l_max, in [0, 64]; 10 */
 } sai_build_opts;
 
 typedef struct {
@@ -163,7 +171,8 @@ int sai_build(const sai_split_t* sp, const sai_build_opts* opts, void* stream,
  * keep_lists: j_ptr/j_idx (int64 offsets, int32 entries) hold J_k, i_ptr/i_idx
  * hold I_k, m_full holds m_k on J_k before dropping (same value type), res
  * the LS residual norms ||A~ m_k - e_k|| (float64, before dropping); otherwise
- * those are NULL. */
+ * those are NULL.  For SAI_PAT_PSAI_TOL, J_k and m_full are the final (dropped)
+ * pattern and values and res the residual of the last solve before its drop. */
 typedef struct {
   int32_t n, precision;
   int64_t nnz;

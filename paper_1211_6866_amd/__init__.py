@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libsai.so")
 # status codes (include/sai.h)
 OK, EINVAL, EZERODIAG, ESINGULAR, ENOCONV, EBREAKDOWN, ENOMEM, EHIP, ETOOBIG = range(9)
 KEEP_NEAREST, KEEP_LARGEST = 0, 1
-PAT_A, PAT_A2, PAT_SPAI = 0, 1, 2
+PAT_A, PAT_A2, PAT_SPAI, PAT_PSAI_TOL = 0, 1, 2, 3
 DROP_NONE, DROP_ABS, DROP_TOLK = 0, 1, 2
 INIT_PATTERN_A, INIT_DIAG = 0, 1
 FP32, FP64 = 0, 1
@@ -59,7 +59,8 @@ class SplitInfo(C.Structure):
 class BuildOpts(C.Structure):
     _fields_ = [("pattern", C.c_int32), ("drop", C.c_int32), ("tau", C.c_double),
                 ("delta", C.c_double), ("spai_steps", C.c_int32), ("spai_per_step", C.c_int32),
-                ("spai_init", C.c_int32), ("precision", C.c_int32), ("keep_lists", C.c_int32)]
+                ("spai_init", C.c_int32), ("precision", C.c_int32), ("keep_lists", C.c_int32),
+                ("psai_lmax", C.c_int32)]
 
 
 class BuildStats(C.Structure):
@@ -222,11 +223,12 @@ class Precond:
 
     def __init__(self, split: Split, pattern=PAT_A2, drop=DROP_ABS, tau=1e-3, delta=0.4,
                  spai_steps=3, spai_per_step=5, spai_init=INIT_PATTERN_A, precision=FP32,
-                 keep_lists=False):
+                 keep_lists=False, psai_lmax=10):
         L = lib()
         self.split = split
         o = BuildOpts(int(pattern), int(drop), float(tau), float(delta), int(spai_steps),
-                      int(spai_per_step), int(spai_init), int(precision), int(bool(keep_lists)))
+                      int(spai_per_step), int(spai_init), int(precision), int(bool(keep_lists)),
+                      int(psai_lmax))
         self.stats = BuildStats()
         h = C.c_void_p()
         _check(L.sai_build(split.h, C.byref(o), _stream(), C.byref(h), C.byref(self.stats)),

@@ -21,6 +21,10 @@ int solve_columns(const sai_split_s* sp, const int64_t* jptr, const int32_t* jid
 template <class V>
 void csr_transpose(int32_t nrows, int32_t ncols, const int32_t* rp, const int32_t* ci, const V* v,
                    int32_t* cp, int32_t* ri, V* cv, const Allocator& al, hipStream_t st);
+void psai_patterns(const sai_split_s* sp, const sai_build_opts& o, hipStream_t st,
+                   const Allocator& al, DBuf<int64_t>& jptr, DBuf<int32_t>& jidx,
+                   DBuf<int64_t>& iptr, DBuf<int32_t>& iidx, DBuf<int32_t>& cntJ,
+                   DBuf<int32_t>& cntI, DBuf<double>& mval, DBuf<double>& res);
 void spai_patterns(const sai_split_s* sp, const sai_build_opts& o, hipStream_t st,
                    const Allocator& al, DBuf<int64_t>& jptr, DBuf<int32_t>& jidx,
                    DBuf<int64_t>& iptr, DBuf<int32_t>& iidx, DBuf<int32_t>& cntJ,
@@ -85,6 +89,12 @@ __global__ void k_norm1(int32_t n, const int32_t* cp, const double* cv, unsigned
   atomicMax(out, (unsigned long long)__double_as_longlong(s));
 }
 
+template <class T>
+__global__ void k_to_type(int64_t m, const double* __restrict__ in, T* __restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < m; i += (int64_t)gridDim.x * NT)
+    out[i] = (T)in[i];
+}
+
 // Dropping (Section 2.2): entries of the computed column m_k with |m_jk| <= thr
 // are removed (thr = tau, or (tolk) delta / (|J_k| ||A~||_1)); the entry of
 // largest magnitude (the first of equals) is always kept.  32 lanes per column
@@ -144,8 +154,12 @@ void build_typed(const sai_split_s* sp, const sai_build_opts& o, hipStream_t st,
   t_pat.start(st);
   DBuf<int64_t> jptr, iptr;
   DBuf<int32_t> jidx, iidx, cntJ, cntI;
+  const bool psai = o.pattern == SAI_PAT_PSAI_TOL;
+  DBuf<double> m64, res64;  // PSAI(tol): values and residuals from the search
   if (o.pattern == SAI_PAT_SPAI)
     spai_patterns(sp, o, st, al, jptr, jidx, iptr, iidx, cntJ, cntI);
+  else if (psai)
+    psai_patterns(sp, o, st, al, jptr, jidx, iptr, iidx, cntJ, cntI, m64, res64);
   else
     build_patterns(sp, o.pattern, st, al, jptr, jidx, iptr, iidx, cntJ, cntI);
   t_pat.stop(st);
@@ -166,15 +180,26 @@ void build_typed(const sai_split_s* sp, const sai_build_opts& o, hipStream_t st,
   DBuf<T> mfull(&al, (size_t)nnz_full + 1);
   DBuf<double> res(&al, (size_t)n + 1);
   int64_t bcols[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  const int nsing = solve_columns<T>(sp, jptr.p, jidx.p, iptr.p, iidx.p, cntJ.p, cntI.p, hmx[0],
-                                     hmx[1], mfull.p, res.p, bcols, al, st);
+  int nsing = 0;
+  if (psai) {
+    // the search solved (and dropped) in float64; M takes the values in T
+    hipLaunchKernelGGL((k_to_type<T>), dim3(grid_for(nnz_full, NT, 65536)), dim3(NT), 0, st, nnz_full,
+                       m64.p, mfull.p);
+    LAUNCH_CHECK();
+    HIPC(hipMemcpyAsync(res.p, res64.p, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, st));
+  } else {
+    nsing = solve_columns<T>(sp, jptr.p, jidx.p, iptr.p, iidx.p, cntJ.p, cntI.p, hmx[0], hmx[1],
+                             mfull.p, res.p, bcols, al, st);
+  }
   t_ls.stop(st);
   if (nsing > 0)
     SAI_THROW(SAI_ESINGULAR, "%d column least-squares blocks are rank deficient", nsing);
 
   t_asm.start(st);
+  // PSAI(tol) dropped inside its loop: nothing more is dropped here
+  const int drop = psai ? SAI_DROP_NONE : o.drop;
   double norm1 = 0.0;
-  if (o.drop == SAI_DROP_TOLK) {
+  if (drop == SAI_DROP_TOLK) {
     DBuf<unsigned long long> nb(&al, 1);
     HIPC(hipMemsetAsync(nb.p, 0, sizeof(unsigned long long), st));
     hipLaunchKernelGGL(k_norm1, dim3(grid_for(n, NT)), dim3(NT), 0, st, n, sp->t_col_ptr.p,
@@ -185,7 +210,7 @@ void build_typed(const sai_split_s* sp, const sai_build_opts& o, hipStream_t st,
   }
   DBuf<int32_t> ccnt(&al, (size_t)n + 1);
   const unsigned dgrid = grid_for((int64_t)n * 32, NT);
-  hipLaunchKernelGGL((k_drop<T, true>), dim3(dgrid), dim3(NT), 0, st, n, jptr.p, jidx.p, mfull.p, o.drop,
+  hipLaunchKernelGGL((k_drop<T, true>), dim3(dgrid), dim3(NT), 0, st, n, jptr.p, jidx.p, mfull.p, drop,
                      o.tau, o.delta, norm1, ccnt.p, nullptr, nullptr, nullptr);
   LAUNCH_CHECK();
   pc->col_ptr.alloc(&al, (size_t)n + 1);
@@ -194,7 +219,7 @@ void build_typed(const sai_split_s* sp, const sai_build_opts& o, hipStream_t st,
   pc->nnz = nnz;
   pc->row_idx.alloc(&al, (size_t)nnz + 1);
   pc->cval.alloc(&al, ((size_t)nnz + 1) * sizeof(T));
-  hipLaunchKernelGGL((k_drop<T, false>), dim3(dgrid), dim3(NT), 0, st, n, jptr.p, jidx.p, mfull.p, o.drop,
+  hipLaunchKernelGGL((k_drop<T, false>), dim3(dgrid), dim3(NT), 0, st, n, jptr.p, jidx.p, mfull.p, drop,
                      o.tau, o.delta, norm1, nullptr, pc->col_ptr.p, pc->row_idx.p, (T*)pc->cval.p);
   LAUNCH_CHECK();
   pc->row_ptr.alloc(&al, (size_t)n + 1);
@@ -245,7 +270,7 @@ void build_typed(const sai_split_s* sp, const sai_build_opts& o, hipStream_t st,
 
 void build_impl(const sai_split_s* sp, const sai_build_opts& o, hipStream_t st, sai_precond_s* pc,
                 sai_build_stats* stats) {
-  if (o.pattern < SAI_PAT_A || o.pattern > SAI_PAT_SPAI) SAI_THROW(SAI_EINVAL, "bad pattern");
+  if (o.pattern < SAI_PAT_A || o.pattern > SAI_PAT_PSAI_TOL) SAI_THROW(SAI_EINVAL, "bad pattern");
   if (o.drop < SAI_DROP_NONE || o.drop > SAI_DROP_TOLK) SAI_THROW(SAI_EINVAL, "bad drop mode");
   if (o.precision != SAI_FP32 && o.precision != SAI_FP64) SAI_THROW(SAI_EINVAL, "bad precision");
   pc->al = sp->al;

@@ -151,6 +151,123 @@ __global__ void __launch_bounds__(SNT) k_colnorm2(int32_t n, const int32_t* cp, 
   out[j] = s;
 }
 
+// Least-squares solve of column k on the pattern sJ[0..nJ) in the workgroup's
+// workspace: I = nonzero rows of A~(:, J) (ws.I, sorted), the dense block
+// A~(I, J) with e_k(I) (ws.W), Householder QR with Q^T applied to e_k,
+// back-substitution into sm[0..nJ), and the residual r = A~(:, J) m - e_k on I
+// (ws.r, columns added in order).  Returns false when |I| or the gathered
+// entries exceed the workspace or the block is rank deficient (the same in
+// every thread); rr = ||r||^2.  Every thread of the workgroup calls it.
+__device__ bool ls_solve_ws(int64_t k, const int32_t* __restrict__ cp, const int32_t* __restrict__ ri,
+                            const double* __restrict__ cv, const int32_t* sJ, int nJ, const Ws& ws,
+                            double* sm, double* sd, double* red, int* wsum, int* s_int, int& nI_out,
+                            double& rr) {
+  const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
+  // ---- I = rows of A~(:, J)
+  int tot = 0;
+  if (tid == 0) {
+    int acc = 0;
+    for (int c = 0; c < nJ; ++c) {
+      ws.off[c] = acc;
+      acc += cp[sJ[c] + 1] - cp[sJ[c]];
+    }
+    ws.off[nJ] = acc;
+    s_int[0] = acc;
+  }
+  __syncthreads();
+  tot = s_int[0];
+  if (tot > SCAPN) return false;
+  for (int f = tid; f < tot; f += SNT) {
+    int lo = 0, hi = nJ - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (ws.off[mid] <= f) lo = mid; else hi = mid - 1;
+    }
+    ws.cand[f] = ri[cp[sJ[lo]] + (f - ws.off[lo])];
+  }
+  __syncthreads();
+  const int nI = blk_sort_unique(ws.cand, tot, wsum);
+  if (nI > SCAPI || nI < nJ) return false;
+  for (int t = tid; t < nI; t += SNT) ws.I[t] = ws.cand[t];
+  __syncthreads();
+  // ---- dense block A~(I, J) (column-major, ld nI) and e_k(I) in column nJ
+  double* W = ws.W;
+  double* bv = W + (int64_t)nI * nJ;
+  for (int64_t t = tid; t < (int64_t)nI * (nJ + 1); t += SNT) W[t] = 0.0;
+  __syncthreads();
+  for (int c = 0; c < nJ; ++c) {
+    const int32_t j = sJ[c];
+    for (int32_t e = cp[j] + tid; e < cp[j + 1]; e += SNT) {
+      const int pos = bsearch_eq(ws.I, nI, ri[e]);
+      W[(int64_t)c * nI + pos] = cv[e];
+    }
+  }
+  for (int t = tid; t < nI; t += SNT) bv[t] = (ws.I[t] == k) ? 1.0 : 0.0;
+  __syncthreads();
+  // ---- Householder QR, Q^T applied to the right-hand side
+  bool sing = false;
+  for (int j = 0; j < nJ; ++j) {
+    double* colj = W + (int64_t)j * nI;
+    double tail = 0.0;
+    for (int t = j + 1 + tid; t < nI; t += SNT) tail += colj[t] * colj[t];
+    tail = blk_sum(tail, red);
+    const double alpha = colj[j];
+    const double normx = sqrt(tail + alpha * alpha);
+    const double sgn = alpha >= 0.0 ? 1.0 : -1.0;
+    const double vj = alpha + sgn * normx;
+    const double vtv = tail + vj * vj;
+    if (!(normx > 0.0)) sing = true;
+    const double tau = normx > 0.0 ? 2.0 / vtv : 0.0;
+    __syncthreads();
+    if (tid == 0) colj[j] = vj;
+    __syncthreads();
+    for (int c = j + 1 + w; c <= nJ; c += SNT / WAVE) {
+      const double* colc = W + (int64_t)c * nI;
+      double d = 0.0;
+      for (int t = j + lane; t < nI; t += WAVE) d += colj[t] * colc[t];
+      d = wave_sum(d);
+      if (lane == 0) sd[c] = tau * d;
+    }
+    __syncthreads();
+    const int rows = nI - j, ncol = nJ - j;
+    for (int64_t t = tid; t < (int64_t)rows * ncol; t += SNT) {
+      const int c = j + 1 + (int)(t / rows);
+      const int rr = j + (int)(t % rows);
+      W[(int64_t)c * nI + rr] -= sd[c] * colj[rr];
+    }
+    __syncthreads();
+    if (tid == 0) colj[j] = -sgn * normx;
+    __syncthreads();
+  }
+  if (sing) return false;
+  if (w == 0) {
+    for (int c = nJ - 1; c >= 0; --c) {
+      double part = 0.0;
+      for (int q = c + 1 + lane; q < nJ; q += WAVE) part += W[(int64_t)q * nI + c] * sm[q];
+      part = wave_sum(part);
+      if (lane == 0) sm[c] = (bv[c] - part) / W[(int64_t)c * nI + c];
+    }
+  }
+  __syncthreads();
+  // ---- residual r = A~(:, J) m - e_k on I (columns added in order)
+  for (int t = tid; t < nI; t += SNT) ws.r[t] = (ws.I[t] == k) ? -1.0 : 0.0;
+  __syncthreads();
+  for (int c = 0; c < nJ; ++c) {
+    const int32_t j = sJ[c];
+    const double mc = sm[c];
+    for (int32_t e = cp[j] + tid; e < cp[j + 1]; e += SNT) {
+      const int pos = bsearch_eq(ws.I, nI, ri[e]);
+      ws.r[pos] += cv[e] * mc;
+    }
+    __syncthreads();
+  }
+  rr = 0.0;
+  for (int t = tid; t < nI; t += SNT) rr += ws.r[t] * ws.r[t];
+  rr = blk_sum(rr, red);
+  nI_out = nI;
+  return true;
+}
+
 __global__ void __launch_bounds__(SNT) k_spai(int32_t n, const int32_t* __restrict__ cp,
                                               const int32_t* __restrict__ ri,
                                               const double* __restrict__ cv,
@@ -195,107 +312,12 @@ __global__ void __launch_bounds__(SNT) k_spai(int32_t n, const int32_t* __restri
     __syncthreads();
     bool fail = false;
     for (int step = 0; step < steps; ++step) {
-      // ---- I = rows of A~(:, J)
-      int tot = 0;
-      if (tid == 0) {
-        int acc = 0;
-        for (int c = 0; c < nJ; ++c) {
-          ws.off[c] = acc;
-          acc += cp[sJ[c] + 1] - cp[sJ[c]];
-        }
-        ws.off[nJ] = acc;
-        s_int[0] = acc;
-      }
-      __syncthreads();
-      tot = s_int[0];
-      if (tot > SCAPN) { fail = true; break; }
-      for (int f = tid; f < tot; f += SNT) {
-        int lo = 0, hi = nJ - 1;
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (ws.off[mid] <= f) lo = mid; else hi = mid - 1;
-        }
-        ws.cand[f] = ri[cp[sJ[lo]] + (f - ws.off[lo])];
-      }
-      __syncthreads();
-      const int nI = blk_sort_unique(ws.cand, tot, wsum);
-      if (nI > SCAPI || nI < nJ) { fail = true; break; }
-      for (int t = tid; t < nI; t += SNT) ws.I[t] = ws.cand[t];
-      __syncthreads();
-      // ---- dense block A~(I, J) (column-major, ld nI) and e_k(I) in column nJ
-      double* W = ws.W;
-      double* bv = W + (int64_t)nI * nJ;
-      for (int64_t t = tid; t < (int64_t)nI * (nJ + 1); t += SNT) W[t] = 0.0;
-      __syncthreads();
-      for (int c = 0; c < nJ; ++c) {
-        const int32_t j = sJ[c];
-        for (int32_t e = cp[j] + tid; e < cp[j + 1]; e += SNT) {
-          const int pos = bsearch_eq(ws.I, nI, ri[e]);
-          W[(int64_t)c * nI + pos] = cv[e];
-        }
-      }
-      for (int t = tid; t < nI; t += SNT) bv[t] = (ws.I[t] == k) ? 1.0 : 0.0;
-      __syncthreads();
-      // ---- Householder QR, Q^T applied to the right-hand side
-      bool sing = false;
-      for (int j = 0; j < nJ; ++j) {
-        double* colj = W + (int64_t)j * nI;
-        double tail = 0.0;
-        for (int t = j + 1 + tid; t < nI; t += SNT) tail += colj[t] * colj[t];
-        tail = blk_sum(tail, red);
-        const double alpha = colj[j];
-        const double normx = sqrt(tail + alpha * alpha);
-        const double sgn = alpha >= 0.0 ? 1.0 : -1.0;
-        const double vj = alpha + sgn * normx;
-        const double vtv = tail + vj * vj;
-        if (!(normx > 0.0)) sing = true;
-        const double tau = normx > 0.0 ? 2.0 / vtv : 0.0;
-        __syncthreads();
-        if (tid == 0) colj[j] = vj;
-        __syncthreads();
-        for (int c = j + 1 + w; c <= nJ; c += SNT / WAVE) {
-          const double* colc = W + (int64_t)c * nI;
-          double d = 0.0;
-          for (int t = j + lane; t < nI; t += WAVE) d += colj[t] * colc[t];
-          d = wave_sum(d);
-          if (lane == 0) sd[c] = tau * d;
-        }
-        __syncthreads();
-        const int rows = nI - j, ncol = nJ - j;
-        for (int64_t t = tid; t < (int64_t)rows * ncol; t += SNT) {
-          const int c = j + 1 + (int)(t / rows);
-          const int rr = j + (int)(t % rows);
-          W[(int64_t)c * nI + rr] -= sd[c] * colj[rr];
-        }
-        __syncthreads();
-        if (tid == 0) colj[j] = -sgn * normx;
-        __syncthreads();
-      }
-      if (sing) { fail = true; break; }
-      if (w == 0) {
-        for (int c = nJ - 1; c >= 0; --c) {
-          double part = 0.0;
-          for (int q = c + 1 + lane; q < nJ; q += WAVE) part += W[(int64_t)q * nI + c] * sm[q];
-          part = wave_sum(part);
-          if (lane == 0) sm[c] = (bv[c] - part) / W[(int64_t)c * nI + c];
-        }
-      }
-      __syncthreads();
-      // ---- residual r = A~(:, J) m - e_k on I (columns added in order)
-      for (int t = tid; t < nI; t += SNT) ws.r[t] = (ws.I[t] == k) ? -1.0 : 0.0;
-      __syncthreads();
-      for (int c = 0; c < nJ; ++c) {
-        const int32_t j = sJ[c];
-        const double mc = sm[c];
-        for (int32_t e = cp[j] + tid; e < cp[j + 1]; e += SNT) {
-          const int pos = bsearch_eq(ws.I, nI, ri[e]);
-          ws.r[pos] += cv[e] * mc;
-        }
-        __syncthreads();
-      }
+      int nI = 0;
       double rr = 0.0;
-      for (int t = tid; t < nI; t += SNT) rr += ws.r[t] * ws.r[t];
-      rr = blk_sum(rr, red);
+      if (!ls_solve_ws(k, cp, ri, cv, sJ, nJ, ws, sm, sd, red, wsum, s_int, nI, rr)) {
+        fail = true;
+        break;
+      }
       if (sqrt(rr) <= delta) break;
       // ---- candidates: nonzero columns of A~(I, :), minus J
       for (int t = tid; t < nI; t += SNT) ws.off[t] = rp[ws.I[t] + 1] - rp[ws.I[t]];
@@ -391,6 +413,146 @@ __global__ void __launch_bounds__(SNT) k_spai(int32_t n, const int32_t* __restri
   }
 }
 
+// PSAI(tol) (Section 2.2) on A~, in float64, one workgroup per column.  From
+// S = F = {k} (a^(0) = e_k), loop l = 0 .. lmax:
+//   F = nonzero rows of A~(:, F)       (P(a^(l+1)), structural)
+//   S = S u F
+//   m = argmin ||A~(I, S) m - e_k(I)||, r = A~(:, S) m - e_k   (lsprob)
+//   drop |m_j| <= delta / (|S| ||A~||_1), the largest entry kept (first of
+//   equals)                                                    (tolk)
+//   stop when ||r|| <= delta (the residual before the drop).
+// The kept entries keep their values (no re-solve).  The final S and m go to
+// jpad / mpad at k * SJMAX, |S| to cntJ[k], ||r|| to res[k].
+__global__ void __launch_bounds__(SNT) k_psai(int32_t n, const int32_t* __restrict__ cp,
+                                              const int32_t* __restrict__ ri,
+                                              const double* __restrict__ cv, int lmax, double delta,
+                                              double a1, int32_t* __restrict__ jpad,
+                                              double* __restrict__ mpad, int32_t* __restrict__ cntJ,
+                                              double* __restrict__ res, Ws ws0,
+                                              int32_t* __restrict__ fr0, int* __restrict__ err) {
+  __shared__ int32_t sJ[SJMAX + 8];
+  __shared__ double sm[SJMAX];
+  __shared__ double sd[SJMAX + 1];
+  __shared__ double red[SNT / WAVE];
+  __shared__ int wsum[SNT / WAVE + 1];
+  __shared__ int s_int[4];
+  const int tid = threadIdx.x;
+  const int slot = blockIdx.x;
+  Ws ws;
+  ws.I = ws0.I + (int64_t)slot * SCAPI;
+  ws.cand = ws0.cand + (int64_t)slot * SCAPN;
+  ws.off = ws0.off + (int64_t)slot * (SCAPI + 1);
+  ws.W = ws0.W + (int64_t)slot * SCAPI * (SJMAX + 1);
+  ws.r = ws0.r + (int64_t)slot * SCAPI;
+  ws.g = ws0.g + (int64_t)slot * SCAPN;
+  int32_t* F = fr0 + (int64_t)slot * SCAPI;  // P(a^(l)), sorted
+
+  for (int64_t k = blockIdx.x; k < n; k += gridDim.x) {
+    if (tid == 0) {
+      sJ[0] = (int32_t)k;
+      F[0] = (int32_t)k;
+    }
+    int nJ = 1, nF = 1;
+    __syncthreads();
+    bool fail = false;
+    double rr = 0.0;
+    for (int l = 0; l <= lmax; ++l) {
+      // ---- F = nonzero rows of A~(:, F)
+      for (int t = tid; t < nF; t += SNT) ws.off[t] = cp[F[t] + 1] - cp[F[t]];
+      __syncthreads();
+      const int tot = blk_exscan(ws.off, nF, wsum);
+      if (tid == 0) ws.off[nF] = tot;
+      __syncthreads();
+      if (tot > SCAPN) { fail = true; break; }
+      for (int f = tid; f < tot; f += SNT) {
+        int lo = 0, hi = nF - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (ws.off[mid] <= f) lo = mid; else hi = mid - 1;
+        }
+        ws.cand[f] = ri[cp[F[lo]] + (f - ws.off[lo])];
+      }
+      __syncthreads();
+      nF = blk_sort_unique(ws.cand, tot, wsum);
+      if (nF > SCAPI) { fail = true; break; }
+      for (int t = tid; t < nF; t += SNT) F[t] = ws.cand[t];
+      __syncthreads();
+      // ---- S = S u F
+      for (int t = tid; t < nF; t += SNT) ws.cand[t] = F[t];
+      for (int t = tid; t < nJ; t += SNT) ws.cand[nF + t] = sJ[t];
+      __syncthreads();
+      const int nS = blk_sort_unique(ws.cand, nF + nJ, wsum);
+      if (nS > SJMAX) { fail = true; break; }
+      for (int t = tid; t < nS; t += SNT) sJ[t] = ws.cand[t];
+      nJ = nS;
+      __syncthreads();
+      // ---- least-squares solve on S
+      int nI = 0;
+      if (!ls_solve_ws(k, cp, ri, cv, sJ, nJ, ws, sm, sd, red, wsum, s_int, nI, rr)) {
+        fail = true;
+        break;
+      }
+      // ---- (tolk) drop, the largest entry (first of equals) kept
+      if (tid == 0) {
+        const double tol = delta / ((double)nJ * a1);
+        int big = 0;
+        for (int c = 1; c < nJ; ++c)
+          if (fabs(sm[c]) > fabs(sm[big])) big = c;
+        int q = 0;
+        for (int c = 0; c < nJ; ++c) {
+          if (fabs(sm[c]) > tol || c == big) {
+            sJ[q] = sJ[c];
+            sm[q] = sm[c];
+            ++q;
+          }
+        }
+        s_int[1] = q;
+      }
+      __syncthreads();
+      nJ = s_int[1];
+      if (sqrt(rr) <= delta) break;
+    }
+    if (fail) {
+      if (tid == 0) atomicOr(err, E_TOOBIG);
+      __syncthreads();
+      continue;
+    }
+    const int64_t o = k * SJMAX;
+    for (int t = tid; t < nJ; t += SNT) {
+      jpad[o + t] = sJ[t];
+      mpad[o + t] = sm[t];
+    }
+    if (tid == 0) {
+      cntJ[k] = nJ;
+      res[k] = sqrt(rr);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(SNT) k_colabs(int32_t n, const int32_t* cp, const double* cv,
+                                                double* out) {
+  const int64_t j = (int64_t)blockIdx.x * SNT + threadIdx.x;
+  if (j >= n) return;
+  double s = 0.0;
+  for (int32_t e = cp[j]; e < cp[j + 1]; ++e) s += fabs(cv[e]);
+  out[j] = s;
+}
+
+// Copy the padded rows (k * SJMAX, length cnt[k]) of a list and its values to
+// their packed offsets off[k].
+__global__ void k_compact_psai(int32_t n, const int32_t* __restrict__ jpad,
+                               const double* __restrict__ mpad, const int64_t* __restrict__ off,
+                               int32_t* __restrict__ jout, double* __restrict__ mout) {
+  const int64_t k = (int64_t)blockIdx.x * SNT + threadIdx.x;
+  if (k >= n) return;
+  const int64_t a = off[k], b = off[k + 1], p = k * SJMAX;
+  for (int64_t t = 0; t < b - a; ++t) {
+    jout[a + t] = jpad[p + t];
+    mout[a + t] = mpad[p + t];
+  }
+}
+
 __global__ void k_spai_ub(int32_t n, const int32_t* cp, int init, int extra, int32_t* ub) {
   const int64_t k = (int64_t)blockIdx.x * SNT + threadIdx.x;
   if (k < n) ub[k] = (init == SAI_INIT_DIAG ? 1 : cp[k + 1] - cp[k]) + extra;
@@ -456,6 +618,63 @@ void spai_patterns(const sai_split_s* sp, const sai_build_opts& o, hipStream_t s
   jidx.alloc(&al, (size_t)jtot + 1);
   hipLaunchKernelGGL(k_compact_lists, dim3(grid_for(n, SNT)), dim3(SNT), 0, st, n, poff.p, pad.p,
                      jptr.p, jidx.p);
+  LAUNCH_CHECK();
+  rows_of_patterns(sp, st, al, jptr, jidx, iptr, iidx, cntI);
+}
+
+// PSAI(tol): final patterns J_k (packed), their values (float64, packed), the
+// residual norms of the last solves, and |J_k|; I_k for the statistics and
+// inspection.
+void psai_patterns(const sai_split_s* sp, const sai_build_opts& o, hipStream_t st,
+                   const Allocator& al, DBuf<int64_t>& jptr, DBuf<int32_t>& jidx,
+                   DBuf<int64_t>& iptr, DBuf<int32_t>& iidx, DBuf<int32_t>& cntJ,
+                   DBuf<int32_t>& cntI, DBuf<double>& mval, DBuf<double>& res) {
+  const int32_t n = sp->n;
+  if (o.psai_lmax < 0 || o.psai_lmax > 64) SAI_THROW(SAI_EINVAL, "psai_lmax must be in [0, 64]");
+  if (!(o.delta > 0.0)) SAI_THROW(SAI_EINVAL, "delta must be > 0");
+  SAI_PROF("psai_search", st);
+  // ||A~||_1
+  double a1 = 0.0;
+  {
+    DBuf<double> cs(&al, (size_t)n);
+    hipLaunchKernelGGL(k_colabs, dim3(grid_for(n, SNT)), dim3(SNT), 0, st, n, sp->t_col_ptr.p,
+                       sp->t_cval.p, cs.p);
+    LAUNCH_CHECK();
+    std::vector<double> h((size_t)n);
+    HIPC(hipMemcpyAsync(h.data(), cs.p, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    for (double v : h) a1 = std::max(a1, v);
+  }
+  if (!(a1 > 0.0)) SAI_THROW(SAI_EINVAL, "A~ is zero");
+  DBuf<int32_t> jpad(&al, (size_t)n * SJMAX);
+  DBuf<double> mpad(&al, (size_t)n * SJMAX);
+  cntJ.alloc(&al, (size_t)n + 1);
+  res.alloc(&al, (size_t)n + 1);
+  const int nslot = (int)std::min<int64_t>(
+      {(int64_t)n, (int64_t)NSLOT_MAX,
+       (int64_t)tune_get("SPAI_SLOTS", resident_blocks((const void*)k_psai, SNT))});
+  DBuf<int32_t> wI(&al, (size_t)nslot * SCAPI), wc(&al, (size_t)nslot * SCAPN),
+      wo(&al, (size_t)nslot * (SCAPI + 1)), wf(&al, (size_t)nslot * SCAPI);
+  DBuf<double> wW(&al, (size_t)nslot * SCAPI * (SJMAX + 1)), wr(&al, (size_t)nslot * SCAPI),
+      wg(&al, (size_t)nslot * SCAPN);
+  DBuf<int> err(&al, 1);
+  HIPC(hipMemsetAsync(err.p, 0, sizeof(int), st));
+  Ws ws{wI.p, wc.p, wo.p, wW.p, wr.p, wg.p};
+  hipLaunchKernelGGL(k_psai, dim3(nslot), dim3(SNT), 0, st, n, sp->t_col_ptr.p, sp->t_row_idx.p,
+                     sp->t_cval.p, o.psai_lmax, o.delta, a1, jpad.p, mpad.p, cntJ.p, res.p, ws, wf.p,
+                     err.p);
+  LAUNCH_CHECK();
+  const int e = read_scalar(err.p, st);
+  if (e)
+    SAI_THROW(SAI_ETOOBIG, "PSAI(tol) exceeded |J| <= %d, |I| <= %d, %d gathered entries (or a "
+              "rank-deficient block)", SJMAX, SCAPI, SCAPN);
+  jptr.alloc(&al, (size_t)n + 1);
+  exclusive_scan_i32_to_i64(cntJ.p, jptr.p, n, al, st);
+  const int64_t jtot = read_scalar(jptr.p + n, st);
+  jidx.alloc(&al, (size_t)jtot + 1);
+  mval.alloc(&al, (size_t)jtot + 1);
+  hipLaunchKernelGGL(k_compact_psai, dim3(grid_for(n, SNT)), dim3(SNT), 0, st, n, jpad.p, mpad.p,
+                     jptr.p, jidx.p, mval.p);
   LAUNCH_CHECK();
   rows_of_patterns(sp, st, al, jptr, jidx, iptr, iidx, cntI);
 }

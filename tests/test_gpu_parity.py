@@ -126,6 +126,63 @@ def _check_patterns(A, dev, kind, prec):
     print(f"worst column rel err {worst:.2e}")
 
 
+# c1: every column stops after the first loop; c2_12: one or two loops; c4_40:
+# up to eight; c3_3000: l_max = 0; c2_13x9x7: no column reaches delta, all run
+# out of loops.  (All within |S| <= 128 before the drop.)
+@pytest.mark.parametrize("name,delta,lmax", [("c1", 0.4, 10), ("c2_12", 0.2, 10), ("c4_40", 0.15, 10),
+                                              ("c3_3000", 0.4, 0), ("c2_13x9x7", 1e-3, 1)])
+@pytest.mark.parametrize("prec", [P.FP64, P.FP32])
+def test_psai_tol_vs_oracle(name, delta, lmax, prec):
+    """PSAI(tol): final patterns bit-exact, values to the build precision,
+    residuals of the last solve, against the oracle's loop."""
+    from oracle import psai as opsai
+    w, (rp, ci, va) = _load(name)
+    S = osplit.split(w.A)
+    n = w.A.shape[0]
+    g = P.Split(rp, ci, va)
+    pc = P.Precond(g, pattern=P.PAT_PSAI_TOL, delta=delta, psai_lmax=lmax, precision=prec,
+                   keep_lists=True)
+    arr = pc.arrays()
+    jp, ji = _np(arr["j_ptr"]), _np(arr["j_idx"])
+    mf, res = _np(arr["m_full"]).astype(np.float64), _np(arr["res"])
+    Ss, ms, rs, ls = opsai.psai_tol(S.At, delta=delta, lmax=lmax)
+    tol = 1e-12 if prec == P.FP64 else 1e-7
+    worst = 0.0
+    for k in range(n):
+        assert np.array_equal(ji[jp[k]:jp[k + 1]], Ss[k]), (k, ji[jp[k]:jp[k + 1]], Ss[k])
+        e = np.linalg.norm(mf[jp[k]:jp[k + 1]] - ms[k]) / np.linalg.norm(ms[k])
+        worst = max(worst, e)
+        assert e <= tol, (k, e)
+        assert abs(res[k] - rs[k]) <= 1e-12, (k, res[k], rs[k])
+    # M itself (CSC) holds exactly those columns
+    cp, ri = _np(arr["col_ptr"]), _np(arr["row_idx"])
+    assert np.array_equal(cp.astype(np.int64), jp) and np.array_equal(ri, ji)
+    print(f"{name}: loops {np.bincount(ls)}, worst column rel err {worst:.2e}")
+
+
+def test_psai_tol_too_big():
+    # the irregular case's power patterns pass 128 indices at the second loop
+    w, (rp, ci, va) = _load("c3_3000")
+    g = P.Split(rp, ci, va)
+    with pytest.raises(P.SaiError) as e:
+        P.Precond(g, pattern=P.PAT_PSAI_TOL, delta=0.4, psai_lmax=2)
+    assert e.value.code == P.ETOOBIG
+    with pytest.raises(P.SaiError) as e:
+        P.Precond(g, pattern=P.PAT_PSAI_TOL, psai_lmax=-1)
+    assert e.value.code == P.EINVAL
+
+
+def test_psai_tol_solve():
+    """A PSAI(tol) preconditioner drives the whole SMW-split solve to 1e-8."""
+    w, (rp, ci, va) = _load("c2_12")
+    b = torch.from_numpy(w.b).cuda()
+    g = P.Split(rp, ci, va)
+    pc = P.Precond(g, pattern=P.PAT_PSAI_TOL, delta=0.2, psai_lmax=10, precision=P.FP32)
+    x, st = P.solve(g, pc, b, method=P.BICGSTAB, eps=1e-8)
+    rr = np.linalg.norm(w.b - w.A @ _np(x)) / np.linalg.norm(w.b)
+    assert rr < 1.5e-8, (rr, st)
+
+
 @pytest.mark.parametrize("delta,init,prec", [(0.4, P.INIT_PATTERN_A, P.FP64),
                                               (0.05, P.INIT_PATTERN_A, P.FP64),
                                               (0.05, P.INIT_PATTERN_A, P.FP32),
