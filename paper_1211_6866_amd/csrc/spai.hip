@@ -50,6 +50,7 @@ __device__ __forceinline__ int bsearch_eq(const int32_t* a, int n, int32_t x) {
   return (lo < n && a[lo] == x) ? lo : -1;
 }
 
+template <int B>
 __device__ double blk_sum(double v, double* red) {
   v = wave_sum(v);
   const int w = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
@@ -57,16 +58,17 @@ __device__ double blk_sum(double v, double* red) {
   if (l == 0) red[w] = v;
   __syncthreads();
   double s = 0.0;
-  for (int i = 0; i < SNT / WAVE; ++i) s += red[i];
+  for (int i = 0; i < B / WAVE; ++i) s += red[i];
   __syncthreads();
   return s;
 }
 
 // In-place exclusive prefix sum of a[0..m); returns the total.
-__device__ int blk_exscan(int32_t* a, int m, int* wsum /* SNT/WAVE + 1 */) {
+template <int B>
+__device__ int blk_exscan(int32_t* a, int m, int* wsum /* B/WAVE + 1 */) {
   const int tid = threadIdx.x, w = tid / WAVE, l = tid % WAVE;
   int carry = 0;
-  for (int base = 0; base < m; base += SNT) {
+  for (int base = 0; base < m; base += B) {
     const int i = base + tid;
     const int v = i < m ? a[i] : 0;
     int incl = v;
@@ -79,7 +81,7 @@ __device__ int blk_exscan(int32_t* a, int m, int* wsum /* SNT/WAVE + 1 */) {
     if (l == WAVE - 1) wsum[w] = incl;
     __syncthreads();
     int woff = 0, tot = 0;
-    for (int q = 0; q < SNT / WAVE; ++q) {
+    for (int q = 0; q < B / WAVE; ++q) {
       if (q < w) woff += wsum[q];
       tot += wsum[q];
     }
@@ -91,11 +93,11 @@ __device__ int blk_exscan(int32_t* a, int m, int* wsum /* SNT/WAVE + 1 */) {
 }
 
 // Keep a[i] where keep(i) holds, preserving order (in place); returns the count.
-template <class Pred>
+template <int B, class Pred>
 __device__ int blk_compact(int32_t* a, int m, Pred keep, int* wsum) {
   const int tid = threadIdx.x, w = tid / WAVE, l = tid % WAVE;
   int out = 0;
-  for (int base = 0; base < m; base += SNT) {
+  for (int base = 0; base < m; base += B) {
     const int i = base + tid;
     int32_t v = 0;
     bool k = false;
@@ -109,7 +111,7 @@ __device__ int blk_compact(int32_t* a, int m, Pred keep, int* wsum) {
     if (l == 0) wsum[w] = __popcll(bal);
     __syncthreads();
     int woff = 0, tot = 0;
-    for (int q = 0; q < SNT / WAVE; ++q) {
+    for (int q = 0; q < B / WAVE; ++q) {
       if (q < w) woff += wsum[q];
       tot += wsum[q];
     }
@@ -121,15 +123,16 @@ __device__ int blk_compact(int32_t* a, int m, Pred keep, int* wsum) {
 }
 
 // Bitonic sort of a[0..m) (padded to a power of two <= cap) and de-duplication.
+template <int B>
 __device__ int blk_sort_unique(int32_t* a, int m, int* wsum) {
   const int tid = threadIdx.x;
   int P = 1;
   while (P < m) P <<= 1;
-  for (int i = m + tid; i < P; i += SNT) a[i] = 0x7fffffff;
+  for (int i = m + tid; i < P; i += B) a[i] = 0x7fffffff;
   __syncthreads();
   for (int k = 2; k <= P; k <<= 1) {
     for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int t = tid; t < (P >> 1); t += SNT) {
+      for (int t = tid; t < (P >> 1); t += B) {
         const int i = 2 * j * (t / j) + (t % j);
         const int q = i + j;
         const int32_t x = a[i], y = a[q];
@@ -139,7 +142,7 @@ __device__ int blk_sort_unique(int32_t* a, int m, int* wsum) {
     }
   }
   // the predicate reads the sorted array before any write of this chunk
-  return blk_compact(a, m, [&](int i, int32_t v) { return i == 0 || a[i - 1] != v; }, wsum);
+  return blk_compact<B>(a, m, [&](int i, int32_t v) { return i == 0 || a[i - 1] != v; }, wsum);
 }
 
 __global__ void __launch_bounds__(SNT) k_colnorm2(int32_t n, const int32_t* cp, const double* cv,
@@ -158,6 +161,7 @@ __global__ void __launch_bounds__(SNT) k_colnorm2(int32_t n, const int32_t* cp, 
 // (ws.r, columns added in order).  Returns false when |I| or the gathered
 // entries exceed the workspace or the block is rank deficient (the same in
 // every thread); rr = ||r||^2.  Every thread of the workgroup calls it.
+template <int B>
 __device__ bool ls_solve_ws(int64_t k, const int32_t* __restrict__ cp, const int32_t* __restrict__ ri,
                             const double* __restrict__ cv, const int32_t* sJ, int nJ, const Ws& ws,
                             double* sm, double* sd, double* red, int* wsum, int* s_int, int& nI_out,
@@ -177,7 +181,7 @@ __device__ bool ls_solve_ws(int64_t k, const int32_t* __restrict__ cp, const int
   __syncthreads();
   tot = s_int[0];
   if (tot > SCAPN) return false;
-  for (int f = tid; f < tot; f += SNT) {
+  for (int f = tid; f < tot; f += B) {
     int lo = 0, hi = nJ - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
@@ -186,31 +190,31 @@ __device__ bool ls_solve_ws(int64_t k, const int32_t* __restrict__ cp, const int
     ws.cand[f] = ri[cp[sJ[lo]] + (f - ws.off[lo])];
   }
   __syncthreads();
-  const int nI = blk_sort_unique(ws.cand, tot, wsum);
+  const int nI = blk_sort_unique<B>(ws.cand, tot, wsum);
   if (nI > SCAPI || nI < nJ) return false;
-  for (int t = tid; t < nI; t += SNT) ws.I[t] = ws.cand[t];
+  for (int t = tid; t < nI; t += B) ws.I[t] = ws.cand[t];
   __syncthreads();
   // ---- dense block A~(I, J) (column-major, ld nI) and e_k(I) in column nJ
   double* W = ws.W;
   double* bv = W + (int64_t)nI * nJ;
-  for (int64_t t = tid; t < (int64_t)nI * (nJ + 1); t += SNT) W[t] = 0.0;
+  for (int64_t t = tid; t < (int64_t)nI * (nJ + 1); t += B) W[t] = 0.0;
   __syncthreads();
   for (int c = 0; c < nJ; ++c) {
     const int32_t j = sJ[c];
-    for (int32_t e = cp[j] + tid; e < cp[j + 1]; e += SNT) {
+    for (int32_t e = cp[j] + tid; e < cp[j + 1]; e += B) {
       const int pos = bsearch_eq(ws.I, nI, ri[e]);
       W[(int64_t)c * nI + pos] = cv[e];
     }
   }
-  for (int t = tid; t < nI; t += SNT) bv[t] = (ws.I[t] == k) ? 1.0 : 0.0;
+  for (int t = tid; t < nI; t += B) bv[t] = (ws.I[t] == k) ? 1.0 : 0.0;
   __syncthreads();
   // ---- Householder QR, Q^T applied to the right-hand side
   bool sing = false;
   for (int j = 0; j < nJ; ++j) {
     double* colj = W + (int64_t)j * nI;
     double tail = 0.0;
-    for (int t = j + 1 + tid; t < nI; t += SNT) tail += colj[t] * colj[t];
-    tail = blk_sum(tail, red);
+    for (int t = j + 1 + tid; t < nI; t += B) tail += colj[t] * colj[t];
+    tail = blk_sum<B>(tail, red);
     const double alpha = colj[j];
     const double normx = sqrt(tail + alpha * alpha);
     const double sgn = alpha >= 0.0 ? 1.0 : -1.0;
@@ -221,7 +225,7 @@ __device__ bool ls_solve_ws(int64_t k, const int32_t* __restrict__ cp, const int
     __syncthreads();
     if (tid == 0) colj[j] = vj;
     __syncthreads();
-    for (int c = j + 1 + w; c <= nJ; c += SNT / WAVE) {
+    for (int c = j + 1 + w; c <= nJ; c += B / WAVE) {
       const double* colc = W + (int64_t)c * nI;
       double d = 0.0;
       for (int t = j + lane; t < nI; t += WAVE) d += colj[t] * colc[t];
@@ -230,7 +234,7 @@ __device__ bool ls_solve_ws(int64_t k, const int32_t* __restrict__ cp, const int
     }
     __syncthreads();
     const int rows = nI - j, ncol = nJ - j;
-    for (int64_t t = tid; t < (int64_t)rows * ncol; t += SNT) {
+    for (int64_t t = tid; t < (int64_t)rows * ncol; t += B) {
       const int c = j + 1 + (int)(t / rows);
       const int rr = j + (int)(t % rows);
       W[(int64_t)c * nI + rr] -= sd[c] * colj[rr];
@@ -250,25 +254,26 @@ __device__ bool ls_solve_ws(int64_t k, const int32_t* __restrict__ cp, const int
   }
   __syncthreads();
   // ---- residual r = A~(:, J) m - e_k on I (columns added in order)
-  for (int t = tid; t < nI; t += SNT) ws.r[t] = (ws.I[t] == k) ? -1.0 : 0.0;
+  for (int t = tid; t < nI; t += B) ws.r[t] = (ws.I[t] == k) ? -1.0 : 0.0;
   __syncthreads();
   for (int c = 0; c < nJ; ++c) {
     const int32_t j = sJ[c];
     const double mc = sm[c];
-    for (int32_t e = cp[j] + tid; e < cp[j + 1]; e += SNT) {
+    for (int32_t e = cp[j] + tid; e < cp[j + 1]; e += B) {
       const int pos = bsearch_eq(ws.I, nI, ri[e]);
       ws.r[pos] += cv[e] * mc;
     }
     __syncthreads();
   }
   rr = 0.0;
-  for (int t = tid; t < nI; t += SNT) rr += ws.r[t] * ws.r[t];
-  rr = blk_sum(rr, red);
+  for (int t = tid; t < nI; t += B) rr += ws.r[t] * ws.r[t];
+  rr = blk_sum<B>(rr, red);
   nI_out = nI;
   return true;
 }
 
-__global__ void __launch_bounds__(SNT) k_spai(int32_t n, const int32_t* __restrict__ cp,
+template <int B>
+__global__ void __launch_bounds__(B) k_spai(int32_t n, const int32_t* __restrict__ cp,
                                               const int32_t* __restrict__ ri,
                                               const double* __restrict__ cv,
                                               const int32_t* __restrict__ rp,
@@ -281,8 +286,8 @@ __global__ void __launch_bounds__(SNT) k_spai(int32_t n, const int32_t* __restri
   __shared__ int32_t sJ[SJMAX + 8];
   __shared__ double sm[SJMAX];
   __shared__ double sd[SJMAX + 1];
-  __shared__ double red[SNT / WAVE];
-  __shared__ int wsum[SNT / WAVE + 1];
+  __shared__ double red[B / WAVE];
+  __shared__ int wsum[B / WAVE + 1];
   __shared__ int32_t chosen[16];
   __shared__ int s_int[4];
   const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
@@ -307,26 +312,26 @@ __global__ void __launch_bounds__(SNT) k_spai(int32_t n, const int32_t* __restri
         if (tid == 0) atomicOr(err, E_TOOBIG);
         continue;
       }
-      for (int t = tid; t < nJ; t += SNT) sJ[t] = ri[cp[k] + t];
+      for (int t = tid; t < nJ; t += B) sJ[t] = ri[cp[k] + t];
     }
     __syncthreads();
     bool fail = false;
     for (int step = 0; step < steps; ++step) {
       int nI = 0;
       double rr = 0.0;
-      if (!ls_solve_ws(k, cp, ri, cv, sJ, nJ, ws, sm, sd, red, wsum, s_int, nI, rr)) {
+      if (!ls_solve_ws<B>(k, cp, ri, cv, sJ, nJ, ws, sm, sd, red, wsum, s_int, nI, rr)) {
         fail = true;
         break;
       }
       if (sqrt(rr) <= delta) break;
       // ---- candidates: nonzero columns of A~(I, :), minus J
-      for (int t = tid; t < nI; t += SNT) ws.off[t] = rp[ws.I[t] + 1] - rp[ws.I[t]];
+      for (int t = tid; t < nI; t += B) ws.off[t] = rp[ws.I[t] + 1] - rp[ws.I[t]];
       __syncthreads();
-      const int ntot = blk_exscan(ws.off, nI, wsum);
+      const int ntot = blk_exscan<B>(ws.off, nI, wsum);
       if (tid == 0) ws.off[nI] = ntot;
       __syncthreads();
       if (ntot > SCAPN) { fail = true; break; }
-      for (int f = tid; f < ntot; f += SNT) {
+      for (int f = tid; f < ntot; f += B) {
         int lo = 0, hi = nI - 1;
         while (lo < hi) {
           const int mid = (lo + hi + 1) >> 1;
@@ -335,11 +340,11 @@ __global__ void __launch_bounds__(SNT) k_spai(int32_t n, const int32_t* __restri
         ws.cand[f] = ci[rp[ws.I[lo]] + (f - ws.off[lo])];
       }
       __syncthreads();
-      int nN = blk_sort_unique(ws.cand, ntot, wsum);
-      nN = blk_compact(ws.cand, nN, [&](int, int32_t v) { return bsearch_eq(sJ, nJ, v) < 0; }, wsum);
+      int nN = blk_sort_unique<B>(ws.cand, ntot, wsum);
+      nN = blk_compact<B>(ws.cand, nN, [&](int, int32_t v) { return bsearch_eq(sJ, nJ, v) < 0; }, wsum);
       if (nN == 0) break;
       // ---- gains g_j = (r^T A~ e_j)^2 / ||A~ e_j||^2
-      for (int t = tid; t < nN; t += SNT) {
+      for (int t = tid; t < nN; t += B) {
         const int32_t j = ws.cand[t];
         double tj = 0.0;
         for (int32_t e = cp[j]; e < cp[j + 1]; ++e) {
@@ -354,7 +359,7 @@ __global__ void __launch_bounds__(SNT) k_spai(int32_t n, const int32_t* __restri
       for (int q = 0; q < add; ++q) {
         double bg = -1.0;
         int bt = -1;
-        for (int t = tid; t < nN; t += SNT) {
+        for (int t = tid; t < nN; t += B) {
           const double gv = ws.g[t];
           if (gv > bg || (gv == bg && bt >= 0 && ws.cand[t] < ws.cand[bt])) { bg = gv; bt = t; }
         }
@@ -371,7 +376,7 @@ __global__ void __launch_bounds__(SNT) k_spai(int32_t n, const int32_t* __restri
         if (tid == 0) {
           double gbest = -1.0;
           int tbest = -1;
-          for (int q2 = 0; q2 < SNT / WAVE; ++q2) {
+          for (int q2 = 0; q2 < B / WAVE; ++q2) {
             const double og = red[q2];
             const int ot = wsum[q2];
             if (ot >= 0 && (og > gbest || (og == gbest && (tbest < 0 || ws.cand[ot] < ws.cand[tbest])))) {
@@ -407,7 +412,7 @@ __global__ void __launch_bounds__(SNT) k_spai(int32_t n, const int32_t* __restri
       continue;
     }
     const int64_t o = jpoff[k];
-    for (int t = tid; t < nJ; t += SNT) jpad[o + t] = sJ[t];
+    for (int t = tid; t < nJ; t += B) jpad[o + t] = sJ[t];
     if (tid == 0) cntJ[k] = nJ;
     __syncthreads();
   }
@@ -423,7 +428,8 @@ __global__ void __launch_bounds__(SNT) k_spai(int32_t n, const int32_t* __restri
 //   stop when ||r|| <= delta (the residual before the drop).
 // The kept entries keep their values (no re-solve).  The final S and m go to
 // jpad / mpad at k * SJMAX, |S| to cntJ[k], ||r|| to res[k].
-__global__ void __launch_bounds__(SNT) k_psai(int32_t n, const int32_t* __restrict__ cp,
+template <int B>
+__global__ void __launch_bounds__(B) k_psai(int32_t n, const int32_t* __restrict__ cp,
                                               const int32_t* __restrict__ ri,
                                               const double* __restrict__ cv, int lmax, double delta,
                                               double a1, int32_t* __restrict__ jpad,
@@ -433,8 +439,8 @@ __global__ void __launch_bounds__(SNT) k_psai(int32_t n, const int32_t* __restri
   __shared__ int32_t sJ[SJMAX + 8];
   __shared__ double sm[SJMAX];
   __shared__ double sd[SJMAX + 1];
-  __shared__ double red[SNT / WAVE];
-  __shared__ int wsum[SNT / WAVE + 1];
+  __shared__ double red[B / WAVE];
+  __shared__ int wsum[B / WAVE + 1];
   __shared__ int s_int[4];
   const int tid = threadIdx.x;
   const int slot = blockIdx.x;
@@ -458,13 +464,13 @@ __global__ void __launch_bounds__(SNT) k_psai(int32_t n, const int32_t* __restri
     double rr = 0.0;
     for (int l = 0; l <= lmax; ++l) {
       // ---- F = nonzero rows of A~(:, F)
-      for (int t = tid; t < nF; t += SNT) ws.off[t] = cp[F[t] + 1] - cp[F[t]];
+      for (int t = tid; t < nF; t += B) ws.off[t] = cp[F[t] + 1] - cp[F[t]];
       __syncthreads();
-      const int tot = blk_exscan(ws.off, nF, wsum);
+      const int tot = blk_exscan<B>(ws.off, nF, wsum);
       if (tid == 0) ws.off[nF] = tot;
       __syncthreads();
       if (tot > SCAPN) { fail = true; break; }
-      for (int f = tid; f < tot; f += SNT) {
+      for (int f = tid; f < tot; f += B) {
         int lo = 0, hi = nF - 1;
         while (lo < hi) {
           const int mid = (lo + hi + 1) >> 1;
@@ -473,22 +479,22 @@ __global__ void __launch_bounds__(SNT) k_psai(int32_t n, const int32_t* __restri
         ws.cand[f] = ri[cp[F[lo]] + (f - ws.off[lo])];
       }
       __syncthreads();
-      nF = blk_sort_unique(ws.cand, tot, wsum);
+      nF = blk_sort_unique<B>(ws.cand, tot, wsum);
       if (nF > SCAPI) { fail = true; break; }
-      for (int t = tid; t < nF; t += SNT) F[t] = ws.cand[t];
+      for (int t = tid; t < nF; t += B) F[t] = ws.cand[t];
       __syncthreads();
       // ---- S = S u F
-      for (int t = tid; t < nF; t += SNT) ws.cand[t] = F[t];
-      for (int t = tid; t < nJ; t += SNT) ws.cand[nF + t] = sJ[t];
+      for (int t = tid; t < nF; t += B) ws.cand[t] = F[t];
+      for (int t = tid; t < nJ; t += B) ws.cand[nF + t] = sJ[t];
       __syncthreads();
-      const int nS = blk_sort_unique(ws.cand, nF + nJ, wsum);
+      const int nS = blk_sort_unique<B>(ws.cand, nF + nJ, wsum);
       if (nS > SJMAX) { fail = true; break; }
-      for (int t = tid; t < nS; t += SNT) sJ[t] = ws.cand[t];
+      for (int t = tid; t < nS; t += B) sJ[t] = ws.cand[t];
       nJ = nS;
       __syncthreads();
       // ---- least-squares solve on S
       int nI = 0;
-      if (!ls_solve_ws(k, cp, ri, cv, sJ, nJ, ws, sm, sd, red, wsum, s_int, nI, rr)) {
+      if (!ls_solve_ws<B>(k, cp, ri, cv, sJ, nJ, ws, sm, sd, red, wsum, s_int, nI, rr)) {
         fail = true;
         break;
       }
@@ -518,7 +524,7 @@ __global__ void __launch_bounds__(SNT) k_psai(int32_t n, const int32_t* __restri
       continue;
     }
     const int64_t o = k * SJMAX;
-    for (int t = tid; t < nJ; t += SNT) {
+    for (int t = tid; t < nJ; t += B) {
       jpad[o + t] = sJ[t];
       mpad[o + t] = sm[t];
     }
@@ -594,9 +600,12 @@ void spai_patterns(const sai_split_s* sp, const sai_build_opts& o, hipStream_t s
   cntJ.alloc(&al, (size_t)n + 1);
   // one workspace slot per resident workgroup (the search is latency-bound:
   // every workgroup the device can hold at once gets a column)
+  // workgroup size: four wavefronts per column (one wavefront, with more
+  // columns in flight, took twice as long on the irregular workload)
+  const int bnt = tune_get("SPAI_NT", 256) == 64 ? 64 : 256;
+  const void* kern = bnt == 64 ? (const void*)k_spai<64> : (const void*)k_spai<256>;
   const int nslot = (int)std::min<int64_t>(
-      {(int64_t)n, (int64_t)NSLOT_MAX,
-       (int64_t)tune_get("SPAI_SLOTS", resident_blocks((const void*)k_spai, SNT))});
+      {(int64_t)n, (int64_t)NSLOT_MAX, (int64_t)tune_get("SPAI_SLOTS", resident_blocks(kern, bnt))});
   DBuf<int32_t> wI(&al, (size_t)nslot * SCAPI), wc(&al, (size_t)nslot * SCAPN),
       wo(&al, (size_t)nslot * (SCAPI + 1));
   DBuf<double> wW(&al, (size_t)nslot * SCAPI * (SJMAX + 1)), wr(&al, (size_t)nslot * SCAPI),
@@ -604,9 +613,13 @@ void spai_patterns(const sai_split_s* sp, const sai_build_opts& o, hipStream_t s
   DBuf<int> err(&al, 1);
   HIPC(hipMemsetAsync(err.p, 0, sizeof(int), st));
   Ws ws{wI.p, wc.p, wo.p, wW.p, wr.p, wg.p};
-  hipLaunchKernelGGL(k_spai, dim3(nslot), dim3(SNT), 0, st, n, sp->t_col_ptr.p, sp->t_row_idx.p,
-                     sp->t_cval.p, sp->t_row_ptr.p, sp->t_col_idx.p, cn2.p, o.spai_steps,
-                     o.spai_per_step, o.delta, o.spai_init, poff.p, pad.p, cntJ.p, ws, err.p);
+  auto go = [&](auto k) {
+    hipLaunchKernelGGL(k, dim3(nslot), dim3(bnt), 0, st, n, sp->t_col_ptr.p, sp->t_row_idx.p,
+                       sp->t_cval.p, sp->t_row_ptr.p, sp->t_col_idx.p, cn2.p, o.spai_steps,
+                       o.spai_per_step, o.delta, o.spai_init, poff.p, pad.p, cntJ.p, ws, err.p);
+  };
+  if (bnt == 64) go(k_spai<64>);
+  else go(k_spai<256>);
   LAUNCH_CHECK();
   const int e = read_scalar(err.p, st);
   if (e)
@@ -650,9 +663,13 @@ void psai_patterns(const sai_split_s* sp, const sai_build_opts& o, hipStream_t s
   DBuf<double> mpad(&al, (size_t)n * SJMAX);
   cntJ.alloc(&al, (size_t)n + 1);
   res.alloc(&al, (size_t)n + 1);
+  // one wavefront per column: the problems of the first loops are small, and
+  // more columns in flight pay more than threads per column (100^3 matrix:
+  // 52 -> 34 ms); the SPAI search, with larger problems, keeps four
+  const int bnt = tune_get("PSAI_NT", 64) == 256 ? 256 : 64;
+  const void* kern = bnt == 64 ? (const void*)k_psai<64> : (const void*)k_psai<256>;
   const int nslot = (int)std::min<int64_t>(
-      {(int64_t)n, (int64_t)NSLOT_MAX,
-       (int64_t)tune_get("SPAI_SLOTS", resident_blocks((const void*)k_psai, SNT))});
+      {(int64_t)n, (int64_t)NSLOT_MAX, (int64_t)tune_get("SPAI_SLOTS", resident_blocks(kern, bnt))});
   DBuf<int32_t> wI(&al, (size_t)nslot * SCAPI), wc(&al, (size_t)nslot * SCAPN),
       wo(&al, (size_t)nslot * (SCAPI + 1)), wf(&al, (size_t)nslot * SCAPI);
   DBuf<double> wW(&al, (size_t)nslot * SCAPI * (SJMAX + 1)), wr(&al, (size_t)nslot * SCAPI),
@@ -660,9 +677,13 @@ void psai_patterns(const sai_split_s* sp, const sai_build_opts& o, hipStream_t s
   DBuf<int> err(&al, 1);
   HIPC(hipMemsetAsync(err.p, 0, sizeof(int), st));
   Ws ws{wI.p, wc.p, wo.p, wW.p, wr.p, wg.p};
-  hipLaunchKernelGGL(k_psai, dim3(nslot), dim3(SNT), 0, st, n, sp->t_col_ptr.p, sp->t_row_idx.p,
-                     sp->t_cval.p, o.psai_lmax, o.delta, a1, jpad.p, mpad.p, cntJ.p, res.p, ws, wf.p,
-                     err.p);
+  auto go = [&](auto k) {
+    hipLaunchKernelGGL(k, dim3(nslot), dim3(bnt), 0, st, n, sp->t_col_ptr.p, sp->t_row_idx.p,
+                       sp->t_cval.p, o.psai_lmax, o.delta, a1, jpad.p, mpad.p, cntJ.p, res.p, ws, wf.p,
+                       err.p);
+  };
+  if (bnt == 64) go(k_psai<64>);
+  else go(k_psai<256>);
   LAUNCH_CHECK();
   const int e = read_scalar(err.p, st);
   if (e)
