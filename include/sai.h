@@ -285,6 +285,22 @@ int sai_profile_count(void);
 int sai_profile_get(int32_t i, char* name /* host, name_cap bytes */, int32_t name_cap,
                     int64_t* launches /* host */, double* total_ms /* host */);
 
+/* ---------------------------------------------------------------- tuning --
+ * Launch-shape knobs of the kernels (gather batch sizes, grid shapes, workgroup
+ * sizes; names in upper case, e.g. "SPMM_M", "XMAP", "SGRID", "NARROW_MIN",
+ * "PSAI_NT").  A knob's value is taken from the environment variable
+ * SAI_TUNE_<name> if set, else from sai_tune_set, else the built-in default.
+ * They change speed, not results beyond the order of floating-point sums
+ * (every setting is deterministic).  The Python package's autotuner measures
+ * the variants on one device and stores its choices in a JSON file that the
+ * binding passes to sai_tune_set at load.  sai_tune_get reports the value a
+ * kernel would use (dflt when none is set).  Errors: SAI_EINVAL (a name that
+ * is empty, longer than 63 characters or not [A-Z0-9_]).  Process-wide,
+ * thread-safe; a value takes effect at the next launch. */
+int sai_tune_set(const char* name /* host */, int32_t value);
+int sai_tune_get(const char* name /* host */, int32_t dflt, int32_t* value /* host */);
+int sai_tune_clear(void);
+
 /* ------------------------------------------------------------------ misc --*/
 const char* sai_strerror(int code);
 const char* sai_last_error(void);

@@ -17,6 +17,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsai.so")
+TUNING_DIR = os.path.join(_HERE, "tuning")
 
 # status codes (include/sai.h)
 OK, EINVAL, EZERODIAG, ESINGULAR, ENOCONV, EBREAKDOWN, ENOMEM, EHIP, ETOOBIG = range(9)
@@ -133,6 +134,9 @@ def lib():
     L.sai_profile_only.argtypes = [C.c_char_p]
     L.sai_profile_count.argtypes = []
     L.sai_profile_get.argtypes = [i32, C.c_char_p, i32, C.POINTER(i64), C.POINTER(C.c_double)]
+    L.sai_tune_set.argtypes = [C.c_char_p, i32]
+    L.sai_tune_get.argtypes = [C.c_char_p, i32, C.POINTER(i32)]
+    L.sai_tune_clear.argtypes = []
 
     torch = _torch()
 
@@ -148,7 +152,46 @@ def lib():
 
     _alloc_struct = _Allocator(_alloc_fn_t(_alloc), _free_fn_t(_free), None)
     _lib = L
+    if os.environ.get("SAI_TUNING", "on") != "off" and torch.cuda.is_available():
+        load_tuning()
     return L
+
+
+def device_key() -> str:
+    """Name of the tuning file of the current device: arch and CU count."""
+    p = _torch().cuda.get_device_properties(_torch().cuda.current_device())
+    return f"{p.gcnArchName.split(':')[0]}_{p.multi_processor_count}cu"
+
+
+def tune_set(name: str, value: int):
+    """Set a launch-shape knob (sai_tune_set); SAI_TUNE_<name> still overrides."""
+    _check(lib().sai_tune_set(name.encode(), int(value)), "sai_tune_set")
+
+
+def tune_get(name: str, dflt: int = 0) -> int:
+    v = C.c_int32()
+    _check(lib().sai_tune_get(name.encode(), int(dflt), C.byref(v)), "sai_tune_get")
+    return v.value
+
+
+def tune_clear():
+    _check(lib().sai_tune_clear(), "sai_tune_clear")
+
+
+def load_tuning(path: Optional[str] = None) -> Optional[dict]:
+    """Pass the knobs of a tuning file (by default tuning/<device_key()>.json,
+    written by the autotuner) to the library; returns them, or None when there
+    is no file."""
+    import json
+    if path is None:
+        path = os.path.join(TUNING_DIR, device_key() + ".json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        knobs = json.load(f)["knobs"]
+    for name, value in knobs.items():
+        tune_set(name, value)
+    return knobs
 
 
 def _check(code: int, where: str):

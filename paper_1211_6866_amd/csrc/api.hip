@@ -168,6 +168,32 @@ const char* sai_strerror(int code) {
 
 const char* sai_last_error(void) { return sai::g_last_error.c_str(); }
 
+// [A-Z0-9_]{1,63}
+static bool tune_name_ok(const char* name) {
+  if (!name || !*name) return false;
+  size_t len = 0;
+  for (const char* c = name; *c && len < 64; ++c, ++len)
+    if (!((*c >= 'A' && *c <= 'Z') || (*c >= '0' && *c <= '9') || *c == '_')) return false;
+  return len < 64;
+}
+
+int sai_tune_set(const char* name, int32_t value) {
+  if (!tune_name_ok(name)) return SAI_EINVAL;
+  sai::tune_set(name, value);
+  return SAI_OK;
+}
+
+int sai_tune_get(const char* name, int32_t dflt, int32_t* value) {
+  if (!tune_name_ok(name) || !value) return SAI_EINVAL;
+  *value = sai::tune_get(name, dflt);
+  return SAI_OK;
+}
+
+int sai_tune_clear(void) {
+  sai::tune_clear();
+  return SAI_OK;
+}
+
 int sai_memcpy_d2d(void* dst, const void* src, size_t bytes, void* stream) {
   if (bytes == 0) return SAI_OK;
   if (!dst || !src) return SAI_EINVAL;

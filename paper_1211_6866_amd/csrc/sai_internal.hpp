@@ -241,6 +241,8 @@ T read_scalar(const T* dev, hipStream_t st) {
 // Tuning knob `name` (kernel variant or size choice): the value of the
 // environment variable SAI_TUNE_<name> if set, else `dflt`.
 int tune_get(const char* name, int dflt);
+void tune_set(const char* name, int value);
+void tune_clear();
 
 // Workgroups of `kernel` (nt threads, no dynamic LDS) resident on the current
 // device at once (occupancy per CU times the CU count); cached per device.

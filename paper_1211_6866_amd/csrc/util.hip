@@ -217,11 +217,35 @@ void exclusive_scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, const
   scan_rec<int32_t, int64_t>(in, out, n, al, st);
 }
 
+// Launch-shape knobs: the environment (SAI_TUNE_<name>) wins, then the values
+// set through sai_tune_set (a tuning file loaded by the caller), then the
+// built-in default.
+namespace {
+std::mutex tune_mu;
+std::map<std::string, int>& tune_table() {
+  static std::map<std::string, int> t;
+  return t;
+}
+}  // namespace
+
 int tune_get(const char* name, int dflt) {
   char key[128];
   snprintf(key, sizeof(key), "SAI_TUNE_%s", name);
   const char* v = getenv(key);
-  return (v && *v) ? atoi(v) : dflt;
+  if (v && *v) return atoi(v);
+  std::lock_guard<std::mutex> lk(tune_mu);
+  auto it = tune_table().find(name);
+  return it != tune_table().end() ? it->second : dflt;
+}
+
+void tune_set(const char* name, int value) {
+  std::lock_guard<std::mutex> lk(tune_mu);
+  tune_table()[name] = value;
+}
+
+void tune_clear() {
+  std::lock_guard<std::mutex> lk(tune_mu);
+  tune_table().clear();
 }
 
 int resident_blocks(const void* kernel, int nt) {

@@ -33,3 +33,28 @@ def test_library_exports_every_declared_symbol():
     assert not missing, missing
     lib.sai_strerror.restype = ctypes.c_char_p
     assert lib.sai_strerror(0) == b"ok"
+
+
+def test_tuning_knobs_host_only():
+    # sai_tune_* touch no device: set, read back, environment override, clear,
+    # rejected names
+    if not os.path.exists(LIB):
+        from paper_1211_6866_amd import build
+        build.build()
+    lib = ctypes.CDLL(LIB)
+    lib.sai_tune_set.argtypes = [ctypes.c_char_p, ctypes.c_int32]
+    lib.sai_tune_get.argtypes = [ctypes.c_char_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+    v = ctypes.c_int32()
+    assert lib.sai_tune_get(b"ZZ_TEST_KNOB", 7, ctypes.byref(v)) == 0 and v.value == 7
+    assert lib.sai_tune_set(b"ZZ_TEST_KNOB", 3) == 0
+    assert lib.sai_tune_get(b"ZZ_TEST_KNOB", 7, ctypes.byref(v)) == 0 and v.value == 3
+    os.environ["SAI_TUNE_ZZ_TEST_KNOB"] = "5"
+    try:
+        assert lib.sai_tune_get(b"ZZ_TEST_KNOB", 7, ctypes.byref(v)) == 0 and v.value == 5
+    finally:
+        del os.environ["SAI_TUNE_ZZ_TEST_KNOB"]
+    assert lib.sai_tune_clear() == 0
+    assert lib.sai_tune_get(b"ZZ_TEST_KNOB", 7, ctypes.byref(v)) == 0 and v.value == 7
+    for bad in [b"", b"lower", b"A" * 64, b"SP ACE"]:
+        assert lib.sai_tune_set(bad, 1) == 1          # SAI_EINVAL
+    assert lib.sai_tune_get(b"X", 0, None) == 1
