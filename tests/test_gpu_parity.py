@@ -436,6 +436,47 @@ def test_krylov_long_rows():
                 assert np.linalg.norm(R[:, c] - Aop @ Xh[:, c]) < thr[c], (k, transpose, c)
 
 
+def _csr32(A):
+    A = sp.csr_matrix(A)
+    A.sort_indices()
+    A.indptr = A.indptr.astype(np.int32)
+    A.indices = A.indices.astype(np.int32)
+    return A
+
+
+@pytest.mark.parametrize("case", ["n1", "n2", "tridiag5", "stencil30_s0"])
+def test_degenerate_sizes_and_no_dense_columns(case):
+    """s = 0 (no irregular column: x = y, no SMW) and matrices of 1, 2 and 5 rows,
+    through the split, both static patterns, the solve and (30 x 30) the adjoint."""
+    if case == "n1":
+        A = np.array([[3.0]])
+    elif case == "n2":
+        A = np.array([[4.0, -1.0], [-1.5, 3.0]])
+    elif case == "tridiag5":
+        A = sp.diags([np.full(4, -1.0), np.full(5, 2.5), np.full(4, -0.7)], [-1, 0, 1])
+    else:
+        r, c, v, nn = W.stencil((30, 30), 7)
+        A = sp.coo_matrix((v, (r, c)), shape=(nn, nn))
+    A = _csr32(A)
+    n = A.shape[0]
+    b = A @ np.linspace(1.0, 2.0, n)
+    g = P.Split(*P.csr_to_device(A))
+    assert g.s == 0
+    xd = sp.linalg.spsolve(sp.csc_matrix(A), b) if n > 1 else b / A.toarray()[0, 0]
+    for kind in (P.PAT_A, P.PAT_A2):
+        pc = P.Precond(g, pattern=kind, drop=P.DROP_NONE, precision=P.FP64)
+        x, st = P.solve(g, pc, torch.from_numpy(b).cuda(), eps=1e-8)
+        xs = _np(x)
+        rr = np.linalg.norm(b - A @ xs) / np.linalg.norm(b)
+        assert rr < 1.5e-8, (case, kind, rr, st)
+        assert np.linalg.norm(xs - xd) <= 1e-6 * np.linalg.norm(xd), (case, kind)
+    if case == "stencil30_s0":
+        gx = torch.from_numpy(np.cos(np.arange(n))).cuda()
+        gb, ga, bst = P.backward(g, pc, x, gx)
+        lam = sp.linalg.spsolve(sp.csc_matrix(A.T), _np(gx))
+        assert np.linalg.norm(_np(gb) - lam) <= 1e-6 * np.linalg.norm(lam)
+
+
 def test_repeat_runs_bit_identical():
     w, (rp, ci, va) = _load("c2_12")
     b = torch.from_numpy(w.b).cuda()
