@@ -21,6 +21,14 @@ namespace sai {
 void rows_of_patterns(const sai_split_s* sp, hipStream_t st, const Allocator& al,
                       const DBuf<int64_t>& jptr, const DBuf<int32_t>& jidx, DBuf<int64_t>& iptr,
                       DBuf<int32_t>& iidx, DBuf<int32_t>& cntI);
+void build_patterns(const sai_split_s* sp, int kind, hipStream_t st, const Allocator& al,
+                    DBuf<int64_t>& jptr, DBuf<int32_t>& jidx, DBuf<int64_t>& iptr,
+                    DBuf<int32_t>& iidx, DBuf<int32_t>& cntJ, DBuf<int32_t>& cntI);
+template <class T>
+int solve_columns(const sai_split_s* sp, const int64_t* jptr, const int32_t* jidx,
+                  const int64_t* iptr, const int32_t* iidx, const int32_t* cntJ,
+                  const int32_t* cntI, int maxI, int maxJ, T* mout, double* res,
+                  int64_t* bucket_cols, const Allocator& al, hipStream_t st);
 
 namespace {
 
@@ -435,7 +443,8 @@ __global__ void __launch_bounds__(B) k_psai(int32_t n, const int32_t* __restrict
                                               double a1, int32_t* __restrict__ jpad,
                                               double* __restrict__ mpad, int32_t* __restrict__ cntJ,
                                               double* __restrict__ res, Ws ws0,
-                                              int32_t* __restrict__ fr0, int* __restrict__ err) {
+                                              int32_t* __restrict__ fr0, const int32_t* __restrict__ list,
+                                              int32_t nwork, int* __restrict__ err) {
   __shared__ int32_t sJ[SJMAX + 8];
   __shared__ double sm[SJMAX];
   __shared__ double sd[SJMAX + 1];
@@ -453,7 +462,9 @@ __global__ void __launch_bounds__(B) k_psai(int32_t n, const int32_t* __restrict
   ws.g = ws0.g + (int64_t)slot * SCAPN;
   int32_t* F = fr0 + (int64_t)slot * SCAPI;  // P(a^(l)), sorted
 
-  for (int64_t k = blockIdx.x; k < n; k += gridDim.x) {
+  // work item b is column list[b] (or column b when list is NULL)
+  for (int64_t b = blockIdx.x; b < nwork; b += gridDim.x) {
+    const int64_t k = list ? (int64_t)list[b] : b;
     if (tid == 0) {
       sJ[0] = (int32_t)k;
       F[0] = (int32_t)k;
@@ -534,6 +545,83 @@ __global__ void __launch_bounds__(B) k_psai(int32_t n, const int32_t* __restrict
     }
     __syncthreads();
   }
+}
+
+// PSAI(tol) loop l = 0 from a solve on J_k = P(A~(:, k)), which is S^(1) =
+// P(A~ e_k) u {k} when the column holds its diagonal: the (tolk) drop, and the
+// column is finished when ||r|| <= delta or lmax = 0 (its kept entries go to
+// jpad / mpad at k * SJMAX); otherwise, or without a diagonal, todo[k] = 1 and
+// the search kernel redoes it from loop 0.  One thread per column.
+__global__ void __launch_bounds__(SNT) k_psai_first(int32_t n, const int64_t* __restrict__ jptr,
+                                                    const int32_t* __restrict__ jidx,
+                                                    const double* __restrict__ m,
+                                                    const double* __restrict__ r, double delta,
+                                                    double a1, int lmax, int32_t* __restrict__ jpad,
+                                                    double* __restrict__ mpad, int32_t* __restrict__ cntJ,
+                                                    double* __restrict__ res, int32_t* __restrict__ todo) {
+  const int64_t k = (int64_t)blockIdx.x * SNT + threadIdx.x;
+  if (k >= n) return;
+  const int64_t a = jptr[k];
+  const int nJ = (int)(jptr[k + 1] - a);
+  bool diag = false;
+  for (int c = 0; c < nJ; ++c) diag |= jidx[a + c] == (int32_t)k;
+  if (!diag || nJ > SJMAX || !(r[k] <= delta || lmax == 0)) {
+    todo[k] = 1;
+    return;
+  }
+  todo[k] = 0;
+  const double tol = delta / ((double)nJ * a1);
+  int big = 0;
+  for (int c = 1; c < nJ; ++c)
+    if (fabs(m[a + c]) > fabs(m[a + big])) big = c;
+  int q = 0;
+  for (int c = 0; c < nJ; ++c) {
+    if (fabs(m[a + c]) > tol || c == big) {
+      jpad[k * SJMAX + q] = jidx[a + c];
+      mpad[k * SJMAX + q] = m[a + c];
+      ++q;
+    }
+  }
+  cntJ[k] = q;
+  res[k] = r[k];
+}
+
+// out[0] = max cntI, out[1] = max cntJ (block maxima, one atomic per block)
+__global__ void __launch_bounds__(SNT) k_max2(int32_t n, const int32_t* __restrict__ cntI,
+                                              const int32_t* __restrict__ cntJ, int* __restrict__ out) {
+  __shared__ int red[2][SNT / WAVE];
+  int mi = 0, mj = 0;
+  for (int64_t k = (int64_t)blockIdx.x * SNT + threadIdx.x; k < n; k += (int64_t)gridDim.x * SNT) {
+    mi = max(mi, cntI[k]);
+    mj = max(mj, cntJ[k]);
+  }
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    mi = max(mi, __shfl_xor(mi, o, WAVE));
+    mj = max(mj, __shfl_xor(mj, o, WAVE));
+  }
+  if (threadIdx.x % WAVE == 0) {
+    red[0][threadIdx.x / WAVE] = mi;
+    red[1][threadIdx.x / WAVE] = mj;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < SNT / WAVE; ++q) {
+      mi = max(mi, red[0][q]);
+      mj = max(mj, red[1][q]);
+    }
+    atomicMax(&out[0], mi);
+    atomicMax(&out[1], mj);
+  }
+}
+
+// The columns with flag[k] != 0, in unspecified order (at most cap kept), and their number.
+__global__ void __launch_bounds__(SNT) k_list_flagged(int32_t n, const int32_t* __restrict__ flag,
+                                                      int32_t* __restrict__ list, int cap,
+                                                      int* __restrict__ count) {
+  const int64_t k = (int64_t)blockIdx.x * SNT + threadIdx.x;
+  const bool f = k < n && flag[k] != 0;
+  const int slot = block_slot<1>(count, f ? 0 : -1);
+  if (f && slot < cap) list[slot] = (int32_t)k;
 }
 
 __global__ void __launch_bounds__(SNT) k_colabs(int32_t n, const int32_t* cp, const double* cv,
@@ -663,32 +751,65 @@ void psai_patterns(const sai_split_s* sp, const sai_build_opts& o, hipStream_t s
   DBuf<double> mpad(&al, (size_t)n * SJMAX);
   cntJ.alloc(&al, (size_t)n + 1);
   res.alloc(&al, (size_t)n + 1);
-  // one wavefront per column: the problems of the first loops are small, and
-  // more columns in flight pay more than threads per column (100^3 matrix:
-  // 52 -> 34 ms); the SPAI search, with larger problems, keeps four
-  const int bnt = tune_get("PSAI_NT", 64) == 256 ? 256 : 64;
-  const void* kern = bnt == 64 ? (const void*)k_psai<64> : (const void*)k_psai<256>;
-  const int nslot = (int)std::min<int64_t>(
-      {(int64_t)n, (int64_t)NSLOT_MAX, (int64_t)tune_get("SPAI_SLOTS", resident_blocks(kern, bnt))});
-  DBuf<int32_t> wI(&al, (size_t)nslot * SCAPI), wc(&al, (size_t)nslot * SCAPN),
-      wo(&al, (size_t)nslot * (SCAPI + 1)), wf(&al, (size_t)nslot * SCAPI);
-  DBuf<double> wW(&al, (size_t)nslot * SCAPI * (SJMAX + 1)), wr(&al, (size_t)nslot * SCAPI),
-      wg(&al, (size_t)nslot * SCAPN);
-  DBuf<int> err(&al, 1);
-  HIPC(hipMemsetAsync(err.p, 0, sizeof(int), st));
-  Ws ws{wI.p, wc.p, wo.p, wW.p, wr.p, wg.p};
-  auto go = [&](auto k) {
-    hipLaunchKernelGGL(k, dim3(nslot), dim3(bnt), 0, st, n, sp->t_col_ptr.p, sp->t_row_idx.p,
-                       sp->t_cval.p, o.psai_lmax, o.delta, a1, jpad.p, mpad.p, cntJ.p, res.p, ws, wf.p,
-                       err.p);
-  };
-  if (bnt == 64) go(k_psai<64>);
-  else go(k_psai<256>);
+  DBuf<int32_t> todo(&al, (size_t)n + 1);
+  // ---- loop l = 0 on J_k = P(A~(:, k)) with the register-resident column solver
+  {
+    DBuf<int64_t> jA, iA;
+    DBuf<int32_t> jiA, iiA, cJA, cIA;
+    build_patterns(sp, SAI_PAT_A, st, al, jA, jiA, iA, iiA, cJA, cIA);
+    DBuf<int> mx(&al, 2);
+    HIPC(hipMemsetAsync(mx.p, 0, 2 * sizeof(int), st));
+    hipLaunchKernelGGL(k_max2, dim3(grid_for(n, SNT, 256)), dim3(SNT), 0, st, n, cIA.p, cJA.p, mx.p);
+    LAUNCH_CHECK();
+    int hm[2];
+    HIPC(hipMemcpyAsync(hm, mx.p, sizeof(hm), hipMemcpyDeviceToHost, st));
+    const int64_t tot = read_scalar(jA.p + n, st);
+    DBuf<double> m1(&al, (size_t)tot + 1), r1(&al, (size_t)n + 1);
+    const int nsing = solve_columns<double>(sp, jA.p, jiA.p, iA.p, iiA.p, cJA.p, cIA.p, hm[0], hm[1],
+                                            m1.p, r1.p, nullptr, al, st);
+    if (nsing > 0)
+      SAI_THROW(SAI_ESINGULAR, "%d column least-squares blocks are rank deficient", nsing);
+    hipLaunchKernelGGL(k_psai_first, dim3(grid_for(n, SNT)), dim3(SNT), 0, st, n, jA.p, jiA.p, m1.p,
+                       r1.p, o.delta, a1, o.psai_lmax, jpad.p, mpad.p, cntJ.p, res.p, todo.p);
+    LAUNCH_CHECK();
+  }
+  // ---- the other columns: the whole loop in the search kernel
+  DBuf<int32_t> list(&al, (size_t)n + 1);
+  DBuf<int> cnt(&al, 1);
+  HIPC(hipMemsetAsync(cnt.p, 0, sizeof(int), st));
+  hipLaunchKernelGGL(k_list_flagged, dim3(grid_for(n, SNT)), dim3(SNT), 0, st, n, todo.p, list.p, n,
+                     cnt.p);
   LAUNCH_CHECK();
-  const int e = read_scalar(err.p, st);
-  if (e)
-    SAI_THROW(SAI_ETOOBIG, "PSAI(tol) exceeded |J| <= %d, |I| <= %d, %d gathered entries (or a "
-              "rank-deficient block)", SJMAX, SCAPI, SCAPN);
+  const int ntodo = read_scalar(cnt.p, st);
+  if (ntodo > 0) {
+    // one wavefront per column: the problems of the first loops are small, and
+    // more columns in flight pay more than threads per column (100^3 matrix,
+    // every column through this kernel: 52 -> 34 ms); the SPAI search, with
+    // larger problems, keeps four
+    const int bnt = tune_get("PSAI_NT", 64) == 256 ? 256 : 64;
+    const void* kern = bnt == 64 ? (const void*)k_psai<64> : (const void*)k_psai<256>;
+    const int nslot = (int)std::min<int64_t>(
+        {(int64_t)ntodo, (int64_t)NSLOT_MAX, (int64_t)tune_get("SPAI_SLOTS", resident_blocks(kern, bnt))});
+    DBuf<int32_t> wI(&al, (size_t)nslot * SCAPI), wc(&al, (size_t)nslot * SCAPN),
+        wo(&al, (size_t)nslot * (SCAPI + 1)), wf(&al, (size_t)nslot * SCAPI);
+    DBuf<double> wW(&al, (size_t)nslot * SCAPI * (SJMAX + 1)), wr(&al, (size_t)nslot * SCAPI),
+        wg(&al, (size_t)nslot * SCAPN);
+    DBuf<int> err(&al, 1);
+    HIPC(hipMemsetAsync(err.p, 0, sizeof(int), st));
+    Ws ws{wI.p, wc.p, wo.p, wW.p, wr.p, wg.p};
+    auto go = [&](auto k) {
+      hipLaunchKernelGGL(k, dim3(nslot), dim3(bnt), 0, st, n, sp->t_col_ptr.p, sp->t_row_idx.p,
+                         sp->t_cval.p, o.psai_lmax, o.delta, a1, jpad.p, mpad.p, cntJ.p, res.p, ws, wf.p,
+                         (const int32_t*)list.p, (int32_t)ntodo, err.p);
+    };
+    if (bnt == 64) go(k_psai<64>);
+    else go(k_psai<256>);
+    LAUNCH_CHECK();
+    const int e = read_scalar(err.p, st);
+    if (e)
+      SAI_THROW(SAI_ETOOBIG, "PSAI(tol) exceeded |J| <= %d, |I| <= %d, %d gathered entries (or a "
+                "rank-deficient block)", SJMAX, SCAPI, SCAPN);
+  }
   jptr.alloc(&al, (size_t)n + 1);
   exclusive_scan_i32_to_i64(cntJ.p, jptr.p, n, al, st);
   const int64_t jtot = read_scalar(jptr.p + n, st);
