@@ -509,7 +509,7 @@ __global__ void __launch_bounds__(BK_NT) k_bucket_assign(int32_t n, const int32_
     atomicAdd(&lcnt[b < 0 ? nv : b], 1);
   }
   __syncthreads();
-  if (threadIdx.x <= nv && lcnt[threadIdx.x] > 0) atomicAdd(&bcount[threadIdx.x], lcnt[threadIdx.x]);
+  if ((int)threadIdx.x <= nv && lcnt[threadIdx.x] > 0) atomicAdd(&bcount[threadIdx.x], lcnt[threadIdx.x]);
 }
 
 __global__ void __launch_bounds__(BK_NT) k_bucket_scatter(int32_t n, const int32_t* __restrict__ bucket,
