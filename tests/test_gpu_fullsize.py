@@ -18,6 +18,7 @@ import workloads as W
 from oracle import drop as odrop
 from oracle import lsq as olsq
 from oracle import pattern as opat
+from oracle import psai as opsai
 from oracle import spai as ospai
 from oracle import split as osplit
 
@@ -145,3 +146,35 @@ def test_fullsize_workload(idx):
         fd = dl / (2.0 * h)
         assert abs(fd - G[q]) <= 1e-5 * max(abs(G[q]), 1e-6 * np.abs(G).max()), (q, fd, G[q])
     print("workload 4: 16 finite differences ok", flush=True)
+
+
+@pytest.mark.parametrize("idx,delta,lmax", [(2, 0.2, 10), (4, 0.2, 10)])
+def test_fullsize_psai_tol(idx, delta, lmax):
+    """PSAI(tol) at the full sizes: sampled columns against the oracle's loop
+    (final pattern bit-exact, values to FP32 rounding, residual of the last solve)."""
+    print(f"\nworkload {idx}: PSAI(tol) delta={delta} lmax={lmax}", flush=True)
+    w = W.make(idx)
+    n = w.A.shape[0]
+    S = osplit.split(w.A)
+    rp, ci, va = P.csr_to_device(w.A)
+    g = P.Split(rp, ci, va)
+    pc = P.Precond(g, pattern=P.PAT_PSAI_TOL, delta=delta, psai_lmax=lmax, precision=P.FP32,
+                   keep_lists=True)
+    pa = pc.arrays()
+    jp, ji = _np(pa["j_ptr"]), _np(pa["j_idx"])
+    mf, res = _np(pa["m_full"]).astype(np.float64), _np(pa["res"])
+    del pa
+    C = opat.as_csc(S.At)
+    a1 = odrop.norm1(C)
+    for k in _sample(n, S.D, w.seed + 1):
+        Sk, mk, rk, _ = opsai.psai_tol_column(C, k, delta, lmax, a1)
+        assert np.array_equal(ji[jp[k]:jp[k + 1]], Sk), k
+        e = np.linalg.norm(mf[jp[k]:jp[k + 1]] - mk) / np.linalg.norm(mk)
+        assert e <= 1e-7, (k, e)
+        assert abs(res[k] - rk) <= 1e-12, (k, res[k], rk)
+    print(f"workload {idx}: PSAI(tol) sampled columns ok, mean nnz/col {jp[-1] / n:.2f}", flush=True)
+    b = torch.from_numpy(w.b).cuda()
+    x, st = P.solve(g, pc, b, eps=1e-8)
+    rr = np.linalg.norm(w.b - w.A @ _np(x)) / np.linalg.norm(w.b)
+    print(f"workload {idx}: PSAI(tol) rr = {rr:.3e}, iters = {st['iters']}", flush=True)
+    assert rr < 1.5e-8
