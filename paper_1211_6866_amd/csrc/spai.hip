@@ -12,8 +12,9 @@
 // After at most `steps` augmentations the final J_k is written; the final
 // least-squares solve in the build precision happens in the common column
 // solver, as for the static patterns.  The candidate set is taken
-// structurally (all rows of I_k), and the augmented problem is solved again
-// from scratch (the paper updates the factors; the minimiser is the same).
+// structurally (all rows of I_k).  Each augmentation updates the QR factors
+// of the previous step (the rows the new columns bring are appended, the new
+// columns reflected and factored), as Section 2.1 suggests.
 #include "sai_internal.hpp"
 
 namespace sai {
@@ -47,6 +48,8 @@ struct Ws {
   double* W;      // SCAPI * (SJMAX + 1), column-major block + right-hand side
   double* r;      // SCAPI
   double* g;      // SCAPN
+  int32_t* Is;    // SCAPI, SPAI search only: I sorted
+  int32_t* P;     // SCAPI, SPAI search only: storage row of Is[q]
 };
 
 __device__ __forceinline__ int bsearch_eq(const int32_t* a, int n, int32_t x) {
@@ -280,6 +283,187 @@ __device__ bool ls_solve_ws(int64_t k, const int32_t* __restrict__ cp, const int
   return true;
 }
 
+// Least-squares solve of the SPAI search with its QR factors updated as J
+// grows (Section 2.1 notes that the factors of the augmented problem follow
+// from the previous ones).  State kept in the workspace between calls:
+//   ws.I[0..nI)   rows of I_k in storage order (the rows a step adds go last),
+//   ws.Is[0..nI)  the same rows sorted, ws.P[q] = storage row of ws.Is[q],
+//   ws.W          factor column c at W + c * SCAPI: R above the diagonal, the
+//                 reflector's other entries below it; Q^T e_k(I) at W + SJMAX * SCAPI,
+//   hv[c], ht[c]  leading entry and coefficient 2 / (v^T v) of reflector c.
+// Columns fJ[0..j0) are factored; this call adds fJ[j0..nJ): it gathers the
+// rows they bring, applies the stored reflectors to the new columns, factors
+// them, and back-substitutes into sm[0..nJ) (factor order).  Old columns and
+// reflectors are zero in the new rows, so the factors are those of the
+// row-permuted block A~(I, J) and the minimiser is the same as a solve from
+// scratch.  r = A~(:, J) m - e_k on I goes to ws.r (storage order, columns
+// added in factor order), rr = ||r||^2.  Returns false (the same in every
+// thread) when the workspace would overflow or a new column is dependent.
+template <int B>
+__device__ bool ls_extend_ws(int64_t k, const int32_t* __restrict__ cp, const int32_t* __restrict__ ri,
+                             const double* __restrict__ cv, const int32_t* fJ, int j0, int nJ,
+                             const Ws& ws, double* sm, double* sd, double* hv, double* ht, double* red,
+                             int* wsum, int* s_int, int& nI, double& rr) {
+  const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
+  const int nI0 = nI;
+  // ---- rows of the new columns that are not yet in I
+  if (tid == 0) {
+    int acc = 0;
+    for (int c = j0; c < nJ; ++c) {
+      ws.off[c - j0] = acc;
+      acc += cp[fJ[c] + 1] - cp[fJ[c]];
+    }
+    ws.off[nJ - j0] = acc;
+    s_int[0] = acc;
+  }
+  __syncthreads();
+  const int tot = s_int[0];
+  if (tot > SCAPN) return false;
+  for (int f = tid; f < tot; f += B) {
+    int lo = 0, hi = nJ - j0 - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (ws.off[mid] <= f) lo = mid; else hi = mid - 1;
+    }
+    ws.cand[f] = ri[cp[fJ[j0 + lo]] + (f - ws.off[lo])];
+  }
+  __syncthreads();
+  int nNew = blk_sort_unique<B>(ws.cand, tot, wsum);
+  nNew = blk_compact<B>(ws.cand, nNew, [&](int, int32_t v) { return bsearch_eq(ws.Is, nI0, v) < 0; }, wsum);
+  const int nI1 = nI0 + nNew;
+  if (nI1 > SCAPI || nI1 < nJ) return false;
+  // ---- merge the new rows into the sorted copy (cand + SCAPI / + 2 SCAPI as staging)
+  int32_t* tS = ws.cand + SCAPI;
+  int32_t* tP = ws.cand + 2 * SCAPI;
+  for (int q = tid; q < nI0; q += B) {
+    const int32_t v = ws.Is[q];
+    int lo = 0, hi = nNew;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (ws.cand[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    tS[q + lo] = v;
+    tP[q + lo] = ws.P[q];
+  }
+  for (int q = tid; q < nNew; q += B) {
+    const int32_t v = ws.cand[q];
+    int lo = 0, hi = nI0;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (ws.Is[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    tS[q + lo] = v;
+    tP[q + lo] = nI0 + q;
+    ws.I[nI0 + q] = v;
+  }
+  __syncthreads();
+  for (int q = tid; q < nI1; q += B) {
+    ws.Is[q] = tS[q];
+    ws.P[q] = tP[q];
+  }
+  // ---- new rows of the factored columns are zero; e_k on the new rows; the new columns
+  double* W = ws.W;
+  double* bv = W + (int64_t)SJMAX * SCAPI;
+  for (int t = tid; t < j0 * nNew; t += B) W[(int64_t)(t / nNew) * SCAPI + nI0 + t % nNew] = 0.0;
+  for (int t = tid; t < nNew; t += B) bv[nI0 + t] = (ws.I[nI0 + t] == k) ? 1.0 : 0.0;
+  for (int t = tid; t < (nJ - j0) * nI1; t += B) W[(int64_t)(j0 + t / nI1) * SCAPI + t % nI1] = 0.0;
+  __syncthreads();
+  for (int c = j0; c < nJ; ++c) {
+    const int32_t j = fJ[c];
+    for (int32_t e = cp[j] + tid; e < cp[j + 1]; e += B) {
+      const int q = bsearch_eq(ws.Is, nI1, ri[e]);
+      W[(int64_t)c * SCAPI + ws.P[q]] = cv[e];
+    }
+  }
+  __syncthreads();
+  // ---- stored reflectors applied to the new columns: one wavefront per column,
+  // storage row t always handled by lane t % WAVE
+  for (int c = j0 + w; c < nJ; c += B / WAVE) {
+    double* colc = W + (int64_t)c * SCAPI;
+    for (int j = 0; j < j0; ++j) {
+      const double* colj = W + (int64_t)j * SCAPI;
+      double d = 0.0;
+      for (int t = lane; t < nI1; t += WAVE) {
+        if (t > j) d += colj[t] * colc[t];
+        else if (t == j) d += hv[j] * colc[t];
+      }
+      d = ht[j] * wave_sum(d);
+      for (int t = lane; t < nI1; t += WAVE) {
+        if (t > j) colc[t] -= d * colj[t];
+        else if (t == j) colc[t] -= d * hv[j];
+      }
+    }
+  }
+  __syncthreads();
+  // ---- Householder steps on the new columns, applied to the later ones and Q^T e_k
+  bool sing = false;
+  for (int j = j0; j < nJ; ++j) {
+    double* colj = W + (int64_t)j * SCAPI;
+    double tail = 0.0;
+    for (int t = j + 1 + tid; t < nI1; t += B) tail += colj[t] * colj[t];
+    tail = blk_sum<B>(tail, red);
+    const double alpha = colj[j];
+    const double normx = sqrt(tail + alpha * alpha);
+    const double sgn = alpha >= 0.0 ? 1.0 : -1.0;
+    const double vj = alpha + sgn * normx;
+    const double vtv = tail + vj * vj;
+    if (!(normx > 0.0)) sing = true;
+    const double tau = normx > 0.0 ? 2.0 / vtv : 0.0;
+    __syncthreads();
+    if (tid == 0) {
+      colj[j] = vj;
+      hv[j] = vj;
+      ht[j] = tau;
+    }
+    __syncthreads();
+    for (int c = j + 1 + w; c <= nJ; c += B / WAVE) {
+      const double* colc = c == nJ ? bv : W + (int64_t)c * SCAPI;
+      double d = 0.0;
+      for (int t = j + lane; t < nI1; t += WAVE) d += colj[t] * colc[t];
+      d = wave_sum(d);
+      if (lane == 0) sd[c] = tau * d;
+    }
+    __syncthreads();
+    const int rows = nI1 - j, ncol = nJ - j;
+    for (int64_t t = tid; t < (int64_t)rows * ncol; t += B) {
+      const int c = j + 1 + (int)(t / rows);
+      const int r_ = j + (int)(t % rows);
+      double* colc = c == nJ ? bv : W + (int64_t)c * SCAPI;
+      colc[r_] -= sd[c] * colj[r_];
+    }
+    __syncthreads();
+    if (tid == 0) colj[j] = -sgn * normx;
+    __syncthreads();
+  }
+  if (sing) return false;
+  if (w == 0) {
+    for (int c = nJ - 1; c >= 0; --c) {
+      double part = 0.0;
+      for (int q = c + 1 + lane; q < nJ; q += WAVE) part += W[(int64_t)q * SCAPI + c] * sm[q];
+      part = wave_sum(part);
+      if (lane == 0) sm[c] = (bv[c] - part) / W[(int64_t)c * SCAPI + c];
+    }
+  }
+  __syncthreads();
+  // ---- residual r = A~(:, J) m - e_k on I
+  for (int t = tid; t < nI1; t += B) ws.r[t] = (ws.I[t] == k) ? -1.0 : 0.0;
+  __syncthreads();
+  for (int c = 0; c < nJ; ++c) {
+    const int32_t j = fJ[c];
+    const double mc = sm[c];
+    for (int32_t e = cp[j] + tid; e < cp[j + 1]; e += B) {
+      const int q = bsearch_eq(ws.Is, nI1, ri[e]);
+      ws.r[ws.P[q]] += cv[e] * mc;
+    }
+    __syncthreads();
+  }
+  rr = 0.0;
+  for (int t = tid; t < nI1; t += B) rr += ws.r[t] * ws.r[t];
+  rr = blk_sum<B>(rr, red);
+  nI = nI1;
+  return true;
+}
+
 template <int B>
 __global__ void __launch_bounds__(B) k_spai(int32_t n, const int32_t* __restrict__ cp,
                                               const int32_t* __restrict__ ri,
@@ -292,8 +476,11 @@ __global__ void __launch_bounds__(B) k_spai(int32_t n, const int32_t* __restrict
                                               int32_t* __restrict__ jpad, int32_t* __restrict__ cntJ,
                                               Ws ws0, int* __restrict__ err) {
   __shared__ int32_t sJ[SJMAX + 8];
+  __shared__ int32_t fJ[SJMAX];
   __shared__ double sm[SJMAX];
   __shared__ double sd[SJMAX + 1];
+  __shared__ double hv[SJMAX];
+  __shared__ double ht[SJMAX];
   __shared__ double red[B / WAVE];
   __shared__ int wsum[B / WAVE + 1];
   __shared__ int32_t chosen[16];
@@ -307,12 +494,14 @@ __global__ void __launch_bounds__(B) k_spai(int32_t n, const int32_t* __restrict
   ws.W = ws0.W + (int64_t)slot * SCAPI * (SJMAX + 1);
   ws.r = ws0.r + (int64_t)slot * SCAPI;
   ws.g = ws0.g + (int64_t)slot * SCAPN;
+  ws.Is = ws0.Is + (int64_t)slot * SCAPI;
+  ws.P = ws0.P + (int64_t)slot * SCAPI;
 
   for (int64_t k = blockIdx.x; k < n; k += gridDim.x) {
     // ---- initial pattern
     int nJ;
     if (init == SAI_INIT_DIAG) {
-      if (tid == 0) sJ[0] = (int32_t)k;
+      if (tid == 0) sJ[0] = fJ[0] = (int32_t)k;
       nJ = 1;
     } else {
       nJ = cp[k + 1] - cp[k];
@@ -320,17 +509,18 @@ __global__ void __launch_bounds__(B) k_spai(int32_t n, const int32_t* __restrict
         if (tid == 0) atomicOr(err, E_TOOBIG);
         continue;
       }
-      for (int t = tid; t < nJ; t += B) sJ[t] = ri[cp[k] + t];
+      for (int t = tid; t < nJ; t += B) sJ[t] = fJ[t] = ri[cp[k] + t];
     }
     __syncthreads();
     bool fail = false;
+    int nI = 0, j0 = 0;
     for (int step = 0; step < steps; ++step) {
-      int nI = 0;
       double rr = 0.0;
-      if (!ls_solve_ws<B>(k, cp, ri, cv, sJ, nJ, ws, sm, sd, red, wsum, s_int, nI, rr)) {
+      if (!ls_extend_ws<B>(k, cp, ri, cv, fJ, j0, nJ, ws, sm, sd, hv, ht, red, wsum, s_int, nI, rr)) {
         fail = true;
         break;
       }
+      j0 = nJ;
       if (sqrt(rr) <= delta) break;
       // ---- candidates: nonzero columns of A~(I, :), minus J
       for (int t = tid; t < nI; t += B) ws.off[t] = rp[ws.I[t] + 1] - rp[ws.I[t]];
@@ -356,8 +546,8 @@ __global__ void __launch_bounds__(B) k_spai(int32_t n, const int32_t* __restrict
         const int32_t j = ws.cand[t];
         double tj = 0.0;
         for (int32_t e = cp[j]; e < cp[j + 1]; ++e) {
-          const int pos = bsearch_eq(ws.I, nI, ri[e]);
-          if (pos >= 0) tj += ws.r[pos] * cv[e];
+          const int q = bsearch_eq(ws.Is, nI, ri[e]);
+          if (q >= 0) tj += ws.r[ws.P[q]] * cv[e];
         }
         ws.g[t] = tj * tj / cn2[j];
       }
@@ -397,10 +587,11 @@ __global__ void __launch_bounds__(B) k_spai(int32_t n, const int32_t* __restrict
         }
         __syncthreads();
       }
-      // ---- J = sorted(J + chosen)
+      // ---- J = sorted(J + chosen); the factor order appends them
       if (tid == 0) {
         for (int q = 0; q < add; ++q) {
           const int32_t v = chosen[q];
+          fJ[nJ] = v;
           int pos = nJ;
           while (pos > 0 && sJ[pos - 1] > v) {
             sJ[pos] = sJ[pos - 1];
@@ -695,12 +886,12 @@ void spai_patterns(const sai_split_s* sp, const sai_build_opts& o, hipStream_t s
   const int nslot = (int)std::min<int64_t>(
       {(int64_t)n, (int64_t)NSLOT_MAX, (int64_t)tune_get("SPAI_SLOTS", resident_blocks(kern, bnt))});
   DBuf<int32_t> wI(&al, (size_t)nslot * SCAPI), wc(&al, (size_t)nslot * SCAPN),
-      wo(&al, (size_t)nslot * (SCAPI + 1));
+      wo(&al, (size_t)nslot * (SCAPI + 1)), wS(&al, (size_t)nslot * SCAPI), wP(&al, (size_t)nslot * SCAPI);
   DBuf<double> wW(&al, (size_t)nslot * SCAPI * (SJMAX + 1)), wr(&al, (size_t)nslot * SCAPI),
       wg(&al, (size_t)nslot * SCAPN);
   DBuf<int> err(&al, 1);
   HIPC(hipMemsetAsync(err.p, 0, sizeof(int), st));
-  Ws ws{wI.p, wc.p, wo.p, wW.p, wr.p, wg.p};
+  Ws ws{wI.p, wc.p, wo.p, wW.p, wr.p, wg.p, wS.p, wP.p};
   auto go = [&](auto k) {
     hipLaunchKernelGGL(k, dim3(nslot), dim3(bnt), 0, st, n, sp->t_col_ptr.p, sp->t_row_idx.p,
                        sp->t_cval.p, sp->t_row_ptr.p, sp->t_col_idx.p, cn2.p, o.spai_steps,
