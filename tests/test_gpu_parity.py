@@ -183,6 +183,33 @@ def test_psai_tol_solve():
     assert rr < 1.5e-8, (rr, st)
 
 
+def test_spai_long_search_from_diagonal():
+    """SPAI from J = {k} with 6 steps of 8 columns: most columns go through
+    several factor updates (rows appended at each), against the oracle's
+    from-scratch solves: patterns and I bit-exact, values to 1e-12."""
+    from oracle import spai as ospai
+    w, (rp, ci, va) = _load("c3_3000")
+    S = osplit.split(w.A)
+    n = w.A.shape[0]
+    g = P.Split(rp, ci, va)
+    pc = P.Precond(g, pattern=P.PAT_SPAI, drop=P.DROP_NONE, delta=0.05, spai_steps=6,
+                   spai_per_step=8, spai_init=P.INIT_DIAG, precision=P.FP64, keep_lists=True)
+    arr = pc.arrays()
+    jp, ji, ip, ii = (_np(arr[k]) for k in ("j_ptr", "j_idx", "i_ptr", "i_idx"))
+    mf = _np(arr["m_full"])
+    out = ospai.spai(S.At, steps=6, per_step=8, delta=0.05, init="diag")
+    taken = np.zeros(7, dtype=np.int64)
+    for k in range(n):
+        J, I, m, res, t = out[k]
+        taken[t] += 1
+        assert np.array_equal(ji[jp[k]:jp[k + 1]], J), k
+        assert np.array_equal(ii[ip[k]:ip[k + 1]], I), k
+        e = np.linalg.norm(mf[jp[k]:jp[k + 1]] - m) / np.linalg.norm(m)
+        assert e <= 1e-12, (k, e)
+    assert taken[3:].sum() > n // 4
+    print(f"augmentation steps taken per column: {taken.tolist()}")
+
+
 @pytest.mark.parametrize("delta,init,prec", [(0.4, P.INIT_PATTERN_A, P.FP64),
                                               (0.05, P.INIT_PATTERN_A, P.FP64),
                                               (0.05, P.INIT_PATTERN_A, P.FP32),
