@@ -33,7 +33,7 @@ KNOBS_SOLVE = [
     ("NARROW_MIN", [2000000, 500000, 8000000]),
 ]
 KNOBS_SPAI = [
-    ("SPAI_NT", [256, 64]),            # threads per column of the SPAI search
+    ("SPAI_NT", [512, 256, 1024]),     # threads per column of the SPAI search
 ]
 
 

@@ -350,7 +350,7 @@ __global__ void __launch_bounds__(64, MINW) k_ls_qr(const int32_t* __restrict__ 
 
 // ---- large problems: one workgroup, block in global memory ------------------
 
-constexpr int BIG_NT = 256;
+constexpr int BIG_NT = 1024;  // 16 wavefronts: the column updates of a step spread over them
 constexpr int BIG_MAXI = 4096;
 constexpr int BIG_MAXJ = 128;
 
@@ -372,6 +372,7 @@ __global__ void __launch_bounds__(BIG_NT) k_ls_qr_big(const int32_t* __restrict_
   __shared__ T sd[BIG_MAXJ + 1];
   __shared__ T sm[BIG_MAXJ];
   __shared__ T red[BIG_NT / 64];
+  __shared__ T s_tail[2];
   const int tid = threadIdx.x, lane = tid % 64, w = tid / 64;
   T* W = work + (int64_t)blockIdx.x * work_stride;
   for (int64_t q = blockIdx.x; q < ncols; q += gridDim.x) {
@@ -405,12 +406,29 @@ __global__ void __launch_bounds__(BIG_NT) k_ls_qr_big(const int32_t* __restrict_
     }
     for (int t = tid; t < nI; t += BIG_NT) bvec[t] = (sI[t] == k) ? (T)1 : (T)0;
     __syncthreads();
+    // Householder steps.  Column c (c = nJ: the right-hand side) belongs to
+    // wavefront c % NW and its storage row t to lane t % 64, so a column's dot
+    // with the reflector and its update need no barrier; the owner of the next
+    // pivot column also sums that column's tail, and one barrier ends a step.
+    // Row j of pivot column j is not read after step j starts (the reflector's
+    // leading entry is vj, held by every thread), so R_jj is written by its
+    // owner lane at the next step.
+    constexpr int NW = BIG_NT / 64;
     bool sing = false;
+    if (w == 0) {
+      T tl = 0;
+      for (int t = 1 + lane; t < nI; t += 64) tl += W[t] * W[t];
+      tl = wave_sum(tl);
+      if (lane == 0) s_tail[0] = tl;
+    }
+    __syncthreads();
+    int jprev = -1;
+    T rprev = 0;
     for (int j = 0; j < nJ; ++j) {
-      T* colj = W + (int64_t)j * nI;
-      T tail = 0;
-      for (int t = j + 1 + tid; t < nI; t += BIG_NT) tail += colj[t] * colj[t];
-      tail = block_sum<BIG_NT>(tail, red);
+      if (jprev >= 0 && jprev < nI && w == jprev % NW && lane == jprev % 64)
+        W[(int64_t)jprev * nI + jprev] = rprev;
+      const T* colj = W + (int64_t)j * nI;
+      const T tail = s_tail[j & 1];
       const T alpha = j < nI ? colj[j] : (T)0;
       const T normx = sqrt(tail + alpha * alpha);
       const T sgn = alpha >= (T)0 ? (T)1 : (T)-1;
@@ -419,29 +437,29 @@ __global__ void __launch_bounds__(BIG_NT) k_ls_qr_big(const int32_t* __restrict_
       const bool ok = normx > (T)0;
       if (!ok) sing = true;
       const T tau = ok ? (T)2 / vtv : (T)0;
-      __syncthreads();
-      if (tid == 0 && j < nI) colj[j] = vj;  // column j now holds v (rows >= j)
-      __syncthreads();
-      // dots with the remaining columns and the right-hand side (column nJ)
-      for (int c = j + 1 + w; c <= nJ; c += BIG_NT / 64) {
-        const T* colc = W + (int64_t)c * nI;
+      for (int c = j + 1 + ((w - (j + 1) % NW) + NW) % NW; c <= nJ; c += NW) {
+        T* colc = W + (int64_t)c * nI;
         T d = 0;
-        for (int t = j + lane; t < nI; t += 64) d += colj[t] * colc[t];
-        d = wave_sum(d);
-        if (lane == 0) sd[c] = tau * d;
+        for (int t = j + lane; t < nI; t += 64) d += (t == j ? vj : colj[t]) * colc[t];
+        d = tau * wave_sum(d);
+        T nt = 0;
+        for (int t = j + lane; t < nI; t += 64) {
+          const T u = colc[t] - d * (t == j ? vj : colj[t]);
+          colc[t] = u;
+          if (t > j + 1) nt += u * u;
+        }
+        if (c == j + 1) {
+          nt = wave_sum(nt);
+          if (lane == 0) s_tail[(j + 1) & 1] = nt;
+        }
       }
-      __syncthreads();
-      const int rows = nI - j;
-      const int ncol = nJ - j;  // columns j+1..nJ
-      for (int64_t t = tid; t < (int64_t)rows * ncol; t += BIG_NT) {
-        const int c = j + 1 + (int)(t / rows);
-        const int rr = j + (int)(t % rows);
-        W[(int64_t)c * nI + rr] -= sd[c] * colj[rr];
-      }
-      __syncthreads();
-      if (tid == 0 && j < nI) colj[j] = -sgn * normx;  // R_jj
+      jprev = j;
+      rprev = -sgn * normx;
       __syncthreads();
     }
+    if (jprev >= 0 && jprev < nI && w == jprev % NW && lane == jprev % 64)
+      W[(int64_t)jprev * nI + jprev] = rprev;
+    __syncthreads();
     // back-substitution (one wave)
     if (w == 0) {
       for (int c = nJ - 1; c >= 0; --c) {
@@ -484,9 +502,9 @@ struct VariantTable<float> {
 };
 template <>
 struct VariantTable<double> {
-  static constexpr int N = 6;
-  static constexpr Variant v[N] = {{16, 8}, {32, 16}, {64, 32}, {128, 32}, {64, 64},
-                                   {BIG_MAXI, BIG_MAXJ}};
+  static constexpr int N = 8;
+  static constexpr Variant v[N] = {{16, 8}, {32, 16}, {64, 32}, {128, 32}, {256, 16}, {256, 32},
+                                   {64, 64}, {BIG_MAXI, BIG_MAXJ}};
 };
 
 constexpr int BK_NT = 1024;
@@ -568,7 +586,9 @@ void dispatch_variant(int v, const int32_t* list, int cnt, const int64_t* jptr,
       case 1: launch_qr<T, 16, 2, 16>(list, cnt, jptr, jidx, iptr, iidx, sp, mout, res, nsing, st); return;
       case 2: launch_qr<T, 32, 2, 32>(list, cnt, jptr, jidx, iptr, iidx, sp, mout, res, nsing, st); return;
       case 3: launch_qr<T, 64, 2, 32>(list, cnt, jptr, jidx, iptr, iidx, sp, mout, res, nsing, st); return;
-      case 4: launch_qr<T, 64, 1, 64>(list, cnt, jptr, jidx, iptr, iidx, sp, mout, res, nsing, st); return;
+      case 4: launch_qr<T, 64, 4, 16>(list, cnt, jptr, jidx, iptr, iidx, sp, mout, res, nsing, st); return;
+      case 5: launch_qr<T, 64, 4, 32>(list, cnt, jptr, jidx, iptr, iidx, sp, mout, res, nsing, st); return;
+      case 6: launch_qr<T, 64, 1, 64>(list, cnt, jptr, jidx, iptr, iidx, sp, mout, res, nsing, st); return;
       default: break;
     }
   }

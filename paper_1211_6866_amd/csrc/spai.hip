@@ -17,6 +17,8 @@
 // columns reflected and factored), as Section 2.1 suggests.
 #include "sai_internal.hpp"
 
+#include <algorithm>
+
 namespace sai {
 
 void rows_of_patterns(const sai_split_s* sp, hipStream_t st, const Allocator& al,
@@ -474,7 +476,8 @@ __global__ void __launch_bounds__(B) k_spai(int32_t n, const int32_t* __restrict
                                               double delta, int init,
                                               const int64_t* __restrict__ jpoff,
                                               int32_t* __restrict__ jpad, int32_t* __restrict__ cntJ,
-                                              Ws ws0, int* __restrict__ err) {
+                                              Ws ws0, const int32_t* __restrict__ list, int32_t nwork,
+                                              int* __restrict__ next, int* __restrict__ err) {
   __shared__ int32_t sJ[SJMAX + 8];
   __shared__ int32_t fJ[SJMAX];
   __shared__ double sm[SJMAX];
@@ -485,6 +488,7 @@ __global__ void __launch_bounds__(B) k_spai(int32_t n, const int32_t* __restrict
   __shared__ int wsum[B / WAVE + 1];
   __shared__ int32_t chosen[16];
   __shared__ int s_int[4];
+  __shared__ int s_it;
   const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
   const int slot = blockIdx.x;
   Ws ws;
@@ -497,7 +501,15 @@ __global__ void __launch_bounds__(B) k_spai(int32_t n, const int32_t* __restrict
   ws.Is = ws0.Is + (int64_t)slot * SCAPI;
   ws.P = ws0.P + (int64_t)slot * SCAPI;
 
-  for (int64_t k = blockIdx.x; k < n; k += gridDim.x) {
+  // columns are taken one at a time from the counter `next` (the list holds
+  // the costly ones first), so that no workgroup is left with a queue of them
+  for (;;) {
+    __syncthreads();  // every thread has read the previous s_it
+    if (tid == 0) s_it = atomicAdd(next, 1);
+    __syncthreads();
+    const int it = s_it;
+    if (it >= nwork) break;
+    const int64_t k = list ? list[it] : it;
     // ---- initial pattern
     int nJ;
     if (init == SAI_INIT_DIAG) {
@@ -815,6 +827,13 @@ __global__ void __launch_bounds__(SNT) k_list_flagged(int32_t n, const int32_t* 
   if (f && slot < cap) list[slot] = (int32_t)k;
 }
 
+__global__ void __launch_bounds__(SNT) k_gather_i32(int32_t m, const int32_t* __restrict__ idx,
+                                                    const int32_t* __restrict__ src,
+                                                    int32_t* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * SNT + threadIdx.x;
+  if (t < m) out[t] = src[idx[t]];
+}
+
 __global__ void __launch_bounds__(SNT) k_colabs(int32_t n, const int32_t* cp, const double* cv,
                                                 double* out) {
   const int64_t j = (int64_t)blockIdx.x * SNT + threadIdx.x;
@@ -836,6 +855,30 @@ __global__ void k_compact_psai(int32_t n, const int32_t* __restrict__ jpad,
     jout[a + t] = jpad[p + t];
     mout[a + t] = mpad[p + t];
   }
+}
+
+// Step 0 of the search from J = P(A~(:, k)), solved for every column by the
+// register-resident float64 solver (residual norms r): a column whose residual
+// is within delta keeps J (written to pad at poff[k], |J| to cntJ[k]); the
+// others are flagged in todo for the search kernel, which starts them over.
+__global__ void __launch_bounds__(SNT) k_spai_first(int32_t n, const int64_t* __restrict__ jptr,
+                                                    const int32_t* __restrict__ jidx,
+                                                    const double* __restrict__ r, double delta,
+                                                    const int64_t* __restrict__ poff,
+                                                    int32_t* __restrict__ pad, int32_t* __restrict__ cntJ,
+                                                    int32_t* __restrict__ todo) {
+  const int64_t k = (int64_t)blockIdx.x * SNT + threadIdx.x;
+  if (k >= n) return;
+  const int64_t a = jptr[k];
+  const int nJ = (int)(jptr[k + 1] - a);
+  if (!(r[k] <= delta) || nJ > SJMAX) {
+    todo[k] = 1;
+    return;
+  }
+  todo[k] = 0;
+  const int64_t o = poff[k];
+  for (int c = 0; c < nJ; ++c) pad[o + c] = jidx[a + c];
+  cntJ[k] = nJ;
 }
 
 __global__ void k_spai_ub(int32_t n, const int32_t* cp, int init, int extra, int32_t* ub) {
@@ -877,33 +920,93 @@ void spai_patterns(const sai_split_s* sp, const sai_build_opts& o, hipStream_t s
   const int64_t ptot = read_scalar(poff.p + n, st);
   DBuf<int32_t> pad(&al, (size_t)ptot + 1);
   cntJ.alloc(&al, (size_t)n + 1);
-  // one workspace slot per resident workgroup (the search is latency-bound:
-  // every workgroup the device can hold at once gets a column)
-  // workgroup size: four wavefronts per column (one wavefront, with more
-  // columns in flight, took twice as long on the irregular workload)
-  const int bnt = tune_get("SPAI_NT", 256) == 64 ? 64 : 256;
-  const void* kern = bnt == 64 ? (const void*)k_spai<64> : (const void*)k_spai<256>;
-  const int nslot = (int)std::min<int64_t>(
-      {(int64_t)n, (int64_t)NSLOT_MAX, (int64_t)tune_get("SPAI_SLOTS", resident_blocks(kern, bnt))});
-  DBuf<int32_t> wI(&al, (size_t)nslot * SCAPI), wc(&al, (size_t)nslot * SCAPN),
-      wo(&al, (size_t)nslot * (SCAPI + 1)), wS(&al, (size_t)nslot * SCAPI), wP(&al, (size_t)nslot * SCAPI);
-  DBuf<double> wW(&al, (size_t)nslot * SCAPI * (SJMAX + 1)), wr(&al, (size_t)nslot * SCAPI),
-      wg(&al, (size_t)nslot * SCAPN);
-  DBuf<int> err(&al, 1);
-  HIPC(hipMemsetAsync(err.p, 0, sizeof(int), st));
-  Ws ws{wI.p, wc.p, wo.p, wW.p, wr.p, wg.p, wS.p, wP.p};
-  auto go = [&](auto k) {
-    hipLaunchKernelGGL(k, dim3(nslot), dim3(bnt), 0, st, n, sp->t_col_ptr.p, sp->t_row_idx.p,
-                       sp->t_cval.p, sp->t_row_ptr.p, sp->t_col_idx.p, cn2.p, o.spai_steps,
-                       o.spai_per_step, o.delta, o.spai_init, poff.p, pad.p, cntJ.p, ws, err.p);
-  };
-  if (bnt == 64) go(k_spai<64>);
-  else go(k_spai<256>);
-  LAUNCH_CHECK();
-  const int e = read_scalar(err.p, st);
-  if (e)
-    SAI_THROW(SAI_ETOOBIG, "SPAI search exceeded |J| <= %d, |I| <= %d or %d candidates (or a "
-              "rank-deficient block)", SJMAX, SCAPI, SCAPN);
+  // From J = P(A~(:, k)), step 0 of every column runs on the static pattern
+  // builder and the register-resident float64 solver; only the columns whose
+  // residual exceeds delta go to the search kernel (on the irregular 200,000
+  // matrix most columns stop at step 0, and one workgroup per column spent
+  // 30 ms on their first solves).
+  DBuf<int32_t> list;
+  int nwork = n;
+  if (o.spai_init == SAI_INIT_PATTERN_A && o.spai_steps > 0) {
+    DBuf<int64_t> jA, iA;
+    DBuf<int32_t> jiA, iiA, cJA, cIA;
+    build_patterns(sp, SAI_PAT_A, st, al, jA, jiA, iA, iiA, cJA, cIA);
+    DBuf<int> mx(&al, 2);
+    HIPC(hipMemsetAsync(mx.p, 0, 2 * sizeof(int), st));
+    hipLaunchKernelGGL(k_max2, dim3(grid_for(n, SNT, 256)), dim3(SNT), 0, st, n, cIA.p, cJA.p, mx.p);
+    LAUNCH_CHECK();
+    int hm[2];
+    HIPC(hipMemcpyAsync(hm, mx.p, sizeof(hm), hipMemcpyDeviceToHost, st));
+    const int64_t tot = read_scalar(jA.p + n, st);
+    DBuf<double> m1(&al, (size_t)tot + 1), r1(&al, (size_t)n + 1);
+    const int nsing = solve_columns<double>(sp, jA.p, jiA.p, iA.p, iiA.p, cJA.p, cIA.p, hm[0], hm[1],
+                                            m1.p, r1.p, nullptr, al, st);
+    if (nsing > 0)
+      SAI_THROW(SAI_ESINGULAR, "%d column least-squares blocks are rank deficient", nsing);
+    DBuf<int32_t> todo(&al, (size_t)n + 1);
+    hipLaunchKernelGGL(k_spai_first, dim3(grid_for(n, SNT)), dim3(SNT), 0, st, n, jA.p, jiA.p, r1.p,
+                       o.delta, poff.p, pad.p, cntJ.p, todo.p);
+    LAUNCH_CHECK();
+    list.alloc(&al, (size_t)n + 1);
+    DBuf<int> cnt(&al, 1);
+    HIPC(hipMemsetAsync(cnt.p, 0, sizeof(int), st));
+    hipLaunchKernelGGL(k_list_flagged, dim3(grid_for(n, SNT)), dim3(SNT), 0, st, n, todo.p, list.p, n,
+                       cnt.p);
+    LAUNCH_CHECK();
+    nwork = read_scalar(cnt.p, st);
+    if (nwork > 1) {
+      // largest |I| of step 0 first (the order does not change any column's result)
+      DBuf<int32_t> key(&al, (size_t)nwork);
+      hipLaunchKernelGGL(k_gather_i32, dim3(grid_for(nwork, SNT)), dim3(SNT), 0, st, nwork, list.p, cIA.p,
+                         key.p);
+      LAUNCH_CHECK();
+      std::vector<int32_t> hl((size_t)nwork), hk((size_t)nwork), ord((size_t)nwork), sl((size_t)nwork);
+      HIPC(hipMemcpyAsync(hl.data(), list.p, sizeof(int32_t) * (size_t)nwork, hipMemcpyDeviceToHost, st));
+      HIPC(hipMemcpyAsync(hk.data(), key.p, sizeof(int32_t) * (size_t)nwork, hipMemcpyDeviceToHost, st));
+      HIPC(hipStreamSynchronize(st));
+      for (int i = 0; i < nwork; ++i) ord[(size_t)i] = i;
+      std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return hk[(size_t)a] > hk[(size_t)b]; });
+      for (int i = 0; i < nwork; ++i) sl[(size_t)i] = hl[(size_t)ord[(size_t)i]];
+      HIPC(hipMemcpyAsync(list.p, sl.data(), sizeof(int32_t) * (size_t)nwork, hipMemcpyHostToDevice, st));
+      HIPC(hipStreamSynchronize(st));
+    }
+  }
+  if (nwork > 0) {
+    // one workspace slot per resident workgroup (the search is latency-bound:
+    // every workgroup the device can hold at once gets a column)
+    // workgroup size: eight wavefronts per column (irregular 200,000 matrix:
+    // 22.5 ms with 8, 26.3 with 4, 28.2 with 16, 47.9 with 1)
+    const int want = (int)tune_get("SPAI_NT", 512);
+    const int bnt = (want == 64 || want == 256 || want == 1024) ? want : 512;
+    const void* kern = bnt == 64    ? (const void*)k_spai<64>
+                       : bnt == 512 ? (const void*)k_spai<512>
+                       : bnt == 1024 ? (const void*)k_spai<1024>
+                                     : (const void*)k_spai<256>;
+    const int nslot = (int)std::min<int64_t>(
+        {(int64_t)nwork, (int64_t)NSLOT_MAX, (int64_t)tune_get("SPAI_SLOTS", resident_blocks(kern, bnt))});
+    DBuf<int32_t> wI(&al, (size_t)nslot * SCAPI), wc(&al, (size_t)nslot * SCAPN),
+        wo(&al, (size_t)nslot * (SCAPI + 1)), wS(&al, (size_t)nslot * SCAPI), wP(&al, (size_t)nslot * SCAPI);
+    DBuf<double> wW(&al, (size_t)nslot * SCAPI * (SJMAX + 1)), wr(&al, (size_t)nslot * SCAPI),
+        wg(&al, (size_t)nslot * SCAPN);
+    DBuf<int> err(&al, 2);
+    HIPC(hipMemsetAsync(err.p, 0, 2 * sizeof(int), st));
+    Ws ws{wI.p, wc.p, wo.p, wW.p, wr.p, wg.p, wS.p, wP.p};
+    auto go = [&](auto k) {
+      hipLaunchKernelGGL(k, dim3(nslot), dim3(bnt), 0, st, n, sp->t_col_ptr.p, sp->t_row_idx.p,
+                         sp->t_cval.p, sp->t_row_ptr.p, sp->t_col_idx.p, cn2.p, o.spai_steps,
+                         o.spai_per_step, o.delta, o.spai_init, poff.p, pad.p, cntJ.p, ws,
+                         (const int32_t*)list.p, (int32_t)nwork, err.p + 1, err.p);
+    };
+    if (bnt == 64) go(k_spai<64>);
+    else if (bnt == 512) go(k_spai<512>);
+    else if (bnt == 1024) go(k_spai<1024>);
+    else go(k_spai<256>);
+    LAUNCH_CHECK();
+    const int e = read_scalar(err.p, st);
+    if (e)
+      SAI_THROW(SAI_ETOOBIG, "SPAI search exceeded |J| <= %d, |I| <= %d or %d candidates (or a "
+                "rank-deficient block)", SJMAX, SCAPI, SCAPN);
+  }
   jptr.alloc(&al, (size_t)n + 1);
   exclusive_scan_i32_to_i64(cntJ.p, jptr.p, n, al, st);
   const int64_t jtot = read_scalar(jptr.p + n, st);
