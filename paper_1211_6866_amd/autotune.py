@@ -30,7 +30,7 @@ KNOBS_SOLVE = [
     ("SPMM_A", [0, 1, 2]),             # A~ products: 4/2, 8/4, 7/0
     ("SGRID", [1024, 512, 2048]),      # workgroups of the streaming updates
     ("NARROW", [1, 0]),                # narrowing of the BiCGStab block
-    ("NARROW_MIN", [2000000, 500000, 8000000]),
+    ("NARROW_MIN", [1000000, 500000, 2000000, 8000000]),
 ]
 KNOBS_SPAI = [
     ("SPAI_NT", [512, 256, 1024]),     # threads per column of the SPAI search

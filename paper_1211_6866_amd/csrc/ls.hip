@@ -502,9 +502,9 @@ struct VariantTable<float> {
 };
 template <>
 struct VariantTable<double> {
-  static constexpr int N = 8;
-  static constexpr Variant v[N] = {{16, 8}, {32, 16}, {64, 32}, {128, 32}, {256, 16}, {256, 32},
-                                   {64, 64}, {BIG_MAXI, BIG_MAXJ}};
+  static constexpr int N = 9;
+  static constexpr Variant v[N] = {{16, 8}, {32, 16}, {64, 25}, {64, 32}, {128, 32}, {256, 16},
+                                   {256, 32}, {64, 64}, {BIG_MAXI, BIG_MAXJ}};
 };
 
 constexpr int BK_NT = 1024;
@@ -584,11 +584,12 @@ void dispatch_variant(int v, const int32_t* list, int cnt, const int64_t* jptr,
     switch (v) {
       case 0: launch_qr<T, 16, 1, 8>(list, cnt, jptr, jidx, iptr, iidx, sp, mout, res, nsing, st); return;
       case 1: launch_qr<T, 16, 2, 16>(list, cnt, jptr, jidx, iptr, iidx, sp, mout, res, nsing, st); return;
-      case 2: launch_qr<T, 32, 2, 32>(list, cnt, jptr, jidx, iptr, iidx, sp, mout, res, nsing, st); return;
-      case 3: launch_qr<T, 64, 2, 32>(list, cnt, jptr, jidx, iptr, iidx, sp, mout, res, nsing, st); return;
-      case 4: launch_qr<T, 64, 4, 16>(list, cnt, jptr, jidx, iptr, iidx, sp, mout, res, nsing, st); return;
-      case 5: launch_qr<T, 64, 4, 32>(list, cnt, jptr, jidx, iptr, iidx, sp, mout, res, nsing, st); return;
-      case 6: launch_qr<T, 64, 1, 64>(list, cnt, jptr, jidx, iptr, iidx, sp, mout, res, nsing, st); return;
+      case 2: launch_qr<T, 16, 4, 25>(list, cnt, jptr, jidx, iptr, iidx, sp, mout, res, nsing, st); return;
+      case 3: launch_qr<T, 32, 2, 32>(list, cnt, jptr, jidx, iptr, iidx, sp, mout, res, nsing, st); return;
+      case 4: launch_qr<T, 64, 2, 32>(list, cnt, jptr, jidx, iptr, iidx, sp, mout, res, nsing, st); return;
+      case 5: launch_qr<T, 64, 4, 16>(list, cnt, jptr, jidx, iptr, iidx, sp, mout, res, nsing, st); return;
+      case 6: launch_qr<T, 64, 4, 32>(list, cnt, jptr, jidx, iptr, iidx, sp, mout, res, nsing, st); return;
+      case 7: launch_qr<T, 64, 1, 64>(list, cnt, jptr, jidx, iptr, iidx, sp, mout, res, nsing, st); return;
       default: break;
     }
   }
