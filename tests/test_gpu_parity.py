@@ -514,3 +514,24 @@ def test_repeat_runs_bit_identical():
         x, _ = P.solve(g, pc, b)
         outs.append(_np(x))
     assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("kind", ["spai", "psai_tol"])
+def test_adaptive_builds_bit_identical(kind):
+    """The adaptive searches hand columns to workgroups dynamically (largest
+    first); M and the solution must not depend on that order."""
+    w, (rp, ci, va) = _load("c3_3000")
+    b = torch.from_numpy(w.b).cuda()
+    if kind == "spai":
+        kw = dict(pattern=P.PAT_SPAI, drop=P.DROP_NONE, delta=0.05, spai_steps=3, spai_per_step=5)
+    else:
+        kw = dict(pattern=P.PAT_PSAI_TOL, delta=0.4, psai_lmax=0)
+    outs = []
+    for _ in range(2):
+        g = P.Split(rp, ci, va)
+        pc = P.Precond(g, precision=P.FP32, **kw)
+        arr = pc.arrays()
+        x, _ = P.solve(g, pc, b)
+        outs.append([_np(arr[k]) for k in ("col_ptr", "row_idx", "cval")] + [_np(x)])
+    for u, v in zip(*outs):
+        assert np.array_equal(u, v)
