@@ -161,7 +161,9 @@ typedef struct {
   int32_t max_i, max_j;
   int32_t n_c;            /* columns with res_k > delta */
   double spar;            /* nnz(M) / nnz(A~) */
-  int64_t bucket_cols[8]; /* columns per LS kernel variant */
+  int64_t bucket_cols[16]; /* columns per LS kernel variant (in the order of the
+                             precision's variant table, the global-memory kernel
+                             last; unused slots 0) */
   float t_pattern_ms, t_ls_ms, t_assemble_ms, t_total_ms;
 } sai_build_stats;
 

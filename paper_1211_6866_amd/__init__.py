@@ -67,7 +67,7 @@ class BuildOpts(C.Structure):
 class BuildStats(C.Structure):
     _fields_ = [("n", C.c_int32), ("nnz_m", C.c_int64), ("nnz_m_full", C.c_int64),
                 ("sum_i", C.c_int64), ("max_i", C.c_int32), ("max_j", C.c_int32),
-                ("n_c", C.c_int32), ("spar", C.c_double), ("bucket_cols", C.c_int64 * 8),
+                ("n_c", C.c_int32), ("spar", C.c_double), ("bucket_cols", C.c_int64 * 16),
                 ("t_pattern_ms", C.c_float), ("t_ls_ms", C.c_float), ("t_assemble_ms", C.c_float),
                 ("t_total_ms", C.c_float)]
 

@@ -179,7 +179,7 @@ void build_typed(const sai_split_s* sp, const sai_build_opts& o, hipStream_t st,
   t_ls.start(st);
   DBuf<T> mfull(&al, (size_t)nnz_full + 1);
   DBuf<double> res(&al, (size_t)n + 1);
-  int64_t bcols[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int64_t bcols[16] = {};
   int nsing = 0;
   if (psai) {
     // the search solved (and dropped) in float64; M takes the values in T
@@ -247,7 +247,7 @@ void build_typed(const sai_split_s* sp, const sai_build_opts& o, hipStream_t st,
     stats->max_j = hs[1];
     stats->n_c = hs[2];
     stats->spar = sp->nnz_t > 0 ? (double)nnz / (double)sp->nnz_t : 0.0;
-    for (int v = 0; v < 8; ++v) stats->bucket_cols[v] = bcols[v];
+    for (int v = 0; v < 16; ++v) stats->bucket_cols[v] = bcols[v];
     stats->t_pattern_ms = t_pat.ms();
     stats->t_ls_ms = t_ls.ms();
     stats->t_assemble_ms = t_asm.ms();

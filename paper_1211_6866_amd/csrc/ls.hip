@@ -606,7 +606,7 @@ void dispatch_variant(int v, const int32_t* list, int cnt, const int64_t* jptr,
 }
 
 // Solve every column's LS problem; mout is indexed like jidx.  Returns the
-// number of columns whose block was rank deficient.  bucket_cols (host, 8) gets
+// number of columns whose block was rank deficient.  bucket_cols (host, 16) gets
 // the number of columns per kernel variant.
 template <class T>
 int solve_columns(const sai_split_s* sp, const int64_t* jptr, const int32_t* jidx,
@@ -626,6 +626,7 @@ int solve_columns(const sai_split_s* sp, const int64_t* jptr, const int32_t* jid
   HIPC(hipMemsetAsync(bcur.p, 0, sizeof(int) * (NV + 1), st));
   HIPC(hipMemsetAsync(nsing.p, 0, sizeof(int), st));
   static_assert(NV + 1 <= BK_MAXV, "bucket keys");
+  static_assert(NV <= 16, "bucket_cols holds 16 variants");
   hipLaunchKernelGGL(k_bucket_assign, dim3(grid_for(n, BK_NT, 512)), dim3(BK_NT), 0, st, n, cntJ, cntI, NV,
                      vmax.p, vmax.p + NV, bucket.p, bcount.p);
   LAUNCH_CHECK();
@@ -644,7 +645,7 @@ int solve_columns(const sai_split_s* sp, const int64_t* jptr, const int32_t* jid
                      boff.p, bcur.p, lists.p);
   LAUNCH_CHECK();
   for (int v = 0; v < NV; ++v) {
-    if (bucket_cols && v < 8) bucket_cols[v] = hc[v];
+    if (bucket_cols) bucket_cols[v] = hc[v];
     dispatch_variant<T>(v, lists.p + hoff[v], hc[v], jptr, jidx, iptr, iidx, sp, mout, res, nsing.p,
                         maxI, maxJ, al, st);
   }

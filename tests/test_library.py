@@ -1,10 +1,13 @@
 """The C-ABI library loads on the host and exports every function include/sai.h declares.
 
-No compute call is made (there may be no GPU here).
+No compute call is made (there may be no GPU here).  The binding's ctypes structures
+are checked against the C layout of the header.
 """
 import ctypes
 import os
 import re
+
+import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "sai.h")
@@ -58,3 +61,38 @@ def test_tuning_knobs_host_only():
     for bad in [b"", b"lower", b"A" * 64, b"SP ACE"]:
         assert lib.sai_tune_set(bad, 1) == 1          # SAI_EINVAL
     assert lib.sai_tune_get(b"X", 0, None) == 1
+
+
+def test_binding_structs_match_header(tmp_path):
+    """The ctypes structures of the binding have the size and field offsets of
+    the C structures in include/sai.h (compiled here with the host C compiler)."""
+    import ctypes as C
+    import shutil
+    import subprocess
+    import paper_1211_6866_amd as P
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    pairs = [("sai_allocator", P._Allocator), ("sai_split_opts", P.SplitOpts),
+             ("sai_split_info", P.SplitInfo), ("sai_build_opts", P.BuildOpts),
+             ("sai_build_stats", P.BuildStats), ("sai_precond_info", P.PrecondInfo),
+             ("sai_solve_opts", P.SolveOpts), ("sai_solve_stats", P.SolveStats)]
+    lines = ['#include <stdio.h>', '#include "sai.h"', "int main(void) {"]
+    for cname, py in pairs:
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, *_ in py._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("  return 0;\n}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(root, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for ln in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        a, b, v = ln.split()
+        got[(a, b)] = int(v)
+    for cname, py in pairs:
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for fname, *_ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
