@@ -266,7 +266,8 @@ __global__ void __launch_bounds__(256) k_pack_lists(int32_t n, const int64_t* __
 
 // I_k = union of P(A~(:, j)) over the given J_k (count pass: mode 0, fill: mode 1).
 template <int CAP>
-__global__ void __launch_bounds__(64) k_rows_of(int32_t n, const int32_t* __restrict__ cp,
+__global__ void __launch_bounds__(64) k_rows_of(int32_t nwork, const int32_t* __restrict__ list,
+                                                const int32_t* __restrict__ cp,
                                                 const int32_t* __restrict__ ri,
                                                 const int64_t* __restrict__ jptr,
                                                 const int32_t* __restrict__ jidx, int mode,
@@ -283,14 +284,17 @@ __global__ void __launch_bounds__(64) k_rows_of(int32_t n, const int32_t* __rest
   __shared__ int32_t s_off[CAPJ];
   int32_t* const ht = s_start;
   const int l = lane_id();
-  for (int64_t k = blockIdx.x; k < n; k += gridDim.x) {
+  // a column that overflows CAP gets cntI = -1 in the counting pass (mode 0)
+  // and is skipped in the writing pass (the larger variant redoes it)
+  for (int64_t b = blockIdx.x; b < nwork; b += gridDim.x) {
+    const int64_t k = list ? (int64_t)list[b] : b;
     const int64_t j0 = jptr[k];
     const int nJ = (int)(jptr[k + 1] - j0);
-    if (nJ > CAPJ) { if (l == 0) atomicAdd(nover, 1); continue; }
+    if (nJ > CAPJ) { if (l == 0 && mode == 0) { cntI[k] = -1; atomicAdd(nover, 1); } continue; }
     for (int t = l; t < nJ; t += WAVE) sJ[t] = jidx[j0 + t];
     __syncthreads();
     const int m = gather_cols(cp, ri, sJ, nJ, cand, CAP, s_start, s_off);
-    if (m < 0) { if (l == 0) atomicAdd(nover, 1); __syncthreads(); continue; }
+    if (m < 0) { if (l == 0 && mode == 0) { cntI[k] = -1; atomicAdd(nover, 1); } __syncthreads(); continue; }
     const int nI = sort_unique_fast(cand, m, CAP, ht);
     if (mode == 0) {
       if (l == 0) cntI[k] = nI;
@@ -300,31 +304,6 @@ __global__ void __launch_bounds__(64) k_rows_of(int32_t n, const int32_t* __rest
     }
     __syncthreads();
   }
-}
-
-void rows_of_patterns(const sai_split_s* sp, hipStream_t st, const Allocator& al,
-                      const DBuf<int64_t>& jptr, const DBuf<int32_t>& jidx, DBuf<int64_t>& iptr,
-                      DBuf<int32_t>& iidx, DBuf<int32_t>& cntI) {
-  const int32_t n = sp->n;
-  constexpr int CAP = 8192;
-  cntI.alloc(&al, (size_t)n + 1);
-  DBuf<int> nover(&al, 2);
-  HIPC(hipMemsetAsync(nover.p, 0, 2 * sizeof(int), st));
-  const unsigned grid = (unsigned)std::min<int64_t>(n, 1 << 20);
-  hipLaunchKernelGGL((k_rows_of<CAP>), dim3(grid), dim3(64), 0, st, n, sp->t_col_ptr.p,
-                     sp->t_row_idx.p, jptr.p, jidx.p, 0, cntI.p, (const int64_t*)nullptr,
-                     (int32_t*)nullptr, nover.p);
-  LAUNCH_CHECK();
-  if (read_scalar(nover.p, st) > 0)
-    SAI_THROW(SAI_ETOOBIG, "a row set I_k exceeds %d candidate indices", CAP);
-  iptr.alloc(&al, (size_t)n + 1);
-  exclusive_scan_i32_to_i64(cntI.p, iptr.p, n, al, st);
-  const int64_t tot = read_scalar(iptr.p + n, st);
-  iidx.alloc(&al, (size_t)tot + 1);
-  hipLaunchKernelGGL((k_rows_of<CAP>), dim3(grid), dim3(64), 0, st, n, sp->t_col_ptr.p,
-                     sp->t_row_idx.p, jptr.p, jidx.p, 1, cntI.p, (const int64_t*)iptr.p, iidx.p,
-                     nover.p);
-  LAUNCH_CHECK();
 }
 
 // The columns with cnt < 0, in unspecified order (at most cap of them kept),
@@ -337,6 +316,56 @@ __global__ void __launch_bounds__(256) k_list_neg(int32_t n, const int32_t* __re
   const int slot = block_slot<1>(count, neg ? 0 : -1);
   if (neg && slot < cap) list[slot] = (int32_t)k;
 }
+
+void rows_of_patterns(const sai_split_s* sp, hipStream_t st, const Allocator& al,
+                      const DBuf<int64_t>& jptr, const DBuf<int32_t>& jidx, DBuf<int64_t>& iptr,
+                      DBuf<int32_t>& iidx, DBuf<int32_t>& cntI) {
+  const int32_t n = sp->n;
+  // every column through the 5 KB kernel (eight waves per SIMD); the few whose
+  // candidate lists overflow it are redone by the 32 KB one over a list
+  constexpr int CAP_S = 512, CAP_L = 8192;
+  cntI.alloc(&al, (size_t)n + 1);
+  DBuf<int> nover(&al, 2);
+  HIPC(hipMemsetAsync(nover.p, 0, 2 * sizeof(int), st));
+  const unsigned grid = (unsigned)std::min<int64_t>(n, 1 << 20);
+  const int32_t* cp = sp->t_col_ptr.p;
+  const int32_t* ri = sp->t_row_idx.p;
+  hipLaunchKernelGGL((k_rows_of<CAP_S>), dim3(grid), dim3(64), 0, st, n, (const int32_t*)nullptr, cp, ri,
+                     jptr.p, jidx.p, 0, cntI.p, (const int64_t*)nullptr, (int32_t*)nullptr, nover.p);
+  LAUNCH_CHECK();
+  const int nbig = read_scalar(nover.p, st);
+  DBuf<int32_t> list;
+  if (nbig > 0) {
+    list.alloc(&al, (size_t)nbig);
+    HIPC(hipMemsetAsync(nover.p, 0, 2 * sizeof(int), st));
+    hipLaunchKernelGGL(k_list_neg, dim3(grid_for(n, 256)), dim3(256), 0, st, n, cntI.p, list.p, nbig,
+                       nover.p + 1);
+    LAUNCH_CHECK();
+    if (read_scalar(nover.p + 1, st) != nbig)
+      SAI_THROW(SAI_EHIP, "row-set overflow list: %d columns listed, %d counted",
+                read_scalar(nover.p + 1, st), nbig);
+    hipLaunchKernelGGL((k_rows_of<CAP_L>), dim3(std::min(nbig, 1 << 20)), dim3(64), 0, st, nbig,
+                       (const int32_t*)list.p, cp, ri, jptr.p, jidx.p, 0, cntI.p, (const int64_t*)nullptr,
+                       (int32_t*)nullptr, nover.p);
+    LAUNCH_CHECK();
+    if (read_scalar(nover.p, st) > 0)
+      SAI_THROW(SAI_ETOOBIG, "a row set I_k exceeds %d candidate indices", CAP_L);
+  }
+  iptr.alloc(&al, (size_t)n + 1);
+  exclusive_scan_i32_to_i64(cntI.p, iptr.p, n, al, st);
+  const int64_t tot = read_scalar(iptr.p + n, st);
+  iidx.alloc(&al, (size_t)tot + 1);
+  hipLaunchKernelGGL((k_rows_of<CAP_S>), dim3(grid), dim3(64), 0, st, n, (const int32_t*)nullptr, cp, ri,
+                     jptr.p, jidx.p, 1, cntI.p, (const int64_t*)iptr.p, iidx.p, nover.p);
+  LAUNCH_CHECK();
+  if (nbig > 0) {
+    hipLaunchKernelGGL((k_rows_of<CAP_L>), dim3(std::min(nbig, 1 << 20)), dim3(64), 0, st, nbig,
+                       (const int32_t*)list.p, cp, ri, jptr.p, jidx.p, 1, cntI.p, (const int64_t*)iptr.p,
+                       iidx.p, nover.p);
+    LAUNCH_CHECK();
+  }
+}
+
 
 // Sizes, offsets and lists of J_k and I_k.  jptr/iptr get n+1 entries.
 // One union pass: the lists are written at offsets from upper bounds of their
