@@ -19,6 +19,8 @@
 // global workspace.
 #include "sai_internal.hpp"
 
+#include <algorithm>
+
 namespace sai {
 
 template <int CTRL>
@@ -365,7 +367,7 @@ __global__ void __launch_bounds__(BIG_NT) k_ls_qr_big(const int32_t* __restrict_
                                                       const double* __restrict__ cv,
                                                       T* __restrict__ work, int64_t work_stride,
                                                       T* __restrict__ mout, double* __restrict__ res_out,
-                                                      int* __restrict__ nsing) {
+                                                      int* __restrict__ nsing, int* __restrict__ next) {
   __shared__ int32_t sI[BIG_MAXI];
   __shared__ int32_t sStart[BIG_MAXJ];
   __shared__ int32_t sOff[BIG_MAXJ + 1];
@@ -373,9 +375,17 @@ __global__ void __launch_bounds__(BIG_NT) k_ls_qr_big(const int32_t* __restrict_
   __shared__ T sm[BIG_MAXJ];
   __shared__ T red[BIG_NT / 64];
   __shared__ T s_tail[2];
+  __shared__ int s_q;
   const int tid = threadIdx.x, lane = tid % 64, w = tid / 64;
   T* W = work + (int64_t)blockIdx.x * work_stride;
-  for (int64_t q = blockIdx.x; q < ncols; q += gridDim.x) {
+  // problems are taken one at a time from the counter `next` (the list holds
+  // the costliest first), so that no workgroup is left with a queue of them
+  for (;;) {
+    __syncthreads();  // every thread has read the previous s_q
+    if (tid == 0) s_q = atomicAdd(next, 1);
+    __syncthreads();
+    const int q = s_q;
+    if (q >= ncols) break;
     const int k = cols[q];
     const int64_t jo = jptr[k], io = iptr[k];
     const int nJ = (int)(jptr[k + 1] - jo), nI = (int)(iptr[k + 1] - io);
@@ -543,6 +553,36 @@ __global__ void __launch_bounds__(BK_NT) k_bucket_scatter(int32_t n, const int32
   }
 }
 
+// Work of each listed problem, |I| |J|^2 (the Householder flops up to a constant).
+__global__ void __launch_bounds__(256) k_qr_cost(int cnt, const int32_t* __restrict__ list,
+                                                 const int64_t* __restrict__ jptr,
+                                                 const int64_t* __restrict__ iptr, int64_t* __restrict__ cost) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= cnt) return;
+  const int k = list[t];
+  const int64_t nJ = jptr[k + 1] - jptr[k], nI = iptr[k + 1] - iptr[k];
+  cost[t] = nI * nJ * nJ;
+}
+
+// Reorder list[0..cnt) by decreasing cost (stable), for the global-memory kernel.
+void order_by_cost(int32_t* list, int cnt, const int64_t* jptr, const int64_t* iptr, const Allocator& al,
+                   hipStream_t st) {
+  DBuf<int64_t> cost(&al, (size_t)cnt);
+  hipLaunchKernelGGL(k_qr_cost, dim3(grid_for(cnt, 256)), dim3(256), 0, st, cnt, list, jptr, iptr, cost.p);
+  LAUNCH_CHECK();
+  std::vector<int32_t> hl((size_t)cnt), sl((size_t)cnt);
+  std::vector<int64_t> hc((size_t)cnt);
+  std::vector<int> ord((size_t)cnt);
+  HIPC(hipMemcpyAsync(hl.data(), list, sizeof(int32_t) * (size_t)cnt, hipMemcpyDeviceToHost, st));
+  HIPC(hipMemcpyAsync(hc.data(), cost.p, sizeof(int64_t) * (size_t)cnt, hipMemcpyDeviceToHost, st));
+  HIPC(hipStreamSynchronize(st));
+  for (int i = 0; i < cnt; ++i) ord[(size_t)i] = i;
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return hc[(size_t)a] > hc[(size_t)b]; });
+  for (int i = 0; i < cnt; ++i) sl[(size_t)i] = hl[(size_t)ord[(size_t)i]];
+  HIPC(hipMemcpyAsync(list, sl.data(), sizeof(int32_t) * (size_t)cnt, hipMemcpyHostToDevice, st));
+  HIPC(hipStreamSynchronize(st));
+}
+
 template <class T, int G, int R, int JMAX, int MINW = 1>
 void launch_qr(const int32_t* list, int cnt, const int64_t* jptr, const int32_t* jidx,
                const int64_t* iptr, const int32_t* iidx, const sai_split_s* sp, T* mout,
@@ -597,10 +637,12 @@ void dispatch_variant(int v, const int32_t* list, int cnt, const int64_t* jptr,
   const unsigned grid = (unsigned)std::min(cnt, 1024);
   const int64_t stride = (int64_t)maxI * (maxJ + 1);
   DBuf<T> work(&al, (size_t)grid * stride);
+  DBuf<int> next(&al, 1);
+  HIPC(hipMemsetAsync(next.p, 0, sizeof(int), st));
   SAI_PROF(sizeof(T) == 4 ? "ls_qr_f32_big" : "ls_qr_f64_big", st);
   hipLaunchKernelGGL((k_ls_qr_big<T>), dim3(grid), dim3(BIG_NT), 0, st, list, cnt, jptr, jidx, iptr,
                      iidx, sp->t_col_ptr.p, sp->t_row_idx.p, sp->t_cval.p, work.p, stride, mout, res,
-                     nsing);
+                     nsing, next.p);
   LAUNCH_CHECK();
   HIPC(hipStreamSynchronize(st));
 }
@@ -646,6 +688,7 @@ int solve_columns(const sai_split_s* sp, const int64_t* jptr, const int32_t* jid
   LAUNCH_CHECK();
   for (int v = 0; v < NV; ++v) {
     if (bucket_cols) bucket_cols[v] = hc[v];
+    if (v == NV - 1 && hc[v] > 1) order_by_cost(lists.p + hoff[v], hc[v], jptr, iptr, al, st);
     dispatch_variant<T>(v, lists.p + hoff[v], hc[v], jptr, jidx, iptr, iidx, sp, mout, res, nsing.p,
                         maxI, maxJ, al, st);
   }
