@@ -688,7 +688,9 @@ int solve_columns(const sai_split_s* sp, const int64_t* jptr, const int32_t* jid
   LAUNCH_CHECK();
   for (int v = 0; v < NV; ++v) {
     if (bucket_cols) bucket_cols[v] = hc[v];
-    if (v == NV - 1 && hc[v] > 1) order_by_cost(lists.p + hoff[v], hc[v], jptr, iptr, al, st);
+    // the order matters only when there are more problems than resident workgroups
+    if (v == NV - 1 && hc[v] > std::min(1024, resident_blocks((const void*)k_ls_qr_big<T>, BIG_NT)))
+      order_by_cost(lists.p + hoff[v], hc[v], jptr, iptr, al, st);
     dispatch_variant<T>(v, lists.p + hoff[v], hc[v], jptr, jidx, iptr, iidx, sp, mout, res, nsing.p,
                         maxI, maxJ, al, st);
   }
