@@ -1,7 +1,11 @@
 // SPAI adaptive pattern search on A~ (Section 2.1), in float64.
 //
-// One workgroup per column k.  Starting from J = P(A~(:, k)) (or {k}), each
-// step:
+// From J = P(A~(:, k)), step 0 (the first solve and its residual test) runs
+// for every column through the static pattern builder and the
+// register-resident column solver; only the columns whose residual exceeds
+// delta enter the search kernel (from {k}, every column does).  There one
+// workgroup takes one column at a time from a counter, the largest step-0
+// |I_k| first, and starting from J = P(A~(:, k)) (or {k}) runs each step:
 //   I   = nonzero rows of A~(:, J)                         (gather, sort, unique)
 //   m   = argmin ||A~(I, J) m - e_k(I)||                   (Householder QR)
 //   r   = A~(:, J) m - e_k on I;  stop if ||r|| <= delta
