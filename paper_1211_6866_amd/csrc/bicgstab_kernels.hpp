@@ -565,7 +565,11 @@ enum { F_INIT, F_AV, F_AT, F_HALF, F_XR, F_FULL, F_RESTART_END };
 constexpr int FNT = 1024;  // finisher threads
 
 template <int ND, int OP>
-__global__ void __launch_bounds__(FNT) k_fin(int k, State S, int nb, int it = 0, int maxit = 0) {
+// force_it (the F_XR finisher): at iteration it == force_it every active column
+// is handled as a breakdown (restart), so that the restart path can be tested
+// on well-conditioned systems; 0 (the default) never matches.
+__global__ void __launch_bounds__(FNT) k_fin(int k, State S, int nb, int it = 0, int maxit = 0,
+                                             int force_it = 0) {
   // partial sums are read as column pairs; U independent sums per pair and d
   // keep U loads of every d in flight (the partials come from every XCD, so
   // each round of loads is a trip past the L2)
@@ -734,7 +738,7 @@ __global__ void __launch_bounds__(FNT) k_fin(int k, State S, int nb, int it = 0,
       if (sqrt(tot[1][t]) < st_thr) {
         S.full[t] = 1;
         S.any[1] = 1;  // breakdown checks follow the true-residual check
-      } else if (fabs(st_omega) < TINY || fabs(rho_new) < TINY) {
+      } else if (fabs(st_omega) < TINY || fabs(rho_new) < TINY || it == force_it) {
         S.rst[t] = 1;
         S.any[2] = 1;
       }

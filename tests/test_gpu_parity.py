@@ -535,3 +535,26 @@ def test_adaptive_builds_bit_identical(kind):
         outs.append([_np(arr[k]) for k in ("col_ptr", "row_idx", "cval")] + [_np(x)])
     for u, v in zip(*outs):
         assert np.array_equal(u, v)
+
+
+@pytest.mark.parametrize("at", [1, 5])
+def test_bicgstab_forced_restart(at):
+    """The breakdown restart (r_hat = r, p = v = 0, one per column), forced from
+    the host at iteration `at` for every active column of a well-conditioned
+    system: the solve still reaches rr < 1e-8 and agrees with the unforced one."""
+    w, (rp, ci, va) = _load("c2_12")
+    b = torch.from_numpy(w.b).cuda()
+    g = P.Split(rp, ci, va)
+    pc = P.Precond(g, pattern=P.PAT_A2, drop=P.DROP_ABS, tau=1e-3, precision=P.FP32)
+    x0, st0 = P.solve(g, pc, b, method=P.BICGSTAB, eps=1e-8)
+    try:
+        P.tune_set("BRK_TEST", at)
+        x1, st1 = P.solve(g, pc, b, method=P.BICGSTAB, eps=1e-8)
+    finally:
+        P.tune_set("BRK_TEST", 0)
+    x0, x1 = _np(x0), _np(x1)
+    rr = np.linalg.norm(w.b - w.A @ x1) / np.linalg.norm(w.b)
+    assert st1["status"] == P.OK and rr < 1.5e-8, (st1, rr)
+    assert st1["iters"] != st0["iters"], (st0["iters"], st1["iters"])
+    assert np.linalg.norm(x1 - x0) <= 1e-6 * np.linalg.norm(x0)
+    print(f"restart at {at}: iterations {st0['iters']} -> {st1['iters']}, rr {rr:.2e}")
