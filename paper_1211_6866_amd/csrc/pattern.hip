@@ -250,17 +250,20 @@ __global__ void k_pat_ub(int32_t n, int kind, const int32_t* __restrict__ cp,
 }
 
 // Copy the lists written at upper-bound offsets (src_ptr[k], length cnt[k]) to
-// their packed places dst_ptr[k]; one wavefront per column, coalesced.
+// their packed places dst_ptr[k], coalesced, 16 lanes per list (four lists per
+// wavefront): the lists here hold tens of entries (100^3 matrix: 0.52 ms with
+// 64 lanes per list, 0.39 with 32, 0.34 with 16).
 __global__ void __launch_bounds__(256) k_pack_lists(int32_t n, const int64_t* __restrict__ src_ptr,
                                                     const int32_t* __restrict__ src,
                                                     const int64_t* __restrict__ dst_ptr,
                                                     int32_t* __restrict__ dst) {
-  const int l = lane_id();
-  for (int64_t k = ((int64_t)blockIdx.x * 256 + threadIdx.x) / WAVE; k < n;
-       k += (int64_t)gridDim.x * (256 / WAVE)) {
+  constexpr int LPC = 16;
+  const int l = threadIdx.x % LPC;
+  for (int64_t k = ((int64_t)blockIdx.x * 256 + threadIdx.x) / LPC; k < n;
+       k += (int64_t)gridDim.x * (256 / LPC)) {
     const int64_t a = src_ptr[k], b = dst_ptr[k];
     const int c = (int)(dst_ptr[k + 1] - b);
-    for (int t = l; t < c; t += WAVE) dst[b + t] = src[a + t];
+    for (int t = l; t < c; t += LPC) dst[b + t] = src[a + t];
   }
 }
 
@@ -440,7 +443,7 @@ void build_patterns(const sai_split_s* sp, int kind, hipStream_t st, const Alloc
   HIPC(hipStreamSynchronize(st));
   jidx.alloc(&al, (size_t)tot[0] + 1);
   iidx.alloc(&al, (size_t)tot[1] + 1);
-  const unsigned pgrid = grid_for((int64_t)n * WAVE, 256, 8192);
+  const unsigned pgrid = grid_for((int64_t)n * 16, 256, 8192);
   hipLaunchKernelGGL(k_pack_lists, dim3(pgrid), dim3(256), 0, st, n, ujo.p, tJ.p, jptr.p, jidx.p);
   hipLaunchKernelGGL(k_pack_lists, dim3(pgrid), dim3(256), 0, st, n, uio.p, tI.p, iptr.p, iidx.p);
   LAUNCH_CHECK();
