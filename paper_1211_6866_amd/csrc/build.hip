@@ -107,8 +107,8 @@ __global__ void __launch_bounds__(NT) k_drop(int32_t n, const int64_t* __restric
                                              int mode, double tau, double delta, double norm1,
                                              int32_t* __restrict__ cnt, const int32_t* __restrict__ colp,
                                              int32_t* __restrict__ rowi, T* __restrict__ cval) {
-  constexpr int G = 32;
-  const int lane = threadIdx.x & 63, gi = lane & (G - 1), half = lane & G;
+  constexpr int G = 16;  // lanes per column (four columns per wavefront)
+  const int lane = threadIdx.x & 63, gi = lane & (G - 1), gbase = lane & (64 - G);
   const int64_t k = ((int64_t)blockIdx.x * NT + threadIdx.x) / G;
   const bool valid = k < n;
   const int64_t a = valid ? jptr[k] : 0, b = valid ? jptr[k + 1] : 0;
@@ -133,7 +133,7 @@ __global__ void __launch_bounds__(NT) k_drop(int32_t n, const int64_t* __restric
   for (int64_t off = 0; __any(off < nj); off += G) {
     const int64_t e = a + off + gi;
     const bool kf = e < b && (fabs((double)m[e]) > thr || e == amax);
-    const uint32_t gm = (uint32_t)(__ballot(kf) >> half);
+    const uint32_t gm = (uint32_t)(__ballot(kf) >> gbase) & ((1u << G) - 1u);
     if (!COUNT && kf) {
       const int32_t q = o + __popc(gm & ((1u << gi) - 1u));
       rowi[q] = jidx[e];
@@ -209,7 +209,7 @@ void build_typed(const sai_split_s* sp, const sai_build_opts& o, hipStream_t st,
     memcpy(&norm1, &bits, sizeof(double));
   }
   DBuf<int32_t> ccnt(&al, (size_t)n + 1);
-  const unsigned dgrid = grid_for((int64_t)n * 32, NT);
+  const unsigned dgrid = grid_for((int64_t)n * 16, NT);
   hipLaunchKernelGGL((k_drop<T, true>), dim3(dgrid), dim3(NT), 0, st, n, jptr.p, jidx.p, mfull.p, drop,
                      o.tau, o.delta, norm1, ccnt.p, nullptr, nullptr, nullptr);
   LAUNCH_CHECK();
