@@ -558,3 +558,30 @@ def test_bicgstab_forced_restart(at):
     assert st1["iters"] != st0["iters"], (st0["iters"], st1["iters"])
     assert np.linalg.norm(x1 - x0) <= 1e-6 * np.linalg.norm(x0)
     print(f"restart at {at}: iterations {st0['iters']} -> {st1['iters']}, rr {rr:.2e}")
+
+
+@pytest.mark.parametrize("init", [P.INIT_PATTERN_A, P.INIT_DIAG])
+def test_spai_zero_steps(init):
+    """spai_steps = 0: no augmentation, J_k = P(A~(:, k)) (then M is the static
+    P(A~) build, bit for bit) or {k}; against the oracle."""
+    from oracle import spai as ospai
+    w, (rp, ci, va) = _load("c3_3000")
+    S = osplit.split(w.A)
+    n = w.A.shape[0]
+    g = P.Split(rp, ci, va)
+    pc = P.Precond(g, pattern=P.PAT_SPAI, drop=P.DROP_NONE, delta=0.4, spai_steps=0,
+                   spai_per_step=5, spai_init=init, precision=P.FP64, keep_lists=True)
+    arr = pc.arrays()
+    jp, ji = _np(arr["j_ptr"]), _np(arr["j_idx"])
+    mf = _np(arr["m_full"])
+    out = ospai.spai(S.At, steps=0, per_step=5, delta=0.4,
+                     init="A" if init == P.INIT_PATTERN_A else "diag")
+    for k in range(n):
+        J, I, m, res, taken = out[k]
+        assert taken == 0
+        assert np.array_equal(ji[jp[k]:jp[k + 1]], J), k
+        assert np.linalg.norm(mf[jp[k]:jp[k + 1]] - m) <= 1e-12 * np.linalg.norm(m), k
+    if init == P.INIT_PATTERN_A:
+        ref = P.Precond(g, pattern=P.PAT_A, drop=P.DROP_NONE, precision=P.FP64).arrays()
+        for key in ("col_ptr", "row_idx", "cval"):
+            assert np.array_equal(_np(arr[key]), _np(ref[key])), key
