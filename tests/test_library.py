@@ -96,3 +96,19 @@ def test_binding_structs_match_header(tmp_path):
         assert got[(cname, "size")] == C.sizeof(py), cname
         for fname, *_ in py._fields_:
             assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
+
+
+def test_binding_fails_loudly_without_library():
+    """With no libsai.so the binding raises on first use: there is no CPU fallback."""
+    import subprocess
+    import sys
+    code = ("import paper_1211_6866_amd as P\n"
+            "P.LIB_PATH = '/nonexistent/libsai.so'\n"
+            "try:\n"
+            "    P.lib()\n"
+            "except RuntimeError as e:\n"
+            "    print('raised:', e)\n"
+            "else:\n"
+            "    raise SystemExit('the binding loaded without its library')\n")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0 and "raised:" in r.stdout, (r.stdout, r.stderr)
