@@ -454,51 +454,82 @@ __global__ void __launch_bounds__(NT) k_tr_scatter(int32_t n, const int32_t* __r
   }
 }
 
-// Sort each column segment by row (insertion sort; segments are short for the
-// regular sparse matrices this is used on).  Makes the transpose deterministic.
-template <class V>
-__global__ void k_tr_sort(int32_t m, const int32_t* __restrict__ cp, int32_t* __restrict__ ri,
-                          V* __restrict__ cv) {
-  const int64_t j = (int64_t)blockIdx.x * NT + threadIdx.x;
-  if (j >= m) return;
-  const int32_t a = cp[j], b = cp[j + 1];
-  if (b - a <= 32) {
-    // bitonic network in registers (all indices static)
-    const int len = b - a;
-    int32_t key[32];
-    V val[32];
+// Sort the segment lo .. lo+len-1 (len <= 32) of (K, W) by key with a bitonic
+// network in registers (all indices static).
+template <class V, class KP, class WP>
+__device__ __forceinline__ void sort_seg32(KP K, WP W, int64_t lo, int len) {
+  int32_t key[32];
+  V val[32];
 #pragma unroll
-    for (int t = 0; t < 32; ++t) {
-      key[t] = t < len ? ri[a + t] : 0x7fffffff;
-      val[t] = t < len ? cv[a + t] : V(0);
-    }
+  for (int t = 0; t < 32; ++t) {
+    key[t] = t < len ? K[lo + t] : 0x7fffffff;
+    val[t] = t < len ? W[lo + t] : V(0);
+  }
 #pragma unroll
-    for (int kk = 2; kk <= 32; kk <<= 1) {
+  for (int kk = 2; kk <= 32; kk <<= 1) {
 #pragma unroll
-      for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+    for (int jj = kk >> 1; jj > 0; jj >>= 1) {
 #pragma unroll
-        for (int t = 0; t < 32; ++t) {
-          const int l = t ^ jj;
-          if (l > t) {
-            const bool up = (t & kk) == 0;
-            const bool sw = (key[t] > key[l]) == up;
-            const int32_t k0 = key[t], k1 = key[l];
-            const V v0 = val[t], v1 = val[l];
-            key[t] = sw ? k1 : k0;
-            key[l] = sw ? k0 : k1;
-            val[t] = sw ? v1 : v0;
-            val[l] = sw ? v0 : v1;
-          }
+      for (int t = 0; t < 32; ++t) {
+        const int l = t ^ jj;
+        if (l > t) {
+          const bool up = (t & kk) == 0;
+          const bool sw = (key[t] > key[l]) == up;
+          const int32_t k0 = key[t], k1 = key[l];
+          const V v0 = val[t], v1 = val[l];
+          key[t] = sw ? k1 : k0;
+          key[l] = sw ? k0 : k1;
+          val[t] = sw ? v1 : v0;
+          val[l] = sw ? v0 : v1;
         }
       }
     }
+  }
 #pragma unroll
-    for (int t = 0; t < 32; ++t) {
-      if (t < len) {
-        ri[a + t] = key[t];
-        cv[a + t] = val[t];
-      }
+  for (int t = 0; t < 32; ++t) {
+    if (t < len) {
+      K[lo + t] = key[t];
+      W[lo + t] = val[t];
     }
+  }
+}
+
+// Sort each column segment by row (segments are short for the regular sparse
+// matrices this is used on).  Makes the transpose deterministic.  A block's
+// segments are contiguous: when they hold at most TS_CAP entries and none is
+// longer than 32, they are staged in LDS with coalesced loads and stores and
+// each thread sorts its segment there; otherwise each thread sorts in global
+// memory (the register network up to 32 entries, insertion sort beyond).
+constexpr int TS_NT = 64, TS_CAP = 2048;
+template <class V>
+__global__ void __launch_bounds__(TS_NT) k_tr_sort(int32_t m, const int32_t* __restrict__ cp,
+                                                   int32_t* __restrict__ ri, V* __restrict__ cv) {
+  __shared__ int32_t sk[TS_CAP];
+  __shared__ V sv[TS_CAP];
+  const int64_t jb = (int64_t)blockIdx.x * TS_NT;
+  const int64_t jl = min<int64_t>(m, jb + TS_NT);
+  const int64_t j = jb + threadIdx.x;
+  const int32_t eb = cp[jb], el = cp[jl];
+  const int32_t a = j < m ? cp[j] : el, b = j < m ? cp[j + 1] : el;
+  // one wavefront per block: the ballot is the block's
+  const bool staged = el - eb <= TS_CAP && __ballot(b - a > 32) == 0;
+  if (staged) {
+    for (int q = threadIdx.x; q < el - eb; q += TS_NT) {
+      sk[q] = ri[eb + q];
+      sv[q] = cv[eb + q];
+    }
+    __syncthreads();
+    if (j < m) sort_seg32<V>(sk, sv, (int64_t)(a - eb), b - a);
+    __syncthreads();
+    for (int q = threadIdx.x; q < el - eb; q += TS_NT) {
+      ri[eb + q] = sk[q];
+      cv[eb + q] = sv[q];
+    }
+    return;
+  }
+  if (j >= m) return;
+  if (b - a <= 32) {
+    sort_seg32<V>(ri, cv, (int64_t)a, b - a);
     return;
   }
   for (int32_t x = a + 1; x < b; ++x) {
@@ -527,7 +558,7 @@ void csr_transpose(int32_t nrows, int32_t ncols, const int32_t* rp, const int32_
   hipLaunchKernelGGL((k_tr_scatter<V>), dim3(grid_for(nrows, NT)), dim3(NT), 0, st, nrows, rp, ci, v, cp,
                      cnt.p, ri, cv);
   LAUNCH_CHECK();
-  hipLaunchKernelGGL((k_tr_sort<V>), dim3(grid_for(ncols, NT)), dim3(NT), 0, st, ncols, cp, ri, cv);
+  hipLaunchKernelGGL((k_tr_sort<V>), dim3(grid_for(ncols, TS_NT)), dim3(TS_NT), 0, st, ncols, cp, ri, cv);
   LAUNCH_CHECK();
 }
 
