@@ -269,6 +269,7 @@ __global__ void __launch_bounds__(NT) k_dense_select(const int32_t* __restrict__
 // smallest keys of the column (keys are distinct: one per row).
 constexpr int SEL_K = 16;
 
+template <int B = NT>
 __device__ __forceinline__ Key block_min_key(Key k, double* sa, int32_t* si) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
@@ -283,7 +284,7 @@ __device__ __forceinline__ Key block_min_key(Key k, double* sa, int32_t* si) {
   __syncthreads();
   Key b{sa[0], si[0]};
 #pragma unroll
-  for (int q = 1; q < NT / 64; ++q) {
+  for (int q = 1; q < B / 64; ++q) {
     Key y{sa[q], si[q]};
     if (key_less(y, b)) b = y;
   }
@@ -291,7 +292,9 @@ __device__ __forceinline__ Key block_min_key(Key k, double* sa, int32_t* si) {
   return b;
 }
 
-__global__ void __launch_bounds__(NT) k_dense_select_k(const int32_t* __restrict__ dense_cols,
+// one 1024-thread workgroup per irregular column: each scans ~1/1024 of its entries
+constexpr int SEL_NT = 1024;
+__global__ void __launch_bounds__(SEL_NT) k_dense_select_k(const int32_t* __restrict__ dense_cols,
                                                        const int64_t* __restrict__ doff,
                                                        const int32_t* __restrict__ dcount,
                                                        const int32_t* __restrict__ lrow,
@@ -299,8 +302,8 @@ __global__ void __launch_bounds__(NT) k_dense_select_k(const int32_t* __restrict
                                                        const double* __restrict__ val, int keep,
                                                        int rule, uint8_t* __restrict__ drop,
                                                        int* __restrict__ err) {
-  __shared__ double sa[NT / 64];
-  __shared__ int32_t si[NT / 64];
+  __shared__ double sa[SEL_NT / 64];
+  __shared__ int32_t si[SEL_NT / 64];
   __shared__ int has_diag;
   const int d = blockIdx.x;
   const int32_t j = dense_cols[d];
@@ -317,7 +320,7 @@ __global__ void __launch_bounds__(NT) k_dense_select_k(const int32_t* __restrict
     ki[u] = 0x7fffffff;
   }
   bool diag = false;
-  for (int32_t t = threadIdx.x; t < cnt; t += NT) {
+  for (int32_t t = threadIdx.x; t < cnt; t += SEL_NT) {
     const int32_t i = lrow[off + t];
     if (i == j) {
       diag = true;
@@ -358,13 +361,13 @@ __global__ void __launch_bounds__(NT) k_dense_select_k(const int32_t* __restrict
 #pragma unroll
     for (int u = 0; u < SEL_K; ++u)
       if (u == head) mine = Key{ka[u], ki[u]};
-    const Key b = block_min_key(mine, sa, si);
+    const Key b = block_min_key<SEL_NT>(mine, sa, si);
     if (b.i == 0x7fffffff) break;  // fewer off-diagonals than keep-1
     if (b.i == mine.i && head < SEL_K) ++head;
     last = b;
     have = true;
   }
-  for (int32_t t = threadIdx.x; t < cnt; t += NT) {
+  for (int32_t t = threadIdx.x; t < cnt; t += SEL_NT) {
     const int32_t i = lrow[off + t];
     if (i == j) continue;
     bool kept = false;
@@ -647,7 +650,7 @@ void split_impl(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* c
       LAUNCH_CHECK();
     }
     if (keep - 1 <= SEL_K)
-      hipLaunchKernelGGL(k_dense_select_k, dim3(s), dim3(NT), 0, st, h->dense_cols.p, doff.p, dcount.p,
+      hipLaunchKernelGGL(k_dense_select_k, dim3(s), dim3(SEL_NT), 0, st, h->dense_cols.p, doff.p, dcount.p,
                          lrow.p, lpos.p, val, keep, o.rule, drop.p, err.p);
     else
       hipLaunchKernelGGL(k_dense_select, dim3(s), dim3(NT), 0, st, h->dense_cols.p, doff.p, dcount.p,
