@@ -43,8 +43,18 @@ def thresholds(b_norm: float, s: int, eps: float, u_norms=None, c: float = 1.0):
     return np.asarray(t)
 
 
-def bicgstab(A, M, rhs, thr, maxit=500):
-    """Return (x, iterations, status) with status in {"converged", "maxit", "breakdown"}."""
+def bicgstab(A, M, rhs, thr, maxit=500, force_restart_at=(), trace=None):
+    """Return (x, iterations, status) with status in {"converged", "maxit", "breakdown"}.
+
+    Two test hooks leave the arithmetic unchanged: ``force_restart_at`` lists
+    iterations at whose end the solver restarts exactly as after a breakdown of
+    omega (so that the restart can be exercised on well-conditioned systems),
+    and ``trace``, a list, receives ``(event, iteration, state)`` tuples for
+    every restart ("restart") and residual replacement ("replace"), where state
+    holds copies of x, r, r_hat, p and v right after the event (and, for a
+    replacement, the recursive residual it replaced as r_rec).
+    """
+    force = set(int(i) for i in force_restart_at)
     rhs = np.asarray(rhs, dtype=np.float64)
     n = rhs.size
     x = np.zeros(n)
@@ -58,6 +68,12 @@ def bicgstab(A, M, rhs, thr, maxit=500):
     restarts = 0
     it = 0
 
+    def note(event, **extra):
+        if trace is not None:
+            state = dict(x=x.copy(), r=r.copy(), rhat=rhat.copy(), p=p.copy(), v=v.copy())
+            state.update(extra)
+            trace.append((event, it, state))
+
     def restart():
         nonlocal rhat, rho_old, alpha, omega, v, p, restarts
         restarts += 1
@@ -65,6 +81,7 @@ def bicgstab(A, M, rhs, thr, maxit=500):
         rho_old = alpha = omega = 1.0
         v = np.zeros(n)
         p = np.zeros(n)
+        note("restart")
         return restarts <= 1
 
     while it < maxit:
@@ -104,8 +121,9 @@ def bicgstab(A, M, rhs, thr, maxit=500):
             rt = rhs - A @ x
             if np.linalg.norm(rt) < thr:
                 return x, it, "converged"
-            r = rt
-        if abs(omega) < TINY:
+            r_rec, r = r, rt
+            note("replace", r_rec=r_rec)
+        if abs(omega) < TINY or it in force:
             if not restart():
                 return x, it, "breakdown"
     return x, it, "maxit"
@@ -171,8 +189,11 @@ def gmres(A, M, rhs, thr, restart=30, maxit=500):
     return x, it, "maxit"
 
 
-def solve_block(A, M, R, thr, method="bicgstab", restart=30, maxit=500):
-    """Solve A~ X = R column by column; returns (X, iterations list, statuses list)."""
+def solve_block(A, M, R, thr, method="bicgstab", restart=30, maxit=500, force_restart_at=()):
+    """Solve A~ X = R column by column; returns (X, iterations list, statuses list).
+
+    ``force_restart_at`` is passed to every BiCGStab solve (a test hook, see
+    ``bicgstab``)."""
     R = np.asarray(R, dtype=np.float64)
     if R.ndim == 1:
         R = R[:, None]
@@ -180,7 +201,7 @@ def solve_block(A, M, R, thr, method="bicgstab", restart=30, maxit=500):
     its, sts = [], []
     for c in range(R.shape[1]):
         if method == "bicgstab":
-            X[:, c], it, st = bicgstab(A, M, R[:, c], thr[c], maxit)
+            X[:, c], it, st = bicgstab(A, M, R[:, c], thr[c], maxit, force_restart_at)
         elif method == "gmres":
             X[:, c], it, st = gmres(A, M, R[:, c], thr[c], restart, maxit)
         else:

@@ -190,3 +190,64 @@ def check_residual_identity(recover_fn, A, At, U, D, b, rng):
     rhs = ry - RW @ z
     assert np.linalg.norm(r - rhs) <= 1e-10 * (np.linalg.norm(r) + 1)
     assert np.linalg.norm(r) <= np.linalg.norm(ry) + c * np.linalg.norm(RW, "fro") + 1e-10
+
+
+# --------------------------------------------------------------- krylov -----
+
+def check_bicgstab_restart_is_fresh_start(bicgstab_fn, A, M, b, thr, at):
+    """A restart (r_hat = r, p = v = 0, rho_old = alpha = omega = 1; Section 5
+    BiCGStab with the breakdown reading) at the end of iteration `at` makes the
+    rest of the solve a fresh BiCGStab on the residual system A e = b - A x_at
+    started from e = 0.  So the restarted run must equal: `at` iterations,
+    then a new solve of the residual system, added on.  Compared to 1e-12
+    relative, with equal iteration counts; the state right after the restart
+    is also checked (r_hat equal to r, p and v zero)."""
+    trace = []
+    xr, itr, str_ = bicgstab_fn(A, M, b, thr, force_restart_at=[at], trace=trace)
+    xa, ita, sta = bicgstab_fn(A, M, b, 0.0, maxit=at)
+    assert sta == "maxit" and ita == at
+    e, ite, ste = bicgstab_fn(A, M, b - A @ xa, thr)
+    xc = xa + e
+    assert str_ == ste == "converged", (str_, ste)
+    assert itr == at + ite, (itr, at, ite)
+    assert np.linalg.norm(xr - xc) <= 1e-12 * np.linalg.norm(xc), np.linalg.norm(xr - xc)
+    rs = [st for ev, it, st in trace if ev == "restart"]
+    assert len(rs) == 1 and [it for ev, it, _ in trace if ev == "restart"] == [at]
+    st = rs[0]
+    assert np.array_equal(st["rhat"], st["r"]) and not st["p"].any() and not st["v"].any()
+
+
+def check_bicgstab_second_breakdown(bicgstab_fn, A, M, b, thr, at, gap):
+    """A second breakdown ends the solve with status "breakdown" at that
+    iteration; the returned x is the iterate reached by then, i.e. x_at plus
+    `gap` iterations of a fresh solve of the residual system."""
+    xr, itr, str_ = bicgstab_fn(A, M, b, thr, force_restart_at=[at, at + gap])
+    assert str_ == "breakdown" and itr == at + gap, (str_, itr)
+    xa, _, _ = bicgstab_fn(A, M, b, 0.0, maxit=at)
+    e, ite, ste = bicgstab_fn(A, M, b - A @ xa, 0.0, maxit=gap)
+    assert ste == "maxit" and ite == gap
+    assert np.linalg.norm(xr - (xa + e)) <= 1e-12 * np.linalg.norm(xa + e)
+
+
+def check_bicgstab_replacement(bicgstab_fn, A, M, b, thr):
+    """Convergence is declared on the true residual only; when the recursive
+    residual passes and the true one does not, the true residual replaces the
+    recursive one and the iteration continues.  On a system where that branch
+    is reached: the recursive residual had passed (its norm < thr) while
+    b - A x had not, r equals b - A x afterwards, and the solve still ends with
+    a true residual below thr and x within kappa * thr / ||b|| of the dense
+    solution."""
+    trace = []
+    x, it, st = bicgstab_fn(A, M, b, thr, trace=trace)
+    reps = [(i, s) for ev, i, s in trace if ev == "replace"]
+    assert reps, "the residual replacement branch was not reached"
+    for i, s in reps:
+        rt = b - A @ s["x"]
+        assert np.linalg.norm(s["r_rec"]) < thr <= np.linalg.norm(rt), i
+        assert np.array_equal(s["r"], rt), i
+    assert st == "converged", st
+    assert np.linalg.norm(b - A @ x) < thr
+    Ad = A.toarray()
+    xd = np.linalg.solve(Ad, b)
+    kappa = np.linalg.cond(Ad)
+    assert np.linalg.norm(x - xd) <= 2.0 * kappa * thr / np.linalg.norm(b) * np.linalg.norm(xd)

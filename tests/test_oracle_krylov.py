@@ -2,6 +2,7 @@
 import math
 
 import numpy as np
+import pytest
 import scipy.sparse as sp
 
 import workloads as W
@@ -85,3 +86,46 @@ def test_stopping_rules_imply_target():
     assert all(np.linalg.norm(U[:, j] - At @ Wh[:, j]) < thr2[j + 1] * 1.0001 for j in range(s))
     assert smw.relres(A, xh, b) < eps
     assert math.isclose(thr[0], 0.5 * eps * np.linalg.norm(b))
+
+
+def _sai_A(A):
+    """The oracle's own M on the pattern of A (a real preconditioner for the restart pins)."""
+    from oracle import lsq, pattern as opat
+    C = opat.as_csc(A)
+    n = A.shape[0]
+    cols, rows, vals = [], [], []
+    for k in range(n):
+        J = opat.pattern_A(C, k)
+        _, m, _ = lsq.solve_column(C, J, k)
+        rows += list(J)
+        cols += [k] * len(J)
+        vals += list(m)
+    return sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
+
+
+@pytest.mark.parametrize("seed,at,prec", [(0, 2, False), (1, 4, False), (2, 7, False), (3, 3, True)])
+def test_bicgstab_restart_is_fresh_start(seed, at, prec):
+    from tests import pins
+    A = W.random_sparse(150, 0.04, seed, diag=2.0 if not prec else 1.0)
+    M = _sai_A(A) if prec else sp.identity(A.shape[0], format="csr")
+    b = A @ np.ones(A.shape[0])
+    pins.check_bicgstab_restart_is_fresh_start(krylov.bicgstab, A, M, b, 1e-11 * np.linalg.norm(b), at)
+
+
+def test_bicgstab_second_breakdown():
+    from tests import pins
+    A = W.random_sparse(150, 0.04, 5, diag=2.0)
+    b = A @ np.ones(A.shape[0])
+    pins.check_bicgstab_second_breakdown(krylov.bicgstab, A, sp.identity(150, format="csr"), b,
+                                         1e-11 * np.linalg.norm(b), 3, 4)
+
+
+@pytest.mark.parametrize("seed,n,diag", [(13, 60, 0.5), (12, 120, 1.0)])
+def test_bicgstab_residual_replacement(seed, n, diag):
+    """Systems (found by a seed search) whose recursive residual passes 1e-14 ||b||
+    before the true residual does."""
+    from tests import pins
+    A = W.random_sparse(n, 0.08, seed, diag=diag)
+    b = A @ np.ones(n)
+    pins.check_bicgstab_replacement(krylov.bicgstab, A, sp.identity(n, format="csr"), b,
+                                    1e-14 * np.linalg.norm(b))

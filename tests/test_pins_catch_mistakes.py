@@ -153,3 +153,63 @@ def test_smw_mistakes_caught(mistake):
         return x, z, float(np.linalg.norm(z))
     with pytest.raises(AssertionError):
         pins.check_smw_exact(wrong, w.A, S.At, U, S.D, w.b)
+
+
+def _bicgstab_mutant(old, new):
+    """A copy of oracle.krylov.bicgstab with one textual change (the planted mistake)."""
+    import inspect
+    import textwrap
+
+    from oracle import krylov
+    src = textwrap.dedent(inspect.getsource(krylov.bicgstab))
+    assert src.count(old) == 1, old
+    ns = dict(vars(krylov))
+    exec(compile(src.replace(old, new), "<bicgstab mutant>", "exec"), ns)
+    return ns["bicgstab"]
+
+
+_RESTART_MISTAKES = {
+    "old_rhat": ("        rhat = r.copy()\n        rho_old = alpha = omega = 1.0\n",
+                 "        rho_old = alpha = omega = 1.0\n"),
+    "keep_p_v": ("        v = np.zeros(n)\n        p = np.zeros(n)\n        note(", "        note("),
+    "keep_v": ("        v = np.zeros(n)\n        p = np.zeros(n)\n", "        p = np.zeros(n)\n"),
+}
+
+
+@pytest.mark.parametrize("mistake", sorted(_RESTART_MISTAKES))
+def test_bicgstab_restart_mistakes_caught(mistake):
+    f = _bicgstab_mutant(*_RESTART_MISTAKES[mistake])
+    A = W.random_sparse(150, 0.04, 1, diag=2.0)
+    b = A @ np.ones(150)
+    with pytest.raises(AssertionError):
+        pins.check_bicgstab_restart_is_fresh_start(f, A, sp.identity(150, format="csr"), b,
+                                                   1e-11 * np.linalg.norm(b), 4)
+
+
+def test_bicgstab_endless_restarts_caught():
+    f = _bicgstab_mutant("        return restarts <= 1\n", "        return True\n")
+    A = W.random_sparse(150, 0.04, 5, diag=2.0)
+    b = A @ np.ones(150)
+    with pytest.raises(AssertionError):
+        pins.check_bicgstab_second_breakdown(f, A, sp.identity(150, format="csr"), b,
+                                             1e-11 * np.linalg.norm(b), 3, 4)
+
+
+_REPLACE_MISTAKES = {
+    # the recursive residual is kept after a failed true-residual check
+    "no_replacement": ("            r_rec, r = r, rt\n", "            r_rec = r\n"),
+    # sign of the true residual
+    "sign": ("            r_rec, r = r, rt\n", "            r_rec, r = r, -rt\n"),
+    # convergence declared on the recursive residual at the full step
+    "recursive_accept": ("            if np.linalg.norm(rt) < thr:\n                return x, it, \"converged\"\n",
+                         "            return x, it, \"converged\"\n"),
+}
+
+
+@pytest.mark.parametrize("mistake", sorted(_REPLACE_MISTAKES))
+def test_bicgstab_replacement_mistakes_caught(mistake):
+    f = _bicgstab_mutant(*_REPLACE_MISTAKES[mistake])
+    A = W.random_sparse(60, 0.08, 13, diag=0.5)
+    b = A @ np.ones(60)
+    with pytest.raises(AssertionError):
+        pins.check_bicgstab_replacement(f, A, sp.identity(60, format="csr"), b, 1e-14 * np.linalg.norm(b))
