@@ -1,14 +1,14 @@
 #!/usr/bin/env python3
 """Benchmark of the SMW-split SAI path on one MI355X.
 
-Default workload (--workload 2): 3D 7-point convection-diffusion on a 100^3
-grid (n = 1,000,000) with s = 10 seeded dense columns at 5% density; static
-pattern P(|A~|^2) with absolute dropping 1e-3; M built in FP32 ("mixed"),
-Krylov/SMW/check in FP64; 11 right-hand sides in one batched BiCGStab,
-eps = 1e-8.  Workloads 1, 3, 4 and 5 are the other four configurations
-(GMRES(30) on a 45x45 grid; SPAI on a random n = 200,000 matrix; the 500x500
-grid with the adjoint; the 160^3 grid with 51 right-hand sides and the
-adjoint).
+Default workload (--workload 5, the largest single-GPU configuration): 3D
+7-point convection-diffusion on a 160^3 grid (n = 4,096,000) with s = 50 seeded
+dense columns at 1% density; static pattern P(|A~|^2) with absolute dropping
+1e-3; M built in FP32 ("mixed"), Krylov/SMW/check in FP64; 51 right-hand sides
+in one batched BiCGStab, eps = 1e-8; then the adjoint (51 transposed systems)
+and the gradients of the loss 0.5 ||x - x*||^2.  Workloads 1-4 are the other
+configurations (GMRES(30) on a 45x45 grid; the 100^3 grid with s = 10; SPAI on
+a random n = 200,000 matrix; the 500x500 grid with the adjoint).
 
 One step = the whole path on inputs already resident in HBM: split A into
 A~ + U V^T, build M (patterns, column QR, dropping, CSC/CSR assembly), solve
@@ -16,7 +16,8 @@ the s+1 systems to the paper's stopping rules, SMW recovery and the FP64
 residual check (plus, for the workloads with a loss, the adjoint solve and
 the gradients).  value = n / (time per step): SAI columns carried to a 1e-8
 solution per second.  The same step with M in FP64 ("plain") is timed after
-it.  Prints one JSON line.
+it.  Before the GPU runs, the FP64 oracle is timed on the host (cpu_baseline).
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -59,7 +60,8 @@ def counted_traffic(kernel, workload):
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-FP32_VEC_TFLOPS = 157.3
+# FP32 vector FMA rate without packed instructions (the build disables them)
+FP32_VEC_TFLOPS = 78.6
 FP64_VEC_TFLOPS = 78.6
 
 # register LS kernel variants in the order the library assigns columns to them
@@ -99,67 +101,148 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w, bkw, gpu_iters, gpu_nnz_m, seconds=20.0):
-    """The FP64 oracle, as it stands, timed on a bounded sample of the same workload."""
+# ------------------------------------------------------------------ CPU leg --
+# The FP64 oracle, as it stands, on this host.  It runs before anything touches
+# the GPU (its process pool forks), and its per-iteration Krylov costs are scaled
+# by the GPU's iteration counts once those are known.
+
+def _host_cpu():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return model, os.cpu_count() or 1, avail
+
+
+_ORACLE_JOB = {}
+
+
+def _oracle_columns(rng_):
+    """Oracle column build (pattern, QR, drop) of columns [a, b): the kept rows and values."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import drop as odrop
+    from oracle import lsq as olsq
+    from oracle import pattern as opat
+    from oracle import spai as ospai
+    a, b = rng_
+    C, R, cn2, bkw = (_ORACLE_JOB[key] for key in ("C", "R", "cn2", "bkw"))
+    rows, vals, cnt = [], [], np.zeros(b - a, dtype=np.int64)
+    with threadpool_limits(1):
+        for k in range(a, b):
+            if bkw.get("pattern") == 2:
+                J, _, m, _, _ = ospai.spai_column(C, R, cn2, k, bkw["spai_steps"], bkw["spai_per_step"],
+                                                  bkw["delta"])
+            else:
+                J = opat.pattern_A(C, k) if bkw.get("pattern") == 0 else opat.pattern_A2(C, k)
+                _, m, _ = olsq.solve_column(C, J, k)
+            if bkw.get("drop") == 1:
+                keep = odrop.drop_column(m, bkw["tau"])
+                J, m = J[keep], m[keep]
+            rows.append(J.astype(np.int32))
+            vals.append(m)
+            cnt[k - a] = J.size
+    return a, np.concatenate(rows), np.concatenate(vals), cnt
+
+
+def cpu_baseline(w, bkw, adjoint, workers):
+    """Time the oracle on this host: its split of the full matrix, its build of
+    the whole M (columns in chunks over a fork pool of `workers` processes), and
+    two BiCGStab iterations with its own M on two right-hand sides (and on the
+    transposed system for the adjoint), whose per-iteration cost is scaled later
+    by the iteration counts of the GPU solve."""
+    import multiprocessing as mp
+
     import numpy as np
     import scipy.sparse as sp
     from threadpoolctl import threadpool_limits
 
-    from oracle import drop as odrop
     from oracle import krylov as okry
-    from oracle import lsq as olsq
     from oracle import pattern as opat
+    from oracle import smw as osmw
     from oracle import spai as ospai
     from oracle import split as osplit
 
+    n = w.A.shape[0]
+    out = {}
     with threadpool_limits(1):
-        n = w.A.shape[0]
         t0 = time.perf_counter()
         S = osplit.split(w.A)
-        t_split = time.perf_counter() - t0
-        C = opat.as_csc(S.At)
-        R = sp.csr_matrix(S.At)
-        R.sort_indices()
-        cn2 = ospai.column_norms2(C) if bkw.get("pattern") == 2 else None
-        rng = np.random.default_rng(0)
-        cols = rng.permutation(n)
+        out["split_s"] = time.perf_counter() - t0
+    C = opat.as_csc(S.At)
+    R = sp.csr_matrix(S.At)
+    R.sort_indices()
+    _ORACLE_JOB.update(C=C, R=R, cn2=ospai.column_norms2(C) if bkw.get("pattern") == 2 else None, bkw=bkw)
+    chunk = max(1, min(65536, -(-n // (8 * workers))))
+    ranges = [(a, min(n, a + chunk)) for a in range(0, n, chunk)]
+    t0 = time.perf_counter()
+    ctx = mp.get_context("fork")
+    with ctx.Pool(workers) as pool:
+        parts = sorted(pool.imap_unordered(_oracle_columns, ranges), key=lambda t: t[0])
+    out["build_s"] = time.perf_counter() - t0
+    _ORACLE_JOB.clear()
+    cnt = np.concatenate([p[3] for p in parts])
+    cp = np.concatenate([[0], np.cumsum(cnt)])
+    M = sp.csc_matrix((np.concatenate([p[2] for p in parts]), np.concatenate([p[1] for p in parts]), cp),
+                      shape=(n, n))
+    del parts
+    out["nnz_M"] = int(M.nnz)
+    Mr, At = sp.csr_matrix(M), sp.csr_matrix(S.At)
+    rhs = [w.b] + ([S.U[:, 0].toarray().ravel()] if S.s else [])
+    with threadpool_limits(1):
         t0 = time.perf_counter()
-        done = 0
-        while done < n and time.perf_counter() - t0 < 0.5 * seconds:
-            k = int(cols[done])
-            if bkw.get("pattern") == 2:
-                ospai.spai_column(C, R, cn2, k, bkw["spai_steps"], bkw["spai_per_step"], bkw["delta"])
-            else:
-                J = opat.pattern_A(C, k) if bkw.get("pattern") == 0 else opat.pattern_A2(C, k)
-                I, m, r = olsq.solve_column(C, J, k)
-                if bkw.get("drop") == 1:
-                    odrop.drop_column(m, bkw["tau"])
-            done += 1
-        t_col = (time.perf_counter() - t0) / done
-        # Krylov: two oracle BiCGStab iterations per right-hand side at full n, with an
-        # operator of M's size (P(A~) or P(|A~|^2) thinned to nnz(M), values 1/n).
-        At = sp.csr_matrix(S.At)
-        B = (At != 0).astype(np.float64)
-        Mp = sp.coo_matrix(B @ B if bkw.get("pattern") == 1 else B)
-        keep = rng.random(Mp.nnz) < min(1.0, gpu_nnz_m / max(Mp.nnz, 1))
-        Mp = sp.csr_matrix((np.full(int(keep.sum()), 1.0 / n), (Mp.row[keep], Mp.col[keep])),
-                           shape=(n, n))
-        Rb = np.zeros((n, S.s + 1))
-        Rb[:, 0] = w.b
-        Rb[:, 1:] = S.U.toarray()
+        for c in rhs:
+            okry.bicgstab(At, Mr, c, 0.0, maxit=2)
+        out["iter_s"] = (time.perf_counter() - t0) / (2 * len(rhs))
+        if adjoint:
+            AtT, MT = sp.csr_matrix(S.At.T), sp.csr_matrix(M.T)
+            t0 = time.perf_counter()
+            okry.bicgstab(AtT, MT, w.b, 0.0, maxit=2)
+            out["iter_adj_s"] = (time.perf_counter() - t0) / 2
+        Y = np.zeros((n, S.s + 1))
+        Y[:, 0] = w.b
         t0 = time.perf_counter()
-        for c in range(S.s + 1):
-            okry.bicgstab(At, Mp, Rb[:, c], 1e-300, maxit=2)
-        t_two = time.perf_counter() - t0
-    est = t_split + n * t_col + gpu_iters * t_two / 2.0
-    return dict(
-        value=n / est, unit="columns/s (whole path, estimated from the sample)", cores=1,
-        kind="oracle",
-        sample=(f"oracle split of the full matrix ({t_split:.2f} s); column pattern + QR (+ drop) on "
-                f"{done} random columns ({t_col * 1e6:.0f} us/column, x n); 2 BiCGStab iterations on "
-                f"all {S.s + 1} right-hand sides at full n with an operator of nnz(M) "
-                f"({t_two:.2f} s, x {gpu_iters} / 2)"),
-        est_seconds=est)
+        x, _, _ = osmw.recover(Y[:, 0], Y[:, 1:], S.D)
+        osmw.relres(w.A, x, w.b)
+        out["smw_s"] = time.perf_counter() - t0
+    return out
+
+
+def cpu_m_error(w, bkw, arr, count=64):
+    """Worst relative error, over a seeded sample of columns (the irregular
+    columns, the first and the last included), of the FP32 M's columns m_k before
+    dropping against the FP64 oracle's solve on the same pattern."""
+    import numpy as np
+
+    from oracle import lsq as olsq
+    from oracle import pattern as opat
+    from oracle import split as osplit
+    S = osplit.split(w.A)
+    C = opat.as_csc(S.At)
+    n = w.A.shape[0]
+    jp, ji = arr["j_ptr"].cpu().numpy(), arr["j_idx"].cpu().numpy()
+    mf = arr["m_full"].cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(12116866)
+    cols = sorted(set(rng.choice(n, size=min(count, n), replace=False).tolist())
+                  | set(int(j) for j in S.D) | {0, n - 1})
+    errs = []
+    for k in cols:
+        J = ji[jp[k]:jp[k + 1]]
+        _, m, _ = olsq.solve_column(C, J, k)
+        errs.append(float(np.linalg.norm(mf[jp[k]:jp[k + 1]] - m) / np.linalg.norm(m)))
+    errs = np.asarray(errs)
+    return dict(worst=float(errs.max()), median=float(np.median(errs)), columns=len(cols),
+                reference="FP64 oracle column solve on the same J_k")
 
 
 def main():
@@ -167,18 +250,17 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", type=int, default=2)
+    ap.add_argument("--workload", type=int, default=5)
     ap.add_argument("--plain-steps", type=int, default=None)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--cpu-workers", type=int, default=16)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1 "
-                                   "(multi-GPU sharding is not built)"}))
+        print(json.dumps({"error": "this build runs on one GPU: --gpus must be 1 (the path shards by "
+                                   "columns and right-hand sides, but no multi-GPU code is built)"}))
         sys.exit(2)
 
     import numpy as np
-    import torch
 
     import paper_1211_6866_amd as P
     import workloads as W
@@ -187,10 +269,21 @@ def main():
     log(f"bench: generating workload {args.workload} ({name})")
     w = W.make(args.workload)
     n = w.A.shape[0]
+
+    # the CPU oracle leg first: its process pool forks before anything touches the GPU
+    cpu_raw = None
+    model, ncpu, avail = _host_cpu()
+    workers = max(1, min(args.cpu_workers, avail))
+    if not args.no_cpu:
+        log(f"bench: CPU oracle leg ({workers} processes for the build, {model}, {ncpu} CPUs)")
+        cpu_raw = cpu_baseline(w, bkw, adjoint, workers)
+        log(f"bench: CPU oracle leg done: split {cpu_raw['split_s']:.1f} s, build {cpu_raw['build_s']:.1f} s, "
+            f"{cpu_raw['iter_s'] * 1e3:.0f} ms per BiCGStab iteration and right-hand side")
+
+    import torch
     rp, ci, va = P.csr_to_device(w.A)
     b = torch.from_numpy(w.b).cuda()
     xstar = torch.from_numpy(W.x_star(n, w.seed)).cuda() if adjoint else None
-    times = {}
 
     def step(prec):
         sp_ = P.Split(rp, ci, va)
@@ -208,12 +301,13 @@ def main():
     # one untimed mixed step with events around every kernel: the full table, and
     # the dominant kernel (the largest total among single kernels; scopes that cover
     # several launches, like "split" or "spai_search", are listed but not chosen)
+    log("bench: one step with events around every kernel")
     P.profile_enable(1)
     step(P.FP32)
     prof_all = P.profile_read()
     P.profile_enable(0)
-    scopes = {"split", "smw_recover", "spai_search", "gmres_fused", "pattern_bounds", "pattern_fill",
-              "pattern_pack", "bicg_init"}
+    scopes = {"split", "smw_recover", "spai_search", "psai_search", "gmres_fused", "pattern_bounds",
+              "pattern_fill", "pattern_pack", "bicg_init"}
     dom = max((tot, nm) for nm, (l, tot) in prof_all.items() if nm not in scopes)[1]
 
     def timed(prec, K, only=None):
@@ -229,6 +323,7 @@ def main():
             solves.append(last[3]["t_solve_ms"])
             if last[4] is not None:
                 backs.append(last[4]["t_solve_ms"] + last[4]["t_smw_ms"])
+            log(f"bench: step {i + 1}/{K} done")
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         prof = P.profile_read() if only else {}
@@ -244,11 +339,12 @@ def main():
         log(f"bench: timing {kplain} plain FP64 steps")
         # the same event overhead as the mixed steps: around the plain form of that kernel
         dom_p = dom.replace("_f32", "_f64")
-        ms_plain, (sp_p, pc_p, x_p, st_p, bst_p), _, builds_p, solves_p, _ = timed(P.FP64, kplain,
-                                                                                 only=dom_p)
+        ms_plain, (sp_p, pc_p, x_p, st_p, bst_p), _, builds_p, solves_p, backs_p = timed(P.FP64, kplain,
+                                                                                       only=dom_p)
         xhp = x_p.cpu().numpy()
         plain = dict(ms=ms_plain, build=float(np.mean(builds_p)), st=st_p,
-                     rr_host=float(np.linalg.norm(w.b - w.A @ xhp) / np.linalg.norm(w.b)))
+                     rr_host=float(np.linalg.norm(w.b - w.A @ xhp) / np.linalg.norm(w.b)),
+                     adjoint=float(np.mean(backs_p)) if backs_p else None)
 
     xh = x_m.cpu().numpy()
     rr_host = float(np.linalg.norm(w.b - w.A @ xh) / np.linalg.norm(w.b))
@@ -262,6 +358,10 @@ def main():
     arr = pc_l.arrays()
     nJ = np.diff(arr["j_ptr"].cpu().numpy())
     nI = np.diff(arr["i_ptr"].cpu().numpy())
+    m_err = None
+    if not args.no_cpu:
+        log("bench: FP32 M against the FP64 oracle on sampled columns")
+        m_err = cpu_m_error(w, bkw, arr)
     del pc_l, arr
     flops = ls_flops(nI.astype(np.float64), nJ.astype(np.float64))
     ls_work = {}
@@ -282,6 +382,8 @@ def main():
     dom_launches, dom_ms = prof[dom]
     avg_ms = dom_ms / dom_launches
     if dom.startswith("ls_qr_f32"):
+        # FP32 vector FMA without packed instructions (the build disables them):
+        # 256 CUs x 64 lanes x 2 flops x 2.4 GHz
         ach = ls_work.get(dom, 0.0) / (avg_ms * 1e-3) / 1e12
         roof = dict(bound="alu", achieved=round(ach, 3), peak=FP32_VEC_TFLOPS, unit="TFLOP/s",
                     frac=round(ach / FP32_VEC_TFLOPS, 4), traffic=None)
@@ -294,6 +396,8 @@ def main():
     roof["kernel"] = dom
     roof["avg_launch_ms"] = round(avg_ms, 4)
     roof["launches_per_step"] = dom_launches / args.steps
+    if dom in hbm_bytes:
+        roof["algorithmic_bytes_per_launch"] = hbm_bytes[dom]
     counted = counted_traffic(dom, name)
     if counted is not None:
         roof["traffic"] = counted["traffic_bytes_per_launch"]
@@ -311,9 +415,23 @@ def main():
             kern_table[nm]["TFLOP/s"] = round(wf / (kern_table[nm]["avg_ms"] * 1e-3) / 1e12, 2)
 
     cpu = None
-    if not args.no_cpu:
-        log("bench: CPU oracle baseline (bounded sample)")
-        cpu = cpu_baseline(w, bkw, int(st_m["iters_max"]), nnz_m, args.cpu_seconds)
+    if cpu_raw is not None:
+        it_fwd = int(np.sum(st_m["iters"]))
+        it_adj = int(np.sum(bst_m["iters"])) if bst_m is not None else 0
+        t_kry = cpu_raw["iter_s"] * it_fwd + cpu_raw.get("iter_adj_s", 0.0) * it_adj
+        est = cpu_raw["split_s"] + cpu_raw["build_s"] + t_kry + cpu_raw["smw_s"]
+        cpu = dict(
+            value=round(n / est, 1), unit="columns/s", cores=workers, kind="oracle",
+            cpu_model=model, nproc=ncpu,
+            sample=(f"oracle split of the full matrix ({cpu_raw['split_s']:.1f} s, 1 thread); oracle build of "
+                    f"all {n} columns of M ({cpu_raw['nnz_M']} entries) on {workers} processes "
+                    f"({cpu_raw['build_s']:.1f} s); oracle BiCGStab with that M: 2 iterations on 2 "
+                    f"right-hand sides ({cpu_raw['iter_s'] * 1e3:.0f} ms per iteration and right-hand side, "
+                    f"1 thread) scaled by the GPU solve's {it_fwd} column-iterations"
+                    + (f", and on the transposed system ({cpu_raw['iter_adj_s'] * 1e3:.0f} ms) scaled by "
+                       f"the adjoint's {it_adj}" if adjoint else "")
+                    + f" ({t_kry:.0f} s extrapolated); SMW and residual check ({cpu_raw['smw_s']:.2f} s)"),
+            est_seconds=round(est, 2))
 
     value = n / (ms_mixed * 1e-3)
     out = {
@@ -339,13 +457,17 @@ def main():
         "build_columns_per_s": {"mixed": round(n / (np.mean(builds_m) * 1e-3), 1),
                                 "plain_fp64": round(n / (plain["build"] * 1e-3), 1) if plain else None},
         "solve_ms": round(float(np.mean(solves_m)), 3),
-        "adjoint_ms": round(float(np.mean(backs_m)), 3) if backs_m else None,
+        "adjoint_ms": {"mixed": round(float(np.mean(backs_m)), 3) if backs_m else None,
+                       "plain_fp64": round(plain["adjoint"], 3) if plain and plain["adjoint"] else None},
         "solve": {"mixed": {"iters": st_m["iters"], "rr": st_m["rr"], "rr_host": rr_host,
-                            "c": st_m["c"]},
+                            "c": st_m["c"],
+                            "adjoint_iters": bst_m["iters"] if bst_m is not None else None},
                   "plain_fp64": ({"iters": plain["st"]["iters"], "rr": plain["st"]["rr"],
                                   "rr_host": plain["rr_host"]} if plain else None)},
         "M": {"nnz": int(nnz_m), "spar": round(pc_m.stats.spar, 4), "max_I": pc_m.stats.max_i,
-              "max_J": pc_m.stats.max_j, "n_c": pc_m.stats.n_c},
+              "max_J": pc_m.stats.max_j, "n_c": pc_m.stats.n_c, "l_m": pc_m.stats.l_m,
+              "s": pc_m.stats.s, "p": pc_m.stats.p, "drop_undecidable_fp32": int(pc_m.stats.drop_flips),
+              "fp32_vs_fp64_oracle": m_err},
         "roofline": roof,
         "kernels_one_step": kern_table,
         "cpu_baseline": cpu,

@@ -84,6 +84,13 @@ typedef struct {
   double dense_factor; /* 10 */
   int32_t keep;        /* <= 0: p */
   int32_t rule;        /* SAI_KEEP_NEAREST | SAI_KEEP_LARGEST */
+  /* Optional override of the count rule (host array, not kept after the call):
+   * when non-NULL, the s_given columns it lists (strictly ascending, in
+   * [0, n)) are the irregular ones whatever their counts; s_given = 0 gives
+   * A~ = A.  NULL: columns are classified by dense_factor * p.  Errors:
+   * SAI_EINVAL for an unsorted, repeated or out-of-range entry or s_given < 0. */
+  const int32_t* host_dense_cols;
+  int32_t s_given;
 } sai_split_opts;
 
 int sai_split(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
@@ -165,6 +172,17 @@ typedef struct {
                              precision's variant table, the global-memory kernel
                              last; unused slots 0) */
   float t_pattern_ms, t_ls_ms, t_assemble_ms, t_total_ms;
+  int32_t s, p;           /* of the split: irregular columns, floor(nnz(A)/n) */
+  int32_t l_m;            /* most loops a column used (Table 5's l_m): PSAI(tol)
+                             loops run (1 .. psai_lmax + 1); SPAI augmentation
+                             steps taken (0 .. spai_steps); 0 for static patterns */
+  int64_t drop_flips;     /* entries whose keep/drop decision the build precision
+                             cannot settle: | |m_jk| - tol_k | <= eta ||m_k|| /
+                             (1 - eta) with eta = 1e-4 (SAI_FP32) or 1e-12
+                             (SAI_FP64), the always-kept largest entry excluded;
+                             0 without a drop after the solve.  If every column
+                             is within eta ||m'_k|| of an exact column m'_k, the
+                             exact dropping can differ only on these entries. */
 } sai_build_stats;
 
 int sai_build(const sai_split_t* sp, const sai_build_opts* opts, void* stream,

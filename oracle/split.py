@@ -41,7 +41,10 @@ class Split:
 
 
 def split(A: sp.csr_matrix, dense_factor: float = 10.0, keep: int | None = None,
-          rule: str = "nearest") -> Split:
+          rule: str = "nearest", dense_cols=None) -> Split:
+    """Split A = A~ + U V^T.  ``dense_cols`` (optional, ascending) names the
+    irregular columns instead of the count rule; each is then split by the same
+    keep rule."""
     A = sp.csr_matrix(A)
     A.sort_indices()
     n = A.shape[0]
@@ -51,7 +54,8 @@ def split(A: sp.csr_matrix, dense_factor: float = 10.0, keep: int | None = None,
     C = A.tocsc()
     C.sort_indices()
     counts = np.diff(C.indptr)
-    D = np.flatnonzero(counts > dense_factor * p)
+    D = (np.flatnonzero(counts > dense_factor * p) if dense_cols is None
+         else np.asarray(list(dense_cols), dtype=np.int64))
     keep_n = p if keep is None else int(keep)
     if keep_n < 1:
         raise ValueError("keep must be >= 1")

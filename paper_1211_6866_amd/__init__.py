@@ -45,7 +45,8 @@ class _Allocator(C.Structure):
 
 
 class SplitOpts(C.Structure):
-    _fields_ = [("dense_factor", C.c_double), ("keep", C.c_int32), ("rule", C.c_int32)]
+    _fields_ = [("dense_factor", C.c_double), ("keep", C.c_int32), ("rule", C.c_int32),
+                ("host_dense_cols", C.POINTER(C.c_int32)), ("s_given", C.c_int32)]
 
 
 class SplitInfo(C.Structure):
@@ -69,7 +70,8 @@ class BuildStats(C.Structure):
                 ("sum_i", C.c_int64), ("max_i", C.c_int32), ("max_j", C.c_int32),
                 ("n_c", C.c_int32), ("spar", C.c_double), ("bucket_cols", C.c_int64 * 16),
                 ("t_pattern_ms", C.c_float), ("t_ls_ms", C.c_float), ("t_assemble_ms", C.c_float),
-                ("t_total_ms", C.c_float)]
+                ("t_total_ms", C.c_float), ("s", C.c_int32), ("p", C.c_int32), ("l_m", C.c_int32),
+                ("drop_flips", C.c_int64)]
 
 
 class PrecondInfo(C.Structure):
@@ -221,7 +223,9 @@ def _export(ptr, count: int, dtype):
 class Split:
     """Handle of A = A~ + U V^T (owns device copies; freed with the object)."""
 
-    def __init__(self, row_ptr, col_idx, val, dense_factor=10.0, keep=0, rule=KEEP_NEAREST):
+    def __init__(self, row_ptr, col_idx, val, dense_factor=10.0, keep=0, rule=KEEP_NEAREST,
+                 dense_cols=None):
+        """dense_cols: optional list of the irregular columns (overrides the count rule)."""
         torch = _torch()
         L = lib()
         assert row_ptr.dtype == torch.int32 and col_idx.dtype == torch.int32
@@ -230,6 +234,11 @@ class Split:
         self.nnz = int(col_idx.numel())
         h = C.c_void_p()
         o = SplitOpts(float(dense_factor), int(keep), int(rule))
+        if dense_cols is not None:
+            dl = [int(j) for j in dense_cols]
+            self._dense_arr = (C.c_int32 * max(1, len(dl)))(*dl)
+            o.host_dense_cols = C.cast(self._dense_arr, C.POINTER(C.c_int32))
+            o.s_given = len(dl)
         _check(L.sai_split(self.n, self.nnz, _ptr(row_ptr), _ptr(col_idx), _ptr(val), C.byref(o),
                            C.byref(_alloc_struct), _stream(), C.byref(h)), "sai_split")
         self.h = h
@@ -313,7 +322,8 @@ class Precond:
         return dict(n=s.n, nnz_m=s.nnz_m, nnz_m_full=s.nnz_m_full, sum_i=s.sum_i, max_i=s.max_i,
                     max_j=s.max_j, n_c=s.n_c, spar=s.spar, bucket_cols=list(s.bucket_cols),
                     t_pattern_ms=s.t_pattern_ms, t_ls_ms=s.t_ls_ms,
-                    t_assemble_ms=s.t_assemble_ms, t_total_ms=s.t_total_ms)
+                    t_assemble_ms=s.t_assemble_ms, t_total_ms=s.t_total_ms, s=s.s, p=s.p,
+                    l_m=s.l_m, drop_flips=s.drop_flips)
 
 
 def _sopts(method=BICGSTAB, restart=30, eps=1e-8, maxit=500, c_mode=C_ONE):

@@ -42,7 +42,7 @@ int sai_split(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col
   *out = nullptr;
   sai_split_s* h = nullptr;
   int rc = guarded([&] {
-    sai_split_opts o{10.0, 0, SAI_KEEP_NEAREST};
+    sai_split_opts o{10.0, 0, SAI_KEEP_NEAREST, nullptr, 0};
     if (opts) o = *opts;
     Allocator al;
     if (alloc) al.a = *alloc;

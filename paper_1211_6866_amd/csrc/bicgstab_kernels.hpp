@@ -565,11 +565,14 @@ enum { F_INIT, F_AV, F_AT, F_HALF, F_XR, F_FULL, F_RESTART_END };
 constexpr int FNT = 1024;  // finisher threads
 
 template <int ND, int OP>
-// force_it (the F_XR finisher): at iteration it == force_it every active column
-// is handled as a breakdown (restart), so that the restart path can be tested
-// on well-conditioned systems; 0 (the default) never matches.
+// force_it, force_it2 (the F_XR and F_FULL finishers): at the end of iteration
+// it == force_it (or force_it2) every active column that has not converged is
+// handled as a breakdown (restart), so that the restart path and the second
+// breakdown can be tested on well-conditioned systems; 0 (the default) never
+// matches.
 __global__ void __launch_bounds__(FNT) k_fin(int k, State S, int nb, int it = 0, int maxit = 0,
-                                             int force_it = 0) {
+                                             int force_it = 0, int force_it2 = 0) {
+  const bool forced = it > 0 && (it == force_it || it == force_it2);
   // partial sums are read as column pairs; U independent sums per pair and d
   // keep U loads of every d in flight (the partials come from every XCD, so
   // each round of loads is a trip past the L2)
@@ -738,7 +741,7 @@ __global__ void __launch_bounds__(FNT) k_fin(int k, State S, int nb, int it = 0,
       if (sqrt(tot[1][t]) < st_thr) {
         S.full[t] = 1;
         S.any[1] = 1;  // breakdown checks follow the true-residual check
-      } else if (fabs(st_omega) < TINY || fabs(rho_new) < TINY || it == force_it) {
+      } else if (fabs(st_omega) < TINY || fabs(rho_new) < TINY || forced) {
         S.rst[t] = 1;
         S.any[2] = 1;
       }
@@ -751,7 +754,7 @@ __global__ void __launch_bounds__(FNT) k_fin(int k, State S, int nb, int it = 0,
         const double rho_new = tot[1][t];
         S.rho[t] = rho_new;
         S.beta[t] = (rho_new / st_rho_old) * (st_alpha / st_omega);
-        if (fabs(st_omega) < TINY || fabs(rho_new) < TINY) {
+        if (fabs(st_omega) < TINY || fabs(rho_new) < TINY || forced) {
           S.rst[t] = 1;
           S.any[2] = 1;
         }

@@ -24,11 +24,11 @@ void csr_transpose(int32_t nrows, int32_t ncols, const int32_t* rp, const int32_
 void psai_patterns(const sai_split_s* sp, const sai_build_opts& o, hipStream_t st,
                    const Allocator& al, DBuf<int64_t>& jptr, DBuf<int32_t>& jidx,
                    DBuf<int64_t>& iptr, DBuf<int32_t>& iidx, DBuf<int32_t>& cntJ,
-                   DBuf<int32_t>& cntI, DBuf<double>& mval, DBuf<double>& res);
+                   DBuf<int32_t>& cntI, DBuf<double>& mval, DBuf<double>& res, int* l_m);
 void spai_patterns(const sai_split_s* sp, const sai_build_opts& o, hipStream_t st,
                    const Allocator& al, DBuf<int64_t>& jptr, DBuf<int32_t>& jidx,
                    DBuf<int64_t>& iptr, DBuf<int32_t>& iidx, DBuf<int32_t>& cntJ,
-                   DBuf<int32_t>& cntI);
+                   DBuf<int32_t>& cntI, int* l_m);
 
 namespace {
 
@@ -100,13 +100,19 @@ __global__ void k_to_type(int64_t m, const double* __restrict__ in, T* __restric
 // largest magnitude (the first of equals) is always kept.  32 lanes per column
 // (two columns per wavefront) read the column coalesced; the kept entries keep
 // their order (ballot prefix counts).  COUNT: number kept per column; else the
-// kept (row, value) pairs are written from colp[k] on.
+// kept (row, value) pairs are written from colp[k] on.  The COUNT pass also
+// counts, into *nearc, the entries other than the always-kept one with
+// | |m_jk| - thr | <= eta ||m_k|| / (1 - eta): an entry whose decision differs
+// from that on a reference column m' with ||m_k - m'|| <= eta ||m'|| lies
+// within |m_jk - m'_j| <= eta ||m'|| of thr, so these are the only decisions
+// that a column accurate to eta can settle differently.
 template <class T, bool COUNT>
 __global__ void __launch_bounds__(NT) k_drop(int32_t n, const int64_t* __restrict__ jptr,
                                              const int32_t* __restrict__ jidx, const T* __restrict__ m,
                                              int mode, double tau, double delta, double norm1,
                                              int32_t* __restrict__ cnt, const int32_t* __restrict__ colp,
-                                             int32_t* __restrict__ rowi, T* __restrict__ cval) {
+                                             int32_t* __restrict__ rowi, T* __restrict__ cval,
+                                             double eta, unsigned long long* __restrict__ nearc) {
   constexpr int G = 16;  // lanes per column (four columns per wavefront)
   const int lane = threadIdx.x & 63, gi = lane & (G - 1), gbase = lane & (64 - G);
   const int64_t k = ((int64_t)blockIdx.x * NT + threadIdx.x) / G;
@@ -116,23 +122,29 @@ __global__ void __launch_bounds__(NT) k_drop(int32_t n, const int64_t* __restric
   double thr = -1.0;
   if (mode == SAI_DROP_ABS) thr = tau;
   else if (mode == SAI_DROP_TOLK) thr = delta / ((double)nj * norm1);
-  // largest magnitude, first index among equals
-  double vmax = -1.0;
+  // largest magnitude, first index among equals; the column's squared norm
+  double vmax = -1.0, ss = 0.0;
   int64_t amax = INT64_MAX;
   for (int64_t e = a + gi; e < b; e += G) {
     const double v = fabs((double)m[e]);
+    if (COUNT) ss += v * v;
     if (v > vmax) { vmax = v; amax = e; }
   }
 #pragma unroll
   for (int o = G / 2; o > 0; o >>= 1) {
     const double ov = __shfl_xor(vmax, o, 64);
     const int64_t oa = __shfl_xor(amax, o, 64);
+    if (COUNT) ss += __shfl_xor(ss, o, 64);
     if (ov > vmax || (ov == vmax && oa < amax)) { vmax = ov; amax = oa; }
   }
+  const double band = eta * sqrt(ss) / (1.0 - eta);
   int32_t o = COUNT ? 0 : (valid ? colp[k] : 0);
+  int nnear = 0;
   for (int64_t off = 0; __any(off < nj); off += G) {
     const int64_t e = a + off + gi;
-    const bool kf = e < b && (fabs((double)m[e]) > thr || e == amax);
+    const double av = e < b ? fabs((double)m[e]) : 0.0;
+    const bool kf = e < b && (av > thr || e == amax);
+    if (COUNT && e < b && e != amax && thr > 0.0 && fabs(av - thr) <= band) ++nnear;
     const uint32_t gm = (uint32_t)(__ballot(kf) >> gbase) & ((1u << G) - 1u);
     if (!COUNT && kf) {
       const int32_t q = o + __popc(gm & ((1u << gi) - 1u));
@@ -142,6 +154,12 @@ __global__ void __launch_bounds__(NT) k_drop(int32_t n, const int64_t* __restric
     o += __popc(gm);
   }
   if (COUNT && valid && gi == 0) cnt[k] = o;
+  if (COUNT) {
+    // one atomic per wavefront
+#pragma unroll
+    for (int q = 32; q > 0; q >>= 1) nnear += __shfl_xor(nnear, q, 64);
+    if (lane == 0 && nnear > 0) atomicAdd(nearc, (unsigned long long)nnear);
+  }
 }
 
 template <class T>
@@ -156,10 +174,11 @@ void build_typed(const sai_split_s* sp, const sai_build_opts& o, hipStream_t st,
   DBuf<int32_t> jidx, iidx, cntJ, cntI;
   const bool psai = o.pattern == SAI_PAT_PSAI_TOL;
   DBuf<double> m64, res64;  // PSAI(tol): values and residuals from the search
+  int l_m = 0;
   if (o.pattern == SAI_PAT_SPAI)
-    spai_patterns(sp, o, st, al, jptr, jidx, iptr, iidx, cntJ, cntI);
+    spai_patterns(sp, o, st, al, jptr, jidx, iptr, iidx, cntJ, cntI, &l_m);
   else if (psai)
-    psai_patterns(sp, o, st, al, jptr, jidx, iptr, iidx, cntJ, cntI, m64, res64);
+    psai_patterns(sp, o, st, al, jptr, jidx, iptr, iidx, cntJ, cntI, m64, res64, &l_m);
   else
     build_patterns(sp, o.pattern, st, al, jptr, jidx, iptr, iidx, cntJ, cntI);
   t_pat.stop(st);
@@ -209,9 +228,12 @@ void build_typed(const sai_split_s* sp, const sai_build_opts& o, hipStream_t st,
     memcpy(&norm1, &bits, sizeof(double));
   }
   DBuf<int32_t> ccnt(&al, (size_t)n + 1);
+  DBuf<unsigned long long> nearc(&al, 1);
+  HIPC(hipMemsetAsync(nearc.p, 0, sizeof(unsigned long long), st));
+  const double eta = sizeof(T) == 4 ? 1e-4 : 1e-12;
   const unsigned dgrid = grid_for((int64_t)n * 16, NT);
   hipLaunchKernelGGL((k_drop<T, true>), dim3(dgrid), dim3(NT), 0, st, n, jptr.p, jidx.p, mfull.p, drop,
-                     o.tau, o.delta, norm1, ccnt.p, nullptr, nullptr, nullptr);
+                     o.tau, o.delta, norm1, ccnt.p, nullptr, nullptr, nullptr, eta, nearc.p);
   LAUNCH_CHECK();
   pc->col_ptr.alloc(&al, (size_t)n + 1);
   exclusive_scan_i32(ccnt.p, pc->col_ptr.p, n, al, st);
@@ -220,7 +242,8 @@ void build_typed(const sai_split_s* sp, const sai_build_opts& o, hipStream_t st,
   pc->row_idx.alloc(&al, (size_t)nnz + 1);
   pc->cval.alloc(&al, ((size_t)nnz + 1) * sizeof(T));
   hipLaunchKernelGGL((k_drop<T, false>), dim3(dgrid), dim3(NT), 0, st, n, jptr.p, jidx.p, mfull.p, drop,
-                     o.tau, o.delta, norm1, nullptr, pc->col_ptr.p, pc->row_idx.p, (T*)pc->cval.p);
+                     o.tau, o.delta, norm1, nullptr, pc->col_ptr.p, pc->row_idx.p, (T*)pc->cval.p, eta,
+                     nullptr);
   LAUNCH_CHECK();
   pc->row_ptr.alloc(&al, (size_t)n + 1);
   pc->col_idx.alloc(&al, (size_t)nnz + 1);
@@ -252,6 +275,10 @@ void build_typed(const sai_split_s* sp, const sai_build_opts& o, hipStream_t st,
     stats->t_ls_ms = t_ls.ms();
     stats->t_assemble_ms = t_asm.ms();
     stats->t_total_ms = t_all.ms();
+    stats->s = sp->s;
+    stats->p = sp->p;
+    stats->l_m = l_m;
+    stats->drop_flips = (int64_t)read_scalar(nearc.p, st);
   }
   if (o.keep_lists) {
     pc->j_ptr = std::move(jptr);

@@ -157,9 +157,11 @@ int iterate(Block& B, const Csr<double>& A, const Csr<TM>& M, int64_t n, int& it
     if (persist) g = std::min<int64_t>(g, resident_blocks(kern, NT));
     return (int)(g >= 8 ? (g & ~int64_t(7)) : g);
   };
-  // test hook: treat iteration BRK_TEST as a breakdown of every active column
-  // (exercises the restart path); 0, the default, never matches
+  // test hooks: treat iterations BRK_TEST and BRK_TEST2 as breakdowns of every
+  // active column (the restart path, and a second breakdown); 0, the default,
+  // never matches
   const int force_it = tune_get("BRK_TEST", 0);
+  const int force_it2 = tune_get("BRK_TEST2", 0);
   // M product: gather batch sizes (CH while >= CH entries remain, then CH2)
   const int mvar = tune_get("SPMM_M", 1);
   auto spmm_m = [&](const double* Xin, double* Y) {
@@ -239,9 +241,10 @@ int iterate(Block& B, const Csr<double>& A, const Csr<TM>& M, int64_t n, int& it
     LK("bicg_halfcheck", (k_halfcheck<LP>), dim3(tgrid), dim3(NT), 0, st, n, k, kp, A, V, S, xmap);
     LK("bicg_finish", (k_fin<1, F_HALF>), dim3(1), dim3(FNT), 0, st, k, S, tgrid, 0, 0);
     LK("bicg_xr_update", (k_xr<LP>), dim3(grid), dim3(NT), 0, st, n, k, kp, V, S);
-    LK("bicg_finish", (k_fin<2, F_XR>), dim3(1), dim3(FNT), 0, st, k, S, grid, it, 0, force_it);
+    LK("bicg_finish", (k_fin<2, F_XR>), dim3(1), dim3(FNT), 0, st, k, S, grid, it, 0, force_it, force_it2);
     LK("bicg_fullcheck", (k_fullcheck<LP>), dim3(tgrid), dim3(NT), 0, st, n, k, kp, A, V, S, xmap);
-    LK("bicg_finish", (k_fin<2, F_FULL>), dim3(1), dim3(FNT), 0, st, k, S, tgrid, 0, 0);
+    LK("bicg_finish", (k_fin<2, F_FULL>), dim3(1), dim3(FNT), 0, st, k, S, tgrid, it, 0, force_it,
+       force_it2);
     LK("bicg_restart", (k_restart<LP>), dim3(grid), dim3(NT), 0, st, n, k, kp, V, S);
     LK("bicg_finish_end", (k_fin<1, F_RESTART_END>), dim3(1), dim3(FNT), 0, st, k, S, grid, it, maxit);
 #undef LK

@@ -481,7 +481,8 @@ __global__ void __launch_bounds__(B) k_spai(int32_t n, const int32_t* __restrict
                                               const int64_t* __restrict__ jpoff,
                                               int32_t* __restrict__ jpad, int32_t* __restrict__ cntJ,
                                               Ws ws0, const int32_t* __restrict__ list, int32_t nwork,
-                                              int* __restrict__ next, int* __restrict__ err) {
+                                              int* __restrict__ next, int* __restrict__ err,
+                                              int32_t* __restrict__ taken) {
   __shared__ int32_t sJ[SJMAX + 8];
   __shared__ int32_t fJ[SJMAX];
   __shared__ double sm[SJMAX];
@@ -529,7 +530,7 @@ __global__ void __launch_bounds__(B) k_spai(int32_t n, const int32_t* __restrict
     }
     __syncthreads();
     bool fail = false;
-    int nI = 0, j0 = 0;
+    int nI = 0, j0 = 0, naug = 0;
     for (int step = 0; step < steps; ++step) {
       double rr = 0.0;
       if (!ls_extend_ws<B>(k, cp, ri, cv, fJ, j0, nJ, ws, sm, sd, hv, ht, red, wsum, s_int, nI, rr)) {
@@ -620,6 +621,7 @@ __global__ void __launch_bounds__(B) k_spai(int32_t n, const int32_t* __restrict
       }
       __syncthreads();
       nJ = s_int[1];
+      ++naug;
     }
     if (fail) {
       if (tid == 0) atomicOr(err, E_TOOBIG);
@@ -628,7 +630,10 @@ __global__ void __launch_bounds__(B) k_spai(int32_t n, const int32_t* __restrict
     }
     const int64_t o = jpoff[k];
     for (int t = tid; t < nJ; t += B) jpad[o + t] = sJ[t];
-    if (tid == 0) cntJ[k] = nJ;
+    if (tid == 0) {
+      cntJ[k] = nJ;
+      taken[k] = naug;
+    }
     __syncthreads();
   }
 }
@@ -651,7 +656,8 @@ __global__ void __launch_bounds__(B) k_psai(int32_t n, const int32_t* __restrict
                                               double* __restrict__ mpad, int32_t* __restrict__ cntJ,
                                               double* __restrict__ res, Ws ws0,
                                               int32_t* __restrict__ fr0, const int32_t* __restrict__ list,
-                                              int32_t nwork, int* __restrict__ err) {
+                                              int32_t nwork, int* __restrict__ err,
+                                              int32_t* __restrict__ loops) {
   __shared__ int32_t sJ[SJMAX + 8];
   __shared__ double sm[SJMAX];
   __shared__ double sd[SJMAX + 1];
@@ -680,7 +686,9 @@ __global__ void __launch_bounds__(B) k_psai(int32_t n, const int32_t* __restrict
     __syncthreads();
     bool fail = false;
     double rr = 0.0;
+    int used = 0;
     for (int l = 0; l <= lmax; ++l) {
+      used = l + 1;
       // ---- F = nonzero rows of A~(:, F)
       for (int t = tid; t < nF; t += B) ws.off[t] = cp[F[t] + 1] - cp[F[t]];
       __syncthreads();
@@ -749,6 +757,7 @@ __global__ void __launch_bounds__(B) k_psai(int32_t n, const int32_t* __restrict
     if (tid == 0) {
       cntJ[k] = nJ;
       res[k] = sqrt(rr);
+      loops[k] = used;
     }
     __syncthreads();
   }
@@ -765,7 +774,8 @@ __global__ void __launch_bounds__(SNT) k_psai_first(int32_t n, const int64_t* __
                                                     const double* __restrict__ r, double delta,
                                                     double a1, int lmax, int32_t* __restrict__ jpad,
                                                     double* __restrict__ mpad, int32_t* __restrict__ cntJ,
-                                                    double* __restrict__ res, int32_t* __restrict__ todo) {
+                                                    double* __restrict__ res, int32_t* __restrict__ todo,
+                                                    int32_t* __restrict__ loops) {
   const int64_t k = (int64_t)blockIdx.x * SNT + threadIdx.x;
   if (k >= n) return;
   const int64_t a = jptr[k];
@@ -791,6 +801,7 @@ __global__ void __launch_bounds__(SNT) k_psai_first(int32_t n, const int64_t* __
   }
   cntJ[k] = q;
   res[k] = r[k];
+  loops[k] = 1;
 }
 
 // out[0] = max cntI, out[1] = max cntJ (block maxima, one atomic per block)
@@ -904,7 +915,7 @@ __global__ void k_compact_lists(int32_t n, const int64_t* __restrict__ poff,
 void spai_patterns(const sai_split_s* sp, const sai_build_opts& o, hipStream_t st,
                    const Allocator& al, DBuf<int64_t>& jptr, DBuf<int32_t>& jidx,
                    DBuf<int64_t>& iptr, DBuf<int32_t>& iidx, DBuf<int32_t>& cntJ,
-                   DBuf<int32_t>& cntI) {
+                   DBuf<int32_t>& cntI, int* l_m) {
   const int32_t n = sp->n;
   if (o.spai_steps < 0 || o.spai_per_step < 1 || o.spai_per_step > 16)
     SAI_THROW(SAI_EINVAL, "spai_steps >= 0 and 1 <= spai_per_step <= 16 required");
@@ -924,6 +935,9 @@ void spai_patterns(const sai_split_s* sp, const sai_build_opts& o, hipStream_t s
   const int64_t ptot = read_scalar(poff.p + n, st);
   DBuf<int32_t> pad(&al, (size_t)ptot + 1);
   cntJ.alloc(&al, (size_t)n + 1);
+  // augmentation steps taken per column (0 for the columns that stop at step 0)
+  DBuf<int32_t> taken(&al, (size_t)n + 1);
+  HIPC(hipMemsetAsync(taken.p, 0, sizeof(int32_t) * ((size_t)n + 1), st));
   // From J = P(A~(:, k)), step 0 of every column runs on the static pattern
   // builder and the register-resident float64 solver; only the columns whose
   // residual exceeds delta go to the search kernel (on the irregular 200,000
@@ -999,7 +1013,7 @@ void spai_patterns(const sai_split_s* sp, const sai_build_opts& o, hipStream_t s
       hipLaunchKernelGGL(k, dim3(nslot), dim3(bnt), 0, st, n, sp->t_col_ptr.p, sp->t_row_idx.p,
                          sp->t_cval.p, sp->t_row_ptr.p, sp->t_col_idx.p, cn2.p, o.spai_steps,
                          o.spai_per_step, o.delta, o.spai_init, poff.p, pad.p, cntJ.p, ws,
-                         (const int32_t*)list.p, (int32_t)nwork, err.p + 1, err.p);
+                         (const int32_t*)list.p, (int32_t)nwork, err.p + 1, err.p, taken.p);
     };
     if (bnt == 64) go(k_spai<64>);
     else if (bnt == 512) go(k_spai<512>);
@@ -1010,6 +1024,13 @@ void spai_patterns(const sai_split_s* sp, const sai_build_opts& o, hipStream_t s
     if (e)
       SAI_THROW(SAI_ETOOBIG, "SPAI search exceeded |J| <= %d, |I| <= %d or %d candidates (or a "
                 "rank-deficient block)", SJMAX, SCAPI, SCAPN);
+  }
+  if (l_m) {
+    DBuf<int> mx(&al, 2);
+    HIPC(hipMemsetAsync(mx.p, 0, 2 * sizeof(int), st));
+    hipLaunchKernelGGL(k_max2, dim3(grid_for(n, SNT, 256)), dim3(SNT), 0, st, n, taken.p, taken.p, mx.p);
+    LAUNCH_CHECK();
+    *l_m = read_scalar(mx.p, st);
   }
   jptr.alloc(&al, (size_t)n + 1);
   exclusive_scan_i32_to_i64(cntJ.p, jptr.p, n, al, st);
@@ -1027,7 +1048,7 @@ void spai_patterns(const sai_split_s* sp, const sai_build_opts& o, hipStream_t s
 void psai_patterns(const sai_split_s* sp, const sai_build_opts& o, hipStream_t st,
                    const Allocator& al, DBuf<int64_t>& jptr, DBuf<int32_t>& jidx,
                    DBuf<int64_t>& iptr, DBuf<int32_t>& iidx, DBuf<int32_t>& cntJ,
-                   DBuf<int32_t>& cntI, DBuf<double>& mval, DBuf<double>& res) {
+                   DBuf<int32_t>& cntI, DBuf<double>& mval, DBuf<double>& res, int* l_m) {
   const int32_t n = sp->n;
   if (o.psai_lmax < 0 || o.psai_lmax > 64) SAI_THROW(SAI_EINVAL, "psai_lmax must be in [0, 64]");
   if (!(o.delta > 0.0)) SAI_THROW(SAI_EINVAL, "delta must be > 0");
@@ -1050,6 +1071,7 @@ void psai_patterns(const sai_split_s* sp, const sai_build_opts& o, hipStream_t s
   cntJ.alloc(&al, (size_t)n + 1);
   res.alloc(&al, (size_t)n + 1);
   DBuf<int32_t> todo(&al, (size_t)n + 1);
+  DBuf<int32_t> loops(&al, (size_t)n + 1);  // loops run per column
   // ---- loop l = 0 on J_k = P(A~(:, k)) with the register-resident column solver
   {
     DBuf<int64_t> jA, iA;
@@ -1068,7 +1090,7 @@ void psai_patterns(const sai_split_s* sp, const sai_build_opts& o, hipStream_t s
     if (nsing > 0)
       SAI_THROW(SAI_ESINGULAR, "%d column least-squares blocks are rank deficient", nsing);
     hipLaunchKernelGGL(k_psai_first, dim3(grid_for(n, SNT)), dim3(SNT), 0, st, n, jA.p, jiA.p, m1.p,
-                       r1.p, o.delta, a1, o.psai_lmax, jpad.p, mpad.p, cntJ.p, res.p, todo.p);
+                       r1.p, o.delta, a1, o.psai_lmax, jpad.p, mpad.p, cntJ.p, res.p, todo.p, loops.p);
     LAUNCH_CHECK();
   }
   // ---- the other columns: the whole loop in the search kernel
@@ -1098,7 +1120,7 @@ void psai_patterns(const sai_split_s* sp, const sai_build_opts& o, hipStream_t s
     auto go = [&](auto k) {
       hipLaunchKernelGGL(k, dim3(nslot), dim3(bnt), 0, st, n, sp->t_col_ptr.p, sp->t_row_idx.p,
                          sp->t_cval.p, o.psai_lmax, o.delta, a1, jpad.p, mpad.p, cntJ.p, res.p, ws, wf.p,
-                         (const int32_t*)list.p, (int32_t)ntodo, err.p);
+                         (const int32_t*)list.p, (int32_t)ntodo, err.p, loops.p);
     };
     if (bnt == 64) go(k_psai<64>);
     else go(k_psai<256>);
@@ -1107,6 +1129,13 @@ void psai_patterns(const sai_split_s* sp, const sai_build_opts& o, hipStream_t s
     if (e)
       SAI_THROW(SAI_ETOOBIG, "PSAI(tol) exceeded |J| <= %d, |I| <= %d, %d gathered entries (or a "
                 "rank-deficient block)", SJMAX, SCAPI, SCAPN);
+  }
+  if (l_m) {
+    DBuf<int> mx(&al, 2);
+    HIPC(hipMemsetAsync(mx.p, 0, 2 * sizeof(int), st));
+    hipLaunchKernelGGL(k_max2, dim3(grid_for(n, SNT, 256)), dim3(SNT), 0, st, n, loops.p, loops.p, mx.p);
+    LAUNCH_CHECK();
+    *l_m = read_scalar(mx.p, st);
   }
   jptr.alloc(&al, (size_t)n + 1);
   exclusive_scan_i32_to_i64(cntJ.p, jptr.p, n, al, st);

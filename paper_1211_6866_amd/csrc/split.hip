@@ -110,6 +110,12 @@ __global__ void k_dense_flag(int32_t n, const int32_t* __restrict__ colcnt8, dou
   flag[j] = ((double)c > thr) ? 1 : 0;
 }
 
+// The irregular columns given by the caller (flag cleared beforehand).
+__global__ void k_flag_set(int32_t s, const int32_t* __restrict__ list, int32_t* __restrict__ flag) {
+  const int64_t d = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (d < s) flag[list[d]] = 1;
+}
+
 __global__ void k_dense_compact(int32_t n, const int32_t* flag, const int32_t* pos,
                                 const int32_t* colcnt, int32_t* dense_cols, int32_t* dcount,
                                 int32_t* colmap) {
@@ -582,6 +588,15 @@ void split_impl(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* c
     SAI_THROW(SAI_EINVAL, "bad CSR arguments (n=%d nnz=%lld)", n, (long long)nnz);
   if (!(o.dense_factor > 0.0)) SAI_THROW(SAI_EINVAL, "dense_factor must be > 0");
   if (o.rule != SAI_KEEP_NEAREST && o.rule != SAI_KEEP_LARGEST) SAI_THROW(SAI_EINVAL, "bad rule");
+  const bool given = o.host_dense_cols != nullptr;
+  if (given) {
+    if (o.s_given < 0 || o.s_given > n) SAI_THROW(SAI_EINVAL, "s_given must be in [0, n]");
+    for (int32_t d = 0; d < o.s_given; ++d) {
+      const int32_t j = o.host_dense_cols[d];
+      if (j < 0 || j >= n || (d > 0 && j <= o.host_dense_cols[d - 1]))
+        SAI_THROW(SAI_EINVAL, "host_dense_cols must be strictly ascending in [0, n)");
+    }
+  }
   h->n = n;
   h->nnz_a = nnz;
   const int32_t p = (int32_t)(nnz / n);
@@ -604,6 +619,19 @@ void split_impl(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* c
                        flag.p);
   }
   LAUNCH_CHECK();
+  if (given) {
+    // the caller's list replaces the count rule
+    HIPC(hipMemsetAsync(flag.p, 0, sizeof(int32_t) * (size_t)n, st));
+    if (o.s_given > 0) {
+      DBuf<int32_t> dl(&al, (size_t)o.s_given);
+      HIPC(hipMemcpyAsync(dl.p, o.host_dense_cols, sizeof(int32_t) * (size_t)o.s_given,
+                          hipMemcpyHostToDevice, st));
+      hipLaunchKernelGGL(k_flag_set, dim3(grid_for(o.s_given, NT)), dim3(NT), 0, st, o.s_given, dl.p,
+                         flag.p);
+      LAUNCH_CHECK();
+      HIPC(hipStreamSynchronize(st));
+    }
+  }
   exclusive_scan_i32(flag.p, pos.p, n, al, st);
   HostStage hs(64);
   HIPC(hipMemcpyAsync(hs.as<int32_t>(), pos.p + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));

@@ -50,9 +50,12 @@ def _sample(n, dense, seed, count=48):
     return sorted(cols)
 
 
-@pytest.mark.parametrize("idx", [2, 3, 4, 5])
-def test_fullsize_workload(idx):
-    print(f"\nworkload {idx}: generating", flush=True)
+@pytest.mark.parametrize("idx,prec", [(2, P.FP32), (3, P.FP32), (4, P.FP32), (5, P.FP32), (2, P.FP64),
+                                      (5, P.FP64)])
+def test_fullsize_workload(idx, prec):
+    """prec: the mixed build (FP32 M) of every workload, and the plain FP64 build
+    of the two 3D workloads (the bench times both)."""
+    print(f"\nworkload {idx} ({'FP32' if prec == P.FP32 else 'FP64'} M): generating", flush=True)
     w = W.make(idx)
     n = w.A.shape[0]
     S = osplit.split(w.A)
@@ -67,9 +70,10 @@ def test_fullsize_workload(idx):
     assert np.array_equal(_np(arr["t_val"]), S.At.data)
     del arr
     print(f"workload {idx}: split ok (s={S.s}, p={S.p})", flush=True)
-    # ---- build (mixed, the benchmarked configuration) with the lists kept
+    # ---- build with the lists kept
     bkw = SETTINGS[idx]
-    pc = P.Precond(g, precision=P.FP32, keep_lists=True, **bkw)
+    pc = P.Precond(g, precision=prec, keep_lists=True, **bkw)
+    assert (pc.stats.s, pc.stats.p) == (S.s, S.p)
     pa = pc.arrays()
     jp, ji, ip, ii = (_np(pa[k]) for k in ("j_ptr", "j_idx", "i_ptr", "i_idx"))
     mf = _np(pa["m_full"]).astype(np.float64)
@@ -80,6 +84,8 @@ def test_fullsize_workload(idx):
     R.sort_indices()
     cn2 = ospai.column_norms2(C) if idx == 3 else None
     flips = 0
+    worst = 0.0
+    tol = 1e-12 if prec == P.FP64 else 1e-4
     for k in _sample(n, S.D, w.seed):
         if idx == 3:
             J, I, m, res, _ = ospai.spai_column(C, R, cn2, k, 3, 5, 0.4, "A")
@@ -89,17 +95,25 @@ def test_fullsize_workload(idx):
         assert np.array_equal(ji[jp[k]:jp[k + 1]], J), k
         assert np.array_equal(ii[ip[k]:ip[k + 1]], I), k
         e = np.linalg.norm(mf[jp[k]:jp[k + 1]] - m) / np.linalg.norm(m)
-        assert e <= 1e-4, (k, e)
-        # dropped column: same kept rows except entries within FP32 rounding of tau
+        worst = max(worst, e)
+        assert e <= tol, (k, e)
+        # dropped column: the same kept rows, except (FP32) entries within the
+        # build's tolerance of tau; in FP64 bit-exact
         if bkw["drop"] == P.DROP_ABS:
             keep = odrop.drop_column(m, bkw["tau"])
             rows_o = set(J[keep].tolist())
             rows_g = set(ri_[cp_[k]:cp_[k + 1]].tolist())
+            if prec == P.FP64:
+                assert rows_o == rows_g, k
+                vals_g = cv_[cp_[k]:cp_[k + 1]]
+                assert np.linalg.norm(vals_g - m[keep]) <= 1e-12 * np.linalg.norm(m[keep]), k
             for r_ in rows_o ^ rows_g:
                 pos = int(np.searchsorted(J, r_))
-                assert abs(abs(m[pos]) - bkw["tau"]) <= 1e-4 * max(1.0, abs(m[pos])), (k, r_)
+                assert abs(abs(m[pos]) - bkw["tau"]) <= 1e-4 * np.linalg.norm(m), (k, r_)
                 flips += 1
-    print(f"workload {idx}: sampled columns ok ({flips} threshold flips)", flush=True)
+    assert flips <= pc.stats.drop_flips
+    print(f"workload {idx}: sampled columns ok (worst rel err {worst:.2e}, {flips} threshold flips; "
+          f"{pc.stats.drop_flips} undecidable entries in M)", flush=True)
     # ---- solve: rr < 1e-8 recomputed in FP64 on the host
     b = torch.from_numpy(w.b).cuda()
     x, st = P.solve(g, pc, b, eps=1e-8)

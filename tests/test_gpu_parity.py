@@ -146,6 +146,7 @@ def test_psai_tol_vs_oracle(name, delta, lmax, prec):
     jp, ji = _np(arr["j_ptr"]), _np(arr["j_idx"])
     mf, res = _np(arr["m_full"]).astype(np.float64), _np(arr["res"])
     Ss, ms, rs, ls = opsai.psai_tol(S.At, delta=delta, lmax=lmax)
+    assert pc.stats.l_m == int(np.max(ls)), (pc.stats.l_m, int(np.max(ls)))
     tol = 1e-12 if prec == P.FP64 else 1e-7
     worst = 0.0
     for k in range(n):
@@ -229,6 +230,7 @@ def test_spai_patterns_and_columns(delta, init, prec):
                      init="A" if init == P.INIT_PATTERN_A else "diag")
     tol = 1e-12 if prec == P.FP64 else 1e-4
     augmented = 0
+    assert pc.stats.l_m == max(o[4] for o in out), (pc.stats.l_m, max(o[4] for o in out))
     for k in range(n):
         J, I, m, res, taken = out[k]
         augmented += taken > 0
@@ -257,13 +259,30 @@ def test_drop_and_assembly(drop, prec):
     Mo = odrop.assemble(n, Js, ms, mode, tau=2e-3, delta=0.4, At=S.At)
     Mg = sp.csc_matrix((_np(arr["cval"]).astype(np.float64), _np(arr["row_idx"]),
                         _np(arr["col_ptr"])), shape=(n, n))
+    flips = 0
     if prec == P.FP64:
         assert np.array_equal(Mg.indptr, Mo.indptr) and np.array_equal(Mg.indices, Mo.indices)
         assert abs(Mg - Mo).max() <= 1e-12 * abs(Mo).max()
     else:
-        # entries within FP32 rounding of the threshold may flip; count them
+        # entries within the FP32 build's tolerance of the threshold may flip: at
+        # most the number the library reports as undecidable
         flips = abs((Mg != 0).astype(int) - (Mo != 0).astype(int)).sum()
-        assert flips <= max(2, int(1e-4 * Mo.nnz)), flips
+        assert flips <= pc.stats.drop_flips, (flips, pc.stats.drop_flips)
+    # the same count from the oracle's columns (FP64: the same entries)
+    a1 = odrop.norm1(opat.as_csc(S.At))
+    eta = 1e-4 if prec == P.FP32 else 1e-12
+    near = 0
+    for k in range(n):
+        m = ms[k]
+        tk = 2e-3 if drop == P.DROP_ABS else 0.4 / (len(m) * a1)
+        big = int(np.argmax(np.abs(m)))
+        band = eta * np.linalg.norm(m) / (1.0 - eta)
+        near += sum(1 for q in range(len(m)) if q != big and abs(abs(m[q]) - tk) <= band)
+    print(f"undecidable entries: library {pc.stats.drop_flips}, oracle {near}, flips seen "
+          f"{flips if prec == P.FP32 else 0}")
+    if prec == P.FP64:
+        assert pc.stats.drop_flips == near
+    assert (pc.stats.s, pc.stats.p) == (S.s, S.p)
     # CSR is the transpose of the CSC, bit for bit
     Mr = sp.csr_matrix((_np(arr["val"]).astype(np.float64), _np(arr["col_idx"]), _np(arr["row_ptr"])),
                        shape=(n, n))
@@ -271,29 +290,70 @@ def test_drop_and_assembly(drop, prec):
     assert (Mr != sp.csr_matrix(Mg)).nnz == 0
 
 
-@pytest.mark.parametrize("name,method", [("c1", P.GMRES), ("c1", P.BICGSTAB), ("c2_12", P.BICGSTAB),
-                                         ("c2_13x9x7", P.BICGSTAB), ("c4_40", P.BICGSTAB),
-                                         ("c3_3000", P.BICGSTAB)])
-def test_solve_end_to_end(name, method):
+_SIGMA_MIN = {}
+
+
+def _sigma_min(name, A):
+    """Smallest singular value of A (dense SVD, n <= 3000), cached per case."""
+    if name not in _SIGMA_MIN:
+        _SIGMA_MIN[name] = float(np.linalg.svd(A.toarray(), compute_uv=False)[-1])
+    return _SIGMA_MIN[name]
+
+
+def _forward_bound(name, A, b, x1, x2):
+    """||x1 - x2|| <= ||A^{-1}|| (||b - A x1|| + ||b - A x2||): both residuals are
+    recomputed here in float64, ||A^{-1}||_2 = 1 / sigma_min from a dense SVD."""
+    return (np.linalg.norm(b - A @ x1) + np.linalg.norm(b - A @ x2)) / _sigma_min(name, A)
+
+
+SOLVE_CASES = [("c1", P.GMRES), ("c1", P.BICGSTAB), ("c2_12", P.BICGSTAB), ("c2_13x9x7", P.BICGSTAB),
+               ("c4_40", P.BICGSTAB), ("c3_3000", P.BICGSTAB)]
+
+
+def _solve_both(name, method, c_mode):
     w, (rp, ci, va) = _load(name)
     b = torch.from_numpy(w.b).cuda()
     g = P.Split(rp, ci, va)
     kind = P.PAT_A if name in ("c1", "c3_3000") else P.PAT_A2
     drop = P.DROP_NONE if kind == P.PAT_A else P.DROP_ABS
     pc = P.Precond(g, pattern=kind, drop=drop, tau=1e-3, precision=P.FP32)
-    x, st = P.solve(g, pc, b, method=method, restart=30, eps=1e-8)
-    xs = _np(x)
-    rr = np.linalg.norm(w.b - w.A @ xs) / np.linalg.norm(w.b)
-    assert rr < 1e-8 * 1.5, (rr, st)          # c = 1 may leave rr slightly above eps
-    assert abs(rr - st["rr"]) <= 1e-3 * rr + 1e-15
-    xd = sp.linalg.spsolve(sp.csc_matrix(w.A), w.b)
-    kest = 1e4
-    assert np.linalg.norm(xs - xd) <= 2 * kest * 1e-8 * np.linalg.norm(xd)
-    # the s+1 columns each met their own stopping rule (true residuals)
+    x, st = P.solve(g, pc, b, method=method, restart=30, eps=1e-8, c_mode=c_mode)
     out = opipe.run(w.A, w.b, kind="A" if kind == P.PAT_A else "A2",
                     drop="none" if drop == P.DROP_NONE else "abs",
                     method="gmres" if method == P.GMRES else "bicgstab")
-    print(name, "gpu iters", st["iters"], "oracle iters", out["iters"], "rr", rr, out["rr"])
+    return w, _np(x), st, out
+
+
+@pytest.mark.parametrize("name,method", SOLVE_CASES)
+def test_solve_c_one_vs_oracle(name, method):
+    """The paper's setting, c = 1 in (stopU2): the theorem then bounds the final
+    residual by (eps/2)(1 + c) (b - A x = r_y - R_W z, ||R_W z|| < eps ||b|| c / 2),
+    which exceeds eps when c > 1.  x is compared with the oracle's x through
+    ||A^{-1}|| times the sum of both true residuals."""
+    w, xs, st, out = _solve_both(name, method, P.C_ONE)
+    rr = np.linalg.norm(w.b - w.A @ xs) / np.linalg.norm(w.b)
+    c = st["c"]
+    assert rr < 1e-8 * (1.0 + c) / 2.0 * (1.0 + 1e-6), (rr, c, st)
+    assert abs(rr - st["rr"]) <= 1e-3 * rr + 1e-15
+    err = np.linalg.norm(xs - out["x"])
+    bound = _forward_bound(name, w.A, w.b, xs, out["x"])
+    assert err <= bound, (err, bound)
+    print(f"{name}: gpu iters {st['iters']} oracle iters {out['iters']} rr {rr:.2e} / {out['rr']:.2e}, "
+          f"|x - x_oracle| / |x_oracle| {err / np.linalg.norm(out['x']):.2e} "
+          f"(bound {bound / np.linalg.norm(out['x']):.2e})")
+
+
+@pytest.mark.parametrize("name,method", SOLVE_CASES)
+def test_solve_refined_strict(name, method):
+    """SAI_C_ONE_THEN_REFINE: the auxiliary solves are continued to the theorem's
+    thresholds with the computed c, so rr < 1e-8 strictly, recomputed on the
+    host; x against the oracle's as above."""
+    w, xs, st, out = _solve_both(name, method, P.C_ONE_THEN_REFINE)
+    rr = np.linalg.norm(w.b - w.A @ xs) / np.linalg.norm(w.b)
+    assert st["status"] == P.OK and rr < 1e-8, (rr, st)
+    err = np.linalg.norm(xs - out["x"])
+    bound = _forward_bound(name, w.A, w.b, xs, out["x"])
+    assert err <= bound, (err, bound)
 
 
 def test_krylov_block_and_smw_vs_oracle():
@@ -360,7 +420,8 @@ def test_autograd_function():
     xd = np.linalg.solve(Ad, w.b)
     lam = np.linalg.solve(Ad.T, xd - _np(xs))
     assert np.linalg.norm(_np(b.grad) - lam) <= 1e-5 * np.linalg.norm(lam)
-    assert np.linalg.norm(_np(a.grad) - oadj.grad_A_values(w.A, lam, xd)) <= 1e-5 * np.linalg.norm(lam) * np.linalg.norm(xd)
+    Gd = oadj.grad_A_values(w.A, lam, xd)
+    assert np.linalg.norm(_np(a.grad) - Gd) <= 1e-5 * np.linalg.norm(Gd)
 
 
 def test_error_paths():
@@ -537,27 +598,159 @@ def test_adaptive_builds_bit_identical(kind):
         assert np.array_equal(u, v)
 
 
+def _oracle_rhs_and_M(w, S):
+    """[b, U] and the oracle's FP64 M (P(|A~|^2), tau = 1e-3) for the workload."""
+    n, s = w.A.shape[0], S.s
+    R = np.zeros((n, s + 1))
+    R[:, 0] = w.b
+    R[:, 1:] = S.U.toarray()
+    Mo, _ = opipe.build_M(S, "A2", "abs", 1e-3)
+    return R, sp.csr_matrix(Mo)
+
+
 @pytest.mark.parametrize("at", [1, 5])
 def test_bicgstab_forced_restart(at):
-    """The breakdown restart (r_hat = r, p = v = 0, one per column), forced from
-    the host at iteration `at` for every active column of a well-conditioned
-    system: the solve still reaches rr < 1e-8 and agrees with the unforced one."""
+    """The breakdown restart (r_hat = r, p = v = 0), forced at the end of
+    iteration `at` for every active column, against the oracle restarted at the
+    same iteration (same FP64 M up to 1e-12): iteration counts equal (one
+    apart at most, for a column that meets its threshold within rounding), and
+    every column within ||A~^{-1}|| (sum of the two true residuals) of the
+    oracle's."""
     w, (rp, ci, va) = _load("c2_12")
-    b = torch.from_numpy(w.b).cuda()
+    S = osplit.split(w.A)
     g = P.Split(rp, ci, va)
-    pc = P.Precond(g, pattern=P.PAT_A2, drop=P.DROP_ABS, tau=1e-3, precision=P.FP32)
-    x0, st0 = P.solve(g, pc, b, method=P.BICGSTAB, eps=1e-8)
+    pc = P.Precond(g, pattern=P.PAT_A2, drop=P.DROP_ABS, tau=1e-3, precision=P.FP64)
+    R, Mo = _oracle_rhs_and_M(w, S)
+    thr = okry.thresholds(np.linalg.norm(w.b), S.s, 1e-10)
     try:
         P.tune_set("BRK_TEST", at)
-        x1, st1 = P.solve(g, pc, b, method=P.BICGSTAB, eps=1e-8)
+        X, its, sts, code = P.krylov(g, pc, torch.from_numpy(R).cuda(), thr)
     finally:
         P.tune_set("BRK_TEST", 0)
-    x0, x1 = _np(x0), _np(x1)
-    rr = np.linalg.norm(w.b - w.A @ x1) / np.linalg.norm(w.b)
-    assert st1["status"] == P.OK and rr < 1.5e-8, (st1, rr)
-    assert st1["iters"] != st0["iters"], (st0["iters"], st1["iters"])
-    assert np.linalg.norm(x1 - x0) <= 1e-6 * np.linalg.norm(x0)
-    print(f"restart at {at}: iterations {st0['iters']} -> {st1['iters']}, rr {rr:.2e}")
+    assert code == P.OK and all(v == 0 for v in sts), (its, sts)
+    At = sp.csr_matrix(S.At)
+    Xo, itso, stso = okry.solve_block(At, Mo, R, thr, force_restart_at=[at])
+    assert all(v == "converged" for v in stso)
+    Xh = _np(X)
+    smin = float(np.linalg.svd(S.At.toarray(), compute_uv=False)[-1])
+    for c in range(S.s + 1):
+        assert abs(its[c] - itso[c]) <= 1, (c, its, itso)
+        rg = np.linalg.norm(R[:, c] - At @ Xh[:, c])
+        ro = np.linalg.norm(R[:, c] - At @ Xo[:, c])
+        assert rg < thr[c]
+        assert np.linalg.norm(Xh[:, c] - Xo[:, c]) <= (rg + ro) / smin, c
+    print(f"restart at {at}: gpu iterations {its}, oracle {itso}")
+
+
+def test_bicgstab_second_breakdown_vs_oracle():
+    """Two forced breakdowns (iterations 3 and 6): every column still active at
+    iteration 6 ends with status breakdown, sai_krylov returns SAI_EBREAKDOWN and
+    the iterates it wrote equal the oracle's at that point (same FP64 M)."""
+    w, (rp, ci, va) = _load("c2_12")
+    S = osplit.split(w.A)
+    g = P.Split(rp, ci, va)
+    pc = P.Precond(g, pattern=P.PAT_A2, drop=P.DROP_ABS, tau=1e-3, precision=P.FP64)
+    R, Mo = _oracle_rhs_and_M(w, S)
+    thr = okry.thresholds(np.linalg.norm(w.b), S.s, 1e-10)
+    try:
+        P.tune_set("BRK_TEST", 3)
+        P.tune_set("BRK_TEST2", 6)
+        X, its, sts, code = P.krylov(g, pc, torch.from_numpy(R).cuda(), thr)
+        x, st = P.solve(g, pc, torch.from_numpy(w.b).cuda(), eps=1e-10, raise_on_error=False)
+    finally:
+        P.tune_set("BRK_TEST", 0)
+        P.tune_set("BRK_TEST2", 0)
+    Xo, itso, stso = okry.solve_block(sp.csr_matrix(S.At), Mo, R, thr, force_restart_at=[3, 6])
+    assert code == P.EBREAKDOWN and st["code"] == P.EBREAKDOWN and st["status"] == P.EBREAKDOWN
+    assert all(v == "breakdown" for v in stso) and all(v == 2 for v in sts), (sts, stso)
+    assert list(its) == list(itso) == [6] * (S.s + 1), (its, itso)
+    Xh = _np(X)
+    for c in range(S.s + 1):
+        assert np.linalg.norm(Xh[:, c] - Xo[:, c]) <= 1e-9 * np.linalg.norm(Xo[:, c]), c
+    assert np.isfinite(_np(x)).all()
+
+
+def _csr_from_dense(D):
+    return _csr32(sp.csr_matrix(np.asarray(D, dtype=np.float64)))
+
+
+def test_singular_K_from_singular_A():
+    """A singular, A~ nonsingular: by Theorem 3.1, K = I + V^T W is singular.
+    A~ = 2I plus a_01 = 1, one irregular column 0 (13 entries > 10p, p = 1,
+    keep = 1) with a_10 = 4: then M = A~^{-1} exactly, the auxiliary solve is
+    exact (one half step, alpha = 1), w_0 = -1 and K = 1 + w_0 = 0.  The GPU
+    solve returns SAI_ESINGULAR; the oracle's recovery raises."""
+    n = 40
+    D = 2.0 * np.eye(n)
+    D[0, 1] = 1.0
+    D[1, 0] = 4.0
+    for i in range(2, 13):
+        D[i, 0] = 0.5 * i
+    A = _csr_from_dense(D)
+    assert abs(np.linalg.det(D)) < 1e-9
+    b = A @ np.ones(n)
+    g = P.Split(*P.csr_to_device(A))
+    assert g.s == 1
+    for prec in (P.FP64, P.FP32):
+        pc = P.Precond(g, pattern=P.PAT_A, drop=P.DROP_NONE, precision=prec)
+        with pytest.raises(P.SaiError) as e:
+            P.solve(g, pc, torch.from_numpy(b).cuda(), eps=1e-8)
+        assert e.value.code == P.ESINGULAR
+    with pytest.raises(osmw.SingularK):
+        opipe.run(A, b, kind="A", drop="none")
+
+
+def test_rank_deficient_column_block():
+    """A column block without full column rank: columns 3 and 4 of A~ each have
+    one entry, in row 3 (values 2 and 4), and column 10 holds rows 3, 4, 10, so
+    A~(I_10, J_10) with J_10 = P(A~(:, 10)) = {3, 4, 10} has rank 2.  The build
+    returns SAI_ESINGULAR in both precisions; the oracle's triangular solve
+    raises."""
+    import scipy.linalg as sla
+    n = 20
+    D = 2.0 * np.eye(n)
+    D[4, 4] = 0.0
+    D[3, 4] = 4.0
+    D[3, 10] = 1.0
+    D[4, 10] = -1.0
+    A = _csr_from_dense(D)
+    g = P.Split(*P.csr_to_device(A))
+    assert g.s == 0
+    for prec in (P.FP64, P.FP32):
+        with pytest.raises(P.SaiError) as e:
+            P.Precond(g, pattern=P.PAT_A, drop=P.DROP_NONE, precision=prec)
+        assert e.value.code == P.ESINGULAR
+    C = opat.as_csc(osplit.split(A).At)
+    assert list(opat.pattern_A(C, 10)) == [3, 4, 10]
+    with pytest.raises(sla.LinAlgError):
+        olsq.solve_column(C, opat.pattern_A(C, 10), 10)
+
+
+def test_split_dense_cols_override():
+    """host_dense_cols / s_given replace the count rule: the oracle's split with
+    the same irregular columns (forced through a dense factor that selects
+    exactly them) is reproduced bit for bit; s_given = 0 gives A~ = A; a bad
+    list is rejected."""
+    w, (rp, ci, va) = _load("c2_12")
+    S = osplit.split(w.A)
+    # the largest columns of the oracle's list, plus a regular one
+    counts = np.diff(sp.csc_matrix(w.A).indptr)
+    extra = int(np.argmax(np.where(np.isin(np.arange(len(counts)), S.D), -1, counts)))
+    cols = sorted([int(S.D[0]), int(S.D[-1]), extra])
+    g = P.Split(rp, ci, va, dense_cols=cols)
+    arr = g.arrays()
+    assert g.s == 3 and list(_np(arr["dense_cols"])) == cols
+    # expected: the oracle split rule applied to exactly these columns
+    So = osplit.split(w.A, dense_cols=cols)
+    assert np.array_equal(_np(arr["t_col_idx"]), So.At.indices)
+    assert np.array_equal(_np(arr["t_val"]), So.At.data)
+    assert np.array_equal(_np(arr["t_row_ptr"]), So.At.indptr)
+    g0 = P.Split(rp, ci, va, dense_cols=[])
+    assert g0.s == 0 and g0.info.nnz_t == w.A.nnz
+    for bad in ([5, 3], [1, 1], [-1], [w.A.shape[0]]):
+        with pytest.raises(P.SaiError) as e:
+            P.Split(rp, ci, va, dense_cols=bad)
+        assert e.value.code == P.EINVAL
 
 
 @pytest.mark.parametrize("init", [P.INIT_PATTERN_A, P.INIT_DIAG])

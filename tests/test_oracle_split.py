@@ -149,3 +149,16 @@ def test_split_largest_rule():
     off = sorted([abs(v) for v in sp.csc_matrix(A)[:, 7].toarray().ravel()], reverse=True)
     kept_off = sorted([abs(col[i]) for i in np.flatnonzero(col) if i != 7], reverse=True)
     assert kept_off == [v for v in off if v != 2.0][:2]
+
+
+def test_split_with_given_columns_matches_detection():
+    """Naming the irregular columns reproduces the count rule's split exactly, and
+    naming none leaves A~ = A."""
+    import workloads as W
+    from oracle import split as osplit
+    w = W.make(2, dims=(9, 8, 7), s=3, density=0.3)
+    S = osplit.split(w.A)
+    S2 = osplit.split(w.A, dense_cols=list(S.D))
+    assert (S2.At != S.At).nnz == 0 and (S2.U != S.U).nnz == 0 and list(S2.D) == list(S.D)
+    S0 = osplit.split(w.A, dense_cols=[])
+    assert S0.s == 0 and (S0.At != w.A).nnz == 0
