@@ -250,6 +250,17 @@ int sai_krylov(const sai_split_t* sp, const sai_precond_t* pc, int32_t transpose
 int sai_smw(const sai_split_t* sp, const double* Y, double* x, double* c /* host */,
             void* stream);
 
+/* sai_smw for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * recovery and results as sai_smw, with no hipMalloc, hipFree or allocating
+ * library call.  Its workspace (K, z and the pivot flag, 33,536 bytes) is a
+ * file-scope device array that each GPU holds until the process ends; every
+ * call on one GPU shares it, so calls that overlap on one GPU race.  Arguments
+ * as for sai_smw (Y, x device; c host, may be NULL).  Errors: SAI_ETOOBIG for
+ * s > 64, SAI_ESINGULAR for a zero pivot, SAI_EINVAL for a NULL argument. */
+int sai_smw_noalloc(const sai_split_t* sp, const double* Y, double* x, double* c /* host */,
+                    void* stream);
+
 /* rr = ||b - A x|| / ||b|| with A = A~ + U V^T (rrnorm), in float64. */
 int sai_residual(const sai_split_t* sp, const double* b, const double* x,
                  double* rr /* host */, void* stream);

@@ -96,6 +96,9 @@ class SolveStats(C.Structure):
 
 _lib = None
 _alloc_struct = None
+# number of device allocations the library has requested through the binding's
+# allocator (for tests of the allocation-free entry point)
+ALLOC_CALLS = [0]
 
 
 def _torch():
@@ -124,6 +127,7 @@ def lib():
     L.sai_krylov.argtypes = [vp, vp, i32, i32, vp, vp, dp, C.POINTER(SolveOpts), vp,
                              C.POINTER(i32), C.POINTER(i32)]
     L.sai_smw.argtypes = [vp, vp, vp, dp, vp]
+    L.sai_smw_noalloc.argtypes = [vp, vp, vp, dp, vp]
     L.sai_residual.argtypes = [vp, vp, vp, dp, vp]
     L.sai_solve.argtypes = [vp, vp, vp, vp, C.POINTER(SolveOpts), vp, C.POINTER(SolveStats)]
     L.sai_backward.argtypes = [vp, vp, vp, vp, vp, vp, C.POINTER(SolveOpts), vp,
@@ -143,6 +147,7 @@ def lib():
     torch = _torch()
 
     def _alloc(ctx, nbytes, stream):
+        ALLOC_CALLS[0] += 1
         try:
             return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
         except Exception:  # noqa: BLE001 - reported to the library as NULL
@@ -352,6 +357,13 @@ def smw(split: Split, Y):
     c = C.c_double()
     _check(lib().sai_smw(split.h, _ptr(Y), _ptr(x), C.byref(c), _stream()), "sai_smw")
     return x, c.value
+
+
+def smw_noalloc(split: Split, Y, x):
+    """sai_smw_noalloc into the caller's x (the library allocates nothing); returns c."""
+    c = C.c_double()
+    _check(lib().sai_smw_noalloc(split.h, _ptr(Y), _ptr(x), C.byref(c), _stream()), "sai_smw_noalloc")
+    return c.value
 
 
 def residual(split: Split, b, x) -> float:

@@ -131,6 +131,11 @@ int sai_smw(const sai_split_t* sp, const double* Y, double* x, double* c, void* 
   return guarded([&] { sai::smw_recover(sp, Y, x, c, (hipStream_t)stream); });
 }
 
+int sai_smw_noalloc(const sai_split_t* sp, const double* Y, double* x, double* c, void* stream) {
+  if (!sp || !Y || !x) return SAI_EINVAL;
+  return guarded([&] { sai::smw_recover_noalloc(sp, Y, x, c, (hipStream_t)stream); });
+}
+
 int sai_residual(const sai_split_t* sp, const double* b, const double* x, double* rr, void* stream) {
   if (!sp || !b || !x || !rr) return SAI_EINVAL;
   return guarded([&] { *rr = sai::residual_impl(sp, b, x, (hipStream_t)stream); });

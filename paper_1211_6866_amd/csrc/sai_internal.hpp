@@ -286,6 +286,11 @@ int krylov_impl(const sai_split_s* sp, const sai_precond_s* pc, int transpose, i
                 const double* R, double* X, const double* thr, const sai_solve_opts& o,
                 hipStream_t st, int32_t* iters, int32_t* status);
 // K z = rhs with K = I + G (s x s row-major, device), solves in float64 on device.
+// smw_recover without any allocation: K, z and the pivot flag in the file-scope
+// scratch array of smw.hip (s <= SMW_NOALLOC_SMAX).
+constexpr int SMW_NOALLOC_SMAX = 64;
+void smw_recover_noalloc(const sai_split_s* sp, const double* Y, double* x, double* c_host,
+                         hipStream_t st);
 void smw_recover(const sai_split_s* sp, const double* Y, double* x, double* c_host,
                  hipStream_t st);
 double residual_impl(const sai_split_s* sp, const double* b, const double* x, hipStream_t st);
@@ -302,5 +307,8 @@ double dev_norm2(const double* v, int64_t n, int64_t stride, const Allocator& al
 // and rhs (s) are overwritten; the solution is left in rhs.  nrhs columns in
 // rhs (row-major s x nrhs).  Returns false if a zero pivot is met.
 bool dense_lu_solve(double* K, double* rhs, int s, int nrhs, const Allocator& al, hipStream_t st);
+// The same LU kernel on caller-provided memory; *fail (device) must be zero
+// before the launch and is set on a zero pivot.  No allocation.
+void launch_dense_lu(double* K, double* rhs, int s, int nrhs, int* fail, hipStream_t st);
 
 }  // namespace sai

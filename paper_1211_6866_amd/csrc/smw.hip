@@ -10,6 +10,9 @@
 // dL/dA_ij = -lambda_i x_j.
 #include "sai_internal.hpp"
 
+#include <map>
+#include <mutex>
+
 namespace sai {
 namespace {
 
@@ -234,6 +237,79 @@ void smw_recover(const sai_split_s* sp, const double* Y, double* x, double* c_ho
     HIPC(hipStreamSynchronize(st));
     double a = 0.0;
     for (double v : hz) a += v * v;
+    *c_host = std::sqrt(a);
+  }
+  HIPC(hipStreamSynchronize(st));
+}
+
+// ---- SMW recovery without allocation -------------------------------------------
+// For callers that cannot allocate device memory: K (s x s), z (s) and the LU
+// pivot flag live in this file-scope array (one copy per GPU, held until the
+// process ends).  Every call on a GPU uses that GPU's copy, so calls that
+// overlap on one GPU race; each call clears the flag it reads and overwrites
+// K and z before reading them.
+constexpr size_t SMW_SCR_K = (size_t)SMW_NOALLOC_SMAX * SMW_NOALLOC_SMAX;  // doubles
+constexpr size_t SMW_SCR_Z = SMW_SCR_K;                                        // offset of z
+constexpr size_t SMW_SCR_FLAG = SMW_SCR_K + SMW_NOALLOC_SMAX;                  // offset of the flag
+constexpr size_t SMW_SCR_DOUBLES = SMW_SCR_FLAG + 32;                         // 33,536 bytes
+static __device__ __align__(256) double scratch[SMW_SCR_DOUBLES];
+
+namespace {
+// device address of `scratch` per device, resolved once per device with that
+// device current (the host-side name is not a device address)
+std::mutex scr_mu;
+std::map<int, double*> scr_ptr;
+
+double* scratch_ptr() {
+  int dev = 0;
+  HIPC(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(scr_mu);
+  auto it = scr_ptr.find(dev);
+  if (it != scr_ptr.end()) return it->second;
+  double* p = nullptr;
+  HIPC(hipGetSymbolAddress((void**)&p, HIP_SYMBOL(scratch)));
+  if (!p) SAI_THROW(SAI_EHIP, "no device address for the SMW scratch array");
+  scr_ptr[dev] = p;
+  return p;
+}
+}  // namespace
+
+void smw_recover_noalloc(const sai_split_s* sp, const double* Y, double* x, double* c_host,
+                         hipStream_t st) {
+  const int s = sp->s, kk = s + 1;
+  const int64_t n = sp->n;
+  if (s > SMW_NOALLOC_SMAX)
+    SAI_THROW(SAI_ETOOBIG, "s = %d exceeds %d, the limit of the allocation-free SMW recovery", s,
+              SMW_NOALLOC_SMAX);
+  if (s == 0) {
+    hipLaunchKernelGGL(k_smw_apply, dim3(rows_grid(n)), dim3(NT), 0, st, n, 0, 1, Y,
+                       (const double*)nullptr, x);
+    LAUNCH_CHECK();
+    if (c_host) *c_host = 0.0;
+    HIPC(hipStreamSynchronize(st));
+    return;
+  }
+  double* base = scratch_ptr();
+  double* K = base;
+  double* z = base + SMW_SCR_Z;
+  int* fail = reinterpret_cast<int*>(base + SMW_SCR_FLAG);
+  fill_i32(fail, 0, 1, st);  // a kernel, not a memset node
+  hipLaunchKernelGGL(k_smw_gather, dim3(grid_for(s * s, NT)), dim3(NT), 0, st, s, kk, sp->dense_cols.p, Y,
+                     K, z);
+  LAUNCH_CHECK();
+  launch_dense_lu(K, z, s, 1, fail, st);
+  int hfail = 0;
+  HIPC(hipMemcpyAsync(&hfail, fail, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPC(hipStreamSynchronize(st));
+  if (hfail) SAI_THROW(SAI_ESINGULAR, "I + V^T W is singular (zero pivot)");
+  hipLaunchKernelGGL(k_smw_apply, dim3(rows_grid(n)), dim3(NT), 0, st, n, s, kk, Y, (const double*)z, x);
+  LAUNCH_CHECK();
+  if (c_host) {
+    double hz[SMW_NOALLOC_SMAX];
+    HIPC(hipMemcpyAsync(hz, z, sizeof(double) * s, hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    double a = 0.0;
+    for (int d = 0; d < s; ++d) a += hz[d] * hz[d];
     *c_host = std::sqrt(a);
   }
   HIPC(hipStreamSynchronize(st));

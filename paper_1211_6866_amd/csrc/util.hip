@@ -290,6 +290,11 @@ double dev_norm2(const double* v, int64_t n, int64_t stride, const Allocator& al
   return std::sqrt(r);
 }
 
+void launch_dense_lu(double* K, double* rhs, int s, int nrhs, int* fail, hipStream_t st) {
+  hipLaunchKernelGGL(k_dense_lu, dim3(1), dim3(LU_NT), 0, st, K, rhs, s, nrhs, fail);
+  LAUNCH_CHECK();
+}
+
 bool dense_lu_solve(double* K, double* rhs, int s, int nrhs, const Allocator& al, hipStream_t st) {
   if (s <= 0) return true;
   DBuf<int> fail(&al, 1);
