@@ -135,12 +135,15 @@ def _oracle_columns(rng_):
     from oracle import lsq as olsq
     from oracle import pattern as opat
     from oracle import spai as ospai
+    from oracle import psai as opsai
     a, b = rng_
-    C, R, cn2, bkw = (_ORACLE_JOB[key] for key in ("C", "R", "cn2", "bkw"))
+    C, R, cn2, a1, bkw = (_ORACLE_JOB[key] for key in ("C", "R", "cn2", "a1", "bkw"))
     rows, vals, cnt = [], [], np.zeros(b - a, dtype=np.int64)
     with threadpool_limits(1):
         for k in range(a, b):
-            if bkw.get("pattern") == 2:
+            if bkw.get("pattern") == 3:
+                J, m, _, _ = opsai.psai_tol_column(C, k, bkw["delta"], bkw["psai_lmax"], a1)
+            elif bkw.get("pattern") == 2:
                 J, _, m, _, _ = ospai.spai_column(C, R, cn2, k, bkw["spai_steps"], bkw["spai_per_step"],
                                                   bkw["delta"])
             else:
@@ -155,7 +158,7 @@ def _oracle_columns(rng_):
     return a, np.concatenate(rows), np.concatenate(vals), cnt
 
 
-def cpu_baseline(w, bkw, adjoint, workers):
+def cpu_baseline(w, bkw, adjoint, workers, dense_cols=None):
     """Time the oracle on this host: its split of the full matrix, its build of
     the whole M (columns in chunks over a fork pool of `workers` processes), and
     two BiCGStab iterations with its own M on two right-hand sides (and on the
@@ -167,6 +170,7 @@ def cpu_baseline(w, bkw, adjoint, workers):
     import scipy.sparse as sp
     from threadpoolctl import threadpool_limits
 
+    from oracle import drop as odrop
     from oracle import krylov as okry
     from oracle import pattern as opat
     from oracle import smw as osmw
@@ -177,12 +181,13 @@ def cpu_baseline(w, bkw, adjoint, workers):
     out = {}
     with threadpool_limits(1):
         t0 = time.perf_counter()
-        S = osplit.split(w.A)
+        S = osplit.split(w.A, dense_cols=dense_cols)
         out["split_s"] = time.perf_counter() - t0
     C = opat.as_csc(S.At)
     R = sp.csr_matrix(S.At)
     R.sort_indices()
-    _ORACLE_JOB.update(C=C, R=R, cn2=ospai.column_norms2(C) if bkw.get("pattern") == 2 else None, bkw=bkw)
+    _ORACLE_JOB.update(C=C, R=R, cn2=ospai.column_norms2(C) if bkw.get("pattern") == 2 else None,
+                       a1=odrop.norm1(C) if bkw.get("pattern") == 3 else None, bkw=bkw)
     chunk = max(1, min(65536, -(-n // (8 * workers))))
     ranges = [(a, min(n, a + chunk)) for a in range(0, n, chunk)]
     t0 = time.perf_counter()
@@ -218,7 +223,7 @@ def cpu_baseline(w, bkw, adjoint, workers):
     return out
 
 
-def cpu_m_error(w, bkw, arr, count=64):
+def cpu_m_error(w, bkw, arr, count=64, dense_cols=None):
     """Worst relative error, over a seeded sample of columns (the irregular
     columns, the first and the last included), of the FP32 M's columns m_k before
     dropping against the FP64 oracle's solve on the same pattern."""
@@ -227,7 +232,7 @@ def cpu_m_error(w, bkw, arr, count=64):
     from oracle import lsq as olsq
     from oracle import pattern as opat
     from oracle import split as osplit
-    S = osplit.split(w.A)
+    S = osplit.split(w.A, dense_cols=dense_cols)
     C = opat.as_csc(S.At)
     n = w.A.shape[0]
     jp, ji = arr["j_ptr"].cpu().numpy(), arr["j_idx"].cpu().numpy()
@@ -254,6 +259,13 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=None)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-workers", type=int, default=16)
+    ap.add_argument("--approach", choices=("N", "S"), default="N",
+                    help="N: split A = A~ + U V^T (the method); S: the standard approach, M built "
+                         "on A itself and one system solved (no split), for comparison")
+    ap.add_argument("--pattern", choices=("default", "spai", "psai_tol"), default="default",
+                    help="override the workload's pattern: SPAI (delta 0.4, 3 x 5) or PSAI(tol) "
+                         "(delta 0.4, l_max 10)")
+    ap.add_argument("--n", type=int, default=None, help="size of the random workload (3)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU: --gpus must be 1 (the path shards by "
@@ -266,8 +278,21 @@ def main():
     import workloads as W
 
     name, bkw, skw, adjoint = workload_settings(P, args.workload)
+    if args.pattern == "spai":
+        bkw = dict(pattern=P.PAT_SPAI, drop=P.DROP_NONE, delta=0.4, spai_steps=3, spai_per_step=5)
+        name += "_spai3x5"
+    elif args.pattern == "psai_tol":
+        bkw = dict(pattern=P.PAT_PSAI_TOL, delta=0.4, psai_lmax=10)
+        name += "_psaitol0.4"
+    if args.n is not None:
+        name += f"_n{args.n}"
+    split_kw = {}
+    if args.approach == "S":
+        # the standard approach: no irregular column is split off (A~ = A, s = 0)
+        split_kw = dict(dense_cols=[])
+        name += "_standard"
     log(f"bench: generating workload {args.workload} ({name})")
-    w = W.make(args.workload)
+    w = W.make(args.workload, n=args.n) if args.n is not None else W.make(args.workload)
     n = w.A.shape[0]
 
     # the CPU oracle leg first: its process pool forks before anything touches the GPU
@@ -276,7 +301,7 @@ def main():
     workers = max(1, min(args.cpu_workers, avail))
     if not args.no_cpu:
         log(f"bench: CPU oracle leg ({workers} processes for the build, {model}, {ncpu} CPUs)")
-        cpu_raw = cpu_baseline(w, bkw, adjoint, workers)
+        cpu_raw = cpu_baseline(w, bkw, adjoint, workers, dense_cols=split_kw.get("dense_cols"))
         log(f"bench: CPU oracle leg done: split {cpu_raw['split_s']:.1f} s, build {cpu_raw['build_s']:.1f} s, "
             f"{cpu_raw['iter_s'] * 1e3:.0f} ms per BiCGStab iteration and right-hand side")
 
@@ -286,7 +311,7 @@ def main():
     xstar = torch.from_numpy(W.x_star(n, w.seed)).cuda() if adjoint else None
 
     def step(prec):
-        sp_ = P.Split(rp, ci, va)
+        sp_ = P.Split(rp, ci, va, **split_kw)
         pc = P.Precond(sp_, precision=prec, **bkw)
         x, st = P.solve(sp_, pc, b, **skw)
         bst = None
@@ -358,10 +383,36 @@ def main():
     arr = pc_l.arrays()
     nJ = np.diff(arr["j_ptr"].cpu().numpy())
     nI = np.diff(arr["i_ptr"].cpu().numpy())
+    # the gather step on its own (sai_gather of the mixed build's blocks, float32):
+    # algorithmic bytes = list offsets 24 n + J_k and I_k 4 (sum |J| + sum |I|) +
+    # column pointers 8 sum |J| + gathered CSC entries 12 sum_k sum_{j in J_k} nnz(A~(:, j))
+    # + blocks written 4 sum |I||J|
+    gather = None
+    try:
+        log("bench: standalone gather of A~(I_k, J_k)")
+        goff, gblk = P.gather(sp_m, pc_l, precision=P.FP32)
+        P.profile_enable(only="gather")
+        for _ in range(3):
+            P.gather(sp_m, pc_l, precision=P.FP32, blk_off=goff, out=gblk)
+        gl, gms = P.profile_read()["gather_f32"]
+        P.profile_enable(False)
+        del goff, gblk
+        colnnz = np.diff(sp_m.arrays()["t_col_ptr"].cpu().numpy()).astype(np.int64)
+        gathered = float(colnnz[arr["j_idx"].cpu().numpy()].sum())
+        gbytes = (24.0 * n + 12.0 * nJ.sum() + 4.0 * nI.sum() + 12.0 * gathered
+                  + 4.0 * float(np.sum(nJ.astype(np.float64) * nI)))
+        gavg = gms / gl
+        gather = dict(kernel="gather_f32", avg_launch_ms=round(gavg, 4), algorithmic_bytes=gbytes,
+                      achieved_GBs=round(gbytes / (gavg * 1e-3) / 1e9, 1),
+                      frac=round(gbytes / (gavg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                      gathered_entries=int(gathered), block_elements=int(np.sum(nJ.astype(np.int64) * nI)))
+    except Exception as e:  # noqa: BLE001 - reported, the step results stand
+        gather = dict(error=str(e))
     m_err = None
     if not args.no_cpu:
         log("bench: FP32 M against the FP64 oracle on sampled columns")
-        m_err = cpu_m_error(w, bkw, arr)
+        m_err = None if bkw.get("pattern") == P.PAT_PSAI_TOL else cpu_m_error(
+            w, bkw, arr, dense_cols=split_kw.get("dense_cols"))
     del pc_l, arr
     flops = ls_flops(nI.astype(np.float64), nJ.astype(np.float64))
     ls_work = {}
@@ -469,6 +520,7 @@ def main():
               "s": pc_m.stats.s, "p": pc_m.stats.p, "drop_undecidable_fp32": int(pc_m.stats.drop_flips),
               "fp32_vs_fp64_oracle": m_err},
         "roofline": roof,
+        "gather": gather,
         "kernels_one_step": kern_table,
         "cpu_baseline": cpu,
     }

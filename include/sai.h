@@ -214,6 +214,24 @@ typedef struct {
 int sai_precond_get_info(const sai_precond_t* h, sai_precond_info* info /* host */);
 void sai_precond_destroy(sai_precond_t* h);
 
+/* ----------------------------------------------------------------- gather --
+ * The gather step on its own (Section 2, (lsprob): the dense block
+ * A~(I_k, J_k) of every column's least-squares problem, with I_k the nonzero
+ * rows of A~(:, J_k)).  The column solvers of sai_build gather these blocks
+ * internally; these calls write them out, for inspection and for other
+ * solvers.  `pc` must have been built with keep_lists (its J_k and I_k are
+ * used); otherwise SAI_EINVAL.
+ * sai_gather_offsets: blk_off (device, n + 1 int64) = exclusive prefix sums of
+ * |I_k| |J_k|; *total (host, may be NULL) = blk_off[n].
+ * sai_gather: writes block k column-major (element (r, c) = A~(I_k[r], J_k[c]),
+ * leading dimension |I_k|) at element offset blk_off[k] of `blocks` (device,
+ * blk_off[n] elements of float for SAI_FP32 or double for SAI_FP64, owned by
+ * the caller).  Values are copies (rounded to float for SAI_FP32). */
+int sai_gather_offsets(const sai_precond_t* pc, int64_t* blk_off, int64_t* total /* host */,
+                       void* stream);
+int sai_gather(const sai_split_t* sp, const sai_precond_t* pc, int32_t precision,
+               const int64_t* blk_off, void* blocks, void* stream);
+
 /* ----------------------------------------------------------------- krylov --
  * Solves A~ X = R (transpose = 0) or A~^T X = R (transpose = 1, with M^T as
  * preconditioner) for the k columns of the block R independently, right-

@@ -128,6 +128,8 @@ def lib():
                              C.POINTER(i32), C.POINTER(i32)]
     L.sai_smw.argtypes = [vp, vp, vp, dp, vp]
     L.sai_smw_noalloc.argtypes = [vp, vp, vp, dp, vp]
+    L.sai_gather_offsets.argtypes = [vp, vp, C.POINTER(i64), vp]
+    L.sai_gather.argtypes = [vp, vp, i32, vp, vp, vp]
     L.sai_residual.argtypes = [vp, vp, vp, dp, vp]
     L.sai_solve.argtypes = [vp, vp, vp, vp, C.POINTER(SolveOpts), vp, C.POINTER(SolveStats)]
     L.sai_backward.argtypes = [vp, vp, vp, vp, vp, vp, C.POINTER(SolveOpts), vp,
@@ -357,6 +359,26 @@ def smw(split: Split, Y):
     c = C.c_double()
     _check(lib().sai_smw(split.h, _ptr(Y), _ptr(x), C.byref(c), _stream()), "sai_smw")
     return x, c.value
+
+
+def gather(split: Split, pc: Precond, precision=FP32, blk_off=None, out=None):
+    """The dense blocks A~(I_k, J_k) (sai_gather) of a preconditioner built with
+    keep_lists: returns (blk_off int64 tensor of n + 1 offsets, flat tensor of the
+    column-major blocks)."""
+    torch = _torch()
+    L = lib()
+    if blk_off is None:
+        blk_off = torch.empty(split.n + 1, dtype=torch.int64, device="cuda")
+        total = C.c_int64()
+        _check(L.sai_gather_offsets(pc.h, _ptr(blk_off), C.byref(total), _stream()), "sai_gather_offsets")
+        total = total.value
+    else:
+        total = int(blk_off[-1].item())
+    if out is None:
+        out = torch.empty(max(1, total), dtype=torch.float32 if precision == FP32 else torch.float64,
+                          device="cuda")
+    _check(L.sai_gather(split.h, pc.h, int(precision), _ptr(blk_off), _ptr(out), _stream()), "sai_gather")
+    return blk_off, out
 
 
 def smw_noalloc(split: Split, Y, x):

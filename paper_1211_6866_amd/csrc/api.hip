@@ -131,6 +131,17 @@ int sai_smw(const sai_split_t* sp, const double* Y, double* x, double* c, void* 
   return guarded([&] { sai::smw_recover(sp, Y, x, c, (hipStream_t)stream); });
 }
 
+int sai_gather_offsets(const sai_precond_t* pc, int64_t* blk_off, int64_t* total, void* stream) {
+  if (!pc || !blk_off) return SAI_EINVAL;
+  return guarded([&] { sai::gather_offsets(pc, blk_off, total, (hipStream_t)stream); });
+}
+
+int sai_gather(const sai_split_t* sp, const sai_precond_t* pc, int32_t precision, const int64_t* blk_off,
+               void* blocks, void* stream) {
+  if (!sp || !pc || !blk_off || !blocks) return SAI_EINVAL;
+  return guarded([&] { sai::gather_blocks(sp, pc, precision, blk_off, blocks, (hipStream_t)stream); });
+}
+
 int sai_smw_noalloc(const sai_split_t* sp, const double* Y, double* x, double* c, void* stream) {
   if (!sp || !Y || !x) return SAI_EINVAL;
   return guarded([&] { sai::smw_recover_noalloc(sp, Y, x, c, (hipStream_t)stream); });

@@ -285,14 +285,19 @@ void build_impl(const sai_split_s* sp, const sai_build_opts& o, hipStream_t st,
 int krylov_impl(const sai_split_s* sp, const sai_precond_s* pc, int transpose, int k,
                 const double* R, double* X, const double* thr, const sai_solve_opts& o,
                 hipStream_t st, int32_t* iters, int32_t* status);
-// K z = rhs with K = I + G (s x s row-major, device), solves in float64 on device.
+// SMW recovery x = y - W (I + V^T W)^{-1} V^T y on the device (LU in float64).
+void smw_recover(const sai_split_s* sp, const double* Y, double* x, double* c_host,
+                 hipStream_t st);
 // smw_recover without any allocation: K, z and the pivot flag in the file-scope
 // scratch array of smw.hip (s <= SMW_NOALLOC_SMAX).
 constexpr int SMW_NOALLOC_SMAX = 64;
 void smw_recover_noalloc(const sai_split_s* sp, const double* Y, double* x, double* c_host,
                          hipStream_t st);
-void smw_recover(const sai_split_s* sp, const double* Y, double* x, double* c_host,
-                 hipStream_t st);
+// Standalone gather of the dense column blocks A~(I_k, J_k) (column-major, at
+// blk_off[k] elements) in float (precision SAI_FP32) or double.
+void gather_offsets(const sai_precond_s* pc, int64_t* blk_off, int64_t* total, hipStream_t st);
+void gather_blocks(const sai_split_s* sp, const sai_precond_s* pc, int precision,
+                   const int64_t* blk_off, void* blocks, hipStream_t st);
 double residual_impl(const sai_split_s* sp, const double* b, const double* x, hipStream_t st);
 void backward_impl(const sai_split_s* sp, const sai_precond_s* pc, const double* x,
                    const double* gx, double* gb, double* ga, const sai_solve_opts& o,

@@ -112,6 +112,15 @@ def test_fullsize_workload(idx, prec):
                 assert abs(abs(m[pos]) - bkw["tau"]) <= 1e-4 * np.linalg.norm(m), (k, r_)
                 flips += 1
     assert flips <= pc.stats.drop_flips
+    if idx == 2 and prec == P.FP32:
+        # the standalone gather at full size, sampled columns bit-exact (float32 copies)
+        off, blocks = P.gather(g, pc, precision=P.FP32)
+        off = _np(off)
+        for k in _sample(n, S.D, w.seed + 2):
+            J, I = ji[jp[k]:jp[k + 1]], ii[ip[k]:ip[k + 1]]
+            got = _np(blocks[off[k]:off[k + 1]]).reshape(len(J), len(I)).T
+            assert np.array_equal(got, olsq.dense_block(C, I, J).astype(np.float32)), k
+        del blocks
     print(f"workload {idx}: sampled columns ok (worst rel err {worst:.2e}, {flips} threshold flips; "
           f"{pc.stats.drop_flips} undecidable entries in M)", flush=True)
     # ---- solve: rr < 1e-8 recomputed in FP64 on the host

@@ -778,3 +778,41 @@ def test_spai_zero_steps(init):
         ref = P.Precond(g, pattern=P.PAT_A, drop=P.DROP_NONE, precision=P.FP64).arrays()
         for key in ("col_ptr", "row_idx", "cval"):
             assert np.array_equal(_np(arr[key]), _np(ref[key])), key
+
+
+@pytest.mark.parametrize("name,kind", [("c1", P.PAT_A), ("c2_12", P.PAT_A2), ("c2_13x9x7", P.PAT_A2),
+                                       ("c3_3000", P.PAT_SPAI), ("banded", P.PAT_A2)])
+@pytest.mark.parametrize("prec", [P.FP64, P.FP32])
+def test_gather_vs_oracle(name, kind, prec):
+    """sai_gather writes A~(I_k, J_k) for every column: bit-exact against the
+    oracle's dense block (FP32: its float32 rounding).  The SPAI case has blocks
+    larger than the 8 KB LDS tile (more than 2048 float or 1024 double
+    elements, or more than 256 rows), which are filled element by element."""
+    if name == "banded":
+        A = W.banded(600, 8, 2, 0.5, 7)
+        dev = P.csr_to_device(A)
+    else:
+        w, dev = _load(name)
+        A = w.A
+    S = osplit.split(A)
+    C = opat.as_csc(S.At)
+    g = P.Split(*dev)
+    kw = dict(delta=0.05, spai_steps=3, spai_per_step=5) if kind == P.PAT_SPAI else {}
+    pc = P.Precond(g, pattern=kind, drop=P.DROP_NONE, precision=P.FP32, keep_lists=True, **kw)
+    arr = pc.arrays()
+    jp, ji, ip, ii = (_np(arr[k]) for k in ("j_ptr", "j_idx", "i_ptr", "i_idx"))
+    off, blocks = P.gather(g, pc, precision=prec)
+    off, blocks = _np(off), _np(blocks)
+    n = A.shape[0]
+    assert off[0] == 0 and off[-1] == int(np.sum(np.diff(jp) * np.diff(ip)))
+    big = 0
+    for k in range(n):
+        J, I = ji[jp[k]:jp[k + 1]], ii[ip[k]:ip[k + 1]]
+        ref = olsq.dense_block(C, I, J)
+        got = blocks[off[k]:off[k + 1]].reshape(len(J), len(I)).T
+        if prec == P.FP32:
+            ref = ref.astype(np.float32)
+        assert np.array_equal(got, ref), k
+        big += len(I) > 256 or len(J) > 64 or len(I) * len(J) > (2048 if prec == P.FP32 else 1024)
+    if name == "c3_3000":
+        assert big > 0
