@@ -228,20 +228,28 @@ __device__ void block_partials(double (&acc)[ND][2], const State& S, int kp) {
 // Tile loop for sparse products: tiles of TR = RPB rows (one per lane); every thread of
 // the block runs every iteration (the body synchronises).  Workgroups are
 // dispatched to the 8 XCDs round-robin (block b on XCD b % 8), and each XCD
-// has its own L2; with xmap the tiles are split into 8 contiguous chunks,
-// chunk x processed by the blocks of XCD x, so that the band of gathered rows
-// of X stays in that XCD's L2.
+// has its own L2.  xmap selects which tiles an XCD's blocks take:
+//   0   round-robin over all tiles (consecutive tiles on different XCDs);
+//   1   8 contiguous chunks of the tiles, chunk x on XCD x (the band of
+//       gathered rows of X stays in that XCD's L2; for blocks that fit the MALL);
+//   C>1 blocked interleave: super-chunks of 8 C consecutive tiles, whose x-th
+//       run of C tiles goes to XCD x.  The XCDs advance through the rows
+//       together (one shared window of gathered rows in the MALL) while each
+//       keeps a contiguous run of rows, whose nearby gathers hit its L2.
+// Tile m of an XCD (m = b, b + G, ... for its b-th of G blocks) is
+// (m / C) 8 C + x C + m % C, increasing in m.
 #define TILE_LOOP                                                                  \
   constexpr int TR = RPB;                                                          \
   const int64_t ntile_ = (n + TR - 1) / TR;                                        \
-  const bool xcd_map_ = xmap && (gridDim.x % 8) == 0;                              \
-  const int64_t chunk_ = xcd_map_ ? (ntile_ + 7) / 8 : ntile_;                     \
-  const int64_t tfirst_ = xcd_map_ ? (int64_t)(blockIdx.x % 8) * chunk_ : 0;       \
-  const int64_t tstep_ = xcd_map_ ? gridDim.x / 8 : gridDim.x;                     \
-  const int64_t tlast_ = min<int64_t>(ntile_, tfirst_ + chunk_);                   \
-  for (int64_t tile_ = tfirst_ + (xcd_map_ ? blockIdx.x / 8 : blockIdx.x),         \
+  const int xm_ = (gridDim.x % 8) == 0 ? xmap : 0;                                 \
+  const int64_t G_ = xm_ ? (int64_t)gridDim.x / 8 : (int64_t)gridDim.x;            \
+  const int64_t b_ = xm_ ? (int64_t)blockIdx.x / 8 : (int64_t)blockIdx.x;          \
+  const int64_t x_ = (int64_t)blockIdx.x % 8;                                      \
+  const int64_t C_ = xm_ == 1 ? (ntile_ + 7) / 8 : (int64_t)(xm_ > 1 ? xm_ : 1);   \
+  for (int64_t m_ = b_, tile_ = xm_ ? (m_ / C_) * 8 * C_ + x_ * C_ + m_ % C_ : m_, \
                t0 = tile_ * TR;                                                    \
-       tile_ < tlast_; tile_ += tstep_, t0 = tile_ * TR)
+       tile_ < ntile_;                                                             \
+       m_ += G_, tile_ = xm_ ? (m_ / C_) * 8 * C_ + x_ * C_ + m_ % C_ : m_, t0 = tile_ * TR)
 
 // Stage the entries of rows t0 .. t0+rows-1 in LDS; false when they do not fit.
 template <class TV, int CAP>

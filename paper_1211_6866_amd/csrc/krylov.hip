@@ -150,7 +150,15 @@ int iterate(Block& B, const Csr<double>& A, const Csr<TM>& M, int64_t n, int& it
   // resident in the MALL.
   const bool persist = tune_get("PERSIST", 1) != 0;
   const size_t nk = (size_t)n * kp;
-  const int xmap = tune_get("XMAP", nk * sizeof(double) <= (size_t(256) << 20) ? 1 : 0);
+  // tile-to-XCD map (TILE_LOOP): contiguous chunks per XCD when a block fits the
+  // MALL, else round-robin tiles (XCHUNK = 0), or the blocked interleave with
+  // runs of XCHUNK rows per XCD.  On the 160^3 workload (1.7 GB blocks) every
+  // XCHUNK from 1600 to 51200 rows made the M product slower (2.71-3.01 ms
+  // against 2.60 ms round-robin), so round-robin is the default.
+  constexpr int RPB_ = (64 / LP) * (NT / 64);
+  const int xchunk = tune_get("XCHUNK", 0);
+  const int xmap_big = xchunk > 0 ? std::max(2, xchunk / RPB_) : 0;
+  const int xmap = tune_get("XMAP", nk * sizeof(double) <= (size_t(256) << 20) ? 1 : xmap_big);
   auto sp_grid = [&](const void* kern) {
     const int64_t ntiles = (n + RPB - 1) / RPB;
     int64_t g = std::min<int64_t>(NBMAX, ntiles);
