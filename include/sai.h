@@ -140,9 +140,11 @@ void sai_split_destroy(sai_split_t* h);
  * largest entry of each column is always kept; no re-solve.
  * precision: SAI_FP32 builds M in float32 ("mixed"), SAI_FP64 in float64.
  * Errors: SAI_EINVAL, SAI_ESINGULAR (a column block without full column rank),
- * SAI_ETOOBIG (|J_k| > 128 or |I_k| > 4096; in the SPAI and PSAI(tol) searches
- * also |I_k| > 2048 or more than 8192 gathered row or candidate entries for a
- * column that goes past its first solve), SAI_ENOMEM, SAI_EHIP. */
+ * SAI_ETOOBIG (|J_k| > 512 or |I_k| > 8192; in the SPAI and PSAI(tol) searches
+ * also more than 65536 gathered row or candidate entries for a column that
+ * goes past its first solve; columns within the limits of the fast kernels
+ * (|J_k| <= 128, |I_k| <= 2048 and 8192 entries in the searches) run there,
+ * the others in a second pass with these larger limits), SAI_ENOMEM, SAI_EHIP. */
 enum { SAI_PAT_A = 0, SAI_PAT_A2 = 1, SAI_PAT_SPAI = 2, SAI_PAT_PSAI_TOL = 3 };
 enum { SAI_DROP_NONE = 0, SAI_DROP_ABS = 1, SAI_DROP_TOLK = 2 };
 enum { SAI_INIT_PATTERN_A = 0, SAI_INIT_DIAG = 1 };

@@ -353,8 +353,8 @@ __global__ void __launch_bounds__(64, MINW) k_ls_qr(const int32_t* __restrict__ 
 // ---- large problems: one workgroup, block in global memory ------------------
 
 constexpr int BIG_NT = 1024;  // 16 wavefronts: the column updates of a step spread over them
-constexpr int BIG_MAXI = 4096;
-constexpr int BIG_MAXJ = 128;
+constexpr int BIG_MAXI = 8192;  // the large search limits of spai.hip (CapL)
+constexpr int BIG_MAXJ = 512;
 
 template <class T>
 __global__ void __launch_bounds__(BIG_NT) k_ls_qr_big(const int32_t* __restrict__ cols, int ncols,
@@ -633,9 +633,11 @@ void dispatch_variant(int v, const int32_t* list, int cnt, const int64_t* jptr,
       default: break;
     }
   }
-  // global-memory kernel for everything larger
-  const unsigned grid = (unsigned)std::min(cnt, 1024);
+  // global-memory kernel for everything larger: one block (|I| x (|J| + 1))
+  // per workgroup, at most 4 GB of them (problems come from a queue)
   const int64_t stride = (int64_t)maxI * (maxJ + 1);
+  const int64_t wmax = std::max<int64_t>(1, (int64_t(4) << 30) / (stride * (int64_t)sizeof(T)));
+  const unsigned grid = (unsigned)std::min<int64_t>({(int64_t)cnt, 1024, wmax});
   DBuf<T> work(&al, (size_t)grid * stride);
   DBuf<int> next(&al, 1);
   HIPC(hipMemsetAsync(next.p, 0, sizeof(int), st));

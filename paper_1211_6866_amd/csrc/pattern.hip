@@ -106,6 +106,9 @@ __device__ int sort_unique(int32_t* cand, int m, int cap) {
 // sort when there are more than 64 distinct values or more than 512 candidates.
 constexpr int HT = 256;
 constexpr int32_t HT_EMPTY = 0x7fffffff;
+// |J_k| held by the large variants of the pattern and row-set kernels (the
+// large column-solver limits)
+constexpr int CAPJ_L = 512;
 
 __device__ int sort_unique_fast(int32_t* cand, int m, int cap, int32_t* ht) {
   const int l = lane_id();
@@ -156,7 +159,7 @@ __device__ int sort_unique_fast(int32_t* cand, int m, int cap, int32_t* ht) {
 // mode 0: counts only; 1: lists at jptr/iptr; 2: lists at jptr/iptr and counts.
 // A column whose unions overflow the capacities gets cntJ = -1 (modes 0, 2).
 // Work item b < nwork is column list[b] (or column b when list is NULL).
-template <int CAP>
+template <int CAP, int CAPJ = 256>
 __global__ void __launch_bounds__(64) k_pattern(int32_t nwork, int kind, const int32_t* __restrict__ cp,
                                                 const int32_t* __restrict__ ri, int mode,
                                                 const int32_t* __restrict__ list,
@@ -165,8 +168,7 @@ __global__ void __launch_bounds__(64) k_pattern(int32_t nwork, int kind, const i
                                                 int32_t* __restrict__ jout,
                                                 const int64_t* __restrict__ iptr,
                                                 int32_t* __restrict__ iout, int* __restrict__ nover) {
-  constexpr int CAPJ = 256;
-  static_assert(HT == CAPJ, "the hash table reuses the gather scratch");
+  static_assert(CAPJ >= HT, "the hash table reuses the gather scratch");
   __shared__ int32_t cand[CAP];
   __shared__ int32_t sJ[CAPJ];
   // gather scratch; the hash table of a union reuses s_start once the
@@ -268,7 +270,7 @@ __global__ void __launch_bounds__(256) k_pack_lists(int32_t n, const int64_t* __
 }
 
 // I_k = union of P(A~(:, j)) over the given J_k (count pass: mode 0, fill: mode 1).
-template <int CAP>
+template <int CAP, int CAPJ = 256>
 __global__ void __launch_bounds__(64) k_rows_of(int32_t nwork, const int32_t* __restrict__ list,
                                                 const int32_t* __restrict__ cp,
                                                 const int32_t* __restrict__ ri,
@@ -277,8 +279,7 @@ __global__ void __launch_bounds__(64) k_rows_of(int32_t nwork, const int32_t* __
                                                 int32_t* __restrict__ cntI,
                                                 const int64_t* __restrict__ iptr,
                                                 int32_t* __restrict__ iout, int* __restrict__ nover) {
-  constexpr int CAPJ = 256;
-  static_assert(HT == CAPJ, "the hash table reuses the gather scratch");
+  static_assert(CAPJ >= HT, "the hash table reuses the gather scratch");
   __shared__ int32_t cand[CAP];
   __shared__ int32_t sJ[CAPJ];
   // gather scratch; the hash table of a union reuses s_start once the
@@ -347,12 +348,13 @@ void rows_of_patterns(const sai_split_s* sp, hipStream_t st, const Allocator& al
     if (read_scalar(nover.p + 1, st) != nbig)
       SAI_THROW(SAI_EHIP, "row-set overflow list: %d columns listed, %d counted",
                 read_scalar(nover.p + 1, st), nbig);
-    hipLaunchKernelGGL((k_rows_of<CAP_L>), dim3(std::min(nbig, 1 << 20)), dim3(64), 0, st, nbig,
+    hipLaunchKernelGGL((k_rows_of<CAP_L, CAPJ_L>), dim3(std::min(nbig, 1 << 20)), dim3(64), 0, st, nbig,
                        (const int32_t*)list.p, cp, ri, jptr.p, jidx.p, 0, cntI.p, (const int64_t*)nullptr,
                        (int32_t*)nullptr, nover.p);
     LAUNCH_CHECK();
     if (read_scalar(nover.p, st) > 0)
-      SAI_THROW(SAI_ETOOBIG, "a row set I_k exceeds %d candidate indices", CAP_L);
+      SAI_THROW(SAI_ETOOBIG, "a pattern exceeds %d indices or a row set I_k %d candidate indices", CAPJ_L,
+                CAP_L);
   }
   iptr.alloc(&al, (size_t)n + 1);
   exclusive_scan_i32_to_i64(cntI.p, iptr.p, n, al, st);
@@ -362,7 +364,7 @@ void rows_of_patterns(const sai_split_s* sp, hipStream_t st, const Allocator& al
                      jptr.p, jidx.p, 1, cntI.p, (const int64_t*)iptr.p, iidx.p, nover.p);
   LAUNCH_CHECK();
   if (nbig > 0) {
-    hipLaunchKernelGGL((k_rows_of<CAP_L>), dim3(std::min(nbig, 1 << 20)), dim3(64), 0, st, nbig,
+    hipLaunchKernelGGL((k_rows_of<CAP_L, CAPJ_L>), dim3(std::min(nbig, 1 << 20)), dim3(64), 0, st, nbig,
                        (const int32_t*)list.p, cp, ri, jptr.p, jidx.p, 1, cntI.p, (const int64_t*)iptr.p,
                        iidx.p, nover.p);
     LAUNCH_CHECK();
@@ -424,12 +426,13 @@ void build_patterns(const sai_split_s* sp, int kind, hipStream_t st, const Alloc
       if (read_scalar(nover.p + 1, st) != nbig)
         SAI_THROW(SAI_EHIP, "pattern overflow list: %d columns listed, %d counted",
                   read_scalar(nover.p + 1, st), nbig);
-      hipLaunchKernelGGL((k_pattern<CAP_L>), dim3(std::min(nbig, 1 << 20)), dim3(64), 0, st, nbig, kind,
+      hipLaunchKernelGGL((k_pattern<CAP_L, CAPJ_L>), dim3(std::min(nbig, 1 << 20)), dim3(64), 0, st, nbig, kind,
                          cp, ri, 2, (const int32_t*)list.p, cntJ.p, cntI.p, (const int64_t*)ujo.p, tJ.p,
                          (const int64_t*)uio.p, tI.p, nover.p);
       LAUNCH_CHECK();
       if (read_scalar(nover.p, st) > 0)
-        SAI_THROW(SAI_ETOOBIG, "a pattern union exceeds %d candidate indices", CAP_L);
+        SAI_THROW(SAI_ETOOBIG, "a pattern exceeds %d indices or its unions %d candidate indices", CAPJ_L,
+                  CAP_L);
     }
   }
   SAI_PROF("pattern_pack", st);

@@ -40,22 +40,34 @@ int solve_columns(const sai_split_s* sp, const int64_t* jptr, const int32_t* jid
 namespace {
 
 constexpr int SNT = 256;
-constexpr int SJMAX = 128;   // |J_k| limit during the search
-constexpr int SCAPI = 2048;  // |I_k| limit during the search
-constexpr int SCAPN = 8192;  // candidate entries before de-duplication
+// Limits of one column's search workspace: |J_k| (J), |I_k| (I) and candidate or
+// gathered entries before de-duplication (N, a power of two, at least 3 I).
+// Every column is searched with the small limits first; a column that
+// outgrows them is searched again from its start with the large ones, in a
+// second launch with fewer, larger workspace slots.
+template <int J_, int I_, int N_>
+struct Caps {
+  static constexpr int J = J_, I = I_, N = N_;
+};
+using CapS = Caps<128, 2048, 8192>;
+using CapL = Caps<512, 8192, 65536>;
+constexpr int SJMAX = CapS::J;   // |J_k| of the padded per-column result arrays
 constexpr int NSLOT_MAX = 4096;  // columns searched concurrently (workspace slots), at most
+constexpr int NSLOT_L = 64;      // ... with the large limits
+// result of a column solve: done, over the workspace limits, rank deficient
+enum { LS_OK = 0, LS_BIG = 1, LS_SING = 2 };
 
 enum { E_TOOBIG = 1, E_SING = 2 };
 
 struct Ws {
-  int32_t* I;     // SCAPI
-  int32_t* cand;  // SCAPN
-  int32_t* off;   // SCAPI + 1
-  double* W;      // SCAPI * (SJMAX + 1), column-major block + right-hand side
-  double* r;      // SCAPI
-  double* g;      // SCAPN
-  int32_t* Is;    // SCAPI, SPAI search only: I sorted
-  int32_t* P;     // SCAPI, SPAI search only: storage row of Is[q]
+  int32_t* I;     // C::I
+  int32_t* cand;  // C::N
+  int32_t* off;   // C::I + 1
+  double* W;      // C::I * (C::J + 1), column-major block + right-hand side
+  double* r;      // C::I
+  double* g;      // C::N
+  int32_t* Is;    // C::I, SPAI search only: I sorted
+  int32_t* P;     // C::I, SPAI search only: storage row of Is[q]
 };
 
 __device__ __forceinline__ int bsearch_eq(const int32_t* a, int n, int32_t x) {
@@ -175,11 +187,12 @@ __global__ void __launch_bounds__(SNT) k_colnorm2(int32_t n, const int32_t* cp, 
 // workspace: I = nonzero rows of A~(:, J) (ws.I, sorted), the dense block
 // A~(I, J) with e_k(I) (ws.W), Householder QR with Q^T applied to e_k,
 // back-substitution into sm[0..nJ), and the residual r = A~(:, J) m - e_k on I
-// (ws.r, columns added in order).  Returns false when |I| or the gathered
-// entries exceed the workspace or the block is rank deficient (the same in
-// every thread); rr = ||r||^2.  Every thread of the workgroup calls it.
-template <int B>
-__device__ bool ls_solve_ws(int64_t k, const int32_t* __restrict__ cp, const int32_t* __restrict__ ri,
+// (ws.r, columns added in order).  Returns LS_BIG when |I| or the gathered
+// entries exceed the workspace limits C, LS_SING when the block is rank
+// deficient (the same in every thread); rr = ||r||^2.  Every thread of the
+// workgroup calls it.
+template <int B, class C>
+__device__ int ls_solve_ws(int64_t k, const int32_t* __restrict__ cp, const int32_t* __restrict__ ri,
                             const double* __restrict__ cv, const int32_t* sJ, int nJ, const Ws& ws,
                             double* sm, double* sd, double* red, int* wsum, int* s_int, int& nI_out,
                             double& rr) {
@@ -197,7 +210,7 @@ __device__ bool ls_solve_ws(int64_t k, const int32_t* __restrict__ cp, const int
   }
   __syncthreads();
   tot = s_int[0];
-  if (tot > SCAPN) return false;
+  if (tot > C::N) return LS_BIG;
   for (int f = tid; f < tot; f += B) {
     int lo = 0, hi = nJ - 1;
     while (lo < hi) {
@@ -208,7 +221,8 @@ __device__ bool ls_solve_ws(int64_t k, const int32_t* __restrict__ cp, const int
   }
   __syncthreads();
   const int nI = blk_sort_unique<B>(ws.cand, tot, wsum);
-  if (nI > SCAPI || nI < nJ) return false;
+  if (nI > C::I) return LS_BIG;
+  if (nI < nJ) return LS_SING;
   for (int t = tid; t < nI; t += B) ws.I[t] = ws.cand[t];
   __syncthreads();
   // ---- dense block A~(I, J) (column-major, ld nI) and e_k(I) in column nJ
@@ -260,7 +274,7 @@ __device__ bool ls_solve_ws(int64_t k, const int32_t* __restrict__ cp, const int
     if (tid == 0) colj[j] = -sgn * normx;
     __syncthreads();
   }
-  if (sing) return false;
+  if (sing) return LS_SING;
   if (w == 0) {
     for (int c = nJ - 1; c >= 0; --c) {
       double part = 0.0;
@@ -286,7 +300,7 @@ __device__ bool ls_solve_ws(int64_t k, const int32_t* __restrict__ cp, const int
   for (int t = tid; t < nI; t += B) rr += ws.r[t] * ws.r[t];
   rr = blk_sum<B>(rr, red);
   nI_out = nI;
-  return true;
+  return LS_OK;
 }
 
 // Least-squares solve of the SPAI search with its QR factors updated as J
@@ -294,8 +308,8 @@ __device__ bool ls_solve_ws(int64_t k, const int32_t* __restrict__ cp, const int
 // from the previous ones).  State kept in the workspace between calls:
 //   ws.I[0..nI)   rows of I_k in storage order (the rows a step adds go last),
 //   ws.Is[0..nI)  the same rows sorted, ws.P[q] = storage row of ws.Is[q],
-//   ws.W          factor column c at W + c * SCAPI: R above the diagonal, the
-//                 reflector's other entries below it; Q^T e_k(I) at W + SJMAX * SCAPI,
+//   ws.W          factor column c at W + c * C::I: R above the diagonal, the
+//                 reflector's other entries below it; Q^T e_k(I) at W + C::J * C::I,
 //   hv[c], ht[c]  leading entry and coefficient 2 / (v^T v) of reflector c.
 // Columns fJ[0..j0) are factored; this call adds fJ[j0..nJ): it gathers the
 // rows they bring, applies the stored reflectors to the new columns, factors
@@ -303,10 +317,11 @@ __device__ bool ls_solve_ws(int64_t k, const int32_t* __restrict__ cp, const int
 // reflectors are zero in the new rows, so the factors are those of the
 // row-permuted block A~(I, J) and the minimiser is the same as a solve from
 // scratch.  r = A~(:, J) m - e_k on I goes to ws.r (storage order, columns
-// added in factor order), rr = ||r||^2.  Returns false (the same in every
-// thread) when the workspace would overflow or a new column is dependent.
-template <int B>
-__device__ bool ls_extend_ws(int64_t k, const int32_t* __restrict__ cp, const int32_t* __restrict__ ri,
+// added in factor order), rr = ||r||^2.  Returns LS_BIG (the same in every
+// thread) when the workspace would overflow, LS_SING when a new column is
+// dependent.
+template <int B, class C>
+__device__ int ls_extend_ws(int64_t k, const int32_t* __restrict__ cp, const int32_t* __restrict__ ri,
                              const double* __restrict__ cv, const int32_t* fJ, int j0, int nJ,
                              const Ws& ws, double* sm, double* sd, double* hv, double* ht, double* red,
                              int* wsum, int* s_int, int& nI, double& rr) {
@@ -324,7 +339,7 @@ __device__ bool ls_extend_ws(int64_t k, const int32_t* __restrict__ cp, const in
   }
   __syncthreads();
   const int tot = s_int[0];
-  if (tot > SCAPN) return false;
+  if (tot > C::N) return LS_BIG;
   for (int f = tid; f < tot; f += B) {
     int lo = 0, hi = nJ - j0 - 1;
     while (lo < hi) {
@@ -337,10 +352,11 @@ __device__ bool ls_extend_ws(int64_t k, const int32_t* __restrict__ cp, const in
   int nNew = blk_sort_unique<B>(ws.cand, tot, wsum);
   nNew = blk_compact<B>(ws.cand, nNew, [&](int, int32_t v) { return bsearch_eq(ws.Is, nI0, v) < 0; }, wsum);
   const int nI1 = nI0 + nNew;
-  if (nI1 > SCAPI || nI1 < nJ) return false;
-  // ---- merge the new rows into the sorted copy (cand + SCAPI / + 2 SCAPI as staging)
-  int32_t* tS = ws.cand + SCAPI;
-  int32_t* tP = ws.cand + 2 * SCAPI;
+  if (nI1 > C::I) return LS_BIG;
+  if (nI1 < nJ) return LS_SING;
+  // ---- merge the new rows into the sorted copy (cand + C::I / + 2 C::I as staging)
+  int32_t* tS = ws.cand + C::I;
+  int32_t* tP = ws.cand + 2 * C::I;
   for (int q = tid; q < nI0; q += B) {
     const int32_t v = ws.Is[q];
     int lo = 0, hi = nNew;
@@ -369,25 +385,25 @@ __device__ bool ls_extend_ws(int64_t k, const int32_t* __restrict__ cp, const in
   }
   // ---- new rows of the factored columns are zero; e_k on the new rows; the new columns
   double* W = ws.W;
-  double* bv = W + (int64_t)SJMAX * SCAPI;
-  for (int t = tid; t < j0 * nNew; t += B) W[(int64_t)(t / nNew) * SCAPI + nI0 + t % nNew] = 0.0;
+  double* bv = W + (int64_t)C::J * C::I;
+  for (int t = tid; t < j0 * nNew; t += B) W[(int64_t)(t / nNew) * C::I + nI0 + t % nNew] = 0.0;
   for (int t = tid; t < nNew; t += B) bv[nI0 + t] = (ws.I[nI0 + t] == k) ? 1.0 : 0.0;
-  for (int t = tid; t < (nJ - j0) * nI1; t += B) W[(int64_t)(j0 + t / nI1) * SCAPI + t % nI1] = 0.0;
+  for (int t = tid; t < (nJ - j0) * nI1; t += B) W[(int64_t)(j0 + t / nI1) * C::I + t % nI1] = 0.0;
   __syncthreads();
   for (int c = j0; c < nJ; ++c) {
     const int32_t j = fJ[c];
     for (int32_t e = cp[j] + tid; e < cp[j + 1]; e += B) {
       const int q = bsearch_eq(ws.Is, nI1, ri[e]);
-      W[(int64_t)c * SCAPI + ws.P[q]] = cv[e];
+      W[(int64_t)c * C::I + ws.P[q]] = cv[e];
     }
   }
   __syncthreads();
   // ---- stored reflectors applied to the new columns: one wavefront per column,
   // storage row t always handled by lane t % WAVE
   for (int c = j0 + w; c < nJ; c += B / WAVE) {
-    double* colc = W + (int64_t)c * SCAPI;
+    double* colc = W + (int64_t)c * C::I;
     for (int j = 0; j < j0; ++j) {
-      const double* colj = W + (int64_t)j * SCAPI;
+      const double* colj = W + (int64_t)j * C::I;
       double d = 0.0;
       for (int t = lane; t < nI1; t += WAVE) {
         if (t > j) d += colj[t] * colc[t];
@@ -404,7 +420,7 @@ __device__ bool ls_extend_ws(int64_t k, const int32_t* __restrict__ cp, const in
   // ---- Householder steps on the new columns, applied to the later ones and Q^T e_k
   bool sing = false;
   for (int j = j0; j < nJ; ++j) {
-    double* colj = W + (int64_t)j * SCAPI;
+    double* colj = W + (int64_t)j * C::I;
     double tail = 0.0;
     for (int t = j + 1 + tid; t < nI1; t += B) tail += colj[t] * colj[t];
     tail = blk_sum<B>(tail, red);
@@ -423,7 +439,7 @@ __device__ bool ls_extend_ws(int64_t k, const int32_t* __restrict__ cp, const in
     }
     __syncthreads();
     for (int c = j + 1 + w; c <= nJ; c += B / WAVE) {
-      const double* colc = c == nJ ? bv : W + (int64_t)c * SCAPI;
+      const double* colc = c == nJ ? bv : W + (int64_t)c * C::I;
       double d = 0.0;
       for (int t = j + lane; t < nI1; t += WAVE) d += colj[t] * colc[t];
       d = wave_sum(d);
@@ -434,20 +450,20 @@ __device__ bool ls_extend_ws(int64_t k, const int32_t* __restrict__ cp, const in
     for (int64_t t = tid; t < (int64_t)rows * ncol; t += B) {
       const int c = j + 1 + (int)(t / rows);
       const int r_ = j + (int)(t % rows);
-      double* colc = c == nJ ? bv : W + (int64_t)c * SCAPI;
+      double* colc = c == nJ ? bv : W + (int64_t)c * C::I;
       colc[r_] -= sd[c] * colj[r_];
     }
     __syncthreads();
     if (tid == 0) colj[j] = -sgn * normx;
     __syncthreads();
   }
-  if (sing) return false;
+  if (sing) return LS_SING;
   if (w == 0) {
     for (int c = nJ - 1; c >= 0; --c) {
       double part = 0.0;
-      for (int q = c + 1 + lane; q < nJ; q += WAVE) part += W[(int64_t)q * SCAPI + c] * sm[q];
+      for (int q = c + 1 + lane; q < nJ; q += WAVE) part += W[(int64_t)q * C::I + c] * sm[q];
       part = wave_sum(part);
-      if (lane == 0) sm[c] = (bv[c] - part) / W[(int64_t)c * SCAPI + c];
+      if (lane == 0) sm[c] = (bv[c] - part) / W[(int64_t)c * C::I + c];
     }
   }
   __syncthreads();
@@ -467,10 +483,12 @@ __device__ bool ls_extend_ws(int64_t k, const int32_t* __restrict__ cp, const in
   for (int t = tid; t < nI1; t += B) rr += ws.r[t] * ws.r[t];
   rr = blk_sum<B>(rr, red);
   nI = nI1;
-  return true;
+  return LS_OK;
 }
 
-template <int B>
+// A column the workspace limits C cannot hold is appended to ovf (when given:
+// it is searched again with the large limits), else it is an error.
+template <int B, class C>
 __global__ void __launch_bounds__(B) k_spai(int32_t n, const int32_t* __restrict__ cp,
                                               const int32_t* __restrict__ ri,
                                               const double* __restrict__ cv,
@@ -482,13 +500,14 @@ __global__ void __launch_bounds__(B) k_spai(int32_t n, const int32_t* __restrict
                                               int32_t* __restrict__ jpad, int32_t* __restrict__ cntJ,
                                               Ws ws0, const int32_t* __restrict__ list, int32_t nwork,
                                               int* __restrict__ next, int* __restrict__ err,
-                                              int32_t* __restrict__ taken) {
-  __shared__ int32_t sJ[SJMAX + 8];
-  __shared__ int32_t fJ[SJMAX];
-  __shared__ double sm[SJMAX];
-  __shared__ double sd[SJMAX + 1];
-  __shared__ double hv[SJMAX];
-  __shared__ double ht[SJMAX];
+                                              int32_t* __restrict__ taken, int32_t* __restrict__ ovf,
+                                              int* __restrict__ ovf_cnt) {
+  __shared__ int32_t sJ[C::J + 8];
+  __shared__ int32_t fJ[C::J];
+  __shared__ double sm[C::J];
+  __shared__ double sd[C::J + 1];
+  __shared__ double hv[C::J];
+  __shared__ double ht[C::J];
   __shared__ double red[B / WAVE];
   __shared__ int wsum[B / WAVE + 1];
   __shared__ int32_t chosen[16];
@@ -497,14 +516,14 @@ __global__ void __launch_bounds__(B) k_spai(int32_t n, const int32_t* __restrict
   const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
   const int slot = blockIdx.x;
   Ws ws;
-  ws.I = ws0.I + (int64_t)slot * SCAPI;
-  ws.cand = ws0.cand + (int64_t)slot * SCAPN;
-  ws.off = ws0.off + (int64_t)slot * (SCAPI + 1);
-  ws.W = ws0.W + (int64_t)slot * SCAPI * (SJMAX + 1);
-  ws.r = ws0.r + (int64_t)slot * SCAPI;
-  ws.g = ws0.g + (int64_t)slot * SCAPN;
-  ws.Is = ws0.Is + (int64_t)slot * SCAPI;
-  ws.P = ws0.P + (int64_t)slot * SCAPI;
+  ws.I = ws0.I + (int64_t)slot * C::I;
+  ws.cand = ws0.cand + (int64_t)slot * C::N;
+  ws.off = ws0.off + (int64_t)slot * (C::I + 1);
+  ws.W = ws0.W + (int64_t)slot * C::I * (C::J + 1);
+  ws.r = ws0.r + (int64_t)slot * C::I;
+  ws.g = ws0.g + (int64_t)slot * C::N;
+  ws.Is = ws0.Is + (int64_t)slot * C::I;
+  ws.P = ws0.P + (int64_t)slot * C::I;
 
   // columns are taken one at a time from the counter `next` (the list holds
   // the costly ones first), so that no workgroup is left with a queue of them
@@ -517,26 +536,22 @@ __global__ void __launch_bounds__(B) k_spai(int32_t n, const int32_t* __restrict
     const int64_t k = list ? list[it] : it;
     // ---- initial pattern
     int nJ;
+    int fcode = LS_OK;
     if (init == SAI_INIT_DIAG) {
       if (tid == 0) sJ[0] = fJ[0] = (int32_t)k;
       nJ = 1;
     } else {
       nJ = cp[k + 1] - cp[k];
-      if (nJ > SJMAX) {
-        if (tid == 0) atomicOr(err, E_TOOBIG);
-        continue;
-      }
-      for (int t = tid; t < nJ; t += B) sJ[t] = fJ[t] = ri[cp[k] + t];
+      if (nJ > C::J) fcode = LS_BIG;
+      else
+        for (int t = tid; t < nJ; t += B) sJ[t] = fJ[t] = ri[cp[k] + t];
     }
     __syncthreads();
-    bool fail = false;
     int nI = 0, j0 = 0, naug = 0;
-    for (int step = 0; step < steps; ++step) {
+    for (int step = 0; step < steps && fcode == LS_OK; ++step) {
       double rr = 0.0;
-      if (!ls_extend_ws<B>(k, cp, ri, cv, fJ, j0, nJ, ws, sm, sd, hv, ht, red, wsum, s_int, nI, rr)) {
-        fail = true;
-        break;
-      }
+      fcode = ls_extend_ws<B, C>(k, cp, ri, cv, fJ, j0, nJ, ws, sm, sd, hv, ht, red, wsum, s_int, nI, rr);
+      if (fcode != LS_OK) break;
       j0 = nJ;
       if (sqrt(rr) <= delta) break;
       // ---- candidates: nonzero columns of A~(I, :), minus J
@@ -545,7 +560,7 @@ __global__ void __launch_bounds__(B) k_spai(int32_t n, const int32_t* __restrict
       const int ntot = blk_exscan<B>(ws.off, nI, wsum);
       if (tid == 0) ws.off[nI] = ntot;
       __syncthreads();
-      if (ntot > SCAPN) { fail = true; break; }
+      if (ntot > C::N) { fcode = LS_BIG; break; }
       for (int f = tid; f < ntot; f += B) {
         int lo = 0, hi = nI - 1;
         while (lo < hi) {
@@ -570,7 +585,8 @@ __global__ void __launch_bounds__(B) k_spai(int32_t n, const int32_t* __restrict
       }
       __syncthreads();
       // ---- the `add` largest gains, ties to the smaller column index
-      const int add = min(min(per, nN), SJMAX - nJ);
+      const int add = min(per, nN);
+      if (nJ + add > C::J) { fcode = LS_BIG; break; }
       for (int q = 0; q < add; ++q) {
         double bg = -1.0;
         int bt = -1;
@@ -623,8 +639,12 @@ __global__ void __launch_bounds__(B) k_spai(int32_t n, const int32_t* __restrict
       nJ = s_int[1];
       ++naug;
     }
-    if (fail) {
-      if (tid == 0) atomicOr(err, E_TOOBIG);
+    if (fcode != LS_OK) {
+      if (tid == 0) {
+        if (fcode == LS_SING) atomicOr(err, E_SING);
+        else if (ovf) ovf[atomicAdd(ovf_cnt, 1)] = (int32_t)k;
+        else atomicOr(err, E_TOOBIG);
+      }
       __syncthreads();
       continue;
     }
@@ -647,8 +667,10 @@ __global__ void __launch_bounds__(B) k_spai(int32_t n, const int32_t* __restrict
 //   equals)                                                    (tolk)
 //   stop when ||r|| <= delta (the residual before the drop).
 // The kept entries keep their values (no re-solve).  The final S and m go to
-// jpad / mpad at k * SJMAX, |S| to cntJ[k], ||r|| to res[k].
-template <int B>
+// jpad / mpad at k * C::J (or, with out_list, at the work item's position
+// times C::J), |S| to cntJ[k], ||r|| to res[k].  A column the limits C cannot
+// hold is appended to ovf (when given), else it is an error.
+template <int B, class C>
 __global__ void __launch_bounds__(B) k_psai(int32_t n, const int32_t* __restrict__ cp,
                                               const int32_t* __restrict__ ri,
                                               const double* __restrict__ cv, int lmax, double delta,
@@ -657,23 +679,24 @@ __global__ void __launch_bounds__(B) k_psai(int32_t n, const int32_t* __restrict
                                               double* __restrict__ res, Ws ws0,
                                               int32_t* __restrict__ fr0, const int32_t* __restrict__ list,
                                               int32_t nwork, int* __restrict__ err,
-                                              int32_t* __restrict__ loops) {
-  __shared__ int32_t sJ[SJMAX + 8];
-  __shared__ double sm[SJMAX];
-  __shared__ double sd[SJMAX + 1];
+                                              int32_t* __restrict__ loops, int out_list,
+                                              int32_t* __restrict__ ovf, int* __restrict__ ovf_cnt) {
+  __shared__ int32_t sJ[C::J + 8];
+  __shared__ double sm[C::J];
+  __shared__ double sd[C::J + 1];
   __shared__ double red[B / WAVE];
   __shared__ int wsum[B / WAVE + 1];
   __shared__ int s_int[4];
   const int tid = threadIdx.x;
   const int slot = blockIdx.x;
   Ws ws;
-  ws.I = ws0.I + (int64_t)slot * SCAPI;
-  ws.cand = ws0.cand + (int64_t)slot * SCAPN;
-  ws.off = ws0.off + (int64_t)slot * (SCAPI + 1);
-  ws.W = ws0.W + (int64_t)slot * SCAPI * (SJMAX + 1);
-  ws.r = ws0.r + (int64_t)slot * SCAPI;
-  ws.g = ws0.g + (int64_t)slot * SCAPN;
-  int32_t* F = fr0 + (int64_t)slot * SCAPI;  // P(a^(l)), sorted
+  ws.I = ws0.I + (int64_t)slot * C::I;
+  ws.cand = ws0.cand + (int64_t)slot * C::N;
+  ws.off = ws0.off + (int64_t)slot * (C::I + 1);
+  ws.W = ws0.W + (int64_t)slot * C::I * (C::J + 1);
+  ws.r = ws0.r + (int64_t)slot * C::I;
+  ws.g = ws0.g + (int64_t)slot * C::N;
+  int32_t* F = fr0 + (int64_t)slot * C::I;  // P(a^(l)), sorted
 
   // work item b is column list[b] (or column b when list is NULL)
   for (int64_t b = blockIdx.x; b < nwork; b += gridDim.x) {
@@ -684,7 +707,7 @@ __global__ void __launch_bounds__(B) k_psai(int32_t n, const int32_t* __restrict
     }
     int nJ = 1, nF = 1;
     __syncthreads();
-    bool fail = false;
+    int fcode = LS_OK;
     double rr = 0.0;
     int used = 0;
     for (int l = 0; l <= lmax; ++l) {
@@ -695,7 +718,7 @@ __global__ void __launch_bounds__(B) k_psai(int32_t n, const int32_t* __restrict
       const int tot = blk_exscan<B>(ws.off, nF, wsum);
       if (tid == 0) ws.off[nF] = tot;
       __syncthreads();
-      if (tot > SCAPN) { fail = true; break; }
+      if (tot > C::N) { fcode = LS_BIG; break; }
       for (int f = tid; f < tot; f += B) {
         int lo = 0, hi = nF - 1;
         while (lo < hi) {
@@ -706,7 +729,7 @@ __global__ void __launch_bounds__(B) k_psai(int32_t n, const int32_t* __restrict
       }
       __syncthreads();
       nF = blk_sort_unique<B>(ws.cand, tot, wsum);
-      if (nF > SCAPI) { fail = true; break; }
+      if (nF > C::I) { fcode = LS_BIG; break; }
       for (int t = tid; t < nF; t += B) F[t] = ws.cand[t];
       __syncthreads();
       // ---- S = S u F
@@ -714,16 +737,14 @@ __global__ void __launch_bounds__(B) k_psai(int32_t n, const int32_t* __restrict
       for (int t = tid; t < nJ; t += B) ws.cand[nF + t] = sJ[t];
       __syncthreads();
       const int nS = blk_sort_unique<B>(ws.cand, nF + nJ, wsum);
-      if (nS > SJMAX) { fail = true; break; }
+      if (nS > C::J) { fcode = LS_BIG; break; }
       for (int t = tid; t < nS; t += B) sJ[t] = ws.cand[t];
       nJ = nS;
       __syncthreads();
       // ---- least-squares solve on S
       int nI = 0;
-      if (!ls_solve_ws<B>(k, cp, ri, cv, sJ, nJ, ws, sm, sd, red, wsum, s_int, nI, rr)) {
-        fail = true;
-        break;
-      }
+      fcode = ls_solve_ws<B, C>(k, cp, ri, cv, sJ, nJ, ws, sm, sd, red, wsum, s_int, nI, rr);
+      if (fcode != LS_OK) break;
       // ---- (tolk) drop, the largest entry (first of equals) kept
       if (tid == 0) {
         const double tol = delta / ((double)nJ * a1);
@@ -744,12 +765,16 @@ __global__ void __launch_bounds__(B) k_psai(int32_t n, const int32_t* __restrict
       nJ = s_int[1];
       if (sqrt(rr) <= delta) break;
     }
-    if (fail) {
-      if (tid == 0) atomicOr(err, E_TOOBIG);
+    if (fcode != LS_OK) {
+      if (tid == 0) {
+        if (fcode == LS_SING) atomicOr(err, E_SING);
+        else if (ovf) ovf[atomicAdd(ovf_cnt, 1)] = (int32_t)k;
+        else atomicOr(err, E_TOOBIG);
+      }
       __syncthreads();
       continue;
     }
-    const int64_t o = k * SJMAX;
+    const int64_t o = (out_list ? b : k) * C::J;
     for (int t = tid; t < nJ; t += B) {
       jpad[o + t] = sJ[t];
       mpad[o + t] = sm[t];
@@ -859,17 +884,28 @@ __global__ void __launch_bounds__(SNT) k_colabs(int32_t n, const int32_t* cp, co
 }
 
 // Copy the padded rows (k * SJMAX, length cnt[k]) of a list and its values to
-// their packed offsets off[k].
+// their packed offsets off[k]; a column searched with the large limits
+// (bigpos[k] = q >= 0) is read from row q of bigJ / bigM (stride CapL::J).
 __global__ void k_compact_psai(int32_t n, const int32_t* __restrict__ jpad,
                                const double* __restrict__ mpad, const int64_t* __restrict__ off,
-                               int32_t* __restrict__ jout, double* __restrict__ mout) {
+                               int32_t* __restrict__ jout, double* __restrict__ mout,
+                               const int32_t* __restrict__ bigpos, const int32_t* __restrict__ bigJ,
+                               const double* __restrict__ bigM) {
   const int64_t k = (int64_t)blockIdx.x * SNT + threadIdx.x;
   if (k >= n) return;
-  const int64_t a = off[k], b = off[k + 1], p = k * SJMAX;
+  const int64_t a = off[k], b = off[k + 1];
+  const int32_t q = bigpos ? bigpos[k] : -1;
+  const int32_t* js = q >= 0 ? bigJ + (int64_t)q * CapL::J : jpad + k * SJMAX;
+  const double* ms = q >= 0 ? bigM + (int64_t)q * CapL::J : mpad + k * SJMAX;
   for (int64_t t = 0; t < b - a; ++t) {
-    jout[a + t] = jpad[p + t];
-    mout[a + t] = mpad[p + t];
+    jout[a + t] = js[t];
+    mout[a + t] = ms[t];
   }
+}
+
+__global__ void k_mark_list(int32_t m, const int32_t* __restrict__ list, int32_t* __restrict__ pos) {
+  const int64_t q = (int64_t)blockIdx.x * SNT + threadIdx.x;
+  if (q < m) pos[list[q]] = (int32_t)q;
 }
 
 // Step 0 of the search from J = P(A~(:, k)), solved for every column by the
@@ -996,34 +1032,54 @@ void spai_patterns(const sai_split_s* sp, const sai_build_opts& o, hipStream_t s
     // 22.5 ms with 8, 26.3 with 4, 28.2 with 16, 47.9 with 1)
     const int want = (int)tune_get("SPAI_NT", 512);
     const int bnt = (want == 64 || want == 256 || want == 1024) ? want : 512;
-    const void* kern = bnt == 64    ? (const void*)k_spai<64>
-                       : bnt == 512 ? (const void*)k_spai<512>
-                       : bnt == 1024 ? (const void*)k_spai<1024>
-                                     : (const void*)k_spai<256>;
-    const int nslot = (int)std::min<int64_t>(
-        {(int64_t)nwork, (int64_t)NSLOT_MAX, (int64_t)tune_get("SPAI_SLOTS", resident_blocks(kern, bnt))});
-    DBuf<int32_t> wI(&al, (size_t)nslot * SCAPI), wc(&al, (size_t)nslot * SCAPN),
-        wo(&al, (size_t)nslot * (SCAPI + 1)), wS(&al, (size_t)nslot * SCAPI), wP(&al, (size_t)nslot * SCAPI);
-    DBuf<double> wW(&al, (size_t)nslot * SCAPI * (SJMAX + 1)), wr(&al, (size_t)nslot * SCAPI),
-        wg(&al, (size_t)nslot * SCAPN);
-    DBuf<int> err(&al, 2);
-    HIPC(hipMemsetAsync(err.p, 0, 2 * sizeof(int), st));
-    Ws ws{wI.p, wc.p, wo.p, wW.p, wr.p, wg.p, wS.p, wP.p};
-    auto go = [&](auto k) {
-      hipLaunchKernelGGL(k, dim3(nslot), dim3(bnt), 0, st, n, sp->t_col_ptr.p, sp->t_row_idx.p,
-                         sp->t_cval.p, sp->t_row_ptr.p, sp->t_col_idx.p, cn2.p, o.spai_steps,
-                         o.spai_per_step, o.delta, o.spai_init, poff.p, pad.p, cntJ.p, ws,
-                         (const int32_t*)list.p, (int32_t)nwork, err.p + 1, err.p, taken.p);
+    DBuf<int32_t> ovf(&al, (size_t)nwork + 1);
+    DBuf<int> err(&al, 3);  // error flags, work counter, overflow count
+    HIPC(hipMemsetAsync(err.p, 0, 3 * sizeof(int), st));
+    // runs the search over `cnt` columns of `lst` with the limits C, nslot slots
+    auto search = [&](auto capc, const int32_t* lst, int cnt, int32_t* ovf_out, int* ovf_cnt, int nslot_max) {
+      using C = decltype(capc);
+      const void* kern = bnt == 64    ? (const void*)k_spai<64, C>
+                         : bnt == 512 ? (const void*)k_spai<512, C>
+                         : bnt == 1024 ? (const void*)k_spai<1024, C>
+                                       : (const void*)k_spai<256, C>;
+      const int nslot = (int)std::min<int64_t>(
+          {(int64_t)cnt, (int64_t)nslot_max, (int64_t)tune_get("SPAI_SLOTS", resident_blocks(kern, bnt))});
+      DBuf<int32_t> wI(&al, (size_t)nslot * C::I), wc(&al, (size_t)nslot * C::N),
+          wo(&al, (size_t)nslot * (C::I + 1)), wS(&al, (size_t)nslot * C::I), wP(&al, (size_t)nslot * C::I);
+      DBuf<double> wW(&al, (size_t)nslot * C::I * (C::J + 1)), wr(&al, (size_t)nslot * C::I),
+          wg(&al, (size_t)nslot * C::N);
+      HIPC(hipMemsetAsync(err.p + 1, 0, sizeof(int), st));
+      Ws ws{wI.p, wc.p, wo.p, wW.p, wr.p, wg.p, wS.p, wP.p};
+      auto go = [&](auto k) {
+        hipLaunchKernelGGL(k, dim3(nslot), dim3(bnt), 0, st, n, sp->t_col_ptr.p, sp->t_row_idx.p,
+                           sp->t_cval.p, sp->t_row_ptr.p, sp->t_col_idx.p, cn2.p, o.spai_steps,
+                           o.spai_per_step, o.delta, o.spai_init, poff.p, pad.p, cntJ.p, ws, lst,
+                           (int32_t)cnt, err.p + 1, err.p, taken.p, ovf_out, ovf_cnt);
+      };
+      if (bnt == 64) go(k_spai<64, C>);
+      else if (bnt == 512) go(k_spai<512, C>);
+      else if (bnt == 1024) go(k_spai<1024, C>);
+      else go(k_spai<256, C>);
+      LAUNCH_CHECK();
+      HIPC(hipStreamSynchronize(st));  // the workspaces are released on return
     };
-    if (bnt == 64) go(k_spai<64>);
-    else if (bnt == 512) go(k_spai<512>);
-    else if (bnt == 1024) go(k_spai<1024>);
-    else go(k_spai<256>);
-    LAUNCH_CHECK();
-    const int e = read_scalar(err.p, st);
-    if (e)
-      SAI_THROW(SAI_ETOOBIG, "SPAI search exceeded |J| <= %d, |I| <= %d or %d candidates (or a "
-                "rank-deficient block)", SJMAX, SCAPI, SCAPN);
+    search(CapS{}, (const int32_t*)list.p, nwork, ovf.p, err.p + 2, NSLOT_MAX);
+    int hs[3];
+    HIPC(hipMemcpyAsync(hs, err.p, sizeof(hs), hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    if (hs[0] & E_SING)
+      SAI_THROW(SAI_ESINGULAR, "a column least-squares block of the SPAI search is rank deficient");
+    if (hs[2] > 0) {
+      // columns that outgrew the small limits, searched again from their start
+      search(CapL{}, (const int32_t*)ovf.p, hs[2], nullptr, nullptr, NSLOT_L);
+      HIPC(hipMemcpyAsync(hs, err.p, sizeof(hs), hipMemcpyDeviceToHost, st));
+      HIPC(hipStreamSynchronize(st));
+      if (hs[0] & E_SING)
+        SAI_THROW(SAI_ESINGULAR, "a column least-squares block of the SPAI search is rank deficient");
+    }
+    if (hs[0] & E_TOOBIG)
+      SAI_THROW(SAI_ETOOBIG, "SPAI search exceeded |J| <= %d, |I| <= %d or %d candidates", CapL::J, CapL::I,
+                CapL::N);
   }
   if (l_m) {
     DBuf<int> mx(&al, 2);
@@ -1101,34 +1157,64 @@ void psai_patterns(const sai_split_s* sp, const sai_build_opts& o, hipStream_t s
                      cnt.p);
   LAUNCH_CHECK();
   const int ntodo = read_scalar(cnt.p, st);
+  // columns that outgrow the small limits: searched again with the large ones,
+  // their results in rows of bigJ / bigM (bigpos[k] = row, else -1)
+  DBuf<int32_t> bigJ, bigpos;
+  DBuf<double> bigM;
+  int nbig = 0;
   if (ntodo > 0) {
     // one wavefront per column: the problems of the first loops are small, and
     // more columns in flight pay more than threads per column (100^3 matrix,
     // every column through this kernel: 52 -> 34 ms); the SPAI search, with
     // larger problems, keeps four
     const int bnt = tune_get("PSAI_NT", 64) == 256 ? 256 : 64;
-    const void* kern = bnt == 64 ? (const void*)k_psai<64> : (const void*)k_psai<256>;
-    const int nslot = (int)std::min<int64_t>(
-        {(int64_t)ntodo, (int64_t)NSLOT_MAX, (int64_t)tune_get("SPAI_SLOTS", resident_blocks(kern, bnt))});
-    DBuf<int32_t> wI(&al, (size_t)nslot * SCAPI), wc(&al, (size_t)nslot * SCAPN),
-        wo(&al, (size_t)nslot * (SCAPI + 1)), wf(&al, (size_t)nslot * SCAPI);
-    DBuf<double> wW(&al, (size_t)nslot * SCAPI * (SJMAX + 1)), wr(&al, (size_t)nslot * SCAPI),
-        wg(&al, (size_t)nslot * SCAPN);
-    DBuf<int> err(&al, 1);
-    HIPC(hipMemsetAsync(err.p, 0, sizeof(int), st));
-    Ws ws{wI.p, wc.p, wo.p, wW.p, wr.p, wg.p};
-    auto go = [&](auto k) {
-      hipLaunchKernelGGL(k, dim3(nslot), dim3(bnt), 0, st, n, sp->t_col_ptr.p, sp->t_row_idx.p,
-                         sp->t_cval.p, o.psai_lmax, o.delta, a1, jpad.p, mpad.p, cntJ.p, res.p, ws, wf.p,
-                         (const int32_t*)list.p, (int32_t)ntodo, err.p, loops.p);
+    DBuf<int32_t> ovf(&al, (size_t)ntodo + 1);
+    DBuf<int> err(&al, 2);  // error flags, overflow count
+    HIPC(hipMemsetAsync(err.p, 0, 2 * sizeof(int), st));
+    auto search = [&](auto capc, int bthreads, const int32_t* lst, int m, int32_t* jout, double* mout,
+                      int out_list, int32_t* ovf_out, int* ovf_cnt, int nslot_max) {
+      using C = decltype(capc);
+      const void* kern = bthreads == 64 ? (const void*)k_psai<64, C> : (const void*)k_psai<256, C>;
+      const int nslot = (int)std::min<int64_t>(
+          {(int64_t)m, (int64_t)nslot_max, (int64_t)tune_get("SPAI_SLOTS", resident_blocks(kern, bthreads))});
+      DBuf<int32_t> wI(&al, (size_t)nslot * C::I), wc(&al, (size_t)nslot * C::N),
+          wo(&al, (size_t)nslot * (C::I + 1)), wf(&al, (size_t)nslot * C::I);
+      DBuf<double> wW(&al, (size_t)nslot * C::I * (C::J + 1)), wr(&al, (size_t)nslot * C::I),
+          wg(&al, (size_t)nslot * C::N);
+      Ws ws{wI.p, wc.p, wo.p, wW.p, wr.p, wg.p};
+      auto go = [&](auto k) {
+        hipLaunchKernelGGL(k, dim3(nslot), dim3(bthreads), 0, st, n, sp->t_col_ptr.p, sp->t_row_idx.p,
+                           sp->t_cval.p, o.psai_lmax, o.delta, a1, jout, mout, cntJ.p, res.p, ws, wf.p, lst,
+                           (int32_t)m, err.p, loops.p, out_list, ovf_out, ovf_cnt);
+      };
+      if (bthreads == 64) go(k_psai<64, C>);
+      else go(k_psai<256, C>);
+      LAUNCH_CHECK();
+      HIPC(hipStreamSynchronize(st));  // the workspaces are released on return
     };
-    if (bnt == 64) go(k_psai<64>);
-    else go(k_psai<256>);
-    LAUNCH_CHECK();
-    const int e = read_scalar(err.p, st);
-    if (e)
-      SAI_THROW(SAI_ETOOBIG, "PSAI(tol) exceeded |J| <= %d, |I| <= %d, %d gathered entries (or a "
-                "rank-deficient block)", SJMAX, SCAPI, SCAPN);
+    search(CapS{}, bnt, (const int32_t*)list.p, ntodo, jpad.p, mpad.p, 0, ovf.p, err.p + 1, NSLOT_MAX);
+    int hs[2];
+    HIPC(hipMemcpyAsync(hs, err.p, sizeof(hs), hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    nbig = hs[1];
+    if (!(hs[0] & E_SING) && nbig > 0) {
+      bigJ.alloc(&al, (size_t)nbig * CapL::J);
+      bigM.alloc(&al, (size_t)nbig * CapL::J);
+      bigpos.alloc(&al, (size_t)n + 1);
+      fill_i32(bigpos.p, -1, n, st);
+      hipLaunchKernelGGL(k_mark_list, dim3(grid_for(nbig, SNT)), dim3(SNT), 0, st, nbig,
+                         (const int32_t*)ovf.p, bigpos.p);
+      LAUNCH_CHECK();
+      // larger problems: four wavefronts per column
+      search(CapL{}, 256, (const int32_t*)ovf.p, nbig, bigJ.p, bigM.p, 1, nullptr, nullptr, NSLOT_L);
+      HIPC(hipMemcpyAsync(hs, err.p, sizeof(int), hipMemcpyDeviceToHost, st));
+      HIPC(hipStreamSynchronize(st));
+    }
+    if (hs[0] & E_SING)
+      SAI_THROW(SAI_ESINGULAR, "a column least-squares block of the PSAI(tol) loop is rank deficient");
+    if (hs[0] & E_TOOBIG)
+      SAI_THROW(SAI_ETOOBIG, "PSAI(tol) exceeded |J| <= %d, |I| <= %d or %d gathered entries", CapL::J,
+                CapL::I, CapL::N);
   }
   if (l_m) {
     DBuf<int> mx(&al, 2);
@@ -1143,7 +1229,8 @@ void psai_patterns(const sai_split_s* sp, const sai_build_opts& o, hipStream_t s
   jidx.alloc(&al, (size_t)jtot + 1);
   mval.alloc(&al, (size_t)jtot + 1);
   hipLaunchKernelGGL(k_compact_psai, dim3(grid_for(n, SNT)), dim3(SNT), 0, st, n, jpad.p, mpad.p,
-                     jptr.p, jidx.p, mval.p);
+                     jptr.p, jidx.p, mval.p, (const int32_t*)bigpos.p, (const int32_t*)bigJ.p,
+                     (const double*)bigM.p);
   LAUNCH_CHECK();
   rows_of_patterns(sp, st, al, jptr, jidx, iptr, iidx, cntI);
 }

@@ -161,16 +161,92 @@ def test_psai_tol_vs_oracle(name, delta, lmax, prec):
     print(f"{name}: loops {np.bincount(ls)}, worst column rel err {worst:.2e}")
 
 
-def test_psai_tol_too_big():
-    # the irregular case's power patterns pass 128 indices at the second loop
+@pytest.mark.parametrize("prec", [P.FP64, P.FP32])
+def test_psai_tol_large_patterns(prec):
+    """PSAI(tol) with a small delta on a 20 x 20 grid: most columns run all 11
+    loops and their power patterns reach 200-400 indices, past the fast
+    search's 128, so they are searched again with the large limits; against the
+    oracle's loop for every column."""
+    from oracle import psai as opsai
+    w = W.make(4, dims=(20, 20), s=2, density=0.15)
+    S = osplit.split(w.A)
+    n = w.A.shape[0]
+    g = P.Split(*P.csr_to_device(w.A))
+    pc = P.Precond(g, pattern=P.PAT_PSAI_TOL, delta=0.01, psai_lmax=10, precision=prec, keep_lists=True)
+    arr = pc.arrays()
+    jp, ji = _np(arr["j_ptr"]), _np(arr["j_idx"])
+    mf, res = _np(arr["m_full"]).astype(np.float64), _np(arr["res"])
+    Ss, ms, rs, ls = opsai.psai_tol(S.At, delta=0.01, lmax=10)
+    assert max(len(x) for x in Ss) > 128
+    assert pc.stats.l_m == int(np.max(ls))
+    tol = 1e-12 if prec == P.FP64 else 1e-7
+    for k in range(n):
+        assert np.array_equal(ji[jp[k]:jp[k + 1]], Ss[k]), k
+        assert np.linalg.norm(mf[jp[k]:jp[k + 1]] - ms[k]) <= tol * np.linalg.norm(ms[k]), k
+        assert abs(res[k] - rs[k]) <= 1e-12, (k, res[k], rs[k])
+
+
+def test_psai_tol_irregular_limits():
+    """On the irregular matrix the power patterns grow about eightfold per loop:
+    l_max = 1 (patterns up to a few hundred indices, through the large limits)
+    matches the oracle on every column; l_max = 3 needs patterns beyond 512
+    indices and is refused (SAI_ETOOBIG), as is a negative l_max (SAI_EINVAL)."""
+    from oracle import psai as opsai
     w, (rp, ci, va) = _load("c3_3000")
+    S = osplit.split(w.A)
+    n = w.A.shape[0]
     g = P.Split(rp, ci, va)
+    pc = P.Precond(g, pattern=P.PAT_PSAI_TOL, delta=0.4, psai_lmax=1, precision=P.FP64, keep_lists=True)
+    arr = pc.arrays()
+    jp, ji, mf = _np(arr["j_ptr"]), _np(arr["j_idx"]), _np(arr["m_full"])
+    Ss, ms, rs, ls = opsai.psai_tol(S.At, delta=0.4, lmax=1)
+    for k in range(n):
+        assert np.array_equal(ji[jp[k]:jp[k + 1]], Ss[k]), k
+        assert np.linalg.norm(mf[jp[k]:jp[k + 1]] - ms[k]) <= 1e-12 * np.linalg.norm(ms[k]), k
+    assert pc.stats.l_m == int(np.max(ls))
+    print(f"l_max = 1: loops {np.bincount(ls)}, largest pattern {max(len(x) for x in Ss)}")
     with pytest.raises(P.SaiError) as e:
-        P.Precond(g, pattern=P.PAT_PSAI_TOL, delta=0.4, psai_lmax=2)
+        P.Precond(g, pattern=P.PAT_PSAI_TOL, delta=0.4, psai_lmax=3)
     assert e.value.code == P.ETOOBIG
     with pytest.raises(P.SaiError) as e:
         P.Precond(g, pattern=P.PAT_PSAI_TOL, psai_lmax=-1)
     assert e.value.code == P.EINVAL
+
+
+@pytest.mark.parametrize("kind", ["A", "spai"])
+def test_standard_approach_vs_oracle(kind):
+    """The standard approach (Section 5's S-SPAI; M built on A itself, no split):
+    on the 45 x 45 workload the irregular columns give J_k of about 400 indices
+    and I_k of about 1600 rows, past the fast kernels, so the large limits
+    serve them.  Patterns bit-exact and values to 1e-12 against the oracle
+    applied to A, and the solve of A x = b with M reaches (stopb)."""
+    from oracle import spai as ospai
+    w, (rp, ci, va) = _load("c1")
+    n = w.A.shape[0]
+    g = P.Split(rp, ci, va, dense_cols=[])
+    assert g.s == 0
+    kw = (dict(pattern=P.PAT_A, drop=P.DROP_NONE) if kind == "A" else
+          dict(pattern=P.PAT_SPAI, drop=P.DROP_NONE, delta=0.4, spai_steps=3, spai_per_step=5))
+    pc = P.Precond(g, precision=P.FP64, keep_lists=True, **kw)
+    arr = pc.arrays()
+    jp, ji, mf = _np(arr["j_ptr"]), _np(arr["j_idx"]), _np(arr["m_full"])
+    C = opat.as_csc(w.A)
+    out = ospai.spai(w.A, 3, 5, 0.4, "A") if kind == "spai" else None
+    big = 0
+    for k in range(n):
+        if kind == "spai":
+            J, I, m, res, _ = out[k]
+        else:
+            J = opat.pattern_A(C, k)
+            I, m, res = olsq.solve_column(C, J, k)
+        big += len(J) > 128
+        assert np.array_equal(ji[jp[k]:jp[k + 1]], J), k
+        assert np.linalg.norm(mf[jp[k]:jp[k + 1]] - m) <= 1e-12 * np.linalg.norm(m), k
+    assert big > 0
+    x, st = P.solve(g, pc, torch.from_numpy(w.b).cuda(), eps=1e-8)
+    rr = np.linalg.norm(w.b - w.A @ _np(x)) / np.linalg.norm(w.b)
+    assert rr < 0.5e-8, rr
+    print(f"standard approach ({kind}): {big} columns with |J| > 128, iterations {st['iters']}, rr {rr:.2e}")
 
 
 def test_psai_tol_solve():
