@@ -254,6 +254,12 @@ typedef struct {
   double eps;       /* 1e-8 */
   int32_t maxit;    /* 500 */
   int32_t c_mode;   /* SAI_C_ONE (paper) | SAI_C_ONE_THEN_REFINE */
+  int32_t equilibrate; /* sai_solve only; 0: b as given; 1: Section 4's scaling:
+                          solve A (alpha x) = alpha b with alpha = rho / ||b||,
+                          rho = ||A||_F / sqrt(n) (the root-mean-square column norm
+                          of A), so that ||alpha b|| is comparable to the column
+                          norms and hence to the ||u_j||; x is scaled back.  rr is
+                          the same relative residual. */
 } sai_solve_opts;
 
 int sai_krylov(const sai_split_t* sp, const sai_precond_t* pc, int32_t transpose, int32_t k,

@@ -84,7 +84,7 @@ class PrecondInfo(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("method", C.c_int32), ("restart", C.c_int32), ("eps", C.c_double),
-                ("maxit", C.c_int32), ("c_mode", C.c_int32)]
+                ("maxit", C.c_int32), ("c_mode", C.c_int32), ("equilibrate", C.c_int32)]
 
 
 class SolveStats(C.Structure):
@@ -333,8 +333,8 @@ class Precond:
                     l_m=s.l_m, drop_flips=s.drop_flips)
 
 
-def _sopts(method=BICGSTAB, restart=30, eps=1e-8, maxit=500, c_mode=C_ONE):
-    return SolveOpts(int(method), int(restart), float(eps), int(maxit), int(c_mode))
+def _sopts(method=BICGSTAB, restart=30, eps=1e-8, maxit=500, c_mode=C_ONE, equilibrate=False):
+    return SolveOpts(int(method), int(restart), float(eps), int(maxit), int(c_mode), int(bool(equilibrate)))
 
 
 def krylov(split: Split, pc: Precond, R, thr, transpose=False, raise_on_error=True, **kw):

@@ -81,6 +81,11 @@ __global__ void __launch_bounds__(NT) k_residual_final(int nb, const double* par
   }
 }
 
+// y = a x (y may alias x)
+__global__ void k_scale_copy(int64_t n, double a, const double* x, double* y) {
+  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) y[i] = a * x[i];
+}
+
 // R = [b | U] (row-major n x (s+1))
 __global__ void k_rhs_bu(int64_t n, int s, const double* __restrict__ b,
                          const int32_t* __restrict__ urp, const int32_t* __restrict__ ucol,
@@ -341,6 +346,23 @@ void solve_impl(const sai_split_s* sp, const sai_precond_s* pc, const double* b,
   if (kk > 64) SAI_THROW(SAI_ETOOBIG, "s + 1 = %d exceeds 64 right-hand sides", kk);
   EventTimer t_solve, t_smw, t_chk;
   DBuf<double> R(&al, (size_t)n * kk), Y(&al, (size_t)n * kk);
+  // Section 4's scaling (equilibrate): solve with alpha b, alpha = rho / ||b||,
+  // rho = ||A||_F / sqrt(n) (||A||_F^2 = ||A~||_F^2 + ||U||_F^2), x scaled back
+  double alpha = 1.0;
+  DBuf<double> bs;
+  if (o.equilibrate) {
+    const double fa = dev_norm2(sp->t_val.p, sp->nnz_t, 1, al, st);
+    const double fu = sp->nnz_u > 0 ? dev_norm2(sp->u_val.p, sp->nnz_u, 1, al, st) : 0.0;
+    const double rho = std::sqrt((fa * fa + fu * fu) / (double)n);
+    const double b0 = dev_norm2(b, n, 1, al, st);
+    if (b0 > 0.0 && rho > 0.0) {
+      alpha = rho / b0;
+      bs.alloc(&al, (size_t)n);
+      hipLaunchKernelGGL(k_scale_copy, dim3(rows_grid(n)), dim3(NT), 0, st, n, alpha, b, bs.p);
+      LAUNCH_CHECK();
+      b = bs.p;
+    }
+  }
   hipLaunchKernelGGL(k_rhs_bu, dim3(rows_grid(n)), dim3(NT), 0, st, n, s, b, sp->u_row_ptr.p,
                      sp->u_col.p, sp->u_val.p, R.p);
   LAUNCH_CHECK();
@@ -377,6 +399,11 @@ void solve_impl(const sai_split_s* sp, const sai_precond_s* pc, const double* b,
     rr = residual_impl(sp, b, x, st);
     t_ref.stop(st);
     extra_ms = t_ref.ms();
+  }
+  if (alpha != 1.0) {
+    hipLaunchKernelGGL(k_scale_copy, dim3(rows_grid(n)), dim3(NT), 0, st, n, 1.0 / alpha, (const double*)x, x);
+    LAUNCH_CHECK();
+    HIPC(hipStreamSynchronize(st));
   }
   if (stats) {
     stats->s = s;

@@ -892,3 +892,25 @@ def test_gather_vs_oracle(name, kind, prec):
         big += len(I) > 256 or len(J) > 64 or len(I) * len(J) > (2048 if prec == P.FP32 else 1024)
     if name == "c3_3000":
         assert big > 0
+
+
+def test_solve_equilibrated_vs_oracle():
+    """Section 4's scaling of b (equilibrate): with b = 1e10 A 1 the unscaled
+    solve misses eps by far (c = 1 makes the auxiliary thresholds far too
+    loose), the scaled one meets rr < eps; x against the oracle's scaled solve
+    through ||A^{-1}|| times both residuals, and x(1e-10 b) = 1e-10 x(b)."""
+    w, (rp, ci, va) = _load("c2_12")
+    g = P.Split(rp, ci, va)
+    pc = P.Precond(g, pattern=P.PAT_A2, drop=P.DROP_ABS, tau=1e-3, precision=P.FP32)
+    bb = 1e10 * w.b
+    x0, st0 = P.solve(g, pc, torch.from_numpy(bb).cuda(), eps=1e-8, raise_on_error=False)
+    rr0 = np.linalg.norm(bb - w.A @ _np(x0)) / np.linalg.norm(bb)
+    x1, st1 = P.solve(g, pc, torch.from_numpy(bb).cuda(), eps=1e-8, equilibrate=True)
+    xs = _np(x1)
+    rr1 = np.linalg.norm(bb - w.A @ xs) / np.linalg.norm(bb)
+    assert rr0 > 1e-3 and rr1 < 1e-8, (rr0, rr1)
+    out = opipe.run(w.A, bb, kind="A2", drop="abs", tau=1e-3, equilibrate=True)
+    assert np.linalg.norm(xs - out["x"]) <= _forward_bound("c2_12", w.A, bb, xs, out["x"])
+    x2, st2 = P.solve(g, pc, torch.from_numpy(1e-10 * w.b).cuda(), eps=1e-8, equilibrate=True)
+    assert np.linalg.norm(_np(x2) * 1e20 - xs) <= 1e-10 * np.linalg.norm(xs)
+    print(f"unscaled rr {rr0:.2e}, scaled rr {rr1:.2e}, iterations {st1['iters']}")

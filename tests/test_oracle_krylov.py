@@ -129,3 +129,39 @@ def test_bicgstab_residual_replacement(seed, n, diag):
     b = A @ np.ones(n)
     pins.check_bicgstab_replacement(krylov.bicgstab, A, sp.identity(n, format="csr"), b,
                                     1e-14 * np.linalg.norm(b))
+
+
+def check_equilibration(run_fn, A, b):
+    """Section 4's scaling of b: with equilibrate the solve of A x = lambda b is the
+    solve of the same scaled right-hand side rho b / ||b|| for every lambda, so x
+    scales exactly with lambda (to 1e-12) with the same iteration counts, meets
+    rr < eps, and matches the dense solution within ||A^{-1}|| ||r||."""
+    base = run_fn(A, b, equilibrate=True)
+    Ad = A.toarray()
+    smin = np.linalg.svd(Ad, compute_uv=False)[-1]
+    xd = np.linalg.solve(Ad, b)
+    assert base["rr"] < 1e-8
+    assert np.linalg.norm(base["x"] - xd) <= np.linalg.norm(b - A @ base["x"]) / smin * (1 + 1e-6)
+    for lam in (1e-10, 1e10):
+        out = run_fn(A, lam * b, equilibrate=True)
+        assert out["iters"] == base["iters"], (lam, out["iters"], base["iters"])
+        assert np.linalg.norm(out["x"] - lam * base["x"]) <= 1e-12 * np.linalg.norm(lam * base["x"]), lam
+        assert out["rr"] < 1e-8
+
+
+def test_equilibration_scale_invariance():
+    from oracle import pipeline as opipe
+    w = W.make(2, dims=(12, 12, 12), s=4, density=0.2)
+    check_equilibration(lambda A, b, **kw: opipe.run(A, b, kind="A2", drop="abs", tau=1e-3, maxit=300, **kw),
+                        w.A, w.b)
+
+
+def test_equilibration_rescues_large_b():
+    """Without the scaling, b = 1e10 A 1 makes the auxiliary thresholds
+    eps ||b|| / (2 sqrt(s)) far too loose for c = 1 and rr misses eps by far; with
+    it the solve meets rr < eps."""
+    from oracle import pipeline as opipe
+    w = W.make(2, dims=(12, 12, 12), s=4, density=0.2)
+    raw = opipe.run(w.A, 1e10 * w.b, kind="A2", drop="abs", tau=1e-3)
+    eq = opipe.run(w.A, 1e10 * w.b, kind="A2", drop="abs", tau=1e-3, equilibrate=True)
+    assert raw["rr"] > 1e-3 and eq["rr"] < 1e-8

@@ -213,3 +213,24 @@ def test_bicgstab_replacement_mistakes_caught(mistake):
     b = A @ np.ones(60)
     with pytest.raises(AssertionError):
         pins.check_bicgstab_replacement(f, A, sp.identity(60, format="csr"), b, 1e-14 * np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("mistake", ["inverted_alpha", "not_scaled_back"])
+def test_equilibration_mistakes_caught(mistake):
+    from oracle import pipeline as opipe
+    from tests.test_oracle_krylov import check_equilibration
+    w = W.make(2, dims=(9, 8, 7), s=3, density=0.3)
+
+    def wrong(A, b, equilibrate=False):
+        alpha = opipe.equilibration_factor(A, b)
+        if mistake == "inverted_alpha":
+            out = opipe.run(A, b / alpha / alpha if alpha else b, kind="A2", drop="abs", tau=1e-3)
+            out["x"] = out["x"] * alpha * alpha
+            out["rr"] = float(np.linalg.norm(b - A @ out["x"]) / np.linalg.norm(b))
+            return out
+        out = opipe.run(A, b, kind="A2", drop="abs", tau=1e-3, equilibrate=True)
+        out["x"] = out["x"] * out["alpha"]
+        out["rr"] = float(np.linalg.norm(b - A @ out["x"]) / np.linalg.norm(b))
+        return out
+    with pytest.raises(AssertionError):
+        check_equilibration(wrong, w.A, w.b)
