@@ -67,9 +67,7 @@ FP64_VEC_TFLOPS = 78.6
 # register LS kernel variants in the order the library assigns columns to them
 LS_VARIANTS = {
     "f32": [(16, 8, "g16r1j8"), (32, 16, "g16r2j16"), (64, 25, "g16r4j25"), (64, 32, "g16r4j32"),
-            (128, 32, "g64r2j32"), (256, 32, "g64r4j32"), (128, 64, "g64r2j64"), (4096, 128, "big")],
-    "f64": [(16, 8, "g16r1j8"), (32, 16, "g16r2j16"), (64, 32, "g32r2j32"), (128, 32, "g64r2j32"),
-            (64, 64, "g64r1j64"), (4096, 128, "big")],
+            (128, 32, "g64r2j32"), (256, 32, "g64r4j32"), (128, 64, "g64r2j64"), (8192, 512, "big")],
 }
 
 
@@ -307,6 +305,10 @@ def main():
 
     import torch
     rp, ci, va = P.csr_to_device(w.A)
+    # the autotuner's choices for this workload class (bucket edges, launch knobs)
+    P.lib()
+    tuned = P.load_tuning(workload=name) if os.environ.get("SAI_TUNING", "on") != "off" else None
+    tuning = dict(knobs=tuned, record=P.tuning_record(name)) if tuned is not None else None
     b = torch.from_numpy(w.b).cuda()
     xstar = torch.from_numpy(W.x_star(n, w.seed)).cuda() if adjoint else None
 
@@ -427,7 +429,10 @@ def main():
     flops = ls_flops(nI.astype(np.float64), nJ.astype(np.float64))
     ls_work = {}
     assigned = np.zeros(n, dtype=bool)
-    for maxI, maxJ, tag in LS_VARIANTS["f32"]:
+    for v, (maxI, maxJ, tag) in enumerate(LS_VARIANTS["f32"]):
+        if v < len(LS_VARIANTS["f32"]) - 1:  # the bucket edges in effect (autotuned knobs)
+            maxI = P.tune_get(f"LSB_F32_{v}_I", maxI)
+            maxJ = P.tune_get(f"LSB_F32_{v}_J", maxJ)
         sel = (~assigned) & (nI <= maxI) & (nJ <= maxJ)
         assigned |= sel
         ls_work["ls_qr_f32_" + tag] = float(flops[sel].sum())
@@ -530,6 +535,7 @@ def main():
               "s": pc_m.stats.s, "p": pc_m.stats.p, "drop_undecidable_fp32": int(pc_m.stats.drop_flips),
               "fp32_vs_fp64_oracle": m_err},
         "roofline": roof,
+        "tuning": tuning,
         "gather": gather,
         "kernels_one_step": kern_table,
         "cpu_baseline": cpu,

@@ -187,20 +187,35 @@ def tune_clear():
     _check(lib().sai_tune_clear(), "sai_tune_clear")
 
 
-def load_tuning(path: Optional[str] = None) -> Optional[dict]:
+def load_tuning(path: Optional[str] = None, workload: Optional[str] = None) -> Optional[dict]:
     """Pass the knobs of a tuning file (by default tuning/<device_key()>.json,
-    written by the autotuner) to the library; returns them, or None when there
-    is no file."""
+    written by the autotuner) to the library: its device-wide knobs and, when
+    `workload` names one of its classes, that class's knobs.  Returns the knobs
+    set, or None when there is no file."""
     import json
     if path is None:
         path = os.path.join(TUNING_DIR, device_key() + ".json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
-        knobs = json.load(f)["knobs"]
+        rec = json.load(f)
+    knobs = dict(rec.get("knobs", {}))
+    if workload is not None:
+        knobs.update(rec.get("classes", {}).get(workload, {}).get("knobs", {}))
     for name, value in knobs.items():
         tune_set(name, value)
     return knobs
+
+
+def tuning_record(workload: str, path: Optional[str] = None) -> Optional[dict]:
+    """The autotuner's record for a workload class (knobs, default and tuned times)."""
+    import json
+    if path is None:
+        path = os.path.join(TUNING_DIR, device_key() + ".json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f).get("classes", {}).get(workload)
 
 
 def _check(code: int, where: str):

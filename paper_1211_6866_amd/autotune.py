@@ -1,19 +1,24 @@
-"""Autotuner for the library's launch-shape knobs (sai_tune_set, SAI_TUNE_<name>).
+"""Autotuner for the library's bucket edges and launch-shape knobs (sai_tune_set, SAI_TUNE_<name>).
 
     python -m paper_1211_6866_amd.autotune [--workload 2] [--reps 3] [--out PATH]
 
 Run from the repository root (it builds the synthetic workloads of the
-``workloads`` package).  Coordinate descent over the knobs: each knob in turn
-takes every candidate value while the others keep their current best, and is
-timed on whole steps of the workload (split, build, BiCGStab to 1e-8, SMW
-recovery), the median of ``reps`` after one warm-up; the fastest value is kept
-when it beats the current one by more than ``--margin``.  The choices are
-written to tuning/<device>.json (architecture and CU count), which the binding
-passes to the library when it is first used on that device.
+``workloads`` package).  Two searches, each keeping a change only when it beats
+the current setting by more than ``--margin``:
 
-The knobs change speed only; every setting gives deterministic results.  Knobs
-whose best value depends on the problem size (the XCD tile mapping, derived from
-the block size, and the persistent grids) are left to their built-in rules.
+* bucket edges of the column solver (knobs LSB_F32_<v>_I / _J): a column goes
+  to the first register variant whose edges hold its |I| and |J|; each variant
+  in turn is tried disabled (its columns then go to the next variant that
+  holds them), timed on the column solves of whole builds (the median of
+  ``reps`` after one warm-up);
+* launch knobs of the Krylov solve, by coordinate descent: each knob in turn
+  takes every candidate value while the others keep their current best, timed
+  on whole steps (split, build, BiCGStab to 1e-8, SMW recovery).
+
+The choices are stored per workload class (the benchmark's workload name) in
+tuning/<device>.json (architecture and CU count), with the default and tuned
+times; the benchmark loads its class's section before timing.  The knobs change
+speed only; every setting gives deterministic results.
 """
 from __future__ import annotations
 
@@ -35,17 +40,9 @@ KNOBS_SOLVE = [
 KNOBS_SPAI = [
     ("SPAI_NT", [512, 256, 1024]),     # threads per column of the SPAI search
 ]
-
-
-def settings(P, idx):
-    """Build and solve options of the BiCGStab workloads (as the benchmark uses them)."""
-    solve = dict(method=P.BICGSTAB, eps=1e-8, maxit=500)
-    psai = dict(pattern=P.PAT_A2, drop=P.DROP_ABS, tau=1e-3)
-    if idx in (2, 4, 5):
-        return psai, solve
-    if idx == 3:
-        return dict(pattern=P.PAT_SPAI, drop=P.DROP_NONE, delta=0.4, spai_steps=3, spai_per_step=5), solve
-    raise SystemExit(f"workload {idx}: the autotuner covers the BiCGStab workloads 2-5")
+# register variants of the float column solver (|I|, |J| capacities, in the
+# library's order; the global-memory variant after them is never disabled)
+LS_F32 = [(16, 8), (32, 16), (64, 25), (64, 32), (128, 32), (256, 32), (128, 64)]
 
 
 def main(argv=None):
@@ -54,64 +51,107 @@ def main(argv=None):
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--margin", type=float, default=0.01, help="relative gain needed to change a knob")
     ap.add_argument("--out", default=None)
+    ap.add_argument("--skip-solve", action="store_true", help="tune the bucket edges only")
     args = ap.parse_args(argv)
 
     import torch
     import paper_1211_6866_amd as P
     import workloads as W
+    sys.path.insert(0, os.getcwd())
+    from bench import workload_settings
 
     os.environ["SAI_TUNING"] = "off"  # start from the built-in defaults
-    bkw, skw = settings(P, args.workload)
+    name, bkw, skw, adjoint = workload_settings(P, args.workload)
+    if skw.get("method") != P.BICGSTAB:
+        raise SystemExit("the autotuner covers the BiCGStab workloads (2-5)")
     w = W.make(args.workload)
     rp, ci, va = P.csr_to_device(w.A)
     b = torch.from_numpy(w.b).cuda()
     P.lib()
     P.tune_clear()
 
+    def build_ls():
+        sp_ = P.Split(rp, ci, va)
+        pc = P.Precond(sp_, precision=P.FP32, **bkw)
+        return pc.stats.t_ls_ms
+
     def step():
         sp_ = P.Split(rp, ci, va)
         pc = P.Precond(sp_, precision=P.FP32, **bkw)
-        x, st = P.solve(sp_, pc, b, **skw)
-        return st
+        P.solve(sp_, pc, b, **skw)
 
-    def timed():
-        step()
+    def timed(f):
+        f()
         ts = []
         for _ in range(args.reps):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            step()
+            r = f()
             torch.cuda.synchronize()
-            ts.append((time.perf_counter() - t0) * 1e3)
+            ts.append(r if r is not None else (time.perf_counter() - t0) * 1e3)
         return statistics.median(ts)
 
-    knobs = KNOBS_SOLVE + (KNOBS_SPAI if bkw.get("pattern") == P.PAT_SPAI else [])
-    best = {name: vals[0] for name, vals in knobs}
-    for name, v in best.items():
-        P.tune_set(name, v)
-    base = timed()
-    print(f"autotune: workload {args.workload}, defaults {base:.2f} ms per step", flush=True)
-    for name, vals in knobs:
-        cur = best[name]
-        cur_ms = base
-        for v in vals:
-            if v == cur:
-                continue
-            P.tune_set(name, v)
-            ms = timed()
-            print(f"autotune: {name}={v}: {ms:.2f} ms (current {name}={cur}: {cur_ms:.2f})", flush=True)
-            if ms < cur_ms * (1.0 - args.margin):
-                cur, cur_ms = v, ms
-        best[name] = cur
-        base = cur_ms
-        P.tune_set(name, cur)
+    chosen = {}
+    step_default = timed(step)  # every knob at its built-in default
+    print(f"autotune: {name}: {step_default:.2f} ms per step with the built-in defaults", flush=True)
+    # ---- bucket edges (float column solver)
+    ls_default = timed(build_ls)
+    ls_best = ls_default
+    print(f"autotune: {name}: column solves {ls_default:.3f} ms with the default edges", flush=True)
+    for v, (ci_, cj_) in enumerate(LS_F32):
+        kn = f"LSB_F32_{v}_I"
+        P.tune_set(kn, 0)
+        ms = timed(build_ls)
+        print(f"autotune: variant {v} ({ci_} x {cj_}) disabled: {ms:.3f} ms (current {ls_best:.3f})",
+              flush=True)
+        if ms < ls_best * (1.0 - args.margin):
+            ls_best = ms
+            chosen[kn] = 0
+        else:
+            P.tune_set(kn, ci_)
+    # ---- Krylov launch knobs
+    base = step_default
+    if not args.skip_solve:
+        knobs = KNOBS_SOLVE + (KNOBS_SPAI if bkw.get("pattern") == P.PAT_SPAI else [])
+        s = P.Split(rp, ci, va).s
+        if w.A.shape[0] * 8 * (s + 2) > (256 << 20):
+            # the tile-to-XCD map of blocks larger than the MALL
+            knobs = knobs + [("XCHUNK", [0, 3200, 12800])]
+        best = {kname: vals[0] for kname, vals in knobs}
+        for kname, v in best.items():
+            P.tune_set(kname, v)
+        base = timed(step)
+        print(f"autotune: {name}: {base:.2f} ms per step (tuned edges, default launch knobs)", flush=True)
+        for kname, vals in knobs:
+            cur, cur_ms = best[kname], base
+            for v in vals:
+                if v == cur:
+                    continue
+                P.tune_set(kname, v)
+                ms = timed(step)
+                print(f"autotune: {kname}={v}: {ms:.2f} ms (current {kname}={cur}: {cur_ms:.2f})", flush=True)
+                if ms < cur_ms * (1.0 - args.margin):
+                    cur, cur_ms = v, ms
+            best[kname] = cur
+            base = cur_ms
+            P.tune_set(kname, cur)
+            if cur != vals[0]:
+                chosen[kname] = cur
     out = args.out or os.path.join(P.TUNING_DIR, P.device_key() + ".json")
+    rec = {}
+    if os.path.exists(out):
+        with open(out) as f:
+            rec = json.load(f)
+    rec.setdefault("device", P.device_key())
+    rec.setdefault("knobs", {})
+    rec.setdefault("classes", {})
+    rec["classes"][name] = dict(knobs=chosen, column_solves_ms=dict(default=round(ls_default, 3),
+                                                                    tuned=round(ls_best, 3)),
+                                step_ms=dict(default=round(step_default, 3), tuned=round(base, 3)))
     os.makedirs(os.path.dirname(out), exist_ok=True)
-    rec = dict(device=P.device_key(), workload=args.workload, step_ms=round(base, 3),
-               knobs={k: v for k, v in best.items() if v != dict(knobs)[k][0]})
     with open(out, "w") as f:
         json.dump(rec, f, indent=1)
-    print(f"autotune: {json.dumps(rec)} -> {out}", flush=True)
+    print(f"autotune: {name}: {json.dumps(rec['classes'][name])} -> {out}", flush=True)
     return 0
 
 

@@ -660,8 +660,23 @@ int solve_columns(const sai_split_s* sp, const int64_t* jptr, const int32_t* jid
   using VT = VariantTable<T>;
   const int32_t n = sp->n;
   constexpr int NV = VT::N;
+  // bucket edges: a column goes to the first variant v with |I| <= edgeI[v] and
+  // |J| <= edgeJ[v]; the edges default to the variants' capacities and can be
+  // lowered (0 disables a variant) by the knobs LSB_<F32|F64>_<v>_I / _J, which
+  // the autotuner sets per workload class.  The last variant (global memory)
+  // always keeps its capacity, so every column within the limits has a home.
   int hmaxI[NV], hmaxJ[NV];
-  for (int v = 0; v < NV; ++v) { hmaxI[v] = VT::v[v].maxI; hmaxJ[v] = VT::v[v].maxJ; }
+  for (int v = 0; v < NV; ++v) {
+    hmaxI[v] = VT::v[v].maxI;
+    hmaxJ[v] = VT::v[v].maxJ;
+    if (v < NV - 1) {
+      char kn[64];
+      snprintf(kn, sizeof(kn), "LSB_%s_%d_I", sizeof(T) == 4 ? "F32" : "F64", v);
+      hmaxI[v] = std::max(0, std::min(hmaxI[v], tune_get(kn, hmaxI[v])));
+      snprintf(kn, sizeof(kn), "LSB_%s_%d_J", sizeof(T) == 4 ? "F32" : "F64", v);
+      hmaxJ[v] = std::max(0, std::min(hmaxJ[v], tune_get(kn, hmaxJ[v])));
+    }
+  }
   DBuf<int> vmax(&al, 2 * NV), bcount(&al, NV + 1), bcur(&al, NV + 1), nsing(&al, 1);
   DBuf<int32_t> bucket(&al, (size_t)n);
   HIPC(hipMemcpyAsync(vmax.p, hmaxI, sizeof(int) * NV, hipMemcpyHostToDevice, st));
