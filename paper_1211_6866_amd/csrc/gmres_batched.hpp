@@ -1,0 +1,530 @@
+// Batched right-preconditioned GMRES(m) for the k columns of a block (included by
+// krylov.hip after the BiCGStab driver).  Section 5 names GMRES(20) among the
+// solvers tried on the s+1 systems; this form runs the k systems in lockstep, so
+// that each product with M and with A~ streams the matrix once for all columns
+// (the same tiled products as BiCGStab), where the per-column form runs one
+// workgroup per column through the whole solve.
+//
+// The systems live in n x kp row-major blocks (kp = k rounded up to even; the
+// pad column is never active).  Per Arnoldi step j of a cycle, for the columns
+// still in the cycle:
+//   Z = M V_j;  W = A~ Z;
+//   h = V_{0..j}^T W;  W -= V h;  h' = V_{0..j}^T W;  W -= V h'   (classical
+//   Gram-Schmidt with one reorthogonalisation: the projection of modified
+//   Gram-Schmidt in exact arithmetic, as stable in practice, and two passes
+//   over the basis instead of j + 1);
+//   H[0..j, j] = h + h';  H[j+1, j] = ||W||;  Givens rotations as in the
+//   per-column form;  V_{j+1} = W / H[j+1, j].
+// A column leaves the cycle when its rotated residual estimate |g[j+1]| is
+// below its threshold, H[j+1, j] = 0, maxit is reached or j + 1 = m.  At the
+// end of the cycle every column of the cycle solves its triangular system,
+// takes x += M (V y), and its true residual R - A~ x decides convergence (and
+// restarts the next cycle from it).  Dot products are reduced per workgroup
+// and the partial sums added in a fixed order (deterministic results); the
+// small per-column work (rotations, triangular solves, status) runs in
+// one-block kernels, one thread per column, so the host only reads the active
+// count once per cycle.
+#pragma once
+
+namespace sai {
+namespace {
+
+constexpr int GB_NT = 256;
+constexpr int GB_NB = 512;     // workgroups of the reductions (partial sums per column)
+constexpr int GB_CH = 32;      // basis vectors per projection launch
+constexpr int GB_Q = GM_MAXM + 1;
+
+// per-column state, 64 entries each
+struct GbState {
+  int* arn;       // 0 while the column is in the Arnoldi steps of the cycle
+  int* cyc;       // 0 for the columns of the current cycle
+  int* zero;      // 64 zeros (no column skipped)
+  int* any_arn;   // [3]: columns in the Arnoldi steps
+  int* any_cyc;   // [3]: columns of the cycle
+  int* st;        // ST_ACTIVE / ST_CONV / ST_MAXIT
+  int* kk;        // steps of the current cycle
+  int* it;        // iterations so far
+  int* any_st;    // [3]: active columns
+  double *thr, *beta, *a, *g, *cs, *sn, *y, *H, *hh, *hh2, *nn;
+};
+
+// Columns of a thread in the reductions: c = t % kp of rows t / kp + RG b, ...
+#define GB_COLS                                  \
+  const int t_ = threadIdx.x;                    \
+  const int rg = GB_NT / kp;                     \
+  const int c = t_ % kp, ro = t_ / kp;           \
+  (void)c;
+
+// B = R (pad column 0), X = 0, W = B
+__global__ void __launch_bounds__(GB_NT) k_gb_load(int64_t n, int k, int kp, const double* __restrict__ R,
+                                                  double* __restrict__ B, double* __restrict__ X,
+                                                  double* __restrict__ W) {
+  const int64_t nk = n * kp;
+  for (int64_t t = (int64_t)blockIdx.x * GB_NT + threadIdx.x; t < nk; t += (int64_t)gridDim.x * GB_NT) {
+    const int64_t i = t / kp;
+    const int c = (int)(t % kp);
+    const double b = c < k ? R[i * k + c] : 0.0;
+    B[t] = b;
+    X[t] = 0.0;
+    W[t] = b;
+  }
+}
+
+// The basis V_0, V_1, ... is one array, V_q at Vb + q nk (nk = n kp).
+//
+// part[blk][q0 + q][c] = sum over the block's rows of V_{q0+q}[i, c] W[i, c]
+// (q < nv <= GB_CH) for the columns with act[c] == 0; others 0
+__global__ void __launch_bounds__(GB_NT) k_gb_dots(int64_t n, int kp, int q0, int nv, const double* __restrict__ Vb,
+                                                  const double* __restrict__ W, const int* __restrict__ act,
+                                                  const int* __restrict__ cnt, double* __restrict__ part) {
+  if (cnt[3] == 0) return;
+  __shared__ double red[GB_NT];
+  GB_COLS
+  const bool on = ro < rg && act[c] == 0;
+  const int64_t nk = n * kp;
+  const double* V0 = Vb + nk * q0;
+  double acc[GB_CH];
+#pragma unroll
+  for (int q = 0; q < GB_CH; ++q) acc[q] = 0.0;
+  if (on) {
+    for (int64_t i = (int64_t)blockIdx.x * rg + ro; i < n; i += (int64_t)gridDim.x * rg) {
+      const int64_t e = i * kp + c;
+      const double w = W[e];
+#pragma unroll
+      for (int q = 0; q < GB_CH; ++q)
+        if (q < nv) acc[q] += V0[nk * q + e] * w;
+    }
+  }
+  // (unrolled, so that acc stays in registers; nv is uniform over the block)
+#pragma unroll
+  for (int q = 0; q < GB_CH; ++q) {
+    if (q < nv) {
+      red[t_] = on ? acc[q] : 0.0;
+      __syncthreads();
+      if (t_ < kp) {
+        double s = 0.0;
+        for (int r = 0; r < rg; ++r) s += red[r * kp + t_];
+        part[((int64_t)blockIdx.x * GB_Q + q0 + q) * 64 + t_] = s;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// W -= sum_q h[q0 + q][c] V_{q0+q} (q < nv <= GB_CH) for the columns with
+// act[c] == 0; with norm: part[blk][0][c] = sum over the block's rows of the new
+// W[i, c]^2.  The same thread-to-element map as k_gb_dots.
+__global__ void __launch_bounds__(GB_NT) k_gb_project(int64_t n, int kp, int q0, int nv,
+                                                     const double* __restrict__ Vb,
+                                                     const double* __restrict__ h, double* __restrict__ W,
+                                                     const int* __restrict__ act, const int* __restrict__ cnt,
+                                                     int norm, double* __restrict__ part) {
+  if (cnt[3] == 0) return;
+  __shared__ double red[GB_NT];
+  GB_COLS
+  const bool on = ro < rg && act[c] == 0;
+  const int64_t nk = n * kp;
+  const double* V0 = Vb + nk * q0;
+  double hq[GB_CH];
+#pragma unroll
+  for (int q = 0; q < GB_CH; ++q) hq[q] = (on && q < nv) ? h[(q0 + q) * 64 + c] : 0.0;
+  double acc = 0.0;
+  if (on) {
+    for (int64_t i = (int64_t)blockIdx.x * rg + ro; i < n; i += (int64_t)gridDim.x * rg) {
+      const int64_t e = i * kp + c;
+      double w = W[e];
+#pragma unroll
+      for (int q = 0; q < GB_CH; ++q)
+        if (q < nv) w -= hq[q] * V0[nk * q + e];
+      W[e] = w;
+      acc += w * w;
+    }
+  }
+  if (norm) {
+    red[t_] = on ? acc : 0.0;
+    __syncthreads();
+    if (t_ < kp) {
+      double s = 0.0;
+      for (int r = 0; r < rg; ++r) s += red[r * kp + t_];
+      part[(int64_t)blockIdx.x * GB_Q * 64 + t_] = s;
+    }
+  }
+}
+
+// W = B - AX and part[blk][0][c] = sum over the block's rows of W[i, c]^2 for
+// the columns with act[c] == 0
+__global__ void __launch_bounds__(GB_NT) k_gb_resid(int64_t n, int kp, const double* __restrict__ B,
+                                                   const double* __restrict__ AX, double* __restrict__ W,
+                                                   const int* __restrict__ act, const int* __restrict__ cnt,
+                                                   double* __restrict__ part) {
+  if (cnt[3] == 0) return;
+  __shared__ double red[GB_NT];
+  GB_COLS
+  const bool on = ro < rg && act[c] == 0;
+  double acc = 0.0;
+  if (on) {
+    for (int64_t i = (int64_t)blockIdx.x * rg + ro; i < n; i += (int64_t)gridDim.x * rg) {
+      const int64_t e = i * kp + c;
+      const double w = B[e] - AX[e];
+      W[e] = w;
+      acc += w * w;
+    }
+  }
+  red[t_] = on ? acc : 0.0;
+  __syncthreads();
+  if (t_ < kp) {
+    double s = 0.0;
+    for (int r = 0; r < rg; ++r) s += red[r * kp + t_];
+    part[(int64_t)blockIdx.x * GB_Q * 64 + t_] = s;
+  }
+}
+
+// out[q][c] = sum over the nb workgroups, in order, of part[blk][q][c] (one
+// block per q; four groups of 64 threads take every fourth workgroup, then
+// their sums are added in order)
+__global__ void __launch_bounds__(GB_NT) k_gb_fin(int nb, int kp, const double* __restrict__ part,
+                                                 double* __restrict__ out) {
+  __shared__ double red[GB_NT];
+  const int q = blockIdx.x;
+  const int c = threadIdx.x % 64, grp = threadIdx.x / 64;
+  double s = 0.0;
+  if (c < kp)
+    for (int b = grp; b < nb; b += GB_NT / 64) s += part[((int64_t)b * GB_Q + q) * 64 + c];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x < 64)
+    out[q * 64 + c] = c < kp ? ((red[c] + red[64 + c]) + red[128 + c]) + red[192 + c] : 0.0;
+}
+
+// dst = a[c] src for the columns with act[c] == 0
+__global__ void __launch_bounds__(GB_NT) k_gb_scale(int64_t n, int kp, const double* __restrict__ a,
+                                                   const double* __restrict__ src, double* __restrict__ dst,
+                                                   const int* __restrict__ act, const int* __restrict__ cnt) {
+  if (cnt[3] == 0) return;
+  const int64_t nk = n * kp;
+  for (int64_t t = (int64_t)blockIdx.x * GB_NT + threadIdx.x; t < nk; t += (int64_t)gridDim.x * GB_NT) {
+    const int c = (int)(t % kp);
+    if (act[c] == 0) dst[t] = a[c] * src[t];
+  }
+}
+
+// Z[i, c] = sum_{q < kk[c]} y[q][c] V_q[i, c] for the columns with act[c] == 0
+__global__ void __launch_bounds__(GB_NT) k_gb_combine(int64_t n, int kp, const double* __restrict__ Vb,
+                                                     const double* __restrict__ y,
+                                                     const int* __restrict__ kk, double* __restrict__ Z,
+                                                     const int* __restrict__ act, const int* __restrict__ cnt) {
+  if (cnt[3] == 0) return;
+  const int64_t nk = n * kp;
+  for (int64_t t = (int64_t)blockIdx.x * GB_NT + threadIdx.x; t < nk; t += (int64_t)gridDim.x * GB_NT) {
+    const int c = (int)(t % kp);
+    if (act[c] != 0) continue;
+    double s = 0.0;
+    for (int q = 0; q < kk[c]; ++q) s += y[q * 64 + c] * Vb[nk * q + t];
+    Z[t] = s;
+  }
+}
+
+// X += D for the columns with act[c] == 0
+__global__ void __launch_bounds__(GB_NT) k_gb_add(int64_t n, int kp, const double* __restrict__ D,
+                                                 double* __restrict__ X, const int* __restrict__ act,
+                                                 const int* __restrict__ cnt) {
+  if (cnt[3] == 0) return;
+  const int64_t nk = n * kp;
+  for (int64_t t = (int64_t)blockIdx.x * GB_NT + threadIdx.x; t < nk; t += (int64_t)gridDim.x * GB_NT)
+    if (act[t % kp] == 0) X[t] += D[t];
+}
+
+// caller's X (n x k) from the block (n x kp)
+__global__ void __launch_bounds__(GB_NT) k_gb_out(int64_t n, int k, int kp, const double* __restrict__ Xb,
+                                                 double* __restrict__ X) {
+  const int64_t nk = n * k;
+  for (int64_t t = (int64_t)blockIdx.x * GB_NT + threadIdx.x; t < nk; t += (int64_t)gridDim.x * GB_NT)
+    X[t] = Xb[(t / k) * kp + t % k];
+}
+
+// ---- one-block kernels, thread c for column c ---------------------------------------
+
+__device__ __forceinline__ void gb_count(const int* flag, int k, int* any) {
+  __shared__ int s;
+  if (threadIdx.x == 0) s = 0;
+  __syncthreads();
+  if (threadIdx.x < k && flag[threadIdx.x] == 0) atomicAdd(&s, 1);
+  __syncthreads();
+  if (threadIdx.x == 0) any[3] = s;
+}
+
+// status from the initial residual norm (x = 0, r = R)
+__global__ void __launch_bounds__(64) k_gb_setup(int k, int maxit, GbState G) {
+  const int c = threadIdx.x;
+  if (c < k) {
+    const double b = sqrt(G.nn[c]);
+    G.beta[c] = b;
+    G.it[c] = 0;
+    G.st[c] = b < G.thr[c] ? ST_CONV : (maxit <= 0 ? ST_MAXIT : ST_ACTIVE);
+  }
+  __syncthreads();
+  gb_count(G.st, k, G.any_st);
+}
+
+// start a cycle for every active column: V_0 = r / beta (a = 1 / beta), g = beta e_1
+__global__ void __launch_bounds__(64) k_gb_cycle_start(int k, int m, GbState G) {
+  const int c = threadIdx.x;
+  const bool on = c < k && G.st[c] == ST_ACTIVE;
+  G.arn[c] = on ? 0 : 1;
+  G.cyc[c] = on ? 0 : 1;
+  G.kk[c] = 0;
+  G.a[c] = on ? 1.0 / G.beta[c] : 0.0;
+  for (int q = 0; q <= m; ++q) G.g[q * 64 + c] = q == 0 && on ? G.beta[c] : 0.0;
+  __syncthreads();
+  gb_count(G.arn, k, G.any_arn);
+  gb_count(G.cyc, k, G.any_cyc);
+}
+
+// Arnoldi step j: the new column of H from the two projections and ||W||, the
+// previous rotations, a new rotation, the residual estimate and the exit test
+__global__ void __launch_bounds__(64) k_gb_step(int k, int m, int j, int maxit, GbState G) {
+  const int c = threadIdx.x;
+  if (c < k && G.arn[c] == 0) {
+    double* H = G.H;
+    auto h = [&](int q, int jj) -> double& { return H[((int64_t)q * GM_MAXM + jj) * 64 + c]; };
+    for (int q = 0; q <= j; ++q) h(q, j) = G.hh[q * 64 + c] + G.hh2[q * 64 + c];
+    const double hnext = sqrt(G.nn[c]);
+    h(j + 1, j) = hnext;
+    for (int q = 0; q < j; ++q) {
+      const double a = h(q, j), b = h(q + 1, j);
+      const double cq = G.cs[q * 64 + c], sq = G.sn[q * 64 + c];
+      h(q, j) = cq * a + sq * b;
+      h(q + 1, j) = -sq * a + cq * b;
+    }
+    const double a = h(j, j), b = h(j + 1, j);
+    double cc = 1.0, ss = 0.0;
+    if (b != 0.0) {
+      const double r = hypot(a, b);
+      cc = a / r;
+      ss = b / r;
+    }
+    G.cs[j * 64 + c] = cc;
+    G.sn[j * 64 + c] = ss;
+    h(j, j) = cc * a + ss * b;
+    h(j + 1, j) = 0.0;
+    const double gj = G.g[j * 64 + c];
+    G.g[(j + 1) * 64 + c] = -ss * gj;
+    G.g[j * 64 + c] = cc * gj;
+    G.kk[c] = j + 1;
+    const int it = ++G.it[c];
+    const bool leave = hnext == 0.0 || fabs(G.g[(j + 1) * 64 + c]) < G.thr[c] || it >= maxit || j + 1 == m;
+    if (leave) G.arn[c] = 1;
+    else G.a[c] = 1.0 / hnext;
+  }
+  __syncthreads();
+  gb_count(G.arn, k, G.any_arn);
+}
+
+// y = H(0:kk, 0:kk)^{-1} g(0:kk) for the columns of the cycle
+__global__ void __launch_bounds__(64) k_gb_backsolve(int k, GbState G) {
+  const int c = threadIdx.x;
+  if (c >= k || G.cyc[c] != 0) return;
+  const int kk = G.kk[c];
+  for (int q = kk - 1; q >= 0; --q) {
+    double s = G.g[q * 64 + c];
+    for (int u = q + 1; u < kk; ++u) s -= G.H[((int64_t)q * GM_MAXM + u) * 64 + c] * G.y[u * 64 + c];
+    G.y[q * 64 + c] = s / G.H[((int64_t)q * GM_MAXM + q) * 64 + c];
+  }
+}
+
+// convergence on the true residual at the end of a cycle
+__global__ void __launch_bounds__(64) k_gb_cycle_end(int k, int maxit, GbState G) {
+  const int c = threadIdx.x;
+  if (c < k && G.cyc[c] == 0) {
+    const double b = sqrt(G.nn[c]);
+    G.beta[c] = b;
+    G.st[c] = b < G.thr[c] ? ST_CONV : (G.it[c] >= maxit ? ST_MAXIT : ST_ACTIVE);
+  }
+  __syncthreads();
+  gb_count(G.st, k, G.any_st);
+}
+
+template <int LP, class TM>
+int gmres_batched_lp(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, const double* R, double* X,
+                     const double* thr, int m, int maxit, const Allocator& al, hipStream_t st, int* iters,
+                     int* status) {
+  const int kp = k + (k & 1);
+  const size_t nk = (size_t)n * kp;
+  DBuf<double> basis(&al, nk * (size_t)(m + 1));
+  DBuf<double> Bv(&al, nk), Xv(&al, nk), Wv(&al, nk), Zv(&al, nk);
+  DBuf<double> part(&al, (size_t)GB_NB * GB_Q * 64);
+  // thr, beta, a, nn; g; cs, sn, y; hh, hh2; H
+  DBuf<double> sd(&al, (size_t)64 * (4 + GB_Q + 2 * GM_MAXM + GM_MAXM + 2 * GB_Q) +
+                           (size_t)GB_Q * GM_MAXM * 64);
+  DBuf<int> si(&al, 64 * 6 + 3 * 8);
+  GbState G{};
+  G.arn = si.p;
+  G.cyc = si.p + 64;
+  G.zero = si.p + 128;
+  G.st = si.p + 192;
+  G.kk = si.p + 256;
+  G.it = si.p + 320;
+  G.any_arn = si.p + 384;
+  G.any_cyc = si.p + 392;
+  G.any_st = si.p + 400;
+  double* d = sd.p;
+  G.thr = d; d += 64;
+  G.beta = d; d += 64;
+  G.a = d; d += 64;
+  G.nn = d; d += 64;
+  G.g = d; d += 64 * GB_Q;
+  G.cs = d; d += 64 * GM_MAXM;
+  G.sn = d; d += 64 * GM_MAXM;
+  G.y = d; d += 64 * GM_MAXM;
+  G.hh = d; d += 64 * GB_Q;
+  G.hh2 = d; d += 64 * GB_Q;
+  G.H = d;
+  HIPC(hipMemsetAsync(si.p, 0, sizeof(int) * (64 * 6 + 3 * 8), st));
+  HIPC(hipMemsetAsync(sd.p, 0, sizeof(double) * 64 * 4, st));
+  HIPC(hipMemcpyAsync(G.thr, thr, sizeof(double) * k, hipMemcpyHostToDevice, st));
+
+  const double* Vb = basis.p;
+  // the sparse products of the BiCGStab driver, on the columns whose flag is 0
+  State Sarn{}, Scyc{};
+  Sarn.status = G.arn;
+  Sarn.skip = G.zero;
+  Sarn.any = G.any_arn;
+  Scyc.status = G.cyc;
+  Scyc.skip = G.zero;
+  Scyc.any = G.any_cyc;
+  constexpr int RPB = (64 / LP) * (NT / 64);
+  const int xmap = tune_get("XMAP", nk * sizeof(double) <= (size_t(256) << 20) ? 1 : 0);
+  auto sp_grid = [&](const void* kern) {
+    const int64_t ntiles = (n + RPB - 1) / RPB;
+    int64_t g = std::min<int64_t>({(int64_t)NBMAX, ntiles, (int64_t)resident_blocks(kern, NT)});
+    return (int)(g >= 8 ? (g & ~int64_t(7)) : g);
+  };
+  const void* km = (const void*)k_spmm<LP, TM, 6, 3>;
+  const void* ka = (const void*)k_spmm<LP, double, 6, 3>;
+  const int gm = sp_grid(km), ga = sp_grid(ka);
+  auto mprod = [&](const double* in, double* out, const State& S) {
+    hipLaunchKernelGGL((k_spmm<LP, TM, 6, 3>), dim3(gm), dim3(NT), 0, st, n, k, kp, M, in, out, S, xmap);
+  };
+  auto aprod = [&](const double* in, double* out, const State& S) {
+    hipLaunchKernelGGL((k_spmm<LP, double, 6, 3>), dim3(ga), dim3(NT), 0, st, n, k, kp, A, in, out, S, xmap);
+  };
+  const int rg = GB_NT / kp;
+  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(GB_NB, (n + rg - 1) / rg));
+  const unsigned eg = grid_for((int64_t)nk, GB_NT, 4096);
+  // h (nv values per column) = V_{0..nv-1}^T W
+  auto dots = [&](int nv, const double* W, double* out) {
+    for (int q0 = 0; q0 < nv; q0 += GB_CH)
+      hipLaunchKernelGGL(k_gb_dots, dim3(nb), dim3(GB_NT), 0, st, n, kp, q0, std::min(GB_CH, nv - q0), Vb, W,
+                         G.arn, G.any_arn, part.p);
+    hipLaunchKernelGGL(k_gb_fin, dim3(nv), dim3(GB_NT), 0, st, nb, kp, part.p, out);
+  };
+  // W -= V h (chunks of GB_CH vectors; the norm with the last chunk)
+  auto project = [&](int nv, const double* h, double* W, bool norm) {
+    for (int q0 = 0; q0 < nv; q0 += GB_CH) {
+      const bool last = q0 + GB_CH >= nv;
+      hipLaunchKernelGGL(k_gb_project, dim3(nb), dim3(GB_NT), 0, st, n, kp, q0, std::min(GB_CH, nv - q0), Vb, h,
+                         W, G.arn, G.any_arn, norm && last ? 1 : 0, part.p);
+    }
+    if (norm) hipLaunchKernelGGL(k_gb_fin, dim3(1), dim3(GB_NT), 0, st, nb, kp, part.p, G.nn);
+  };
+
+  HostStage hs(16);
+  int* cnt = hs.as<int>();
+  {
+    SAI_PROF("gmres_init", st);
+    hipLaunchKernelGGL(k_gb_load, dim3(eg), dim3(GB_NT), 0, st, n, k, kp, R, Bv.p, Xv.p, Wv.p);
+    // ||R|| per column (the "cycle" set is every column here)
+    HIPC(hipMemsetAsync(G.any_cyc, 0xff, sizeof(int) * 8, st));
+    hipLaunchKernelGGL(k_gb_resid, dim3(nb), dim3(GB_NT), 0, st, n, kp, Bv.p, Xv.p, Wv.p, G.zero, G.any_cyc,
+                       part.p);
+    hipLaunchKernelGGL(k_gb_fin, dim3(1), dim3(GB_NT), 0, st, nb, kp, part.p, G.nn);
+    hipLaunchKernelGGL(k_gb_setup, dim3(1), dim3(64), 0, st, k, maxit, G);
+  }
+  LAUNCH_CHECK();
+  for (;;) {
+    HIPC(hipMemcpyAsync(cnt, G.any_st + 3, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    if (cnt[0] == 0) break;
+    {
+      SAI_PROF("gmres_cycle_start", st);
+      hipLaunchKernelGGL(k_gb_cycle_start, dim3(1), dim3(64), 0, st, k, m, G);
+      hipLaunchKernelGGL(k_gb_scale, dim3(eg), dim3(GB_NT), 0, st, n, kp, G.a, Wv.p, basis.p, G.cyc,
+                         G.any_cyc);
+    }
+    for (int j = 0; j < m; ++j) {
+      {
+        SAI_PROF(sizeof(TM) == 4 ? "gmres_spmm_M_f32" : "gmres_spmm_M_f64", st);
+        mprod(Vb + nk * j, Zv.p, Sarn);
+      }
+      {
+        SAI_PROF("gmres_spmm_A", st);
+        aprod(Zv.p, Wv.p, Sarn);
+      }
+      {
+        SAI_PROF("gmres_orth", st);
+        dots(j + 1, Wv.p, G.hh);
+        project(j + 1, G.hh, Wv.p, false);
+        dots(j + 1, Wv.p, G.hh2);
+        project(j + 1, G.hh2, Wv.p, true);
+      }
+      {
+        SAI_PROF("gmres_step", st);
+        hipLaunchKernelGGL(k_gb_step, dim3(1), dim3(64), 0, st, k, m, j, maxit, G);
+        if (j + 1 < m)
+          hipLaunchKernelGGL(k_gb_scale, dim3(eg), dim3(GB_NT), 0, st, n, kp, G.a, Wv.p,
+                             basis.p + nk * (j + 1), G.arn, G.any_arn);
+      }
+      LAUNCH_CHECK();
+    }
+    {
+      SAI_PROF("gmres_cycle_end", st);
+      hipLaunchKernelGGL(k_gb_backsolve, dim3(1), dim3(64), 0, st, k, G);
+      hipLaunchKernelGGL(k_gb_combine, dim3(eg), dim3(GB_NT), 0, st, n, kp, Vb, G.y, G.kk, Zv.p, G.cyc,
+                         G.any_cyc);
+      mprod(Zv.p, Wv.p, Scyc);
+      hipLaunchKernelGGL(k_gb_add, dim3(eg), dim3(GB_NT), 0, st, n, kp, Wv.p, Xv.p, G.cyc, G.any_cyc);
+      aprod(Xv.p, Zv.p, Scyc);
+      hipLaunchKernelGGL(k_gb_resid, dim3(nb), dim3(GB_NT), 0, st, n, kp, Bv.p, Zv.p, Wv.p, G.cyc, G.any_cyc,
+                         part.p);
+      hipLaunchKernelGGL(k_gb_fin, dim3(1), dim3(GB_NT), 0, st, nb, kp, part.p, G.nn);
+      hipLaunchKernelGGL(k_gb_cycle_end, dim3(1), dim3(64), 0, st, k, maxit, G);
+    }
+    LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL(k_gb_out, dim3(grid_for((int64_t)n * k, GB_NT, 4096)), dim3(GB_NT), 0, st, n, k, kp, Xv.p,
+                     X);
+  LAUNCH_CHECK();
+  std::vector<int> hst(k), hit(k);
+  HIPC(hipMemcpyAsync(hst.data(), G.st, sizeof(int) * k, hipMemcpyDeviceToHost, st));
+  HIPC(hipMemcpyAsync(hit.data(), G.it, sizeof(int) * k, hipMemcpyDeviceToHost, st));
+  HIPC(hipStreamSynchronize(st));
+  int worst = SAI_OK;
+  for (int c = 0; c < k; ++c) {
+    const int code = hst[c] == ST_CONV ? 0 : 1;
+    if (status) status[c] = code;
+    if (iters) iters[c] = hit[c];
+    if (code) worst = SAI_ENOCONV;
+  }
+  return worst;
+}
+
+#undef GB_COLS
+
+template <class TM>
+int gmres_batched(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, const double* R, double* X,
+                  const double* thr, int m, int maxit, const Allocator& al, hipStream_t st, int* iters,
+                  int* status) {
+  switch (lp_class(k)) {
+    case 1: return gmres_batched_lp<1, TM>(A, M, n, k, R, X, thr, m, maxit, al, st, iters, status);
+    case 2: return gmres_batched_lp<2, TM>(A, M, n, k, R, X, thr, m, maxit, al, st, iters, status);
+    case 4: return gmres_batched_lp<4, TM>(A, M, n, k, R, X, thr, m, maxit, al, st, iters, status);
+    case 6: return gmres_batched_lp<6, TM>(A, M, n, k, R, X, thr, m, maxit, al, st, iters, status);
+    case 8: return gmres_batched_lp<8, TM>(A, M, n, k, R, X, thr, m, maxit, al, st, iters, status);
+    case 12: return gmres_batched_lp<12, TM>(A, M, n, k, R, X, thr, m, maxit, al, st, iters, status);
+    case 16: return gmres_batched_lp<16, TM>(A, M, n, k, R, X, thr, m, maxit, al, st, iters, status);
+    default: return gmres_batched_lp<32, TM>(A, M, n, k, R, X, thr, m, maxit, al, st, iters, status);
+  }
+}
+
+}  // namespace
+}  // namespace sai

@@ -23,9 +23,11 @@
 // sparse products, 2 true-residual checks that return at once unless a column
 // is flagged, and 5 one-block finishers.
 //
-// GMRES(m) (used for the smallest workload) runs one workgroup per column for
-// the whole solve: modified Gram-Schmidt Arnoldi, Givens rotations, solution
-// update at the end of each cycle, convergence on the true residual.
+// GMRES(m) has two forms: for small n one workgroup per column for the whole
+// solve (modified Gram-Schmidt Arnoldi, Givens rotations, solution update at
+// the end of each cycle, convergence on the true residual), and for large n the
+// batched form of gmres_batched.hpp, whose sparse products are the BiCGStab
+// ones.
 #include "sai_internal.hpp"
 
 #include "bicgstab_kernels.hpp"
@@ -588,6 +590,26 @@ int gmres_run(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, const do
   return worst;
 }
 
+}  // namespace
+}  // namespace sai
+
+#include "gmres_batched.hpp"
+
+namespace sai {
+namespace {
+
+// GMRES(m): the batched form from GMRES_BATCH_N rows on (default 20,000),
+// the per-column workgroups below it
+template <class TM>
+int gmres_solve(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, const double* R, double* X,
+                const double* thr, int restart, int maxit, const Allocator& al, hipStream_t st, int* iters,
+                int* status) {
+  if (restart < 1 || restart > GM_MAXM) SAI_THROW(SAI_EINVAL, "GMRES restart must be in [1, %d]", GM_MAXM);
+  if (n >= (int64_t)tune_get("GMRES_BATCH_N", 20000))
+    return gmres_batched<TM>(A, M, n, k, R, X, thr, restart, maxit, al, st, iters, status);
+  return gmres_run<TM>(A, M, n, k, R, X, thr, restart, maxit, al, st, iters, status);
+}
+
 template <class TM>
 int krylov_typed(const sai_split_s* sp, const sai_precond_s* pc, int transpose, int k,
                  const double* R, double* X, const double* thr, const sai_solve_opts& o,
@@ -604,7 +626,7 @@ int krylov_typed(const sai_split_s* sp, const sai_precond_s* pc, int transpose, 
   }
   const int64_t n = sp->n;
   if (o.method == SAI_GMRES)
-    return gmres_run<TM>(A, M, n, k, R, X, thr, o.restart, o.maxit, al, st, iters, status);
+    return gmres_solve<TM>(A, M, n, k, R, X, thr, o.restart, o.maxit, al, st, iters, status);
   return bicgstab<TM>(A, M, n, k, R, X, thr, o.maxit, al, st, iters, status);
 }
 
