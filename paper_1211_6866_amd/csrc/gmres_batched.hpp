@@ -30,7 +30,7 @@ namespace sai {
 namespace {
 
 constexpr int GB_NT = 256;
-constexpr int GB_NB = 512;     // workgroups of the reductions (partial sums per column)
+constexpr int GB_NB = 1024;    // most workgroups of a reduction (partial sums per column)
 constexpr int GB_CH = 32;      // basis vectors per projection launch
 constexpr int GB_Q = GM_MAXM + 1;
 
@@ -48,13 +48,6 @@ struct GbState {
   double *thr, *beta, *a, *g, *cs, *sn, *y, *H, *hh, *hh2, *nn;
 };
 
-// Columns of a thread in the reductions: c = t % kp of rows t / kp + RG b, ...
-#define GB_COLS                                  \
-  const int t_ = threadIdx.x;                    \
-  const int rg = GB_NT / kp;                     \
-  const int c = t_ % kp, ro = t_ / kp;           \
-  (void)c;
-
 // B = R (pad column 0), X = 0, W = B
 __global__ void __launch_bounds__(GB_NT) k_gb_load(int64_t n, int k, int kp, const double* __restrict__ R,
                                                   double* __restrict__ B, double* __restrict__ X,
@@ -70,130 +63,173 @@ __global__ void __launch_bounds__(GB_NT) k_gb_load(int64_t n, int k, int kp, con
   }
 }
 
-// The basis V_0, V_1, ... is one array, V_q at Vb + q nk (nk = n kp).
+// ---- reductions over the rows ------------------------------------------------------
 //
-// part[blk][q0 + q][c] = sum over the block's rows of V_{q0+q}[i, c] W[i, c]
-// (q < nv <= GB_CH) for the columns with act[c] == 0; others 0
-__global__ void __launch_bounds__(GB_NT) k_gb_dots(int64_t n, int kp, int q0, int nv, const double* __restrict__ Vb,
+// The basis V_0, V_1, ... is one array, V_q at Vb + q nk (nk = n kp).  A
+// reduction block has GB_RT threads; thread t owns column c = t % kp of the
+// rows g, g + RG, ... of the block's slice (g = t / kp, RG = GB_RT / kp row
+// groups), a wavefront's loads covering consecutive elements.  The number of
+// basis vectors NV is a template parameter so that the NV + 1 loads of a row
+// are issued together.  Per-column block sums go to part[blk][q][c] (column
+// partials of row groups added in a fixed order), and k_gb_fin adds the blocks'
+// partials in a fixed order.
+
+constexpr int GB_RT = 512;
+
+// block sum of v over the row groups of column c, written to part[blk][q][c]
+__device__ __forceinline__ void gb_block_sum(double v, bool on, int kp, int rg, int q, double* red,
+                                             double* __restrict__ part) {
+  const int t = threadIdx.x;
+  red[t] = on ? v : 0.0;
+  __syncthreads();
+  if (t < kp) {
+    double s = 0.0;
+    for (int r = 0; r < rg; ++r) s += red[r * kp + t];
+    part[((int64_t)blockIdx.x * GB_Q + q) * 64 + t] = s;
+  }
+  __syncthreads();
+}
+
+#define GB_RED_SETUP                                        \
+  __shared__ double red[GB_RT];                             \
+  const int rg = GB_RT / kp;                                \
+  const int c = (int)threadIdx.x % kp, ro = (int)threadIdx.x / kp; \
+  const bool on = ro < rg && act[c] == 0;                   \
+  const int64_t nk = n * kp;                                \
+  (void)nk;
+
+#define GB_ROWS for (int64_t i = (int64_t)blockIdx.x * rg + ro; i < n; i += (int64_t)gridDim.x * rg)
+
+// part[blk][q0 + q][c] = V_{q0+q}[rows of blk, c]^T W[rows of blk, c], q < NV
+template <int NV>
+__global__ void __launch_bounds__(GB_RT) k_gb_dots(int64_t n, int kp, int q0, const double* __restrict__ Vb,
                                                   const double* __restrict__ W, const int* __restrict__ act,
                                                   const int* __restrict__ cnt, double* __restrict__ part) {
   if (cnt[3] == 0) return;
-  __shared__ double red[GB_NT];
-  GB_COLS
-  const bool on = ro < rg && act[c] == 0;
-  const int64_t nk = n * kp;
+  GB_RED_SETUP
   const double* V0 = Vb + nk * q0;
-  double acc[GB_CH];
+  double acc[NV];
 #pragma unroll
-  for (int q = 0; q < GB_CH; ++q) acc[q] = 0.0;
+  for (int q = 0; q < NV; ++q) acc[q] = 0.0;
   if (on) {
-    for (int64_t i = (int64_t)blockIdx.x * rg + ro; i < n; i += (int64_t)gridDim.x * rg) {
+    GB_ROWS {
       const int64_t e = i * kp + c;
+      double v[NV];
+#pragma unroll
+      for (int q = 0; q < NV; ++q) v[q] = V0[nk * q + e];
       const double w = W[e];
 #pragma unroll
-      for (int q = 0; q < GB_CH; ++q)
-        if (q < nv) acc[q] += V0[nk * q + e] * w;
+      for (int q = 0; q < NV; ++q) acc[q] += v[q] * w;
     }
   }
-  // (unrolled, so that acc stays in registers; nv is uniform over the block)
 #pragma unroll
-  for (int q = 0; q < GB_CH; ++q) {
-    if (q < nv) {
-      red[t_] = on ? acc[q] : 0.0;
-      __syncthreads();
-      if (t_ < kp) {
-        double s = 0.0;
-        for (int r = 0; r < rg; ++r) s += red[r * kp + t_];
-        part[((int64_t)blockIdx.x * GB_Q + q0 + q) * 64 + t_] = s;
-      }
-      __syncthreads();
-    }
-  }
+  for (int q = 0; q < NV; ++q) gb_block_sum(acc[q], on, kp, rg, q0 + q, red, part);
 }
 
-// W -= sum_q h[q0 + q][c] V_{q0+q} (q < nv <= GB_CH) for the columns with
-// act[c] == 0; with norm: part[blk][0][c] = sum over the block's rows of the new
-// W[i, c]^2.  The same thread-to-element map as k_gb_dots.
-__global__ void __launch_bounds__(GB_NT) k_gb_project(int64_t n, int kp, int q0, int nv,
-                                                     const double* __restrict__ Vb,
+// W -= V_{0..NV-1} h, then part[blk][q][c] = V_q^T W (the second Gram-Schmidt
+// pass's products, on the projected W, from the same loads of V)
+template <int NV>
+__global__ void __launch_bounds__(GB_RT) k_gb_projdots(int64_t n, int kp, const double* __restrict__ Vb,
+                                                      const double* __restrict__ h, double* __restrict__ W,
+                                                      const int* __restrict__ act, const int* __restrict__ cnt,
+                                                      double* __restrict__ part) {
+  if (cnt[3] == 0) return;
+  GB_RED_SETUP
+  double hq[NV], acc[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    hq[q] = on ? h[q * 64 + c] : 0.0;
+    acc[q] = 0.0;
+  }
+  if (on) {
+    GB_ROWS {
+      const int64_t e = i * kp + c;
+      double v[NV];
+#pragma unroll
+      for (int q = 0; q < NV; ++q) v[q] = Vb[nk * q + e];
+      double w = W[e];
+#pragma unroll
+      for (int q = 0; q < NV; ++q) w -= hq[q] * v[q];
+      W[e] = w;
+#pragma unroll
+      for (int q = 0; q < NV; ++q) acc[q] += v[q] * w;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NV; ++q) gb_block_sum(acc[q], on, kp, rg, q, red, part);
+}
+
+// W -= V_{q0..q0+NV-1} h[q0..]; with norm, part[blk][0][c] = sum of the new W^2
+template <int NV>
+__global__ void __launch_bounds__(GB_RT) k_gb_project(int64_t n, int kp, int q0, const double* __restrict__ Vb,
                                                      const double* __restrict__ h, double* __restrict__ W,
                                                      const int* __restrict__ act, const int* __restrict__ cnt,
                                                      int norm, double* __restrict__ part) {
   if (cnt[3] == 0) return;
-  __shared__ double red[GB_NT];
-  GB_COLS
-  const bool on = ro < rg && act[c] == 0;
-  const int64_t nk = n * kp;
+  GB_RED_SETUP
   const double* V0 = Vb + nk * q0;
-  double hq[GB_CH];
+  double hq[NV];
 #pragma unroll
-  for (int q = 0; q < GB_CH; ++q) hq[q] = (on && q < nv) ? h[(q0 + q) * 64 + c] : 0.0;
+  for (int q = 0; q < NV; ++q) hq[q] = on ? h[(q0 + q) * 64 + c] : 0.0;
   double acc = 0.0;
   if (on) {
-    for (int64_t i = (int64_t)blockIdx.x * rg + ro; i < n; i += (int64_t)gridDim.x * rg) {
+    GB_ROWS {
       const int64_t e = i * kp + c;
+      double v[NV];
+#pragma unroll
+      for (int q = 0; q < NV; ++q) v[q] = V0[nk * q + e];
       double w = W[e];
 #pragma unroll
-      for (int q = 0; q < GB_CH; ++q)
-        if (q < nv) w -= hq[q] * V0[nk * q + e];
+      for (int q = 0; q < NV; ++q) w -= hq[q] * v[q];
       W[e] = w;
       acc += w * w;
     }
   }
-  if (norm) {
-    red[t_] = on ? acc : 0.0;
-    __syncthreads();
-    if (t_ < kp) {
-      double s = 0.0;
-      for (int r = 0; r < rg; ++r) s += red[r * kp + t_];
-      part[(int64_t)blockIdx.x * GB_Q * 64 + t_] = s;
-    }
-  }
+  if (norm) gb_block_sum(acc, on, kp, rg, 0, red, part);
 }
 
-// W = B - AX and part[blk][0][c] = sum over the block's rows of W[i, c]^2 for
-// the columns with act[c] == 0
-__global__ void __launch_bounds__(GB_NT) k_gb_resid(int64_t n, int kp, const double* __restrict__ B,
+// W = B - AX and part[blk][0][c] = sum of W^2
+__global__ void __launch_bounds__(GB_RT) k_gb_resid(int64_t n, int kp, const double* __restrict__ B,
                                                    const double* __restrict__ AX, double* __restrict__ W,
                                                    const int* __restrict__ act, const int* __restrict__ cnt,
                                                    double* __restrict__ part) {
   if (cnt[3] == 0) return;
-  __shared__ double red[GB_NT];
-  GB_COLS
-  const bool on = ro < rg && act[c] == 0;
+  GB_RED_SETUP
   double acc = 0.0;
   if (on) {
-    for (int64_t i = (int64_t)blockIdx.x * rg + ro; i < n; i += (int64_t)gridDim.x * rg) {
+    GB_ROWS {
       const int64_t e = i * kp + c;
       const double w = B[e] - AX[e];
       W[e] = w;
       acc += w * w;
     }
   }
-  red[t_] = on ? acc : 0.0;
-  __syncthreads();
-  if (t_ < kp) {
-    double s = 0.0;
-    for (int r = 0; r < rg; ++r) s += red[r * kp + t_];
-    part[(int64_t)blockIdx.x * GB_Q * 64 + t_] = s;
-  }
+  gb_block_sum(acc, on, kp, rg, 0, red, part);
 }
 
-// out[q][c] = sum over the nb workgroups, in order, of part[blk][q][c] (one
-// block per q; four groups of 64 threads take every fourth workgroup, then
-// their sums are added in order)
-__global__ void __launch_bounds__(GB_NT) k_gb_fin(int nb, int kp, const double* __restrict__ part,
+#undef GB_ROWS
+#undef GB_RED_SETUP
+
+// out[q][c] = sum over the nb blocks of part[blk][q][c] (one block per q):
+// thread (g, c) adds blocks g, g + G, ... in order (G = GB_RT / kp), then the
+// G sums are added in order
+__global__ void __launch_bounds__(GB_RT) k_gb_fin(int nb, int kp, const double* __restrict__ part,
                                                  double* __restrict__ out) {
-  __shared__ double red[GB_NT];
+  __shared__ double red[GB_RT];
   const int q = blockIdx.x;
-  const int c = threadIdx.x % 64, grp = threadIdx.x / 64;
+  const int G = GB_RT / kp;
+  const int c = (int)threadIdx.x % kp, g = (int)threadIdx.x / kp;
   double s = 0.0;
-  if (c < kp)
-    for (int b = grp; b < nb; b += GB_NT / 64) s += part[((int64_t)b * GB_Q + q) * 64 + c];
+  if (g < G)
+    for (int b = g; b < nb; b += G) s += part[((int64_t)b * GB_Q + q) * 64 + c];
   red[threadIdx.x] = s;
   __syncthreads();
-  if (threadIdx.x < 64)
-    out[q * 64 + c] = c < kp ? ((red[c] + red[64 + c]) + red[128 + c]) + red[192 + c] : 0.0;
+  if (threadIdx.x < 64) {
+    double r = 0.0;
+    if ((int)threadIdx.x < kp)
+      for (int u = 0; u < G; ++u) r += red[u * kp + threadIdx.x];
+    out[q * 64 + threadIdx.x] = r;
+  }
 }
 
 // dst = a[c] src for the columns with act[c] == 0
@@ -218,8 +254,18 @@ __global__ void __launch_bounds__(GB_NT) k_gb_combine(int64_t n, int kp, const d
   for (int64_t t = (int64_t)blockIdx.x * GB_NT + threadIdx.x; t < nk; t += (int64_t)gridDim.x * GB_NT) {
     const int c = (int)(t % kp);
     if (act[c] != 0) continue;
+    const int kq = kk[c];
     double s = 0.0;
-    for (int q = 0; q < kk[c]; ++q) s += y[q * 64 + c] * Vb[nk * q + t];
+    int q = 0;
+    for (; q + 4 <= kq; q += 4) {  // four independent loads at a time
+      const double v0 = Vb[nk * q + t], v1 = Vb[nk * (q + 1) + t];
+      const double v2 = Vb[nk * (q + 2) + t], v3 = Vb[nk * (q + 3) + t];
+      s += y[q * 64 + c] * v0;
+      s += y[(q + 1) * 64 + c] * v1;
+      s += y[(q + 2) * 64 + c] * v2;
+      s += y[(q + 3) * 64 + c] * v3;
+    }
+    for (; q < kq; ++q) s += y[q * 64 + c] * Vb[nk * q + t];
     Z[t] = s;
   }
 }
@@ -408,24 +454,65 @@ int gmres_batched_lp(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, c
   auto aprod = [&](const double* in, double* out, const State& S) {
     hipLaunchKernelGGL((k_spmm<LP, double, 6, 3>), dim3(ga), dim3(NT), 0, st, n, k, kp, A, in, out, S, xmap);
   };
-  const int rg = GB_NT / kp;
+  const int rg = GB_RT / kp;
   const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(GB_NB, (n + rg - 1) / rg));
   const unsigned eg = grid_for((int64_t)nk, GB_NT, 4096);
-  // h (nv values per column) = V_{0..nv-1}^T W
-  auto dots = [&](int nv, const double* W, double* out) {
-    for (int q0 = 0; q0 < nv; q0 += GB_CH)
-      hipLaunchKernelGGL(k_gb_dots, dim3(nb), dim3(GB_NT), 0, st, n, kp, q0, std::min(GB_CH, nv - q0), Vb, W,
-                         G.arn, G.any_arn, part.p);
-    hipLaunchKernelGGL(k_gb_fin, dim3(nv), dim3(GB_NT), 0, st, nb, kp, part.p, out);
+#define GB_CASES(X)                                                                              \
+  X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) \
+  X(18) X(19) X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31) X(32)
+  auto fin = [&](int nq, double* out) {
+    hipLaunchKernelGGL(k_gb_fin, dim3(nq), dim3(GB_RT), 0, st, nb, kp, part.p, out);
   };
-  // W -= V h (chunks of GB_CH vectors; the norm with the last chunk)
-  auto project = [&](int nv, const double* h, double* W, bool norm) {
-    for (int q0 = 0; q0 < nv; q0 += GB_CH) {
-      const bool last = q0 + GB_CH >= nv;
-      hipLaunchKernelGGL(k_gb_project, dim3(nb), dim3(GB_NT), 0, st, n, kp, q0, std::min(GB_CH, nv - q0), Vb, h,
-                         W, G.arn, G.any_arn, norm && last ? 1 : 0, part.p);
+  // partials of V_{q0..q0+nv-1}^T W, nv <= GB_CH
+  auto dots_chunk = [&](int q0, int nv, const double* W) {
+    switch (nv) {
+#define GB_X(N)                                                                                      \
+  case N:                                                                                            \
+    hipLaunchKernelGGL((k_gb_dots<N>), dim3(nb), dim3(GB_RT), 0, st, n, kp, q0, Vb, W, G.arn, G.any_arn, \
+                       part.p);                                                                      \
+    break;
+      GB_CASES(GB_X)
+#undef GB_X
     }
-    if (norm) hipLaunchKernelGGL(k_gb_fin, dim3(1), dim3(GB_NT), 0, st, nb, kp, part.p, G.nn);
+  };
+  // W -= V_{q0..q0+nv-1} h[q0..], nv <= GB_CH (with the norm partials)
+  auto project_chunk = [&](int q0, int nv, const double* h, double* W, int norm) {
+    switch (nv) {
+#define GB_X(N)                                                                                         \
+  case N:                                                                                               \
+    hipLaunchKernelGGL((k_gb_project<N>), dim3(nb), dim3(GB_RT), 0, st, n, kp, q0, Vb, h, W, G.arn, G.any_arn, \
+                       norm, part.p);                                                                   \
+    break;
+      GB_CASES(GB_X)
+#undef GB_X
+    }
+  };
+  auto projdots = [&](int nv, const double* h, double* W) {
+    switch (nv) {
+#define GB_X(N)                                                                                          \
+  case N:                                                                                                \
+    hipLaunchKernelGGL((k_gb_projdots<N>), dim3(nb), dim3(GB_RT), 0, st, n, kp, Vb, h, W, G.arn, G.any_arn, \
+                       part.p);                                                                          \
+    break;
+      GB_CASES(GB_X)
+#undef GB_X
+    }
+  };
+#undef GB_CASES
+  // Gram-Schmidt twice against V_{0..nv-1}: hh, hh2 and nn = ||W||^2 after
+  auto orthogonalise = [&](int nv, double* W) {
+    for (int q0 = 0; q0 < nv; q0 += GB_CH) dots_chunk(q0, std::min(GB_CH, nv - q0), W);
+    fin(nv, G.hh);
+    if (nv <= GB_CH) {
+      projdots(nv, G.hh, W);  // first projection fused with the second products
+    } else {
+      for (int q0 = 0; q0 < nv; q0 += GB_CH) project_chunk(q0, std::min(GB_CH, nv - q0), G.hh, W, 0);
+      for (int q0 = 0; q0 < nv; q0 += GB_CH) dots_chunk(q0, std::min(GB_CH, nv - q0), W);
+    }
+    fin(nv, G.hh2);
+    for (int q0 = 0; q0 < nv; q0 += GB_CH)
+      project_chunk(q0, std::min(GB_CH, nv - q0), G.hh2, W, q0 + GB_CH >= nv ? 1 : 0);
+    fin(1, G.nn);
   };
 
   HostStage hs(16);
@@ -435,9 +522,9 @@ int gmres_batched_lp(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, c
     hipLaunchKernelGGL(k_gb_load, dim3(eg), dim3(GB_NT), 0, st, n, k, kp, R, Bv.p, Xv.p, Wv.p);
     // ||R|| per column (the "cycle" set is every column here)
     HIPC(hipMemsetAsync(G.any_cyc, 0xff, sizeof(int) * 8, st));
-    hipLaunchKernelGGL(k_gb_resid, dim3(nb), dim3(GB_NT), 0, st, n, kp, Bv.p, Xv.p, Wv.p, G.zero, G.any_cyc,
+    hipLaunchKernelGGL(k_gb_resid, dim3(nb), dim3(GB_RT), 0, st, n, kp, Bv.p, Xv.p, Wv.p, G.zero, G.any_cyc,
                        part.p);
-    hipLaunchKernelGGL(k_gb_fin, dim3(1), dim3(GB_NT), 0, st, nb, kp, part.p, G.nn);
+    fin(1, G.nn);
     hipLaunchKernelGGL(k_gb_setup, dim3(1), dim3(64), 0, st, k, maxit, G);
   }
   LAUNCH_CHECK();
@@ -462,10 +549,7 @@ int gmres_batched_lp(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, c
       }
       {
         SAI_PROF("gmres_orth", st);
-        dots(j + 1, Wv.p, G.hh);
-        project(j + 1, G.hh, Wv.p, false);
-        dots(j + 1, Wv.p, G.hh2);
-        project(j + 1, G.hh2, Wv.p, true);
+        orthogonalise(j + 1, Wv.p);
       }
       {
         SAI_PROF("gmres_step", st);
@@ -484,9 +568,9 @@ int gmres_batched_lp(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, c
       mprod(Zv.p, Wv.p, Scyc);
       hipLaunchKernelGGL(k_gb_add, dim3(eg), dim3(GB_NT), 0, st, n, kp, Wv.p, Xv.p, G.cyc, G.any_cyc);
       aprod(Xv.p, Zv.p, Scyc);
-      hipLaunchKernelGGL(k_gb_resid, dim3(nb), dim3(GB_NT), 0, st, n, kp, Bv.p, Zv.p, Wv.p, G.cyc, G.any_cyc,
+      hipLaunchKernelGGL(k_gb_resid, dim3(nb), dim3(GB_RT), 0, st, n, kp, Bv.p, Zv.p, Wv.p, G.cyc, G.any_cyc,
                          part.p);
-      hipLaunchKernelGGL(k_gb_fin, dim3(1), dim3(GB_NT), 0, st, nb, kp, part.p, G.nn);
+      fin(1, G.nn);
       hipLaunchKernelGGL(k_gb_cycle_end, dim3(1), dim3(64), 0, st, k, maxit, G);
     }
     LAUNCH_CHECK();
