@@ -156,12 +156,13 @@ def _oracle_columns(rng_):
     return a, np.concatenate(rows), np.concatenate(vals), cnt
 
 
-def cpu_baseline(w, bkw, adjoint, workers, dense_cols=None):
+def cpu_baseline(w, bkw, adjoint, workers, dense_cols=None, gmres_m=None):
     """Time the oracle on this host: its split of the full matrix, its build of
     the whole M (columns in chunks over a fork pool of `workers` processes), and
     two BiCGStab iterations with its own M on two right-hand sides (and on the
     transposed system for the adjoint), whose per-iteration cost is scaled later
-    by the iteration counts of the GPU solve."""
+    by the iteration counts of the GPU solve.  For GMRES(m) (gmres_m) the
+    per-iteration cost is the average over one full cycle of m steps."""
     import multiprocessing as mp
 
     import numpy as np
@@ -203,15 +204,24 @@ def cpu_baseline(w, bkw, adjoint, workers, dense_cols=None):
     Mr, At = sp.csr_matrix(M), sp.csr_matrix(S.At)
     rhs = [w.b] + ([S.U[:, 0].toarray().ravel()] if S.s else [])
     with threadpool_limits(1):
+        its = gmres_m or 2
+
+        def kry(Aop, Mop, c):
+            if gmres_m:
+                okry.gmres(Aop, Mop, c, 0.0, restart=gmres_m, maxit=gmres_m)
+            else:
+                okry.bicgstab(Aop, Mop, c, 0.0, maxit=2)
+        out["krylov"] = f"GMRES({gmres_m})" if gmres_m else "BiCGStab"
+        out["krylov_its"] = its
         t0 = time.perf_counter()
         for c in rhs:
-            okry.bicgstab(At, Mr, c, 0.0, maxit=2)
-        out["iter_s"] = (time.perf_counter() - t0) / (2 * len(rhs))
+            kry(At, Mr, c)
+        out["iter_s"] = (time.perf_counter() - t0) / (its * len(rhs))
         if adjoint:
             AtT, MT = sp.csr_matrix(S.At.T), sp.csr_matrix(M.T)
             t0 = time.perf_counter()
-            okry.bicgstab(AtT, MT, w.b, 0.0, maxit=2)
-            out["iter_adj_s"] = (time.perf_counter() - t0) / 2
+            kry(AtT, MT, w.b)
+            out["iter_adj_s"] = (time.perf_counter() - t0) / its
         Y = np.zeros((n, S.s + 1))
         Y[:, 0] = w.b
         t0 = time.perf_counter()
@@ -264,6 +274,9 @@ def main():
                     help="override the workload's pattern: SPAI (delta 0.4, 3 x 5) or PSAI(tol) "
                          "(delta 0.4, l_max 10)")
     ap.add_argument("--n", type=int, default=None, help="size of the random workload (3)")
+    ap.add_argument("--method", choices=("default", "bicgstab", "gmres"), default="default",
+                    help="override the workload's Krylov method (GMRES: restart --restart)")
+    ap.add_argument("--restart", type=int, default=20)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU: --gpus must be 1 (the path shards by "
@@ -284,6 +297,13 @@ def main():
         name += "_psaitol0.4"
     if args.n is not None:
         name += f"_n{args.n}"
+    if args.method == "gmres" and not (skw["method"] == P.GMRES and skw.get("restart") == args.restart):
+        skw = dict(skw, method=P.GMRES, restart=args.restart)
+        name += f"_gmres{args.restart}"
+    elif args.method == "bicgstab" and skw["method"] != P.BICGSTAB:
+        skw = dict(skw, method=P.BICGSTAB)
+        name += "_bicgstab"
+    gmres_m = skw.get("restart") if skw["method"] == P.GMRES else None
     split_kw = {}
     if args.approach == "S":
         # the standard approach: no irregular column is split off (A~ = A, s = 0)
@@ -299,9 +319,10 @@ def main():
     workers = max(1, min(args.cpu_workers, avail))
     if not args.no_cpu:
         log(f"bench: CPU oracle leg ({workers} processes for the build, {model}, {ncpu} CPUs)")
-        cpu_raw = cpu_baseline(w, bkw, adjoint, workers, dense_cols=split_kw.get("dense_cols"))
+        cpu_raw = cpu_baseline(w, bkw, adjoint, workers, dense_cols=split_kw.get("dense_cols"),
+                               gmres_m=gmres_m)
         log(f"bench: CPU oracle leg done: split {cpu_raw['split_s']:.1f} s, build {cpu_raw['build_s']:.1f} s, "
-            f"{cpu_raw['iter_s'] * 1e3:.0f} ms per BiCGStab iteration and right-hand side")
+            f"{cpu_raw['iter_s'] * 1e3:.0f} ms per {cpu_raw['krylov']} iteration and right-hand side")
 
     import torch
     rp, ci, va = P.csr_to_device(w.A)
@@ -344,7 +365,8 @@ def main():
     prof_all = P.profile_read()
     P.profile_enable(0)
     scopes = {"split", "smw_recover", "spai_search", "psai_search", "gmres_fused", "pattern_bounds",
-              "pattern_fill", "pattern_pack", "bicg_init"}
+              "pattern_fill", "pattern_pack", "bicg_init", "gmres_init", "gmres_orth", "gmres_step",
+              "gmres_cycle_start", "gmres_cycle_end"}
     dom = max((tot, nm) for nm, (l, tot) in prof_all.items() if nm not in scopes)[1]
 
     def timed(prec, K, only=None):
@@ -444,6 +466,8 @@ def main():
         "bicg_p_update": 4 * bytes_kn,
         "bicg_s_update": 3 * bytes_kn,
         "bicg_xr_update": 8 * bytes_kn,
+        "gmres_spmm_M_f32": 8.0 * nnz_m + 4.0 * (n + 1) + 2 * bytes_kn,
+        "gmres_spmm_A": 12.0 * nnz_t + 4.0 * (n + 1) + 2 * bytes_kn,
     }
     dom_launches, dom_ms = prof[dom]
     avg_ms = dom_ms / dom_launches
@@ -491,7 +515,8 @@ def main():
             cpu_model=model, nproc=ncpu,
             sample=(f"oracle split of the full matrix ({cpu_raw['split_s']:.1f} s, 1 thread); oracle build of "
                     f"all {n} columns of M ({cpu_raw['nnz_M']} entries) on {workers} processes "
-                    f"({cpu_raw['build_s']:.1f} s); oracle BiCGStab with that M: 2 iterations on 2 "
+                    f"({cpu_raw['build_s']:.1f} s); oracle {cpu_raw['krylov']} with that M: "
+                    f"{cpu_raw['krylov_its']} iterations on 2 "
                     f"right-hand sides ({cpu_raw['iter_s'] * 1e3:.0f} ms per iteration and right-hand side, "
                     f"1 thread) scaled by the GPU solve's {it_fwd} column-iterations"
                     + (f", and on the transposed system ({cpu_raw['iter_adj_s'] * 1e3:.0f} ms) scaled by "
@@ -514,7 +539,8 @@ def main():
         "dtype": "f32 M build + f64 Krylov/SMW/check",
         "data": "synthetic",
         "config": {"workload": name, "n": n, "s": s, "nnz_A": int(w.A.nnz), "rhs": k,
-                   "solver": "gmres30" if skw["method"] == P.GMRES else "bicgstab", "eps": skw["eps"],
+                   "solver": f"gmres{skw['restart']}" if skw["method"] == P.GMRES else "bicgstab",
+                   "eps": skw["eps"],
                    "adjoint_in_step": adjoint, "parallelism": "single GPU"},
         "time_to_1e-8_ms": {"mixed": round(ms_mixed, 3),
                             "plain_fp64": round(plain["ms"], 3) if plain else None},

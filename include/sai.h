@@ -242,7 +242,12 @@ int sai_gather(const sai_split_t* sp, const sai_precond_t* pc, int32_t precision
  * array of k absolute thresholds; the Section 4 theorem gives them, see
  * sai_solve).  Methods: SAI_BICGSTAB (van der Vorst, r_hat = r_0; one restart
  * with r_hat = r on breakdown; residual replacement when a recursive residual
- * passes but the true one does not) or SAI_GMRES (GMRES(restart)).
+ * passes but the true one does not) or SAI_GMRES (GMRES(restart), restart in
+ * [1, 64]; Arnoldi with Givens rotations, x updated and the true residual
+ * checked at the end of each cycle; a column leaves a cycle early when its
+ * rotated residual estimate passes thr[c]).  GMRES runs the k columns in
+ * lockstep (shared sparse products, Gram-Schmidt twice) once n k >= 32768, else
+ * one workgroup per column (modified Gram-Schmidt); the two round differently.
  * iters/status: host arrays of k entries (may be NULL); status per column is
  * 0 converged, 1 maxit, 2 breakdown.  Returns SAI_ENOCONV / SAI_EBREAKDOWN if
  * any column ended that way (X is written in every case).  k <= 64. */

@@ -2,7 +2,7 @@
 
 The batched form (one lockstep run over the k columns, the BiCGStab sparse
 products, classical Gram-Schmidt with one reorthogonalisation) is forced with
-the GMRES_BATCH_N knob at 0 on matrices small enough for a dense SVD.  The
+the GMRES_BATCH_NK knob at 0 on matrices small enough for a dense SVD.  The
 oracle runs GMRES(m) column by column with modified Gram-Schmidt on the same
 right-hand sides with its own FP64 M (equal to the library's FP64 build to
 1e-12).  Bars: every column's true residual, recomputed on the host in FP64,
@@ -63,11 +63,11 @@ def _setup(name):
 
 def _krylov(g, pc, R, thr, batch_n=0, **kw):
     try:
-        P.tune_set("GMRES_BATCH_N", batch_n)
+        P.tune_set("GMRES_BATCH_NK", batch_n)
         X, its, sts, code = P.krylov(g, pc, torch.from_numpy(np.ascontiguousarray(R)).cuda(), thr,
                                      method=P.GMRES, **kw)
     finally:
-        P.tune_set("GMRES_BATCH_N", 20000)
+        P.tune_set("GMRES_BATCH_NK", 32768)
     return X.cpu().numpy(), its, sts, code
 
 
