@@ -111,34 +111,41 @@ __global__ void k_set_units(int s, const int32_t* D, double* R) {
   if (d < s) R[(int64_t)D[d] * (s + 1) + 1 + d] = 1.0;
 }
 
-// correction solves: R = U - A~ W for the auxiliary columns (c-refinement)
+// correction solves: R = U - A~ W for the auxiliary columns (c-refinement).  One
+// thread per (row i, column d), consecutive threads on consecutive columns of a
+// row, so that the gathered rows of Y are read whole by neighbouring lanes.
 __global__ void k_aux_residual(int64_t n, int s, const int32_t* __restrict__ rp,
                                const int32_t* __restrict__ ci, const double* __restrict__ v,
                                const int32_t* __restrict__ urp, const int32_t* __restrict__ ucol,
                                const double* __restrict__ uval, const double* __restrict__ Y,
                                double* __restrict__ R) {
   const int kk = s + 1;
-  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
-    for (int d = 0; d < s; ++d) {
-      double y = 0.0;
-      for (int32_t e = rp[i]; e < rp[i + 1]; ++e) y += v[e] * Y[(int64_t)ci[e] * kk + 1 + d];
-      R[i * s + d] = -y;
-    }
-    for (int32_t e = urp[i]; e < urp[i + 1]; ++e) R[i * s + ucol[e]] += uval[e];
+  const int64_t ns = n * s;
+  for (int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x; t < ns; t += (int64_t)gridDim.x * NT) {
+    const int64_t i = t / s;
+    const int d = (int)(t % s);
+    double y = 0.0;
+    for (int32_t e = rp[i]; e < rp[i + 1]; ++e) y += v[e] * Y[(int64_t)ci[e] * kk + 1 + d];
+    double r = -y;
+    for (int32_t e = urp[i]; e < urp[i + 1]; ++e)
+      if (ucol[e] == d) r += uval[e];
+    R[t] = r;
   }
 }
 // adjoint correction solves: R = V - A~^T Z for the auxiliary columns, with A~^T
-// given as the CSC of A~ and V = (e_{j_1} .. e_{j_s})
+// given as the CSC of A~ and V = (e_{j_1} .. e_{j_s}) (added by k_add_units);
+// the thread map of k_aux_residual
 __global__ void k_aux_residual_t(int64_t n, int s, const int32_t* __restrict__ cp,
                                  const int32_t* __restrict__ ri, const double* __restrict__ cv,
                                  const double* __restrict__ Y, double* __restrict__ R) {
   const int kk = s + 1;
-  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
-    for (int d = 0; d < s; ++d) {
-      double y = 0.0;
-      for (int32_t e = cp[i]; e < cp[i + 1]; ++e) y += cv[e] * Y[(int64_t)ri[e] * kk + 1 + d];
-      R[i * s + d] = -y;
-    }
+  const int64_t ns = n * s;
+  for (int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x; t < ns; t += (int64_t)gridDim.x * NT) {
+    const int64_t i = t / s;
+    const int d = (int)(t % s);
+    double y = 0.0;
+    for (int32_t e = cp[i]; e < cp[i + 1]; ++e) y += cv[e] * Y[(int64_t)ri[e] * kk + 1 + d];
+    R[t] = -y;
   }
 }
 __global__ void k_add_units(int s, const int32_t* D, double* R) {
@@ -148,8 +155,9 @@ __global__ void k_add_units(int s, const int32_t* D, double* R) {
 
 __global__ void k_aux_add(int64_t n, int s, const double* __restrict__ dW, double* __restrict__ Y) {
   const int kk = s + 1;
-  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT)
-    for (int d = 0; d < s; ++d) Y[i * kk + 1 + d] += dW[i * s + d];
+  const int64_t ns = n * s;
+  for (int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x; t < ns; t += (int64_t)gridDim.x * NT)
+    Y[(t / s) * kk + 1 + t % s] += dW[t];
 }
 
 // P = U^T Y (s x kk): block b accumulates the U entries of its row range in row
@@ -386,13 +394,13 @@ void solve_impl(const sai_split_s* sp, const sai_precond_s* pc, const double* b,
     t_ref.start(st);
     std::vector<double> thr2 = thresholds(bnorm, s, o.eps, c);
     DBuf<double> Raux(&al, (size_t)n * s), dW(&al, (size_t)n * s);
-    hipLaunchKernelGGL(k_aux_residual, dim3(rows_grid(n)), dim3(NT), 0, st, n, s, sp->t_row_ptr.p,
+    hipLaunchKernelGGL(k_aux_residual, dim3(grid_for(n * s, NT, 8192)), dim3(NT), 0, st, n, s, sp->t_row_ptr.p,
                        sp->t_col_idx.p, sp->t_val.p, sp->u_row_ptr.p, sp->u_col.p, sp->u_val.p,
                        Y.p, Raux.p);
     LAUNCH_CHECK();
     std::vector<int32_t> its2(s, 0), sts2(s, 0);
     code = krylov_impl(sp, pc, 0, s, Raux.p, dW.p, thr2.data() + 1, o, st, its2.data(), sts2.data());
-    hipLaunchKernelGGL(k_aux_add, dim3(rows_grid(n)), dim3(NT), 0, st, n, s, dW.p, Y.p);
+    hipLaunchKernelGGL(k_aux_add, dim3(grid_for(n * s, NT, 8192)), dim3(NT), 0, st, n, s, dW.p, Y.p);
     LAUNCH_CHECK();
     for (int d = 0; d < s; ++d) its[d + 1] += its2[d];
     smw_recover(sp, Y.p, x, &c, st);
@@ -482,7 +490,7 @@ void backward_impl(const sai_split_s* sp, const sai_precond_s* pc, const double*
     // solves (correction solves on V - A~^T Z) to eps ||g|| / (2 sqrt(s) c')
     std::vector<double> thr2 = thresholds(gnorm, s, o.eps, cprime);
     DBuf<double> Raux(&al, (size_t)n * s), dZ(&al, (size_t)n * s);
-    hipLaunchKernelGGL(k_aux_residual_t, dim3(rows_grid(n)), dim3(NT), 0, st, n, s, sp->t_col_ptr.p,
+    hipLaunchKernelGGL(k_aux_residual_t, dim3(grid_for(n * s, NT, 8192)), dim3(NT), 0, st, n, s, sp->t_col_ptr.p,
                        sp->t_row_idx.p, sp->t_cval.p, Y.p, Raux.p);
     LAUNCH_CHECK();
     hipLaunchKernelGGL(k_add_units, dim3(grid_for(s, NT)), dim3(NT), 0, st, s, sp->dense_cols.p,
@@ -490,7 +498,7 @@ void backward_impl(const sai_split_s* sp, const sai_precond_s* pc, const double*
     LAUNCH_CHECK();
     std::vector<int32_t> its2(s, 0), sts2(s, 0);
     code = krylov_impl(sp, pc, 1, s, Raux.p, dZ.p, thr2.data() + 1, o, st, its2.data(), sts2.data());
-    hipLaunchKernelGGL(k_aux_add, dim3(rows_grid(n)), dim3(NT), 0, st, n, s, dZ.p, Y.p);
+    hipLaunchKernelGGL(k_aux_add, dim3(grid_for(n * s, NT, 8192)), dim3(NT), 0, st, n, s, dZ.p, Y.p);
     LAUNCH_CHECK();
     for (int d = 0; d < s; ++d) its[d + 1] += its2[d];
     cprime = recover();
