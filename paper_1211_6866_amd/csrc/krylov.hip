@@ -128,13 +128,28 @@ void block_alloc(Block& B, int k, int64_t n, const Allocator& al, double* part, 
 
 enum { IT_DONE = 0, IT_NARROW = 1 };
 
+// Profile names of one iteration's launches; the launches on a narrowed block
+// carry their own names, so that the per-launch figures of the full-width
+// block (whose algorithmic bytes follow from k) stay apart.
+struct IterNames {
+  const char *pup, *m32, *m64, *av, *fin, *s, *at, *half, *xr, *full, *rst, *fend;
+};
+const IterNames kWideNames{"bicg_p_update", "bicg_spmm_M_f32", "bicg_spmm_M_f64", "bicg_spmm_A_dot1",
+                           "bicg_finish", "bicg_s_update", "bicg_spmm_A_dot2", "bicg_halfcheck",
+                           "bicg_xr_update", "bicg_fullcheck", "bicg_restart", "bicg_finish_end"};
+const IterNames kNarrowNames{"bicg_narrow_p_update", "bicg_spmm_narrow_M_f32", "bicg_spmm_narrow_M_f64",
+                             "bicg_spmm_narrow_A_dot1", "bicg_narrow_finish", "bicg_narrow_s_update",
+                             "bicg_spmm_narrow_A_dot2", "bicg_narrow_halfcheck", "bicg_narrow_xr_update",
+                             "bicg_narrow_fullcheck", "bicg_narrow_restart", "bicg_narrow_finish_end"};
+
 // Iterations it, it+1, ... on block B with LP lanes per row, until every column
 // has stopped or maxit is reached (IT_DONE), or the active columns would fit a
 // narrower lane class (IT_NARROW).  The first phase also initialises from R.
 template <int LP, class TM>
 int iterate(Block& B, const Csr<double>& A, const Csr<TM>& M, int64_t n, int& it, int maxit, bool first,
-            bool narrow_ok, const double* R, hipStream_t st, int* slot, hipEvent_t* ev) {
+            bool narrow_ok, bool narrowed, const double* R, hipStream_t st, int* slot, hipEvent_t* ev) {
   const int k = B.k, kp = B.kp;
+  const IterNames& N = narrowed ? kNarrowNames : kWideNames;
   const State S = B.S;
   const Vec V = B.V;
   constexpr int RPB = (64 / LP) * (NT / 64);
@@ -228,35 +243,35 @@ int iterate(Block& B, const Csr<double>& A, const Csr<TM>& M, int64_t n, int& it
     hipLaunchKernelGGL(__VA_ARGS__); \
   } while (0)
     constexpr bool MF = sizeof(TM) == 4;
-    LK("bicg_p_update", (k_pupdate<LP>), dim3(grid), dim3(NT), 0, st, n, k, kp, V, S);
+    LK(N.pup, (k_pupdate<LP>), dim3(grid), dim3(NT), 0, st, n, k, kp, V, S);
     {
-      SAI_PROF(MF ? "bicg_spmm_M_f32" : "bicg_spmm_M_f64", st);
+      SAI_PROF(MF ? N.m32 : N.m64, st);
       spmm_m(V.p, V.ph);
     }
     {
-      SAI_PROF("bicg_spmm_A_dot1", st);
+      SAI_PROF(N.av, st);
       spmm_av();
     }
-    LK("bicg_finish", (k_fin<1, F_AV>), dim3(1), dim3(FNT), 0, st, k, S, tgrid, 0, 0);
-    LK("bicg_s_update", (k_s<LP>), dim3(grid), dim3(NT), 0, st, n, k, kp, V, S);
+    LK(N.fin, (k_fin<1, F_AV>), dim3(1), dim3(FNT), 0, st, k, S, tgrid, 0, 0);
+    LK(N.s, (k_s<LP>), dim3(grid), dim3(NT), 0, st, n, k, kp, V, S);
     {
-      SAI_PROF(MF ? "bicg_spmm_M_f32" : "bicg_spmm_M_f64", st);
+      SAI_PROF(MF ? N.m32 : N.m64, st);
       spmm_m(V.s, V.sh);
     }
     {
-      SAI_PROF("bicg_spmm_A_dot2", st);
+      SAI_PROF(N.at, st);
       spmm_at();
     }
-    LK("bicg_finish", (k_fin<3, F_AT>), dim3(1), dim3(FNT), 0, st, k, S, tgrid, 0, 0);
-    LK("bicg_halfcheck", (k_halfcheck<LP>), dim3(tgrid), dim3(NT), 0, st, n, k, kp, A, V, S, xmap);
-    LK("bicg_finish", (k_fin<1, F_HALF>), dim3(1), dim3(FNT), 0, st, k, S, tgrid, 0, 0);
-    LK("bicg_xr_update", (k_xr<LP>), dim3(grid), dim3(NT), 0, st, n, k, kp, V, S);
-    LK("bicg_finish", (k_fin<2, F_XR>), dim3(1), dim3(FNT), 0, st, k, S, grid, it, 0, force_it, force_it2);
-    LK("bicg_fullcheck", (k_fullcheck<LP>), dim3(tgrid), dim3(NT), 0, st, n, k, kp, A, V, S, xmap);
-    LK("bicg_finish", (k_fin<2, F_FULL>), dim3(1), dim3(FNT), 0, st, k, S, tgrid, it, 0, force_it,
+    LK(N.fin, (k_fin<3, F_AT>), dim3(1), dim3(FNT), 0, st, k, S, tgrid, 0, 0);
+    LK(N.half, (k_halfcheck<LP>), dim3(tgrid), dim3(NT), 0, st, n, k, kp, A, V, S, xmap);
+    LK(N.fin, (k_fin<1, F_HALF>), dim3(1), dim3(FNT), 0, st, k, S, tgrid, 0, 0);
+    LK(N.xr, (k_xr<LP>), dim3(grid), dim3(NT), 0, st, n, k, kp, V, S);
+    LK(N.fin, (k_fin<2, F_XR>), dim3(1), dim3(FNT), 0, st, k, S, grid, it, 0, force_it, force_it2);
+    LK(N.full, (k_fullcheck<LP>), dim3(tgrid), dim3(NT), 0, st, n, k, kp, A, V, S, xmap);
+    LK(N.fin, (k_fin<2, F_FULL>), dim3(1), dim3(FNT), 0, st, k, S, tgrid, it, 0, force_it,
        force_it2);
-    LK("bicg_restart", (k_restart<LP>), dim3(grid), dim3(NT), 0, st, n, k, kp, V, S);
-    LK("bicg_finish_end", (k_fin<1, F_RESTART_END>), dim3(1), dim3(FNT), 0, st, k, S, grid, it, maxit);
+    LK(N.rst, (k_restart<LP>), dim3(grid), dim3(NT), 0, st, n, k, kp, V, S);
+    LK(N.fend, (k_fin<1, F_RESTART_END>), dim3(1), dim3(FNT), 0, st, k, S, grid, it, maxit);
 #undef LK
     LAUNCH_CHECK();
     HIPC(hipMemcpyAsync(slot + (it & 1), S.any + 3, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -288,16 +303,17 @@ int iterate(Block& B, const Csr<double>& A, const Csr<TM>& M, int64_t n, int& it
 
 template <class TM>
 int iterate_lp(int lp, Block& B, const Csr<double>& A, const Csr<TM>& M, int64_t n, int& it, int maxit,
-               bool first, bool narrow_ok, const double* R, hipStream_t st, int* slot, hipEvent_t* ev) {
+               bool first, bool narrow_ok, bool narrowed, const double* R, hipStream_t st, int* slot,
+               hipEvent_t* ev) {
   switch (lp) {
-    case 1: return iterate<1, TM>(B, A, M, n, it, maxit, first, narrow_ok, R, st, slot, ev);
-    case 2: return iterate<2, TM>(B, A, M, n, it, maxit, first, narrow_ok, R, st, slot, ev);
-    case 4: return iterate<4, TM>(B, A, M, n, it, maxit, first, narrow_ok, R, st, slot, ev);
-    case 6: return iterate<6, TM>(B, A, M, n, it, maxit, first, narrow_ok, R, st, slot, ev);
-    case 8: return iterate<8, TM>(B, A, M, n, it, maxit, first, narrow_ok, R, st, slot, ev);
-    case 12: return iterate<12, TM>(B, A, M, n, it, maxit, first, narrow_ok, R, st, slot, ev);
-    case 16: return iterate<16, TM>(B, A, M, n, it, maxit, first, narrow_ok, R, st, slot, ev);
-    default: return iterate<32, TM>(B, A, M, n, it, maxit, first, narrow_ok, R, st, slot, ev);
+    case 1: return iterate<1, TM>(B, A, M, n, it, maxit, first, narrow_ok, narrowed, R, st, slot, ev);
+    case 2: return iterate<2, TM>(B, A, M, n, it, maxit, first, narrow_ok, narrowed, R, st, slot, ev);
+    case 4: return iterate<4, TM>(B, A, M, n, it, maxit, first, narrow_ok, narrowed, R, st, slot, ev);
+    case 6: return iterate<6, TM>(B, A, M, n, it, maxit, first, narrow_ok, narrowed, R, st, slot, ev);
+    case 8: return iterate<8, TM>(B, A, M, n, it, maxit, first, narrow_ok, narrowed, R, st, slot, ev);
+    case 12: return iterate<12, TM>(B, A, M, n, it, maxit, first, narrow_ok, narrowed, R, st, slot, ev);
+    case 16: return iterate<16, TM>(B, A, M, n, it, maxit, first, narrow_ok, narrowed, R, st, slot, ev);
+    default: return iterate<32, TM>(B, A, M, n, it, maxit, first, narrow_ok, narrowed, R, st, slot, ev);
   }
 }
 
@@ -347,10 +363,12 @@ int bicgstab(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, const dou
   const bool narrow_ok = tune_get("NARROW", 1) != 0;
   std::vector<int> rstat(k, ST_MAXIT), riter(k, 0);
   int it = 1;
-  bool first = true;
+  bool first = true, first_block = true;
   for (;;) {
     Block& B = blk[cur];
-    const int r = iterate_lp<TM>(lp_class(B.k), B, A, M, n, it, maxit, first, narrow_ok, R, st, slot, ev);
+    const int r = iterate_lp<TM>(lp_class(B.k), B, A, M, n, it, maxit, first, narrow_ok, !first_block, R, st,
+                                 slot, ev);
+    first_block = false;
     first = false;
     HIPC(hipMemcpyAsync(hsc, B.sc.p, sizeof(double) * SC_N, hipMemcpyDeviceToHost, st));
     HIPC(hipMemcpyAsync(hsi, B.si.p, sizeof(int) * SI_N, hipMemcpyDeviceToHost, st));
