@@ -250,7 +250,10 @@ int sai_gather(const sai_split_t* sp, const sai_precond_t* pc, int32_t precision
  * one workgroup per column (modified Gram-Schmidt); the two round differently.
  * iters/status: host arrays of k entries (may be NULL); status per column is
  * 0 converged, 1 maxit, 2 breakdown.  Returns SAI_ENOCONV / SAI_EBREAKDOWN if
- * any column ended that way (X is written in every case).  k <= 64. */
+ * any column ended that way (X is written in every case).  Any k >= 1: up to
+ * 64 columns run as one lockstep solve, wider blocks in groups of 64 columns
+ * one after the other (sai_solve and sai_backward pass s + 1 columns, so s is
+ * not limited by the solver; the allocation-free SMW below takes s <= 64). */
 enum { SAI_BICGSTAB = 0, SAI_GMRES = 1 };
 enum { SAI_C_ONE = 0, SAI_C_ONE_THEN_REFINE = 1 };
 typedef struct {

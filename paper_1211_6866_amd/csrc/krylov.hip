@@ -651,18 +651,58 @@ int krylov_typed(const sai_split_s* sp, const sai_precond_s* pc, int transpose, 
   return bicgstab<TM>(A, M, n, k, R, X, thr, o.maxit, al, st, iters, status);
 }
 
+// dst (n x kc, row stride kc) = columns c0 .. c0+kc-1 of src (row stride lds),
+// or back (to_src): those columns of src = dst
+__global__ void k_col_group(int64_t n, int lds, int c0, int kc, const double* __restrict__ a,
+                            double* __restrict__ b, int to_src) {
+  const int64_t nk = n * kc;
+  for (int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x; t < nk; t += (int64_t)gridDim.x * NT) {
+    const int64_t i = t / kc, e = i * lds + c0 + t % kc;
+    if (to_src) b[e] = a[t];
+    else b[t] = a[e];
+  }
+}
+
+int krylov_one(const sai_split_s* sp, const sai_precond_s* pc, int transpose, int k, const double* R,
+               double* X, const double* thr, const sai_solve_opts& o, hipStream_t st, int32_t* iters,
+               int32_t* status) {
+  if (pc->precision == SAI_FP32)
+    return krylov_typed<float>(sp, pc, transpose, k, R, X, thr, o, st, iters, status);
+  return krylov_typed<double>(sp, pc, transpose, k, R, X, thr, o, st, iters, status);
+}
+
 }  // namespace
+
+// Blocks of up to KMAX columns run as one lockstep solve; wider blocks in groups
+// of KMAX columns, one after the other (the systems are independent, so each
+// column's iterates do not depend on the grouping).
+constexpr int KMAX = 64;
 
 int krylov_impl(const sai_split_s* sp, const sai_precond_s* pc, int transpose, int k,
                 const double* R, double* X, const double* thr, const sai_solve_opts& o,
                 hipStream_t st, int32_t* iters, int32_t* status) {
-  if (k < 1 || k > 64) SAI_THROW(SAI_EINVAL, "k must be in [1, 64] (got %d)", k);
+  if (k < 1) SAI_THROW(SAI_EINVAL, "k must be >= 1 (got %d)", k);
   if (o.method != SAI_BICGSTAB && o.method != SAI_GMRES) SAI_THROW(SAI_EINVAL, "bad method");
   if (o.maxit < 0) SAI_THROW(SAI_EINVAL, "maxit < 0");
   if (pc->n != sp->n) SAI_THROW(SAI_EINVAL, "preconditioner and split sizes differ");
-  if (pc->precision == SAI_FP32)
-    return krylov_typed<float>(sp, pc, transpose, k, R, X, thr, o, st, iters, status);
-  return krylov_typed<double>(sp, pc, transpose, k, R, X, thr, o, st, iters, status);
+  if (k <= KMAX) return krylov_one(sp, pc, transpose, k, R, X, thr, o, st, iters, status);
+  const Allocator al{sp->al.a, st};
+  const int64_t n = sp->n;
+  DBuf<double> Rg(&al, (size_t)n * KMAX), Xg(&al, (size_t)n * KMAX);
+  int worst = SAI_OK;
+  for (int c0 = 0; c0 < k; c0 += KMAX) {
+    const int kc = std::min(KMAX, k - c0);
+    const unsigned g = grid_for(n * kc, NT, 8192);
+    hipLaunchKernelGGL(k_col_group, dim3(g), dim3(NT), 0, st, n, k, c0, kc, R, Rg.p, 0);
+    LAUNCH_CHECK();
+    const int code = krylov_one(sp, pc, transpose, kc, Rg.p, Xg.p, thr + c0, o, st,
+                                iters ? iters + c0 : nullptr, status ? status + c0 : nullptr);
+    hipLaunchKernelGGL(k_col_group, dim3(g), dim3(NT), 0, st, n, k, c0, kc, (const double*)Xg.p, X, 1);
+    LAUNCH_CHECK();
+    if (code == SAI_EBREAKDOWN || (code == SAI_ENOCONV && worst == SAI_OK)) worst = code;
+  }
+  HIPC(hipStreamSynchronize(st));
+  return worst;
 }
 
 }  // namespace sai

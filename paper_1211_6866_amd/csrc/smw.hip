@@ -161,17 +161,20 @@ __global__ void k_aux_add(int64_t n, int s, const double* __restrict__ dW, doubl
 }
 
 // P = U^T Y (s x kk): block b accumulates the U entries of its row range in row
-// order; lane e owns column e.  Then the partials are summed over blocks in order.
+// order for the columns c0 .. c0+cw-1 of Y (s x cw doubles of LDS); lane e owns
+// columns c0 + e, c0 + e + 64, ...  Then the partials are summed over blocks in
+// order.  UTY_LDS bounds the LDS of one launch; wider blocks take several.
 constexpr int UTY_ROWS = 4096;
-__global__ void __launch_bounds__(64) k_uty_partial(int64_t n, int s, int kk,
+constexpr int UTY_LDS = 6144;  // doubles (48 KB)
+__global__ void __launch_bounds__(64) k_uty_partial(int64_t n, int s, int kk, int c0, int cw,
                                                     const int32_t* __restrict__ urp,
                                                     const int32_t* __restrict__ ucol,
                                                     const double* __restrict__ uval,
                                                     const double* __restrict__ Y,
                                                     double* __restrict__ part) {
-  extern __shared__ double acc[];  // s * kk
+  extern __shared__ double acc[];  // s * cw
   const int e = threadIdx.x;
-  for (int t = e; t < s * kk; t += 64) acc[t] = 0.0;
+  for (int t = e; t < s * cw; t += 64) acc[t] = 0.0;
   __syncthreads();
   const int64_t i0 = (int64_t)blockIdx.x * UTY_ROWS;
   const int64_t i1 = std::min<int64_t>(n, i0 + UTY_ROWS);
@@ -179,11 +182,12 @@ __global__ void __launch_bounds__(64) k_uty_partial(int64_t n, int s, int kk,
     for (int32_t q = urp[i]; q < urp[i + 1]; ++q) {
       const int d = ucol[q];
       const double u = uval[q];
-      for (int c = e; c < kk; c += 64) acc[d * kk + c] += u * Y[i * kk + c];
+      for (int c = e; c < cw; c += 64) acc[d * cw + c] += u * Y[i * kk + c0 + c];
     }
   }
   __syncthreads();
-  for (int t = e; t < s * kk; t += 64) part[(int64_t)blockIdx.x * s * kk + t] = acc[t];
+  for (int t = e; t < s * cw; t += 64)
+    part[((int64_t)blockIdx.x * s + t / cw) * kk + c0 + t % cw] = acc[t];
 }
 __global__ void k_uty_final(int nb, int s, int kk, const double* __restrict__ part,
                             double* __restrict__ P) {
@@ -351,7 +355,6 @@ void solve_impl(const sai_split_s* sp, const sai_precond_s* pc, const double* b,
   const Allocator al{sp->al.a, st};
   const int s = sp->s, kk = s + 1;
   const int64_t n = sp->n;
-  if (kk > 64) SAI_THROW(SAI_ETOOBIG, "s + 1 = %d exceeds 64 right-hand sides", kk);
   EventTimer t_solve, t_smw, t_chk;
   DBuf<double> R(&al, (size_t)n * kk), Y(&al, (size_t)n * kk);
   // Section 4's scaling (equilibrate): solve with alpha b, alpha = rho / ||b||,
@@ -437,7 +440,6 @@ void backward_impl(const sai_split_s* sp, const sai_precond_s* pc, const double*
   const Allocator al{sp->al.a, st};
   const int s = sp->s, kk = s + 1;
   const int64_t n = sp->n;
-  if (kk > 64) SAI_THROW(SAI_ETOOBIG, "s + 1 = %d exceeds 64 right-hand sides", kk);
   EventTimer t_solve, t_smw;
   DBuf<double> R(&al, (size_t)n * kk), Y(&al, (size_t)n * kk), lam(&al, (size_t)n);
   hipLaunchKernelGGL(k_rhs_gv, dim3(rows_grid(n)), dim3(NT), 0, st, n, s, gx, R.p);
@@ -464,9 +466,13 @@ void backward_impl(const sai_split_s* sp, const sai_precond_s* pc, const double*
     const int64_t nb = (n + UTY_ROWS - 1) / UTY_ROWS;
     DBuf<double> part(&al, (size_t)nb * s * kk), P(&al, (size_t)s * kk), K(&al, (size_t)s * s),
         w(&al, (size_t)s);
-    hipLaunchKernelGGL(k_uty_partial, dim3((unsigned)nb), dim3(64), sizeof(double) * s * kk, st, n, s,
-                       kk, sp->u_row_ptr.p, sp->u_col.p, sp->u_val.p, Y.p, part.p);
-    LAUNCH_CHECK();
+    const int cw = std::max(1, std::min(kk, UTY_LDS / s));
+    for (int c0 = 0; c0 < kk; c0 += cw) {
+      const int w = std::min(cw, kk - c0);
+      hipLaunchKernelGGL(k_uty_partial, dim3((unsigned)nb), dim3(64), sizeof(double) * s * w, st, n, s,
+                         kk, c0, w, sp->u_row_ptr.p, sp->u_col.p, sp->u_val.p, Y.p, part.p);
+      LAUNCH_CHECK();
+    }
     hipLaunchKernelGGL(k_uty_final, dim3(grid_for(s * kk, NT)), dim3(NT), 0, st, (int)nb, s, kk, part.p,
                        P.p);
     LAUNCH_CHECK();

@@ -483,6 +483,50 @@ def test_adjoint_vs_oracle(name):
     assert np.linalg.norm(_np(ga) - Gd) <= 1e-5 * np.linalg.norm(Gd)
 
 
+def test_more_than_64_right_hand_sides():
+    """s = 100 irregular columns (101 right-hand sides, solved in groups of 64
+    and 37): the forward solve against the oracle pipeline (rr within the
+    theorem's (eps/2)(1 + c), x within ||A^{-1}|| times both residuals), the
+    Krylov block against the oracle column by column, and the adjoint (U^T Z
+    reduced in two column groups) against the dense solve."""
+    w = W.make(4, dims=(60, 60), s=100, density=0.15)
+    rp, ci, va = P.csr_to_device(w.A)
+    g = P.Split(rp, ci, va)
+    assert g.s == 100
+    pc = P.Precond(g, pattern=P.PAT_A2, drop=P.DROP_ABS, tau=1e-3, precision=P.FP64)
+    b = torch.from_numpy(w.b).cuda()
+    x, st = P.solve(g, pc, b)
+    xs = _np(x)
+    out = opipe.run(w.A, w.b, kind="A2", drop="abs")
+    rr = np.linalg.norm(w.b - w.A @ xs) / np.linalg.norm(w.b)
+    assert st["status"] == P.OK and rr < 1e-8 * (1.0 + st["c"]) / 2.0 * (1.0 + 1e-6), (rr, st["c"])
+    assert len(st["iters"]) == 101 and all(abs(a - o) <= 1 for a, o in zip(st["iters"], out["iters"]))
+    smin = float(np.linalg.svd(w.A.toarray(), compute_uv=False)[-1])
+    bound = (np.linalg.norm(w.b - w.A @ xs) + np.linalg.norm(w.b - w.A @ out["x"])) / smin
+    assert np.linalg.norm(xs - out["x"]) <= bound
+    # the block through sai_krylov directly, against the oracle's solves
+    S = osplit.split(w.A)
+    R = np.zeros((w.A.shape[0], 101))
+    R[:, 0] = w.b
+    R[:, 1:] = S.U.toarray()
+    thr = okry.thresholds(np.linalg.norm(w.b), S.s, 1e-10)
+    X, its, sts, code = P.krylov(g, pc, torch.from_numpy(R).cuda(), thr)
+    assert code == P.OK and all(v == 0 for v in sts)
+    Xh = _np(X)
+    At = sp.csr_matrix(S.At)
+    for c in range(101):
+        assert np.linalg.norm(R[:, c] - At @ Xh[:, c]) < thr[c], c
+    # adjoint
+    xst = W.x_star(w.A.shape[0], w.seed)
+    gx = x - torch.from_numpy(xst).cuda()
+    gb, ga, bst = P.backward(g, pc, x, gx, eps=1e-12)
+    Ad = w.A.toarray()
+    lam = np.linalg.solve(Ad.T, xs - xst)
+    assert np.linalg.norm(_np(gb) - lam) <= 1e-5 * np.linalg.norm(lam)
+    Gd = oadj.grad_A_values(w.A, lam, xs)
+    assert np.linalg.norm(_np(ga) - Gd) <= 1e-5 * np.linalg.norm(Gd)
+
+
 def test_autograd_function():
     w, (rp, ci, va) = _load("c2_12")
     a = va.clone().requires_grad_(True)
