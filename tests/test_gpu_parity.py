@@ -905,9 +905,11 @@ def test_spai_zero_steps(init):
 @pytest.mark.parametrize("prec", [P.FP64, P.FP32])
 def test_gather_vs_oracle(name, kind, prec):
     """sai_gather writes A~(I_k, J_k) for every column: bit-exact against the
-    oracle's dense block (FP32: its float32 rounding).  The SPAI case has blocks
-    larger than the 8 KB LDS tile (more than 2048 float or 1024 double
-    elements, or more than 256 rows), which are filled element by element."""
+    oracle's dense block (FP32: its float32 rounding).  Blocks of up to 256 rows,
+    64 columns and 256 gathered entries are staged and written in 4 KB chunks
+    (several chunks for the larger ones, with unaligned heads and tails); the
+    SPAI case also has blocks past those limits, which are filled element by
+    element."""
     if name == "banded":
         A = W.banded(600, 8, 2, 0.5, 7)
         dev = P.csr_to_device(A)
@@ -925,7 +927,8 @@ def test_gather_vs_oracle(name, kind, prec):
     off, blocks = _np(off), _np(blocks)
     n = A.shape[0]
     assert off[0] == 0 and off[-1] == int(np.sum(np.diff(jp) * np.diff(ip)))
-    big = 0
+    colnnz = np.diff(C.indptr)
+    big = multi = 0
     for k in range(n):
         J, I = ji[jp[k]:jp[k + 1]], ii[ip[k]:ip[k + 1]]
         ref = olsq.dense_block(C, I, J)
@@ -933,9 +936,12 @@ def test_gather_vs_oracle(name, kind, prec):
         if prec == P.FP32:
             ref = ref.astype(np.float32)
         assert np.array_equal(got, ref), k
-        big += len(I) > 256 or len(J) > 64 or len(I) * len(J) > (2048 if prec == P.FP32 else 1024)
+        staged = len(I) <= 256 and len(J) <= 64 and int(colnnz[J].sum()) <= 256
+        big += not staged
+        multi += staged and len(I) * len(J) > (1024 if prec == P.FP32 else 512)
     if name == "c3_3000":
         assert big > 0
+    print(f"{name}: {big} blocks past the staging limits, {multi} staged blocks of several chunks")
 
 
 def test_solve_equilibrated_vs_oracle():
