@@ -90,6 +90,25 @@ def workload_settings(P, idx):
     raise SystemExit(f"unknown workload {idx}")
 
 
+def device_copy_gbs(torch, nbytes=1 << 31, reps=5):
+    """Bytes read + written per second by a plain device-to-device copy of
+    nbytes (torch's copy kernel), the median of reps after one warm-up."""
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        y.copy_(x)
+        b.record()
+        b.synchronize()
+        ts.append(a.elapsed_time(b) * 1e-3)
+    del x, y
+    ts.sort()
+    return 2.0 * nbytes / ts[len(ts) // 2] / 1e9
+
+
 def ls_flops(nI, nJ):
     """Householder QR of |I| x |J|, Q^T e and back-substitution."""
     return 2.0 * nJ * nJ * (nI - nJ / 3.0) + 4.0 * nI * nJ - nJ * nJ
@@ -410,6 +429,7 @@ def main():
 
     xh = x_m.cpu().numpy()
     rr_host = float(np.linalg.norm(w.b - w.A @ xh) / np.linalg.norm(w.b))
+    copy_gbs = device_copy_gbs(torch)
 
     # algorithmic work per kernel, for the roofline of the dominant one
     s = sp_m.s
@@ -440,6 +460,7 @@ def main():
                   + 4.0 * float(np.sum(nJ.astype(np.float64) * nI)))
         gavg = gms / gl
         gather = dict(kernel="gather_f32", avg_launch_ms=round(gavg, 4), algorithmic_bytes=gbytes,
+                      frac_of_copy=round(gbytes / (gavg * 1e-3) / 1e9 / copy_gbs, 4) if copy_gbs else None,
                       achieved_GBs=round(gbytes / (gavg * 1e-3) / 1e9, 1),
                       frac=round(gbytes / (gavg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                       gathered_entries=int(gathered), block_elements=int(np.sum(nJ.astype(np.int64) * nI)))
@@ -488,6 +509,10 @@ def main():
         roof = dict(bound="latency", achieved=None, peak=None, unit=None, frac=None, traffic=None)
     roof["kernel"] = dom
     roof["avg_launch_ms"] = round(avg_ms, 4)
+    if copy_gbs and roof.get("bound") == "hbm":
+        # against what a plain device copy reaches on this GPU
+        roof["measured_copy_GBs"] = round(copy_gbs, 1)
+        roof["frac_of_copy"] = round(roof["achieved"] / copy_gbs, 4)
     roof["launches_per_step"] = dom_launches / args.steps
     if dom in hbm_bytes:
         roof["algorithmic_bytes_per_launch"] = hbm_bytes[dom]

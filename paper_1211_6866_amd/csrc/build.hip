@@ -97,8 +97,8 @@ __global__ void k_to_type(int64_t m, const double* __restrict__ in, T* __restric
 
 // Dropping (Section 2.2): entries of the computed column m_k with |m_jk| <= thr
 // are removed (thr = tau, or (tolk) delta / (|J_k| ||A~||_1)); the entry of
-// largest magnitude (the first of equals) is always kept.  32 lanes per column
-// (two columns per wavefront) read the column coalesced; the kept entries keep
+// largest magnitude (the first of equals) is always kept.  16 lanes per column
+// (four columns per wavefront) read the column coalesced; the kept entries keep
 // their order (ballot prefix counts).  COUNT: number kept per column; else the
 // kept (row, value) pairs are written from colp[k] on.  The COUNT pass also
 // counts, into *nearc, the entries other than the always-kept one with
