@@ -201,3 +201,29 @@ def test_fullsize_psai_tol(idx, delta, lmax):
     rr = np.linalg.norm(w.b - w.A @ _np(x)) / np.linalg.norm(w.b)
     print(f"workload {idx}: PSAI(tol) rr = {rr:.3e}, iters = {st['iters']}", flush=True)
     assert rr < 1e-8 * (1.0 + st["c"]) / 2.0 * (1.0 + 1e-6), (rr, st["c"])  # the theorem with c = 1
+
+
+@pytest.mark.parametrize("idx", [2, 5])
+def test_fullsize_gmres20(idx):
+    """GMRES(20) on the s+1 systems at full size (the batched form, run by
+    `bench.py --method gmres --restart 20`): every column meets its (stopb) /
+    (stopU2) threshold, so rr recomputed on the host in FP64 is within the
+    theorem's (eps/2)(1 + c), as is BiCGStab's.  The two x differ by at most
+    ||A^{-1}|| times the sum of their residuals; kappa(A) of these stencil
+    matrices is of order 1e4, so they must agree to 1e-3 relative."""
+    print(f"\nworkload {idx}: GMRES(20)", flush=True)
+    w = W.make(idx)
+    rp, ci, va = P.csr_to_device(w.A)
+    g = P.Split(rp, ci, va)
+    pc = P.Precond(g, precision=P.FP32, **SETTINGS[idx])
+    b = torch.from_numpy(w.b).cuda()
+    xg, sg = P.solve(g, pc, b, method=P.GMRES, restart=20, eps=1e-8)
+    xb, sb = P.solve(g, pc, b, method=P.BICGSTAB, eps=1e-8)
+    bn = np.linalg.norm(w.b)
+    for x, st in ((xg, sg), (xb, sb)):
+        rr = np.linalg.norm(w.b - w.A @ _np(x)) / bn
+        assert st["status"] == P.OK and rr < 1e-8 * (1.0 + st["c"]) / 2.0 * (1.0 + 1e-6), (rr, st["c"])
+    e = np.linalg.norm(_np(xg) - _np(xb)) / np.linalg.norm(_np(xb))
+    print(f"workload {idx}: GMRES(20) iterations max {max(sg['iters'])}, BiCGStab {max(sb['iters'])}, "
+          f"|x_g - x_b| / |x_b| = {e:.2e}", flush=True)
+    assert e <= 1e-3
