@@ -445,11 +445,24 @@ int gmres_batched_lp(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, c
     int64_t g = std::min<int64_t>({(int64_t)NBMAX, ntiles, (int64_t)resident_blocks(kern, NT)});
     return (int)(g >= 8 ? (g & ~int64_t(7)) : g);
   };
-  const void* km = (const void*)k_spmm<LP, TM, 6, 3>;
+  // the M product's gather batches follow the SPMM_M knob, as in BiCGStab
+  const int mvar = tune_get("SPMM_M", 1);
+  const void* km = mvar == 0   ? (const void*)k_spmm<LP, TM, 8, 4>
+                   : mvar == 2 ? (const void*)k_spmm<LP, TM, 5, 0>
+                   : mvar == 3 ? (const void*)k_spmm<LP, TM, 16, 8>
+                               : (const void*)k_spmm<LP, TM, 6, 3>;
   const void* ka = (const void*)k_spmm<LP, double, 6, 3>;
   const int gm = sp_grid(km), ga = sp_grid(ka);
   auto mprod = [&](const double* in, double* out, const State& S) {
-    hipLaunchKernelGGL((k_spmm<LP, TM, 6, 3>), dim3(gm), dim3(NT), 0, st, n, k, kp, M, in, out, S, xmap);
+    auto go = [&](auto kern) {
+      hipLaunchKernelGGL(kern, dim3(gm), dim3(NT), 0, st, n, k, kp, M, in, out, S, xmap);
+    };
+    switch (mvar) {
+      case 0: go(k_spmm<LP, TM, 8, 4>); break;
+      case 2: go(k_spmm<LP, TM, 5, 0>); break;
+      case 3: go(k_spmm<LP, TM, 16, 8>); break;
+      default: go(k_spmm<LP, TM, 6, 3>); break;
+    }
   };
   auto aprod = [&](const double* in, double* out, const State& S) {
     hipLaunchKernelGGL((k_spmm<LP, double, 6, 3>), dim3(ga), dim3(NT), 0, st, n, k, kp, A, in, out, S, xmap);
