@@ -298,7 +298,7 @@ def main():
     ap.add_argument("--restart", type=int, default=20)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU: --gpus must be 1 (the path shards by "
+        print(json.dumps({"error": "this benchmark runs on one GPU: --gpus must be 1 (the path shards by "
                                    "columns and right-hand sides, but no multi-GPU code is built)"}))
         sys.exit(2)
 
