@@ -572,6 +572,9 @@ def main():
                    "adjoint_in_step": adjoint, "parallelism": "single GPU"},
         "time_to_1e-8_ms": {"mixed": round(ms_mixed, 3),
                             "plain_fp64": round(plain["ms"], 3) if plain else None},
+        # the forward path alone (split, build, solve, SMW, check): the step less its adjoint
+        "forward_ms": {"mixed": round(ms_mixed - (float(np.mean(backs_m)) if backs_m else 0.0), 3),
+                       "plain_fp64": (round(plain["ms"] - (plain["adjoint"] or 0.0), 3) if plain else None)},
         "build_ms": {"mixed": round(float(np.mean(builds_m)), 3),
                      "plain_fp64": round(plain["build"], 3) if plain else None},
         "build_columns_per_s": {"mixed": round(n / (np.mean(builds_m) * 1e-3), 1),
