@@ -251,3 +251,36 @@ def check_bicgstab_replacement(bicgstab_fn, A, M, b, thr):
     xd = np.linalg.solve(Ad, b)
     kappa = np.linalg.cond(Ad)
     assert np.linalg.norm(x - xd) <= 2.0 * kappa * thr / np.linalg.norm(b) * np.linalg.norm(xd)
+
+
+def _krylov_minres(AM, r, m):
+    """argmin ||r - AM z|| over z in K_m(AM, r), from an orthonormal basis of
+    the explicit Krylov vectors r, AM r, ..., (AM)^(m-1) r (numpy QR) and a dense
+    least-squares solve: a formulation independent of Arnoldi and Givens."""
+    K = np.empty((r.size, m))
+    v = r / np.linalg.norm(r)
+    for j in range(m):
+        K[:, j] = v
+        v = AM @ v
+        v = v / np.linalg.norm(v)
+    Q, _ = np.linalg.qr(K)
+    y, *_ = np.linalg.lstsq(AM @ Q, r, rcond=None)
+    return Q @ y
+
+
+def check_gmres_cycles_minimise(gmres_fn, A, M, b, m, cycles=2):
+    """GMRES(m) (Section 5's setting, right preconditioning): each full cycle
+    takes x_{c+1} = x_c + M z with z minimising ||r_c - A M z|| over the Krylov
+    space K_m(A M, r_c) of the current true residual r_c = b - A x_c.  Run for
+    exactly `cycles` full cycles (threshold 0, maxit = cycles m) and compare with
+    those minimisers built without Arnoldi (to 1e-8 relative)."""
+    Ad = A.toarray() if sp.issparse(A) else np.asarray(A)
+    Md = M.toarray() if sp.issparse(M) else np.asarray(M)
+    AM = Ad @ Md
+    x, it, st = gmres_fn(A, M, b, 0.0, restart=m, maxit=cycles * m)
+    assert st == "maxit" and it == cycles * m, (st, it)
+    xe = np.zeros(b.size)
+    for _ in range(cycles):
+        r = b - Ad @ xe
+        xe = xe + Md @ _krylov_minres(AM, r, m)
+    assert np.linalg.norm(x - xe) <= 1e-8 * np.linalg.norm(xe), np.linalg.norm(x - xe) / np.linalg.norm(xe)

@@ -33,6 +33,19 @@ def test_unpreconditioned_gmres_exact_in_n_steps():
     assert np.allclose(x, np.linalg.solve(A.toarray(), b), atol=1e-9)
 
 
+@pytest.mark.parametrize("m,cycles", [(5, 1), (5, 3), (12, 2)])
+def test_gmres_cycles_minimise_residual(m, cycles):
+    """GMRES(m) against the minimal residual over each cycle's Krylov space,
+    with a sparse approximate inverse as M (its entries from a dense inverse)."""
+    import pins
+    A = _small(4, n=80)
+    Ad = A.toarray()
+    Minv = np.linalg.inv(Ad)
+    Minv[np.abs(Minv) < 0.05 * np.abs(Minv).max()] = 0.0
+    b = np.random.default_rng(4).standard_normal(80)
+    pins.check_gmres_cycles_minimise(krylov.gmres, A, sp.csr_matrix(Minv), b, m, cycles)
+
+
 def test_bicgstab_true_residual_and_dense_solution():
     A = _small(2, n=200)
     I = sp.identity(200, format="csr")

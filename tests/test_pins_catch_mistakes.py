@@ -234,3 +234,37 @@ def test_equilibration_mistakes_caught(mistake):
         return out
     with pytest.raises(AssertionError):
         check_equilibration(wrong, w.A, w.b)
+
+
+def _gmres_mutant(old, new):
+    """A copy of oracle.krylov.gmres with one textual change (the planted mistake)."""
+    import inspect
+    import textwrap
+
+    from oracle import krylov
+    src = textwrap.dedent(inspect.getsource(krylov.gmres))
+    assert src.count(old) == 1, old
+    ns = dict(vars(krylov))
+    exec(compile(src.replace(old, new), "<gmres mutant>", "exec"), ns)
+    return ns["gmres"]
+
+
+_GMRES_MISTAKES = {
+    "givens_sign": ("g[j + 1] = -sn[j] * g[j]", "g[j + 1] = sn[j] * g[j]"),
+    "no_back_substitution": ("y[i] = (g[i] - H[i, i + 1:k] @ y[i + 1:k]) / H[i, i]", "y[i] = g[i] / H[i, i]"),
+    "restart_from_rhs": ("r = rhs - A @ x", "r = rhs.copy()"),
+    "stale_rotations": ("H[i + 1, j] = -sn[i] * a + cs[i] * b", "H[i + 1, j] = b"),
+    "wrong_basis_vector": ("w = w - H[i, j] * V[i]", "w = w - H[i, j] * V[0]"),
+}
+
+
+@pytest.mark.parametrize("mistake", sorted(_GMRES_MISTAKES))
+def test_gmres_mistakes_caught(mistake):
+    f = _gmres_mutant(*_GMRES_MISTAKES[mistake])
+    A = W.random_sparse(80, 0.04, 4, diag=3.0)
+    Ad = A.toarray()
+    Minv = np.linalg.inv(Ad)
+    Minv[np.abs(Minv) < 0.05 * np.abs(Minv).max()] = 0.0
+    b = np.random.default_rng(4).standard_normal(80)
+    with pytest.raises(AssertionError):
+        pins.check_gmres_cycles_minimise(f, A, sp.csr_matrix(Minv), b, 5, 2)
