@@ -532,6 +532,29 @@ def test_more_than_64_right_hand_sides():
     assert np.linalg.norm(_np(ga) - Gd) <= 1e-5 * np.linalg.norm(Gd)
 
 
+def test_m_product_variants_bit_identical():
+    """The M product's gather-batch variants (SPMM_M = 0 .. 3, chosen by the
+    autotuner) change only how many loads are in flight: each row's products
+    are added in the same order, so the whole Krylov solve is bit-identical."""
+    w, (rp, ci, va) = _load("c2_12")
+    S = osplit.split(w.A)
+    g = P.Split(rp, ci, va)
+    pc = P.Precond(g, pattern=P.PAT_A2, drop=P.DROP_ABS, tau=1e-3, precision=P.FP32)
+    R, _ = _oracle_rhs_and_M(w, S)
+    thr = okry.thresholds(np.linalg.norm(w.b), S.s, 1e-10)
+    out = []
+    try:
+        for v in (1, 0, 2, 3):
+            P.tune_set("SPMM_M", v)
+            X, its, sts, code = P.krylov(g, pc, torch.from_numpy(R).cuda(), thr)
+            assert code == P.OK
+            out.append((_np(X), its))
+    finally:
+        P.tune_set("SPMM_M", 1)
+    for X, its in out[1:]:
+        assert its == out[0][1] and np.array_equal(X, out[0][0])
+
+
 def test_autograd_function():
     w, (rp, ci, va) = _load("c2_12")
     a = va.clone().requires_grad_(True)
