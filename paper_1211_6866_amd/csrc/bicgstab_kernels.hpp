@@ -294,6 +294,20 @@ __device__ __forceinline__ bool stage_tile(const Csr<TV>& A, int64_t t0, int row
     BODY                                                                                \
   }
 
+// The same without LDS staging (STG = false): the lane's row t0 + rib is read
+// from the matrix in global memory (the lanes of a row load the same entries,
+// served by one access), and the tile loop needs no workgroup barrier.  For
+// short rows the staging's barriers and dependent loads cost more than they save.
+#define GLOBAL_ROW_PROD(TV, CH, CH2, A, X, PRE, BODY)                                   \
+  if (rib < rows) {                                                                     \
+    const int64_t i_ = t0 + rib;                                                        \
+    const int64_t qq = i_ * kp + c0;                                                    \
+    PRE                                                                                 \
+    double y0, y1;                                                                      \
+    row_prod<TV, CH, CH2>((A).ci, (A).v, (A).rp[i_], (A).rp[i_ + 1], (X), kp, c0, y0, y1); \
+    BODY                                                                                \
+  }
+
 // ---- initialisation: b = R (pad column 0), x = 0, r = r_hat = b, p = v = 0 -------
 template <int LP>
 __global__ void __launch_bounds__(NT) k_init(int64_t n, int k, int kp, const double* __restrict__ R,
@@ -356,24 +370,35 @@ __global__ void __launch_bounds__(NT) k_spmm(int64_t n, int k, int kp, Csr<TV> A
 }
 
 // ---- v = A p_hat; partial sigma = r_hat^T v --------------------------------------
-template <int LP, int CH, int CH2>
+template <int LP, int CH, int CH2, bool STG = true>
 __global__ void __launch_bounds__(NT) k_av(int64_t n, int k, int kp, Csr<double> A, Vec V, State S,
                                            int xmap) {
   LANES(LP)
-  constexpr int CAP_A = cap_a(RPB);
-  STAGE_DECL(double, CAP_A, RPB)
   double acc[1][2] = {{0.0, 0.0}};
   const bool o0 = lok_ && col_on(S, c0, k), o1 = lok_ && col_on(S, c0 + 1, k);
-  if (S.any[3] != 0) {
-    TILE_LOOP {
-      const int rows = (int)min<int64_t>(TR, n - t0);
-      const bool fit = stage_tile<double, CAP_A>(A, t0, rows, s_rp, s_ci, s_v);
-      if (o0 || o1) {
-        TILE_ROW_PROD(double, CH, CH2, A, V.ph, const double2 rh = ld2(V.rh, qq);,
-                      st2(V.v, qq, y0, y1, o0, o1);
-                      if (o0) acc[0][0] += rh.x * y0; if (o1) acc[0][1] += rh.y * y1;)
+  if constexpr (STG) {
+    constexpr int CAP_A = cap_a(RPB);
+    STAGE_DECL(double, CAP_A, RPB)
+    if (S.any[3] != 0) {
+      TILE_LOOP {
+        const int rows = (int)min<int64_t>(TR, n - t0);
+        const bool fit = stage_tile<double, CAP_A>(A, t0, rows, s_rp, s_ci, s_v);
+        if (o0 || o1) {
+          TILE_ROW_PROD(double, CH, CH2, A, V.ph, const double2 rh = ld2(V.rh, qq);,
+                        st2(V.v, qq, y0, y1, o0, o1);
+                        if (o0) acc[0][0] += rh.x * y0; if (o1) acc[0][1] += rh.y * y1;)
+        }
+        __syncthreads();
       }
-      __syncthreads();
+    }
+  } else {
+    if (S.any[3] != 0 && (o0 || o1)) {
+      TILE_LOOP {
+        const int rows = (int)min<int64_t>(TR, n - t0);
+        GLOBAL_ROW_PROD(double, CH, CH2, A, V.ph, const double2 rh = ld2(V.rh, qq);,
+                        st2(V.v, qq, y0, y1, o0, o1);
+                        if (o0) acc[0][0] += rh.x * y0; if (o1) acc[0][1] += rh.y * y1;)
+      }
     }
   }
   block_partials<LP, 1>(acc, S, kp);
@@ -428,27 +453,36 @@ __global__ void __launch_bounds__(NT) k_halfcheck(int64_t n, int k, int kp, Csr<
 }
 
 // ---- t = A s_hat; partials t^T s, t^T t, s^T s ------------------------------------
-template <int LP, int CH, int CH2>
+template <int LP, int CH, int CH2, bool STG = true>
 __global__ void __launch_bounds__(NT) k_at(int64_t n, int k, int kp, Csr<double> A, Vec V, State S,
                                            int xmap) {
   LANES(LP)
-  constexpr int CAP_A = cap_a(RPB);
-  STAGE_DECL(double, CAP_A, RPB)
   double acc[3][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
   const bool o0 = lok_ && col_on(S, c0, k), o1 = lok_ && col_on(S, c0 + 1, k);
-  if (S.any[3] != 0) {
-    TILE_LOOP {
-      const int rows = (int)min<int64_t>(TR, n - t0);
-      const bool fit = stage_tile<double, CAP_A>(A, t0, rows, s_rp, s_ci, s_v);
-      if (o0 || o1) {
-        TILE_ROW_PROD(double, CH, CH2, A, V.sh, const double2 sv = ld2(V.s, qq);,
-                      st2(V.t, qq, y0, y1, o0, o1);
-                      if (o0) { acc[0][0] += y0 * sv.x; acc[1][0] += y0 * y0; acc[2][0] += sv.x * sv.x; }
-                      if (o1) { acc[0][1] += y1 * sv.y; acc[1][1] += y1 * y1; acc[2][1] += sv.y * sv.y; })
+#define AT_BODY                                                                                  \
+  st2(V.t, qq, y0, y1, o0, o1);                                                                  \
+  if (o0) { acc[0][0] += y0 * sv.x; acc[1][0] += y0 * y0; acc[2][0] += sv.x * sv.x; }            \
+  if (o1) { acc[0][1] += y1 * sv.y; acc[1][1] += y1 * y1; acc[2][1] += sv.y * sv.y; }
+  if constexpr (STG) {
+    constexpr int CAP_A = cap_a(RPB);
+    STAGE_DECL(double, CAP_A, RPB)
+    if (S.any[3] != 0) {
+      TILE_LOOP {
+        const int rows = (int)min<int64_t>(TR, n - t0);
+        const bool fit = stage_tile<double, CAP_A>(A, t0, rows, s_rp, s_ci, s_v);
+        if (o0 || o1) { TILE_ROW_PROD(double, CH, CH2, A, V.sh, const double2 sv = ld2(V.s, qq);, AT_BODY) }
+        __syncthreads();
       }
-      __syncthreads();
+    }
+  } else {
+    if (S.any[3] != 0 && (o0 || o1)) {
+      TILE_LOOP {
+        const int rows = (int)min<int64_t>(TR, n - t0);
+        GLOBAL_ROW_PROD(double, CH, CH2, A, V.sh, const double2 sv = ld2(V.s, qq);, AT_BODY)
+      }
     }
   }
+#undef AT_BODY
   block_partials<LP, 3>(acc, S, kp);
 }
 

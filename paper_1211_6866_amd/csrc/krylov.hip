@@ -203,20 +203,38 @@ int iterate(Block& B, const Csr<double>& A, const Csr<TM>& M, int64_t n, int& it
   };
   // A~ products (with their dot products): gather batch sizes
   const int avar = tune_get("SPMM_A", 0);
-  const void* kav = avar == 1 ? (const void*)k_av<LP, 8, 4>
-                    : avar == 2 ? (const void*)k_av<LP, 7, 0> : (const void*)k_av<LP, 4, 2>;
-  const void* kat = avar == 1 ? (const void*)k_at<LP, 8, 4>
-                    : avar == 2 ? (const void*)k_at<LP, 7, 0> : (const void*)k_at<LP, 4, 2>;
+  // (3 and 4: the 8/4 and 7/0 batches reading A~ from global memory, no LDS staging)
+  const void* kav = avar == 1   ? (const void*)k_av<LP, 8, 4>
+                    : avar == 2 ? (const void*)k_av<LP, 7, 0>
+                    : avar == 3 ? (const void*)k_av<LP, 8, 4, false>
+                    : avar == 4 ? (const void*)k_av<LP, 7, 0, false>
+                                : (const void*)k_av<LP, 4, 2>;
+  const void* kat = avar == 1   ? (const void*)k_at<LP, 8, 4>
+                    : avar == 2 ? (const void*)k_at<LP, 7, 0>
+                    : avar == 3 ? (const void*)k_at<LP, 8, 4, false>
+                    : avar == 4 ? (const void*)k_at<LP, 7, 0, false>
+                                : (const void*)k_at<LP, 4, 2>;
   const int tgrid = std::min(sp_grid(kav), sp_grid(kat));
+  auto go_a = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3(tgrid), dim3(NT), 0, st, n, k, kp, A, V, S, xmap);
+  };
   auto spmm_av = [&]() {
-    if (avar == 1) hipLaunchKernelGGL((k_av<LP, 8, 4>), dim3(tgrid), dim3(NT), 0, st, n, k, kp, A, V, S, xmap);
-    else if (avar == 2) hipLaunchKernelGGL((k_av<LP, 7, 0>), dim3(tgrid), dim3(NT), 0, st, n, k, kp, A, V, S, xmap);
-    else hipLaunchKernelGGL((k_av<LP, 4, 2>), dim3(tgrid), dim3(NT), 0, st, n, k, kp, A, V, S, xmap);
+    switch (avar) {
+      case 1: go_a(k_av<LP, 8, 4>); break;
+      case 2: go_a(k_av<LP, 7, 0>); break;
+      case 3: go_a(k_av<LP, 8, 4, false>); break;
+      case 4: go_a(k_av<LP, 7, 0, false>); break;
+      default: go_a(k_av<LP, 4, 2>); break;
+    }
   };
   auto spmm_at = [&]() {
-    if (avar == 1) hipLaunchKernelGGL((k_at<LP, 8, 4>), dim3(tgrid), dim3(NT), 0, st, n, k, kp, A, V, S, xmap);
-    else if (avar == 2) hipLaunchKernelGGL((k_at<LP, 7, 0>), dim3(tgrid), dim3(NT), 0, st, n, k, kp, A, V, S, xmap);
-    else hipLaunchKernelGGL((k_at<LP, 4, 2>), dim3(tgrid), dim3(NT), 0, st, n, k, kp, A, V, S, xmap);
+    switch (avar) {
+      case 1: go_a(k_at<LP, 8, 4>); break;
+      case 2: go_a(k_at<LP, 7, 0>); break;
+      case 3: go_a(k_at<LP, 8, 4, false>); break;
+      case 4: go_a(k_at<LP, 7, 0, false>); break;
+      default: go_a(k_at<LP, 4, 2>); break;
+    }
   };
   if (first) {
     {
