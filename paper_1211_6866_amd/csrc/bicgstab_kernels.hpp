@@ -296,8 +296,9 @@ __device__ __forceinline__ bool stage_tile(const Csr<TV>& A, int64_t t0, int row
 
 // The same without LDS staging (STG = false): the lane's row t0 + rib is read
 // from the matrix in global memory (the lanes of a row load the same entries,
-// served by one access), and the tile loop needs no workgroup barrier.  For
-// short rows the staging's barriers and dependent loads cost more than they save.
+// served by one access; non-temporal loads here were slower), and the tile
+// loop needs no workgroup barrier.  For short rows and narrow blocks the
+// staging's barriers and dependent loads cost more than they save.
 #define GLOBAL_ROW_PROD(TV, CH, CH2, A, X, PRE, BODY)                                   \
   if (rib < rows) {                                                                     \
     const int64_t i_ = t0 + rib;                                                        \
