@@ -284,3 +284,24 @@ def check_gmres_cycles_minimise(gmres_fn, A, M, b, m, cycles=2):
         r = b - Ad @ xe
         xe = xe + Md @ _krylov_minres(AM, r, m)
     assert np.linalg.norm(x - xe) <= 1e-8 * np.linalg.norm(xe), np.linalg.norm(x - xe) / np.linalg.norm(xe)
+
+
+def check_forward_correction_exact(correction_fn, A, At, U, D, v):
+    """With exact W = A~^{-1} U, solving A~^T lam = correction_fn(W, D, v) gives
+    A^{-T} v (Theorem 3.1's A^{-1} transposed)."""
+    Ad = sp.csr_matrix(A).toarray()
+    Atd = sp.csr_matrix(At).toarray()
+    W = np.linalg.solve(Atd, sp.csc_matrix(U).toarray())
+    rhs, _ = correction_fn(W, np.asarray(D, dtype=np.int64), v)
+    lam = np.linalg.solve(Atd.T, rhs)
+    lam_d = np.linalg.solve(Ad.T, v)
+    assert np.linalg.norm(lam - lam_d) <= 1e-10 * np.linalg.norm(lam_d)
+
+
+def check_adjoint_reported_residual(adjoint_fn, A, S, M, W, g, eps):
+    """The adjoint's reported rr is the true ||g - A^T lam|| / ||g|| (to 1e-3 of
+    itself: the two ways of forming A^T lam round differently), below eps."""
+    out = adjoint_fn(S, M, W, g, eps=eps)
+    rr = np.linalg.norm(g - sp.csr_matrix(A).T @ out["lam"]) / np.linalg.norm(g)
+    assert abs(rr - out["rr"]) <= 1e-3 * rr + 1e-15
+    assert rr < eps

@@ -268,3 +268,46 @@ def test_gmres_mistakes_caught(mistake):
     b = np.random.default_rng(4).standard_normal(80)
     with pytest.raises(AssertionError):
         pins.check_gmres_cycles_minimise(f, A, sp.csr_matrix(Minv), b, 5, 2)
+
+
+_CORRECTION_MISTAKES = {
+    "K_not_transposed": ("z = np.linalg.solve(K.T, W.T @ v)", "z = np.linalg.solve(K, W.T @ v)"),
+    "plus_sign": ("rhs[D] -= z", "rhs[D] += z"),
+    "no_K": ("z = np.linalg.solve(K.T, W.T @ v)", "z = W.T @ v"),
+}
+
+
+def _adjoint_mutant(fn, old, new):
+    """A copy of an oracle.adjoint function with one textual change."""
+    import inspect
+    import textwrap
+
+    from oracle import adjoint
+    src = textwrap.dedent(inspect.getsource(getattr(adjoint, fn)))
+    assert src.count(old) == 1, old
+    ns = dict(vars(adjoint))
+    exec(compile(src.replace(old, new), "<adjoint mutant>", "exec"), ns)
+    return ns[fn]
+
+
+@pytest.mark.parametrize("mistake", sorted(_CORRECTION_MISTAKES))
+def test_forward_correction_mistakes_caught(mistake):
+    f = _adjoint_mutant("forward_correction", *_CORRECTION_MISTAKES[mistake])
+    w = W.make(1, dims=(14, 16), s=4, density=0.3)
+    S = osplit.split(w.A)
+    g = np.random.default_rng(7).standard_normal(w.A.shape[0])
+    with pytest.raises(AssertionError):
+        pins.check_forward_correction_exact(f, w.A, S.At, S.U, S.D, g)
+
+
+@pytest.mark.parametrize("mistake", ["residual_without_U", "no_accumulation"])
+def test_adjoint_from_forward_mistakes_caught(mistake):
+    from oracle import pipeline
+    old, new = {"residual_without_U": ("rho[D] -= U.T @ lam", "pass"),
+                "no_accumulation": ("lam = lam + X[:, 0]", "lam = X[:, 0]")}[mistake]
+    f = _adjoint_mutant("adjoint_from_forward", old, new)
+    w = W.make(1)
+    out = pipeline.run(w.A, w.b, kind="A2", drop="none", eps=1e-8)
+    g = out["x"] - W.x_star(w.A.shape[0], w.seed)
+    with pytest.raises(AssertionError):
+        pins.check_adjoint_reported_residual(f, w.A, out["split"], out["M"], out["Y"][:, 1:], g, 1e-8)
