@@ -5,8 +5,9 @@ Default workload (--workload 5, the largest single-GPU configuration): 3D
 7-point convection-diffusion on a 160^3 grid (n = 4,096,000) with s = 50 seeded
 dense columns at 1% density; static pattern P(|A~|^2) with absolute dropping
 1e-3; M built in FP32 ("mixed"), Krylov/SMW/check in FP64; 51 right-hand sides
-in one batched BiCGStab, eps = 1e-8; then the adjoint (51 transposed systems)
-and the gradients of the loss 0.5 ||x - x*||^2.  Workloads 1-4 are the other
+in one batched BiCGStab, eps = 1e-8; then the adjoint of the loss
+0.5 ||x - x*||^2 from the forward solve's W = A~^{-1} U (one transposed system
+per correction pass, its true residual below 1e-8) and the gradients.  Workloads 1-4 are the other
 configurations (GMRES(30) on a 45x45 grid; the 100^3 grid with s = 10; SPAI on
 a random n = 200,000 matrix; the 500x500 grid with the adjoint).
 
@@ -355,10 +356,14 @@ def main():
     def step(prec):
         sp_ = P.Split(rp, ci, va, **split_kw)
         pc = P.Precond(sp_, precision=prec, **bkw)
-        x, st = P.solve(sp_, pc, b, **skw)
         bst = None
         if adjoint:
-            gb, ga, bst = P.backward(sp_, pc, x, x - xstar, **skw)
+            # the forward keeps [y, W]; the adjoint reuses W (sai_backward_y)
+            x, Y, st = P.solve_y(sp_, pc, b, **skw)
+            gb, ga, bst = P.backward_y(sp_, pc, x, Y, x - xstar, **skw)
+            del Y
+        else:
+            x, st = P.solve(sp_, pc, b, **skw)
         return sp_, pc, x, st, bst
 
     try:
@@ -403,7 +408,7 @@ def main():
             builds.append(last[1].stats.t_total_ms)
             solves.append(last[3]["t_solve_ms"])
             if last[4] is not None:
-                backs.append(last[4]["t_solve_ms"] + last[4]["t_smw_ms"])
+                backs.append(last[4]["t_solve_ms"] + last[4]["t_smw_ms"] + last[4]["t_check_ms"])
             log(f"bench: step {i + 1}/{K} done")
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -429,6 +434,27 @@ def main():
 
     xh = x_m.cpu().numpy()
     rr_host = float(np.linalg.norm(w.b - w.A @ xh) / np.linalg.norm(w.b))
+    adj_cmp = None
+    if adjoint:
+        # the other adjoint form once, for comparison (not in the step): s+1 systems
+        # with A~^T (sai_backward), each residual recomputed on the host
+        log("bench: the adjoint through s+1 transposed systems, once, for comparison")
+        gv = (x_m - xstar).cpu().numpy()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gb_t, _, bst_t = P.backward(sp_m, pc_m, x_m, x_m - xstar, want_a=False, **skw)
+        torch.cuda.synchronize()
+        ms_t = (time.perf_counter() - t0) * 1e3
+        gb_y, _, bst_y = P.backward_y(sp_m, pc_m, x_m, P.solve_y(sp_m, pc_m, b, **skw)[1], x_m - xstar,
+                                      want_a=False, **skw)
+        gn = float(np.linalg.norm(gv))
+        adj_cmp = dict(
+            form="from the forward's W: one system with A~^T per correction pass (sai_backward_y)",
+            rr_host=float(np.linalg.norm(gv - w.A.T @ gb_y.cpu().numpy()) / gn),
+            column_iters=int(np.sum(bst_y["iters"])),
+            transposed_split=dict(ms=round(ms_t, 3), column_iters=int(np.sum(bst_t["iters"])),
+                                  rr_host=float(np.linalg.norm(gv - w.A.T @ gb_t.cpu().numpy()) / gn)))
+        del gb_t, gb_y
     copy_gbs = device_copy_gbs(torch)
 
     # algorithmic work per kernel, for the roofline of the dominant one
@@ -582,6 +608,7 @@ def main():
         "solve_ms": round(float(np.mean(solves_m)), 3),
         "adjoint_ms": {"mixed": round(float(np.mean(backs_m)), 3) if backs_m else None,
                        "plain_fp64": round(plain["adjoint"], 3) if plain and plain["adjoint"] else None},
+        "adjoint": adj_cmp,
         "solve": {"mixed": {"iters": st_m["iters"], "rr": st_m["rr"], "rr_host": rr_host,
                             "c": st_m["c"],
                             "adjoint_iters": bst_m["iters"] if bst_m is not None else None},

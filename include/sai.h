@@ -318,6 +318,14 @@ typedef struct {
 int sai_solve(const sai_split_t* sp, const sai_precond_t* pc, const double* b, double* x,
               const sai_solve_opts* opts, void* stream, sai_solve_stats* stats /* host */);
 
+/* sai_solve, with the s+1 Krylov solutions Y = [y, W] (device, n x (s+1),
+ * row-major, caller-owned; W approximates A~^{-1} U, y the solution of
+ * A~ y = b, of the scaled b under `equilibrate`) written to Y instead of a
+ * workspace, for sai_backward_y.  Errors as sai_solve; SAI_EINVAL for a NULL Y. */
+int sai_solve_y(const sai_split_t* sp, const sai_precond_t* pc, const double* b, double* x,
+                double* Y, const sai_solve_opts* opts, void* stream,
+                sai_solve_stats* stats /* host */);
+
 /* --------------------------------------------------------------- backward --
  * Gradient of a scalar loss L(x), x = A^{-1} b, given grad_x = dL/dx (device,
  * n).  Derived from Theorem 3.1 applied to A^T = A~^T + V U^T: solves
@@ -334,6 +342,29 @@ int sai_solve(const sai_split_t* sp, const sai_precond_t* pc, const double* b, d
 int sai_backward(const sai_split_t* sp, const sai_precond_t* pc, const double* x,
                  const double* grad_x, double* grad_b, double* grad_a_val,
                  const sai_solve_opts* opts, void* stream, sai_solve_stats* stats /* host */);
+
+/* The same gradients from the forward solve's W (Y of sai_solve_y on this split
+ * and preconditioner; only Y[:, 1..s] is read; Y may be NULL when s = 0), with
+ * one system with A~^T per pass instead of s+1.  Theorem 3.1's
+ * A^{-1} = A~^{-1} - W K^{-1} V^T A~^{-1}, K = I + V^T W, transposes to
+ * A^{-T} = A~^{-T} (I - V K^{-T} W^T).  Pass p solves A~^T d = r - V z,
+ * K^T z = W^T r, with M^T as right preconditioner and adds d to lambda; r is
+ * grad_x in the first pass, then the true residual grad_x - A~^T lambda -
+ * V (U^T lambda) (float64).  The passes stop once that residual is below
+ * eps ||grad_x||, at most 4.  The first solve stops at (eps/2)||grad_x||, each
+ * later one at (eps/2)||grad_x|| divided by the amplification seen (true
+ * residual over the last threshold), since the true residual is (I + V W^T)
+ * times the solve's residual plus the effect of W's own error.  stats: iters[0]
+ * = the iterations of all passes (iters[1..s] = 0), rr = the final adjoint
+ * residual ||grad_x - A^T lambda|| / ||grad_x||, c = ||z|| of the first pass,
+ * t_check_ms = the residual checks, t_smw_ms = the corrections; c_mode and
+ * equilibrate are not used.  Outputs as sai_backward (written also when the
+ * status is not SAI_OK).  Errors: SAI_ENOCONV when 4 passes leave the residual
+ * at or above eps, SAI_EBREAKDOWN, SAI_ESINGULAR for a zero pivot of K^T,
+ * SAI_EINVAL for a NULL argument (Y with s > 0). */
+int sai_backward_y(const sai_split_t* sp, const sai_precond_t* pc, const double* x,
+                   const double* Y, const double* grad_x, double* grad_b, double* grad_a_val,
+                   const sai_solve_opts* opts, void* stream, sai_solve_stats* stats /* host */);
 
 /* -------------------------------------------------------------- profiling --
  * While enabled, the library records a pair of HIP events on the launch stream

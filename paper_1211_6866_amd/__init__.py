@@ -134,6 +134,9 @@ def lib():
     L.sai_solve.argtypes = [vp, vp, vp, vp, C.POINTER(SolveOpts), vp, C.POINTER(SolveStats)]
     L.sai_backward.argtypes = [vp, vp, vp, vp, vp, vp, C.POINTER(SolveOpts), vp,
                                C.POINTER(SolveStats)]
+    L.sai_solve_y.argtypes = [vp, vp, vp, vp, vp, C.POINTER(SolveOpts), vp, C.POINTER(SolveStats)]
+    L.sai_backward_y.argtypes = [vp, vp, vp, vp, vp, vp, vp, C.POINTER(SolveOpts), vp,
+                                 C.POINTER(SolveStats)]
     L.sai_strerror.restype = C.c_char_p
     L.sai_strerror.argtypes = [C.c_int]
     L.sai_last_error.restype = C.c_char_p
@@ -429,6 +432,46 @@ def solve(split: Split, pc: Precond, b, raise_on_error=True, **kw):
     d = _stats_dict(st, iters)
     d["code"] = code
     return x, d
+
+
+def solve_y(split: Split, pc: Precond, b, raise_on_error=True, **kw):
+    """sai_solve_y: Procedure * keeping the Krylov solutions; returns (x, Y, stats dict)
+    with Y = [y, W] (n x (s+1) float64) for backward_y."""
+    torch = _torch()
+    x = torch.empty(split.n, dtype=torch.float64, device="cuda")
+    Y = torch.empty((split.n, split.s + 1), dtype=torch.float64, device="cuda")
+    iters = (C.c_int32 * (split.s + 1))()
+    st = SolveStats()
+    st.iters = C.cast(iters, C.POINTER(C.c_int32))
+    o = _sopts(**kw)
+    code = lib().sai_solve_y(split.h, pc.h, _ptr(b), _ptr(x), _ptr(Y), C.byref(o), _stream(), C.byref(st))
+    if raise_on_error:
+        _check(code, "sai_solve_y")
+    d = _stats_dict(st, iters)
+    d["code"] = code
+    return x, Y, d
+
+
+def backward_y(split: Split, pc: Precond, x, Y, grad_x, want_b=True, want_a=True, raise_on_error=True,
+               **kw):
+    """sai_backward_y: the gradients of backward from the forward's Y (solve_y), one
+    system with A~^T per correction pass; returns (grad_b, grad_a, stats dict)."""
+    torch = _torch()
+    gb = torch.empty(split.n, dtype=torch.float64, device="cuda") if want_b else None
+    ga = torch.empty(split.nnz, dtype=torch.float64, device="cuda") if want_a else None
+    iters = (C.c_int32 * (split.s + 1))()
+    st = SolveStats()
+    st.iters = C.cast(iters, C.POINTER(C.c_int32))
+    o = _sopts(**kw)
+    code = lib().sai_backward_y(split.h, pc.h, _ptr(x), _ptr(Y) if Y is not None else None, _ptr(grad_x),
+                                _ptr(gb) if gb is not None else None,
+                                _ptr(ga) if ga is not None else None, C.byref(o), _stream(),
+                                C.byref(st))
+    if raise_on_error:
+        _check(code, "sai_backward_y")
+    d = _stats_dict(st, iters)
+    d["code"] = code
+    return gb, ga, d
 
 
 def backward(split: Split, pc: Precond, x, grad_x, want_b=True, want_a=True, raise_on_error=True,

@@ -158,6 +158,21 @@ int sai_solve(const sai_split_t* sp, const sai_precond_t* pc, const double* b, d
   return guarded([&] { sai::solve_impl(sp, pc, b, x, *opts, (hipStream_t)stream, stats); });
 }
 
+int sai_solve_y(const sai_split_t* sp, const sai_precond_t* pc, const double* b, double* x, double* Y,
+                const sai_solve_opts* opts, void* stream, sai_solve_stats* stats) {
+  if (!sp || !pc || !b || !x || !Y || !opts) return SAI_EINVAL;
+  return guarded([&] { sai::solve_impl(sp, pc, b, x, *opts, (hipStream_t)stream, stats, Y); });
+}
+
+int sai_backward_y(const sai_split_t* sp, const sai_precond_t* pc, const double* x, const double* Y,
+                   const double* grad_x, double* grad_b, double* grad_a_val, const sai_solve_opts* opts,
+                   void* stream, sai_solve_stats* stats) {
+  if (!sp || !pc || !x || !grad_x || !opts) return SAI_EINVAL;
+  return guarded([&] {
+    sai::backward_y_impl(sp, pc, x, Y, grad_x, grad_b, grad_a_val, *opts, (hipStream_t)stream, stats);
+  });
+}
+
 int sai_backward(const sai_split_t* sp, const sai_precond_t* pc, const double* x, const double* grad_x,
                  double* grad_b, double* grad_a_val, const sai_solve_opts* opts, void* stream,
                  sai_solve_stats* stats) {

@@ -302,8 +302,13 @@ double residual_impl(const sai_split_s* sp, const double* b, const double* x, hi
 void backward_impl(const sai_split_s* sp, const sai_precond_s* pc, const double* x,
                    const double* gx, double* gb, double* ga, const sai_solve_opts& o,
                    hipStream_t st, sai_solve_stats* stats);
+// y_out (device, n x (s+1), may be null): receives the Krylov solutions [y, W]
 void solve_impl(const sai_split_s* sp, const sai_precond_s* pc, const double* b, double* x,
-                const sai_solve_opts& o, hipStream_t st, sai_solve_stats* stats);
+                const sai_solve_opts& o, hipStream_t st, sai_solve_stats* stats, double* y_out = nullptr);
+// the adjoint from the forward solve's W = Y[:, 1..s]: one system with A~^T per pass
+void backward_y_impl(const sai_split_s* sp, const sai_precond_s* pc, const double* x, const double* Y,
+                     const double* gx, double* gb, double* ga, const sai_solve_opts& o, hipStream_t st,
+                     sai_solve_stats* stats);
 
 // Device-wide deterministic float64 norms / dots (two-level, fixed order).
 double dev_norm2(const double* v, int64_t n, int64_t stride, const Allocator& al, hipStream_t st);

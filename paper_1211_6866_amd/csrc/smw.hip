@@ -7,7 +7,9 @@
 // Residual (rrnorm): rr = ||b - A~ x - U x(j)|| / ||b||, A = A~ + U V^T.
 // Adjoint (Theorem 3.1 applied to A^T = A~^T + V U^T): A~^T [eta, Z] =
 // [g, V], K' = I + U^T Z, lambda = eta - Z K'^{-1} U^T eta; dL/db = lambda and
-// dL/dA_ij = -lambda_i x_j.
+// dL/dA_ij = -lambda_i x_j.  With the forward solve's W (backward_y_impl):
+// Theorem 3.1's A^{-1} = A~^{-1} - W K^{-1} V^T A~^{-1} transposes to
+// A^{-T} = A~^{-T} (I - V K^{-T} W^T), one system with A~^T per pass.
 #include "sai_internal.hpp"
 
 #include <map>
@@ -215,6 +217,78 @@ __global__ void k_grad_a(int64_t n, const int32_t* __restrict__ rp, const int32_
   }
 }
 
+// ---- the adjoint from the forward solve's W ----------------------------------------
+
+// part[b][c0 + c] = sum over the rows of block b of W[i, c0 + c] v[i], W = Y[:, 1..s]
+// (row stride s + 1): thread t takes column c0 + t % cw and the rows i0 + t / cw,
+// i0 + t / cw + G, ... (G = NT / cw row groups, added in order afterwards)
+constexpr int WTV_ROWS = 2048;
+__global__ void __launch_bounds__(NT) k_wtv_partial(int64_t n, int s, int c0, int cw,
+                                                    const double* __restrict__ Y,
+                                                    const double* __restrict__ v,
+                                                    double* __restrict__ part) {
+  __shared__ double red[NT];
+  const int G = NT / cw;
+  const int t = threadIdx.x, c = t % cw, g = t / cw;
+  const int kk = s + 1;
+  const int64_t i0 = (int64_t)blockIdx.x * WTV_ROWS;
+  const int64_t i1 = std::min<int64_t>(n, i0 + WTV_ROWS);
+  double a = 0.0;
+  if (g < G)
+    for (int64_t i = i0 + g; i < i1; i += G) a += Y[i * kk + 1 + c0 + c] * v[i];
+  red[t] = a;
+  __syncthreads();
+  if (t < cw) {
+    double r = 0.0;
+    for (int u = 0; u < G; ++u) r += red[u * cw + t];
+    part[(int64_t)blockIdx.x * s + c0 + t] = r;
+  }
+}
+
+// P[e] = sum over blocks b < nb of part[b s + e]: block e; thread t adds the blocks
+// t, t + NT, ... in order, then a fixed-order block sum
+__global__ void __launch_bounds__(NT) k_cols_final(int nb, int s, const double* __restrict__ part,
+                                                   double* __restrict__ P) {
+  __shared__ double red[NT / WAVE];
+  const int e = blockIdx.x;
+  double a = 0.0;
+  for (int b = threadIdx.x; b < nb; b += NT) a += part[(int64_t)b * s + e];
+  a = block_sum<NT>(a, red);
+  if (threadIdx.x == 0) P[e] = a;
+}
+
+// K^T (row-major s x s) with K = I + V^T W: K^T[e][d] = delta_de + W[j_d, e]
+__global__ void k_kt(int s, int kk, const int32_t* __restrict__ D, const double* __restrict__ Y,
+                     double* __restrict__ Kt) {
+  const int t = blockIdx.x * NT + threadIdx.x;
+  if (t >= s * s) return;
+  const int e = t / s, d = t % s;
+  Kt[t] = (d == e ? 1.0 : 0.0) + Y[(int64_t)D[d] * kk + 1 + e];
+}
+
+// v(j_d) -= z_d, i.e. v -= V z (the j_d are distinct)
+__global__ void k_sub_units(int s, const int32_t* __restrict__ D, const double* __restrict__ z,
+                            double* __restrict__ v) {
+  const int d = blockIdx.x * NT + threadIdx.x;
+  if (d < s) v[D[d]] -= z[d];
+}
+
+// rho = g - A~^T lam, with A~^T given as the CSC of A~ (row j of A~^T = column j)
+__global__ void k_resid_t(int64_t n, const int32_t* __restrict__ cp, const int32_t* __restrict__ ri,
+                          const double* __restrict__ cv, const double* __restrict__ g,
+                          const double* __restrict__ lam, double* __restrict__ rho) {
+  for (int64_t j = (int64_t)blockIdx.x * NT + threadIdx.x; j < n; j += (int64_t)gridDim.x * NT) {
+    double y = 0.0;
+    for (int32_t e = cp[j]; e < cp[j + 1]; ++e) y += cv[e] * lam[ri[e]];
+    rho[j] = g[j] - y;
+  }
+}
+
+// y += d
+__global__ void k_add_vec(int64_t n, const double* __restrict__ d, double* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) y[i] += d[i];
+}
+
 unsigned rows_grid(int64_t n) { return grid_for(n, NT, 8192); }
 
 std::vector<double> thresholds(double bnorm, int s, double eps, double c) {
@@ -351,12 +425,15 @@ double residual_impl(const sai_split_s* sp, const double* b, const double* x, hi
 }
 
 void solve_impl(const sai_split_s* sp, const sai_precond_s* pc, const double* b, double* x,
-                const sai_solve_opts& o, hipStream_t st, sai_solve_stats* stats) {
+                const sai_solve_opts& o, hipStream_t st, sai_solve_stats* stats, double* y_out) {
   const Allocator al{sp->al.a, st};
   const int s = sp->s, kk = s + 1;
   const int64_t n = sp->n;
   EventTimer t_solve, t_smw, t_chk;
-  DBuf<double> R(&al, (size_t)n * kk), Y(&al, (size_t)n * kk);
+  // the Krylov solutions [y, W] go to the caller's y_out when given
+  DBuf<double> R(&al, (size_t)n * kk), Ybuf;
+  if (!y_out) Ybuf.alloc(&al, (size_t)n * kk);
+  double* const Y = y_out ? y_out : Ybuf.p;
   // Section 4's scaling (equilibrate): solve with alpha b, alpha = rho / ||b||,
   // rho = ||A||_F / sqrt(n) (||A||_F^2 = ||A~||_F^2 + ||U||_F^2), x scaled back
   double alpha = 1.0;
@@ -381,11 +458,11 @@ void solve_impl(const sai_split_s* sp, const sai_precond_s* pc, const double* b,
   std::vector<double> thr = thresholds(bnorm, s, o.eps, 1.0);
   std::vector<int32_t> its(kk, 0), sts(kk, 0);
   t_solve.start(st);
-  int code = krylov_impl(sp, pc, 0, kk, R.p, Y.p, thr.data(), o, st, its.data(), sts.data());
+  int code = krylov_impl(sp, pc, 0, kk, R.p, Y, thr.data(), o, st, its.data(), sts.data());
   t_solve.stop(st);
   double c = 0.0;
   t_smw.start(st);
-  smw_recover(sp, Y.p, x, &c, st);
+  smw_recover(sp, Y, x, &c, st);
   t_smw.stop(st);
   t_chk.start(st);
   double rr = residual_impl(sp, b, x, st);
@@ -399,14 +476,14 @@ void solve_impl(const sai_split_s* sp, const sai_precond_s* pc, const double* b,
     DBuf<double> Raux(&al, (size_t)n * s), dW(&al, (size_t)n * s);
     hipLaunchKernelGGL(k_aux_residual, dim3(grid_for(n * s, NT, 8192)), dim3(NT), 0, st, n, s, sp->t_row_ptr.p,
                        sp->t_col_idx.p, sp->t_val.p, sp->u_row_ptr.p, sp->u_col.p, sp->u_val.p,
-                       Y.p, Raux.p);
+                       Y, Raux.p);
     LAUNCH_CHECK();
     std::vector<int32_t> its2(s, 0), sts2(s, 0);
     code = krylov_impl(sp, pc, 0, s, Raux.p, dW.p, thr2.data() + 1, o, st, its2.data(), sts2.data());
-    hipLaunchKernelGGL(k_aux_add, dim3(grid_for(n * s, NT, 8192)), dim3(NT), 0, st, n, s, dW.p, Y.p);
+    hipLaunchKernelGGL(k_aux_add, dim3(grid_for(n * s, NT, 8192)), dim3(NT), 0, st, n, s, dW.p, Y);
     LAUNCH_CHECK();
     for (int d = 0; d < s; ++d) its[d + 1] += its2[d];
-    smw_recover(sp, Y.p, x, &c, st);
+    smw_recover(sp, Y, x, &c, st);
     rr = residual_impl(sp, b, x, st);
     t_ref.stop(st);
     extra_ms = t_ref.ms();
@@ -533,6 +610,135 @@ void backward_impl(const sai_split_s* sp, const sai_precond_s* pc, const double*
     stats->t_check_ms = 0.0f;
   }
   if (code != SAI_OK) throw Error{code, "adjoint Krylov solve did not converge on every column"};
+}
+
+}  // namespace sai
+
+namespace sai {
+
+// Adjoint from the forward solve's W = Y[:, 1..s] (approximately A~^{-1} U).
+// A^{-T} = A~^{-T} (I - V K^{-T} W^T), K = I + V^T W, so each pass solves one
+// system A~^T d = r - V K^{-T} W^T r (M^T as right preconditioner) and adds d
+// to lambda; r is grad_x, then the true residual grad_x - A~^T lambda -
+// V (U^T lambda).  The true residual is (I + V W^T) times the solve's residual
+// (plus the effect of W's own error), so the first solve stops at
+// (eps/2)||g|| and each later one at (eps/2)||g|| over the amplification seen
+// (true residual / last threshold); passes stop once the true residual is
+// below eps ||g||.
+void backward_y_impl(const sai_split_s* sp, const sai_precond_s* pc, const double* x, const double* Y,
+                     const double* gx, double* gb, double* ga, const sai_solve_opts& o, hipStream_t st,
+                     sai_solve_stats* stats) {
+  constexpr int PASSES = 4;
+  const Allocator al{sp->al.a, st};
+  const int s = sp->s, kk = s + 1;
+  const int64_t n = sp->n;
+  if (s > 0 && !Y) SAI_THROW(SAI_EINVAL, "Y (the forward solutions [y, W]) is required when s > 0");
+  EventTimer t_all, t_solve, t_chk;
+  float solve_ms = 0.0f, chk_ms = 0.0f;
+  t_all.start(st);
+  DBuf<double> lam(&al, (size_t)n), res(&al, (size_t)n), rhs(&al, (size_t)n), del(&al, (size_t)n);
+  const int64_t nbw = (n + WTV_ROWS - 1) / WTV_ROWS, nbu = (n + UTY_ROWS - 1) / UTY_ROWS;
+  const int sm = std::max(s, 1);
+  DBuf<double> part(&al, (size_t)std::max(nbw, nbu) * sm), P(&al, (size_t)sm), Kt(&al, (size_t)sm * sm);
+  const double gnorm = dev_norm2(gx, n, 1, al, st);
+  // out = v - V K^{-T} W^T v; returns ||K^{-T} W^T v|| when `norm`
+  auto correct = [&](const double* v, double* out, bool norm) -> double {
+    SAI_PROF("adjoint_correction", st);
+    hipLaunchKernelGGL(k_scale_copy, dim3(rows_grid(n)), dim3(NT), 0, st, n, 1.0, v, out);
+    LAUNCH_CHECK();
+    if (s == 0) return 0.0;
+    for (int c0 = 0; c0 < s; c0 += NT) {
+      const int cw = std::min(NT, s - c0);
+      hipLaunchKernelGGL(k_wtv_partial, dim3((unsigned)nbw), dim3(NT), 0, st, n, s, c0, cw, Y, v, part.p);
+      LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(k_cols_final, dim3(s), dim3(NT), 0, st, (int)nbw, s, (const double*)part.p, P.p);
+    hipLaunchKernelGGL(k_kt, dim3(grid_for(s * s, NT)), dim3(NT), 0, st, s, kk, sp->dense_cols.p, Y, Kt.p);
+    LAUNCH_CHECK();
+    if (!dense_lu_solve(Kt.p, P.p, s, 1, al, st))
+      SAI_THROW(SAI_ESINGULAR, "I + V^T W is singular (zero pivot)");
+    hipLaunchKernelGGL(k_sub_units, dim3(grid_for(s, NT)), dim3(NT), 0, st, s, sp->dense_cols.p,
+                       (const double*)P.p, out);
+    LAUNCH_CHECK();
+    if (!norm) return 0.0;
+    std::vector<double> hz(s);
+    HIPC(hipMemcpyAsync(hz.data(), P.p, sizeof(double) * s, hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    double a = 0.0;
+    for (double v : hz) a += v * v;
+    return std::sqrt(a);
+  };
+  // res = g - A~^T lam - V (U^T lam); returns ||res||
+  auto true_residual = [&]() -> double {
+    SAI_PROF("adjoint_residual", st);
+    hipLaunchKernelGGL(k_resid_t, dim3(rows_grid(n)), dim3(NT), 0, st, n, sp->t_col_ptr.p, sp->t_row_idx.p,
+                       sp->t_cval.p, gx, (const double*)lam.p, res.p);
+    LAUNCH_CHECK();
+    if (s > 0) {
+      hipLaunchKernelGGL(k_uty_partial, dim3((unsigned)nbu), dim3(64), sizeof(double) * s, st, n, s, 1, 0, 1,
+                         sp->u_row_ptr.p, sp->u_col.p, sp->u_val.p, (const double*)lam.p, part.p);
+      LAUNCH_CHECK();
+      hipLaunchKernelGGL(k_cols_final, dim3(s), dim3(NT), 0, st, (int)nbu, s, (const double*)part.p, P.p);
+      hipLaunchKernelGGL(k_sub_units, dim3(grid_for(s, NT)), dim3(NT), 0, st, s, sp->dense_cols.p,
+                         (const double*)P.p, res.p);
+      LAUNCH_CHECK();
+    }
+    return dev_norm2(res.p, n, 1, al, st);
+  };
+  HIPC(hipMemsetAsync(lam.p, 0, sizeof(double) * n, st));
+  int code = SAI_OK, its = 0;
+  double rr = 0.0, c = 0.0;
+  if (gnorm > 0.0) {
+    double thr = 0.5 * o.eps * gnorm;
+    const double* src = gx;
+    for (int pass = 1; pass <= PASSES; ++pass) {
+      const double zn = correct(src, rhs.p, pass == 1);
+      if (pass == 1) c = zn;
+      int32_t it = 0, stc = 0;
+      t_solve.start(st);
+      const int kc = krylov_impl(sp, pc, 1, 1, rhs.p, del.p, &thr, o, st, &it, &stc);
+      t_solve.stop(st);
+      solve_ms += t_solve.ms();
+      its += it;
+      hipLaunchKernelGGL(k_add_vec, dim3(rows_grid(n)), dim3(NT), 0, st, n, (const double*)del.p, lam.p);
+      LAUNCH_CHECK();
+      t_chk.start(st);
+      const double rn = true_residual();
+      t_chk.stop(st);
+      chk_ms += t_chk.ms();
+      rr = rn / gnorm;
+      if (rr < o.eps) {
+        code = SAI_OK;
+        break;
+      }
+      code = kc == SAI_EBREAKDOWN ? SAI_EBREAKDOWN : SAI_ENOCONV;
+      if (kc == SAI_EBREAKDOWN) break;
+      thr = 0.5 * o.eps * gnorm / (rn / thr);
+      src = res.p;
+    }
+  }
+  if (gb) HIPC(hipMemcpyAsync(gb, lam.p, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+  if (ga) {
+    hipLaunchKernelGGL(k_grad_a, dim3(rows_grid(n)), dim3(NT), 0, st, n, sp->a_row_ptr.p, sp->a_col_idx.p,
+                       (const double*)lam.p, x, ga);
+    LAUNCH_CHECK();
+  }
+  t_all.stop(st);
+  HIPC(hipStreamSynchronize(st));
+  if (stats) {
+    stats->s = s;
+    stats->status = code;
+    stats->iters_max = its;
+    if (stats->iters)
+      for (int q = 0; q < kk; ++q) stats->iters[q] = q == 0 ? its : 0;
+    stats->rr = rr;
+    stats->a = rr / o.eps;
+    stats->c = c;
+    stats->t_solve_ms = solve_ms;
+    stats->t_smw_ms = std::max(0.0f, t_all.ms() - solve_ms - chk_ms);
+    stats->t_check_ms = chk_ms;
+  }
+  if (code != SAI_OK) throw Error{code, "adjoint residual not below eps after the correction passes"};
 }
 
 }  // namespace sai

@@ -149,6 +149,23 @@ def test_fullsize_workload(idx, prec):
     assert abs(trace + lam @ w.b) <= 1e-8 * abs(lam @ w.b)
     rows = np.repeat(np.arange(n), np.diff(w.A.indptr))
     assert np.array_equal(G, -lam[rows] * xs[w.A.indices])
+    # the same from the forward solve's W (sai_solve_y, sai_backward_y): one system
+    # with A~^T per correction pass, its true residual checked below eps
+    x2, Y2, st2 = P.solve_y(g, pc, b, eps=1e-10)
+    xs2 = _np(x2)
+    gv2 = xs2 - xstar
+    gb2, ga2, bst2 = P.backward_y(g, pc, x2, Y2, torch.from_numpy(gv2).cuda(), eps=1e-10)
+    lam2, G2 = _np(gb2), _np(ga2)
+    res2 = np.linalg.norm(w.A.T @ lam2 - gv2) / np.linalg.norm(gv2)
+    print(f"workload {idx}: from the forward's W ||A^T lam - g||/||g|| = {res2:.2e} "
+          f"({bst2['iters'][0]} iterations against {sum(bst['iters'])})", flush=True)
+    assert bst2["status"] == P.OK and res2 < 1e-10 * (1 + 1e-3)
+    # the GPU's residual (A~^T lam + V U^T lam) and the host's round differently:
+    # 1e-3 of themselves plus 64 unit roundoffs of || |A|^T |lam| || + ||g|| over ||g||
+    gn2 = np.linalg.norm(gv2)
+    rnd = 64 * np.finfo(np.float64).eps * (np.linalg.norm(abs(w.A).T @ np.abs(lam2)) + gn2) / gn2
+    assert abs(res2 - bst2["rr"]) <= 1e-3 * res2 + rnd
+    assert np.array_equal(G2, -lam2[rows] * xs2[w.A.indices])
     if idx != 4:
         return
     # ---- central differences of the exact loss (workload 4)
@@ -168,7 +185,8 @@ def test_fullsize_workload(idx, prec):
         dl = 0.5 * np.dot(dp - dm, 2.0 * (x0 - xstar) + dp + dm)
         fd = dl / (2.0 * h)
         assert abs(fd - G[q]) <= 1e-5 * max(abs(G[q]), 1e-6 * np.abs(G).max()), (q, fd, G[q])
-    print("workload 4: 16 finite differences ok", flush=True)
+        assert abs(fd - G2[q]) <= 1e-5 * max(abs(G2[q]), 1e-6 * np.abs(G2).max()), (q, fd, G2[q])
+    print("workload 4: 16 finite differences ok (both adjoint forms)", flush=True)
 
 
 @pytest.mark.parametrize("idx,delta,lmax", [(2, 0.2, 10), (4, 0.2, 10)])
