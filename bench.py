@@ -391,10 +391,12 @@ def main():
     P.profile_enable(0)
     scopes = {"split", "smw_recover", "spai_search", "psai_search", "gmres_fused", "pattern_bounds",
               "pattern_fill", "pattern_pack", "bicg_init", "gmres_init", "gmres_orth", "gmres_step",
+              "adjoint_correction", "adjoint_residual",
               "gmres_cycle_start", "gmres_cycle_end"}
-    # launches on a narrowed BiCGStab block (names with "narrow") are left out: their widths vary, so
-    # their bytes per launch do not follow from k
-    dom = max((tot, nm) for nm, (l, tot) in prof_all.items() if nm not in scopes and "narrow" not in nm)[1]
+    # launches on a narrowed BiCGStab block (names with "narrow") and those of the adjoint's transposed
+    # solves (names with "_t_", one column) are left out: their bytes per launch do not follow from k
+    dom = max((tot, nm) for nm, (l, tot) in prof_all.items()
+              if nm not in scopes and "narrow" not in nm and "_t_" not in nm)[1]
 
     def timed(prec, K, only=None):
         torch.cuda.synchronize()

@@ -390,10 +390,21 @@ __global__ void __launch_bounds__(64) k_gb_cycle_end(int k, int maxit, GbState G
   gb_count(G.st, k, G.any_st);
 }
 
+// profile names: the forward's, and those of transposed solves (the adjoint)
+struct GmresNames {
+  const char *init, *start, *m32, *m64, *a, *orth, *step, *end;
+};
+const GmresNames kGmresNames{"gmres_init", "gmres_cycle_start", "gmres_spmm_M_f32", "gmres_spmm_M_f64",
+                             "gmres_spmm_A", "gmres_orth", "gmres_step", "gmres_cycle_end"};
+const GmresNames kGmresNamesT{"gmres_t_init", "gmres_t_cycle_start", "gmres_t_spmm_M_f32",
+                              "gmres_t_spmm_M_f64", "gmres_t_spmm_A", "gmres_t_orth", "gmres_t_step",
+                              "gmres_t_cycle_end"};
+
 template <int LP, class TM>
 int gmres_batched_lp(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, const double* R, double* X,
                      const double* thr, int m, int maxit, const Allocator& al, hipStream_t st, int* iters,
-                     int* status) {
+                     int* status, bool transposed) {
+  const GmresNames& GN = transposed ? kGmresNamesT : kGmresNames;
   const int kp = k + (k & 1);
   const size_t nk = (size_t)n * kp;
   DBuf<double> basis(&al, nk * (size_t)(m + 1));
@@ -531,7 +542,7 @@ int gmres_batched_lp(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, c
   HostStage hs(16);
   int* cnt = hs.as<int>();
   {
-    SAI_PROF("gmres_init", st);
+    SAI_PROF(GN.init, st);
     hipLaunchKernelGGL(k_gb_load, dim3(eg), dim3(GB_NT), 0, st, n, k, kp, R, Bv.p, Xv.p, Wv.p);
     // ||R|| per column (the "cycle" set is every column here)
     HIPC(hipMemsetAsync(G.any_cyc, 0xff, sizeof(int) * 8, st));
@@ -546,26 +557,26 @@ int gmres_batched_lp(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, c
     HIPC(hipStreamSynchronize(st));
     if (cnt[0] == 0) break;
     {
-      SAI_PROF("gmres_cycle_start", st);
+      SAI_PROF(GN.start, st);
       hipLaunchKernelGGL(k_gb_cycle_start, dim3(1), dim3(64), 0, st, k, m, G);
       hipLaunchKernelGGL(k_gb_scale, dim3(eg), dim3(GB_NT), 0, st, n, kp, G.a, Wv.p, basis.p, G.cyc,
                          G.any_cyc);
     }
     for (int j = 0; j < m; ++j) {
       {
-        SAI_PROF(sizeof(TM) == 4 ? "gmres_spmm_M_f32" : "gmres_spmm_M_f64", st);
+        SAI_PROF(sizeof(TM) == 4 ? GN.m32 : GN.m64, st);
         mprod(Vb + nk * j, Zv.p, Sarn);
       }
       {
-        SAI_PROF("gmres_spmm_A", st);
+        SAI_PROF(GN.a, st);
         aprod(Zv.p, Wv.p, Sarn);
       }
       {
-        SAI_PROF("gmres_orth", st);
+        SAI_PROF(GN.orth, st);
         orthogonalise(j + 1, Wv.p);
       }
       {
-        SAI_PROF("gmres_step", st);
+        SAI_PROF(GN.step, st);
         hipLaunchKernelGGL(k_gb_step, dim3(1), dim3(64), 0, st, k, m, j, maxit, G);
         if (j + 1 < m)
           hipLaunchKernelGGL(k_gb_scale, dim3(eg), dim3(GB_NT), 0, st, n, kp, G.a, Wv.p,
@@ -574,7 +585,7 @@ int gmres_batched_lp(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, c
       LAUNCH_CHECK();
     }
     {
-      SAI_PROF("gmres_cycle_end", st);
+      SAI_PROF(GN.end, st);
       hipLaunchKernelGGL(k_gb_backsolve, dim3(1), dim3(64), 0, st, k, G);
       hipLaunchKernelGGL(k_gb_combine, dim3(eg), dim3(GB_NT), 0, st, n, kp, Vb, G.y, G.kk, Zv.p, G.cyc,
                          G.any_cyc);
@@ -610,16 +621,16 @@ int gmres_batched_lp(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, c
 template <class TM>
 int gmres_batched(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, const double* R, double* X,
                   const double* thr, int m, int maxit, const Allocator& al, hipStream_t st, int* iters,
-                  int* status) {
+                  int* status, bool transposed) {
   switch (lp_class(k)) {
-    case 1: return gmres_batched_lp<1, TM>(A, M, n, k, R, X, thr, m, maxit, al, st, iters, status);
-    case 2: return gmres_batched_lp<2, TM>(A, M, n, k, R, X, thr, m, maxit, al, st, iters, status);
-    case 4: return gmres_batched_lp<4, TM>(A, M, n, k, R, X, thr, m, maxit, al, st, iters, status);
-    case 6: return gmres_batched_lp<6, TM>(A, M, n, k, R, X, thr, m, maxit, al, st, iters, status);
-    case 8: return gmres_batched_lp<8, TM>(A, M, n, k, R, X, thr, m, maxit, al, st, iters, status);
-    case 12: return gmres_batched_lp<12, TM>(A, M, n, k, R, X, thr, m, maxit, al, st, iters, status);
-    case 16: return gmres_batched_lp<16, TM>(A, M, n, k, R, X, thr, m, maxit, al, st, iters, status);
-    default: return gmres_batched_lp<32, TM>(A, M, n, k, R, X, thr, m, maxit, al, st, iters, status);
+    case 1: return gmres_batched_lp<1, TM>(A, M, n, k, R, X, thr, m, maxit, al, st, iters, status, transposed);
+    case 2: return gmres_batched_lp<2, TM>(A, M, n, k, R, X, thr, m, maxit, al, st, iters, status, transposed);
+    case 4: return gmres_batched_lp<4, TM>(A, M, n, k, R, X, thr, m, maxit, al, st, iters, status, transposed);
+    case 6: return gmres_batched_lp<6, TM>(A, M, n, k, R, X, thr, m, maxit, al, st, iters, status, transposed);
+    case 8: return gmres_batched_lp<8, TM>(A, M, n, k, R, X, thr, m, maxit, al, st, iters, status, transposed);
+    case 12: return gmres_batched_lp<12, TM>(A, M, n, k, R, X, thr, m, maxit, al, st, iters, status, transposed);
+    case 16: return gmres_batched_lp<16, TM>(A, M, n, k, R, X, thr, m, maxit, al, st, iters, status, transposed);
+    default: return gmres_batched_lp<32, TM>(A, M, n, k, R, X, thr, m, maxit, al, st, iters, status, transposed);
   }
 }
 

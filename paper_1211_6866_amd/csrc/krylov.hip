@@ -129,27 +129,38 @@ void block_alloc(Block& B, int k, int64_t n, const Allocator& al, double* part, 
 enum { IT_DONE = 0, IT_NARROW = 1 };
 
 // Profile names of one iteration's launches; the launches on a narrowed block
+// and those of transposed solves (the adjoint: products with M^T and A~^T)
 // carry their own names, so that the per-launch figures of the full-width
-// block (whose algorithmic bytes follow from k) stay apart.
+// forward block (whose algorithmic bytes follow from k) stay apart.
 struct IterNames {
-  const char *pup, *m32, *m64, *av, *fin, *s, *at, *half, *xr, *full, *rst, *fend;
+  const char *init, *pup, *m32, *m64, *av, *fin, *s, *at, *half, *xr, *full, *rst, *fend;
 };
-const IterNames kWideNames{"bicg_p_update", "bicg_spmm_M_f32", "bicg_spmm_M_f64", "bicg_spmm_A_dot1",
-                           "bicg_finish", "bicg_s_update", "bicg_spmm_A_dot2", "bicg_halfcheck",
-                           "bicg_xr_update", "bicg_fullcheck", "bicg_restart", "bicg_finish_end"};
-const IterNames kNarrowNames{"bicg_narrow_p_update", "bicg_spmm_narrow_M_f32", "bicg_spmm_narrow_M_f64",
-                             "bicg_spmm_narrow_A_dot1", "bicg_narrow_finish", "bicg_narrow_s_update",
-                             "bicg_spmm_narrow_A_dot2", "bicg_narrow_halfcheck", "bicg_narrow_xr_update",
-                             "bicg_narrow_fullcheck", "bicg_narrow_restart", "bicg_narrow_finish_end"};
+const IterNames kWideNames{"bicg_init", "bicg_p_update", "bicg_spmm_M_f32", "bicg_spmm_M_f64",
+                           "bicg_spmm_A_dot1", "bicg_finish", "bicg_s_update", "bicg_spmm_A_dot2",
+                           "bicg_halfcheck", "bicg_xr_update", "bicg_fullcheck", "bicg_restart",
+                           "bicg_finish_end"};
+const IterNames kNarrowNames{"bicg_narrow_init", "bicg_narrow_p_update", "bicg_spmm_narrow_M_f32",
+                             "bicg_spmm_narrow_M_f64", "bicg_spmm_narrow_A_dot1", "bicg_narrow_finish",
+                             "bicg_narrow_s_update", "bicg_spmm_narrow_A_dot2", "bicg_narrow_halfcheck",
+                             "bicg_narrow_xr_update", "bicg_narrow_fullcheck", "bicg_narrow_restart",
+                             "bicg_narrow_finish_end"};
+const IterNames kWideNamesT{"bicg_t_init", "bicg_t_p_update", "bicg_t_spmm_M_f32", "bicg_t_spmm_M_f64",
+                            "bicg_t_spmm_A_dot1", "bicg_t_finish", "bicg_t_s_update", "bicg_t_spmm_A_dot2",
+                            "bicg_t_halfcheck", "bicg_t_xr_update", "bicg_t_fullcheck", "bicg_t_restart",
+                            "bicg_t_finish_end"};
+const IterNames kNarrowNamesT{"bicg_t_narrow_init", "bicg_t_narrow_p_update", "bicg_t_spmm_narrow_M_f32",
+                              "bicg_t_spmm_narrow_M_f64", "bicg_t_spmm_narrow_A_dot1", "bicg_t_narrow_finish",
+                              "bicg_t_narrow_s_update", "bicg_t_spmm_narrow_A_dot2",
+                              "bicg_t_narrow_halfcheck", "bicg_t_narrow_xr_update", "bicg_t_narrow_fullcheck",
+                              "bicg_t_narrow_restart", "bicg_t_narrow_finish_end"};
 
 // Iterations it, it+1, ... on block B with LP lanes per row, until every column
 // has stopped or maxit is reached (IT_DONE), or the active columns would fit a
 // narrower lane class (IT_NARROW).  The first phase also initialises from R.
 template <int LP, class TM>
 int iterate(Block& B, const Csr<double>& A, const Csr<TM>& M, int64_t n, int& it, int maxit, bool first,
-            bool narrow_ok, bool narrowed, const double* R, hipStream_t st, int* slot, hipEvent_t* ev) {
+            bool narrow_ok, const IterNames& N, const double* R, hipStream_t st, int* slot, hipEvent_t* ev) {
   const int k = B.k, kp = B.kp;
-  const IterNames& N = narrowed ? kNarrowNames : kWideNames;
   const State S = B.S;
   const Vec V = B.V;
   constexpr int RPB = (64 / LP) * (NT / 64);
@@ -238,7 +249,7 @@ int iterate(Block& B, const Csr<double>& A, const Csr<TM>& M, int64_t n, int& it
   };
   if (first) {
     {
-      SAI_PROF("bicg_init", st);
+      SAI_PROF(N.init, st);
       hipLaunchKernelGGL((k_init<LP>), dim3(grid), dim3(NT), 0, st, n, k, kp, R, V, S);
       hipLaunchKernelGGL((k_fin<1, F_INIT>), dim3(1), dim3(FNT), 0, st, k, S, grid, 0, 0);
     }
@@ -321,17 +332,17 @@ int iterate(Block& B, const Csr<double>& A, const Csr<TM>& M, int64_t n, int& it
 
 template <class TM>
 int iterate_lp(int lp, Block& B, const Csr<double>& A, const Csr<TM>& M, int64_t n, int& it, int maxit,
-               bool first, bool narrow_ok, bool narrowed, const double* R, hipStream_t st, int* slot,
+               bool first, bool narrow_ok, const IterNames& N, const double* R, hipStream_t st, int* slot,
                hipEvent_t* ev) {
   switch (lp) {
-    case 1: return iterate<1, TM>(B, A, M, n, it, maxit, first, narrow_ok, narrowed, R, st, slot, ev);
-    case 2: return iterate<2, TM>(B, A, M, n, it, maxit, first, narrow_ok, narrowed, R, st, slot, ev);
-    case 4: return iterate<4, TM>(B, A, M, n, it, maxit, first, narrow_ok, narrowed, R, st, slot, ev);
-    case 6: return iterate<6, TM>(B, A, M, n, it, maxit, first, narrow_ok, narrowed, R, st, slot, ev);
-    case 8: return iterate<8, TM>(B, A, M, n, it, maxit, first, narrow_ok, narrowed, R, st, slot, ev);
-    case 12: return iterate<12, TM>(B, A, M, n, it, maxit, first, narrow_ok, narrowed, R, st, slot, ev);
-    case 16: return iterate<16, TM>(B, A, M, n, it, maxit, first, narrow_ok, narrowed, R, st, slot, ev);
-    default: return iterate<32, TM>(B, A, M, n, it, maxit, first, narrow_ok, narrowed, R, st, slot, ev);
+    case 1: return iterate<1, TM>(B, A, M, n, it, maxit, first, narrow_ok, N, R, st, slot, ev);
+    case 2: return iterate<2, TM>(B, A, M, n, it, maxit, first, narrow_ok, N, R, st, slot, ev);
+    case 4: return iterate<4, TM>(B, A, M, n, it, maxit, first, narrow_ok, N, R, st, slot, ev);
+    case 6: return iterate<6, TM>(B, A, M, n, it, maxit, first, narrow_ok, N, R, st, slot, ev);
+    case 8: return iterate<8, TM>(B, A, M, n, it, maxit, first, narrow_ok, N, R, st, slot, ev);
+    case 12: return iterate<12, TM>(B, A, M, n, it, maxit, first, narrow_ok, N, R, st, slot, ev);
+    case 16: return iterate<16, TM>(B, A, M, n, it, maxit, first, narrow_ok, N, R, st, slot, ev);
+    default: return iterate<32, TM>(B, A, M, n, it, maxit, first, narrow_ok, N, R, st, slot, ev);
   }
 }
 
@@ -355,7 +366,8 @@ void cols_copy(int64_t n, const ColCopy& cc, int nv, int lds, int ldd, const std
 
 template <class TM>
 int bicgstab(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, const double* R, double* X,
-             const double* thr, int maxit, const Allocator& al, hipStream_t st, int* iters, int* status) {
+             const double* thr, int maxit, const Allocator& al, hipStream_t st, int* iters, int* status,
+             bool transposed) {
   DBuf<double> part(&al, (size_t)3 * NBMAX * PSTRIDE);
   // two sets of block buffers, used alternately when the block narrows
   Block blk[2];
@@ -384,7 +396,9 @@ int bicgstab(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, const dou
   bool first = true, first_block = true;
   for (;;) {
     Block& B = blk[cur];
-    const int r = iterate_lp<TM>(lp_class(B.k), B, A, M, n, it, maxit, first, narrow_ok, !first_block, R, st,
+    const IterNames& nm = transposed ? (first_block ? kWideNamesT : kNarrowNamesT)
+                                     : (first_block ? kWideNames : kNarrowNames);
+    const int r = iterate_lp<TM>(lp_class(B.k), B, A, M, n, it, maxit, first, narrow_ok, nm, R, st,
                                  slot, ev);
     first_block = false;
     first = false;
@@ -602,13 +616,13 @@ __global__ void __launch_bounds__(GM_NT) k_gmres(int64_t n, int k, Csr<double> A
 template <class TM>
 int gmres_run(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, const double* R, double* X,
               const double* thr, int restart, int maxit, const Allocator& al, hipStream_t st,
-              int* iters, int* status) {
+              int* iters, int* status, bool transposed) {
   if (restart < 1 || restart > GM_MAXM) SAI_THROW(SAI_EINVAL, "GMRES restart must be in [1, %d]", GM_MAXM);
   DBuf<double> work(&al, (size_t)k * (restart + 3) * n);
   DBuf<double> dthr(&al, k);
   DBuf<int> dit(&al, k), dst(&al, k);
   HIPC(hipMemcpyAsync(dthr.p, thr, sizeof(double) * k, hipMemcpyHostToDevice, st));
-  SAI_PROF("gmres_fused", st);
+  SAI_PROF(transposed ? "gmres_t_fused" : "gmres_fused", st);
   hipLaunchKernelGGL((k_gmres<TM>), dim3(k), dim3(GM_NT), 0, st, n, k, A, M, R, X, dthr.p, restart,
                      maxit, work.p, dit.p, dst.p);
   LAUNCH_CHECK();
@@ -642,11 +656,11 @@ namespace {
 template <class TM>
 int gmres_solve(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, const double* R, double* X,
                 const double* thr, int restart, int maxit, const Allocator& al, hipStream_t st, int* iters,
-                int* status) {
+                int* status, bool transposed) {
   if (restart < 1 || restart > GM_MAXM) SAI_THROW(SAI_EINVAL, "GMRES restart must be in [1, %d]", GM_MAXM);
   if (n * k >= (int64_t)tune_get("GMRES_BATCH_NK", 32768))
-    return gmres_batched<TM>(A, M, n, k, R, X, thr, restart, maxit, al, st, iters, status);
-  return gmres_run<TM>(A, M, n, k, R, X, thr, restart, maxit, al, st, iters, status);
+    return gmres_batched<TM>(A, M, n, k, R, X, thr, restart, maxit, al, st, iters, status, transposed);
+  return gmres_run<TM>(A, M, n, k, R, X, thr, restart, maxit, al, st, iters, status, transposed);
 }
 
 template <class TM>
@@ -665,8 +679,8 @@ int krylov_typed(const sai_split_s* sp, const sai_precond_s* pc, int transpose, 
   }
   const int64_t n = sp->n;
   if (o.method == SAI_GMRES)
-    return gmres_solve<TM>(A, M, n, k, R, X, thr, o.restart, o.maxit, al, st, iters, status);
-  return bicgstab<TM>(A, M, n, k, R, X, thr, o.maxit, al, st, iters, status);
+    return gmres_solve<TM>(A, M, n, k, R, X, thr, o.restart, o.maxit, al, st, iters, status, transpose != 0);
+  return bicgstab<TM>(A, M, n, k, R, X, thr, o.maxit, al, st, iters, status, transpose != 0);
 }
 
 // dst (n x kc, row stride kc) = columns c0 .. c0+kc-1 of src (row stride lds),
