@@ -79,10 +79,13 @@ def adjoint_from_forward(S, M, W, g, eps=1e-8, method="bicgstab", restart=30, ma
     Each pass solves A~^T d = forward_correction(W, D, res) for one column (M^T
     as right preconditioner) and adds d to lambda; res starts as g and is then
     the true residual g - A^T lambda = g - A~^T lambda - V (U^T lambda).  The
-    passes stop once ||g - A^T lambda|| < eps ||g||.  The first solve stops at
-    (eps/2) ||g||; each later one at (eps/2) ||g|| divided by the amplification
-    seen so far (the true residual over the last threshold), because the true
-    residual is (I + V W^T) times the solve's residual (plus W's own error).
+    passes stop once ||g - A^T lambda|| < eps ||g||.  After a pass the true
+    residual is (I + V W^T) r_s - V R^T d (r_s = the solve's residual, R = U -
+    A~ W the forward's auxiliary residuals, d the pass's solution): the second
+    term, W's own error, usually keeps the first pass above eps and the next
+    pass removes it.  The first solve stops at (eps/2) ||g||, each later one at
+    (eps/2) ||g|| / a with a = max(1, ||(I + V W^T) r_s|| / ||r_s||) of the pass
+    before, so that the next pass's (I + V W^T) r_s stays below (eps/2) ||g||.
     Returns dict(lam, grad_b, iters, passes, rr, status)."""
     n = S.At.shape[0]
     D = np.asarray(S.D, dtype=np.int64)
@@ -110,7 +113,13 @@ def adjoint_from_forward(S, M, W, g, eps=1e-8, method="bicgstab", restart=30, ma
         rr = rnorm / gnorm
         if rr < eps:
             break
-        thr = 0.5 * eps * gnorm / (rnorm / thr)
+        rs = rhs - AtT @ X[:, 0]
+        ars = rs.copy()
+        if len(D):
+            ars[D] += W.T @ rs
+        nrs = float(np.linalg.norm(rs))
+        amp = max(1.0, float(np.linalg.norm(ars)) / nrs) if nrs > 0.0 else 1.0
+        thr = 0.5 * eps * gnorm / amp
         res = rho
     return dict(lam=lam, grad_b=lam, iters=iters, passes=p, rr=rr,
                 status="converged" if rr < eps else "maxit")
