@@ -351,10 +351,12 @@ int sai_backward(const sai_split_t* sp, const sai_precond_t* pc, const double* x
  * K^T z = W^T r, with M^T as right preconditioner and adds d to lambda; r is
  * grad_x in the first pass, then the true residual grad_x - A~^T lambda -
  * V (U^T lambda) (float64).  The passes stop once that residual is below
- * eps ||grad_x||, at most 4.  The first solve stops at (eps/2)||grad_x||, each
- * later one at (eps/2)||grad_x|| divided by the amplification seen (true
- * residual over the last threshold), since the true residual is (I + V W^T)
- * times the solve's residual plus the effect of W's own error.  stats: iters[0]
+ * eps ||grad_x||, at most 4.  After a pass it is (I + V W^T) r_s - V R^T d
+ * (r_s the solve's residual, R = U - A~ W the forward's auxiliary residuals,
+ * d the pass's solution); the second term usually keeps the first pass above
+ * eps and the next pass removes it.  The first solve stops at
+ * (eps/2)||grad_x||, each later one at (eps/2)||grad_x|| / a with
+ * a = max(1, ||(I + V W^T) r_s|| / ||r_s||) of the pass before.  stats: iters[0]
  * = the iterations of all passes (iters[1..s] = 0), rr = the final adjoint
  * residual ||grad_x - A^T lambda|| / ||grad_x||, c = ||z|| of the first pass,
  * t_check_ms = the residual checks, t_smw_ms = the corrections; c_mode and

@@ -284,6 +284,18 @@ __global__ void k_resid_t(int64_t n, const int32_t* __restrict__ cp, const int32
   }
 }
 
+// out[0] = sum over d of (r(j_d) + q_d)^2 - r(j_d)^2, in order (||r + V q||^2 - ||r||^2)
+__global__ void k_amp_terms(int s, const int32_t* __restrict__ D, const double* __restrict__ r,
+                            const double* __restrict__ q, double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double a = 0.0;
+  for (int d = 0; d < s; ++d) {
+    const double v = r[D[d]];
+    a += (v + q[d]) * (v + q[d]) - v * v;
+  }
+  out[0] = a;
+}
+
 // y += d
 __global__ void k_add_vec(int64_t n, const double* __restrict__ d, double* __restrict__ y) {
   for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) y[i] += d[i];
@@ -620,11 +632,12 @@ namespace sai {
 // A^{-T} = A~^{-T} (I - V K^{-T} W^T), K = I + V^T W, so each pass solves one
 // system A~^T d = r - V K^{-T} W^T r (M^T as right preconditioner) and adds d
 // to lambda; r is grad_x, then the true residual grad_x - A~^T lambda -
-// V (U^T lambda).  The true residual is (I + V W^T) times the solve's residual
-// (plus the effect of W's own error), so the first solve stops at
-// (eps/2)||g|| and each later one at (eps/2)||g|| over the amplification seen
-// (true residual / last threshold); passes stop once the true residual is
-// below eps ||g||.
+// V (U^T lambda).  After a pass the true residual is (I + V W^T) r_s - V R^T d
+// (r_s the solve's residual, R = U - A~ W the forward's auxiliary residuals:
+// W's own error, which usually keeps the first pass above eps and which the
+// next pass removes).  The first solve stops at (eps/2)||g||, each later one
+// at (eps/2)||g|| / a with a = max(1, ||(I + V W^T) r_s|| / ||r_s||) of the
+// pass before; passes stop once the true residual is below eps ||g||.
 void backward_y_impl(const sai_split_s* sp, const sai_precond_s* pc, const double* x, const double* Y,
                      const double* gx, double* gb, double* ga, const sai_solve_opts& o, hipStream_t st,
                      sai_solve_stats* stats) {
@@ -636,7 +649,8 @@ void backward_y_impl(const sai_split_s* sp, const sai_precond_s* pc, const doubl
   EventTimer t_all, t_solve, t_chk;
   float solve_ms = 0.0f, chk_ms = 0.0f;
   t_all.start(st);
-  DBuf<double> lam(&al, (size_t)n), res(&al, (size_t)n), rhs(&al, (size_t)n), del(&al, (size_t)n);
+  DBuf<double> lam(&al, (size_t)n), res(&al, (size_t)n), rhs(&al, (size_t)n), del(&al, (size_t)n),
+      rs(&al, (size_t)n);
   const int64_t nbw = (n + WTV_ROWS - 1) / WTV_ROWS, nbu = (n + UTY_ROWS - 1) / UTY_ROWS;
   const int sm = std::max(s, 1);
   DBuf<double> part(&al, (size_t)std::max(nbw, nbu) * sm), P(&al, (size_t)sm), Kt(&al, (size_t)sm * sm);
@@ -685,6 +699,29 @@ void backward_y_impl(const sai_split_s* sp, const sai_precond_s* pc, const doubl
     }
     return dev_norm2(res.p, n, 1, al, st);
   };
+  // a = max(1, ||(I + V W^T) r_s|| / ||r_s||) for the last solve, r_s = rhs - A~^T del
+  auto solve_amplification = [&]() -> double {
+    SAI_PROF("adjoint_correction", st);
+    hipLaunchKernelGGL(k_resid_t, dim3(rows_grid(n)), dim3(NT), 0, st, n, sp->t_col_ptr.p, sp->t_row_idx.p,
+                       sp->t_cval.p, (const double*)rhs.p, (const double*)del.p, rs.p);
+    LAUNCH_CHECK();
+    const double nrs = dev_norm2(rs.p, n, 1, al, st);
+    if (s == 0 || !(nrs > 0.0)) return 1.0;
+    for (int c0 = 0; c0 < s; c0 += NT) {
+      const int cw = std::min(NT, s - c0);
+      hipLaunchKernelGGL(k_wtv_partial, dim3((unsigned)nbw), dim3(NT), 0, st, n, s, c0, cw, Y,
+                         (const double*)rs.p, part.p);
+      LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(k_cols_final, dim3(s), dim3(NT), 0, st, (int)nbw, s, (const double*)part.p, P.p);
+    hipLaunchKernelGGL(k_amp_terms, dim3(1), dim3(64), 0, st, s, sp->dense_cols.p, (const double*)rs.p,
+                       (const double*)P.p, Kt.p);
+    LAUNCH_CHECK();
+    double extra = 0.0;
+    HIPC(hipMemcpyAsync(&extra, Kt.p, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    return std::max(1.0, std::sqrt(std::max(0.0, nrs * nrs + extra)) / nrs);
+  };
   HIPC(hipMemsetAsync(lam.p, 0, sizeof(double) * n, st));
   int code = SAI_OK, its = 0;
   double rr = 0.0, c = 0.0;
@@ -712,8 +749,8 @@ void backward_y_impl(const sai_split_s* sp, const sai_precond_s* pc, const doubl
         break;
       }
       code = kc == SAI_EBREAKDOWN ? SAI_EBREAKDOWN : SAI_ENOCONV;
-      if (kc == SAI_EBREAKDOWN) break;
-      thr = 0.5 * o.eps * gnorm / (rn / thr);
+      if (kc == SAI_EBREAKDOWN || pass == PASSES) break;
+      thr = 0.5 * o.eps * gnorm / solve_amplification();
       src = res.p;
     }
   }
