@@ -31,8 +31,10 @@ import time
 
 # knob -> candidate values, the built-in default first
 KNOBS_SOLVE = [
-    ("SPMM_M", [1, 0, 2, 3]),          # M product gather batches: 6/3, 8/4, 5/0, 16/8
-    ("SPMM_A", [0, 1, 2, 3, 4]),       # A~ products: 4/2, 8/4, 7/0 (LDS-staged tiles); 8/4, 7/0 (no staging)
+    ("SPMM_M", [1, 0, 2, 3, 4]),       # M product gather batches: 6/3, 8/4, 5/0, 16/8, 2/0
+    ("SPMM_A", [0, 1, 2, 3, 4, 5]),    # A~ products: 4/2, 8/4, 7/0 (LDS-staged tiles); 8/4, 7/0 (no staging); 2/0
+    ("SPMM_M_WIDE", [4, 0, 1]),        # the same for blocks over 32 columns: 2/0, 8/4, 6/3
+    ("SPMM_A_WIDE", [5, 0, 1]),        # 2/0, 4/2, 8/4
     ("SGRID", [512, 1024, 256]),       # workgroups of the streaming updates
     ("NARROW", [1, 0]),                # narrowing of the BiCGStab block
     ("NARROW_MIN", [1000000, 500000, 2000000, 8000000]),

@@ -456,11 +456,12 @@ int gmres_batched_lp(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, c
     int64_t g = std::min<int64_t>({(int64_t)NBMAX, ntiles, (int64_t)resident_blocks(kern, NT)});
     return (int)(g >= 8 ? (g & ~int64_t(7)) : g);
   };
-  // the M product's gather batches follow the SPMM_M knob, as in BiCGStab
-  const int mvar = tune_get("SPMM_M", 1);
+  // the M product's gather batches follow the SPMM_M (SPMM_M_WIDE) knob, as in BiCGStab
+  const int mvar = LP >= 32 ? tune_get("SPMM_M_WIDE", 4) : tune_get("SPMM_M", 1);
   const void* km = mvar == 0   ? (const void*)k_spmm<LP, TM, 8, 4>
                    : mvar == 2 ? (const void*)k_spmm<LP, TM, 5, 0>
                    : mvar == 3 ? (const void*)k_spmm<LP, TM, 16, 8>
+                   : mvar == 4 ? (const void*)k_spmm<LP, TM, 2, 0>
                                : (const void*)k_spmm<LP, TM, 6, 3>;
   const void* ka = (const void*)k_spmm<LP, double, 6, 3>;
   const int gm = sp_grid(km), ga = sp_grid(ka);
@@ -472,6 +473,7 @@ int gmres_batched_lp(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, c
       case 0: go(k_spmm<LP, TM, 8, 4>); break;
       case 2: go(k_spmm<LP, TM, 5, 0>); break;
       case 3: go(k_spmm<LP, TM, 16, 8>); break;
+      case 4: go(k_spmm<LP, TM, 2, 0>); break;
       default: go(k_spmm<LP, TM, 6, 3>); break;
     }
   };

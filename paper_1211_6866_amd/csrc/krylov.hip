@@ -198,8 +198,13 @@ int iterate(Block& B, const Csr<double>& A, const Csr<TM>& M, int64_t n, int& it
   // never matches
   const int force_it = tune_get("BRK_TEST", 0);
   const int force_it2 = tune_get("BRK_TEST2", 0);
-  // M product: gather batch sizes (CH while >= CH entries remain, then CH2)
-  const int mvar = tune_get("SPMM_M", 1);
+  // M product: gather batch sizes (CH while >= CH entries remain, then CH2).
+  // Blocks over 32 columns (LP = 32) take their own knob: there fewer loads in
+  // flight per wavefront are faster (52 columns at 160^3: batches of 2 take
+  // 2.82 ms against 3.20 with 8/4; the gathers are bound by the misses the
+  // vector L1 keeps in flight), while one-column blocks wait on each batch
+  // (0.28 ms with 8/4, 1.18 ms with batches of 2).
+  const int mvar = LP >= 32 ? tune_get("SPMM_M_WIDE", 4) : tune_get("SPMM_M", 1);
   auto spmm_m = [&](const double* Xin, double* Y) {
     auto go = [&](auto kern) {
       hipLaunchKernelGGL(kern, dim3(sp_grid((const void*)kern)), dim3(NT), 0, st, n, k, kp, M, Xin, Y,
@@ -209,21 +214,25 @@ int iterate(Block& B, const Csr<double>& A, const Csr<TM>& M, int64_t n, int& it
       case 0: go(k_spmm<LP, TM, 8, 4>); break;
       case 2: go(k_spmm<LP, TM, 5, 0>); break;
       case 3: go(k_spmm<LP, TM, 16, 8>); break;
+      case 4: go(k_spmm<LP, TM, 2, 0>); break;
       default: go(k_spmm<LP, TM, 6, 3>); break;
     }
   };
   // A~ products (with their dot products): gather batch sizes
-  const int avar = tune_get("SPMM_A", 0);
-  // (3 and 4: the 8/4 and 7/0 batches reading A~ from global memory, no LDS staging)
+  const int avar = LP >= 32 ? tune_get("SPMM_A_WIDE", 5) : tune_get("SPMM_A", 0);
+  // (3 and 4: the 8/4 and 7/0 batches reading A~ from global memory, no LDS staging;
+  // 5: batches of 2)
   const void* kav = avar == 1   ? (const void*)k_av<LP, 8, 4>
                     : avar == 2 ? (const void*)k_av<LP, 7, 0>
                     : avar == 3 ? (const void*)k_av<LP, 8, 4, false>
                     : avar == 4 ? (const void*)k_av<LP, 7, 0, false>
+                    : avar == 5 ? (const void*)k_av<LP, 2, 0>
                                 : (const void*)k_av<LP, 4, 2>;
   const void* kat = avar == 1   ? (const void*)k_at<LP, 8, 4>
                     : avar == 2 ? (const void*)k_at<LP, 7, 0>
                     : avar == 3 ? (const void*)k_at<LP, 8, 4, false>
                     : avar == 4 ? (const void*)k_at<LP, 7, 0, false>
+                    : avar == 5 ? (const void*)k_at<LP, 2, 0>
                                 : (const void*)k_at<LP, 4, 2>;
   const int tgrid = std::min(sp_grid(kav), sp_grid(kat));
   auto go_a = [&](auto kern) {
@@ -235,6 +244,7 @@ int iterate(Block& B, const Csr<double>& A, const Csr<TM>& M, int64_t n, int& it
       case 2: go_a(k_av<LP, 7, 0>); break;
       case 3: go_a(k_av<LP, 8, 4, false>); break;
       case 4: go_a(k_av<LP, 7, 0, false>); break;
+      case 5: go_a(k_av<LP, 2, 0>); break;
       default: go_a(k_av<LP, 4, 2>); break;
     }
   };
@@ -244,6 +254,7 @@ int iterate(Block& B, const Csr<double>& A, const Csr<TM>& M, int64_t n, int& it
       case 2: go_a(k_at<LP, 7, 0>); break;
       case 3: go_a(k_at<LP, 8, 4, false>); break;
       case 4: go_a(k_at<LP, 7, 0, false>); break;
+      case 5: go_a(k_at<LP, 2, 0>); break;
       default: go_a(k_at<LP, 4, 2>); break;
     }
   };

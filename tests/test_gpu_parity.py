@@ -532,25 +532,37 @@ def test_more_than_64_right_hand_sides():
     assert np.linalg.norm(_np(ga) - Gd) <= 1e-5 * np.linalg.norm(Gd)
 
 
-def test_m_product_variants_bit_identical():
-    """The M product's gather-batch variants (SPMM_M = 0 .. 3, chosen by the
-    autotuner) change only how many loads are in flight: each row's products
-    are added in the same order, so the whole Krylov solve is bit-identical."""
+@pytest.mark.parametrize("width", ["narrow", "wide"])
+def test_m_product_variants_bit_identical(width):
+    """The sparse products' gather-batch variants (SPMM_M = 0 .. 4 and SPMM_A =
+    0 .. 5, or SPMM_M_WIDE / SPMM_A_WIDE for blocks over 32 columns, chosen by
+    the autotuner) change only how many loads are in flight: each row's
+    products are added in the same order, so the whole Krylov solve is
+    bit-identical.  narrow: [b, U] of a 12^3 matrix (5 columns); wide: 40
+    seeded right-hand sides (the 32-lane class)."""
     w, (rp, ci, va) = _load("c2_12")
     S = osplit.split(w.A)
     g = P.Split(rp, ci, va)
     pc = P.Precond(g, pattern=P.PAT_A2, drop=P.DROP_ABS, tau=1e-3, precision=P.FP32)
-    R, _ = _oracle_rhs_and_M(w, S)
-    thr = okry.thresholds(np.linalg.norm(w.b), S.s, 1e-10)
+    if width == "narrow":
+        R, _ = _oracle_rhs_and_M(w, S)
+        thr = okry.thresholds(np.linalg.norm(w.b), S.s, 1e-10)
+        km, ka, dm, da = "SPMM_M", "SPMM_A", 1, 0
+    else:
+        R = np.random.default_rng(40).standard_normal((w.A.shape[0], 40))
+        thr = [1e-10 * np.linalg.norm(R[:, c]) for c in range(40)]
+        km, ka, dm, da = "SPMM_M_WIDE", "SPMM_A_WIDE", 4, 5
     out = []
     try:
-        for v in (1, 0, 2, 3):
-            P.tune_set("SPMM_M", v)
+        for m, a in [(dm, da)] + [(v, da) for v in range(5) if v != dm] + [(dm, v) for v in range(6) if v != da]:
+            P.tune_set(km, m)
+            P.tune_set(ka, a)
             X, its, sts, code = P.krylov(g, pc, torch.from_numpy(R).cuda(), thr)
             assert code == P.OK
             out.append((_np(X), its))
     finally:
-        P.tune_set("SPMM_M", 1)
+        P.tune_set(km, dm)
+        P.tune_set(ka, da)
     for X, its in out[1:]:
         assert its == out[0][1] and np.array_equal(X, out[0][0])
 
