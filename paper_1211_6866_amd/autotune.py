@@ -13,7 +13,8 @@ the current setting by more than ``--margin``:
   ``reps`` after one warm-up);
 * launch knobs of the Krylov solve, by coordinate descent: each knob in turn
   takes every candidate value while the others keep their current best, timed
-  on whole steps (split, build, BiCGStab to 1e-8, SMW recovery).
+  on whole steps (split, build, BiCGStab to 1e-8, SMW recovery, and for the
+  workloads with a loss the adjoint from the forward's W).
 
 The choices are stored per workload class (the benchmark's workload name) in
 tuning/<device>.json (architecture and CU count), with the default and tuned
@@ -77,10 +78,17 @@ def main(argv=None):
         pc = P.Precond(sp_, precision=P.FP32, **bkw)
         return pc.stats.t_ls_ms
 
+    xstar = torch.from_numpy(W.x_star(w.A.shape[0], w.seed)).cuda() if adjoint else None
+
     def step():
+        # the benchmark's step: with a loss, the adjoint from the forward's W too
         sp_ = P.Split(rp, ci, va)
         pc = P.Precond(sp_, precision=P.FP32, **bkw)
-        P.solve(sp_, pc, b, **skw)
+        if adjoint:
+            x, Y, _ = P.solve_y(sp_, pc, b, **skw)
+            P.backward_y(sp_, pc, x, Y, x - xstar, **skw)
+        else:
+            P.solve(sp_, pc, b, **skw)
 
     def timed(f):
         f()
