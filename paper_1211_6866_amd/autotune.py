@@ -37,6 +37,7 @@ KNOBS_SOLVE = [
     ("SPMM_M_WIDE", [4, 0, 1]),        # the same for blocks over 32 columns: 2/0, 8/4, 6/3
     ("SPMM_A_WIDE", [5, 0, 1]),        # 2/0, 4/2, 8/4
     ("SGRID", [512, 1024, 256]),       # workgroups of the streaming updates
+    ("LP_MIN", [1, 2]),                # smallest lane class (one-column blocks on tiles of 128 rows)
     ("NARROW", [1, 0]),                # narrowing of the BiCGStab block
     ("NARROW_MIN", [1000000, 500000, 2000000, 8000000]),
 ]

@@ -46,12 +46,14 @@ namespace {
 // the order of the partial sums of its dot products follows the grid).
 
 // lanes per row for k columns: the smallest of 1, 2, 4, 6, 8, 12, 16, 32 covering
-// the column pairs
+// the column pairs, and at least LP_MIN (knob, default 1: with 2 a one-column
+// block takes tiles of 128 rows, whose entries of M fit the LDS staging area)
 int lp_class(int k) {
   const int pairs = (k + 1) / 2;
+  const int lmin = tune_get("LP_MIN", 1);
   const int cls[] = {1, 2, 4, 6, 8, 12, 16, 32};
   for (int c : cls)
-    if (pairs <= c) return c;
+    if (pairs <= c && c >= lmin) return c;
   return 32;
 }
 
