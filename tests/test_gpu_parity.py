@@ -1003,3 +1003,39 @@ def test_solve_equilibrated_vs_oracle():
     x2, st2 = P.solve(g, pc, torch.from_numpy(1e-10 * w.b).cuda(), eps=1e-8, equilibrate=True)
     assert np.linalg.norm(_np(x2) * 1e20 - xs) <= 1e-10 * np.linalg.norm(xs)
     print(f"unscaled rr {rr0:.2e}, scaled rr {rr1:.2e}, iterations {st1['iters']}")
+
+
+@pytest.mark.parametrize("knobs", [dict(LP_MIN=2), dict(LP_MIN=4), dict(XMAP=0), dict(XMAP=3),
+                                   dict(XMAP=16), dict(PERSIST=0)],
+                         ids=["lp_min2", "lp_min4", "round_robin", "runs3", "runs16", "not_persistent"])
+def test_launch_knobs_vs_oracle(knobs):
+    """Launch-shape knobs the tuning file may set (the smallest lane class, the
+    tile-to-XCD maps: round-robin, runs of 3 or 16 tiles per XCD; grids larger
+    than the resident count) change only rounding: [b, U] of a 12^3 matrix and
+    one seeded right-hand side solved with each, every true residual below its
+    threshold, iterations within 2 of the oracle's, x within ||A~^{-1}| (sum of
+    both true residuals) of the oracle's."""
+    w, (rp, ci, va) = _load("c2_12")
+    S = osplit.split(w.A)
+    g = P.Split(rp, ci, va)
+    pc = P.Precond(g, pattern=P.PAT_A2, drop=P.DROP_ABS, tau=1e-3, precision=P.FP64)
+    R, Mo = _oracle_rhs_and_M(w, S)
+    r1 = np.random.default_rng(77).standard_normal((w.A.shape[0], 1))
+    At = sp.csr_matrix(S.At)
+    smin = float(np.linalg.svd(S.At.toarray(), compute_uv=False)[-1])
+    for RR, thr in ((R, okry.thresholds(np.linalg.norm(w.b), S.s, 1e-10)),
+                    (r1, [1e-10 * np.linalg.norm(r1)])):
+        try:
+            for kname, v in knobs.items():
+                P.tune_set(kname, v)
+            X, its, sts, code = P.krylov(g, pc, torch.from_numpy(np.ascontiguousarray(RR)).cuda(), thr)
+        finally:
+            P.tune_clear()
+        assert code == P.OK and all(v == 0 for v in sts), (knobs, its, sts)
+        Xh = _np(X)
+        Xo, itso, _ = okry.solve_block(At, Mo, RR, thr)
+        for c in range(RR.shape[1]):
+            rg = np.linalg.norm(RR[:, c] - At @ Xh[:, c])
+            ro = np.linalg.norm(RR[:, c] - At @ Xo[:, c])
+            assert rg < thr[c] and abs(its[c] - itso[c]) <= 2, (knobs, c, rg, its, itso)
+            assert np.linalg.norm(Xh[:, c] - Xo[:, c]) <= (rg + ro) / smin
