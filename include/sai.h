@@ -363,7 +363,7 @@ int sai_backward(const sai_split_t* sp, const sai_precond_t* pc, const double* x
  * equilibrate are not used.  Outputs as sai_backward (written also when the
  * status is not SAI_OK).  Errors: SAI_ENOCONV when 4 passes leave the residual
  * at or above eps, SAI_EBREAKDOWN, SAI_ESINGULAR for a zero pivot of K^T,
- * SAI_EINVAL for a NULL argument (Y with s > 0). */
+ * SAI_EINVAL for a NULL argument (Y with s > 0) or a non-finite grad_x. */
 int sai_backward_y(const sai_split_t* sp, const sai_precond_t* pc, const double* x,
                    const double* Y, const double* grad_x, double* grad_b, double* grad_a_val,
                    const sai_solve_opts* opts, void* stream, sai_solve_stats* stats /* host */);

@@ -655,6 +655,7 @@ void backward_y_impl(const sai_split_s* sp, const sai_precond_s* pc, const doubl
   const int sm = std::max(s, 1);
   DBuf<double> part(&al, (size_t)std::max(nbw, nbu) * sm), P(&al, (size_t)sm), Kt(&al, (size_t)sm * sm);
   const double gnorm = dev_norm2(gx, n, 1, al, st);
+  if (!std::isfinite(gnorm)) SAI_THROW(SAI_EINVAL, "grad_x has a non-finite entry");
   // out = v - V K^{-T} W^T v; returns ||K^{-T} W^T v|| when `norm`
   auto correct = [&](const double* v, double* out, bool norm) -> double {
     SAI_PROF("adjoint_correction", st);

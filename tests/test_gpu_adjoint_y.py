@@ -194,9 +194,15 @@ def test_backward_y_many_dense_columns():
     assert np.linalg.norm(_np(ga) - Gd) <= 1e-5 * np.linalg.norm(Gd)
 
 
-def test_backward_y_rejects_missing_y():
+def test_backward_y_rejects_missing_y_and_non_finite_gradient():
     w, g, pc, _ = _setup("c2_12")
     x = torch.zeros(w.A.shape[0], dtype=torch.float64, device="cuda")
     with pytest.raises(P.SaiError) as e:
         P.backward_y(g, pc, x, None, x.clone())
+    assert e.value.code == P.EINVAL
+    x2, Y, _ = P.solve_y(g, pc, torch.from_numpy(w.b).cuda(), eps=1e-8)
+    gx = torch.ones_like(x2)
+    gx[5] = float("nan")
+    with pytest.raises(P.SaiError) as e:
+        P.backward_y(g, pc, x2, Y, gx)
     assert e.value.code == P.EINVAL
