@@ -206,3 +206,20 @@ def test_backward_y_rejects_missing_y_and_non_finite_gradient():
     with pytest.raises(P.SaiError) as e:
         P.backward_y(g, pc, x2, Y, gx)
     assert e.value.code == P.EINVAL
+
+
+def test_backward_y_iteration_limit():
+    """maxit = 3: the passes stop without reaching eps; SAI_ENOCONV with the
+    gradients still written (finite) and the reported residual the true one."""
+    w, g, pc, _ = _setup("c4_40")
+    b = torch.from_numpy(w.b).cuda()
+    x, Y, _ = P.solve_y(g, pc, b, eps=1e-8)
+    gv = _np(x) - W.x_star(w.A.shape[0], w.seed)
+    gb, ga, st = P.backward_y(g, pc, x, Y, torch.from_numpy(gv).cuda(), eps=1e-8, maxit=3,
+                              raise_on_error=False)
+    assert st["code"] == P.ENOCONV and st["status"] == P.ENOCONV
+    lam = _np(gb)
+    assert np.isfinite(lam).all() and np.isfinite(_np(ga)).all()
+    rr = _true_rr(w.A, lam, gv)
+    assert rr >= 1e-8 and _rr_agrees(w.A, lam, gv, rr, st["rr"])
+    assert 0 < st["iters"][0] <= 4 * 3
