@@ -182,9 +182,9 @@ int iterate(Block& B, const Csr<double>& A, const Csr<TM>& M, int64_t n, int& it
   const size_t nk = (size_t)n * kp;
   // tile-to-XCD map (TILE_LOOP): contiguous chunks per XCD when a block fits the
   // MALL, else round-robin tiles (XCHUNK = 0), or the blocked interleave with
-  // runs of XCHUNK rows per XCD.  On the 160^3 workload (1.7 GB blocks) every
-  // XCHUNK from 1600 to 51200 rows made the M product slower (2.71-3.01 ms
-  // against 2.60 ms round-robin), so round-robin is the default.
+  // runs of XCHUNK rows per XCD (set per workload class by the tuning file).  On
+  // the 160^3 workload (1.7 GB blocks) runs of 800-3200 rows take the M product
+  // from 2.82 to 2.56 ms with gathers in batches of 2 (slower with 8/4).
   constexpr int RPB_ = (64 / LP) * (NT / 64);
   const int xchunk = tune_get("XCHUNK", 0);
   const int xmap_big = xchunk > 0 ? std::max(2, xchunk / RPB_) : 0;
