@@ -176,10 +176,18 @@ __global__ void __launch_bounds__(GNT) k_gather(int32_t n, const int32_t* __rest
         const int t0 = h + g * V;
         T v[V];
         elems<T, V>(t0, nI, sr, so, er, ev, v);
-        if constexpr (V == 4)
-          *reinterpret_cast<float4*>(out + o + t0) = make_float4(v[0], v[1], v[2], v[3]);
-        else
-          *reinterpret_cast<double2*>(out + o + t0) = make_double2(v[0], v[1]);
+        // the blocks are written once and not read back here: non-temporal
+        // stores keep them from displacing the CSC entries that neighbouring
+        // columns gather again
+        if constexpr (V == 4) {
+          typedef float f4v __attribute__((ext_vector_type(4)));
+          const f4v q = {v[0], v[1], v[2], v[3]};
+          __builtin_nontemporal_store(q, reinterpret_cast<f4v*>(out + o + t0));
+        } else {
+          typedef double d2v __attribute__((ext_vector_type(2)));
+          const d2v q = {v[0], v[1]};
+          __builtin_nontemporal_store(q, reinterpret_cast<d2v*>(out + o + t0));
+        }
       }
       for (int t = h + nv * V + lane; t < (int)ne; t += WAVE) out[o + t] = elem<T>(t, nI, sr, so, er, ev);
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
