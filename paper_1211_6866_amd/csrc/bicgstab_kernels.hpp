@@ -53,6 +53,7 @@ struct State {
   int* pend;  // t^T t below TINY at a column that awaits its half-step check
   int* any;   // 0 half, 1 full, 2 restart, 3 active count, 4 half-converged
   double* part;
+  int nt;     // output blocks stored non-temporally (st2)
 };
 
 // n x kp blocks (b: the right-hand sides, copied in with the pad column zeroed)
@@ -73,19 +74,25 @@ __device__ __forceinline__ double2 ld2(const double* __restrict__ p, int64_t q) 
 // store when the first is on.  The pad column is zero in every block and each
 // kernel computes zero for it from zero inputs (its scalars are zero), so the
 // store leaves it unchanged; a single 16-byte store instead of a divergent pair
-// of stores made the M product on the 52-wide block about 10% faster.  The
-// stores are non-temporal: an output block is next read by another kernel, and
-// keeping it out of the caches' recently-used lines leaves them to the rows the
-// sparse products gather (every kernel of the iteration 3-7% faster at 160^3).
+// of stores made the M product on the 52-wide block about 10% faster.  With nt
+// (blocks larger than the L2s together; State::nt) the stores are non-temporal:
+// an output block is next read by another kernel, and keeping it out of the
+// caches' recently-used lines leaves them to the rows the sparse products gather
+// (every kernel of the iteration 3-7% faster at 160^3); blocks that fit the L2s
+// are read back from there.
 typedef double sai_d2v __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ void st2(double* __restrict__ p, int64_t q, double a, double b, bool o0,
-                                    bool o1, bool pad = false) {
+                                    bool o1, bool pad, int nt) {
   if (o0 && (o1 || pad)) {
     const sai_d2v v = {a, b};
-    __builtin_nontemporal_store(v, reinterpret_cast<sai_d2v*>(p + q));
-  } else {
+    if (nt) __builtin_nontemporal_store(v, reinterpret_cast<sai_d2v*>(p + q));
+    else *reinterpret_cast<sai_d2v*>(p + q) = v;
+  } else if (nt) {
     if (o0) __builtin_nontemporal_store(a, p + q);
     if (o1) __builtin_nontemporal_store(b, p + q + 1);
+  } else {
+    if (o0) p[q] = a;
+    if (o1) p[q + 1] = b;
   }
 }
 
@@ -366,7 +373,7 @@ __global__ void __launch_bounds__(NT) k_pupdate(int64_t n, int k, int kp, Vec V,
   ROW_LOOP {
     const int64_t q = i * kp + c0;
     const double2 r = ld2(V.r, q), p = ld2(V.p, q), v = ld2(V.v, q);
-    st2(V.p, q, r.x + be0 * (p.x - om0 * v.x), r.y + be1 * (p.y - om1 * v.y), o0, o1, pad1_);
+    st2(V.p, q, r.x + be0 * (p.x - om0 * v.x), r.y + be1 * (p.y - om1 * v.y), o0, o1, pad1_, S.nt);
   }
 }
 
@@ -383,7 +390,7 @@ __global__ void __launch_bounds__(NT) k_spmm(int64_t n, int k, int kp, Csr<TV> A
   TILE_LOOP {
     const int rows = (int)min<int64_t>(TR, n - t0);
     const bool fit = stage_tile<TV, CAP_M>(A, t0, rows, s_rp, s_ci, s_v);
-    if (o0 || o1) { TILE_ROW_PROD(TV, CH, CH2, A, X, , st2(Y, qq, y0, y1, o0, o1, pad1_);) }
+    if (o0 || o1) { TILE_ROW_PROD(TV, CH, CH2, A, X, , st2(Y, qq, y0, y1, o0, o1, pad1_, S.nt);) }
     __syncthreads();
   }
 }
@@ -404,7 +411,7 @@ __global__ void __launch_bounds__(NT) k_av(int64_t n, int k, int kp, Csr<double>
         const bool fit = stage_tile<double, CAP_A>(A, t0, rows, s_rp, s_ci, s_v);
         if (o0 || o1) {
           TILE_ROW_PROD(double, CH, CH2, A, V.ph, const double2 rh = ld2(V.rh, qq);,
-                        st2(V.v, qq, y0, y1, o0, o1, pad1_);
+                        st2(V.v, qq, y0, y1, o0, o1, pad1_, S.nt);
                         if (o0) acc[0][0] += rh.x * y0; if (o1) acc[0][1] += rh.y * y1;)
         }
         __syncthreads();
@@ -415,7 +422,7 @@ __global__ void __launch_bounds__(NT) k_av(int64_t n, int k, int kp, Csr<double>
       TILE_LOOP {
         const int rows = (int)min<int64_t>(TR, n - t0);
         GLOBAL_ROW_PROD(double, CH, CH2, A, V.ph, const double2 rh = ld2(V.rh, qq);,
-                        st2(V.v, qq, y0, y1, o0, o1, pad1_);
+                        st2(V.v, qq, y0, y1, o0, o1, pad1_, S.nt);
                         if (o0) acc[0][0] += rh.x * y0; if (o1) acc[0][1] += rh.y * y1;)
       }
     }
@@ -433,7 +440,7 @@ __global__ void __launch_bounds__(NT) k_s(int64_t n, int k, int kp, Vec V, State
   ROW_LOOP {
     const int64_t q = i * kp + c0;
     const double2 r = ld2(V.r, q), v = ld2(V.v, q);
-    st2(V.s, q, r.x - al0 * v.x, r.y - al1 * v.y, o0, o1, pad1_);
+    st2(V.s, q, r.x - al0 * v.x, r.y - al1 * v.y, o0, o1, pad1_, S.nt);
   }
 }
 
@@ -479,7 +486,7 @@ __global__ void __launch_bounds__(NT) k_at(int64_t n, int k, int kp, Csr<double>
   double acc[3][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
   const bool o0 = lok_ && col_on(S, c0, k), o1 = lok_ && col_on(S, c0 + 1, k);
 #define AT_BODY                                                                                  \
-  st2(V.t, qq, y0, y1, o0, o1, pad1_);                                                                  \
+  st2(V.t, qq, y0, y1, o0, o1, pad1_, S.nt);                                                                  \
   if (o0) { acc[0][0] += y0 * sv.x; acc[1][0] += y0 * y0; acc[2][0] += sv.x * sv.x; }            \
   if (o1) { acc[0][1] += y1 * sv.y; acc[1][1] += y1 * y1; acc[2][1] += sv.y * sv.y; }
   if constexpr (STG) {
@@ -520,11 +527,11 @@ __global__ void __launch_bounds__(NT) k_xr(int64_t n, int k, int kp, Vec V, Stat
     ROW_LOOP {
       const int64_t q = i * kp + c0;
       const double2 x = ld2(V.x, q), ph = ld2(V.ph, q), sh = ld2(V.sh, q);
-      st2(V.x, q, x.x + al0 * ph.x + om0 * sh.x, x.y + al1 * ph.y + om1 * sh.y, a0, a1, pad1_);
+      st2(V.x, q, x.x + al0 * ph.x + om0 * sh.x, x.y + al1 * ph.y + om1 * sh.y, a0, a1, pad1_, S.nt);
       if (o0 || o1) {
         const double2 s = ld2(V.s, q), t = ld2(V.t, q), rh = ld2(V.rh, q);
         const double r0 = s.x - om0 * t.x, r1 = s.y - om1 * t.y;
-        st2(V.r, q, r0, r1, o0, o1, pad1_);
+        st2(V.r, q, r0, r1, o0, o1, pad1_, S.nt);
         if (o0) { acc[0][0] += rh.x * r0; acc[1][0] += r0 * r0; }
         if (o1) { acc[0][1] += rh.y * r1; acc[1][1] += r1 * r1; }
       }
@@ -551,7 +558,7 @@ __global__ void __launch_bounds__(NT) k_fullcheck(int64_t n, int k, int kp, Csr<
     if (o0 || o1) {
       TILE_ROW_PROD(double, 4, 2, A, V.x, const double2 b = ld2(V.b, qq); const double2 rh = ld2(V.rh, qq);,
                     const double r0 = b.x - y0; const double r1 = b.y - y1;
-                    st2(V.r, qq, r0, r1, o0, o1, pad1_);
+                    st2(V.r, qq, r0, r1, o0, o1, pad1_, S.nt);
                     if (o0) { acc[0][0] += r0 * r0; acc[1][0] += rh.x * r0; }
                     if (o1) { acc[0][1] += r1 * r1; acc[1][1] += rh.y * r1; })
     }
@@ -572,9 +579,9 @@ __global__ void __launch_bounds__(NT) k_restart(int64_t n, int k, int kp, Vec V,
     ROW_LOOP {
       const int64_t q = i * kp + c0;
       const double2 r = ld2(V.r, q);
-      st2(V.rh, q, r.x, r.y, o0, o1, pad1_);
-      st2(V.p, q, 0.0, 0.0, o0, o1, pad1_);
-      st2(V.v, q, 0.0, 0.0, o0, o1, pad1_);
+      st2(V.rh, q, r.x, r.y, o0, o1, pad1_, S.nt);
+      st2(V.p, q, 0.0, 0.0, o0, o1, pad1_, S.nt);
+      st2(V.v, q, 0.0, 0.0, o0, o1, pad1_, S.nt);
       if (o0) acc[0][0] += r.x * r.x;
       if (o1) acc[0][1] += r.y * r.y;
     }

@@ -449,6 +449,10 @@ int gmres_batched_lp(const Csr<double>& A, const Csr<TM>& M, int64_t n, int k, c
   Scyc.status = G.cyc;
   Scyc.skip = G.zero;
   Scyc.any = G.any_cyc;
+  {
+    const int ntk = tune_get("NT_STORE", -1);
+    Sarn.nt = Scyc.nt = ntk >= 0 ? ntk : ((size_t)n * kp * sizeof(double) > (size_t(32) << 20) ? 1 : 0);
+  }
   constexpr int RPB = (64 / LP) * (NT / 64);
   const int xmap = tune_get("XMAP", nk * sizeof(double) <= (size_t(256) << 20) ? 1 : 0);
   auto sp_grid = [&](const void* kern) {

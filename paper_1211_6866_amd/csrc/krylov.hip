@@ -163,7 +163,13 @@ template <int LP, class TM>
 int iterate(Block& B, const Csr<double>& A, const Csr<TM>& M, int64_t n, int& it, int maxit, bool first,
             bool narrow_ok, const IterNames& N, const double* R, hipStream_t st, int* slot, hipEvent_t* ev) {
   const int k = B.k, kp = B.kp;
-  const State S = B.S;
+  State S = B.S;
+  // output blocks larger than the 8 XCDs' L2s together are stored non-temporally
+  // (NT_STORE: -1 by size, 0 never, 1 always)
+  {
+    const int ntk = tune_get("NT_STORE", -1);
+    S.nt = ntk >= 0 ? ntk : ((size_t)n * kp * sizeof(double) > (size_t(32) << 20) ? 1 : 0);
+  }
   const Vec V = B.V;
   constexpr int RPB = (64 / LP) * (NT / 64);
   // streaming kernels: a grid-stride loop over rows (fewer blocks also means

@@ -538,8 +538,9 @@ def test_m_product_variants_bit_identical(width):
     0 .. 5, or SPMM_M_WIDE / SPMM_A_WIDE for blocks over 32 columns, chosen by
     the autotuner) change only how many loads are in flight: each row's
     products are added in the same order, so the whole Krylov solve is
-    bit-identical.  narrow: [b, U] of a 12^3 matrix (5 columns); wide: 40
-    seeded right-hand sides (the 32-lane class)."""
+    bit-identical.  So are the output blocks stored non-temporally (NT_STORE = 1;
+    blocks this small are stored plainly by default).  narrow: [b, U] of a 12^3
+    matrix (5 columns); wide: 40 seeded right-hand sides (the 32-lane class)."""
     w, (rp, ci, va) = _load("c2_12")
     S = osplit.split(w.A)
     g = P.Split(rp, ci, va)
@@ -552,17 +553,21 @@ def test_m_product_variants_bit_identical(width):
         R = np.random.default_rng(40).standard_normal((w.A.shape[0], 40))
         thr = [1e-10 * np.linalg.norm(R[:, c]) for c in range(40)]
         km, ka, dm, da = "SPMM_M_WIDE", "SPMM_A_WIDE", 4, 5
+    cases = [(dm, da, -1)] + [(v, da, -1) for v in range(5) if v != dm] + [(dm, v, -1) for v in range(6) if v != da]
+    cases += [(dm, da, 1), (dm, da, 0)]
     out = []
     try:
-        for m, a in [(dm, da)] + [(v, da) for v in range(5) if v != dm] + [(dm, v) for v in range(6) if v != da]:
+        for m, a, nt in cases:
             P.tune_set(km, m)
             P.tune_set(ka, a)
+            P.tune_set("NT_STORE", nt)
             X, its, sts, code = P.krylov(g, pc, torch.from_numpy(R).cuda(), thr)
             assert code == P.OK
             out.append((_np(X), its))
     finally:
         P.tune_set(km, dm)
         P.tune_set(ka, da)
+        P.tune_set("NT_STORE", -1)
     for X, its in out[1:]:
         assert its == out[0][1] and np.array_equal(X, out[0][0])
 
