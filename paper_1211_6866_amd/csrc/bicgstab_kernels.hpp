@@ -54,6 +54,7 @@ struct State {
   int* any;   // 0 half, 1 full, 2 restart, 3 active count, 4 half-converged
   double* part;
   int nt;     // output blocks stored non-temporally (st2)
+  int ntl;    // streamed (not gathered) block reads non-temporal (lds2)
 };
 
 // n x kp blocks (b: the right-hand sides, copied in with the pad column zeroed)
@@ -66,6 +67,16 @@ __device__ __forceinline__ bool col_on(const State& S, int c, int k) {
 }
 
 __device__ __forceinline__ double2 ld2(const double* __restrict__ p, int64_t q) {
+  return *reinterpret_cast<const double2*>(p + q);
+}
+// a streamed read of a block (the row's own pair, not a gathered one); with ntl
+// non-temporal, which leaves L2 to the gathered rows
+__device__ __forceinline__ double2 lds2(const double* __restrict__ p, int64_t q, int ntl) {
+  typedef double d2v_ __attribute__((ext_vector_type(2)));
+  if (ntl) {
+    const d2v_ v = __builtin_nontemporal_load(reinterpret_cast<const d2v_*>(p + q));
+    return make_double2(v.x, v.y);
+  }
   return *reinterpret_cast<const double2*>(p + q);
 }
 
@@ -372,7 +383,7 @@ __global__ void __launch_bounds__(NT) k_pupdate(int64_t n, int k, int kp, Vec V,
   const double be1 = o1 ? S.beta[c0 + 1] : 0.0, om1 = o1 ? S.omega[c0 + 1] : 0.0;
   ROW_LOOP {
     const int64_t q = i * kp + c0;
-    const double2 r = ld2(V.r, q), p = ld2(V.p, q), v = ld2(V.v, q);
+    const double2 r = lds2(V.r, q, S.ntl), p = lds2(V.p, q, S.ntl), v = lds2(V.v, q, S.ntl);
     st2(V.p, q, r.x + be0 * (p.x - om0 * v.x), r.y + be1 * (p.y - om1 * v.y), o0, o1, pad1_, S.nt);
   }
 }
@@ -410,7 +421,7 @@ __global__ void __launch_bounds__(NT) k_av(int64_t n, int k, int kp, Csr<double>
         const int rows = (int)min<int64_t>(TR, n - t0);
         const bool fit = stage_tile<double, CAP_A>(A, t0, rows, s_rp, s_ci, s_v);
         if (o0 || o1) {
-          TILE_ROW_PROD(double, CH, CH2, A, V.ph, const double2 rh = ld2(V.rh, qq);,
+          TILE_ROW_PROD(double, CH, CH2, A, V.ph, const double2 rh = lds2(V.rh, qq, S.ntl);,
                         st2(V.v, qq, y0, y1, o0, o1, pad1_, S.nt);
                         if (o0) acc[0][0] += rh.x * y0; if (o1) acc[0][1] += rh.y * y1;)
         }
@@ -421,7 +432,7 @@ __global__ void __launch_bounds__(NT) k_av(int64_t n, int k, int kp, Csr<double>
     if (S.any[3] != 0 && (o0 || o1)) {
       TILE_LOOP {
         const int rows = (int)min<int64_t>(TR, n - t0);
-        GLOBAL_ROW_PROD(double, CH, CH2, A, V.ph, const double2 rh = ld2(V.rh, qq);,
+        GLOBAL_ROW_PROD(double, CH, CH2, A, V.ph, const double2 rh = lds2(V.rh, qq, S.ntl);,
                         st2(V.v, qq, y0, y1, o0, o1, pad1_, S.nt);
                         if (o0) acc[0][0] += rh.x * y0; if (o1) acc[0][1] += rh.y * y1;)
       }
@@ -439,7 +450,7 @@ __global__ void __launch_bounds__(NT) k_s(int64_t n, int k, int kp, Vec V, State
   const double al0 = o0 ? S.alpha[c0] : 0.0, al1 = o1 ? S.alpha[c0 + 1] : 0.0;
   ROW_LOOP {
     const int64_t q = i * kp + c0;
-    const double2 r = ld2(V.r, q), v = ld2(V.v, q);
+    const double2 r = lds2(V.r, q, S.ntl), v = lds2(V.v, q, S.ntl);
     st2(V.s, q, r.x - al0 * v.x, r.y - al1 * v.y, o0, o1, pad1_, S.nt);
   }
 }
@@ -468,7 +479,7 @@ __global__ void __launch_bounds__(NT) k_halfcheck(int64_t n, int k, int kp, Csr<
                                   al1, kp, c0, y0, y1);
       else
         row_prod_xp<double, 4, 2>(A.ci, A.v, s_rp[rib], s_rp[rib + 1], V.x, V.ph, al0, al1, kp, c0, y0, y1);
-      const double2 b = ld2(V.b, qq);
+      const double2 b = lds2(V.b, qq, S.ntl);
       const double r0 = b.x - y0, r1 = b.y - y1;
       if (o0) acc[0][0] += r0 * r0;
       if (o1) acc[0][1] += r1 * r1;
@@ -496,7 +507,7 @@ __global__ void __launch_bounds__(NT) k_at(int64_t n, int k, int kp, Csr<double>
       TILE_LOOP {
         const int rows = (int)min<int64_t>(TR, n - t0);
         const bool fit = stage_tile<double, CAP_A>(A, t0, rows, s_rp, s_ci, s_v);
-        if (o0 || o1) { TILE_ROW_PROD(double, CH, CH2, A, V.sh, const double2 sv = ld2(V.s, qq);, AT_BODY) }
+        if (o0 || o1) { TILE_ROW_PROD(double, CH, CH2, A, V.sh, const double2 sv = lds2(V.s, qq, S.ntl);, AT_BODY) }
         __syncthreads();
       }
     }
@@ -504,7 +515,7 @@ __global__ void __launch_bounds__(NT) k_at(int64_t n, int k, int kp, Csr<double>
     if (S.any[3] != 0 && (o0 || o1)) {
       TILE_LOOP {
         const int rows = (int)min<int64_t>(TR, n - t0);
-        GLOBAL_ROW_PROD(double, CH, CH2, A, V.sh, const double2 sv = ld2(V.s, qq);, AT_BODY)
+        GLOBAL_ROW_PROD(double, CH, CH2, A, V.sh, const double2 sv = lds2(V.s, qq, S.ntl);, AT_BODY)
       }
     }
   }
@@ -526,10 +537,10 @@ __global__ void __launch_bounds__(NT) k_xr(int64_t n, int k, int kp, Vec V, Stat
   if (a0 || a1) {
     ROW_LOOP {
       const int64_t q = i * kp + c0;
-      const double2 x = ld2(V.x, q), ph = ld2(V.ph, q), sh = ld2(V.sh, q);
+      const double2 x = lds2(V.x, q, S.ntl), ph = lds2(V.ph, q, S.ntl), sh = lds2(V.sh, q, S.ntl);
       st2(V.x, q, x.x + al0 * ph.x + om0 * sh.x, x.y + al1 * ph.y + om1 * sh.y, a0, a1, pad1_, S.nt);
       if (o0 || o1) {
-        const double2 s = ld2(V.s, q), t = ld2(V.t, q), rh = ld2(V.rh, q);
+        const double2 s = lds2(V.s, q, S.ntl), t = lds2(V.t, q, S.ntl), rh = lds2(V.rh, q, S.ntl);
         const double r0 = s.x - om0 * t.x, r1 = s.y - om1 * t.y;
         st2(V.r, q, r0, r1, o0, o1, pad1_, S.nt);
         if (o0) { acc[0][0] += rh.x * r0; acc[1][0] += r0 * r0; }
@@ -556,7 +567,7 @@ __global__ void __launch_bounds__(NT) k_fullcheck(int64_t n, int k, int kp, Csr<
     const int rows = (int)min<int64_t>(TR, n - t0);
     const bool fit = stage_tile<double, CAP_A>(A, t0, rows, s_rp, s_ci, s_v);
     if (o0 || o1) {
-      TILE_ROW_PROD(double, 4, 2, A, V.x, const double2 b = ld2(V.b, qq); const double2 rh = ld2(V.rh, qq);,
+      TILE_ROW_PROD(double, 4, 2, A, V.x, const double2 b = lds2(V.b, qq, S.ntl); const double2 rh = lds2(V.rh, qq, S.ntl);,
                     const double r0 = b.x - y0; const double r1 = b.y - y1;
                     st2(V.r, qq, r0, r1, o0, o1, pad1_, S.nt);
                     if (o0) { acc[0][0] += r0 * r0; acc[1][0] += rh.x * r0; }
@@ -578,7 +589,7 @@ __global__ void __launch_bounds__(NT) k_restart(int64_t n, int k, int kp, Vec V,
   if (o0 || o1) {
     ROW_LOOP {
       const int64_t q = i * kp + c0;
-      const double2 r = ld2(V.r, q);
+      const double2 r = lds2(V.r, q, S.ntl);
       st2(V.rh, q, r.x, r.y, o0, o1, pad1_, S.nt);
       st2(V.p, q, 0.0, 0.0, o0, o1, pad1_, S.nt);
       st2(V.v, q, 0.0, 0.0, o0, o1, pad1_, S.nt);

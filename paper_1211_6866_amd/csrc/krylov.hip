@@ -165,10 +165,14 @@ int iterate(Block& B, const Csr<double>& A, const Csr<TM>& M, int64_t n, int& it
   const int k = B.k, kp = B.kp;
   State S = B.S;
   // output blocks larger than the 8 XCDs' L2s together are stored non-temporally
-  // (NT_STORE: -1 by size, 0 never, 1 always)
+  // (NT_STORE: -1 by size, 0 never, 1 always).  Streamed reads non-temporal
+  // (NT_LOAD = 1, set per workload class by the tuning file): faster on the
+  // 100^3 matrix (96 MB blocks), slower on the 160^3 one (1.7 GB), on the
+  // irregular 200,000 matrix (35 MB) and on the 500^2 one (20 MB)
   {
     const int ntk = tune_get("NT_STORE", -1);
     S.nt = ntk >= 0 ? ntk : ((size_t)n * kp * sizeof(double) > (size_t(32) << 20) ? 1 : 0);
+    S.ntl = tune_get("NT_LOAD", 0) != 0 ? 1 : 0;
   }
   const Vec V = B.V;
   constexpr int RPB = (64 / LP) * (NT / 64);

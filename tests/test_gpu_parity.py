@@ -538,8 +538,9 @@ def test_m_product_variants_bit_identical(width):
     0 .. 5, or SPMM_M_WIDE / SPMM_A_WIDE for blocks over 32 columns, chosen by
     the autotuner) change only how many loads are in flight: each row's
     products are added in the same order, so the whole Krylov solve is
-    bit-identical.  So are the output blocks stored non-temporally (NT_STORE = 1;
-    blocks this small are stored plainly by default).  narrow: [b, U] of a 12^3
+    bit-identical.  So are the output blocks stored and the streamed ones read
+    non-temporally (NT_STORE = NT_LOAD = 1; blocks this small use plain accesses
+    by default).  narrow: [b, U] of a 12^3
     matrix (5 columns); wide: 40 seeded right-hand sides (the 32-lane class)."""
     w, (rp, ci, va) = _load("c2_12")
     S = osplit.split(w.A)
@@ -561,6 +562,7 @@ def test_m_product_variants_bit_identical(width):
             P.tune_set(km, m)
             P.tune_set(ka, a)
             P.tune_set("NT_STORE", nt)
+            P.tune_set("NT_LOAD", nt)
             X, its, sts, code = P.krylov(g, pc, torch.from_numpy(R).cuda(), thr)
             assert code == P.OK
             out.append((_np(X), its))
@@ -568,6 +570,7 @@ def test_m_product_variants_bit_identical(width):
         P.tune_set(km, dm)
         P.tune_set(ka, da)
         P.tune_set("NT_STORE", -1)
+        P.tune_set("NT_LOAD", -1)
     for X, its in out[1:]:
         assert its == out[0][1] and np.array_equal(X, out[0][0])
 
