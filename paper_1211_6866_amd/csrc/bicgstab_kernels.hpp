@@ -298,10 +298,27 @@ __device__ __forceinline__ bool stage_tile(const Csr<TV>& A, int64_t t0, int row
   const bool fit = cnt <= CAP;
   if (fit) {
     // the matrix is streamed once per product: non-temporal loads keep it from
-    // displacing the gathered rows of X in L2
-    for (int q = threadIdx.x; q < cnt; q += NT) {
-      s_ci[q] = __builtin_nontemporal_load(&A.ci[e0 + q]);
-      s_v[q] = __builtin_nontemporal_load(&A.v[e0 + q]);
+    // displacing the gathered rows of X in L2.  Each thread issues up to SU
+    // rounds of loads before its first store, so that staging a tile of many
+    // entries waits on memory once per SU rounds, not once per round.
+    constexpr int SU = 8;
+    for (int q0 = threadIdx.x; q0 < cnt; q0 += SU * NT) {
+      int32_t c[SU];
+      TV v[SU];
+#pragma unroll
+      for (int u = 0; u < SU; ++u) {
+        const int q = q0 + u * NT;
+        c[u] = q < cnt ? __builtin_nontemporal_load(&A.ci[e0 + q]) : 0;
+        v[u] = q < cnt ? __builtin_nontemporal_load(&A.v[e0 + q]) : TV(0);
+      }
+#pragma unroll
+      for (int u = 0; u < SU; ++u) {
+        const int q = q0 + u * NT;
+        if (q < cnt) {
+          s_ci[q] = c[u];
+          s_v[q] = v[u];
+        }
+      }
     }
   }
   __syncthreads();
