@@ -38,6 +38,7 @@ KNOBS_SOLVE = [
     ("SPMM_A_WIDE", [5, 0, 1]),        # 2/0, 4/2, 8/4
     ("SGRID", [512, 1024, 256]),       # workgroups of the streaming updates
     ("LP_MIN", [1, 2]),                # smallest lane class (one-column blocks on tiles of 128 rows)
+    ("SPMM_M_LP2", [1, 0]),            # one-column blocks: the M product alone on two lanes per row
     ("NT_STORE", [-1, 0, 1]),          # output blocks stored non-temporally: by size, never, always
     ("NT_LOAD", [0, 1]),               # streamed block reads non-temporal
     ("NARROW", [1, 0]),                # narrowing of the BiCGStab block

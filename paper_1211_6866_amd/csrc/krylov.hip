@@ -217,11 +217,40 @@ int iterate(Block& B, const Csr<double>& A, const Csr<TM>& M, int64_t n, int& it
   // vector L1 keeps in flight), while one-column blocks wait on each batch
   // (0.28 ms with 8/4, 1.18 ms with batches of 2).
   const int mvar = LP >= 32 ? tune_get("SPMM_M_WIDE", 4) : tune_get("SPMM_M", 1);
+  // One-column blocks (kp = 2) take the M product on the two-lane geometry
+  // (SPMM_M_LP2, 1 by default): tiles of 128 rows, whose entries of M fit the
+  // staging area, with the lane of the pad pair idle; the other kernels keep
+  // one lane per row.  The block layout is the same, and so are the sums.  On
+  // the 160^3 matrix the adjoint's M^T product went 0.282 -> 0.257 ms (with
+  // LP_MIN = 2, which moves the other kernels too, the adjoint was slower).
+  const bool m_lp2 = LP == 1 && tune_get("SPMM_M_LP2", 1) != 0;
   auto spmm_m = [&](const double* Xin, double* Y) {
     auto go = [&](auto kern) {
       hipLaunchKernelGGL(kern, dim3(sp_grid((const void*)kern)), dim3(NT), 0, st, n, k, kp, M, Xin, Y,
                          S, xmap);
     };
+    if constexpr (LP == 1) {
+      if (m_lp2) {
+        constexpr int RPB2 = (64 / 2) * (NT / 64);
+        const int xmap2 = tune_get("XMAP", nk * sizeof(double) <= (size_t(256) << 20)
+                                               ? 1
+                                               : (xchunk > 0 ? std::max(2, xchunk / RPB2) : 0));
+        auto go2 = [&](auto kern) {
+          int64_t g = std::min<int64_t>(NBMAX, (n + RPB2 - 1) / RPB2);
+          if (persist) g = std::min<int64_t>(g, resident_blocks((const void*)kern, NT));
+          g = g >= 8 ? (g & ~int64_t(7)) : g;
+          hipLaunchKernelGGL(kern, dim3((int)g), dim3(NT), 0, st, n, k, kp, M, Xin, Y, S, xmap2);
+        };
+        switch (mvar) {
+          case 0: go2(k_spmm<2, TM, 8, 4>); break;
+          case 2: go2(k_spmm<2, TM, 5, 0>); break;
+          case 3: go2(k_spmm<2, TM, 16, 8>); break;
+          case 4: go2(k_spmm<2, TM, 2, 0>); break;
+          default: go2(k_spmm<2, TM, 6, 3>); break;
+        }
+        return;
+      }
+    }
     switch (mvar) {
       case 0: go(k_spmm<LP, TM, 8, 4>); break;
       case 2: go(k_spmm<LP, TM, 5, 0>); break;

@@ -1014,12 +1014,14 @@ def test_solve_equilibrated_vs_oracle():
 
 
 @pytest.mark.parametrize("knobs", [dict(LP_MIN=2), dict(LP_MIN=4), dict(XMAP=0), dict(XMAP=3),
-                                   dict(XMAP=16), dict(PERSIST=0)],
-                         ids=["lp_min2", "lp_min4", "round_robin", "runs3", "runs16", "not_persistent"])
+                                   dict(XMAP=16), dict(PERSIST=0), dict(SPMM_M_LP2=0)],
+                         ids=["lp_min2", "lp_min4", "round_robin", "runs3", "runs16", "not_persistent",
+                              "m_one_lane"])
 def test_launch_knobs_vs_oracle(knobs):
     """Launch-shape knobs the tuning file may set (the smallest lane class, the
     tile-to-XCD maps: round-robin, runs of 3 or 16 tiles per XCD; grids larger
-    than the resident count) change only rounding: [b, U] of a 12^3 matrix and
+    than the resident count; the M product of one-column blocks on one lane per
+    row instead of two) change only rounding: [b, U] of a 12^3 matrix and
     one seeded right-hand side solved with each, every true residual below its
     threshold, iterations within 2 of the oracle's, x within ||A~^{-1}| (sum of
     both true residuals) of the oracle's."""
